@@ -1,0 +1,243 @@
+"""Pins for the CPU oracle: it is checked against things other than itself.
+
+* hand-worked fixtures written from the definitions (tests/golden),
+* the paper's statement that order [0 1 2] is a plain memcpy (Table 1, first row),
+* NumPy's own transpose / stack / reshape (an independent library routine),
+* brute force over every permutation of small ranks and odd extents,
+* algebraic invariants: inverse, composition, interlace o de-interlace = id,
+  the element-size split,
+* the paper's fastest-first notation against the row-major one.
+
+Each planted mistake (mutant build of the oracle) must fail at least one pin.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+from tests import golden_io
+
+
+def _iota(n):
+    return (np.arange(n) % 256).astype(np.uint8)
+
+
+def _np_permute(x_bytes, dims, perm, esize):
+    """NumPy's transpose on a (dims..., esize) byte view; independent of the oracle."""
+    a = x_bytes.reshape(tuple(dims) + (esize,))
+    return np.ascontiguousarray(np.transpose(a, tuple(perm) + (len(dims),))).reshape(-1)
+
+
+def paper_order_to_numpy_perm(order):
+    """Fastest-first order o -> row-major perm: perm[j] = N-1-o[N-1-j] (reading of Sec. III.B)."""
+    n = len(order)
+    return tuple(n - 1 - order[n - 1 - j] for j in range(n))
+
+
+# --------------------------------------------------------------------------- pins
+def pin_golden(golden_dir, m=0):
+    for case in golden_io.load_all(golden_dir):
+        op = case["op"]
+        e = case["esize"][0]
+        if op == "permute":
+            n = int(np.prod(case["dims"])) * e
+            got = oracle.permute(_iota(n), case["dims"], case["perm"], e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
+        elif op == "reorder_paper":
+            n = int(np.prod(case["sizes"])) * e
+            got = oracle.reorder_paper(_iota(n), case["sizes"], case["order"], e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
+            dims = list(reversed(case["sizes"]))
+            got2 = oracle.permute(_iota(n), dims, case["numpy_perm"], e, mutant=m)
+            if got2.tolist() != case["expect"]:
+                return False
+        elif op == "interlace":
+            planes = [np.array(p, dtype=np.uint8) for p in case["planes"]]
+            got = oracle.interlace(planes, e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
+        elif op == "deinterlace":
+            n = int(case["input"][1])
+            got = oracle.deinterlace(_iota(n), case["n"][0], e, mutant=m)
+            if [g.tolist() for g in got] != case["expect_planes"]:
+                return False
+        else:
+            raise AssertionError(f"unknown op {op}")
+    return True
+
+
+def pin_identity_is_memcpy(m=0):
+    """Table 1, first row: order [0 1 2] is the memcpy reference."""
+    for dims, e in [((5, 7, 3), 4), ((2, 3, 4, 5), 3), ((17,), 16)]:
+        n = int(np.prod(dims)) * e
+        x = rr_synth.random_bytes(11, n)
+        if not np.array_equal(oracle.permute(x, dims, tuple(range(len(dims))), e, mutant=m), x):
+            return False
+    return True
+
+
+def pin_numpy_random(m=0, trials=60):
+    g = rr_synth.rng(1234)
+    for t in range(trials):
+        nd = int(g.integers(1, 6))
+        dims = tuple(int(g.integers(1, 7)) for _ in range(nd))
+        perm = tuple(int(v) for v in g.permutation(nd))
+        e = int(g.integers(1, 17))
+        x = rr_synth.random_bytes(100 + t, int(np.prod(dims)) * e)
+        if not np.array_equal(oracle.permute(x, dims, perm, e, mutant=m),
+                              _np_permute(x, dims, perm, e)):
+            return False
+    return True
+
+
+def pin_brute_force(m=0, max_ndim=5):
+    """Every permutation of rank <= max_ndim on odd extents, against NumPy."""
+    ext = (3, 2, 5, 1, 2)
+    for nd in range(1, max_ndim + 1):
+        dims = ext[:nd]
+        for e in (1, 3, 8):
+            x = rr_synth.random_bytes(7 * nd + e, int(np.prod(dims)) * e)
+            for perm in itertools.permutations(range(nd)):
+                if not np.array_equal(oracle.permute(x, dims, perm, e, mutant=m),
+                                      _np_permute(x, dims, perm, e)):
+                    return False
+    return True
+
+
+def pin_inverse_and_composition(m=0):
+    g = rr_synth.rng(77)
+    for t in range(20):
+        nd = int(g.integers(2, 6))
+        dims = tuple(int(g.integers(1, 6)) for _ in range(nd))
+        p = tuple(int(v) for v in g.permutation(nd))
+        q = tuple(int(v) for v in g.permutation(nd))
+        e = int(g.choice([1, 2, 4, 5]))
+        x = rr_synth.random_bytes(500 + t, int(np.prod(dims)) * e)
+        y = oracle.permute(x, dims, p, e, mutant=m)
+        pdims = tuple(dims[k] for k in p)
+        inv = tuple(int(v) for v in np.argsort(p))
+        if not np.array_equal(oracle.permute(y, pdims, inv, e, mutant=m), x):
+            return False
+        # permute(permute(x, p), q) == permute(x, p[q])
+        z = oracle.permute(y, pdims, q, e, mutant=m)
+        pq = tuple(p[k] for k in q)
+        if not np.array_equal(z, oracle.permute(x, dims, pq, e, mutant=m)):
+            return False
+    return True
+
+
+def pin_esize_split(m=0):
+    """An e-byte element permute equals a 1-byte permute with the bytes as an extra last axis."""
+    for dims, perm, e in [((4, 3, 5), (2, 0, 1), 6), ((3, 7), (1, 0), 16), ((2, 3, 2, 3), (3, 1, 0, 2), 3)]:
+        x = rr_synth.random_bytes(9, int(np.prod(dims)) * e)
+        a = oracle.permute(x, dims, perm, e, mutant=m)
+        b = oracle.permute(x, tuple(dims) + (e,), tuple(perm) + (len(dims),), 1, mutant=m)
+        if not np.array_equal(a, b):
+            return False
+    return True
+
+
+def pin_interlace_numpy(m=0):
+    for n, count, e in [(2, 37, 4), (3, 50, 4), (4, 64, 1), (9, 13, 2), (1, 5, 8), (16, 3, 16)]:
+        planes = [rr_synth.random_bytes(40 + c, count * e) for c in range(n)]
+        got = oracle.interlace(planes, e, mutant=m)
+        ref = np.stack([p.reshape(count, e) for p in planes], axis=1).reshape(-1)
+        if not np.array_equal(got, ref):
+            return False
+        back = oracle.deinterlace(got, n, e, mutant=m)
+        if not all(np.array_equal(b, p) for b, p in zip(back, planes)):
+            return False
+        x = rr_synth.random_bytes(90, n * count * e)
+        split = oracle.deinterlace(x, n, e, mutant=m)
+        ref_split = x.reshape(count, n, e).transpose(1, 0, 2)
+        if not all(np.array_equal(split[c], ref_split[c].reshape(-1)) for c in range(n)):
+            return False
+    # Sec. III.C example: complex numbers split into real and imaginary planes.
+    z = rr_synth.random_bytes(5, 8 * 100).view(np.complex64)
+    re, im = oracle.deinterlace(z.view(np.uint8), 2, 4)
+    if not (np.array_equal(re.view(np.float32).view(np.uint32), z.real.view(np.uint32))
+            and np.array_equal(im.view(np.float32).view(np.uint32), z.imag.view(np.uint32))):
+        return False
+    return True
+
+
+def pin_paper_notation(m=0):
+    """Every fastest-first order of ranks 2..4 equals the converted row-major permute."""
+    for sizes in [(3, 2), (4, 3, 2), (2, 3, 1, 5)]:
+        n = len(sizes)
+        x = rr_synth.random_bytes(3, int(np.prod(sizes)) * 2)
+        for order in itertools.permutations(range(n)):
+            a = oracle.reorder_paper(x, sizes, order, 2, mutant=m)
+            b = oracle.permute(x, tuple(reversed(sizes)), paper_order_to_numpy_perm(order), 2, mutant=m)
+            c = _np_permute(x, tuple(reversed(sizes)), paper_order_to_numpy_perm(order), 2)
+            if not (np.array_equal(a, b) and np.array_equal(a, c)):
+                return False
+    return True
+
+
+def pin_permute_at(m=0):
+    dims, perm, e = (6, 5, 7, 3), (3, 0, 2, 1), 4
+    x = rr_synth.random_bytes(21, int(np.prod(dims)) * e)
+    full = _np_permute(x, dims, perm, e).reshape(-1, e)
+    idx = np.array([0, 1, 17, 200, int(np.prod(dims)) - 1], dtype=np.int64)
+    return np.array_equal(oracle.permute_at(x, dims, perm, e, idx, mutant=m), full[idx])
+
+
+ALL_PINS = {
+    "identity": lambda gd, m: pin_identity_is_memcpy(m),
+    "golden": lambda gd, m: pin_golden(gd, m),
+    "numpy": lambda gd, m: pin_numpy_random(m),
+    "brute": lambda gd, m: pin_brute_force(m),
+    "inverse": lambda gd, m: pin_inverse_and_composition(m),
+    "esize_split": lambda gd, m: pin_esize_split(m),
+    "interlace": lambda gd, m: pin_interlace_numpy(m),
+    "paper_notation": lambda gd, m: pin_paper_notation(m),
+    "permute_at": lambda gd, m: pin_permute_at(m),
+}
+
+
+@pytest.mark.parametrize("name", sorted(ALL_PINS))
+def test_oracle_pin(name, golden_dir):
+    assert oracle.mutant_id(0) == 0
+    assert ALL_PINS[name](golden_dir, 0), f"oracle fails pin {name}"
+
+
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4])
+def test_planted_mistake_is_caught(mutant, golden_dir):
+    """Each planted oracle mistake (gather/scatter swap, dropped term, wrong stride,
+    transposed interlace) must fail at least one pin."""
+    oracle.build(mutant, force=False)
+    assert oracle.mutant_id(mutant) == mutant
+    failed = []
+    for name, fn in ALL_PINS.items():
+        try:
+            ok = fn(golden_dir, mutant)
+        except Exception:
+            ok = False
+        if not ok:
+            failed.append(name)
+    assert failed, f"mutant {mutant} passed every pin"
+
+
+def test_paper_table_orders_convert():
+    """Orders of Tables 1 and 2 mapped to row-major perms (reading of Sec. III.B)."""
+    expect = {
+        (0, 2, 1): (1, 0, 2), (1, 0, 2): (0, 2, 1), (1, 2, 0): (2, 0, 1),
+        (2, 0, 1): (1, 2, 0), (2, 1, 0): (2, 1, 0), (1, 0, 2, 3): (0, 1, 3, 2),
+        (3, 2, 0, 1): (2, 3, 1, 0), (3, 0, 2, 1, 4): (0, 3, 2, 4, 1),
+    }
+    for order, perm in expect.items():
+        assert paper_order_to_numpy_perm(order) == perm
+
+
+def test_paper_table2_shapes_small_esize():
+    """Table 2 reorders (2^24 elements each) at 1-byte elements: paper notation == NumPy."""
+    for sizes, order in rr_synth.PAPER_TABLE2[:2]:
+        x = rr_synth.random_bytes(8, int(np.prod(sizes)))
+        a = oracle.reorder_paper(x, sizes, order, 1)
+        c = _np_permute(x, tuple(reversed(sizes)), paper_order_to_numpy_perm(order), 1)
+        assert np.array_equal(a, c)
