@@ -1,0 +1,203 @@
+/*
+ * rr.h -- C ABI of librr, an MI355X (gfx950) library of data-rearrangement
+ * kernels: N-D permute/transpose/reorder, interlace and de-interlace, a batched
+ * launch for many uneven permutes, and a continuous-batching server.
+ *
+ * The operations are those of "Fast GPGPU Data Rearrangement Kernels using
+ * CUDA" (arXiv:1011.3583), Sec. III.B (re-ordering an N-dimensional array under
+ * a given order of its axes) and Sec. III.C (interlace / de-interlace).
+ *
+ * Conventions
+ *  - Arrays are dense and row-major ("linearized storage", Sec. III.B): the LAST
+ *    axis varies fastest.  Axis permutations use the row-major (NumPy) reading:
+ *    the output has shape out_dims[j] = dims[perm[j]] and
+ *        out[J] = in[I]  with  I[perm[j]] = J[j].
+ *    The paper lists orders fastest-dimension-first; rr_order_to_perm converts.
+ *  - Elements are opaque runs of elem_size bytes (1..16).  No arithmetic is
+ *    ever done on values: results are bit-exact copies (NaN payloads survive).
+ *  - Device pointers are plain HIP device addresses (hipMalloc, or any torch
+ *    CUDA tensor's data_ptr()).  The caller owns every buffer passed in; the
+ *    library never frees caller memory.
+ *  - `stream` is a hipStream_t passed as void*; NULL means the null stream.
+ *    Calls are stream-ordered and asynchronous: they return after enqueueing.
+ *  - Argument validation happens synchronously, before anything is enqueued;
+ *    on any error nothing is written and nothing is launched.
+ *  - Source and destination byte ranges must not overlap (no in-place).
+ *  - A problem with zero elements returns RR_OK and does nothing.
+ *  - Error detail for the calling thread is available from rr_last_error().
+ */
+#ifndef RR_H
+#define RR_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define RR_MAX_DIMS   8   /* input rank accepted by rr_permute */
+#define RR_MAX_PLANES 16  /* data sets accepted by rr_interlace / rr_deinterlace */
+
+typedef enum {
+    RR_OK = 0,
+    RR_ERR_INVALID_ARG = 1,  /* bad rank, perm, elem_size, count or NULL pointer   */
+    RR_ERR_OVERFLOW = 2,     /* element count * elem_size does not fit in int64     */
+    RR_ERR_ALIAS = 3,        /* source and destination byte ranges overlap          */
+    RR_ERR_UNSUPPORTED = 4,  /* valid request outside what this build handles       */
+    RR_ERR_NO_MEMORY = 5,    /* device/host allocation or server HBM budget refused */
+    RR_ERR_BUSY = 6,         /* server queue full, retry later                      */
+    RR_ERR_NOT_READY = 7,    /* server ticket still pending                         */
+    RR_ERR_HIP = 8           /* a HIP runtime call failed; see rr_last_error()      */
+} rr_status;
+
+typedef void* rr_stream_t; /* a hipStream_t */
+
+/* -------------------------------------------------------------------------
+ * Permute (Sec. III.B, 3D Permute Kernel and generic Reorder Kernel).
+ *   dst     device buffer of prod(dims)*elem_size bytes, written in the output
+ *           order (row-major over out_dims[j] = dims[perm[j]]).
+ *   src     device buffer of prod(dims)*elem_size bytes, row-major over dims.
+ *   ndim    1..RR_MAX_DIMS.  dims[k] >= 0.  Size-1 axes are allowed anywhere.
+ *   perm    a permutation of 0..ndim-1 (row-major reading above).
+ *   elem_size 1..16 bytes.
+ * Any alignment of src/dst is accepted; 16-byte aligned buffers take the
+ * widest vector path.
+ * Errors: RR_ERR_INVALID_ARG, RR_ERR_OVERFLOW, RR_ERR_ALIAS, RR_ERR_UNSUPPORTED,
+ * RR_ERR_HIP (launch failure).
+ */
+rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims,
+                     const int* perm, int elem_size, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Interlace (Sec. III.C): join n equally long data sets, set index fastest:
+ *   dst[i*n + c] = srcs[c][i]    for 0 <= i < count, 0 <= c < n.
+ *   dst   device buffer of n*count*elem_size bytes.
+ *   srcs  host array of n device pointers, each count*elem_size bytes.
+ *   n     1..RR_MAX_PLANES.  count >= 0.  elem_size 1..16.
+ * Errors: as rr_permute (RR_ERR_ALIAS if dst overlaps any source plane).
+ */
+rr_status rr_interlace(void* dst, const void* const* srcs, int n, int64_t count,
+                       int elem_size, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * De-interlace (Sec. III.C): split one interlaced set into n data sets:
+ *   dsts[c][i] = src[i*n + c]    (e.g. complex numbers into real and
+ *                                 imaginary planes with n = 2).
+ *   dsts  host array of n device pointers, each count*elem_size bytes; the
+ *         planes must not overlap each other or src.
+ * Errors: as rr_interlace.
+ */
+rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t count,
+                         int elem_size, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Batched permutes: many independent, unevenly shaped rr_permute jobs run in
+ * one persistent launch per kernel family (the paper's "batched 2D data
+ * movement", Sec. III.B, applied across jobs).  Each job's result is identical
+ * to running it alone with rr_permute.
+ *   jobs   host array of njobs descriptors (copied before return; the array may
+ *          be reused immediately).  Job buffers must not overlap each other.
+ *   njobs  >= 0.
+ * The job table is staged through a pinned host buffer and a device buffer the
+ * library owns (grown on demand, freed at process exit).
+ * Errors: the first invalid job's error (nothing is launched), RR_ERR_NO_MEMORY,
+ * RR_ERR_HIP.
+ */
+typedef struct {
+    void* dst;
+    const void* src;
+    int32_t ndim;
+    int32_t elem_size;
+    int64_t dims[RR_MAX_DIMS];
+    int32_t perm[RR_MAX_DIMS];
+} rr_job;
+
+rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Serving: a background thread that owns a HIP stream and an HBM budget,
+ * admits submitted permute jobs as budget and in-flight slots free up, and
+ * batches whatever has arrived into one batched launch while earlier batches
+ * are still running (continuous batching).  Large jobs are cut into chunks of
+ * at most chunk_bytes of output so small jobs interleave with them.
+ */
+typedef struct rr_server rr_server;
+
+typedef struct {
+    int32_t device;             /* HIP device ordinal                               */
+    int32_t max_inflight;       /* batches on the GPU at once (>= 1)                 */
+    int32_t max_batch_jobs;     /* jobs per batch (>= 1)                             */
+    int32_t queue_capacity;     /* pending submissions before RR_ERR_BUSY            */
+    uint64_t hbm_budget_bytes;  /* cap on server-allocated device memory             */
+    uint64_t chunk_bytes;       /* large jobs split into pieces of <= this (0 = off) */
+    uint32_t tick_us;           /* idle wait of the server thread                    */
+    uint32_t reserved;
+} rr_serve_config;
+
+typedef struct {
+    int32_t status;          /* rr_status of the job                                 */
+    int32_t reserved;
+    void* dst;               /* output buffer (server-allocated when job.dst == NULL) */
+    uint64_t t_submit_ns;    /* host steady-clock timestamps                          */
+    uint64_t t_admit_ns;
+    uint64_t t_launch_ns;
+    uint64_t t_done_ns;
+} rr_job_result;
+
+/* Create a server; *out receives the handle.  Errors: RR_ERR_INVALID_ARG, RR_ERR_HIP. */
+rr_status rr_serve_create(const rr_serve_config* cfg, rr_server** out);
+/* Allocate device memory counted against the budget (for resident inputs). */
+rr_status rr_serve_alloc(rr_server* s, uint64_t bytes, void** dptr);
+rr_status rr_serve_free(rr_server* s, void* dptr);
+/* Submit a job.  job->dst == NULL asks the server to allocate the output at
+ * admission (counted against the budget, freed by rr_serve_release).
+ * Errors: validation errors of rr_permute, RR_ERR_NO_MEMORY (job larger than the
+ * whole budget), RR_ERR_BUSY (queue full). */
+rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket);
+/* RR_ERR_NOT_READY while pending; otherwise fills *out and returns RR_OK (the
+ * job's own status is out->status). */
+rr_status rr_serve_poll(rr_server* s, uint64_t ticket, rr_job_result* out);
+/* Forget a completed ticket and free its server-allocated output. */
+rr_status rr_serve_release(rr_server* s, uint64_t ticket);
+/* Drain every admitted and queued job, stop the thread, free the server. */
+rr_status rr_serve_destroy(rr_server* s);
+/* Counters: submitted, completed, batches launched, bytes moved, peak budget use. */
+typedef struct {
+    uint64_t submitted, completed, failed, batches, chunks, bytes_moved, budget_peak, budget_used;
+} rr_serve_stats;
+rr_status rr_serve_get_stats(rr_server* s, rr_serve_stats* out);
+
+/* -------------------------------------------------------------------------
+ * Paper notation (Sec. III.B): an order vector lists dimensions fastest first
+ * and sizes are given fastest first.  For sizes listed fastest first, the
+ * row-major dims are the reversed list, and
+ *   perm[j] = ndim-1 - paper_order[ndim-1-j].
+ * Errors: RR_ERR_INVALID_ARG if paper_order is not a permutation.
+ */
+rr_status rr_order_to_perm(int ndim, const int* paper_order, int* perm_out);
+
+/* -------------------------------------------------------------------------
+ * Host-only plan introspection (no GPU needed): the canonical form and kernel
+ * plan rr_permute would use for this problem, written as one line of text
+ * "class=... rank=... dims=... perm=... esize_bytes=... unit=... ..." into buf.
+ * Alignment is taken from the two pointer values (which need not be valid).
+ */
+rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
+                           const int* perm, int elem_size, char* buf, int buflen);
+
+/* Tile-shape override for the autotuner: row targets in bytes for the input
+ * and output sides of the tiled kernel, 0 = built-in choice.  Applies to the
+ * calling process. */
+rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
+
+const char* rr_status_string(rr_status s);
+/* Detail of the last error on the calling thread ("" if none). */
+const char* rr_last_error(void);
+/* Library version string. */
+const char* rr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* RR_H */

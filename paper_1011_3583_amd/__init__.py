@@ -1,0 +1,285 @@
+"""Python binding of librr: N-D permute, interlace / de-interlace, batched and
+served permutes on one MI355X.
+
+Argument marshalling only.  Every byte is moved by the HIP kernels in
+``librr.so`` (built in-tree by ``python -m paper_1011_3583_amd.build``); if the
+library is missing this module raises instead of falling back to anything.
+PyTorch supplies device memory and streams for the tensor helpers.
+
+Conventions (row-major, NumPy-style perms) follow the C header include/rr.h.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "librr.so")
+
+RR_MAX_DIMS = 8
+RR_MAX_PLANES = 16
+
+STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_ALIAS",
+          4: "RR_ERR_UNSUPPORTED", 5: "RR_ERR_NO_MEMORY", 6: "RR_ERR_BUSY",
+          7: "RR_ERR_NOT_READY", 8: "RR_ERR_HIP"}
+RR_OK, RR_ERR_NOT_READY = 0, 7
+
+EXPORTS = ("rr_permute", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
+           "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
+           "rr_serve_poll", "rr_serve_release", "rr_serve_destroy", "rr_serve_get_stats",
+           "rr_order_to_perm", "rr_plan_describe", "rr_set_tile_override",
+           "rr_status_string", "rr_last_error", "rr_version")
+
+
+class RRError(RuntimeError):
+    def __init__(self, status: int, detail: str):
+        self.status = status
+        super().__init__(f"{STATUS.get(status, status)}: {detail}")
+
+
+class Job(ctypes.Structure):
+    _fields_ = [("dst", ctypes.c_void_p), ("src", ctypes.c_void_p), ("ndim", ctypes.c_int32),
+                ("elem_size", ctypes.c_int32), ("dims", ctypes.c_int64 * RR_MAX_DIMS),
+                ("perm", ctypes.c_int32 * RR_MAX_DIMS)]
+
+
+class ServeConfig(ctypes.Structure):
+    _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
+                ("max_batch_jobs", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
+                ("hbm_budget_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64),
+                ("tick_us", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+
+
+class JobResult(ctypes.Structure):
+    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dst", ctypes.c_void_p),
+                ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
+                ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
+
+
+class ServeStats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "batches", "chunks",
+                                               "bytes_moved", "budget_peak", "budget_used")]
+
+
+_lib = None
+
+
+def lib() -> ctypes.CDLL:
+    """Load librr.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(f"{LIB_PATH} is missing: build it with `python -m paper_1011_3583_amd.build`")
+    L = ctypes.CDLL(LIB_PATH)
+    vp, i32, i64 = ctypes.c_void_p, ctypes.c_int, ctypes.c_int64
+    i64p, i32p = ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int)
+    L.rr_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp]
+    L.rr_interlace.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i32, vp]
+    L.rr_deinterlace.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i32, vp]
+    L.rr_permute_batched.argtypes = [ctypes.POINTER(Job), i32, vp]
+    L.rr_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
+    L.rr_serve_alloc.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
+    L.rr_serve_free.argtypes = [vp, vp]
+    L.rr_serve_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
+    L.rr_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(JobResult)]
+    L.rr_serve_release.argtypes = [vp, ctypes.c_uint64]
+    L.rr_serve_destroy.argtypes = [vp]
+    L.rr_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
+    L.rr_order_to_perm.argtypes = [i32, i32p, i32p]
+    L.rr_plan_describe.argtypes = [vp, vp, i32, i64p, i32p, i32, ctypes.c_char_p, i32]
+    L.rr_set_tile_override.argtypes = [i32, i32, i32]
+    L.rr_status_string.argtypes = [i32]
+    L.rr_status_string.restype = ctypes.c_char_p
+    L.rr_last_error.restype = ctypes.c_char_p
+    L.rr_version.restype = ctypes.c_char_p
+    for name in EXPORTS:
+        fn = getattr(L, name)
+        if name not in ("rr_status_string", "rr_last_error", "rr_version"):
+            fn.restype = ctypes.c_int
+    _lib = L
+    return L
+
+
+def last_error() -> str:
+    return lib().rr_last_error().decode()
+
+
+def check(status: int) -> int:
+    if status != RR_OK:
+        raise RRError(status, last_error())
+    return status
+
+
+def _i64(seq):
+    return (ctypes.c_int64 * max(1, len(seq)))(*[int(x) for x in seq])
+
+
+def _i32(seq):
+    return (ctypes.c_int * max(1, len(seq)))(*[int(x) for x in seq])
+
+
+def _stream_handle(stream) -> int:
+    if stream is None:
+        import torch
+        return torch.cuda.current_stream().cuda_stream
+    if isinstance(stream, int):
+        return stream
+    return stream.cuda_stream
+
+
+# ----------------------------------------------------------------- raw pointer API
+def permute_raw(dst: int, src: int, dims, perm, elem_size: int, stream=0) -> int:
+    """rr_permute on raw device addresses; returns the rr_status (no raise)."""
+    return lib().rr_permute(dst, src, len(dims), _i64(dims), _i32(perm), int(elem_size),
+                            _stream_handle(stream))
+
+
+def interlace_raw(dst: int, srcs, count: int, elem_size: int, stream=0) -> int:
+    n = len(srcs)
+    arr = (ctypes.c_void_p * max(1, n))(*srcs)
+    return lib().rr_interlace(dst, arr, n, int(count), int(elem_size), _stream_handle(stream))
+
+
+def deinterlace_raw(dsts, src: int, count: int, elem_size: int, stream=0) -> int:
+    n = len(dsts)
+    arr = (ctypes.c_void_p * max(1, n))(*dsts)
+    return lib().rr_deinterlace(arr, src, n, int(count), int(elem_size), _stream_handle(stream))
+
+
+def make_jobs(specs):
+    """specs: iterable of (dst_ptr, src_ptr, dims, perm, elem_size) -> ctypes array of Job."""
+    specs = list(specs)
+    arr = (Job * max(1, len(specs)))()
+    for i, (d, s, dims, perm, e) in enumerate(specs):
+        if len(dims) > RR_MAX_DIMS:
+            raise ValueError("too many dims")
+        arr[i].dst, arr[i].src, arr[i].ndim, arr[i].elem_size = d, s, len(dims), e
+        for k, v in enumerate(dims):
+            arr[i].dims[k] = int(v)
+        for k, v in enumerate(perm):
+            arr[i].perm[k] = int(v)
+    return arr
+
+
+def permute_batched_raw(jobs, njobs: int | None = None, stream=0) -> int:
+    if not isinstance(jobs, ctypes.Array):
+        jobs = make_jobs(jobs)
+        njobs = len(jobs) if njobs is None else njobs
+    n = len(jobs) if njobs is None else njobs
+    return lib().rr_permute_batched(jobs, n, _stream_handle(stream))
+
+
+def order_to_perm(order):
+    n = len(order)
+    out = (ctypes.c_int * n)()
+    check(lib().rr_order_to_perm(n, _i32(order), out))
+    return tuple(out)
+
+
+def plan_describe(dims, perm, elem_size: int, dst: int = 0, src: int = 0) -> dict:
+    buf = ctypes.create_string_buffer(1024)
+    check(lib().rr_plan_describe(dst, src, len(dims), _i64(dims), _i32(perm), int(elem_size), buf, 1024))
+    out = {}
+    for tok in buf.value.decode().split():
+        k, v = tok.split("=", 1)
+        out[k] = v
+    return out
+
+
+def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out: bool = False):
+    check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), 1 if order_out else 0))
+
+
+# ----------------------------------------------------------------- torch helpers
+def permute(src, perm, out=None, stream=None):
+    """Permute a contiguous CUDA tensor (elements copied as opaque bytes)."""
+    import torch
+    if not src.is_contiguous():
+        raise ValueError("src must be contiguous")
+    dims = tuple(src.shape)
+    perm = tuple(int(p) for p in perm)
+    oshape = tuple(dims[p] for p in perm)
+    if out is None:
+        out = torch.empty(oshape, dtype=src.dtype, device=src.device)
+    check(permute_raw(out.data_ptr(), src.data_ptr(), dims, perm, src.element_size(), stream))
+    return out
+
+
+def interlace(planes, out=None, stream=None):
+    import torch
+    n = len(planes)
+    count = planes[0].numel()
+    if out is None:
+        out = torch.empty((count, n), dtype=planes[0].dtype, device=planes[0].device)
+    check(interlace_raw(out.data_ptr(), [p.data_ptr() for p in planes], count, planes[0].element_size(),
+                        stream))
+    return out
+
+
+def deinterlace(src, n: int, outs=None, stream=None):
+    import torch
+    count = src.numel() // n
+    if outs is None:
+        outs = [torch.empty(count, dtype=src.dtype, device=src.device) for _ in range(n)]
+    check(deinterlace_raw([o.data_ptr() for o in outs], src.data_ptr(), count, src.element_size(), stream))
+    return outs
+
+
+class Server:
+    """Thin wrapper over rr_serve_*."""
+
+    def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_batch_jobs: int = 1024,
+                 queue_capacity: int = 1 << 16, chunk_bytes: int = 64 << 20, tick_us: int = 20,
+                 device: int = 0):
+        cfg = ServeConfig(device, max_inflight, max_batch_jobs, queue_capacity, hbm_budget_bytes,
+                          chunk_bytes, tick_us, 0)
+        h = ctypes.c_void_p()
+        check(lib().rr_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
+        self.h = h
+
+    def alloc(self, nbytes: int) -> int:
+        p = ctypes.c_void_p()
+        check(lib().rr_serve_alloc(self.h, int(nbytes), ctypes.byref(p)))
+        return p.value
+
+    def free(self, ptr: int):
+        check(lib().rr_serve_free(self.h, ptr))
+
+    def submit_raw(self, job) -> tuple[int, int]:
+        t = ctypes.c_uint64()
+        st = lib().rr_serve_submit(self.h, ctypes.byref(job), ctypes.byref(t))
+        return st, t.value
+
+    def submit(self, dst, src, dims, perm, elem_size) -> int:
+        job = make_jobs([(dst or 0, src, dims, perm, elem_size)])[0]
+        st, t = self.submit_raw(job)
+        check(st)
+        return t
+
+    def poll(self, ticket: int):
+        r = JobResult()
+        st = lib().rr_serve_poll(self.h, int(ticket), ctypes.byref(r))
+        if st == RR_ERR_NOT_READY:
+            return None
+        check(st)
+        return r
+
+    def release(self, ticket: int):
+        check(lib().rr_serve_release(self.h, int(ticket)))
+
+    def stats(self) -> dict:
+        s = ServeStats()
+        check(lib().rr_serve_get_stats(self.h, ctypes.byref(s)))
+        return {n: getattr(s, n) for n, _ in ServeStats._fields_}
+
+    def close(self):
+        if self.h:
+            check(lib().rr_serve_destroy(self.h))
+            self.h = None
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *exc):
+        self.close()

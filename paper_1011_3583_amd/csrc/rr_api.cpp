@@ -1,0 +1,173 @@
+// rr_api.cpp -- the extern "C" entry points of librr (see include/rr.h).
+#include <hip/hip_runtime_api.h>
+
+#include <cstdio>
+#include <cstring>
+#include <string>
+
+#include "rr_internal.hpp"
+#include "rr_kernels.hpp"
+#include "rr_plan.hpp"
+
+namespace rr {
+
+static thread_local std::string g_last_error;
+
+rr_status fail(rr_status s, const std::string& why) {
+    g_last_error = why;
+    return s;
+}
+
+void clear_error() { g_last_error.clear(); }
+
+bool ranges_overlap(uint64_t a, uint64_t na, uint64_t b, uint64_t nb) {
+    if (na == 0 || nb == 0) return false;
+    return a < b + nb && b < a + na;
+}
+
+rr_status hip_fail(hipError_t e, const char* what) {
+    char buf[256];
+    std::snprintf(buf, sizeof buf, "%s: %s (%d)", what, hipGetErrorString(e), (int)e);
+    return fail(RR_ERR_HIP, buf);
+}
+
+rr_status validate_permute(const void* dst, const void* src, int ndim, const int64_t* dims,
+                           const int* perm, int elem_size, Canon* c) {
+    std::string why;
+    rr_status st = canonicalize(ndim, dims, perm, elem_size, c, &why);
+    if (st != RR_OK) return fail(st, why);
+    if (c->total_bytes == 0) return RR_OK;
+    if (!dst || !src) return fail(RR_ERR_INVALID_ARG, "NULL buffer for a non-empty problem");
+    if (ranges_overlap((uint64_t)dst, (uint64_t)c->total_bytes, (uint64_t)src, (uint64_t)c->total_bytes))
+        return fail(RR_ERR_ALIAS, "source and destination overlap");
+    return RR_OK;
+}
+
+}  // namespace rr
+
+using namespace rr;
+
+extern "C" {
+
+rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims, const int* perm,
+                     int elem_size, rr_stream_t stream) {
+    clear_error();
+    Canon c;
+    rr_status st = validate_permute(dst, src, ndim, dims, perm, elem_size, &c);
+    if (st != RR_OK) return st;
+    if (c.total_bytes == 0) return RR_OK;
+    Plan p;
+    std::string why;
+    st = plan_permute((uint64_t)dst, (uint64_t)src, c, tile_override(), &p, &why);
+    if (st != RR_OK) return fail(st, why);
+    hipError_t e = launch_plan(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rr_permute launch");
+    return RR_OK;
+}
+
+static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
+                                  int elem_size, rr_stream_t stream, bool de) {
+    clear_error();
+    if (n < 1 || n > RR_MAX_PLANES) return fail(RR_ERR_INVALID_ARG, "n must be 1..RR_MAX_PLANES");
+    if (count < 0) return fail(RR_ERR_INVALID_ARG, "count must be >= 0");
+    if (elem_size < 1 || elem_size > 16) return fail(RR_ERR_INVALID_ARG, "elem_size must be 1..16");
+    if (!planes) return fail(RR_ERR_INVALID_ARG, "plane array is NULL");
+    int64_t plane_bytes, total;
+    if (__builtin_mul_overflow(count, (int64_t)elem_size, &plane_bytes) ||
+        __builtin_mul_overflow(plane_bytes, (int64_t)n, &total))
+        return fail(RR_ERR_OVERFLOW, "byte count overflows int64");
+    if (count == 0) return RR_OK;
+    if (!flat) return fail(RR_ERR_INVALID_ARG, "NULL joined buffer");
+    uint64_t pl[RR_MAX_PLANES];
+    for (int c = 0; c < n; ++c) {
+        if (!planes[c]) return fail(RR_ERR_INVALID_ARG, "NULL plane pointer");
+        pl[c] = (uint64_t)planes[c];
+        if (ranges_overlap(pl[c], plane_bytes, (uint64_t)flat, total))
+            return fail(RR_ERR_ALIAS, "a plane overlaps the joined buffer");
+    }
+    if (de)
+        for (int c = 0; c < n; ++c)
+            for (int c2 = c + 1; c2 < n; ++c2)
+                if (ranges_overlap(pl[c], plane_bytes, pl[c2], plane_bytes))
+                    return fail(RR_ERR_ALIAS, "output planes overlap");
+    Plan p;
+    std::string why;
+    rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, tile_override(), &p, &why);
+    if (st != RR_OK) return fail(st, why);
+    hipError_t e = launch_plan(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, de ? "rr_deinterlace launch" : "rr_interlace launch");
+    return RR_OK;
+}
+
+rr_status rr_interlace(void* dst, const void* const* srcs, int n, int64_t count, int elem_size,
+                       rr_stream_t stream) {
+    return interlace_common(dst, srcs, n, count, elem_size, stream, false);
+}
+
+rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t count, int elem_size,
+                         rr_stream_t stream) {
+    return interlace_common(const_cast<void*>(src), (const void* const*)dsts, n, count, elem_size,
+                            stream, true);
+}
+
+rr_status rr_order_to_perm(int ndim, const int* paper_order, int* perm_out) {
+    clear_error();
+    if (ndim < 1 || ndim > RR_MAX_DIMS || !paper_order || !perm_out)
+        return fail(RR_ERR_INVALID_ARG, "bad ndim or NULL array");
+    bool seen[RR_MAX_DIMS] = {};
+    for (int k = 0; k < ndim; ++k) {
+        int o = paper_order[k];
+        if (o < 0 || o >= ndim || seen[o]) return fail(RR_ERR_INVALID_ARG, "order is not a permutation");
+        seen[o] = true;
+    }
+    for (int j = 0; j < ndim; ++j) perm_out[j] = ndim - 1 - paper_order[ndim - 1 - j];
+    return RR_OK;
+}
+
+rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
+                           const int* perm, int elem_size, char* buf, int buflen) {
+    clear_error();
+    if (!buf || buflen < 1) return fail(RR_ERR_INVALID_ARG, "NULL output buffer");
+    Canon c;
+    std::string why;
+    rr_status st = canonicalize(ndim, dims, perm, elem_size, &c, &why);
+    if (st != RR_OK) return fail(st, why);
+    Plan p;
+    st = plan_permute((uint64_t)dst, (uint64_t)src, c, tile_override(), &p, &why);
+    if (st != RR_OK) return fail(st, why);
+    std::string s = describe(p);
+    std::snprintf(buf, (size_t)buflen, "%s", s.c_str());
+    return RR_OK;
+}
+
+rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
+    clear_error();
+    if (in_row_bytes < 0 || out_row_bytes < 0 || in_row_bytes > 4096 || out_row_bytes > 4096)
+        return fail(RR_ERR_INVALID_ARG, "row bytes must be 0..4096");
+    TileOptions& o = tile_override();
+    o.in_row_bytes = in_row_bytes;
+    o.out_row_bytes = out_row_bytes;
+    o.order_out = (flags & 1) ? 1 : 0;
+    return RR_OK;
+}
+
+const char* rr_status_string(rr_status s) {
+    switch (s) {
+        case RR_OK: return "RR_OK";
+        case RR_ERR_INVALID_ARG: return "RR_ERR_INVALID_ARG";
+        case RR_ERR_OVERFLOW: return "RR_ERR_OVERFLOW";
+        case RR_ERR_ALIAS: return "RR_ERR_ALIAS";
+        case RR_ERR_UNSUPPORTED: return "RR_ERR_UNSUPPORTED";
+        case RR_ERR_NO_MEMORY: return "RR_ERR_NO_MEMORY";
+        case RR_ERR_BUSY: return "RR_ERR_BUSY";
+        case RR_ERR_NOT_READY: return "RR_ERR_NOT_READY";
+        case RR_ERR_HIP: return "RR_ERR_HIP";
+    }
+    return "RR_ERR_UNKNOWN";
+}
+
+const char* rr_last_error(void) { return g_last_error.c_str(); }
+
+const char* rr_version(void) { return "librr 0.1 (gfx950)"; }
+
+}  // extern "C"

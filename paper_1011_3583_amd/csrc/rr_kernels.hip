@@ -1,0 +1,108 @@
+// rr_kernels.hip -- gfx950 kernels for N-D data rearrangement.
+//
+// Pure data movement, so no MFMA: every kernel is bound by HBM bandwidth and is
+// shaped so that both its read side and its write side move whole 16-byte
+// vectors along contiguous memory (the paper's requirement that "coalescing is
+// maintained during both read and write", Sec. III.B).
+//
+//  * k_copy  -- identity after canonicalisation (the order [0 1 ... ] row of
+//               Table 1, which the paper measures as a memcpy).
+//  * k_run   -- permutes whose fastest axis stays fastest: every output run is
+//               a contiguous input run, copied with vector loads and stores.
+//  * k_tile  -- a true transpose between the input's fastest axis (or axes) and
+//               the output's fastest axis (or axes), staged through an LDS
+//               tile (Sec. III.B's shared-memory tile; Sec. III.C's shared
+//               buffer for interlace).  Each lane reads G rows of G elements
+//               (G*U = up to 16 bytes) from LDS, transposes the GxG block in
+//               registers, and writes G output vectors -- so LDS traffic is in
+//               16-byte operations even for 1- and 2-byte elements.
+#include <hip/hip_runtime.h>
+
+#include "rr_device.hpp"
+#include "rr_kernels.hpp"
+
+namespace rr {
+
+template <int W>
+__global__ __launch_bounds__(NT) void k_copy(const CopyArgs a) {
+    copy_thread<W>(a, blockIdx.x, gridDim.x, threadIdx.x);
+}
+
+template <int W>
+__global__ __launch_bounds__(NT) void k_run(const RunArgs a) {
+    run_thread<W>(a, blockIdx.x, threadIdx.x);
+}
+
+template <int U, int G>
+__global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
+    extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
+    const TileCtx t = tile_decode(a, blockIdx.x);
+    read_dispatch<G>(a, t, smem, threadIdx.x);
+    __syncthreads();
+    write_phase<U, G>(a, t, smem, threadIdx.x);
+}
+
+// ----------------------------------------------------------------- launch
+template <int U, int G>
+static hipError_t launch_tile_ug(const TileArgs& a, uint32_t grid, hipStream_t st) {
+    static bool attr_done = false;
+    if (!attr_done) {
+        hipError_t e = hipFuncSetAttribute(reinterpret_cast<const void*>(&k_tile<U, G>),
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 65536);
+        if (e != hipSuccess) return e;
+        attr_done = true;
+    }
+    hipLaunchKernelGGL((k_tile<U, G>), dim3(grid), dim3(NT), a.lds_bytes, st, a);
+    return hipGetLastError();
+}
+
+static hipError_t launch_tile(const TileArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.unit * 100 + a.g) {
+        case 101: return launch_tile_ug<1, 1>(a, grid, st);
+        case 102: return launch_tile_ug<1, 2>(a, grid, st);
+        case 104: return launch_tile_ug<1, 4>(a, grid, st);
+        case 108: return launch_tile_ug<1, 8>(a, grid, st);
+        case 116: return launch_tile_ug<1, 16>(a, grid, st);
+        case 201: return launch_tile_ug<2, 1>(a, grid, st);
+        case 202: return launch_tile_ug<2, 2>(a, grid, st);
+        case 204: return launch_tile_ug<2, 4>(a, grid, st);
+        case 208: return launch_tile_ug<2, 8>(a, grid, st);
+        case 401: return launch_tile_ug<4, 1>(a, grid, st);
+        case 402: return launch_tile_ug<4, 2>(a, grid, st);
+        case 404: return launch_tile_ug<4, 4>(a, grid, st);
+        case 801: return launch_tile_ug<8, 1>(a, grid, st);
+        case 802: return launch_tile_ug<8, 2>(a, grid, st);
+        case 1601: return launch_tile_ug<16, 1>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_plan(const Plan& p, hipStream_t st) {
+    switch (p.kind) {
+        case K_EMPTY:
+            return hipSuccess;
+        case K_COPY:
+            switch (p.copy.wbytes) {
+                case 16: hipLaunchKernelGGL(k_copy<16>, dim3(p.grid), dim3(NT), 0, st, p.copy); break;
+                case 8: hipLaunchKernelGGL(k_copy<8>, dim3(p.grid), dim3(NT), 0, st, p.copy); break;
+                case 4: hipLaunchKernelGGL(k_copy<4>, dim3(p.grid), dim3(NT), 0, st, p.copy); break;
+                case 2: hipLaunchKernelGGL(k_copy<2>, dim3(p.grid), dim3(NT), 0, st, p.copy); break;
+                default: hipLaunchKernelGGL(k_copy<1>, dim3(p.grid), dim3(NT), 0, st, p.copy); break;
+            }
+            return hipGetLastError();
+        case K_RUN:
+            switch (p.run.wbytes) {
+                case 16: hipLaunchKernelGGL(k_run<16>, dim3(p.grid), dim3(NT), 0, st, p.run); break;
+                case 8: hipLaunchKernelGGL(k_run<8>, dim3(p.grid), dim3(NT), 0, st, p.run); break;
+                case 4: hipLaunchKernelGGL(k_run<4>, dim3(p.grid), dim3(NT), 0, st, p.run); break;
+                case 2: hipLaunchKernelGGL(k_run<2>, dim3(p.grid), dim3(NT), 0, st, p.run); break;
+                default: hipLaunchKernelGGL(k_run<1>, dim3(p.grid), dim3(NT), 0, st, p.run); break;
+            }
+            return hipGetLastError();
+        case K_TILE:
+            return launch_tile(p.tile, p.grid, st);
+    }
+    return hipErrorInvalidValue;
+}
+
+}  // namespace rr

@@ -1,0 +1,447 @@
+// rr_plan.cpp -- validation, canonicalisation and kernel planning (host only).
+//
+// A permute (Sec. III.B) is reduced to the smallest equivalent problem before a
+// kernel is chosen:
+//   1. axes of extent 1 are dropped (Table 2 of the paper carries such axes);
+//   2. input axes that stay adjacent and in the same order in the output are
+//      fused into one axis (the offset/stride representation only needs one
+//      stride per fused axis);
+//   3. if the fastest input axis is also the fastest output axis it is folded
+//      into the element, which becomes a contiguous run of bytes.
+// What is left is either a plain copy, a copy of long runs, or a true
+// transpose between the input's fastest axis and the output's fastest axis --
+// the paper's choice of the 2-D plane "of the fastest changing dimensions of
+// the input and desired order" (Sec. III.B), here widened to several axes per
+// side when extents are short.
+#include "rr_plan.hpp"
+
+#include <algorithm>
+#include <cstring>
+#include <sstream>
+
+namespace rr {
+
+Magic make_magic(uint32_t d) {
+    if (d == 0) d = 1;
+    uint32_t l = 0;
+    while ((uint64_t(1) << l) < d) ++l;
+    uint64_t mul = ((uint64_t(1) << 32) * ((uint64_t(1) << l) - d)) / d + 1;
+    return Magic{(uint32_t)mul, l};
+}
+
+TileOptions& tile_override() {
+    static TileOptions o;
+    return o;
+}
+
+static bool mul_ovf(int64_t a, int64_t b, int64_t* r) { return __builtin_mul_overflow(a, b, r); }
+
+rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_size,
+                       Canon* out, std::string* why) {
+    if (ndim > RR_MAX_DIMS) {
+        *why = "ndim exceeds RR_MAX_DIMS";
+        return RR_ERR_UNSUPPORTED;
+    }
+    if (ndim < 1) { *why = "ndim must be >= 1"; return RR_ERR_INVALID_ARG; }
+    if (!dims || !perm) { *why = "dims and perm must be non-NULL"; return RR_ERR_INVALID_ARG; }
+    if (elem_size < 1 || elem_size > 16) { *why = "elem_size must be 1..16"; return RR_ERR_INVALID_ARG; }
+    bool seen[MAXR] = {};
+    for (int j = 0; j < ndim; ++j) {
+        if (perm[j] < 0 || perm[j] >= ndim || seen[perm[j]]) {
+            *why = "perm is not a permutation of 0..ndim-1";
+            return RR_ERR_INVALID_ARG;
+        }
+        seen[perm[j]] = true;
+    }
+    int64_t count = 1;
+    for (int k = 0; k < ndim; ++k) {
+        if (dims[k] < 0) { *why = "negative extent"; return RR_ERR_INVALID_ARG; }
+        if (mul_ovf(count, dims[k], &count)) { *why = "element count overflows int64"; return RR_ERR_OVERFLOW; }
+    }
+    int64_t bytes;
+    if (mul_ovf(count, elem_size, &bytes)) { *why = "byte count overflows int64"; return RR_ERR_OVERFLOW; }
+
+    Canon c;
+    c.total_bytes = bytes;
+    if (count == 0) {
+        c.rank = 0; c.count = 0; c.elem_bytes = elem_size;
+        *out = c;
+        return RR_OK;
+    }
+    // 1. squeeze extent-1 axes
+    int newidx[MAXR];
+    int64_t d[MAXR];
+    int r = 0;
+    for (int k = 0; k < ndim; ++k) {
+        if (dims[k] != 1) { newidx[k] = r; d[r++] = dims[k]; } else newidx[k] = -1;
+    }
+    int p[MAXR];
+    int j2 = 0;
+    for (int j = 0; j < ndim; ++j)
+        if (dims[perm[j]] != 1) p[j2++] = newidx[perm[j]];
+    // 2. fuse runs of input axes that stay consecutive in the output
+    int gstart[MAXR], glen[MAXR];
+    int ng = 0;
+    for (int j = 0; j < r; ++j) {
+        if (j > 0 && p[j] == p[j - 1] + 1) glen[ng - 1]++;
+        else { gstart[ng] = p[j]; glen[ng] = 1; ++ng; }
+    }
+    // groups are listed in output order; rank them by input position
+    int rank_of[MAXR];
+    for (int g = 0; g < ng; ++g) {
+        int rk = 0;
+        for (int h = 0; h < ng; ++h) if (gstart[h] < gstart[g]) ++rk;
+        rank_of[g] = rk;
+    }
+    int64_t cd[MAXR];
+    int cp[MAXR];
+    for (int g = 0; g < ng; ++g) {
+        int64_t e = 1;
+        for (int a = 0; a < glen[g]; ++a) e *= d[gstart[g] + a];
+        cd[rank_of[g]] = e;
+        cp[g] = rank_of[g];
+    }
+    // 3. fold a trailing axis that is fastest on both sides into the element
+    int64_t R = elem_size;
+    int rc = ng;
+    while (rc >= 1 && cp[rc - 1] == rc - 1) {
+        R *= cd[rc - 1];
+        --rc;
+    }
+    c.rank = rc;
+    c.elem_bytes = R;
+    c.count = 1;
+    for (int k = 0; k < rc; ++k) { c.dims[k] = cd[k]; c.perm[k] = cp[k]; c.count *= cd[k]; }
+    *out = c;
+    return RR_OK;
+}
+
+void plan_copy(uint64_t dst, uint64_t src, uint64_t nbytes, Plan* p) {
+    p->kind = K_COPY;
+    p->bytes = nbytes;
+    CopyArgs& a = p->copy;
+    std::memset(&a, 0, sizeof(a));
+    uint32_t W = 16;
+    while (W > 1 && ((src - dst) % W)) W >>= 1;
+    uint64_t head = (W - (dst % W)) % W;
+    if (head > nbytes) head = nbytes;
+    uint64_t body = (nbytes - head) / W;
+    uint64_t tail = nbytes - head - body * W;
+    a.src = src; a.dst = dst; a.nvec = body; a.head = (uint32_t)head; a.tail = (uint32_t)tail; a.wbytes = W;
+    uint64_t per_block = (uint64_t)NT * 4;
+    uint64_t g = (body + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 65536) g = 65536;  // grid-stride beyond this
+    p->grid = (uint32_t)g;
+}
+
+static int pow2_divisor_cap16(int64_t x) {
+    int u = 1;
+    while (u < 16 && (x % (u * 2)) == 0) u <<= 1;
+    return u;
+}
+
+static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, std::string* why) {
+    p->kind = K_RUN;
+    RunArgs& a = p->run;
+    std::memset(&a, 0, sizeof(a));
+    const int r = c.rank;
+    const int64_t R = c.elem_bytes;
+    uint32_t W = 16;
+    while (W > 1 && (src % W || dst % W || R % W)) W >>= 1;
+    int64_t vpr = R / W;
+    int64_t nvec = c.count * vpr;
+    if (vpr > 0xffffffffLL || nvec > 0xffffffffLL) {
+        *why = "run-copy problem exceeds 2^32 vectors per launch";
+        return RR_ERR_UNSUPPORTED;
+    }
+    int64_t sin_el[MAXR];
+    int64_t s = 1;
+    for (int k = r - 1; k >= 0; --k) { sin_el[k] = s; s *= c.dims[k]; }
+    a.src = src; a.dst = dst; a.nvec = (uint32_t)nvec; a.vpr = (uint32_t)vpr;
+    a.mvpr = make_magic((uint32_t)vpr); a.wbytes = W; a.nax = r; a.run_bytes = (uint64_t)R;
+    for (int j = 0; j < r; ++j) {
+        a.on[j] = (uint32_t)c.dims[c.perm[j]];
+        a.om[j] = make_magic(a.on[j]);
+        a.sin[j] = (uint64_t)(sin_el[c.perm[j]] * R);
+    }
+    uint64_t per_block = (uint64_t)NT * 4;
+    uint64_t g = ((uint64_t)nvec + per_block - 1) / per_block;
+    if (g > 0x7fffffffULL) { *why = "grid too large"; return RR_ERR_UNSUPPORTED; }
+    p->grid = (uint32_t)std::max<uint64_t>(1, g);
+    p->bytes = (uint64_t)c.total_bytes;
+    return RR_OK;
+}
+
+static int default_row_bytes(int U, bool in_side) {
+    switch (U) {
+        case 1: return 256;
+        case 2: return 256;
+        case 4: return 256;
+        case 8: return in_side ? 256 : 512;
+        default: return 512;
+    }
+}
+
+static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Fill the LDS / read / write geometry of a tile plan whose extents are set.
+static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_align_in,
+                             const TileOptions& opt, std::string* why) {
+    a.unit = U; a.g = G; a.k = k;
+    a.mk = make_magic(k);
+    const uint64_t rowbytes = (uint64_t)a.TA * a.R;
+    a.pitch = (uint32_t)((rowbytes + 15) / 16 * 16);
+    a.nch16 = a.pitch / 16;
+    uint32_t pw = 1;
+    while (pw * 2 <= a.nch16) pw <<= 1;
+    a.rotmask = pw - 1;
+    a.lds_bytes = a.pitch * a.TB;
+    if (a.lds_bytes > (uint32_t)opt.max_lds) { *why = "tile does not fit LDS"; return RR_ERR_UNSUPPORTED; }
+    uint32_t win = 16;
+    while (win > (uint32_t)U && ((row_align_in % win) || (rowbytes % win))) win >>= 1;
+    if (win < (uint32_t)U) win = U;
+    a.win = win;
+    a.rch = (uint32_t)(rowbytes / win);
+    a.mrch = make_magic(a.rch);
+    if (k == 1) {
+        a.nmb = a.TB / G;
+        a.nwork = a.nmb * (a.TA / G);
+    } else {
+        a.nmb = a.TB * k;      // units per output row
+        a.nwork = a.nmb * a.TA;
+    }
+    a.mnmb = make_magic(a.nmb);
+    return RR_OK;
+}
+
+static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
+                           Plan* p, std::string* why) {
+    p->kind = K_TILE;
+    TileArgs& a = p->tile;
+    std::memset(&a, 0, sizeof(a));
+    const int r = c.rank;
+    const int64_t* d = c.dims;
+    const int* pm = c.perm;
+    const int64_t R = c.elem_bytes;
+    int pos[MAXR];
+    for (int j = 0; j < r; ++j) pos[pm[j]] = j;
+    int64_t sin_el[MAXR], sout_el[MAXR];
+    {
+        int64_t s = 1;
+        for (int k = r - 1; k >= 0; --k) { sin_el[k] = s; s *= d[k]; }
+        s = 1;
+        for (int j = r - 1; j >= 0; --j) { sout_el[pm[j]] = s; s *= d[pm[j]]; }
+    }
+    int U = pow2_divisor_cap16(R);
+    U = std::min(U, std::min(addr_align(src), addr_align(dst)));
+    const int k = (int)(R / U);
+    const int a1 = r - 1, b1 = pm[r - 1];
+    int G = 1;
+    if (k == 1) {
+        G = 16 / U;
+        while (G > 1 && ((d[a1] % G) || (d[b1] % G) || addr_align(src) < U * G ||
+                         addr_align(dst) < U * G))
+            G >>= 1;
+    }
+    const int in_rb = opt.in_row_bytes > 0 ? opt.in_row_bytes : default_row_bytes(U, true);
+    const int out_rb = opt.out_row_bytes > 0 ? opt.out_row_bytes : default_row_bytes(U, false);
+    const int64_t targetA = std::max<int64_t>(G, cdiv(in_rb, R));
+    const int64_t targetB = std::max<int64_t>(G, cdiv(out_rb, R));
+
+    int A[MAXS], B[MAXS];
+    int nA = 0, nB = 0;
+    bool inA[MAXR] = {}, inB[MAXR] = {};
+    A[nA++] = a1; inA[a1] = true;
+    int64_t prodA = d[a1];
+    for (int nx = r - 2; prodA < targetA && nx >= 0 && nx != b1 && nA < MAXS; --nx) {
+        A[nA++] = nx; inA[nx] = true; prodA *= d[nx];
+    }
+    B[nB++] = b1; inB[b1] = true;
+    int64_t prodB = d[b1];
+    for (int jn = r - 2; prodB < targetB && jn >= 0 && !inA[pm[jn]] && nB < MAXS; --jn) {
+        B[nB++] = pm[jn]; inB[pm[jn]] = true; prodB *= d[pm[jn]];
+    }
+    int64_t t[MAXR];
+    for (int i = 0; i < r; ++i) t[i] = 1;
+    int64_t innerA = 1, innerB = 1;
+    for (int i = 0; i < nA - 1; ++i) { t[A[i]] = d[A[i]]; innerA *= d[A[i]]; }
+    for (int i = 0; i < nB - 1; ++i) { t[B[i]] = d[B[i]]; innerB *= d[B[i]]; }
+    const int aO = A[nA - 1], bO = B[nB - 1];
+    auto set_outer = [&](int ax, int64_t target, int64_t inner, bool single) {
+        int64_t v = std::min<int64_t>(d[ax], cdiv(target, inner));
+        if (single) v = std::min<int64_t>(d[ax], (v + G - 1) / G * G);
+        t[ax] = std::max<int64_t>(1, v);
+    };
+    set_outer(aO, targetA, innerA, nA == 1);
+    set_outer(bO, targetB, innerB, nB == 1);
+    // shrink until the tile fits in LDS
+    for (int guard = 0; guard < 64; ++guard) {
+        int64_t TA = innerA * t[aO], TB = innerB * t[bO];
+        int64_t bytes = TB * ((TA * R + 15) / 16 * 16);
+        if (bytes <= opt.max_lds) break;
+        int64_t stepA = nA == 1 ? G : 1, stepB = nB == 1 ? G : 1;
+        bool canA = t[aO] > stepA, canB = t[bO] > stepB;
+        if (!canA && !canB) { *why = "cannot fit a tile in LDS"; return RR_ERR_UNSUPPORTED; }
+        bool shrinkA = canA && (!canB || TA * R >= TB * R);
+        if (shrinkA) t[aO] = std::max(stepA, (t[aO] / 2 + stepA - 1) / stepA * stepA);
+        else t[bO] = std::max(stepB, (t[bO] / 2 + stepB - 1) / stepB * stepB);
+    }
+    a.TA = (uint32_t)(innerA * t[aO]);
+    a.TB = (uint32_t)(innerB * t[bO]);
+    a.TAinner = (uint32_t)innerA;
+    a.TBinner = (uint32_t)innerB;
+    a.nA = nA; a.nB = nB;
+    for (int i = 0; i < nA; ++i) {
+        a.tA[i] = (uint32_t)t[A[i]]; a.mA[i] = make_magic(a.tA[i]);
+        a.soutA[i] = (uint64_t)(sout_el[A[i]] * R);
+    }
+    for (int i = 0; i < nB; ++i) {
+        a.tB[i] = (uint32_t)t[B[i]]; a.mB[i] = make_magic(a.tB[i]);
+        a.sinB[i] = (uint64_t)(sin_el[B[i]] * R);
+    }
+    a.R = (uint32_t)R;
+    a.src = src; a.dst = dst;
+    // tile grid
+    int order[MAXR];
+    for (int i = 0; i < r; ++i) order[i] = i;
+    if (opt.order_out) for (int j = 0; j < r; ++j) order[j] = pm[j];
+    a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1;
+    uint64_t ntiles = 1;
+    for (int oi = 0; oi < r; ++oi) {
+        int s = order[oi];
+        bool tiled = inA[s] || inB[s];
+        int64_t n = tiled ? cdiv(d[s], t[s]) : d[s];
+        if (n <= 1) continue;
+        int g = a.ngrid++;
+        a.gn[g] = (uint32_t)n; a.gm[g] = make_magic((uint32_t)n);
+        int64_t step = tiled ? t[s] : 1;
+        a.gsin[g] = (uint64_t)(step * sin_el[s] * R);
+        a.gsout[g] = (uint64_t)(step * sout_el[s] * R);
+        if (s == aO) a.grid_aO = g;
+        if (s == bO) a.grid_bO = g;
+        ntiles *= (uint64_t)n;
+        if (ntiles > 0x7fffffffULL) { *why = "too many tiles for one launch"; return RR_ERR_UNSUPPORTED; }
+    }
+    a.aO_len = (uint32_t)d[aO]; a.aO_t = (uint32_t)t[aO];
+    a.bO_len = (uint32_t)d[bO]; a.bO_t = (uint32_t)t[bO];
+    a.ntiles = (uint32_t)ntiles;
+    // input rows start at multiples of d[a1]*R plus the tile's column offset
+    uint64_t ra = src | (uint64_t)(d[a1] * R);
+    if (nA == 1) ra |= (uint64_t)(t[a1] * R);
+    rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+    if (st != RR_OK) return st;
+    p->grid = a.ntiles;
+    p->bytes = (uint64_t)c.total_bytes;
+    return RR_OK;
+}
+
+rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
+                       Plan* p, std::string* why) {
+    p->c = c;
+    p->bytes = (uint64_t)c.total_bytes;
+    if (c.count == 0 || c.total_bytes == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
+    if (c.rank == 0) { plan_copy(dst, src, (uint64_t)c.total_bytes, p); return RR_OK; }
+    if (c.elem_bytes >= RUN_MIN_BYTES) return plan_run(dst, src, c, p, why);
+    return plan_tile(dst, src, c, opt, p, why);
+}
+
+// Interlace: virtual input (n planes, count) -> output (count, n).
+// De-interlace: input (count, n) -> virtual output (n planes, count).
+rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
+                         bool de, const TileOptions& opt, Plan* p, std::string* why) {
+    const uint64_t dst = flat;  // interlace: the joined output; de-interlace: the joined input
+    p->c = Canon{};
+    p->bytes = (uint64_t)(count * n * esize);
+    if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
+    if (n == 1) { plan_copy(de ? planes[0] : flat, de ? flat : planes[0], (uint64_t)(count * esize), p); return RR_OK; }
+    p->kind = K_TILE;
+    TileArgs& a = p->tile;
+    std::memset(&a, 0, sizeof(a));
+    const int64_t R = esize;
+    int al = addr_align(dst);
+    for (int c = 0; c < n; ++c) al = std::min(al, addr_align(planes[c]));
+    int U = std::min(pow2_divisor_cap16(R), al);
+    const int k = (int)(R / U);
+    int G = 1;
+    if (k == 1) {
+        G = 16 / U;
+        while (G > 1 && ((count % G) || (n % G) || al < U * G)) G >>= 1;
+    }
+    const int in_rb = opt.in_row_bytes > 0 ? opt.in_row_bytes : default_row_bytes(U, true);
+    const int out_rb = opt.out_row_bytes > 0 ? opt.out_row_bytes : default_row_bytes(U, false);
+    // aim for ~16 KiB tiles: the plane axis is short
+    const int64_t tile_target = 16384;
+    int64_t L = std::max<int64_t>(cdiv(de ? out_rb : in_rb, R), cdiv(tile_target, n * R));
+    L = std::min<int64_t>(count, (L + G - 1) / G * G);
+    while (L > G && (int64_t)((L * R + 15) / 16 * 16) * n > opt.max_lds && !de) L = std::max<int64_t>(G, L / 2 / G * G);
+    while (L > G && (int64_t)(((int64_t)n * R + 15) / 16 * 16) * L > opt.max_lds && de) L = std::max<int64_t>(G, L / 2 / G * G);
+    a.R = (uint32_t)R;
+    a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1;
+    int64_t nt = cdiv(count, L);
+    if (nt > 0x7fffffffLL) { *why = "too many tiles"; return RR_ERR_UNSUPPORTED; }
+    if (!de) {
+        // A = element axis (length L per tile), B = plane axis (n, full)
+        a.flags = TF_IN_TABLE;
+        a.src = 0; a.dst = dst;
+        a.TA = (uint32_t)L; a.TB = (uint32_t)n; a.TAinner = 1; a.TBinner = 1;
+        a.nA = 1; a.tA[0] = (uint32_t)L; a.mA[0] = make_magic((uint32_t)L); a.soutA[0] = (uint64_t)(n * R);
+        a.nB = 1; a.tB[0] = (uint32_t)n; a.mB[0] = make_magic((uint32_t)n); a.sinB[0] = 0;
+        if (nt > 1) {
+            a.ngrid = 1; a.gn[0] = (uint32_t)nt; a.gm[0] = make_magic((uint32_t)nt);
+            a.gsin[0] = (uint64_t)(L * R); a.gsout[0] = (uint64_t)(L * n * R); a.grid_aO = 0;
+        }
+        a.aO_len = (uint32_t)count; a.aO_t = (uint32_t)L;
+        a.bO_len = (uint32_t)n; a.bO_t = (uint32_t)n;
+        for (int c = 0; c < n; ++c) a.table[c] = planes[c];
+        uint64_t ra = (uint64_t)(L * R) | (uint64_t)(count * R);
+        for (int c = 0; c < n; ++c) ra |= planes[c];
+        rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+        if (st != RR_OK) return st;
+    } else {
+        // A = plane axis (n, full), B = element axis (length L per tile)
+        a.flags = TF_OUT_TABLE;
+        a.src = flat;
+        a.dst = 0;
+        a.TA = (uint32_t)n; a.TB = (uint32_t)L; a.TAinner = 1; a.TBinner = 1;
+        a.nA = 1; a.tA[0] = (uint32_t)n; a.mA[0] = make_magic((uint32_t)n); a.soutA[0] = 0;
+        a.nB = 1; a.tB[0] = (uint32_t)L; a.mB[0] = make_magic((uint32_t)L); a.sinB[0] = (uint64_t)(n * R);
+        if (nt > 1) {
+            a.ngrid = 1; a.gn[0] = (uint32_t)nt; a.gm[0] = make_magic((uint32_t)nt);
+            a.gsin[0] = (uint64_t)(L * n * R); a.gsout[0] = (uint64_t)(L * R); a.grid_bO = 0;
+        }
+        a.aO_len = (uint32_t)n; a.aO_t = (uint32_t)n;
+        a.bO_len = (uint32_t)count; a.bO_t = (uint32_t)L;
+        for (int c = 0; c < n; ++c) a.table[c] = planes[c];
+        uint64_t ra = a.src | (uint64_t)(n * R);
+        rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+        if (st != RR_OK) return st;
+    }
+    a.ntiles = (uint32_t)nt;
+    p->grid = a.ntiles;
+    return RR_OK;
+}
+
+std::string describe(const Plan& p) {
+    std::ostringstream o;
+    static const char* names[] = {"empty", "copy", "run", "tile"};
+    o << "class=" << names[p.kind];
+    const Canon& c = p.c;
+    o << " rank=" << c.rank << " dims=";
+    for (int k = 0; k < c.rank; ++k) o << (k ? "," : "") << c.dims[k];
+    o << " perm=";
+    for (int k = 0; k < c.rank; ++k) o << (k ? "," : "") << c.perm[k];
+    o << " esize_bytes=" << c.elem_bytes << " bytes=" << p.bytes << " grid=" << p.grid;
+    if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
+    if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr;
+    if (p.kind == K_TILE) {
+        const TileArgs& a = p.tile;
+        o << " unit=" << a.unit << " g=" << a.g << " k=" << a.k << " TA=" << a.TA << " TB=" << a.TB
+          << " nA=" << a.nA << " nB=" << a.nB << " win=" << a.win << " pitch=" << a.pitch
+          << " lds=" << a.lds_bytes << " ntiles=" << a.ntiles << " ngrid=" << a.ngrid
+          << " flags=" << a.flags;
+    }
+    return o.str();
+}
+
+}  // namespace rr

@@ -1,0 +1,155 @@
+// rr_plan.hpp -- problem canonicalisation and kernel plans (host side), plus the
+// plain-data argument blocks the HIP kernels read.  No HIP types appear here so
+// the planner can be exercised on a machine without a GPU.
+#pragma once
+
+#include <cstdint>
+#include <string>
+
+#include "../../include/rr.h"
+
+namespace rr {
+
+constexpr int MAXR = RR_MAX_DIMS;  // canonical rank never exceeds the input rank
+constexpr int MAXS = 4;            // axes on one side of a tile
+constexpr int NT = 256;            // threads per workgroup of the tiled kernels
+
+// Unsigned division by an invariant 32-bit divisor d >= 1 (Granlund & Montgomery,
+// "Division by Invariant Integers using Multiplication", PLDI 1994):
+//   l = ceil(log2 d),  mul = floor(2^32 * (2^l - d) / d) + 1,
+//   x / d = (mulhi(x, mul) + x) >> l   with a 33-bit intermediate sum.
+struct Magic {
+    uint32_t mul;
+    uint32_t shift;
+};
+Magic make_magic(uint32_t d);
+inline uint32_t magic_div_host(uint32_t x, Magic m) {
+    uint32_t hi = (uint32_t)(((uint64_t)x * m.mul) >> 32);
+    return (uint32_t)(((uint64_t)hi + x) >> m.shift);
+}
+
+// A permute problem after squeezing size-1 axes, fusing axes that stay adjacent
+// and in order, and folding the trailing unpermuted axis into the element.
+struct Canon {
+    int rank = 0;              // 0 means "plain copy of elem_bytes * count bytes"
+    int64_t dims[MAXR] = {};   // row-major input extents
+    int perm[MAXR] = {};       // out axis j reads input axis perm[j]
+    int64_t elem_bytes = 0;    // bytes per canonical element (run length)
+    int64_t count = 0;         // canonical elements (product of dims)
+    int64_t total_bytes = 0;   // bytes per side
+};
+
+enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3 };
+
+// ---------------------------------------------------------------- kernel args
+struct CopyArgs {
+    uint64_t src, dst;
+    uint64_t nvec;      // W-byte vectors in the body
+    uint32_t head;      // bytes copied one by one before the body
+    uint32_t tail;      // bytes copied one by one after the body
+    uint32_t wbytes;    // W
+    uint32_t pad_;
+};
+
+struct RunArgs {
+    uint64_t src, dst;
+    uint32_t nvec;        // total W-byte vectors
+    uint32_t vpr;         // vectors per run (run_bytes / W)
+    Magic mvpr;
+    uint32_t wbytes;      // W
+    int32_t nax;          // output axes (canonical rank)
+    uint32_t on[MAXR];    // output extents, slowest first
+    Magic om[MAXR];
+    uint64_t sin[MAXR];   // input byte stride of output axis j
+    uint64_t run_bytes;
+};
+
+enum TileFlags : uint32_t {
+    TF_IN_TABLE = 1u,    // input rows are absolute plane pointers (interlace)
+    TF_OUT_TABLE = 2u,   // output rows are absolute plane pointers (de-interlace)
+};
+
+struct TileArgs {
+    uint64_t src, dst;        // byte base addresses (0 in table mode)
+    uint32_t ntiles;
+    int32_t ngrid;            // tile-grid axes, slowest first
+    uint32_t gn[MAXR];        // tiles along each grid axis
+    Magic gm[MAXR];
+    uint64_t gsin[MAXR];      // input byte step per tile step
+    uint64_t gsout[MAXR];     // output byte step per tile step
+    int32_t grid_aO, grid_bO; // grid index of the partial outer A / B axis (-1: none)
+    uint32_t aO_len, aO_t;    // extent and tile extent of the outer A axis
+    uint32_t bO_len, bO_t;
+    uint32_t TAinner, TBinner;
+    uint32_t TA, TB;          // tile extents (elements): row length, row count
+    int32_t nA, nB;
+    uint32_t tA[MAXS];        // tile extent of each A axis (fastest first)
+    Magic mA[MAXS];
+    uint64_t soutA[MAXS];     // output byte stride of each A axis
+    uint32_t tB[MAXS];
+    Magic mB[MAXS];
+    uint64_t sinB[MAXS];      // input byte stride of each B axis
+    uint32_t R;               // bytes per element
+    uint32_t k;               // units per element
+    Magic mk;
+    uint32_t pitch;           // LDS row pitch in bytes (multiple of 16)
+    uint32_t nch16;           // pitch / 16
+    uint32_t rotmask;         // (largest power of two <= nch16) - 1
+    uint32_t win;             // read vector bytes
+    uint32_t rch;             // read chunks per row
+    Magic mrch;
+    uint32_t nmb;             // write micro-tiles per output row (TB / G); unit path: TB*k
+    Magic mnmb;
+    uint32_t nwork;           // write work items per tile
+    uint32_t flags;
+    uint32_t lds_bytes;
+    uint32_t unit;            // U
+    uint32_t g;               // G
+    uint32_t pad_;
+    uint64_t table[RR_MAX_PLANES];
+};
+
+struct TileOptions {
+    int in_row_bytes = 0;   // 0 = default
+    int out_row_bytes = 0;
+    int order_out = 0;      // 1: traverse tiles in output order
+    int max_lds = 65536;
+};
+
+// Process-wide override (autotuner hook).
+TileOptions& tile_override();
+
+// Validation + canonicalisation.  Writes a human-readable reason on failure.
+rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_size,
+                       Canon* out, std::string* why);
+
+// Alignment (largest power of two <= 16 dividing the address).
+inline int addr_align(uint64_t p) {
+    int a = 16;
+    while (a > 1 && (p % (uint64_t)a)) a >>= 1;
+    return a;
+}
+
+// Runs at least this long (bytes) are copied run by run without LDS.
+constexpr int64_t RUN_MIN_BYTES = 64;
+
+struct Plan {
+    Kind kind = K_EMPTY;
+    Canon c;
+    CopyArgs copy;
+    RunArgs run;
+    TileArgs tile;
+    uint32_t grid = 0;       // workgroups to launch
+    uint64_t bytes = 0;      // bytes per side
+};
+
+rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
+                       Plan* p, std::string* why);
+// flat = joined buffer (interlace output / de-interlace input); planes = the n sets.
+rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
+                         bool deinterlace, const TileOptions& opt, Plan* p, std::string* why);
+void plan_copy(uint64_t dst, uint64_t src, uint64_t nbytes, Plan* p);
+
+std::string describe(const Plan& p);
+
+}  // namespace rr

@@ -1,0 +1,188 @@
+// rr_emu.cpp -- CPU execution of librr's kernel bodies, for tests only.
+//
+// Builds the product's planner (rr_plan.cpp) and per-thread kernel bodies
+// (rr_device.hpp) for the host and runs every workgroup and thread of a launch
+// sequentially: the read phase of all threads, then (after what is a barrier on
+// the GPU) the write phase.  Every buffer -- source, destination, each plane and
+// each LDS tile -- is a separate heap allocation of exactly its size, so under
+// AddressSanitizer any out-of-bounds access of the GPU index arithmetic aborts
+// here instead of faulting a GPU.  LDS tiles are filled with a poison byte so a
+// read of a never-written LDS byte shows up as a wrong output byte.
+//
+// Input: a manifest, one job per line:
+//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order infile outfile
+//   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
+//   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
+// Prints one line per job: "ok <plan description>" or "err <status> <reason>".
+#include <cstdio>
+#include <cstdlib>
+#include <cstring>
+#include <fstream>
+#include <sstream>
+#include <string>
+#include <vector>
+
+#include "../../paper_1011_3583_amd/csrc/rr_device.hpp"
+#include "../../paper_1011_3583_amd/csrc/rr_plan.hpp"
+
+using namespace rr;
+
+static std::vector<uint8_t> read_file(const std::string& path) {
+    std::ifstream f(path, std::ios::binary);
+    return std::vector<uint8_t>((std::istreambuf_iterator<char>(f)), std::istreambuf_iterator<char>());
+}
+
+static void write_file(const std::string& path, const uint8_t* p, size_t n) {
+    std::ofstream f(path, std::ios::binary);
+    f.write(reinterpret_cast<const char*>(p), (std::streamsize)n);
+}
+
+template <int U, int G>
+static void run_tile_ug(const TileArgs& a, uint32_t grid) {
+    for (uint32_t tile = 0; tile < grid; ++tile) {
+        uint8_t* lds = new uint8_t[a.lds_bytes];
+        std::memset(lds, 0xA5, a.lds_bytes);
+        const TileCtx t = tile_decode(a, tile);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<G>(a, t, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) write_phase<U, G>(a, t, lds, tid);
+        delete[] lds;
+    }
+}
+
+static bool run_tile(const TileArgs& a, uint32_t grid) {
+    switch (a.unit * 100 + a.g) {
+        case 101: run_tile_ug<1, 1>(a, grid); return true;
+        case 102: run_tile_ug<1, 2>(a, grid); return true;
+        case 104: run_tile_ug<1, 4>(a, grid); return true;
+        case 108: run_tile_ug<1, 8>(a, grid); return true;
+        case 116: run_tile_ug<1, 16>(a, grid); return true;
+        case 201: run_tile_ug<2, 1>(a, grid); return true;
+        case 202: run_tile_ug<2, 2>(a, grid); return true;
+        case 204: run_tile_ug<2, 4>(a, grid); return true;
+        case 208: run_tile_ug<2, 8>(a, grid); return true;
+        case 401: run_tile_ug<4, 1>(a, grid); return true;
+        case 402: run_tile_ug<4, 2>(a, grid); return true;
+        case 404: run_tile_ug<4, 4>(a, grid); return true;
+        case 801: run_tile_ug<8, 1>(a, grid); return true;
+        case 802: run_tile_ug<8, 2>(a, grid); return true;
+        case 1601: run_tile_ug<16, 1>(a, grid); return true;
+    }
+    return false;
+}
+
+template <int W>
+static void run_copy_w(const CopyArgs& a, uint32_t grid) {
+    for (uint32_t b = 0; b < grid; ++b)
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) copy_thread<W>(a, b, grid, tid);
+}
+
+template <int W>
+static void run_run_w(const RunArgs& a, uint32_t grid) {
+    for (uint32_t b = 0; b < grid; ++b)
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) run_thread<W>(a, b, tid);
+}
+
+static bool emulate(const Plan& p) {
+    switch (p.kind) {
+        case K_EMPTY: return true;
+        case K_COPY:
+            switch (p.copy.wbytes) {
+                case 16: run_copy_w<16>(p.copy, p.grid); return true;
+                case 8: run_copy_w<8>(p.copy, p.grid); return true;
+                case 4: run_copy_w<4>(p.copy, p.grid); return true;
+                case 2: run_copy_w<2>(p.copy, p.grid); return true;
+                default: run_copy_w<1>(p.copy, p.grid); return true;
+            }
+        case K_RUN:
+            switch (p.run.wbytes) {
+                case 16: run_run_w<16>(p.run, p.grid); return true;
+                case 8: run_run_w<8>(p.run, p.grid); return true;
+                case 4: run_run_w<4>(p.run, p.grid); return true;
+                case 2: run_run_w<2>(p.run, p.grid); return true;
+                default: run_run_w<1>(p.run, p.grid); return true;
+            }
+        case K_TILE:
+            return run_tile(p.tile, p.grid);
+    }
+    return false;
+}
+
+int main(int argc, char** argv) {
+    if (argc < 2) { std::fprintf(stderr, "usage: rr_emu manifest\n"); return 2; }
+    std::ifstream mf(argv[1]);
+    std::string line;
+    while (std::getline(mf, line)) {
+        if (line.empty() || line[0] == '#') continue;
+        std::istringstream is(line);
+        std::string op;
+        is >> op;
+        TileOptions opt;
+        Plan plan;
+        std::string why;
+        if (op == "permute") {
+            int ndim; is >> ndim;
+            std::vector<int64_t> dims(ndim);
+            std::vector<int> perm(ndim);
+            for (auto& d : dims) is >> d;
+            for (auto& q : perm) is >> q;
+            int esize, soff, doff, order; std::string inf, outf;
+            is >> esize >> soff >> doff >> opt.in_row_bytes >> opt.out_row_bytes >> order >> inf >> outf;
+            opt.order_out = order;
+            Canon c;
+            rr_status st = canonicalize(ndim, dims.data(), perm.data(), esize, &c, &why);
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); continue; }
+            std::vector<uint8_t> in = read_file(inf);
+            const size_t nb = (size_t)c.total_bytes;
+            uint8_t* sbuf = new uint8_t[soff + nb + 1];
+            uint8_t* dbuf = new uint8_t[doff + nb + 1];
+            // exact-size views: the +1 keeps zero-byte buffers valid; nothing may touch it
+            if (nb) std::memcpy(sbuf + soff, in.data(), nb);
+            std::memset(dbuf, 0x5A, doff + nb + 1);
+            st = plan_permute((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff), c, opt, &plan, &why);
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); delete[] sbuf; delete[] dbuf; continue; }
+            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); delete[] sbuf; delete[] dbuf; continue; }
+            if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+            for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
+            write_file(outf, dbuf + doff, nb);
+            std::printf("ok %s\n", describe(plan).c_str());
+            delete[] sbuf;
+            delete[] dbuf;
+        } else if (op == "interlace" || op == "deinterlace") {
+            const bool de = op == "deinterlace";
+            int n, esize, off; int64_t count; std::string inf, outf;
+            is >> n >> count >> esize >> off >> opt.in_row_bytes >> opt.out_row_bytes >> inf >> outf;
+            std::vector<uint8_t> in = read_file(inf);
+            const size_t pb = (size_t)count * esize;
+            std::vector<uint8_t*> planes(n);
+            for (int c = 0; c < n; ++c) {
+                planes[c] = new uint8_t[off + pb + 1];
+                std::memset(planes[c], 0x5A, off + pb + 1);
+            }
+            uint8_t* flat = new uint8_t[off + pb * n + 1];
+            std::memset(flat, 0x5A, off + pb * n + 1);
+            if (!de) {
+                for (int c = 0; c < n; ++c) std::memcpy(planes[c] + off, in.data() + c * pb, pb);
+            } else {
+                std::memcpy(flat + off, in.data(), pb * n);
+            }
+            std::vector<uint64_t> pl(n);
+            for (int c = 0; c < n; ++c) pl[c] = (uint64_t)(planes[c] + off);
+            rr_status st = plan_interlace((uint64_t)(flat + off), pl.data(), n, count, esize, de, opt, &plan, &why);
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); continue; }
+            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); continue; }
+            if (!de) {
+                write_file(outf, flat + off, pb * n);
+            } else {
+                std::ofstream f(outf, std::ios::binary);
+                for (int c = 0; c < n; ++c) f.write(reinterpret_cast<const char*>(planes[c] + off), (std::streamsize)pb);
+            }
+            std::printf("ok %s\n", describe(plan).c_str());
+            for (int c = 0; c < n; ++c) delete[] planes[c];
+            delete[] flat;
+        } else {
+            std::printf("err -1 unknown op %s\n", op.c_str());
+        }
+        std::fflush(stdout);
+    }
+    return 0;
+}

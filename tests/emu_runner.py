@@ -1,0 +1,82 @@
+"""Drive the CPU emulator of librr's kernel bodies (tests/emu/rr_emu.cpp).
+
+The emulator is built with g++ under AddressSanitizer/UBSan from the library's
+own planner and per-thread kernel code; it is test infrastructure that lets the
+CPU suite check kernel index arithmetic and bounds without a GPU.
+"""
+import os
+import subprocess
+import tempfile
+
+import numpy as np
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+EMU_SRC = os.path.join(ROOT, "tests", "emu", "rr_emu.cpp")
+EMU_BIN = os.path.join(ROOT, "tests", "emu", "_build", "rr_emu")
+DEPS = [EMU_SRC,
+        os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_device.hpp"),
+        os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_plan.hpp"),
+        os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_plan.cpp"),
+        os.path.join(ROOT, "include", "rr.h")]
+
+
+def build():
+    if os.path.exists(EMU_BIN) and all(os.path.getmtime(EMU_BIN) >= os.path.getmtime(d) for d in DEPS):
+        return EMU_BIN
+    os.makedirs(os.path.dirname(EMU_BIN), exist_ok=True)
+    tmp = EMU_BIN + f".tmp{os.getpid()}"
+    cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
+           "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-Wall", "-Wno-unknown-pragmas",
+           "-o", tmp, EMU_SRC, DEPS[3]]
+    subprocess.run(cmd, check=True)
+    os.replace(tmp, EMU_BIN)
+    return EMU_BIN
+
+
+def run(jobs):
+    """Run jobs through the emulator.  Each job is a dict:
+       permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order
+       interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
+       deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb
+    Returns a list of (status_line, output) with output a uint8 array or list of planes."""
+    exe = build()
+    with tempfile.TemporaryDirectory() as td:
+        lines = []
+        for i, j in enumerate(jobs):
+            inf = os.path.join(td, f"in{i}")
+            outf = os.path.join(td, f"out{i}")
+            rb = f"{j.get('in_rb', 0)} {j.get('out_rb', 0)}"
+            if j["op"] == "permute":
+                j["input"].tofile(inf)
+                nd = len(j["dims"])
+                lines.append(" ".join(["permute", str(nd), *map(str, j["dims"]), *map(str, j["perm"]),
+                                       str(j["esize"]), str(j.get("src_off", 0)), str(j.get("dst_off", 0)),
+                                       rb, str(j.get("order", 0)), inf, outf]))
+            elif j["op"] == "interlace":
+                np.concatenate(j["planes"]).tofile(inf)
+                lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
+            else:
+                j["input"].tofile(inf)
+                lines.append(f"deinterlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
+        man = os.path.join(td, "manifest")
+        with open(man, "w") as fh:
+            fh.write("\n".join(lines) + "\n")
+        env = dict(os.environ, ASAN_OPTIONS="detect_leaks=0:abort_on_error=1",
+                   UBSAN_OPTIONS="print_stacktrace=1:halt_on_error=1")
+        r = subprocess.run([exe, man], capture_output=True, text=True, env=env)
+        if r.returncode != 0:
+            raise AssertionError(f"emulator failed (rc={r.returncode}):\n{r.stdout[-3000:]}\n{r.stderr[-6000:]}")
+        status = r.stdout.strip().splitlines()
+        assert len(status) == len(jobs), r.stdout
+        out = []
+        for i, (j, s) in enumerate(zip(jobs, status)):
+            outf = os.path.join(td, f"out{i}")
+            if not s.startswith("ok"):
+                out.append((s, None))
+                continue
+            data = np.fromfile(outf, dtype=np.uint8)
+            if j["op"] == "deinterlace":
+                pb = j["count"] * j["esize"]
+                data = [data[c * pb:(c + 1) * pb] for c in range(j["n"])]
+            out.append((s, data))
+        return out

@@ -1,0 +1,132 @@
+"""Host-side checks of librr: the C ABI loads and exports what include/rr.h declares,
+and validation / canonicalisation / planning behave as documented.  No GPU is
+touched: every call here returns before any launch."""
+import ctypes
+import os
+import re
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+import paper_1011_3583_amd as rr
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def _header_functions():
+    src = open(os.path.join(ROOT, "include", "rr.h")).read()
+    src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
+    return sorted(set(re.findall(r"\b(rr_[a-z_]+)\s*\(", src)))
+
+
+def test_library_exports_every_declared_symbol():
+    L = rr.lib()
+    names = _header_functions()
+    assert len(names) >= 18
+    for n in names:
+        assert hasattr(L, n), f"librr.so does not export {n}"
+    assert set(names) == set(rr.EXPORTS)
+    assert b"gfx950" in L.rr_version()
+
+
+def test_status_strings():
+    for code, name in rr.STATUS.items():
+        assert rr.lib().rr_status_string(code).decode() == name
+
+
+def test_order_to_perm_matches_paper_reading():
+    table = {(0, 2, 1): (1, 0, 2), (1, 0, 2): (0, 2, 1), (1, 2, 0): (2, 0, 1), (2, 0, 1): (1, 2, 0),
+             (2, 1, 0): (2, 1, 0), (1, 0, 2, 3): (0, 1, 3, 2), (3, 2, 0, 1): (2, 3, 1, 0),
+             (3, 0, 2, 1, 4): (0, 3, 2, 4, 1)}
+    for order, perm in table.items():
+        assert rr.order_to_perm(order) == perm
+    # and the converted perm reproduces the oracle's paper-notation reorder
+    for sizes, order in [((4, 3, 2), (1, 2, 0)), ((3, 2, 5, 2), (3, 0, 2, 1))]:
+        x = rr_synth.random_bytes(5, int(np.prod(sizes)) * 4)
+        a = oracle.reorder_paper(x, sizes, order, 4)
+        b = oracle.permute(x, tuple(reversed(sizes)), rr.order_to_perm(order), 4)
+        assert np.array_equal(a, b)
+    with pytest.raises(rr.RRError):
+        rr.order_to_perm((0, 0, 1))
+
+
+def _status(dims, perm, e, dst=0x100000, src=0x900000):
+    return rr.permute_raw(dst, src, dims, perm, e, stream=0)
+
+
+def test_validation_errors_return_before_launch():
+    assert _status((4, 4), (0, 0), 4) == 1          # not a permutation
+    assert _status((4, 4), (1, 0), 0) == 1          # elem_size
+    assert _status((4, 4), (1, 0), 17) == 1
+    assert _status((4, -1), (1, 0), 4) == 1         # negative extent
+    assert _status(tuple([2] * 9), tuple(range(9)), 1) == 4  # rank > 8
+    assert _status((1 << 40, 1 << 30), (1, 0), 4) == 2       # overflow
+    assert _status((4, 4), (1, 0), 4, dst=0x1000, src=0x1008) == 3  # alias
+    assert _status((4, 4), (1, 0), 4, dst=0, src=0x1000) == 1       # NULL
+    assert "permutation" in rr.last_error() or "NULL" in rr.last_error()
+    # zero elements: nothing to do, no launch, OK even with NULL pointers
+    assert _status((0, 5), (1, 0), 4, dst=0, src=0) == 0
+    # interlace validation
+    assert rr.interlace_raw(0x1000, [0x100000, 0x200000], 16, 0) == 1
+    assert rr.interlace_raw(0x1000, [0x100000] * 17, 16, 4) == 1
+    assert rr.interlace_raw(0x100000, [0x100000, 0x200000], 16, 4) == 3
+    assert rr.deinterlace_raw([0x200000, 0x200010], 0x100000, 16, 4) == 3  # planes overlap
+    assert rr.interlace_raw(0x1000, [0x100000, 0x200000], 0, 4) == 0
+
+
+CANON = [
+    # (dims, perm, esize) -> (class, canonical dims, canonical perm, element bytes)
+    ((512, 512, 256), (0, 1, 2), 4, "copy", "", "", 2**26 * 4),
+    ((512, 512, 256), (0, 2, 1), 4, "tile", "512,512,256", "0,2,1", 4),
+    ((512, 512, 256), (1, 0, 2), 4, "run", "512,512", "1,0", 1024),
+    ((512, 512, 256), (1, 2, 0), 4, "tile", "512,131072", "1,0", 4),
+    ((512, 512, 256), (2, 0, 1), 4, "tile", "262144,256", "1,0", 4),
+    ((512, 512, 256), (2, 1, 0), 4, "tile", "512,512,256", "2,1,0", 4),
+    ((64, 128, 128, 64), (0, 3, 1, 2), 2, "tile", "64,16384,64", "0,2,1", 2),
+    ((64, 128, 128, 64), (0, 2, 3, 1), 2, "tile", "64,128,8192", "0,2,1", 2),
+    ((32, 32, 32, 32, 32), (4, 2, 0, 3, 1), 1, "tile", "32,32,32,32,32", "4,2,0,3,1", 1),
+    ((16384, 16384), (1, 0), 16, "tile", "16384,16384", "1,0", 16),
+    ((256, 16, 1, 256, 16), (0, 3, 2, 4, 1), 4, "tile", "256,16,4096", "0,2,1", 4),
+    ((1, 256, 256, 256), (0, 1, 3, 2), 4, "tile", "256,256,256", "0,2,1", 4),  # Table 2 row 2 squeezed
+]
+
+
+@pytest.mark.parametrize("dims,perm,e,cls,cdims,cperm,eb", CANON)
+def test_canonical_forms(dims, perm, e, cls, cdims, cperm, eb):
+    d = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    assert d["class"] == cls
+    if cls != "copy":
+        assert d["dims"] == cdims and d["perm"] == cperm
+    assert int(d["esize_bytes"]) == eb
+
+
+def test_canonical_form_is_equivalent_to_the_original():
+    """The rewritten problem (squeezed, fused, element-folded) moves the same bytes."""
+    g = rr_synth.rng(31)
+    for t in range(150):
+        nd = int(g.integers(1, 7))
+        dims = tuple(int(g.choice([1, 1, 2, 3, 4, 5])) for _ in range(nd))
+        perm = tuple(int(v) for v in g.permutation(nd))
+        e = int(g.integers(1, 17))
+        d = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+        x = rr_synth.random_bytes(t, int(np.prod(dims)) * e)
+        ref = oracle.permute(x, dims, perm, e)
+        eb = int(d["esize_bytes"])
+        if d["class"] in ("copy",) or d["dims"] == "":
+            assert np.array_equal(ref, x)
+            continue
+        cd = tuple(int(v) for v in d["dims"].split(","))
+        cp = tuple(int(v) for v in d["perm"].split(","))
+        assert np.array_equal(oracle.permute(x, cd, cp, eb), ref), (dims, perm, e, d)
+
+
+def test_plan_uses_widest_vectors_on_aligned_buffers():
+    d = rr.plan_describe((16384, 16384), (1, 0), 1, dst=1 << 20, src=1 << 30)
+    assert (d["unit"], d["g"], d["win"]) == ("1", "16", "16")
+    d = rr.plan_describe((1024, 1024), (1, 0), 4, dst=1 << 20, src=1 << 30)
+    assert (d["unit"], d["g"], d["win"]) == ("4", "4", "16")
+    # misaligned base pointer -> narrower access, still a valid plan
+    d = rr.plan_describe((1024, 1024), (1, 0), 4, dst=(1 << 20) + 2, src=1 << 30)
+    assert d["unit"] == "2"

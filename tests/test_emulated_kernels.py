@@ -1,0 +1,146 @@
+"""CPU runs of the library's kernel bodies (planner + per-thread code) against the oracle.
+
+The emulator executes every workgroup and thread of each launch on the host
+under AddressSanitizer, so these tests prove the GPU index arithmetic stays in
+bounds and produces the oracle's bytes, for the same plans the GPU runs.
+"""
+import itertools
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+from tests import emu_runner
+
+
+def _perm_job(dims, perm, e, seed, **kw):
+    n = int(np.prod(dims, dtype=np.int64)) * e
+    return dict(op="permute", dims=tuple(dims), perm=tuple(perm), esize=e,
+                input=rr_synth.random_bytes(seed, n), **kw)
+
+
+def _check(jobs):
+    res = emu_runner.run(jobs)
+    for j, (status, out) in zip(jobs, res):
+        assert status.startswith("ok"), (j.get("dims"), j.get("perm"), status)
+        if j["op"] == "permute":
+            ref = oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])
+            assert np.array_equal(out, ref), (j["dims"], j["perm"], j["esize"], j.get("src_off"),
+                                              j.get("dst_off"), status)
+        elif j["op"] == "interlace":
+            ref = oracle.interlace(j["planes"], j["esize"])
+            assert np.array_equal(out, ref), (j["n"], j["count"], j["esize"], status)
+        else:
+            ref = oracle.deinterlace(j["input"], j["n"], j["esize"])
+            for c in range(j["n"]):
+                assert np.array_equal(out[c], ref[c]), (j["n"], j["count"], j["esize"], c, status)
+    return res
+
+
+def test_emu_brute_force_small_ranks():
+    """Every permutation of ranks 1-4 on odd extents, several element sizes and misalignments."""
+    jobs = []
+    shapes = {1: (7,), 2: (5, 3), 3: (3, 5, 2), 4: (2, 3, 1, 5)}
+    seed = 0
+    for nd, dims in shapes.items():
+        for perm in itertools.permutations(range(nd)):
+            for e in (1, 2, 3, 4, 8, 12, 16):
+                seed += 1
+                jobs.append(_perm_job(dims, perm, e, seed, src_off=seed % 16, dst_off=(seed * 7) % 16))
+    _check(jobs)
+
+
+def test_emu_rank5_all_perms_aligned():
+    jobs = []
+    for i, perm in enumerate(itertools.permutations(range(5))):
+        e = (1, 2, 4, 8, 16)[i % 5]
+        jobs.append(_perm_job((2, 3, 2, 4, 2), perm, e, 1000 + i))
+    _check(jobs)
+
+
+@pytest.mark.parametrize("e", [1, 2, 4, 8, 16])
+def test_emu_wide_vectors_and_partial_tiles(e):
+    """Extents that are multiples of 16 (full 16-byte micro-tiles) plus ragged tails."""
+    jobs = []
+    cases = [((48, 80), (1, 0)), ((272, 48), (1, 0)), ((32, 48, 64), (2, 1, 0)),
+             ((32, 48, 64), (1, 2, 0)), ((32, 48, 64), (2, 0, 1)), ((16, 32, 48), (0, 2, 1)),
+             ((33, 47), (1, 0)), ((129, 3, 65), (2, 1, 0)), ((16, 16, 16, 16), (0, 3, 1, 2)),
+             ((16, 16, 16, 16), (0, 2, 3, 1)), ((8, 8, 8, 8, 8), (4, 2, 0, 3, 1))]
+    for i, (dims, perm) in enumerate(cases):
+        jobs.append(_perm_job(dims, perm, e, 2000 + i))
+        jobs.append(_perm_job(dims, perm, e, 3000 + i, src_off=e % 16 or 4, dst_off=8))
+    _check(jobs)
+
+
+def test_emu_multi_axis_tiles_small_extents():
+    """Short fastest axes force several axes per tile side (5-D 16^5, odd minor extents)."""
+    jobs = []
+    for i, (dims, perm) in enumerate([((16, 16, 16, 16, 16), (4, 2, 0, 3, 1)),
+                                      ((9, 7, 5, 3), (3, 2, 1, 0)),
+                                      ((4, 100, 3, 6), (1, 3, 0, 2)),
+                                      ((2, 3, 64, 3, 2), (2, 4, 0, 3, 1)),
+                                      ((1000, 3), (1, 0)), ((3, 1000), (1, 0))]):
+        for e in (1, 2, 4):
+            jobs.append(_perm_job(dims, perm, e, 4000 + 10 * i + e))
+    _check(jobs)
+
+
+def test_emu_tile_overrides_and_orders():
+    """Autotuner search space: every row-size pair and both tile traversal orders."""
+    jobs = []
+    k = 0
+    for rbi, rbo in [(64, 64), (128, 512), (512, 128), (1024, 64), (64, 1024), (2048, 2048)]:
+        for order in (0, 1):
+            for dims, perm, e in [((96, 80), (1, 0), 1), ((40, 24, 48), (2, 0, 1), 4),
+                                  ((40, 24, 48), (1, 2, 0), 2), ((20, 36, 16), (2, 1, 0), 8),
+                                  ((17, 31), (1, 0), 16), ((12, 12, 12, 12), (3, 1, 2, 0), 12)]:
+                k += 1
+                jobs.append(_perm_job(dims, perm, e, 5000 + k, in_rb=rbi, out_rb=rbo, order=order))
+    _check(jobs)
+
+
+def test_emu_size_zero_and_one():
+    jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
+            _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),
+            _perm_job((1, 7, 1, 9), (3, 2, 1, 0), 4, 5), _perm_job((256, 256, 1, 4), (3, 2, 0, 1), 1, 6)]
+    _check(jobs)
+
+
+def test_emu_run_copy_class():
+    """Permutes that keep the fastest axis: contiguous runs copied without LDS."""
+    jobs = []
+    for i, (dims, perm, e) in enumerate([((64, 64, 32), (1, 0, 2), 4), ((8, 9, 10, 64), (2, 0, 1, 3), 2),
+                                         ((7, 5, 33), (1, 0, 2), 8), ((3, 4, 5, 6), (2, 1, 0, 3), 16)]):
+        jobs.append(_perm_job(dims, perm, e, 6000 + i))
+        jobs.append(_perm_job(dims, perm, e, 6100 + i, src_off=3, dst_off=5))
+    res = _check(jobs)
+    assert any("class=run" in s for s, _ in res)
+
+
+def test_emu_config1_transpose():
+    """1024x1024 transpose of 4-byte elements (the small dense case)."""
+    _check([_perm_job((1024, 1024), (1, 0), 4, 77)])
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_emu_interlace_deinterlace(n):
+    jobs = []
+    for i, (count, e) in enumerate([(1, 4), (37, 1), (64, 4), (129, 2), (256, 8), (50, 16), (33, 3), (48, 12)]):
+        planes = [rr_synth.random_bytes(7000 + 100 * n + 10 * i + c, count * e) for c in range(n)]
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, off=(i * 5) % 16))
+        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e, off=(i * 3) % 16,
+                         input=rr_synth.random_bytes(8000 + 100 * n + i, n * count * e)))
+    _check(jobs)
+
+
+def test_emu_interlace_large_counts():
+    """Counts spanning several tiles with ragged tails, the three interlace workloads' shapes."""
+    jobs = []
+    for n, e in [(2, 4), (4, 1), (3, 4)]:
+        count = 3 * 4096 + 17 * (5 - n)
+        planes = [rr_synth.random_bytes(9000 + c, count * e) for c in range(n)]
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
+        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e,
+                         input=rr_synth.random_bytes(9100 + n, n * count * e)))
+    _check(jobs)

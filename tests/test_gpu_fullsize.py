@@ -1,0 +1,96 @@
+"""GPU parity at the full benchmark sizes, in the launch configuration the benchmark times.
+
+Outputs of up to 4 GiB are checked on sampled elements the oracle computes one
+by one (random positions plus the first and last 64 Ki elements), and the
+interlace workloads additionally round-trip through de-interlace.
+"""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+
+pytestmark = [pytest.mark.gpu, pytest.mark.slow]
+
+torch = pytest.importorskip("torch")
+
+NSAMPLE = 200_000
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available()
+    import paper_1011_3583_amd as rr
+    rr.set_tile_override(0, 0, False)
+    return rr
+
+
+@pytest.fixture(scope="module")
+def pool():
+    """4 GiB of seeded random bits on the host and on the device (inputs are slices)."""
+    host = rr_synth.random_bytes(20251202, 4 << 30)
+    dev = torch.from_numpy(host).to("cuda")
+    return host, dev
+
+
+def _sample_idx(n, seed):
+    g = rr_synth.rng(seed)
+    head = np.arange(min(n, 65536), dtype=np.int64)
+    tail = np.arange(max(0, n - 65536), n, dtype=np.int64)
+    rnd = g.integers(0, n, size=min(n, NSAMPLE), dtype=np.int64)
+    return np.unique(np.concatenate([head, tail, rnd]))
+
+
+@pytest.mark.parametrize("case", list(range(len(rr_synth.DENSE_CASES))))
+def test_dense_full_size(rr, pool, case):
+    host, dev = pool
+    name, dims, perm = rr_synth.DENSE_CASES[case]
+    out = None
+    for e in rr_synth.ESIZES:
+        n = int(np.prod(dims, dtype=np.int64))
+        nb = n * e
+        _say(name, dims, perm, e, nb)
+        del out
+        out = torch.empty(nb, dtype=torch.uint8, device="cuda")
+        st = rr.permute_raw(out.data_ptr(), dev.data_ptr(), dims, perm, e,
+                            stream=torch.cuda.current_stream().cuda_stream)
+        assert st == 0, rr.last_error()
+        torch.cuda.synchronize()
+        idx = _sample_idx(n, case * 100 + e)
+        got = out.view(n, e)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+        ref = oracle.permute_at(host[:nb], dims, perm, e, idx)
+        assert np.array_equal(got, ref), (name, perm, e)
+
+
+@pytest.mark.parametrize("case", list(range(len(rr_synth.INTERLACE_CASES))))
+def test_interlace_full_size(rr, pool, case):
+    host, dev = pool
+    name, n, count, e = rr_synth.INTERLACE_CASES[case]
+    pb = count * e
+    _say(name, n, count, e)
+    planes_dev = [dev[c * pb:(c + 1) * pb] for c in range(n)]
+    joined = torch.empty(n * pb, dtype=torch.uint8, device="cuda")
+    st = rr.interlace_raw(joined.data_ptr(), [p.data_ptr() for p in planes_dev], count, e,
+                          stream=torch.cuda.current_stream().cuda_stream)
+    assert st == 0, rr.last_error()
+    torch.cuda.synchronize()
+    idx = _sample_idx(count, 900 + case)
+    j = joined.view(count, n, e)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
+    for c in range(n):
+        ref = host[c * pb:(c + 1) * pb].reshape(count, e)[idx]
+        assert np.array_equal(j[:, c, :], ref), (name, c)
+    # de-interlace the joined buffer back into planes: must equal the originals exactly
+    outs = [torch.empty(pb, dtype=torch.uint8, device="cuda") for _ in range(n)]
+    st = rr.deinterlace_raw([o.data_ptr() for o in outs], joined.data_ptr(), count, e,
+                            stream=torch.cuda.current_stream().cuda_stream)
+    assert st == 0, rr.last_error()
+    torch.cuda.synchronize()
+    for c in range(n):
+        assert torch.equal(outs[c], planes_dev[c]), (name, c)

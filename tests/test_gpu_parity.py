@@ -1,0 +1,210 @@
+"""GPU parity: librr on cuda:0 against the CPU oracle, bit for bit.
+
+Small and medium problems are compared element by element over the whole
+output; the full-size dense and interlace workloads are compared on sampled
+output elements the oracle computes one by one, plus the head and tail of the
+output.  Every case prints its name before it runs.
+"""
+import itertools
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available(), "GPU tests need cuda:0"
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    rr.set_tile_override(0, 0, False)
+    return rr
+
+
+def _dev_buf(nbytes, off=0):
+    """A device byte buffer with a usable window of nbytes starting `off` bytes past a
+    256-byte-aligned base."""
+    t = torch.empty(nbytes + off + 16, dtype=torch.uint8, device="cuda")
+    return t, t.data_ptr() + off
+
+
+def _upload(x, off=0):
+    t, p = _dev_buf(x.size, off)
+    if x.size:
+        t[off:off + x.size].copy_(torch.from_numpy(x))
+    return t, p
+
+
+def _download(t, off, n):
+    return t[off:off + n].cpu().numpy()
+
+
+def gpu_permute(rr, x, dims, perm, e, soff=0, doff=0):
+    n = x.size
+    ts, ps = _upload(x, soff)
+    td, pd = _dev_buf(n, doff)
+    td.fill_(0x5A)
+    st = rr.permute_raw(pd, ps, dims, perm, e, stream=torch.cuda.current_stream().cuda_stream)
+    assert st == 0, rr.last_error()
+    torch.cuda.synchronize()
+    out = _download(td, doff, n)
+    # nothing written outside the window
+    guard = td.cpu().numpy()
+    assert np.all(guard[:doff] == 0x5A) and np.all(guard[doff + n:] == 0x5A)
+    return out
+
+
+def check_permute(rr, dims, perm, e, seed, soff=0, doff=0):
+    _say("permute", dims, perm, e, soff, doff)
+    x = rr_synth.random_bytes(seed, int(np.prod(dims, dtype=np.int64)) * e)
+    got = gpu_permute(rr, x, dims, perm, e, soff, doff)
+    ref = oracle.permute(x, dims, perm, e)
+    assert np.array_equal(got, ref), (dims, perm, e, soff, doff)
+
+
+def test_small_dense_transpose_1024(rr):
+    """1024x1024 transpose of 4-byte random bit patterns."""
+    check_permute(rr, (1024, 1024), (1, 0), 4, 1)
+
+
+def test_brute_force_small_ranks(rr):
+    shapes = {1: (7,), 2: (5, 3), 3: (3, 5, 2), 4: (2, 3, 1, 5)}
+    seed = 0
+    for nd, dims in shapes.items():
+        for perm in itertools.permutations(range(nd)):
+            for e in (1, 2, 3, 4, 5, 6, 7, 8, 12, 16):
+                seed += 1
+                check_permute(rr, dims, perm, e, seed, soff=seed % 16, doff=(seed * 7) % 16)
+
+
+def test_rank5_all_perms(rr):
+    for i, perm in enumerate(itertools.permutations(range(5))):
+        check_permute(rr, (2, 3, 2, 4, 2), perm, (1, 2, 4, 8, 16)[i % 5], 1000 + i)
+
+
+@pytest.mark.parametrize("e", [1, 2, 4, 8, 16])
+def test_wide_vectors_and_partial_tiles(rr, e):
+    cases = [((48, 80), (1, 0)), ((272, 48), (1, 0)), ((32, 48, 64), (2, 1, 0)),
+             ((32, 48, 64), (1, 2, 0)), ((32, 48, 64), (2, 0, 1)), ((16, 32, 48), (0, 2, 1)),
+             ((33, 47), (1, 0)), ((129, 3, 65), (2, 1, 0)), ((16, 16, 16, 16), (0, 3, 1, 2)),
+             ((16, 16, 16, 16), (0, 2, 3, 1)), ((8, 8, 8, 8, 8), (4, 2, 0, 3, 1)),
+             ((1000, 3), (1, 0)), ((3, 1000), (1, 0)), ((4, 100, 3, 6), (1, 3, 0, 2))]
+    for i, (dims, perm) in enumerate(cases):
+        check_permute(rr, dims, perm, e, 2000 + i)
+        check_permute(rr, dims, perm, e, 3000 + i, soff=(e % 16) or 4, doff=8)
+
+
+def test_medium_ragged_multi_tile(rr):
+    """Sizes spanning many tiles with ragged tails on every tiled axis."""
+    for i, (dims, perm, e) in enumerate([((1000, 1001), (1, 0), 4), ((333, 444, 5), (2, 0, 1), 2),
+                                         ((97, 129, 65), (2, 1, 0), 1), ((32, 32, 32, 32, 32), (4, 2, 0, 3, 1), 1),
+                                         ((64, 65, 66, 7), (3, 1, 0, 2), 8), ((513, 257), (1, 0), 16),
+                                         ((255, 257, 3), (1, 2, 0), 12), ((3000, 17), (1, 0), 6)]):
+        check_permute(rr, dims, perm, e, 4000 + i)
+
+
+def test_tile_overrides(rr):
+    try:
+        k = 0
+        for rbi, rbo in [(64, 64), (128, 512), (512, 128), (1024, 64), (2048, 2048)]:
+            for order in (False, True):
+                rr.set_tile_override(rbi, rbo, order)
+                for dims, perm, e in [((96, 80), (1, 0), 1), ((40, 24, 48), (2, 0, 1), 4),
+                                      ((40, 24, 48), (1, 2, 0), 2), ((20, 36, 16), (2, 1, 0), 8),
+                                      ((17, 31), (1, 0), 16), ((12, 12, 12, 12), (3, 1, 2, 0), 12)]:
+                    k += 1
+                    check_permute(rr, dims, perm, e, 5000 + k)
+    finally:
+        rr.set_tile_override(0, 0, False)
+
+
+def test_size_zero_and_one(rr):
+    for i, (dims, perm, e) in enumerate([((0, 5), (1, 0), 4), ((5, 0, 3), (2, 0, 1), 2),
+                                         ((1, 1, 1), (2, 1, 0), 8), ((1,), (0,), 16),
+                                         ((1, 7, 1, 9), (3, 2, 1, 0), 4)]):
+        check_permute(rr, dims, perm, e, 6000 + i)
+
+
+def test_paper_table1_orders(rr):
+    """Table 1: all six orders of the fastest-first 128x256x512 set, 4-byte elements."""
+    sizes = rr_synth.PAPER_TABLE1_SIZES
+    dims = tuple(reversed(sizes))
+    x = rr_synth.random_bytes(7, int(np.prod(dims)) * 4)
+    for order in itertools.permutations(range(3)):
+        perm = rr.order_to_perm(order)
+        _say("table1", order, perm)
+        got = gpu_permute(rr, x, dims, perm, 4)
+        ref = oracle.reorder_paper(x, sizes, order, 4)
+        assert np.array_equal(got, ref), order
+
+
+def test_paper_table2_reorders(rr):
+    """Table 2's four reorders in the paper's notation, 4-byte elements."""
+    for i, (sizes, order) in enumerate(rr_synth.PAPER_TABLE2):
+        dims = tuple(reversed(sizes))
+        perm = rr.order_to_perm(order)
+        _say("table2", sizes, order, perm)
+        x = rr_synth.random_bytes(70 + i, int(np.prod(dims)) * 4)
+        got = gpu_permute(rr, x, dims, perm, 4)
+        assert np.array_equal(got, oracle.reorder_paper(x, sizes, order, 4)), order
+
+
+# ----------------------------------------------------------------- interlace
+def gpu_interlace(rr, planes, e, off=0):
+    n = len(planes)
+    count = planes[0].size // e
+    dev = [_upload(p, off) for p in planes]
+    td, pd = _dev_buf(n * count * e, off)
+    st = rr.interlace_raw(pd, [p for _, p in dev], count, e, stream=torch.cuda.current_stream().cuda_stream)
+    assert st == 0, rr.last_error()
+    torch.cuda.synchronize()
+    return _download(td, off, n * count * e)
+
+
+def gpu_deinterlace(rr, x, n, e, off=0):
+    count = x.size // (n * e)
+    ts, ps = _upload(x, off)
+    outs = [_dev_buf(count * e, off) for _ in range(n)]
+    st = rr.deinterlace_raw([p for _, p in outs], ps, count, e, stream=torch.cuda.current_stream().cuda_stream)
+    assert st == 0, rr.last_error()
+    torch.cuda.synchronize()
+    return [_download(t, off, count * e) for t, _ in outs]
+
+
+@pytest.mark.parametrize("n", list(range(1, 17)))
+def test_interlace_deinterlace_small(rr, n):
+    for i, (count, e) in enumerate([(1, 4), (37, 1), (64, 4), (129, 2), (256, 8), (50, 16), (33, 3),
+                                    (48, 12), (5000, 4), (4099, 1)]):
+        _say("interlace", n, count, e)
+        planes = [rr_synth.random_bytes(7000 + 100 * n + 10 * i + c, count * e) for c in range(n)]
+        off = (i * 5) % 16
+        assert np.array_equal(gpu_interlace(rr, planes, e, off), oracle.interlace(planes, e))
+        x = rr_synth.random_bytes(8000 + 100 * n + i, n * count * e)
+        got = gpu_deinterlace(rr, x, n, e, (i * 3) % 16)
+        ref = oracle.deinterlace(x, n, e)
+        for c in range(n):
+            assert np.array_equal(got[c], ref[c]), (n, count, e, c)
+
+
+def test_paper_table3_interlace_counts(rr):
+    """Table 3's four to nine arrays at 2^24 4-byte elements each (reduced to 2^22 here)."""
+    count = 1 << 22
+    for n in range(4, 10):
+        _say("table3", n)
+        planes = [rr_synth.random_bytes(300 + 10 * n + c, count * 4) for c in range(n)]
+        joined = gpu_interlace(rr, planes, 4)
+        assert np.array_equal(joined, oracle.interlace(planes, 4))
+        back = gpu_deinterlace(rr, joined, n, 4)
+        assert all(np.array_equal(b, p) for b, p in zip(back, planes))
