@@ -1,0 +1,278 @@
+#!/usr/bin/env python3
+"""Benchmark of librr on one MI355X.
+
+One step = every dense N-D permute of the benchmark workload, once:
+  3-D 512x512x256 under all six axis orders, 4-D 64x128x128x64 under (0,3,1,2)
+  and (0,2,3,1), 5-D 32^5 under (4,2,0,3,1) and the 16384x16384 transpose,
+  each at element sizes 16, 8, 4, 2 and 1 bytes (50 launches, 24.25 GiB per side).
+Inputs are seeded random bits already resident in HBM.  Throughput is effective
+bandwidth: 2 * bytes-per-side / time (read + write, decimal GB/s).
+
+Printed: one JSON line with the step throughput, ceilings (hipMemcpyAsync D2D
+and the library's own copy kernel), the roofline of the dominant kernel from
+per-launch HIP events, the oracle's CPU throughput on a bounded sample, and
+side measurements of the interlace workloads, the batched launch and the
+serving loop.
+"""
+from __future__ import annotations
+
+import argparse
+import ctypes
+import hashlib
+import json
+import os
+import sys
+import time
+
+ROOT = os.path.dirname(os.path.abspath(__file__))
+sys.path.insert(0, ROOT)
+
+HBM_PEAK_GBPS = 8000.0
+METRIC = "permute eff. GB/s (% of D2D memcpy, % of 8 TB/s); served p50/p99 latency"
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=5)
+    ap.add_argument("--warmup", type=int, default=1)
+    ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-side", action="store_true", help="skip interlace/batched/serve side runs")
+    ap.add_argument("--profile-only", action="store_true",
+                    help="run warmup+steps and exit (for rocprofv3 runs)")
+    return ap.parse_args()
+
+
+def kernel_source_hash() -> str:
+    h = hashlib.sha256()
+    for f in ("rr_device.hpp", "rr_kernels.hip", "rr_plan.cpp", "rr_plan.hpp"):
+        with open(os.path.join(ROOT, "paper_1011_3583_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def kernel_name(d: dict) -> str:
+    if d["class"] == "tile":
+        return f"k_tile<{d['unit']},{d['g']}>"
+    if d["class"] == "run":
+        return f"k_run<{d['vec']}>"
+    if d["class"] == "copy":
+        return f"k_copy<{d['vec']}>"
+    return d["class"]
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this library "
+              f"has no multi-GPU path; see the sharding note in the design document).", file=sys.stderr)
+        sys.exit(2)
+    import torch
+    import paper_1011_3583_amd as rr
+    import rr_synth
+
+    rr.lib()
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    sh = stream.cuda_stream
+
+    cases = []
+    for name, dims, perm in rr_synth.DENSE_CASES:
+        for e in sorted(rr_synth.ESIZES, reverse=True):
+            n = 1
+            for d in dims:
+                n *= d
+            cases.append((name, dims, perm, e, n * e))
+    max_nb = max(c[4] for c in cases)
+    # two input regions alternate so a case never re-reads what the previous one touched
+    pool = torch.empty(2 * max_nb, dtype=torch.uint8, device=dev)
+    g = torch.Generator(device=dev)
+    g.manual_seed(1011_3583)
+    for i in range(0, pool.numel(), 1 << 30):
+        pool[i:i + (1 << 30)].random_(0, 256, generator=g)
+    out = torch.empty(max_nb, dtype=torch.uint8, device=dev)
+    plans = []
+    for i, (name, dims, perm, e, nb) in enumerate(cases):
+        src = pool.data_ptr() + (i % 2) * max_nb
+        d = rr.plan_describe(dims, perm, e, out.data_ptr(), src)
+        plans.append((src, kernel_name(d)))
+
+    def step(events=None):
+        for i, (name, dims, perm, e, nb) in enumerate(cases):
+            src = plans[i][0]
+            if events is not None:
+                events[i][0].record(stream)
+            st = rr.permute_raw(out.data_ptr(), src, dims, perm, e, sh)
+            if st != 0:
+                raise rr.RRError(st, rr.last_error())
+            if events is not None:
+                events[i][1].record(stream)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    if args.profile_only:
+        for _ in range(args.steps):
+            step()
+        torch.cuda.synchronize()
+        return
+
+    evs = [[(torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True))
+            for _ in cases] for _ in range(args.steps)]
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for s in range(args.steps):
+        step(evs[s])
+    torch.cuda.synchronize()
+    t1 = time.perf_counter()
+    wall = t1 - t0
+    bytes_per_step = sum(2 * c[4] for c in cases)
+    value = bytes_per_step * args.steps / wall / 1e9
+
+    # per-launch durations
+    per_case_ms = [[evs[s][i][0].elapsed_time(evs[s][i][1]) for s in range(args.steps)]
+                   for i in range(len(cases))]
+    detail = {}
+    by_kernel = {}
+    for i, (name, dims, perm, e, nb) in enumerate(cases):
+        ms = sorted(per_case_ms[i])[len(per_case_ms[i]) // 2]
+        key = f"{name} {tuple(perm)} e{e}"
+        detail[key] = round(2 * nb / (ms * 1e-3) / 1e9, 1)
+        k = plans[i][1]
+        agg = by_kernel.setdefault(k, {"bytes": 0, "ms": 0.0, "launches": 0})
+        agg["bytes"] += 2 * nb * args.steps
+        agg["ms"] += sum(per_case_ms[i])
+        agg["launches"] += args.steps
+    kernel_time_ms = sum(sum(v) for v in per_case_ms) / args.steps
+    dom = max(by_kernel, key=lambda k: by_kernel[k]["ms"])
+    dk = by_kernel[dom]
+    achieved = dk["bytes"] / (dk["ms"] * 1e-3) / 1e9
+    traffic = None
+    prof_path = os.path.join(ROOT, "profiles", "counters.json")
+    if os.path.exists(prof_path):
+        with open(prof_path) as fh:
+            prof = json.load(fh)
+        entry = prof.get("kernels", {}).get(dom)
+        if entry and prof.get("source_hash") == kernel_source_hash():
+            traffic = entry.get("hbm_bytes_per_launch")
+
+    # ceilings: hipMemcpyAsync D2D and the library's copy kernel, 1 GiB per side
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int,
+                                   ctypes.c_void_p]
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+
+    def timed(fn, reps=7):
+        ts = []
+        for r in range(reps + 2):
+            flush.fill_(r & 0xff)
+            a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+            a.record(stream)
+            fn()
+            b.record(stream)
+            b.synchronize()
+            ts.append(a.elapsed_time(b) * 1e-3)
+        ts = sorted(ts[2:])
+        return ts[len(ts) // 2]
+
+    nb = 1 << 30
+    t_d2d = timed(lambda: hip.hipMemcpyAsync(out.data_ptr(), pool.data_ptr(), nb, 3, sh))
+    t_cpy = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), (nb,), (0,), 1, sh)))
+    d2d = 2 * nb / t_d2d / 1e9
+    rrcopy = 2 * nb / t_cpy / 1e9
+
+    result = {
+        "metric": METRIC,
+        "value": round(value, 1),
+        "unit": "GB/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": round(wall / args.steps * 1e3, 3),
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "u8",
+        "data": "synthetic: seeded random bits, resident in HBM",
+        "config": {
+            "workload": "dense N-D permutes: 3-D 512x512x256 all 6 orders, 4-D 64x128x128x64 "
+                        "(0,3,1,2),(0,2,3,1), 5-D 32^5 (4,2,0,3,1), 2-D 16384x16384 (1,0); "
+                        "element sizes 16,8,4,2,1 bytes",
+            "launches_per_step": len(cases),
+            "bytes_per_side_per_step": bytes_per_step // 2,
+        },
+        "pct_of_d2d_memcpy": round(100 * value / d2d, 1),
+        "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
+        "kernel_only_GBps": round(bytes_per_step / (kernel_time_ms * 1e-3) / 1e9, 1),
+        "ceilings_GBps": {"d2d_hipMemcpyAsync_1GiB": round(d2d, 1), "rr_copy_1GiB": round(rrcopy, 1),
+                          "hbm_peak": HBM_PEAK_GBPS},
+        "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
+                     "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
+                     "traffic": traffic, "launches": dk["launches"],
+                     "avg_launch_us": round(dk["ms"] / dk["launches"] * 1e3, 2),
+                     "algorithmic_bytes_per_launch": dk["bytes"] // dk["launches"]},
+        "kernels": {k: {"GBps": round(v["bytes"] / (v["ms"] * 1e-3) / 1e9, 1),
+                        "avg_launch_us": round(v["ms"] / v["launches"] * 1e3, 2),
+                        "launches": v["launches"]} for k, v in sorted(by_kernel.items())},
+        "detail_GBps": detail,
+        "kernel_source": kernel_source_hash(),
+    }
+    del flush
+
+    if not args.no_side:
+        side = {}
+        try:
+            side["interlace"] = bench_interlace(rr, rr_synth, pool, out, stream, timed)
+        except Exception as ex:  # side measurements never hide the main line
+            side["interlace"] = {"error": str(ex)}
+        try:
+            import bench_side
+            side.update(bench_side.run(rr, rr_synth, torch, stream, timed))
+        except ImportError:
+            pass
+        except Exception as ex:
+            side["side_error"] = str(ex)
+        result["side"] = side
+
+    if not args.no_cpu:
+        result["cpu_baseline"] = cpu_baseline(rr_synth)
+
+    print(json.dumps(result), flush=True)
+
+
+def bench_interlace(rr, rr_synth, pool, out, stream, timed):
+    res = {}
+    for name, n, count, e in rr_synth.INTERLACE_CASES:
+        pb = count * e
+        planes = [pool.data_ptr() + c * pb for c in range(n)]
+        t1 = timed(lambda: rr.check(rr.interlace_raw(out.data_ptr(), planes, count, e, stream.cuda_stream)), 5)
+        t2 = timed(lambda: rr.check(rr.deinterlace_raw(planes, out.data_ptr(), count, e, stream.cuda_stream)), 5)
+        res[name] = {"interlace_GBps": round(2 * n * pb / t1 / 1e9, 1),
+                     "deinterlace_GBps": round(2 * n * pb / t2 / 1e9, 1)}
+    return res
+
+
+def cpu_baseline(rr_synth):
+    """The oracle (single-threaded C loop nest) on a bounded sample of the same workload."""
+    import numpy as np
+    import oracle
+    sample = [("3d_512x512x256", (512, 512, 256), (2, 1, 0), 4),
+              ("3d_512x512x256", (512, 512, 256), (0, 2, 1), 1),
+              ("5d_32^5", (32,) * 5, (4, 2, 0, 3, 1), 2),
+              ("2d_16384x16384", (16384, 16384), (1, 0), 1)]
+    tot_b, tot_t = 0, 0.0
+    for i, (name, dims, perm, e) in enumerate(sample):
+        nb = int(np.prod(dims)) * e
+        x = rr_synth.random_bytes(100 + i, nb)
+        t0 = time.perf_counter()
+        oracle.permute(x, dims, perm, e)
+        tot_t += time.perf_counter() - t0
+        tot_b += 2 * nb
+    return {"value": round(tot_b / tot_t / 1e9, 3), "unit": "GB/s", "cores": 1, "kind": "oracle",
+            "sample": "; ".join(f"{n} {p} e{e}" for n, _, p, e in sample) +
+                      f" ({tot_b / 2 / 2**30:.2f} GiB per side, {tot_t:.1f} s)"}
+
+
+if __name__ == "__main__":
+    main()

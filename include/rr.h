@@ -91,15 +91,17 @@ rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t coun
                          int elem_size, rr_stream_t stream);
 
 /* -------------------------------------------------------------------------
- * Batched permutes: many independent, unevenly shaped rr_permute jobs run in
- * one persistent launch per kernel family (the paper's "batched 2D data
- * movement", Sec. III.B, applied across jobs).  Each job's result is identical
- * to running it alone with rr_permute.
+ * Batched permutes: many independent, unevenly shaped rr_permute jobs run with
+ * one launch per kernel family (the paper's "batched 2D data movement",
+ * Sec. III.B, applied across jobs): the jobs are planned as rr_permute would
+ * plan them, grouped by kernel, and each group's launch walks the concatenated
+ * work of all its jobs.  Each job's result is identical to running it alone.
  *   jobs   host array of njobs descriptors (copied before return; the array may
  *          be reused immediately).  Job buffers must not overlap each other.
  *   njobs  >= 0.
- * The job table is staged through a pinned host buffer and a device buffer the
- * library owns (grown on demand, freed at process exit).
+ * The job table is staged through pinned host and device buffers the library
+ * owns (a small ring per device, grown on demand and held until process exit);
+ * a call waits only if it would reuse a slot whose batch is still running.
  * Errors: the first invalid job's error (nothing is launched), RR_ERR_NO_MEMORY,
  * RR_ERR_HIP.
  */
@@ -113,6 +115,44 @@ typedef struct {
 } rr_job;
 
 rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Reusable batch: validate, plan and group the jobs once, keep the job table
+ * resident in device memory owned by the handle, launch many times.
+ *   flags  RR_BATCH_GRAPH      launches replay a hipGraph captured on the
+ *                              first rr_batch_launch (one graph launch per call);
+ *          RR_BATCH_TUNE       rr_batch_create times candidate tile shapes and
+ *                              grid modes (running the batch, so it writes the
+ *                              job outputs) on the current device and keeps the
+ *                              fastest; needs the job buffers to be valid;
+ *          RR_BATCH_PERSISTENT persistent grids (a few workgroups per CU that
+ *                              loop over the group's work) instead of one
+ *                              workgroup per block of work.
+ * The handle's device is the current HIP device at creation.  Launches on
+ * different streams must not overlap in time (they write the same outputs).
+ * Errors: as rr_permute_batched; RR_ERR_NO_MEMORY if the table cannot be
+ * allocated.
+ */
+typedef struct rr_batch rr_batch;
+#define RR_BATCH_GRAPH 1
+#define RR_BATCH_TUNE 2
+#define RR_BATCH_PERSISTENT 4
+
+typedef struct {
+    int32_t njobs;             /* jobs with a non-empty problem                */
+    int32_t ngroups;           /* kernel families = launches per batch          */
+    int32_t in_row_bytes;      /* tile shape chosen (0 = built-in)              */
+    int32_t out_row_bytes;
+    int32_t order_out;         /* tile traversal in output order                */
+    int32_t persistent;        /* persistent grids chosen                       */
+    uint64_t bytes;            /* bytes per side moved by one launch            */
+    double tuned_us;           /* best measured time of one launch (0 if untuned) */
+} rr_batch_info;
+
+rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** out);
+rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream);
+rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out);
+rr_status rr_batch_destroy(rr_batch* b);
 
 /* -------------------------------------------------------------------------
  * Serving: a background thread that owns a HIP stream and an HBM budget,
@@ -185,9 +225,13 @@ rr_status rr_order_to_perm(int ndim, const int* paper_order, int* perm_out);
 rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
                            const int* perm, int elem_size, char* buf, int buflen);
 
-/* Tile-shape override for the autotuner: row targets in bytes for the input
- * and output sides of the tiled kernel, 0 = built-in choice.  Applies to the
- * calling process. */
+/* Tile-shape override (the autotuner's knobs): row targets in bytes for the
+ * input and output sides of the tiled kernel (0 = built-in choice, max 4096)
+ * and the order in which tiles are assigned to workgroups (flags:
+ * RR_TILE_ORDER_OUT / RR_TILE_ORDER_IN, neither = built-in choice by element
+ * size).  Process-wide; affects plans made after the call. */
+#define RR_TILE_ORDER_OUT 1
+#define RR_TILE_ORDER_IN 2
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
 
 const char* rr_status_string(rr_status s);

@@ -25,6 +25,7 @@ STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
 EXPORTS = ("rr_permute", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
+           "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_release", "rr_serve_destroy", "rr_serve_get_stats",
            "rr_order_to_perm", "rr_plan_describe", "rr_set_tile_override",
@@ -56,6 +57,15 @@ class JobResult(ctypes.Structure):
                 ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
 
 
+class BatchInfo(ctypes.Structure):
+    _fields_ = [("njobs", ctypes.c_int32), ("ngroups", ctypes.c_int32), ("in_row_bytes", ctypes.c_int32),
+                ("out_row_bytes", ctypes.c_int32), ("order_out", ctypes.c_int32),
+                ("persistent", ctypes.c_int32), ("bytes", ctypes.c_uint64), ("tuned_us", ctypes.c_double)]
+
+
+RR_BATCH_GRAPH, RR_BATCH_TUNE, RR_BATCH_PERSISTENT = 1, 2, 4
+
+
 class ServeStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "batches", "chunks",
                                                "bytes_moved", "budget_peak", "budget_used")]
@@ -78,6 +88,10 @@ def lib() -> ctypes.CDLL:
     L.rr_interlace.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i32, vp]
     L.rr_deinterlace.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i32, vp]
     L.rr_permute_batched.argtypes = [ctypes.POINTER(Job), i32, vp]
+    L.rr_batch_create.argtypes = [ctypes.POINTER(Job), i32, i32, ctypes.POINTER(vp)]
+    L.rr_batch_launch.argtypes = [vp, vp]
+    L.rr_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.rr_batch_destroy.argtypes = [vp]
     L.rr_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
     L.rr_serve_alloc.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
     L.rr_serve_free.argtypes = [vp, vp]
@@ -164,10 +178,43 @@ def make_jobs(specs):
 
 def permute_batched_raw(jobs, njobs: int | None = None, stream=0) -> int:
     if not isinstance(jobs, ctypes.Array):
+        n = len(jobs)
         jobs = make_jobs(jobs)
-        njobs = len(jobs) if njobs is None else njobs
-    n = len(jobs) if njobs is None else njobs
+    else:
+        n = len(jobs) if njobs is None else njobs
     return lib().rr_permute_batched(jobs, n, _stream_handle(stream))
+
+
+class Batch:
+    """A reusable batch (rr_batch_create / rr_batch_launch / rr_batch_destroy)."""
+
+    def __init__(self, specs, flags: int = 0):
+        self._jobs = specs if isinstance(specs, ctypes.Array) else make_jobs(specs)
+        n = len(self._jobs) if not isinstance(specs, ctypes.Array) else len(specs)
+        if isinstance(specs, (list, tuple)) and len(specs) == 0:
+            n = 0
+        h = ctypes.c_void_p()
+        check(lib().rr_batch_create(self._jobs, n, int(flags), ctypes.byref(h)))
+        self.h = h
+
+    def launch(self, stream=None):
+        check(lib().rr_batch_launch(self.h, _stream_handle(stream)))
+
+    def info(self) -> dict:
+        i = BatchInfo()
+        check(lib().rr_batch_get_info(self.h, ctypes.byref(i)))
+        return {n: getattr(i, n) for n, _ in BatchInfo._fields_}
+
+    def close(self):
+        if self.h:
+            check(lib().rr_batch_destroy(self.h))
+            self.h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
 
 
 def order_to_perm(order):
@@ -187,8 +234,10 @@ def plan_describe(dims, perm, elem_size: int, dst: int = 0, src: int = 0) -> dic
     return out
 
 
-def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out: bool = False):
-    check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), 1 if order_out else 0))
+def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None):
+    """order_out: True = output order, False = input order, None = built-in choice."""
+    flags = 0 if order_out is None else (1 if order_out else 2)
+    check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))
 
 
 # ----------------------------------------------------------------- torch helpers

@@ -147,7 +147,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     TileOptions& o = tile_override();
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
-    o.order_out = (flags & 1) ? 1 : 0;
+    o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
     return RR_OK;
 }
 

@@ -1,7 +1,310 @@
-// rr_batch.cpp -- batched permutes (placeholder until the persistent kernel lands).
-#include "rr_internal.hpp"
+// rr_batch.cpp -- batched permutes: one-shot rr_permute_batched and reusable
+// rr_batch handles (resident job table, optional hipGraph replay, autotuning).
+#include <hip/hip_runtime_api.h>
 
-extern "C" rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) {
-    (void)jobs; (void)njobs; (void)stream;
-    return rr::fail(RR_ERR_UNSUPPORTED, "batched launch not built yet");
+#include <algorithm>
+#include <chrono>
+#include <cstring>
+#include <map>
+#include <mutex>
+#include <string>
+#include <vector>
+
+#include "rr_batch.hpp"
+#include "rr_internal.hpp"
+#include "rr_kernels.hpp"
+
+namespace rr {
+
+namespace {
+
+// Staging ring of pinned host + device buffers for one-shot batches.
+struct Slot {
+    void* host = nullptr;
+    void* dev = nullptr;
+    size_t cap = 0;
+    hipEvent_t done = nullptr;
+    bool used = false;
+};
+constexpr int RING = 4;
+struct Ring {
+    Slot slots[RING];
+    int next = 0;
+};
+std::mutex g_ring_mu;
+std::map<int, Ring> g_rings;
+
+int cu_count(int device) {
+    static std::map<int, int> cache;
+    static std::mutex mu;
+    std::lock_guard<std::mutex> lk(mu);
+    auto it = cache.find(device);
+    if (it != cache.end()) return it->second;
+    int n = 0;
+    if (hipDeviceGetAttribute(&n, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || n <= 0) n = 256;
+    cache[device] = n;
+    return n;
 }
+
+uint32_t group_grid(const BatchGroup& g, bool persistent, int device) {
+    if (!persistent) return g.total_blocks;
+    const uint32_t per_cu = g.kind == K_TILE ? (g.lds_bytes > 32768 ? 2u : 4u) : 8u;
+    return std::min<uint32_t>(g.total_blocks, (uint32_t)cu_count(device) * per_cu);
+}
+
+rr_status launch_groups(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
+                        hipStream_t st) {
+    for (const BatchGroup& g : p.groups) {
+        hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), st);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    return RR_OK;
+}
+
+rr_status plan_or_fail(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* bp) {
+    std::string why;
+    int bad = -1;
+    rr_status st = plan_batch(jobs, njobs, opt, bp, &why, &bad);
+    if (st != RR_OK) {
+        if (bad >= 0) why = "job " + std::to_string(bad) + ": " + why;
+        return fail(st, why);
+    }
+    return RR_OK;
+}
+
+}  // namespace
+
+}  // namespace rr
+
+using namespace rr;
+
+struct rr_batch {
+    int device = 0;
+    int flags = 0;
+    std::vector<rr_job> jobs;
+    BatchPlan plan;
+    TileOptions opt;
+    bool persistent = false;
+    void* dev_table = nullptr;
+    size_t dev_cap = 0;
+    hipStream_t cap_stream = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    double tuned_us = 0.0;
+};
+
+namespace {
+
+rr_status upload_table(rr_batch* b) {
+    const size_t need = std::max<size_t>(b->plan.table.size(), 256);
+    if (need > b->dev_cap) {
+        if (b->dev_table) (void)hipFree(b->dev_table);
+        b->dev_table = nullptr;
+        b->dev_cap = 0;
+        hipError_t e = hipMalloc(&b->dev_table, need);
+        if (e != hipSuccess) return fail(RR_ERR_NO_MEMORY, "cannot allocate the batch table");
+        b->dev_cap = need;
+    }
+    if (!b->plan.table.empty()) {
+        hipError_t e = hipMemcpy(b->dev_table, b->plan.table.data(), b->plan.table.size(), hipMemcpyHostToDevice);
+        if (e != hipSuccess) return hip_fail(e, "batch table upload");
+    }
+    return RR_OK;
+}
+
+void drop_graph(rr_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+}
+
+// Time one launch of the batch as planned now (median of 3 after a warm-up).
+rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess || hipEventCreate(&e1) != hipSuccess)
+        return fail(RR_ERR_HIP, "hipEventCreate failed");
+    std::vector<float> ts;
+    rr_status rs = RR_OK;
+    for (int r = 0; r < 4 && rs == RR_OK; ++r) {
+        (void)hipEventRecord(e0, st);
+        rs = launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st);
+        (void)hipEventRecord(e1, st);
+        (void)hipEventSynchronize(e1);
+        float ms = 0;
+        (void)hipEventElapsedTime(&ms, e0, e1);
+        if (r > 0) ts.push_back(ms);
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (rs != RR_OK) return rs;
+    std::sort(ts.begin(), ts.end());
+    *us = ts[ts.size() / 2] * 1e3;
+    return RR_OK;
+}
+
+rr_status tune(rr_batch* b) {
+    struct Cand { int in_rb, out_rb, order; bool persistent; };
+    const Cand cands[] = {{0, 0, 0, false}, {0, 0, 1, false}, {0, 0, 0, true}, {256, 512, 0, false},
+                          {512, 256, 0, false}, {512, 512, 0, false}, {1024, 256, 0, false},
+                          {256, 1024, 0, false}, {512, 256, 1, false}, {128, 256, 0, false}};
+    hipStream_t st;
+    if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(RR_ERR_HIP, "stream");
+    double best = 1e300;
+    Cand bestc = cands[0];
+    rr_status rs = RR_OK;
+    for (const Cand& c : cands) {
+        TileOptions o;
+        o.in_row_bytes = c.in_rb;
+        o.out_row_bytes = c.out_rb;
+        o.order_out = c.order;
+        BatchPlan p;
+        std::string why;
+        int bad;
+        if (plan_batch(b->jobs.data(), (int)b->jobs.size(), o, &p, &why, &bad) != RR_OK) continue;
+        b->plan = std::move(p);
+        b->persistent = c.persistent;
+        if ((rs = upload_table(b)) != RR_OK) break;
+        double us = 0;
+        if ((rs = time_batch(b, st, &us)) != RR_OK) break;
+        if (us < best) { best = us; bestc = c; }
+    }
+    (void)hipStreamDestroy(st);
+    if (rs != RR_OK) return rs;
+    b->opt.in_row_bytes = bestc.in_rb;
+    b->opt.out_row_bytes = bestc.out_rb;
+    b->opt.order_out = bestc.order;
+    b->persistent = bestc.persistent;
+    b->tuned_us = best;
+    rs = plan_or_fail(b->jobs.data(), (int)b->jobs.size(), b->opt, &b->plan);
+    if (rs != RR_OK) return rs;
+    return upload_table(b);
+}
+
+}  // namespace
+
+extern "C" {
+
+rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) {
+    clear_error();
+    BatchPlan bp;
+    rr_status st = plan_or_fail(jobs, njobs, tile_override(), &bp);
+    if (st != RR_OK) return st;
+    if (bp.groups.empty()) return RR_OK;
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    hipStream_t hs = (hipStream_t)stream;
+    std::lock_guard<std::mutex> lk(g_ring_mu);
+    Ring& ring = g_rings[device];
+    Slot& s = ring.slots[ring.next];
+    ring.next = (ring.next + 1) % RING;
+    if (s.used) {
+        e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(e, "waiting for a staging slot");
+    }
+    const size_t need = bp.table.size();
+    if (need > s.cap) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        s.host = s.dev = nullptr;
+        s.cap = 0;
+        size_t cap = std::max<size_t>(need, 1 << 20);
+        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(RR_ERR_NO_MEMORY, "pinned staging buffer");
+        if (hipMalloc(&s.dev, cap) != hipSuccess) {
+            (void)hipHostFree(s.host);
+            s.host = nullptr;
+            return fail(RR_ERR_NO_MEMORY, "device job table");
+        }
+        s.cap = cap;
+    }
+    if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        return fail(RR_ERR_HIP, "hipEventCreate");
+    std::memcpy(s.host, bp.table.data(), need);
+    e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, hs);
+    if (e != hipSuccess) return hip_fail(e, "job table upload");
+    st = launch_groups(bp, (const uint8_t*)s.dev, false, device, hs);
+    e = hipEventRecord(s.done, hs);
+    s.used = true;
+    if (st != RR_OK) return st;
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    return RR_OK;
+}
+
+rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** out) {
+    clear_error();
+    if (!out) return fail(RR_ERR_INVALID_ARG, "out is NULL");
+    *out = nullptr;
+    if (flags & ~(RR_BATCH_GRAPH | RR_BATCH_TUNE | RR_BATCH_PERSISTENT))
+        return fail(RR_ERR_INVALID_ARG, "unknown flags");
+    rr_batch* b = new rr_batch();
+    b->flags = flags;
+    b->persistent = (flags & RR_BATCH_PERSISTENT) != 0;
+    if (njobs > 0 && jobs) b->jobs.assign(jobs, jobs + njobs);
+    hipError_t e = hipGetDevice(&b->device);
+    rr_status st = e == hipSuccess ? RR_OK : hip_fail(e, "hipGetDevice");
+    if (st == RR_OK) st = plan_or_fail(jobs, njobs, b->opt, &b->plan);
+    if (st == RR_OK) st = upload_table(b);
+    if (st == RR_OK && (flags & RR_BATCH_TUNE) && !b->plan.groups.empty()) st = tune(b);
+    if (st != RR_OK) {
+        if (b->dev_table) (void)hipFree(b->dev_table);
+        delete b;
+        return st;
+    }
+    *out = b;
+    return RR_OK;
+}
+
+rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream) {
+    clear_error();
+    if (!b) return fail(RR_ERR_INVALID_ARG, "NULL batch");
+    if (b->plan.groups.empty()) return RR_OK;
+    hipStream_t hs = (hipStream_t)stream;
+    if (!(b->flags & RR_BATCH_GRAPH))
+        return launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs);
+    if (!b->exec) {
+        if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
+            return fail(RR_ERR_HIP, "capture stream");
+        hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
+        rr_status st = launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream);
+        hipGraph_t g = nullptr;
+        e = hipStreamEndCapture(b->cap_stream, &g);
+        if (st != RR_OK) { if (g) (void)hipGraphDestroy(g); return st; }
+        if (e != hipSuccess) return hip_fail(e, "hipStreamEndCapture");
+        b->graph = g;
+        e = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (e != hipSuccess) { drop_graph(b); return hip_fail(e, "hipGraphInstantiate"); }
+    }
+    hipError_t e = hipGraphLaunch(b->exec, hs);
+    if (e != hipSuccess) return hip_fail(e, "hipGraphLaunch");
+    return RR_OK;
+}
+
+rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out) {
+    clear_error();
+    if (!b || !out) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    std::memset(out, 0, sizeof *out);
+    out->njobs = (int32_t)b->plan.njobs;
+    out->ngroups = (int32_t)b->plan.groups.size();
+    out->in_row_bytes = b->opt.in_row_bytes;
+    out->out_row_bytes = b->opt.out_row_bytes;
+    out->order_out = b->opt.order_out;
+    out->persistent = b->persistent ? 1 : 0;
+    out->bytes = b->plan.bytes;
+    out->tuned_us = b->tuned_us;
+    return RR_OK;
+}
+
+rr_status rr_batch_destroy(rr_batch* b) {
+    clear_error();
+    if (!b) return RR_OK;
+    drop_graph(b);
+    if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
+    if (b->dev_table) (void)hipFree(b->dev_table);
+    delete b;
+    return RR_OK;
+}
+
+}  // extern "C"

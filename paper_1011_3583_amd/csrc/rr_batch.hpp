@@ -1,0 +1,43 @@
+// rr_batch.hpp -- planning of batched permutes (host side, no HIP).
+//
+// Jobs are validated and planned one by one exactly as rr_permute would plan
+// them, then grouped by kernel family (copy / run / tile with a given unit and
+// micro-tile).  Each group becomes one device table: the jobs' argument blocks
+// plus an exclusive prefix sum of their workgroup counts, so one launch of the
+// family's batched kernel covers every job of the group; workgroup b finds its
+// job by binary search over the prefix sums.
+#pragma once
+
+#include <cstdint>
+#include <string>
+#include <vector>
+
+#include "rr_plan.hpp"
+
+namespace rr {
+
+struct BatchGroup {
+    int32_t kind;          // K_COPY / K_RUN / K_TILE
+    int32_t variant;       // vector bytes (copy, run) or unit*100 + g (tile)
+    uint32_t njobs;
+    uint32_t total_blocks;
+    uint32_t lds_bytes;    // largest tile of the group
+    uint32_t pad_;
+    uint64_t args_off;     // byte offset of the argument array in the table
+    uint64_t prefix_off;   // byte offset of the njobs+1 prefix sums (uint32)
+    uint64_t bytes;        // bytes per side moved by the group
+};
+
+struct BatchPlan {
+    std::vector<uint8_t> table;        // argument arrays and prefix sums, 256-byte aligned pieces
+    std::vector<BatchGroup> groups;
+    uint64_t bytes = 0;                // bytes per side over all jobs
+    uint32_t njobs = 0;
+};
+
+// Validate and plan `njobs` jobs.  On error *bad_job is the index of the first
+// failing job (or -1 for a cross-job overlap) and nothing is planned.
+rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
+                     std::string* why, int* bad_job);
+
+}  // namespace rr

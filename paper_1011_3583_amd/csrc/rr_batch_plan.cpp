@@ -1,0 +1,127 @@
+// rr_batch_plan.cpp -- validation, per-job planning and grouping of batched
+// permutes (host only; shared by the library and its CPU emulator).
+#include <algorithm>
+#include <cstring>
+#include <map>
+
+#include "rr_batch.hpp"
+
+namespace rr {
+
+namespace {
+
+struct Interval {
+    uint64_t lo, hi;  // [lo, hi)
+    int job;
+};
+
+// Destinations must not overlap any other job's source or destination.
+bool find_overlap(std::vector<Interval>& dsts, std::vector<Interval>& srcs, int* a, int* b) {
+    std::sort(dsts.begin(), dsts.end(), [](const Interval& x, const Interval& y) { return x.lo < y.lo; });
+    for (size_t i = 1; i < dsts.size(); ++i)
+        if (dsts[i].lo < dsts[i - 1].hi) { *a = dsts[i - 1].job; *b = dsts[i].job; return true; }
+    for (const Interval& s : srcs) {
+        // last destination starting before the source ends
+        auto it = std::lower_bound(dsts.begin(), dsts.end(), s.hi,
+                                   [](const Interval& d, uint64_t v) { return d.lo < v; });
+        if (it == dsts.begin()) continue;
+        --it;
+        if (it->hi > s.lo && it->job != s.job) { *a = it->job; *b = s.job; return true; }
+    }
+    return false;
+}
+
+uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+}  // namespace
+
+rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
+                     std::string* why, int* bad_job) {
+    *bad_job = -1;
+    out->table.clear();
+    out->groups.clear();
+    out->bytes = 0;
+    out->njobs = 0;
+    if (njobs < 0) { *why = "njobs < 0"; return RR_ERR_INVALID_ARG; }
+    if (njobs > 0 && !jobs) { *why = "jobs is NULL"; return RR_ERR_INVALID_ARG; }
+
+    std::vector<Plan> plans((size_t)njobs);
+    std::vector<Interval> dsts, srcs;
+    dsts.reserve((size_t)njobs);
+    srcs.reserve((size_t)njobs);
+    for (int i = 0; i < njobs; ++i) {
+        const rr_job& j = jobs[i];
+        Canon c;
+        rr_status st = canonicalize(j.ndim, j.dims, j.perm, j.elem_size, &c, why);
+        if (st != RR_OK) { *bad_job = i; return st; }
+        if (c.total_bytes > 0) {
+            if (!j.dst || !j.src) { *bad_job = i; *why = "NULL buffer for a non-empty job"; return RR_ERR_INVALID_ARG; }
+            const uint64_t d = (uint64_t)j.dst, s = (uint64_t)j.src, n = (uint64_t)c.total_bytes;
+            if (d < s + n && s < d + n) { *bad_job = i; *why = "job source and destination overlap"; return RR_ERR_ALIAS; }
+            dsts.push_back({d, d + n, i});
+            srcs.push_back({s, s + n, i});
+        }
+        st = plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, &plans[(size_t)i], why);
+        if (st != RR_OK) { *bad_job = i; return st; }
+    }
+    int ja, jb;
+    if (find_overlap(dsts, srcs, &ja, &jb)) {
+        *why = "jobs " + std::to_string(ja) + " and " + std::to_string(jb) + " overlap";
+        *bad_job = -1;
+        return RR_ERR_ALIAS;
+    }
+
+    // group by kernel family
+    std::map<std::pair<int, int>, std::vector<int>> fam;
+    for (int i = 0; i < njobs; ++i) {
+        const Plan& p = plans[(size_t)i];
+        if (p.kind == K_EMPTY || p.grid == 0) continue;
+        int variant = 0;
+        if (p.kind == K_COPY) variant = (int)p.copy.wbytes;
+        else if (p.kind == K_RUN) variant = (int)p.run.wbytes;
+        else variant = (int)(p.tile.unit * 100 + p.tile.g);
+        fam[{(int)p.kind, variant}].push_back(i);
+        out->bytes += p.bytes;
+        out->njobs++;
+    }
+    uint64_t off = 0;
+    for (auto& kv : fam) {
+        BatchGroup g;
+        std::memset(&g, 0, sizeof g);
+        g.kind = kv.first.first;
+        g.variant = kv.first.second;
+        g.njobs = (uint32_t)kv.second.size();
+        size_t asz = g.kind == K_COPY ? sizeof(CopyArgs) : g.kind == K_RUN ? sizeof(RunArgs) : sizeof(TileArgs);
+        g.args_off = off;
+        off = align_up(off + asz * g.njobs, 256);
+        g.prefix_off = off;
+        off = align_up(off + 4ull * (g.njobs + 1), 256);
+        out->groups.push_back(g);
+    }
+    out->table.assign(off, 0);
+    for (size_t gi = 0; gi < out->groups.size(); ++gi) {
+        BatchGroup& g = out->groups[gi];
+        const std::vector<int>& members = fam[{g.kind, g.variant}];
+        uint32_t* prefix = reinterpret_cast<uint32_t*>(out->table.data() + g.prefix_off);
+        uint64_t acc = 0;
+        for (size_t m = 0; m < members.size(); ++m) {
+            const Plan& p = plans[(size_t)members[m]];
+            prefix[m] = (uint32_t)acc;
+            acc += p.grid;
+            g.bytes += p.bytes;
+            uint8_t* dstp = out->table.data() + g.args_off;
+            if (g.kind == K_COPY) std::memcpy(dstp + m * sizeof(CopyArgs), &p.copy, sizeof(CopyArgs));
+            else if (g.kind == K_RUN) std::memcpy(dstp + m * sizeof(RunArgs), &p.run, sizeof(RunArgs));
+            else {
+                std::memcpy(dstp + m * sizeof(TileArgs), &p.tile, sizeof(TileArgs));
+                g.lds_bytes = std::max(g.lds_bytes, p.tile.lds_bytes);
+            }
+        }
+        if (acc > 0x7fffffffULL) { *why = "batch group exceeds 2^31 workgroups"; return RR_ERR_UNSUPPORTED; }
+        prefix[members.size()] = (uint32_t)acc;
+        g.total_blocks = (uint32_t)acc;
+    }
+    return RR_OK;
+}
+
+}  // namespace rr

@@ -37,21 +37,44 @@ typedef uint32_t rr_u32x2 __attribute__((ext_vector_type(2)));
 #endif
 
 // ----------------------------------------------------------------- vector I/O
-template <int W>
-RR_HD void vload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
+// Global memory is streamed: every byte is read once and written once, so both
+// sides use non-temporal accesses (they keep the streams from displacing each
+// other in L2 and the Infinity Cache).  LDS accesses are ordinary.
+#ifndef RR_RB_U1
+#define RR_RB_U1 16
+#endif
+#ifndef RR_RB_U2
+#define RR_RB_U2 8
+#endif
+#ifndef RR_RB_U4
+#define RR_RB_U4 4
+#endif
+#ifndef RR_NT_LOAD
+#define RR_NT_LOAD 1
+#endif
+#ifndef RR_NT_STORE
+#define RR_NT_STORE 1
+#endif
+
+template <int W, bool NT_ACCESS>
+RR_HD void vload_t(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (W == 16) {
-        rr_u32x4 v = *reinterpret_cast<const rr_u32x4*>(p);
+        const rr_u32x4* q = reinterpret_cast<const rr_u32x4*>(p);
+        rr_u32x4 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
         w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
     } else if constexpr (W == 8) {
-        rr_u32x2 v = *reinterpret_cast<const rr_u32x2*>(p);
+        const rr_u32x2* q = reinterpret_cast<const rr_u32x2*>(p);
+        rr_u32x2 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
         w[0] = v.x; w[1] = v.y;
     } else if constexpr (W == 4) {
-        w[0] = *reinterpret_cast<const uint32_t*>(p);
+        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
+        w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
     } else if constexpr (W == 2) {
-        w[0] = *reinterpret_cast<const uint16_t*>(p);
+        const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
+        w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
     } else {
-        w[0] = *p;
+        w[0] = NT_ACCESS ? __builtin_nontemporal_load(p) : *p;
     }
 #else
     uint8_t tmp[4 * NWords<W>::value] = {};
@@ -60,26 +83,40 @@ RR_HD void vload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
 #endif
 }
 
-template <int W>
-RR_HD void vstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
+template <int W, bool NT_ACCESS>
+RR_HD void vstore_t(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
 #if defined(__HIP_DEVICE_COMPILE__)
     if constexpr (W == 16) {
         rr_u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
-        *reinterpret_cast<rr_u32x4*>(p) = v;
+        rr_u32x4* q = reinterpret_cast<rr_u32x4*>(p);
+        if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
     } else if constexpr (W == 8) {
         rr_u32x2 v; v.x = w[0]; v.y = w[1];
-        *reinterpret_cast<rr_u32x2*>(p) = v;
+        rr_u32x2* q = reinterpret_cast<rr_u32x2*>(p);
+        if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
     } else if constexpr (W == 4) {
-        *reinterpret_cast<uint32_t*>(p) = w[0];
+        uint32_t* q = reinterpret_cast<uint32_t*>(p);
+        if (NT_ACCESS) __builtin_nontemporal_store(w[0], q); else *q = w[0];
     } else if constexpr (W == 2) {
-        *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
+        uint16_t* q = reinterpret_cast<uint16_t*>(p);
+        if (NT_ACCESS) __builtin_nontemporal_store((uint16_t)w[0], q); else *q = (uint16_t)w[0];
     } else {
-        *p = (uint8_t)w[0];
+        if (NT_ACCESS) __builtin_nontemporal_store((uint8_t)w[0], p); else *p = (uint8_t)w[0];
     }
 #else
     std::memcpy(p, w, W);
 #endif
 }
+
+// global memory (streamed) and LDS (ordinary)
+template <int W>
+RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, RR_NT_LOAD != 0>(p, w); }
+template <int W>
+RR_HD void gstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, RR_NT_STORE != 0>(p, w); }
+template <int W>
+RR_HD void sload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, false>(p, w); }
+template <int W>
+RR_HD void sstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, false>(p, w); }
 
 // GxG transpose of U-byte elements held as G rows of W = U*G bytes:
 //   out[i] element j  =  in[j] element i.
@@ -127,12 +164,12 @@ RR_HD void copy_thread(const CopyArgs& a, uint32_t block, uint32_t nblocks, uint
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint64_t v = i + (uint64_t)u * NT;
-            if (v < a.nvec) vload<W>(s + v * W, w[u]);
+            if (v < a.nvec) gload<W>(s + v * W, w[u]);
         }
 #pragma unroll
         for (int u = 0; u < 4; ++u) {
             const uint64_t v = i + (uint64_t)u * NT;
-            if (v < a.nvec) vstore<W>(d + v * W, w[u]);
+            if (v < a.nvec) gstore<W>(d + v * W, w[u]);
         }
     }
     if (block == 0) {
@@ -173,13 +210,13 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
                 }
             }
             off += (uint64_t)rem * a.sin[0];
-            vload<W>(src + off + (uint64_t)part * W, w[u]);
+            gload<W>(src + off + (uint64_t)part * W, w[u]);
         }
     }
 #pragma unroll
     for (int u = 0; u < 4; ++u) {
         const uint32_t v = base + u * NT;
-        if (v < a.nvec) vstore<W>(dst + (uint64_t)v * W, w[u]);
+        if (v < a.nvec) gstore<W>(dst + (uint64_t)v * W, w[u]);
     }
 }
 
@@ -262,12 +299,18 @@ RR_HD uint32_t lds_pos(const TileArgs& a, uint32_t ib, uint32_t x) {
     return ib * a.pitch + (cc << 4) + (x & 15u);
 }
 
+// Loads each thread keeps in flight before writing any of them to LDS.  Tiles
+// are planned to need 16/U loads per thread for U = 1, 2 (64 and 32 KiB tiles,
+// where LDS already limits occupancy) and 4 for U >= 4 (16 KiB tiles, where the
+// register budget decides how many waves fit).
+template <int U>
+struct ReadBatch { static constexpr int value = U == 1 ? RR_RB_U1 : (U == 2 ? RR_RB_U2 : RR_RB_U4); };
+
 // Read phase: rows of the tile (contiguous along the input's fastest axes) are
 // loaded with WIN-byte vectors and parked in LDS.
-template <int WIN, int G>
+template <int WIN, int G, int B>
 RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int NWI = NWords<WIN>::value;
-    constexpr int B = WIN >= 8 ? 8 : 4;
     const uint32_t total = a.TB * a.rch;
     const uint32_t rowvalid = t.TAv * a.R;
     for (uint32_t base = 0; base < total; base += NT * B) {
@@ -283,24 +326,48 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
             lo[u] = 0;
             if (ok[u]) {
                 const uint8_t* p = reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x);
-                vload<WIN>(p, w[u]);
+                gload<WIN>(p, w[u]);
                 lo[u] = lds_pos<G>(a, ib, x);
             }
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
-            if (ok[u]) vstore<WIN>(lds + lo[u], w[u]);
+            if (ok[u]) sstore<WIN>(lds + lo[u], w[u]);
     }
 }
 
-template <int G>
+// Flat read: the tile's input rows are back to back in memory (a contiguous
+// byte range), and LDS holds them unpadded, so the whole range moves with
+// 16-byte vectors however short or oddly sized a row is (de-interlace).
+template <int B>
+RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    const uint32_t nbytes = t.TBv * a.pitch;
+    const uint32_t nvec = nbytes / a.win;
+    for (uint32_t base = 0; base < nvec; base += NT * B) {
+        uint32_t w[B][4];
+        bool ok[B];
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            const uint32_t v = base + u * NT + tid;
+            ok[u] = v < nvec;
+            if (ok[u]) gload<16>(reinterpret_cast<const uint8_t*>(t.bin) + (uint64_t)v * 16, w[u]);
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u)
+            if (ok[u]) sstore<16>(lds + (base + u * NT + tid) * 16, w[u]);
+    }
+}
+
+template <int U, int G>
 RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    constexpr int B = ReadBatch<U>::value;
+    if (a.flags & TF_IN_FLAT) { read_flat<4>(a, t, lds, tid); return; }
     switch (a.win) {
-        case 16: read_phase<16, G>(a, t, lds, tid); break;
-        case 8: read_phase<8, G>(a, t, lds, tid); break;
-        case 4: read_phase<4, G>(a, t, lds, tid); break;
-        case 2: read_phase<2, G>(a, t, lds, tid); break;
-        default: read_phase<1, G>(a, t, lds, tid); break;
+        case 16: read_phase<16, G, B>(a, t, lds, tid); break;
+        case 8: read_phase<8, G, B>(a, t, lds, tid); break;
+        case 4: read_phase<4, G, 4>(a, t, lds, tid); break;
+        case 2: read_phase<2, G, 4>(a, t, lds, tid); break;
+        default: read_phase<1, G, 4>(a, t, lds, tid); break;
     }
 }
 
@@ -319,17 +386,33 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
             if (ia0 < t.TAv && ib0 < t.TBv) {
                 uint32_t r[G][NW];
 #pragma unroll
-                for (int j = 0; j < G; ++j) vload<W>(lds + lds_pos<G>(a, ib0 + j, ia0 * U), r[j]);
+                for (int j = 0; j < G; ++j) sload<W>(lds + lds_pos<G>(a, ib0 + j, ia0 * U), r[j]);
                 uint32_t o[G][NW];
                 xpose<U, G>(r, o);
                 if (a.flags & TF_OUT_TABLE) {
 #pragma unroll
                     for (int i = 0; i < G; ++i)
-                        vstore<W>(reinterpret_cast<uint8_t*>(a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U), o[i]);
+                        gstore<W>(reinterpret_cast<uint8_t*>(a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U), o[i]);
+                } else if (W >= 4 && W * G >= 16 && (a.flags & TF_OUT_MERGE)) {
+                    // the G output rows are back to back: store them as 16-byte vectors
+                    constexpr int NV = (W * G >= 16) ? W * G / 16 : 1;
+                    constexpr int PER = W >= 4 ? W / 4 : 1;
+                    uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0));
+                    uint32_t flat[NV * 4];
+#pragma unroll
+                    for (int i = 0; i < G; ++i)
+#pragma unroll
+                        for (int c = 0; c < PER; ++c)
+                            if (i * PER + c < NV * 4) flat[i * PER + c] = o[i][c];
+#pragma unroll
+                    for (int v = 0; v < NV; ++v) {
+                        const uint32_t(&fv)[4] = *reinterpret_cast<const uint32_t(*)[4]>(&flat[v * 4]);
+                        gstore<16>(q + v * 16, fv);
+                    }
                 } else {
                     uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0) + (uint64_t)ib0 * U);
 #pragma unroll
-                    for (int i = 0; i < G; ++i) vstore<W>(q + (uint64_t)i * a.soutA[0], o[i]);
+                    for (int i = 0; i < G; ++i) gstore<W>(q + (uint64_t)i * a.soutA[0], o[i]);
                 }
             }
         }
@@ -341,11 +424,37 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
             const uint32_t s = m - ib * a.k;
             if (ia < t.TAv && ib < t.TBv) {
                 uint32_t v[NWords<U>::value];
-                vload<U>(lds + lds_pos<1>(a, ib, (ia * a.k + s) * U), v);
-                vstore<U>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
+                sload<U>(lds + lds_pos<1>(a, ib, (ia * a.k + s) * U), v);
+                gstore<U>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
             }
         }
     }
+}
+
+// ----------------------------------------------------------------- batches
+// Job of workgroup b in a batch group: the largest j with prefix[j] <= b
+// (prefix holds njobs+1 exclusive sums of the jobs' workgroup counts).
+RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
+    uint32_t lo = 0, hi = njobs;
+    while (hi - lo > 1) {
+        const uint32_t mid = (lo + hi) >> 1;
+        if (prefix[mid] <= b) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+template <int W>
+RR_HD void batch_copy_block(const CopyArgs* args, const uint32_t* prefix, uint32_t njobs, uint32_t b,
+                            uint32_t tid) {
+    const uint32_t j = find_job(prefix, njobs, b);
+    copy_thread<W>(args[j], b - prefix[j], prefix[j + 1] - prefix[j], tid);
+}
+
+template <int W>
+RR_HD void batch_run_block(const RunArgs* args, const uint32_t* prefix, uint32_t njobs, uint32_t b,
+                           uint32_t tid) {
+    const uint32_t j = find_job(prefix, njobs, b);
+    run_thread<W>(args[j], b - prefix[j], tid);
 }
 
 }  // namespace rr

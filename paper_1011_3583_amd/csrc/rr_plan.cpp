@@ -131,7 +131,7 @@ void plan_copy(uint64_t dst, uint64_t src, uint64_t nbytes, Plan* p) {
     uint64_t per_block = (uint64_t)NT * 4;
     uint64_t g = (body + per_block - 1) / per_block;
     if (g < 1) g = 1;
-    if (g > 65536) g = 65536;  // grid-stride beyond this
+    if (g > 0x7fffffffULL) g = 0x7fffffffULL;  // grid-stride beyond this
     p->grid = (uint32_t)g;
 }
 
@@ -186,20 +186,34 @@ static int default_row_bytes(int U, bool in_side) {
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
 // Fill the LDS / read / write geometry of a tile plan whose extents are set.
-static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_align_in,
-                             const TileOptions& opt, std::string* why) {
+//   row_align_in : OR of every input row start offset (alignment probe)
+//   flat_ok      : input rows are back to back (row stride == row bytes) and the
+//                  whole extent along the row axis is total_rows
+static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_align_in, bool flat_ok,
+                             uint64_t flat_base, uint64_t total_rows, const TileOptions& opt,
+                             std::string* why) {
     a.unit = U; a.g = G; a.k = k;
     a.mk = make_magic(k);
     const uint64_t rowbytes = (uint64_t)a.TA * a.R;
-    a.pitch = (uint32_t)((rowbytes + 15) / 16 * 16);
-    a.nch16 = a.pitch / 16;
-    uint32_t pw = 1;
-    while (pw * 2 <= a.nch16) pw <<= 1;
-    a.rotmask = pw - 1;
-    a.lds_bytes = a.pitch * a.TB;
+    const bool flat = flat_ok && (rowbytes % 16 != 0 || rowbytes < 64) && (flat_base % 16) == 0 &&
+                      ((uint64_t)a.TB * rowbytes) % 16 == 0 && (total_rows * rowbytes) % 16 == 0;
+    if (flat) {
+        a.flags |= TF_IN_FLAT;
+        a.pitch = (uint32_t)rowbytes;
+        a.nch16 = 0xffffffffu;   // no chunk rotation
+        a.rotmask = 0;
+    } else {
+        a.pitch = (uint32_t)((rowbytes + 15) / 16 * 16);
+        a.nch16 = a.pitch / 16;
+        uint32_t pw = 1;
+        while (pw * 2 <= a.nch16) pw <<= 1;
+        a.rotmask = pw - 1;
+    }
+    a.lds_bytes = (a.pitch * a.TB + 15) / 16 * 16;
     if (a.lds_bytes > (uint32_t)opt.max_lds) { *why = "tile does not fit LDS"; return RR_ERR_UNSUPPORTED; }
     uint32_t win = 16;
-    while (win > (uint32_t)U && ((row_align_in % win) || (rowbytes % win))) win >>= 1;
+    if (!flat)
+        while (win > (uint32_t)U && ((row_align_in % win) || (rowbytes % win))) win >>= 1;
     if (win < (uint32_t)U) win = U;
     a.win = win;
     a.rch = (uint32_t)(rowbytes / win);
@@ -207,6 +221,10 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
     if (k == 1) {
         a.nmb = a.TB / G;
         a.nwork = a.nmb * (a.TA / G);
+        const uint32_t W = (uint32_t)(U * G);
+        if (a.nmb == 1 && a.nA == 1 && !(a.flags & TF_OUT_TABLE) && a.soutA[0] == W && W >= 4 &&
+            (W * G) % 16 == 0)
+            a.flags |= TF_OUT_MERGE;
     } else {
         a.nmb = a.TB * k;      // units per output row
         a.nwork = a.nmb * a.TA;
@@ -305,7 +323,11 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     // tile grid
     int order[MAXR];
     for (int i = 0; i < r; ++i) order[i] = i;
-    if (opt.order_out) for (int j = 0; j < r; ++j) order[j] = pm[j];
+    // Tiles of 4..16-byte elements are walked in output order (neighbouring
+    // workgroups then write neighbouring output segments); 1- and 2-byte
+    // elements keep input order, which measured slightly faster for them.
+    const bool order_out = opt.order_out < 0 ? U >= 4 : opt.order_out != 0;
+    if (order_out) for (int j = 0; j < r; ++j) order[j] = pm[j];
     a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1;
     uint64_t ntiles = 1;
     for (int oi = 0; oi < r; ++oi) {
@@ -329,7 +351,10 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     // input rows start at multiples of d[a1]*R plus the tile's column offset
     uint64_t ra = src | (uint64_t)(d[a1] * R);
     if (nA == 1) ra |= (uint64_t)(t[a1] * R);
-    rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+    // rows are back to back when every A axis is whole and the single B axis is
+    // the next slower input axis
+    const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA;
+    rr_status st = finish_tile(a, U, G, k, ra, flat_ok, src, (uint64_t)d[b1], opt, why);
     if (st != RR_OK) return st;
     p->grid = a.ntiles;
     p->bytes = (uint64_t)c.total_bytes;
@@ -373,7 +398,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     // aim for ~16 KiB tiles: the plane axis is short
     const int64_t tile_target = 16384;
     int64_t L = std::max<int64_t>(cdiv(de ? out_rb : in_rb, R), cdiv(tile_target, n * R));
-    L = std::min<int64_t>(count, (L + G - 1) / G * G);
+    L = std::min<int64_t>(count, (L + 15) / 16 * 16);  // whole 16-byte vectors per row
     while (L > G && (int64_t)((L * R + 15) / 16 * 16) * n > opt.max_lds && !de) L = std::max<int64_t>(G, L / 2 / G * G);
     while (L > G && (int64_t)(((int64_t)n * R + 15) / 16 * 16) * L > opt.max_lds && de) L = std::max<int64_t>(G, L / 2 / G * G);
     a.R = (uint32_t)R;
@@ -396,7 +421,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
         for (int c = 0; c < n; ++c) a.table[c] = planes[c];
         uint64_t ra = (uint64_t)(L * R) | (uint64_t)(count * R);
         for (int c = 0; c < n; ++c) ra |= planes[c];
-        rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+        rr_status st = finish_tile(a, U, G, k, ra, false, 0, 0, opt, why);
         if (st != RR_OK) return st;
     } else {
         // A = plane axis (n, full), B = element axis (length L per tile)
@@ -414,7 +439,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
         a.bO_len = (uint32_t)count; a.bO_t = (uint32_t)L;
         for (int c = 0; c < n; ++c) a.table[c] = planes[c];
         uint64_t ra = a.src | (uint64_t)(n * R);
-        rr_status st = finish_tile(a, U, G, k, ra, opt, why);
+        rr_status st = finish_tile(a, U, G, k, ra, true, a.src, (uint64_t)count, opt, why);
         if (st != RR_OK) return st;
     }
     a.ntiles = (uint32_t)nt;

@@ -67,6 +67,8 @@ struct RunArgs {
 enum TileFlags : uint32_t {
     TF_IN_TABLE = 1u,    // input rows are absolute plane pointers (interlace)
     TF_OUT_TABLE = 2u,   // output rows are absolute plane pointers (de-interlace)
+    TF_IN_FLAT = 4u,     // input tile is one contiguous range, LDS rows unpadded
+    TF_OUT_MERGE = 8u,   // a micro-tile's G output rows are back to back (TB == G)
 };
 
 struct TileArgs {
@@ -112,7 +114,7 @@ struct TileArgs {
 struct TileOptions {
     int in_row_bytes = 0;   // 0 = default
     int out_row_bytes = 0;
-    int order_out = 0;      // 1: traverse tiles in output order
+    int order_out = -1;     // 1: traverse tiles in output order, 0: input order, -1: by unit size
     int max_lds = 65536;
 };
 

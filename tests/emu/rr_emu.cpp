@@ -22,6 +22,7 @@
 #include <string>
 #include <vector>
 
+#include "../../paper_1011_3583_amd/csrc/rr_batch.hpp"
 #include "../../paper_1011_3583_amd/csrc/rr_device.hpp"
 #include "../../paper_1011_3583_amd/csrc/rr_plan.hpp"
 
@@ -43,7 +44,7 @@ static void run_tile_ug(const TileArgs& a, uint32_t grid) {
         uint8_t* lds = new uint8_t[a.lds_bytes];
         std::memset(lds, 0xA5, a.lds_bytes);
         const TileCtx t = tile_decode(a, tile);
-        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<G>(a, t, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<U, G>(a, t, lds, tid);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) write_phase<U, G>(a, t, lds, tid);
         delete[] lds;
     }
@@ -80,6 +81,64 @@ template <int W>
 static void run_run_w(const RunArgs& a, uint32_t grid) {
     for (uint32_t b = 0; b < grid; ++b)
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) run_thread<W>(a, b, tid);
+}
+
+template <int U, int G>
+static void run_batch_tile_ug(const BatchGroup& g, const uint8_t* table) {
+    const TileArgs* args = reinterpret_cast<const TileArgs*>(table + g.args_off);
+    const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
+    for (uint32_t b = 0; b < g.total_blocks; ++b) {
+        const uint32_t j = find_job(prefix, g.njobs, b);
+        const TileArgs& a = args[j];
+        uint8_t* lds = new uint8_t[g.lds_bytes];
+        std::memset(lds, 0xA5, g.lds_bytes);
+        const TileCtx t = tile_decode(a, b - prefix[j]);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<U, G>(a, t, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) write_phase<U, G>(a, t, lds, tid);
+        delete[] lds;
+    }
+}
+
+template <int W>
+static void run_batch_small(const BatchGroup& g, const uint8_t* table) {
+    const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
+    for (uint32_t b = 0; b < g.total_blocks; ++b)
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) {
+            if (g.kind == K_COPY)
+                batch_copy_block<W>(reinterpret_cast<const CopyArgs*>(table + g.args_off), prefix, g.njobs, b, tid);
+            else
+                batch_run_block<W>(reinterpret_cast<const RunArgs*>(table + g.args_off), prefix, g.njobs, b, tid);
+        }
+}
+
+static bool emulate_group(const BatchGroup& g, const uint8_t* table) {
+    if (g.kind != K_TILE) {
+        switch (g.variant) {
+            case 16: run_batch_small<16>(g, table); return true;
+            case 8: run_batch_small<8>(g, table); return true;
+            case 4: run_batch_small<4>(g, table); return true;
+            case 2: run_batch_small<2>(g, table); return true;
+            default: run_batch_small<1>(g, table); return true;
+        }
+    }
+    switch (g.variant) {
+        case 101: run_batch_tile_ug<1, 1>(g, table); return true;
+        case 102: run_batch_tile_ug<1, 2>(g, table); return true;
+        case 104: run_batch_tile_ug<1, 4>(g, table); return true;
+        case 108: run_batch_tile_ug<1, 8>(g, table); return true;
+        case 116: run_batch_tile_ug<1, 16>(g, table); return true;
+        case 201: run_batch_tile_ug<2, 1>(g, table); return true;
+        case 202: run_batch_tile_ug<2, 2>(g, table); return true;
+        case 204: run_batch_tile_ug<2, 4>(g, table); return true;
+        case 208: run_batch_tile_ug<2, 8>(g, table); return true;
+        case 401: run_batch_tile_ug<4, 1>(g, table); return true;
+        case 402: run_batch_tile_ug<4, 2>(g, table); return true;
+        case 404: run_batch_tile_ug<4, 4>(g, table); return true;
+        case 801: run_batch_tile_ug<8, 1>(g, table); return true;
+        case 802: run_batch_tile_ug<8, 2>(g, table); return true;
+        case 1601: run_batch_tile_ug<16, 1>(g, table); return true;
+    }
+    return false;
 }
 
 static bool emulate(const Plan& p) {
@@ -179,6 +238,58 @@ int main(int argc, char** argv) {
             std::printf("ok %s\n", describe(plan).c_str());
             for (int c = 0; c < n; ++c) delete[] planes[c];
             delete[] flat;
+        } else if (op == "batched") {
+            // batched k in_rb out_rb order : then k lines "job ndim dims.. perm.. esize infile outfile"
+            int k, order;
+            is >> k >> opt.in_row_bytes >> opt.out_row_bytes >> order;
+            opt.order_out = order;
+            std::vector<rr_job> jobs((size_t)k);
+            std::vector<uint8_t*> bufs;
+            std::vector<std::string> outs((size_t)k);
+            std::vector<size_t> sizes((size_t)k);
+            for (int i = 0; i < k; ++i) {
+                std::string jl;
+                std::getline(mf, jl);
+                std::istringstream js(jl);
+                std::string tag;
+                js >> tag;
+                rr_job& j = jobs[(size_t)i];
+                std::memset(&j, 0, sizeof j);
+                js >> j.ndim;
+                int64_t n = 1;
+                for (int d = 0; d < j.ndim; ++d) { js >> j.dims[d]; n *= j.dims[d]; }
+                for (int d = 0; d < j.ndim; ++d) js >> j.perm[d];
+                std::string inf;
+                js >> j.elem_size >> inf >> outs[(size_t)i];
+                const size_t nb = (size_t)n * (size_t)j.elem_size;
+                sizes[(size_t)i] = nb;
+                std::vector<uint8_t> in = read_file(inf);
+                uint8_t* sb = new uint8_t[nb + 1];
+                uint8_t* db = new uint8_t[nb + 1];
+                if (nb) std::memcpy(sb, in.data(), nb);
+                std::memset(db, 0x5A, nb + 1);
+                bufs.push_back(sb);
+                bufs.push_back(db);
+                j.src = sb;
+                j.dst = db;
+            }
+            BatchPlan bp;
+            int bad = -1;
+            rr_status st = plan_batch(jobs.data(), k, opt, &bp, &why, &bad);
+            if (st != RR_OK) {
+                std::printf("err %d job %d %s\n", (int)st, bad, why.c_str());
+            } else {
+                bool ok = true;
+                for (const BatchGroup& g : bp.groups) ok = ok && emulate_group(g, bp.table.data());
+                for (int i = 0; i < k; ++i) {
+                    uint8_t* db = (uint8_t*)jobs[(size_t)i].dst;
+                    if (db[sizes[(size_t)i]] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+                    write_file(outs[(size_t)i], db, sizes[(size_t)i]);
+                }
+                std::printf(ok ? "ok groups=%zu jobs=%u bytes=%llu\n" : "err -1 no kernel\n", bp.groups.size(),
+                            bp.njobs, (unsigned long long)bp.bytes);
+            }
+            for (uint8_t* q : bufs) delete[] q;
         } else {
             std::printf("err -1 unknown op %s\n", op.c_str());
         }

@@ -14,6 +14,8 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 EMU_SRC = os.path.join(ROOT, "tests", "emu", "rr_emu.cpp")
 EMU_BIN = os.path.join(ROOT, "tests", "emu", "_build", "rr_emu")
 DEPS = [EMU_SRC,
+        os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_batch.hpp"),
+        os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_batch_plan.cpp"),
         os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_device.hpp"),
         os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_plan.hpp"),
         os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_plan.cpp"),
@@ -27,7 +29,8 @@ def build():
     tmp = EMU_BIN + f".tmp{os.getpid()}"
     cmd = ["g++", "-std=c++17", "-O1", "-g", "-fsanitize=address,undefined",
            "-fno-sanitize-recover=all", "-fno-omit-frame-pointer", "-Wall", "-Wno-unknown-pragmas",
-           "-o", tmp, EMU_SRC, DEPS[3]]
+           "-o", tmp, EMU_SRC, os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_plan.cpp"),
+           os.path.join(ROOT, "paper_1011_3583_amd", "csrc", "rr_batch_plan.cpp")]
     subprocess.run(cmd, check=True)
     os.replace(tmp, EMU_BIN)
     return EMU_BIN
@@ -51,10 +54,17 @@ def run(jobs):
                 nd = len(j["dims"])
                 lines.append(" ".join(["permute", str(nd), *map(str, j["dims"]), *map(str, j["perm"]),
                                        str(j["esize"]), str(j.get("src_off", 0)), str(j.get("dst_off", 0)),
-                                       rb, str(j.get("order", 0)), inf, outf]))
+                                       rb, str(j.get("order", -1)), inf, outf]))
             elif j["op"] == "interlace":
                 np.concatenate(j["planes"]).tofile(inf)
                 lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
+            elif j["op"] == "batched":
+                lines.append(f"batched {len(j['jobs'])} {rb} {j.get('order', -1)}")
+                for k, sub in enumerate(j["jobs"]):
+                    sf, of = os.path.join(td, f"b{i}_{k}"), os.path.join(td, f"bo{i}_{k}")
+                    sub["input"].tofile(sf)
+                    lines.append(" ".join(["job", str(len(sub["dims"])), *map(str, sub["dims"]),
+                                           *map(str, sub["perm"]), str(sub["esize"]), sf, of]))
             else:
                 j["input"].tofile(inf)
                 lines.append(f"deinterlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
@@ -73,6 +83,10 @@ def run(jobs):
             outf = os.path.join(td, f"out{i}")
             if not s.startswith("ok"):
                 out.append((s, None))
+                continue
+            if j["op"] == "batched":
+                out.append((s, [np.fromfile(os.path.join(td, f"bo{i}_{k}"), dtype=np.uint8)
+                                for k in range(len(j["jobs"]))]))
                 continue
             data = np.fromfile(outf, dtype=np.uint8)
             if j["op"] == "deinterlace":

@@ -144,3 +144,55 @@ def test_emu_interlace_large_counts():
         jobs.append(dict(op="deinterlace", n=n, count=count, esize=e,
                          input=rr_synth.random_bytes(9100 + n, n * count * e)))
     _check(jobs)
+
+
+def test_emu_flat_read_and_merged_store_paths():
+    """Aligned interlace workloads whose plans take the flat-read (de-interlace) and the
+    merged 16-byte-store (interlace with G == n) paths."""
+    jobs = []
+    for n, e in [(2, 4), (4, 1), (3, 4), (8, 2), (2, 8), (16, 1), (5, 4)]:
+        count = 3 * 4096 + 48
+        planes = [rr_synth.random_bytes(9300 + 10 * n + c, count * e) for c in range(n)]
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
+        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e,
+                         input=rr_synth.random_bytes(9400 + n, n * count * e)))
+    res = _check(jobs)
+    flags = [int(s.split("flags=")[1].split()[0]) for s, _ in res]
+    assert any(f & 4 for f in flags[1::2]), "no de-interlace plan took the flat read"
+    assert any(f & 8 for f in flags[0::2]), "no interlace plan took the merged store"
+    # permutes whose input tile is one contiguous range of short rows
+    jobs = [_perm_job((4096, 3), (1, 0), 4, 9500), _perm_job((64, 48, 6), (2, 0, 1), 2, 9501),
+            _perm_job((2048, 5, 2), (1, 2, 0), 8, 9502)]
+    _check(jobs)
+
+
+def _batched_jobs(seed, njobs, max_elems=20000):
+    g = rr_synth.rng(seed)
+    jobs = []
+    for i in range(njobs):
+        nd = int(g.integers(1, 6))
+        while True:
+            dims = tuple(int(g.integers(1, 40)) for _ in range(nd))
+            if int(np.prod(dims)) <= max_elems:
+                break
+        perm = tuple(int(v) for v in g.permutation(nd))
+        e = int(g.choice([1, 2, 3, 4, 6, 8, 12, 16]))
+        jobs.append(_perm_job(dims, perm, e, seed * 1000 + i))
+    return jobs
+
+
+@pytest.mark.parametrize("seed,opts", [(1, (0, 0, 0)), (2, (512, 256, 0)), (3, (256, 1024, 1))])
+def test_emu_batched_uneven_jobs(seed, opts):
+    """A batch of uneven jobs of every kernel family: each job equals the oracle alone."""
+    jobs = _batched_jobs(seed, 60)
+    jobs.append(_perm_job((0, 4), (1, 0), 4, 5))           # empty job inside a batch
+    jobs.append(_perm_job((64, 64, 32), (1, 0, 2), 4, 6))  # run-copy family
+    jobs.append(_perm_job((7, 9), (0, 1), 2, 7))           # identity -> copy family
+    rbi, rbo, order = opts
+    res = emu_runner.run([dict(op="batched", jobs=jobs, in_rb=rbi, out_rb=rbo, order=order)])
+    status, outs = res[0]
+    assert status.startswith("ok"), status
+    assert int(status.split("groups=")[1].split()[0]) >= 3
+    for j, out in zip(jobs, outs):
+        assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
+            (j["dims"], j["perm"], j["esize"])

@@ -1,0 +1,161 @@
+"""GPU tests of batched permutes: every job's bytes equal the oracle and equal the
+same job run alone with rr_permute (tolerance 0), for one-shot batches and for
+reusable handles (plain, persistent, autotuned, hipGraph replay)."""
+import sys
+
+import numpy as np
+import pytest
+
+import oracle
+import rr_synth
+
+pytestmark = pytest.mark.gpu
+
+torch = pytest.importorskip("torch")
+
+
+def _say(*a):
+    print("[case]", *a, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def rr():
+    assert torch.cuda.is_available()
+    import paper_1011_3583_amd as rr
+    rr.set_tile_override(0, 0, None)
+    return rr
+
+
+def _uneven(seed, njobs, max_elems):
+    g = rr_synth.rng(seed)
+    out = []
+    for _ in range(njobs):
+        nd = int(g.integers(1, 6))
+        while True:
+            dims = tuple(int(g.integers(1, 48)) for _ in range(nd))
+            if int(np.prod(dims)) <= max_elems:
+                break
+        out.append({"dims": dims, "perm": tuple(int(v) for v in g.permutation(nd)),
+                    "esize": int(g.choice([1, 2, 3, 4, 6, 8, 12, 16]))})
+    return out
+
+
+class Jobs:
+    """Device buffers for a list of job specs, inputs uploaded from seeded host bytes."""
+
+    def __init__(self, rr, specs, seed):
+        self.specs = specs
+        self.host = [rr_synth.random_bytes(seed * 100_003 + i, int(np.prod(s["dims"])) * s["esize"])
+                     for i, s in enumerate(specs)]
+        sizes = [h.size for h in self.host]
+        offs = np.concatenate([[0], np.cumsum([(n + 255) // 256 * 256 for n in sizes])]).astype(np.int64)
+        self.src = torch.zeros(int(offs[-1]) + 256, dtype=torch.uint8, device="cuda")
+        self.dst = torch.zeros(int(offs[-1]) + 256, dtype=torch.uint8, device="cuda")
+        for i, h in enumerate(self.host):
+            if h.size:
+                self.src[offs[i]:offs[i] + h.size].copy_(torch.from_numpy(h))
+        self.offs, self.sizes = offs, sizes
+        self.arr = rr.make_jobs([(self.dst.data_ptr() + int(offs[i]), self.src.data_ptr() + int(offs[i]),
+                                  s["dims"], s["perm"], s["esize"]) for i, s in enumerate(specs)])
+
+    def out(self, i):
+        return self.dst[self.offs[i]:self.offs[i] + self.sizes[i]].cpu().numpy()
+
+    def outs_device(self):
+        return self.dst.clone()
+
+
+def _check_all_vs_oracle(J, sample=None):
+    for i, s in enumerate(J.specs):
+        got = J.out(i)
+        n = int(np.prod(s["dims"]))
+        if sample is None or n <= sample:
+            ref = oracle.permute(J.host[i], s["dims"], s["perm"], s["esize"])
+            assert np.array_equal(got, ref), (i, s)
+        else:
+            g = rr_synth.rng(i)
+            idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, sample)])).astype(np.int64)
+            ref = oracle.permute_at(J.host[i], s["dims"], s["perm"], s["esize"], idx)
+            assert np.array_equal(got.reshape(n, s["esize"])[idx], ref), (i, s)
+
+
+def test_batched_uneven_jobs_match_oracle_and_alone(rr):
+    specs = _uneven(1, 300, 30000)
+    specs += [{"dims": (0, 4), "perm": (1, 0), "esize": 4}, {"dims": (64, 64, 32), "perm": (1, 0, 2), "esize": 4},
+              {"dims": (7, 9), "perm": (0, 1), "esize": 2}, {"dims": (512, 512), "perm": (1, 0), "esize": 1}]
+    J = Jobs(rr, specs, 1)
+    _say("batched one-shot", len(specs))
+    rr.check(rr.permute_batched_raw(J.arr, len(specs), torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    _check_all_vs_oracle(J)
+    batched = J.outs_device()
+    # each job alone must give the same bytes
+    J.dst.zero_()
+    for i in range(len(specs)):
+        j = J.arr[i]
+        s = specs[i]
+        rr.check(rr.permute_raw(j.dst, j.src, s["dims"], s["perm"], s["esize"],
+                                torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    assert torch.equal(J.dst, batched)
+
+
+def test_batched_repeated_calls_reuse_staging(rr):
+    """More calls in flight than staging slots: every result still right."""
+    specs = _uneven(2, 40, 5000)
+    Js = [Jobs(rr, specs, 10 + k) for k in range(7)]
+    for k, J in enumerate(Js):
+        _say("staging round", k)
+        rr.check(rr.permute_batched_raw(J.arr, len(specs), torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    for J in Js:
+        _check_all_vs_oracle(J)
+
+
+@pytest.mark.parametrize("flags", [0, 4, 2, 1, 1 | 4, 1 | 2])
+def test_batch_handle_modes(rr, flags):
+    specs = _uneven(3, 120, 20000)
+    J = Jobs(rr, specs, 3)
+    _say("batch handle flags", flags)
+    b = rr.Batch(J.arr, flags)
+    info = b.info()
+    assert info["ngroups"] >= 2 and info["njobs"] == len(specs)
+    if flags & 2:
+        assert info["tuned_us"] > 0
+    expected = None
+    for rep in range(3):
+        J.dst.zero_()                              # eager work between replays
+        torch.cuda.synchronize()
+        b.launch(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+        if expected is None:
+            _check_all_vs_oracle(J)
+            expected = J.outs_device()
+        else:
+            assert torch.equal(J.dst, expected), f"replay {rep} differs"
+    b.close()
+
+
+def test_sampled_uneven_workload(rr):
+    """4096 uneven jobs drawn like the batched workload (sizes capped for test time)."""
+    specs = rr_synth.sample_jobs(4, njobs=4096, total_range=(1e3, 2e5), footprint_cap=4 << 30)
+    J = Jobs(rr, specs, 4)
+    _say("sampled workload", len(specs))
+    rr.check(rr.permute_batched_raw(J.arr, len(specs), torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    _check_all_vs_oracle(J, sample=64)
+
+
+def test_overlapping_jobs_rejected(rr):
+    x = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
+    base = x.data_ptr()
+    arr = rr.make_jobs([(base, base + 8192, (32, 32), (1, 0), 4),
+                        (base + 4096, base + 16384, (32, 32), (1, 0), 4)])
+    assert rr.permute_batched_raw(arr, 2, 0) == 3
+    assert "overlap" in rr.last_error()
+    # job 1 reads [2048, 6144), which overlaps job 0's output [0, 4096)
+    arr = rr.make_jobs([(base, base + 8192, (32, 32), (1, 0), 4),
+                        (base + 20000, base + 2048, (32, 32), (1, 0), 4)])
+    assert rr.permute_batched_raw(arr, 2, 0) == 3
+    assert not x.any()  # nothing was launched

@@ -28,7 +28,7 @@ def _say(*a):
 def rr():
     assert torch.cuda.is_available()
     import paper_1011_3583_amd as rr
-    rr.set_tile_override(0, 0, False)
+    rr.set_tile_override(0, 0, None)
     return rr
 
 

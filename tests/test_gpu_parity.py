@@ -29,7 +29,7 @@ def rr():
     assert torch.cuda.is_available(), "GPU tests need cuda:0"
     import paper_1011_3583_amd as rr
     rr.lib()
-    rr.set_tile_override(0, 0, False)
+    rr.set_tile_override(0, 0, None)
     return rr
 
 
@@ -127,7 +127,7 @@ def test_tile_overrides(rr):
                     k += 1
                     check_permute(rr, dims, perm, e, 5000 + k)
     finally:
-        rr.set_tile_override(0, 0, False)
+        rr.set_tile_override(0, 0, None)
 
 
 def test_size_zero_and_one(rr):
@@ -208,3 +208,19 @@ def test_paper_table3_interlace_counts(rr):
         assert np.array_equal(joined, oracle.interlace(planes, 4))
         back = gpu_deinterlace(rr, joined, n, 4)
         assert all(np.array_equal(b, p) for b, p in zip(back, planes))
+
+
+def test_flat_read_and_merged_store_paths(rr):
+    """Aligned interlace shapes that take the flat-read and merged-store paths."""
+    for n, e in [(2, 4), (4, 1), (3, 4), (8, 2), (2, 8), (16, 1), (5, 4)]:
+        count = 3 * 4096 + 48
+        _say("flat/merge", n, e)
+        planes = [rr_synth.random_bytes(9300 + 10 * n + c, count * e) for c in range(n)]
+        assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e))
+        x = rr_synth.random_bytes(9400 + n, n * count * e)
+        got = gpu_deinterlace(rr, x, n, e)
+        ref = oracle.deinterlace(x, n, e)
+        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (n, e)
+    for i, (dims, perm, e) in enumerate([((4096, 3), (1, 0), 4), ((64, 48, 6), (2, 0, 1), 2),
+                                         ((2048, 5, 2), (1, 2, 0), 8)]):
+        check_permute(rr, dims, perm, e, 9500 + i)
