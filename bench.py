@@ -37,7 +37,13 @@ def parse():
     ap.add_argument("--steps", type=int, default=5)
     ap.add_argument("--warmup", type=int, default=1)
     ap.add_argument("--no-cpu", action="store_true", help="skip the oracle CPU baseline")
+    ap.add_argument("--no-tune", action="store_true", help="time the built-in tile shapes only")
+    ap.add_argument("--tune-cache", default=None,
+                    help="load tuned tile shapes from this file if it exists (no tuning launches), "
+                         "else tune and save them there")
     ap.add_argument("--no-side", action="store_true", help="skip interlace/batched/serve side runs")
+    ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop side run")
+    ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per arrival rate")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps and exit (for rocprofv3 runs)")
     return ap.parse_args()
@@ -109,6 +115,30 @@ def main():
             if events is not None:
                 events[i][1].record(stream)
 
+    # untuned pass (built-in tile shapes), for reference
+    untuned_ms = None
+    cached = bool(args.tune_cache) and os.path.exists(args.tune_cache) and not args.no_tune
+    if cached:
+        rr.tune_load(args.tune_cache)
+        plans[:] = [(plans[i][0], kernel_name(rr.plan_describe(c[1], c[2], c[3], out.data_ptr(), plans[i][0])))
+                    for i, c in enumerate(cases)]
+    elif not args.no_tune:
+        rr.tune_clear()
+        step()
+        torch.cuda.synchronize()
+        a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+        a.record(stream)
+        step()
+        b.record(stream)
+        b.synchronize()
+        untuned_ms = a.elapsed_time(b)
+        # autotune every case once (runs each candidate tile shape; cached for the timed steps)
+        for i, (name, dims, perm, e, nb) in enumerate(cases):
+            rr.tune_permute(out.data_ptr(), plans[i][0], dims, perm, e, sh)
+        plans[:] = [(plans[i][0], kernel_name(rr.plan_describe(c[1], c[2], c[3], out.data_ptr(), plans[i][0])))
+                    for i, c in enumerate(cases)]
+        if args.tune_cache:
+            rr.tune_save(args.tune_cache)
     for _ in range(args.warmup):
         step()
     torch.cuda.synchronize()
@@ -205,6 +235,8 @@ def main():
         "pct_of_d2d_memcpy": round(100 * value / d2d, 1),
         "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
         "kernel_only_GBps": round(bytes_per_step / (kernel_time_ms * 1e-3) / 1e9, 1),
+        "autotuned": not args.no_tune,
+        "untuned_step_GBps": round(bytes_per_step / (untuned_ms * 1e-3) / 1e9, 1) if untuned_ms else None,
         "ceilings_GBps": {"d2d_hipMemcpyAsync_1GiB": round(d2d, 1), "rr_copy_1GiB": round(rrcopy, 1),
                           "hbm_peak": HBM_PEAK_GBPS},
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
@@ -218,21 +250,24 @@ def main():
         "detail_GBps": detail,
         "kernel_source": kernel_source_hash(),
     }
-    del flush
-
     if not args.no_side:
         side = {}
         try:
             side["interlace"] = bench_interlace(rr, rr_synth, pool, out, stream, timed)
         except Exception as ex:  # side measurements never hide the main line
             side["interlace"] = {"error": str(ex)}
+        del pool, out, flush
+        torch.cuda.empty_cache()
         try:
-            import bench_side
-            side.update(bench_side.run(rr, rr_synth, torch, stream, timed))
-        except ImportError:
-            pass
+            side["batched"] = bench_batched(rr, rr_synth, torch, stream)
         except Exception as ex:
-            side["side_error"] = str(ex)
+            side["batched"] = {"error": repr(ex)}
+        torch.cuda.empty_cache()
+        if not args.no_serve:
+            try:
+                side["serve"] = bench_serve(rr, rr_synth, torch, args.serve_requests)
+            except Exception as ex:
+                side["serve"] = {"error": repr(ex)}
         result["side"] = side
 
     if not args.no_cpu:
@@ -250,6 +285,162 @@ def bench_interlace(rr, rr_synth, pool, out, stream, timed):
         t2 = timed(lambda: rr.check(rr.deinterlace_raw(planes, out.data_ptr(), count, e, stream.cuda_stream)), 5)
         res[name] = {"interlace_GBps": round(2 * n * pb / t1 / 1e9, 1),
                      "deinterlace_GBps": round(2 * n * pb / t2 / 1e9, 1)}
+    return res
+
+
+def _job_buffers(torch, specs, dev="cuda"):
+    """One source and one destination allocation holding every job at 256-byte offsets."""
+    sizes = [int(__import__("numpy").prod(s["dims"])) * s["esize"] for s in specs]
+    offs, acc = [], 0
+    for n in sizes:
+        offs.append(acc)
+        acc += (n + 255) // 256 * 256
+    src = torch.empty(acc + 256, dtype=torch.uint8, device=dev)
+    dst = torch.empty(acc + 256, dtype=torch.uint8, device=dev)
+    for i in range(0, src.numel(), 1 << 30):
+        src[i:i + (1 << 30)].random_(0, 256)
+    return src, dst, offs, sizes
+
+
+def bench_batched(rr, rr_synth, torch, stream):
+    """4096 uneven permutes: one rr_permute per job vs one batched call vs a reusable,
+    autotuned handle replayed through a hipGraph (wall clock, median of runs)."""
+    specs = rr_synth.sample_jobs(4096_0001, njobs=4096)
+    src, dst, offs, sizes = _job_buffers(torch, specs)
+    sh = stream.cuda_stream
+    jobs = rr.make_jobs([(dst.data_ptr() + o, src.data_ptr() + o, s["dims"], s["perm"], s["esize"])
+                         for o, s in zip(offs, specs)])
+    total = sum(sizes)
+
+    def wall(fn, reps=5):
+        ts = []
+        for _ in range(reps + 1):
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            fn()
+            torch.cuda.synchronize()
+            ts.append(time.perf_counter() - t0)
+        ts = sorted(ts[1:])
+        return ts[len(ts) // 2]
+
+    def per_job():
+        for i, s in enumerate(specs):
+            rr.check(rr.permute_raw(jobs[i].dst, jobs[i].src, s["dims"], s["perm"], s["esize"], sh))
+
+    t_per = wall(per_job, 3)
+    t_oneshot = wall(lambda: rr.check(rr.permute_batched_raw(jobs, len(specs), sh)))
+    plain = rr.Batch(jobs, 0)
+    t_plain = wall(lambda: plain.launch(stream))
+    tuned = rr.Batch(jobs, rr.RR_BATCH_TUNE | rr.RR_BATCH_GRAPH)
+    t_tuned = wall(lambda: tuned.launch(stream))
+    info = tuned.info()
+    plain.close()
+    tuned.close()
+    gbps = lambda t: round(2 * total / t / 1e9, 1)
+    return {
+        "jobs": len(specs), "bytes_per_side": total, "groups": info["ngroups"],
+        "per_job_rr_permute_GBps": gbps(t_per), "per_job_ms": round(t_per * 1e3, 2),
+        "batched_call_GBps": gbps(t_oneshot), "batched_call_ms": round(t_oneshot * 1e3, 2),
+        "batch_handle_GBps": gbps(t_plain),
+        "batch_handle_tuned_graph_GBps": gbps(t_tuned), "batch_handle_tuned_graph_ms": round(t_tuned * 1e3, 2),
+        "tuned_choice": {k: info[k] for k in ("in_row_bytes", "out_row_bytes", "order_out", "persistent")},
+        "speedup_batched_call_vs_per_job": round(t_per / t_oneshot, 2),
+        "speedup_tuned_graph_vs_per_job": round(t_per / t_tuned, 2),
+        "sizes_elems_min_median_max": [int(x) for x in __import__("numpy").percentile(
+            [s // e["esize"] for s, e in zip(sizes, specs)], [0, 50, 100])],
+    }
+
+
+def _serve_run(rr, rr_synth, torch, rate, nreq, direct, small_specs, large_specs):
+    """Open-loop Poisson arrivals; latency from the scheduled arrival to completion."""
+    import numpy as np
+    budget = 96 << 30
+    srv = rr.Server(budget, max_inflight=4, max_batch_jobs=1024, chunk_bytes=64 << 20, tick_us=5,
+                    direct=direct, queue_capacity=1 << 20)
+    try:
+        # resident inputs in the server's budget
+        def resident(specs, seed):
+            ptrs = []
+            for s in specs:
+                n = int(np.prod(s["dims"])) * s["esize"]
+                p = srv.alloc(n)
+                ptrs.append(p)
+            return ptrs
+        sp = resident(small_specs, 1)
+        lp = resident(large_specs, 2)
+        small_jobs = rr.make_jobs([(0, p, s["dims"], s["perm"], s["esize"]) for p, s in zip(sp, small_specs)])
+        large_jobs = rr.make_jobs([(0, p, s["dims"], s["perm"], s["esize"]) for p, s in zip(lp, large_specs)])
+        g = rr_synth.rng(int(rate))
+        arrivals = rr_synth.poisson_arrivals(int(rate) + 7, rate, nreq)
+        is_large = g.random(nreq) < 0.01
+        pick_s = g.integers(0, len(small_specs), nreq)
+        pick_l = g.integers(0, len(large_specs), nreq)
+        nbytes_small = [int(np.prod(s["dims"])) * s["esize"] for s in small_specs]
+        nbytes_large = [int(np.prod(s["dims"])) * s["esize"] for s in large_specs]
+        sched = np.empty(nreq, dtype=np.int64)
+        lat = {}
+        tick_of = {}
+        lib = rr.lib()
+        import ctypes
+        tk = ctypes.c_uint64()
+        busy = 0
+        t0 = time.monotonic_ns() + 2_000_000
+        for i in range(nreq):
+            ts = t0 + int(arrivals[i] * 1e9)
+            sched[i] = ts
+            while time.monotonic_ns() < ts:
+                pass
+            job = large_jobs[pick_l[i]] if is_large[i] else small_jobs[pick_s[i]]
+            while True:
+                st = lib.rr_serve_submit(srv.h, ctypes.byref(job), ctypes.byref(tk))
+                if st != 6:
+                    break
+                busy += 1
+                _drain(srv, lat, tick_of)
+            rr.check(st)
+            tick_of[tk.value] = i
+            if i % 64 == 0:
+                _drain(srv, lat, tick_of)
+        while len(lat) < nreq:
+            _drain(srv, lat, tick_of)
+            time.sleep(0.0002)
+        t_end = max(v[1] for v in lat.values())
+        stats = srv.stats()
+    finally:
+        srv.close()
+    lat_us = np.array([(lat[i][1] - sched[i]) / 1e3 for i in range(nreq)])
+    small_mask = ~is_large
+    moved = sum(nbytes_large[pick_l[i]] if is_large[i] else nbytes_small[pick_s[i]] for i in range(nreq))
+    span = (t_end - sched[0]) / 1e9
+    pct = lambda a, q: round(float(np.percentile(a, q)), 1)
+    return {"p50_us": pct(lat_us, 50), "p99_us": pct(lat_us, 99), "p999_us": pct(lat_us, 99.9),
+            "small_p50_us": pct(lat_us[small_mask], 50), "small_p99_us": pct(lat_us[small_mask], 99),
+            "large_p50_us": pct(lat_us[is_large], 50) if is_large.any() else None,
+            "aggregate_GBps": round(2 * moved / span / 1e9, 1), "offered_GBps": round(2 * moved / (arrivals[-1]) / 1e9, 1),
+            "requests": nreq, "large_requests": int(is_large.sum()), "batches": stats["batches"],
+            "budget_peak_GiB": round(stats["budget_peak"] / 2**30, 2), "busy_retries": busy}
+
+
+def _drain(srv, lat, tick_of):
+    for t in srv.completions():
+        r = srv.poll(t)
+        if r.status != 0:
+            raise RuntimeError(f"served job failed with status {r.status}")
+        lat[tick_of.pop(t)] = (r.t_submit_ns, r.t_done_ns)
+        srv.release(t)
+
+
+def bench_serve(rr, rr_synth, torch, nreq):
+    """Config: Poisson arrivals of batched-workload jobs plus 1% large 1-4 GiB transposes,
+    served by the continuous-batching server vs one rr_permute launch per request."""
+    small_specs = rr_synth.sample_jobs(5_0001, njobs=4096)
+    large_specs = rr_synth.large_jobs(5_0002, count=4)
+    res = {"large_job_shapes": [(s["dims"], s["perm"], s["esize"]) for s in large_specs]}
+    for rate in (5_000, 20_000, 50_000):
+        res[f"{rate}_per_s"] = {
+            "batched": _serve_run(rr, rr_synth, torch, rate, nreq, False, small_specs, large_specs),
+            "per_request": _serve_run(rr, rr_synth, torch, rate, nreq, True, small_specs, large_specs),
+        }
     return res
 
 

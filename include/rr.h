@@ -155,33 +155,45 @@ rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out);
 rr_status rr_batch_destroy(rr_batch* b);
 
 /* -------------------------------------------------------------------------
- * Serving: a background thread that owns a HIP stream and an HBM budget,
+ * Serving: a background thread that owns HIP streams and an HBM budget. It
  * admits submitted permute jobs as budget and in-flight slots free up, and
- * batches whatever has arrived into one batched launch while earlier batches
- * are still running (continuous batching).  Large jobs are cut into chunks of
- * at most chunk_bytes of output so small jobs interleave with them.
+ * keeps forming batches from whatever has arrived while earlier batches are
+ * still running (continuous batching); consecutive batches go to different
+ * streams so their work overlaps on the device.  A job whose launch would need
+ * more than chunk_bytes of output is cut into ranges of its own workgroups
+ * (each range rewrites a disjoint part of the output), at most one range per
+ * batch, so small jobs keep flowing past it.  Results are identical to
+ * rr_permute run alone.
  */
 typedef struct rr_server rr_server;
+
+#define RR_SERVE_SIMULATED 1u  /* no GPU: memory is virtual, a batch "completes"
+                                  after bytes / sim_bytes_per_us microseconds;
+                                  exercises admission and batching on a host. */
+#define RR_SERVE_DIRECT 2u     /* baseline: every job is launched alone, in arrival
+                                  order, exactly as rr_permute launches it (no
+                                  batching, no chunking). */
 
 typedef struct {
     int32_t device;             /* HIP device ordinal                               */
     int32_t max_inflight;       /* batches on the GPU at once (>= 1)                 */
-    int32_t max_batch_jobs;     /* jobs per batch (>= 1)                             */
+    int32_t max_batch_jobs;     /* whole jobs or chunks per batch (>= 1)             */
     int32_t queue_capacity;     /* pending submissions before RR_ERR_BUSY            */
     uint64_t hbm_budget_bytes;  /* cap on server-allocated device memory             */
-    uint64_t chunk_bytes;       /* large jobs split into pieces of <= this (0 = off) */
-    uint32_t tick_us;           /* idle wait of the server thread                    */
-    uint32_t reserved;
+    uint64_t chunk_bytes;       /* output bytes per chunk of a large job (0 = never) */
+    uint32_t tick_us;           /* longest idle wait of the server thread            */
+    uint32_t flags;             /* RR_SERVE_SIMULATED                                */
+    double sim_bytes_per_us;    /* simulated read+write bandwidth (simulated mode)   */
 } rr_serve_config;
 
 typedef struct {
     int32_t status;          /* rr_status of the job                                 */
-    int32_t reserved;
+    int32_t chunks;          /* batches the job was spread over                      */
     void* dst;               /* output buffer (server-allocated when job.dst == NULL) */
-    uint64_t t_submit_ns;    /* host steady-clock timestamps                          */
+    uint64_t t_submit_ns;    /* steady-clock (CLOCK_MONOTONIC) timestamps             */
     uint64_t t_admit_ns;
-    uint64_t t_launch_ns;
-    uint64_t t_done_ns;
+    uint64_t t_launch_ns;    /* first batch holding the job was launched             */
+    uint64_t t_done_ns;      /* server thread saw the job's last batch complete      */
 } rr_job_result;
 
 /* Create a server; *out receives the handle.  Errors: RR_ERR_INVALID_ARG, RR_ERR_HIP. */
@@ -197,15 +209,23 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket);
 /* RR_ERR_NOT_READY while pending; otherwise fills *out and returns RR_OK (the
  * job's own status is out->status). */
 rr_status rr_serve_poll(rr_server* s, uint64_t ticket, rr_job_result* out);
-/* Forget a completed ticket and free its server-allocated output. */
+/* Completion queue: tickets finished since the previous call, oldest first;
+ * up to max are written to out, *n receives the count. */
+rr_status rr_serve_completions(rr_server* s, uint64_t* out, int max, int* n);
+/* Forget a completed ticket and free its server-allocated output
+ * (RR_ERR_NOT_READY if it is still pending). */
 rr_status rr_serve_release(rr_server* s, uint64_t ticket);
 /* Drain every admitted and queued job, stop the thread, free the server. */
 rr_status rr_serve_destroy(rr_server* s);
-/* Counters: submitted, completed, batches launched, bytes moved, peak budget use. */
+/* Counters since creation. */
 typedef struct {
     uint64_t submitted, completed, failed, batches, chunks, bytes_moved, budget_peak, budget_used;
 } rr_serve_stats;
 rr_status rr_serve_get_stats(rr_server* s, rr_serve_stats* out);
+/* Failure-handling hook: the next batch the server forms is not launched and
+ * its jobs complete with RR_ERR_HIP, as if the launch had failed; the server
+ * keeps serving.  For the tests of that path. */
+rr_status rr_serve_fail_next_batch(rr_server* s);
 
 /* -------------------------------------------------------------------------
  * Paper notation (Sec. III.B): an order vector lists dimensions fastest first
@@ -233,6 +253,24 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
+
+/* -------------------------------------------------------------------------
+ * Autotuner for single permutes: runs the problem (writing dst, so the buffers
+ * must be valid) once per candidate tile shape and traversal order on `stream`,
+ * times each with HIP events, and caches the fastest for the problem's
+ * canonical form and pointer-alignment class.  Every later plan with the same
+ * key (rr_permute, rr_permute_batched, batch handles, the server) uses it,
+ * unless rr_set_tile_override is active.  Problems that plan to a copy or run
+ * copy have nothing to tune and return at once.
+ *   best_us, default_us (either may be NULL): best and built-in-choice times.
+ * Errors: as rr_permute; RR_ERR_HIP if timing fails.
+ */
+rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* dims, const int* perm,
+                          int elem_size, rr_stream_t stream, double* best_us, double* default_us);
+/* Persist / restore / forget the tuning cache (one text line per key). */
+rr_status rr_tune_save(const char* path);
+rr_status rr_tune_load(const char* path);
+rr_status rr_tune_clear(void);
 
 const char* rr_status_string(rr_status s);
 /* Detail of the last error on the calling thread ("" if none). */

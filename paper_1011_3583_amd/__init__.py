@@ -22,13 +22,16 @@ RR_MAX_PLANES = 16
 STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_ALIAS",
           4: "RR_ERR_UNSUPPORTED", 5: "RR_ERR_NO_MEMORY", 6: "RR_ERR_BUSY",
           7: "RR_ERR_NOT_READY", 8: "RR_ERR_HIP"}
+STATUS_CODE = {v: k for k, v in STATUS.items()}
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
 EXPORTS = ("rr_permute", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
            "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
-           "rr_serve_poll", "rr_serve_release", "rr_serve_destroy", "rr_serve_get_stats",
+           "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
+           "rr_serve_get_stats", "rr_serve_fail_next_batch",
            "rr_order_to_perm", "rr_plan_describe", "rr_set_tile_override",
+           "rr_tune_permute", "rr_tune_save", "rr_tune_load", "rr_tune_clear",
            "rr_status_string", "rr_last_error", "rr_version")
 
 
@@ -48,11 +51,15 @@ class ServeConfig(ctypes.Structure):
     _fields_ = [("device", ctypes.c_int32), ("max_inflight", ctypes.c_int32),
                 ("max_batch_jobs", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64),
-                ("tick_us", ctypes.c_uint32), ("reserved", ctypes.c_uint32)]
+                ("tick_us", ctypes.c_uint32), ("flags", ctypes.c_uint32),
+                ("sim_bytes_per_us", ctypes.c_double)]
+
+
+RR_SERVE_SIMULATED, RR_SERVE_DIRECT = 1, 2
 
 
 class JobResult(ctypes.Structure):
-    _fields_ = [("status", ctypes.c_int32), ("reserved", ctypes.c_int32), ("dst", ctypes.c_void_p),
+    _fields_ = [("status", ctypes.c_int32), ("chunks", ctypes.c_int32), ("dst", ctypes.c_void_p),
                 ("t_submit_ns", ctypes.c_uint64), ("t_admit_ns", ctypes.c_uint64),
                 ("t_launch_ns", ctypes.c_uint64), ("t_done_ns", ctypes.c_uint64)]
 
@@ -98,11 +105,17 @@ def lib() -> ctypes.CDLL:
     L.rr_serve_submit.argtypes = [vp, ctypes.POINTER(Job), ctypes.POINTER(ctypes.c_uint64)]
     L.rr_serve_poll.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(JobResult)]
     L.rr_serve_release.argtypes = [vp, ctypes.c_uint64]
+    L.rr_serve_completions.argtypes = [vp, ctypes.POINTER(ctypes.c_uint64), i32, ctypes.POINTER(ctypes.c_int)]
+    L.rr_serve_fail_next_batch.argtypes = [vp]
     L.rr_serve_destroy.argtypes = [vp]
     L.rr_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.rr_order_to_perm.argtypes = [i32, i32p, i32p]
     L.rr_plan_describe.argtypes = [vp, vp, i32, i64p, i32p, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
+    L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
+                                  ctypes.POINTER(ctypes.c_double)]
+    L.rr_tune_save.argtypes = [ctypes.c_char_p]
+    L.rr_tune_load.argtypes = [ctypes.c_char_p]
     L.rr_status_string.argtypes = [i32]
     L.rr_status_string.restype = ctypes.c_char_p
     L.rr_last_error.restype = ctypes.c_char_p
@@ -240,6 +253,26 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))
 
 
+def tune_permute(dst: int, src: int, dims, perm, elem_size: int, stream=None):
+    """Autotune one permute problem (runs it); returns (best_us, default_us)."""
+    b, d = ctypes.c_double(), ctypes.c_double()
+    check(lib().rr_tune_permute(dst, src, len(dims), _i64(dims), _i32(perm), int(elem_size),
+                                _stream_handle(stream), ctypes.byref(b), ctypes.byref(d)))
+    return b.value, d.value
+
+
+def tune_save(path: str):
+    check(lib().rr_tune_save(path.encode()))
+
+
+def tune_load(path: str):
+    check(lib().rr_tune_load(path.encode()))
+
+
+def tune_clear():
+    check(lib().rr_tune_clear())
+
+
 # ----------------------------------------------------------------- torch helpers
 def permute(src, perm, out=None, stream=None):
     """Permute a contiguous CUDA tensor (elements copied as opaque bytes)."""
@@ -280,12 +313,15 @@ class Server:
 
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_batch_jobs: int = 1024,
                  queue_capacity: int = 1 << 16, chunk_bytes: int = 64 << 20, tick_us: int = 20,
-                 device: int = 0):
+                 device: int = 0, simulated: bool = False, sim_bytes_per_us: float = 0.0,
+                 direct: bool = False):
+        flags = (RR_SERVE_SIMULATED if simulated else 0) | (RR_SERVE_DIRECT if direct else 0)
         cfg = ServeConfig(device, max_inflight, max_batch_jobs, queue_capacity, hbm_budget_bytes,
-                          chunk_bytes, tick_us, 0)
+                          chunk_bytes, tick_us, flags, float(sim_bytes_per_us))
         h = ctypes.c_void_p()
         check(lib().rr_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h
+        self._cq = (ctypes.c_uint64 * 4096)()
 
     def alloc(self, nbytes: int) -> int:
         p = ctypes.c_void_p()
@@ -316,6 +352,19 @@ class Server:
 
     def release(self, ticket: int):
         check(lib().rr_serve_release(self.h, int(ticket)))
+
+    def completions(self) -> list:
+        """Tickets completed since the last call (oldest first)."""
+        out = []
+        n = ctypes.c_int()
+        while True:
+            check(lib().rr_serve_completions(self.h, self._cq, len(self._cq), ctypes.byref(n)))
+            out.extend(self._cq[:n.value])
+            if n.value < len(self._cq):
+                return out
+
+    def fail_next_batch(self):
+        check(lib().rr_serve_fail_next_batch(self.h))
 
     def stats(self) -> dict:
         s = ServeStats()

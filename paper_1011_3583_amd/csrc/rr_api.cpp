@@ -1,9 +1,11 @@
 // rr_api.cpp -- the extern "C" entry points of librr (see include/rr.h).
 #include <hip/hip_runtime_api.h>
 
+#include <algorithm>
 #include <cstdio>
 #include <cstring>
 #include <string>
+#include <vector>
 
 #include "rr_internal.hpp"
 #include "rr_kernels.hpp"
@@ -148,6 +150,97 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
+    return RR_OK;
+}
+
+rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* dims, const int* perm,
+                          int elem_size, rr_stream_t stream, double* best_us, double* default_us) {
+    clear_error();
+    Canon c;
+    rr_status st = validate_permute(dst, src, ndim, dims, perm, elem_size, &c);
+    if (st != RR_OK) return st;
+    if (best_us) *best_us = 0;
+    if (default_us) *default_us = 0;
+    if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
+    struct Cand { int in_rb, out_rb, order; };
+    static const Cand cands[] = {{0, 0, -1}, {0, 0, 1}, {0, 0, 0}, {128, 256, -1}, {256, 128, -1},
+                                 {256, 512, -1}, {512, 256, -1}, {512, 512, -1}, {1024, 256, -1},
+                                 {256, 1024, -1}, {1024, 1024, -1}, {2048, 512, -1}, {512, 2048, -1},
+                                 {256, 512, 1}, {512, 256, 1}, {256, 128, 1}, {128, 512, 0}};
+    hipStream_t hs = (hipStream_t)stream;
+    hipEvent_t e0, e1;
+    if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
+    if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(RR_ERR_HIP, "hipEventCreate"); }
+    double best = 1e300, def = 0;
+    TileOptions bestopt;
+    std::vector<std::string> seen;
+    for (const Cand& cd : cands) {
+        TileOptions o;
+        o.in_row_bytes = cd.in_rb;
+        o.out_row_bytes = cd.out_rb;
+        o.order_out = cd.order;
+        Plan p;
+        std::string why;
+        if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;
+        // skip candidates that plan to a launch already timed
+        std::string sig = describe(p);
+        sig += " o" + std::to_string(cd.order < 0 ? (p.tile.unit >= 4 ? 1 : 0) : cd.order);
+        if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
+        seen.push_back(sig);
+        std::vector<float> ts;
+        for (int r = 0; r < 4 && st == RR_OK; ++r) {
+            (void)hipEventRecord(e0, hs);
+            hipError_t e = launch_plan(p, hs);
+            (void)hipEventRecord(e1, hs);
+            if (e != hipSuccess) { st = hip_fail(e, "tuning launch"); break; }
+            if ((e = hipEventSynchronize(e1)) != hipSuccess) { st = hip_fail(e, "tuning sync"); break; }
+            float ms = 0;
+            (void)hipEventElapsedTime(&ms, e0, e1);
+            if (r > 0) ts.push_back(ms);
+        }
+        if (st != RR_OK) break;
+        std::sort(ts.begin(), ts.end());
+        const double us = ts[ts.size() / 2] * 1e3;
+        if (cd.in_rb == 0 && cd.out_rb == 0 && cd.order == -1) def = us;
+        if (us < best) { best = us; bestopt = o; }
+    }
+    (void)hipEventDestroy(e0);
+    (void)hipEventDestroy(e1);
+    if (st != RR_OK) return st;
+    tune_store(tune_key(c, (uint64_t)dst, (uint64_t)src), bestopt);
+    if (best_us) *best_us = best;
+    if (default_us) *default_us = def;
+    return RR_OK;
+}
+
+rr_status rr_tune_save(const char* path) {
+    clear_error();
+    if (!path) return fail(RR_ERR_INVALID_ARG, "NULL path");
+    FILE* f = std::fopen(path, "w");
+    if (!f) return fail(RR_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    const std::string s = tune_dump();
+    std::fwrite(s.data(), 1, s.size(), f);
+    std::fclose(f);
+    return RR_OK;
+}
+
+rr_status rr_tune_load(const char* path) {
+    clear_error();
+    if (!path) return fail(RR_ERR_INVALID_ARG, "NULL path");
+    FILE* f = std::fopen(path, "r");
+    if (!f) return fail(RR_ERR_INVALID_ARG, std::string("cannot read ") + path);
+    std::string s;
+    char buf[4096];
+    size_t n;
+    while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
+    std::fclose(f);
+    if (tune_parse(s) < 0) return fail(RR_ERR_INVALID_ARG, "malformed tuning file");
+    return RR_OK;
+}
+
+rr_status rr_tune_clear(void) {
+    clear_error();
+    tune_clear();
     return RR_OK;
 }
 

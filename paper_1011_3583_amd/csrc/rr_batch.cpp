@@ -52,14 +52,6 @@ uint32_t group_grid(const BatchGroup& g, bool persistent, int device) {
     return std::min<uint32_t>(g.total_blocks, (uint32_t)cu_count(device) * per_cu);
 }
 
-rr_status launch_groups(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
-                        hipStream_t st) {
-    for (const BatchGroup& g : p.groups) {
-        hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), st);
-        if (e != hipSuccess) return hip_fail(e, "batched launch");
-    }
-    return RR_OK;
-}
 
 rr_status plan_or_fail(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* bp) {
     std::string why;
@@ -73,6 +65,15 @@ rr_status plan_or_fail(const rr_job* jobs, int njobs, const TileOptions& opt, Ba
 }
 
 }  // namespace
+
+rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
+                            hipStream_t st) {
+    for (const BatchGroup& g : p.groups) {
+        hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), st);
+        if (e != hipSuccess) return hip_fail(e, "batched launch");
+    }
+    return RR_OK;
+}
 
 }  // namespace rr
 
@@ -128,7 +129,7 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
     rr_status rs = RR_OK;
     for (int r = 0; r < 4 && rs == RR_OK; ++r) {
         (void)hipEventRecord(e0, st);
-        rs = launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st);
+        rs = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0;
@@ -224,7 +225,7 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) 
     std::memcpy(s.host, bp.table.data(), need);
     e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "job table upload");
-    st = launch_groups(bp, (const uint8_t*)s.dev, false, device, hs);
+    st = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device, hs);
     e = hipEventRecord(s.done, hs);
     s.used = true;
     if (st != RR_OK) return st;
@@ -262,13 +263,13 @@ rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream) {
     if (b->plan.groups.empty()) return RR_OK;
     hipStream_t hs = (hipStream_t)stream;
     if (!(b->flags & RR_BATCH_GRAPH))
-        return launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs);
+        return launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs);
     if (!b->exec) {
         if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(RR_ERR_HIP, "capture stream");
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        rr_status st = launch_groups(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream);
+        rr_status st = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != RR_OK) { if (g) (void)hipGraphDestroy(g); return st; }

@@ -19,13 +19,29 @@ namespace rr {
 struct BatchGroup {
     int32_t kind;          // K_COPY / K_RUN / K_TILE
     int32_t variant;       // vector bytes (copy, run) or unit*100 + g (tile)
-    uint32_t njobs;
+    uint32_t njobs;        // entries (whole jobs or chunks of jobs)
     uint32_t total_blocks;
     uint32_t lds_bytes;    // largest tile of the group
     uint32_t pad_;
     uint64_t args_off;     // byte offset of the argument array in the table
     uint64_t prefix_off;   // byte offset of the njobs+1 prefix sums (uint32)
+    uint64_t range_off;    // byte offset of njobs EntryRange records
     uint64_t bytes;        // bytes per side moved by the group
+};
+
+// Which of its job's workgroups an entry runs: blocks [first, first + count)
+// of a launch of `job_blocks` workgroups.  A whole job is {0, grid, grid}.
+struct EntryRange {
+    uint32_t first;
+    uint32_t job_blocks;
+};
+
+// One entry of a batch: a planned job, or a contiguous range of its workgroups.
+struct BatchEntry {
+    const Plan* plan;
+    uint32_t first_block;
+    uint32_t nblocks;
+    uint64_t bytes;        // bytes per side this entry moves (for accounting)
 };
 
 struct BatchPlan {
@@ -39,5 +55,11 @@ struct BatchPlan {
 // failing job (or -1 for a cross-job overlap) and nothing is planned.
 rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
                      std::string* why, int* bad_job);
+
+// Validate one job and plan it (no overlap check against other jobs).
+rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string* why);
+
+// Group already planned entries into a batch table.
+rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, std::string* why);
 
 }  // namespace rr

@@ -35,6 +35,18 @@ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
+rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string* why) {
+    Canon c;
+    rr_status st = canonicalize(j.ndim, j.dims, j.perm, j.elem_size, &c, why);
+    if (st != RR_OK) return st;
+    if (c.total_bytes > 0) {
+        if (!j.dst || !j.src) { *why = "NULL buffer for a non-empty job"; return RR_ERR_INVALID_ARG; }
+        const uint64_t d = (uint64_t)j.dst, s = (uint64_t)j.src, n = (uint64_t)c.total_bytes;
+        if (d < s + n && s < d + n) { *why = "job source and destination overlap"; return RR_ERR_ALIAS; }
+    }
+    return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, p, why);
+}
+
 rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
                      std::string* why, int* bad_job) {
     *bad_job = -1;
@@ -50,19 +62,14 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
     dsts.reserve((size_t)njobs);
     srcs.reserve((size_t)njobs);
     for (int i = 0; i < njobs; ++i) {
-        const rr_job& j = jobs[i];
-        Canon c;
-        rr_status st = canonicalize(j.ndim, j.dims, j.perm, j.elem_size, &c, why);
+        rr_status st = plan_job(jobs[i], opt, &plans[(size_t)i], why);
         if (st != RR_OK) { *bad_job = i; return st; }
-        if (c.total_bytes > 0) {
-            if (!j.dst || !j.src) { *bad_job = i; *why = "NULL buffer for a non-empty job"; return RR_ERR_INVALID_ARG; }
-            const uint64_t d = (uint64_t)j.dst, s = (uint64_t)j.src, n = (uint64_t)c.total_bytes;
-            if (d < s + n && s < d + n) { *bad_job = i; *why = "job source and destination overlap"; return RR_ERR_ALIAS; }
+        const uint64_t n = plans[(size_t)i].bytes;
+        if (plans[(size_t)i].kind != K_EMPTY && n > 0) {
+            const uint64_t d = (uint64_t)jobs[i].dst, s = (uint64_t)jobs[i].src;
             dsts.push_back({d, d + n, i});
             srcs.push_back({s, s + n, i});
         }
-        st = plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, &plans[(size_t)i], why);
-        if (st != RR_OK) { *bad_job = i; return st; }
     }
     int ja, jb;
     if (find_overlap(dsts, srcs, &ja, &jb)) {
@@ -70,18 +77,29 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
         *bad_job = -1;
         return RR_ERR_ALIAS;
     }
+    std::vector<BatchEntry> entries;
+    entries.reserve((size_t)njobs);
+    for (const Plan& p : plans)
+        if (p.kind != K_EMPTY && p.grid > 0) entries.push_back({&p, 0, p.grid, p.bytes});
+    return build_batch(entries, out, why);
+}
 
-    // group by kernel family
-    std::map<std::pair<int, int>, std::vector<int>> fam;
-    for (int i = 0; i < njobs; ++i) {
-        const Plan& p = plans[(size_t)i];
-        if (p.kind == K_EMPTY || p.grid == 0) continue;
+rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, std::string* why) {
+    out->table.clear();
+    out->groups.clear();
+    out->bytes = 0;
+    out->njobs = 0;
+    // group by kernel family, keeping entry order within a group
+    std::map<std::pair<int, int>, std::vector<size_t>> fam;
+    for (size_t i = 0; i < entries.size(); ++i) {
+        const Plan& p = *entries[i].plan;
+        if (p.kind == K_EMPTY || entries[i].nblocks == 0) continue;
         int variant = 0;
         if (p.kind == K_COPY) variant = (int)p.copy.wbytes;
         else if (p.kind == K_RUN) variant = (int)p.run.wbytes;
         else variant = (int)(p.tile.unit * 100 + p.tile.g);
         fam[{(int)p.kind, variant}].push_back(i);
-        out->bytes += p.bytes;
+        out->bytes += entries[i].bytes;
         out->njobs++;
     }
     uint64_t off = 0;
@@ -96,24 +114,29 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
         off = align_up(off + asz * g.njobs, 256);
         g.prefix_off = off;
         off = align_up(off + 4ull * (g.njobs + 1), 256);
+        g.range_off = off;
+        off = align_up(off + sizeof(EntryRange) * g.njobs, 256);
         out->groups.push_back(g);
     }
     out->table.assign(off, 0);
-    for (size_t gi = 0; gi < out->groups.size(); ++gi) {
-        BatchGroup& g = out->groups[gi];
-        const std::vector<int>& members = fam[{g.kind, g.variant}];
+    for (BatchGroup& g : out->groups) {
+        const std::vector<size_t>& members = fam[{g.kind, g.variant}];
         uint32_t* prefix = reinterpret_cast<uint32_t*>(out->table.data() + g.prefix_off);
+        EntryRange* ranges = reinterpret_cast<EntryRange*>(out->table.data() + g.range_off);
+        uint8_t* argp = out->table.data() + g.args_off;
         uint64_t acc = 0;
         for (size_t m = 0; m < members.size(); ++m) {
-            const Plan& p = plans[(size_t)members[m]];
+            const BatchEntry& e = entries[members[m]];
+            const Plan& p = *e.plan;
             prefix[m] = (uint32_t)acc;
-            acc += p.grid;
-            g.bytes += p.bytes;
-            uint8_t* dstp = out->table.data() + g.args_off;
-            if (g.kind == K_COPY) std::memcpy(dstp + m * sizeof(CopyArgs), &p.copy, sizeof(CopyArgs));
-            else if (g.kind == K_RUN) std::memcpy(dstp + m * sizeof(RunArgs), &p.run, sizeof(RunArgs));
+            acc += e.nblocks;
+            ranges[m].first = e.first_block;
+            ranges[m].job_blocks = p.grid;
+            g.bytes += e.bytes;
+            if (g.kind == K_COPY) std::memcpy(argp + m * sizeof(CopyArgs), &p.copy, sizeof(CopyArgs));
+            else if (g.kind == K_RUN) std::memcpy(argp + m * sizeof(RunArgs), &p.run, sizeof(RunArgs));
             else {
-                std::memcpy(dstp + m * sizeof(TileArgs), &p.tile, sizeof(TileArgs));
+                std::memcpy(argp + m * sizeof(TileArgs), &p.tile, sizeof(TileArgs));
                 g.lds_bytes = std::max(g.lds_bytes, p.tile.lds_bytes);
             }
         }

@@ -11,6 +11,7 @@
 #include <cstdint>
 #include <cstring>
 
+#include "rr_batch.hpp"
 #include "rr_plan.hpp"
 
 #if defined(__HIPCC__)
@@ -444,17 +445,17 @@ RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
 }
 
 template <int W>
-RR_HD void batch_copy_block(const CopyArgs* args, const uint32_t* prefix, uint32_t njobs, uint32_t b,
-                            uint32_t tid) {
+RR_HD void batch_copy_block(const CopyArgs* args, const uint32_t* prefix, const EntryRange* ranges,
+                            uint32_t njobs, uint32_t b, uint32_t tid) {
     const uint32_t j = find_job(prefix, njobs, b);
-    copy_thread<W>(args[j], b - prefix[j], prefix[j + 1] - prefix[j], tid);
+    copy_thread<W>(args[j], b - prefix[j] + ranges[j].first, ranges[j].job_blocks, tid);
 }
 
 template <int W>
-RR_HD void batch_run_block(const RunArgs* args, const uint32_t* prefix, uint32_t njobs, uint32_t b,
-                           uint32_t tid) {
+RR_HD void batch_run_block(const RunArgs* args, const uint32_t* prefix, const EntryRange* ranges,
+                           uint32_t njobs, uint32_t b, uint32_t tid) {
     const uint32_t j = find_job(prefix, njobs, b);
-    run_thread<W>(args[j], b - prefix[j], tid);
+    run_thread<W>(args[j], b - prefix[j] + ranges[j].first, tid);
 }
 
 }  // namespace rr

@@ -46,13 +46,14 @@ __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
 // workgroup index walks the concatenation of the jobs' own launch grids.
 template <int U, int G>
 __global__ __launch_bounds__(NT) void k_batch_tile(const TileArgs* __restrict__ args,
-                                                   const uint32_t* __restrict__ prefix, uint32_t njobs,
+                                                   const uint32_t* __restrict__ prefix,
+                                                   const EntryRange* __restrict__ ranges, uint32_t njobs,
                                                    uint32_t total) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const uint32_t j = find_job(prefix, njobs, b);
         const TileArgs& a = args[j];
-        const TileCtx t = tile_decode(a, b - prefix[j]);
+        const TileCtx t = tile_decode(a, b - prefix[j] + ranges[j].first);
         read_dispatch<U, G>(a, t, smem, threadIdx.x);
         __syncthreads();
         write_phase<U, G>(a, t, smem, threadIdx.x);
@@ -62,18 +63,20 @@ __global__ __launch_bounds__(NT) void k_batch_tile(const TileArgs* __restrict__ 
 
 template <int W>
 __global__ __launch_bounds__(NT) void k_batch_run(const RunArgs* __restrict__ args,
-                                                  const uint32_t* __restrict__ prefix, uint32_t njobs,
+                                                  const uint32_t* __restrict__ prefix,
+                                                  const EntryRange* __restrict__ ranges, uint32_t njobs,
                                                   uint32_t total) {
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x)
-        batch_run_block<W>(args, prefix, njobs, b, threadIdx.x);
+        batch_run_block<W>(args, prefix, ranges, njobs, b, threadIdx.x);
 }
 
 template <int W>
 __global__ __launch_bounds__(NT) void k_batch_copy(const CopyArgs* __restrict__ args,
-                                                   const uint32_t* __restrict__ prefix, uint32_t njobs,
+                                                   const uint32_t* __restrict__ prefix,
+                                                   const EntryRange* __restrict__ ranges, uint32_t njobs,
                                                    uint32_t total) {
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x)
-        batch_copy_block<W>(args, prefix, njobs, b, threadIdx.x);
+        batch_copy_block<W>(args, prefix, ranges, njobs, b, threadIdx.x);
 }
 
 // ----------------------------------------------------------------- launch
@@ -123,7 +126,8 @@ static hipError_t launch_batch_tile_ug(const BatchGroup& g, const uint8_t* table
     }
     hipLaunchKernelGGL((k_batch_tile<U, G>), dim3(grid), dim3(NT), g.lds_bytes, st,
                        reinterpret_cast<const TileArgs*>(table + g.args_off),
-                       reinterpret_cast<const uint32_t*>(table + g.prefix_off), g.njobs, g.total_blocks);
+                       reinterpret_cast<const uint32_t*>(table + g.prefix_off),
+                       reinterpret_cast<const EntryRange*>(table + g.range_off), g.njobs, g.total_blocks);
     return hipGetLastError();
 }
 
@@ -131,25 +135,26 @@ hipError_t launch_batch_group(const BatchGroup& g, const uint8_t* table, uint32_
     if (g.total_blocks == 0) return hipSuccess;
     if (grid == 0 || grid > g.total_blocks) grid = g.total_blocks;
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
+    const EntryRange* ranges = reinterpret_cast<const EntryRange*>(table + g.range_off);
     if (g.kind == K_COPY) {
         const CopyArgs* args = reinterpret_cast<const CopyArgs*>(table + g.args_off);
         switch (g.variant) {
-            case 16: hipLaunchKernelGGL(k_batch_copy<16>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 8: hipLaunchKernelGGL(k_batch_copy<8>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 4: hipLaunchKernelGGL(k_batch_copy<4>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 2: hipLaunchKernelGGL(k_batch_copy<2>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            default: hipLaunchKernelGGL(k_batch_copy<1>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
+            case 16: hipLaunchKernelGGL(k_batch_copy<16>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 8: hipLaunchKernelGGL(k_batch_copy<8>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 4: hipLaunchKernelGGL(k_batch_copy<4>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 2: hipLaunchKernelGGL(k_batch_copy<2>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            default: hipLaunchKernelGGL(k_batch_copy<1>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
         }
         return hipGetLastError();
     }
     if (g.kind == K_RUN) {
         const RunArgs* args = reinterpret_cast<const RunArgs*>(table + g.args_off);
         switch (g.variant) {
-            case 16: hipLaunchKernelGGL(k_batch_run<16>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 8: hipLaunchKernelGGL(k_batch_run<8>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 4: hipLaunchKernelGGL(k_batch_run<4>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            case 2: hipLaunchKernelGGL(k_batch_run<2>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
-            default: hipLaunchKernelGGL(k_batch_run<1>, dim3(grid), dim3(NT), 0, st, args, prefix, g.njobs, g.total_blocks); break;
+            case 16: hipLaunchKernelGGL(k_batch_run<16>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 8: hipLaunchKernelGGL(k_batch_run<8>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 4: hipLaunchKernelGGL(k_batch_run<4>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            case 2: hipLaunchKernelGGL(k_batch_run<2>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
+            default: hipLaunchKernelGGL(k_batch_run<1>, dim3(grid), dim3(NT), 0, st, args, prefix, ranges, g.njobs, g.total_blocks); break;
         }
         return hipGetLastError();
     }

@@ -17,6 +17,8 @@
 
 #include <algorithm>
 #include <cstring>
+#include <map>
+#include <mutex>
 #include <sstream>
 
 namespace rr {
@@ -32,6 +34,72 @@ Magic make_magic(uint32_t d) {
 TileOptions& tile_override() {
     static TileOptions o;
     return o;
+}
+
+bool tile_override_active() {
+    const TileOptions& o = tile_override();
+    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1;
+}
+
+namespace {
+std::mutex g_tune_mu;
+std::map<std::string, TileOptions>& tune_cache() {
+    static std::map<std::string, TileOptions> m;
+    return m;
+}
+}  // namespace
+
+std::string tune_key(const Canon& c, uint64_t dst, uint64_t src) {
+    std::string k = "r" + std::to_string(c.rank) + ":e" + std::to_string(c.elem_bytes) + ":a" +
+                    std::to_string(addr_align(src)) + "/" + std::to_string(addr_align(dst)) + ":d";
+    for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.dims[i]);
+    k += ":p";
+    for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.perm[i]);
+    return k;
+}
+
+bool tune_lookup(const std::string& key, TileOptions* out) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    auto& m = tune_cache();
+    if (m.empty()) return false;
+    auto it = m.find(key);
+    if (it == m.end()) return false;
+    *out = it->second;
+    return true;
+}
+
+void tune_store(const std::string& key, const TileOptions& o) {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache()[key] = o;
+}
+
+void tune_clear() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    tune_cache().clear();
+}
+
+std::string tune_dump() {
+    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::ostringstream o;
+    for (const auto& kv : tune_cache())
+        o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
+          << kv.second.order_out << "\n";
+    return o.str();
+}
+
+int tune_parse(const std::string& text) {
+    std::istringstream in(text);
+    std::string key;
+    int n = 0;
+    TileOptions o;
+    while (in >> key >> o.in_row_bytes >> o.out_row_bytes >> o.order_out) {
+        if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
+            o.order_out < -1 || o.order_out > 1)
+            return -1;
+        tune_store(key, o);
+        ++n;
+    }
+    return n;
 }
 
 static bool mul_ovf(int64_t a, int64_t b, int64_t* r) { return __builtin_mul_overflow(a, b, r); }
@@ -293,6 +361,15 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     };
     set_outer(aO, targetA, innerA, nA == 1);
     set_outer(bO, targetB, innerB, nB == 1);
+    // Short output rows whose next output axis sits on the input side: with the
+    // whole B side in the tile, consecutive values of that axis are adjacent
+    // output rows, so taking it whole turns short rows into one long output run.
+    // (The input side needs no such step: when A is whole and B starts at the
+    // next input axis, input rows are already back to back.)
+    if (nB < r && t[bO] == d[bO] && innerB * d[bO] * R < out_rb) {
+        const int x = pm[r - 1 - nB];
+        if (x == aO) t[aO] = d[aO];
+    }
     // shrink until the tile fits in LDS
     for (int guard = 0; guard < 64; ++guard) {
         int64_t TA = innerA * t[aO], TB = innerB * t[bO];
@@ -368,6 +445,12 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.count == 0 || c.total_bytes == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (c.rank == 0) { plan_copy(dst, src, (uint64_t)c.total_bytes, p); return RR_OK; }
     if (c.elem_bytes >= RUN_MIN_BYTES) return plan_run(dst, src, c, p, why);
+    // a tuned shape for this problem replaces the built-in choice (not an explicit override)
+    TileOptions tuned;
+    if (!tile_override_active() && &opt == &tile_override() && tune_lookup(tune_key(c, dst, src), &tuned)) {
+        tuned.max_lds = opt.max_lds;
+        return plan_tile(dst, src, c, tuned, p, why);
+    }
     return plan_tile(dst, src, c, opt, p, why);
 }
 

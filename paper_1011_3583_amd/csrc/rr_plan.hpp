@@ -120,6 +120,15 @@ struct TileOptions {
 
 // Process-wide override (autotuner hook).
 TileOptions& tile_override();
+bool tile_override_active();
+
+// Tuning cache: canonical problem + alignment class -> tile options.
+std::string tune_key(const Canon& c, uint64_t dst, uint64_t src);
+bool tune_lookup(const std::string& key, TileOptions* out);
+void tune_store(const std::string& key, const TileOptions& o);
+void tune_clear();
+std::string tune_dump();
+int tune_parse(const std::string& text);
 
 // Validation + canonicalisation.  Writes a human-readable reason on failure.
 rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_size,

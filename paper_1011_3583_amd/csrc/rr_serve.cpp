@@ -1,13 +1,609 @@
-// rr_serve.cpp -- serving loop (placeholder until the server lands).
+// rr_serve.cpp -- continuous-batching server for permute jobs.
+//
+// One server thread owns admission, batching and completion:
+//   * submissions wait in a FIFO queue; a job is admitted when its output (if the
+//     server allocates it) fits in the HBM budget -- jobs that need no memory may
+//     pass a job that is waiting for memory;
+//   * while fewer than max_inflight batches are on the device, the thread forms
+//     the next batch from every admitted piece of work (at most max_batch_jobs):
+//     one chunk of each large job in progress, then newly admitted jobs;
+//   * a large job is cut into ranges of its own workgroups of about chunk_bytes
+//     of output each, so one huge permute never blocks small jobs for long;
+//   * batches are launched through the batched kernels on streams taken in turn,
+//     so consecutive batches overlap on the device; completion is observed with
+//     events and published to a completion queue.
+// A simulated backend (RR_SERVE_SIMULATED) replaces memory and launches with
+// virtual addresses and synthetic durations, so the same policy code runs on a
+// machine without a GPU.
+#include <hip/hip_runtime_api.h>
+
+#include <algorithm>
+#include <chrono>
+#include <condition_variable>
+#include <cstring>
+#include <deque>
+#include <map>
+#include <memory>
+#include <mutex>
+#include <thread>
+#include <unordered_map>
+#include <vector>
+
+#include "rr_batch.hpp"
 #include "rr_internal.hpp"
+#include "rr_kernels.hpp"
+
+namespace rr {
+namespace {
+
+uint64_t now_ns() {
+    return (uint64_t)std::chrono::duration_cast<std::chrono::nanoseconds>(
+               std::chrono::steady_clock::now().time_since_epoch())
+        .count();
+}
+
+uint64_t round_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
+
+// ----------------------------------------------------------------- backends
+struct Backend {
+    virtual ~Backend() {}
+    virtual rr_status init(int device, int nslots, int nstreams) = 0;
+    virtual void bind_thread() {}
+    virtual void* reserve(uint64_t bytes) = 0;
+    virtual void release(void* p) = 0;
+    // stage the table and launch a batch in slot `slot` on stream `stream`
+    virtual rr_status launch(int slot, int stream, const BatchPlan& bp) = 0;
+    // launch one job exactly as rr_permute does
+    virtual rr_status launch_single(int slot, int stream, const Plan& p) = 0;
+    virtual bool done(int slot) = 0;
+};
+
+class HipBackend : public Backend {
+   public:
+    ~HipBackend() override {
+        for (Slot& s : slots_) {
+            if (s.ev) (void)hipEventSynchronize(s.ev);
+            if (s.ev) (void)hipEventDestroy(s.ev);
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.dev) (void)hipFree(s.dev);
+        }
+        for (hipStream_t st : streams_) (void)hipStreamDestroy(st);
+    }
+    rr_status init(int device, int nslots, int nstreams) override {
+        device_ = device;
+        hipError_t e = hipSetDevice(device);
+        if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+        slots_.resize((size_t)nslots);
+        for (Slot& s : slots_)
+            if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess)
+                return hip_fail(e, "hipEventCreate");
+        streams_.resize((size_t)nstreams);
+        for (hipStream_t& st : streams_)
+            if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
+                return hip_fail(e, "hipStreamCreate");
+        return RR_OK;
+    }
+    void bind_thread() override { (void)hipSetDevice(device_); }
+    void* reserve(uint64_t bytes) override {
+        // allocate on the server's device without changing the caller's current device
+        int prev = 0;
+        (void)hipGetDevice(&prev);
+        (void)hipSetDevice(device_);
+        void* p = nullptr;
+        if (hipMalloc(&p, bytes) != hipSuccess) p = nullptr;
+        (void)hipSetDevice(prev);
+        return p;
+    }
+    void release(void* p) override { (void)hipFree(p); }
+    rr_status launch(int slot, int stream, const BatchPlan& bp) override {
+        Slot& s = slots_[(size_t)slot];
+        const size_t need = bp.table.size();
+        if (need > s.cap) {
+            if (s.host) (void)hipHostFree(s.host);
+            if (s.dev) (void)hipFree(s.dev);
+            s.host = s.dev = nullptr;
+            s.cap = 0;
+            const size_t cap = std::max<size_t>(round_up(need, 1 << 20), 1 << 20);
+            if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
+                return fail(RR_ERR_NO_MEMORY, "pinned staging");
+            if (hipMalloc(&s.dev, cap) != hipSuccess) return fail(RR_ERR_NO_MEMORY, "device job table");
+            s.cap = cap;
+        }
+        hipStream_t st = streams_[(size_t)stream];
+        std::memcpy(s.host, bp.table.data(), need);
+        hipError_t e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, st);
+        if (e != hipSuccess) return hip_fail(e, "server table upload");
+        rr_status rs = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device_, st);
+        e = hipEventRecord(s.ev, st);
+        if (rs != RR_OK) return rs;
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        return RR_OK;
+    }
+    rr_status launch_single(int slot, int stream, const Plan& p) override {
+        hipStream_t st = streams_[(size_t)stream];
+        hipError_t e = launch_plan(p, st);
+        if (e != hipSuccess) return hip_fail(e, "server direct launch");
+        e = hipEventRecord(slots_[(size_t)slot].ev, st);
+        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+        return RR_OK;
+    }
+    bool done(int slot) override { return hipEventQuery(slots_[(size_t)slot].ev) != hipErrorNotReady; }
+
+   private:
+    struct Slot {
+        void* host = nullptr;
+        void* dev = nullptr;
+        size_t cap = 0;
+        hipEvent_t ev = nullptr;
+    };
+    int device_ = 0;
+    std::vector<Slot> slots_;
+    std::vector<hipStream_t> streams_;
+};
+
+class SimBackend : public Backend {
+   public:
+    explicit SimBackend(double bytes_per_us) : bpus_(bytes_per_us > 0 ? bytes_per_us : 4e6) {}
+    rr_status init(int, int nslots, int) override {
+        done_at_.assign((size_t)nslots, 0);
+        return RR_OK;
+    }
+    void* reserve(uint64_t bytes) override {
+        const uint64_t p = next_;
+        next_ += round_up(bytes, 1 << 20) + (1 << 20);
+        return reinterpret_cast<void*>(p);
+    }
+    void release(void*) override {}
+    rr_status launch(int slot, int, const BatchPlan& bp) override {
+        const uint64_t t = now_ns();
+        const uint64_t dur = (uint64_t)(2.0 * (double)bp.bytes / bpus_ * 1e3) + 2000;  // + launch cost
+        busy_until_ = std::max(busy_until_, t) + dur;   // one device: batches share its bandwidth
+        done_at_[(size_t)slot] = busy_until_;
+        return RR_OK;
+    }
+    rr_status launch_single(int slot, int, const Plan& p) override {
+        const uint64_t t = now_ns();
+        const uint64_t dur = (uint64_t)(2.0 * (double)p.bytes / bpus_ * 1e3) + 2000;
+        busy_until_ = std::max(busy_until_, t) + dur;
+        done_at_[(size_t)slot] = busy_until_;
+        return RR_OK;
+    }
+    bool done(int slot) override { return now_ns() >= done_at_[(size_t)slot]; }
+
+   private:
+    double bpus_;
+    uint64_t next_ = 0x200000000000ull;
+    uint64_t busy_until_ = 0;
+    std::vector<uint64_t> done_at_;
+};
+
+// ----------------------------------------------------------------- arena
+// First-fit allocator with coalescing over slabs reserved from the backend.
+class Arena {
+   public:
+    explicit Arena(Backend* be) : be_(be) {}
+    ~Arena() {
+        for (auto& s : slabs_) be_->release(reinterpret_cast<void*>(s.base));
+    }
+    void* alloc(uint64_t bytes) {
+        bytes = round_up(std::max<uint64_t>(bytes, 1), 256);
+        for (Slab& s : slabs_) {
+            for (auto it = s.free.begin(); it != s.free.end(); ++it) {
+                if (it->second >= bytes) {
+                    const uint64_t off = it->first, len = it->second;
+                    s.free.erase(it);
+                    if (len > bytes) s.free[off + bytes] = len - bytes;
+                    used_[s.base + off] = bytes;
+                    return reinterpret_cast<void*>(s.base + off);
+                }
+            }
+        }
+        const uint64_t slab = std::max<uint64_t>(bytes, 256ull << 20);
+        void* p = be_->reserve(slab);
+        if (!p) return nullptr;
+        slabs_.push_back(Slab{(uint64_t)p, slab, {}});
+        Slab& s = slabs_.back();
+        if (slab > bytes) s.free[bytes] = slab - bytes;
+        used_[s.base] = bytes;
+        return p;
+    }
+    // returns the bytes freed (0 if p is not an allocation of this arena)
+    uint64_t free(void* p) {
+        auto u = used_.find((uint64_t)p);
+        if (u == used_.end()) return 0;
+        const uint64_t addr = u->first, len = u->second;
+        used_.erase(u);
+        for (Slab& s : slabs_) {
+            if (addr < s.base || addr >= s.base + s.size) continue;
+            uint64_t off = addr - s.base, n = len;
+            auto next = s.free.lower_bound(off);
+            if (next != s.free.end() && next->first == off + n) { n += next->second; next = s.free.erase(next); }
+            if (next != s.free.begin()) {
+                auto prev = std::prev(next);
+                if (prev->first + prev->second == off) { prev->second += n; return len; }
+            }
+            s.free[off] = n;
+            return len;
+        }
+        return len;
+    }
+
+   private:
+    struct Slab {
+        uint64_t base, size;
+        std::map<uint64_t, uint64_t> free;  // offset -> length
+    };
+    Backend* be_;
+    std::vector<Slab> slabs_;
+    std::unordered_map<uint64_t, uint64_t> used_;
+};
+
+// ----------------------------------------------------------------- server
+struct JobState {
+    uint64_t ticket = 0;
+    rr_job job{};
+    Plan plan;
+    bool own_dst = false;
+    uint64_t out_bytes = 0;
+    uint32_t next_block = 0;     // first workgroup not yet put in a batch
+    uint32_t chunk_blocks = 0;   // workgroups per chunk (0: whole job)
+    uint32_t outstanding = 0;    // batches in flight holding a piece of this job
+    int32_t chunks = 0;
+    int32_t status = RR_OK;
+    bool done = false;
+    uint64_t t_submit = 0, t_admit = 0, t_launch = 0, t_done = 0;
+};
+
+struct InFlight {
+    int slot;
+    std::vector<JobState*> jobs;
+    uint64_t bytes;
+};
+
+}  // namespace
+}  // namespace rr
+
+using namespace rr;
+
+struct rr_server {
+    rr_serve_config cfg{};
+    std::unique_ptr<Backend> be;
+    std::unique_ptr<Arena> arena;
+    std::mutex mu;
+    std::condition_variable cv;
+    std::deque<JobState*> pending;
+    std::deque<JobState*> large;
+    std::unordered_map<uint64_t, std::unique_ptr<JobState>> jobs;
+    std::deque<uint64_t> completions;
+    std::vector<InFlight> inflight;
+    std::vector<bool> slot_busy;
+    std::unordered_map<uint64_t, uint64_t> user_allocs;
+    uint64_t next_ticket = 1;
+    uint64_t budget_used = 0;
+    bool stopping = false;
+    bool fail_next = false;
+    int next_stream = 0;
+    int nstreams = 1;
+    rr_serve_stats stats{};
+    std::thread th;
+
+    void complete(JobState* j, uint64_t t) {
+        j->done = true;
+        j->t_done = t;
+        if (j->status == RR_OK) stats.completed++; else stats.failed++;
+        completions.push_back(j->ticket);
+    }
+
+    // Admit job j (lock held): allocate its output if needed and plan it.
+    bool admit(JobState* j) {
+        if (j->own_dst) {
+            if (budget_used + round_up(j->out_bytes, 256) > cfg.hbm_budget_bytes) return false;
+            void* p = arena->alloc(j->out_bytes);
+            if (!p) return false;
+            budget_used += round_up(j->out_bytes, 256);
+            stats.budget_peak = std::max(stats.budget_peak, budget_used);
+            j->job.dst = p;
+        }
+        j->t_admit = now_ns();
+        std::string why;
+        rr_status st = plan_job(j->job, tile_override(), &j->plan, &why);
+        if (st != RR_OK) { j->status = st; return true; }
+        if (!(cfg.flags & RR_SERVE_DIRECT) && cfg.chunk_bytes > 0 && j->plan.grid > 1 &&
+            j->plan.bytes > cfg.chunk_bytes) {
+            const uint64_t per_block = std::max<uint64_t>(1, j->plan.bytes / j->plan.grid);
+            j->chunk_blocks = (uint32_t)std::max<uint64_t>(1, cfg.chunk_bytes / per_block);
+        }
+        return true;
+    }
+
+    void loop() {
+        be->bind_thread();
+        const int maxin = std::max(1, cfg.max_inflight);
+        const bool direct = (cfg.flags & RR_SERVE_DIRECT) != 0;
+        const size_t maxjobs = direct ? 1 : (size_t)std::max(1, cfg.max_batch_jobs);
+        for (;;) {
+            std::vector<BatchEntry> entries;
+            std::vector<JobState*> members;
+            int slot = -1, stream = 0;
+            bool fail_this = false;
+            {
+                std::unique_lock<std::mutex> lk(mu);
+                // retire finished batches
+                const uint64_t t = now_ns();
+                for (size_t i = 0; i < inflight.size();) {
+                    if (!be->done(inflight[i].slot)) { ++i; continue; }
+                    InFlight f = std::move(inflight[i]);
+                    inflight.erase(inflight.begin() + (long)i);
+                    slot_busy[(size_t)f.slot] = false;
+                    stats.bytes_moved += f.bytes;
+                    for (JobState* j : f.jobs) {
+                        j->outstanding--;
+                        const bool all_launched = j->status != RR_OK || j->next_block >= j->plan.grid;
+                        if (j->outstanding == 0 && all_launched && !j->done) complete(j, t);
+                    }
+                }
+                if (stopping && pending.empty() && large.empty() && inflight.empty()) break;
+                if (stopping && large.empty() && inflight.empty()) {
+                    // shutting down and idle: whatever is still queued waits for memory that
+                    // only a release (which cannot come any more) would free
+                    bool any = false;
+                    for (JobState* j : pending) {
+                        if (j->own_dst && budget_used + round_up(j->out_bytes, 256) > cfg.hbm_budget_bytes) {
+                            j->status = RR_ERR_NO_MEMORY;
+                            complete(j, now_ns());
+                            any = true;
+                        }
+                    }
+                    if (any)
+                        pending.erase(std::remove_if(pending.begin(), pending.end(),
+                                                     [](JobState* j) { return j->done; }),
+                                      pending.end());
+                }
+                if ((int)inflight.size() < maxin) {
+                    for (int s = 0; s < maxin; ++s) if (!slot_busy[(size_t)s]) { slot = s; break; }
+                }
+                if (slot >= 0) {
+                    // one chunk of every large job in progress, oldest first
+                    for (size_t k = 0; k < large.size() && entries.size() < maxjobs;) {
+                        JobState* j = large[k];
+                        const uint32_t n = std::min(j->chunk_blocks, j->plan.grid - j->next_block);
+                        const uint64_t bytes = (uint64_t)((double)j->plan.bytes * n / j->plan.grid);
+                        entries.push_back({&j->plan, j->next_block, n, bytes});
+                        members.push_back(j);
+                        j->next_block += n;
+                        j->outstanding++;
+                        j->chunks++;
+                        if (j->next_block >= j->plan.grid) large.erase(large.begin() + (long)k);
+                        else ++k;
+                    }
+                    // newly admitted jobs, FIFO; jobs needing no memory may pass one that waits
+                    bool head_blocked = false;
+                    for (auto it = pending.begin(); it != pending.end() && entries.size() < maxjobs;) {
+                        JobState* j = *it;
+                        if (head_blocked && j->own_dst) { ++it; continue; }
+                        if (!admit(j)) { head_blocked = true; ++it; continue; }
+                        it = pending.erase(it);
+                        if (j->status != RR_OK) { complete(j, now_ns()); continue; }
+                        if (j->plan.kind == K_EMPTY || j->plan.grid == 0) { complete(j, now_ns()); continue; }
+                        const uint32_t n = j->chunk_blocks ? j->chunk_blocks : j->plan.grid;
+                        const uint64_t bytes = (uint64_t)((double)j->plan.bytes * n / j->plan.grid);
+                        entries.push_back({&j->plan, 0, n, bytes});
+                        members.push_back(j);
+                        j->next_block = n;
+                        j->outstanding++;
+                        j->chunks++;
+                        if (j->next_block < j->plan.grid) large.push_back(j);
+                    }
+                    if (entries.empty()) {
+                        slot = -1;
+                    } else {
+                        slot_busy[(size_t)slot] = true;
+                        stream = next_stream;
+                        next_stream = (next_stream + 1) % nstreams;
+                        fail_this = fail_next;
+                        fail_next = false;
+                        const uint64_t tl = now_ns();
+                        for (JobState* j : members) if (!j->t_launch) j->t_launch = tl;
+                        stats.batches++;
+                        stats.chunks += entries.size();
+                    }
+                }
+                if (slot < 0) {
+                    // nothing to launch now: sleep until a submission or the next poll
+                    const uint32_t us = inflight.empty() ? std::max<uint32_t>(cfg.tick_us, 1) * 50
+                                                         : std::max<uint32_t>(cfg.tick_us, 1);
+                    cv.wait_for(lk, std::chrono::microseconds(us));
+                    continue;
+                }
+            }
+            // build and launch outside the lock
+            BatchPlan bp;
+            std::string why;
+            rr_status st = RR_ERR_HIP;
+            if (!fail_this && direct) {
+                st = be->launch_single(slot, stream, *entries[0].plan);
+                bp.bytes = entries[0].bytes;
+            } else if (!fail_this) {
+                st = build_batch(entries, &bp, &why);
+                if (st == RR_OK) st = be->launch(slot, stream, bp);
+            }
+            std::lock_guard<std::mutex> lk(mu);
+            if (st != RR_OK) {
+                slot_busy[(size_t)slot] = false;
+                const uint64_t t = now_ns();
+                for (JobState* j : members) {
+                    j->status = RR_ERR_HIP;
+                    j->outstanding--;
+                    // stop issuing the rest of a failed large job
+                    auto it = std::find(large.begin(), large.end(), j);
+                    if (it != large.end()) large.erase(it);
+                    if (j->outstanding == 0 && !j->done) complete(j, t);
+                }
+            } else {
+                inflight.push_back(InFlight{slot, std::move(members), bp.bytes});
+            }
+        }
+    }
+};
 
 extern "C" {
-rr_status rr_serve_create(const rr_serve_config*, rr_server**) { return rr::fail(RR_ERR_UNSUPPORTED, "server not built yet"); }
-rr_status rr_serve_alloc(rr_server*, uint64_t, void**) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_free(rr_server*, void*) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_submit(rr_server*, const rr_job*, uint64_t*) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_poll(rr_server*, uint64_t, rr_job_result*) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_release(rr_server*, uint64_t) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_destroy(rr_server*) { return RR_ERR_UNSUPPORTED; }
-rr_status rr_serve_get_stats(rr_server*, rr_serve_stats*) { return RR_ERR_UNSUPPORTED; }
+
+rr_status rr_serve_create(const rr_serve_config* cfg, rr_server** out) {
+    clear_error();
+    if (!cfg || !out) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    *out = nullptr;
+    if (cfg->max_inflight < 1 || cfg->max_inflight > 64 || cfg->max_batch_jobs < 1 ||
+        cfg->queue_capacity < 1 || cfg->hbm_budget_bytes == 0)
+        return fail(RR_ERR_INVALID_ARG, "bad server configuration");
+    auto s = std::make_unique<rr_server>();
+    s->cfg = *cfg;
+    if (cfg->flags & RR_SERVE_SIMULATED) s->be = std::make_unique<SimBackend>(cfg->sim_bytes_per_us);
+    else s->be = std::make_unique<HipBackend>();
+    s->nstreams = std::min(cfg->max_inflight, 4);
+    rr_status st = s->be->init(cfg->device, cfg->max_inflight, s->nstreams);
+    if (st != RR_OK) return st;
+    s->arena = std::make_unique<Arena>(s->be.get());
+    s->slot_busy.assign((size_t)cfg->max_inflight, false);
+    rr_server* raw = s.release();
+    raw->th = std::thread([raw] { raw->loop(); });
+    *out = raw;
+    return RR_OK;
 }
+
+rr_status rr_serve_alloc(rr_server* s, uint64_t bytes, void** dptr) {
+    clear_error();
+    if (!s || !dptr || bytes == 0) return fail(RR_ERR_INVALID_ARG, "bad argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    const uint64_t b = round_up(bytes, 256);
+    if (s->budget_used + b > s->cfg.hbm_budget_bytes) return fail(RR_ERR_NO_MEMORY, "over the HBM budget");
+    void* p = s->arena->alloc(bytes);
+    if (!p) return fail(RR_ERR_NO_MEMORY, "device allocation failed");
+    s->budget_used += b;
+    s->stats.budget_peak = std::max(s->stats.budget_peak, s->budget_used);
+    s->user_allocs[(uint64_t)p] = b;
+    *dptr = p;
+    return RR_OK;
+}
+
+rr_status rr_serve_free(rr_server* s, void* dptr) {
+    clear_error();
+    if (!s) return fail(RR_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->user_allocs.find((uint64_t)dptr);
+    if (it == s->user_allocs.end()) return fail(RR_ERR_INVALID_ARG, "not a server allocation");
+    s->arena->free(dptr);
+    s->budget_used -= it->second;
+    s->user_allocs.erase(it);
+    return RR_OK;
+}
+
+rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
+    clear_error();
+    if (!s || !job || !ticket) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    Canon c;
+    std::string why;
+    rr_status st = canonicalize(job->ndim, job->dims, job->perm, job->elem_size, &c, &why);
+    if (st != RR_OK) return fail(st, why);
+    const uint64_t nb = (uint64_t)c.total_bytes;
+    if (nb > 0 && !job->src) return fail(RR_ERR_INVALID_ARG, "NULL source");
+    if (job->dst && ranges_overlap((uint64_t)job->dst, nb, (uint64_t)job->src, nb))
+        return fail(RR_ERR_ALIAS, "source and destination overlap");
+    const bool own = job->dst == nullptr && nb > 0;
+    if (own && round_up(nb, 256) > s->cfg.hbm_budget_bytes) return fail(RR_ERR_NO_MEMORY, "job exceeds the budget");
+    std::lock_guard<std::mutex> lk(s->mu);
+    if (s->stopping) return fail(RR_ERR_INVALID_ARG, "server is shutting down");
+    if (nb > 0 && (int)s->pending.size() >= s->cfg.queue_capacity) return fail(RR_ERR_BUSY, "queue full");
+    auto j = std::make_unique<JobState>();
+    j->ticket = s->next_ticket++;
+    j->job = *job;
+    j->own_dst = own;
+    j->out_bytes = nb;
+    j->t_submit = now_ns();
+    JobState* raw = j.get();
+    s->jobs[j->ticket] = std::move(j);
+    s->stats.submitted++;
+    *ticket = raw->ticket;
+    if (nb == 0) {
+        s->complete(raw, raw->t_submit);
+        return RR_OK;
+    }
+    s->pending.push_back(raw);
+    s->cv.notify_one();
+    return RR_OK;
+}
+
+rr_status rr_serve_poll(rr_server* s, uint64_t ticket, rr_job_result* out) {
+    if (!s || !out) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return fail(RR_ERR_INVALID_ARG, "unknown ticket");
+    const JobState& j = *it->second;
+    if (!j.done) return RR_ERR_NOT_READY;
+    out->status = j.status;
+    out->chunks = j.chunks;
+    out->dst = j.job.dst;
+    out->t_submit_ns = j.t_submit;
+    out->t_admit_ns = j.t_admit;
+    out->t_launch_ns = j.t_launch;
+    out->t_done_ns = j.t_done;
+    return RR_OK;
+}
+
+rr_status rr_serve_completions(rr_server* s, uint64_t* out, int max, int* n) {
+    if (!s || !n || (max > 0 && !out)) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    int k = 0;
+    while (k < max && !s->completions.empty()) {
+        out[k++] = s->completions.front();
+        s->completions.pop_front();
+    }
+    *n = k;
+    return RR_OK;
+}
+
+rr_status rr_serve_release(rr_server* s, uint64_t ticket) {
+    if (!s) return fail(RR_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    auto it = s->jobs.find(ticket);
+    if (it == s->jobs.end()) return fail(RR_ERR_INVALID_ARG, "unknown ticket");
+    JobState& j = *it->second;
+    if (!j.done) return fail(RR_ERR_NOT_READY, "ticket still pending");
+    if (j.own_dst && j.job.dst) {
+        s->arena->free(j.job.dst);
+        s->budget_used -= round_up(j.out_bytes, 256);
+    }
+    s->jobs.erase(it);
+    return RR_OK;
+}
+
+rr_status rr_serve_destroy(rr_server* s) {
+    clear_error();
+    if (!s) return RR_OK;
+    {
+        std::lock_guard<std::mutex> lk(s->mu);
+        s->stopping = true;
+    }
+    s->cv.notify_all();
+    if (s->th.joinable()) s->th.join();
+    s->arena.reset();
+    s->be.reset();
+    delete s;
+    return RR_OK;
+}
+
+rr_status rr_serve_get_stats(rr_server* s, rr_serve_stats* out) {
+    if (!s || !out) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    std::lock_guard<std::mutex> lk(s->mu);
+    *out = s->stats;
+    out->budget_used = s->budget_used;
+    return RR_OK;
+}
+
+rr_status rr_serve_fail_next_batch(rr_server* s) {
+    if (!s) return fail(RR_ERR_INVALID_ARG, "NULL server");
+    std::lock_guard<std::mutex> lk(s->mu);
+    s->fail_next = true;
+    return RR_OK;
+}
+
+}  // extern "C"

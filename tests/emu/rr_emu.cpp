@@ -17,6 +17,7 @@
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
+#include <algorithm>
 #include <fstream>
 #include <sstream>
 #include <string>
@@ -87,12 +88,13 @@ template <int U, int G>
 static void run_batch_tile_ug(const BatchGroup& g, const uint8_t* table) {
     const TileArgs* args = reinterpret_cast<const TileArgs*>(table + g.args_off);
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
+    const EntryRange* ranges = reinterpret_cast<const EntryRange*>(table + g.range_off);
     for (uint32_t b = 0; b < g.total_blocks; ++b) {
         const uint32_t j = find_job(prefix, g.njobs, b);
         const TileArgs& a = args[j];
         uint8_t* lds = new uint8_t[g.lds_bytes];
         std::memset(lds, 0xA5, g.lds_bytes);
-        const TileCtx t = tile_decode(a, b - prefix[j]);
+        const TileCtx t = tile_decode(a, b - prefix[j] + ranges[j].first);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<U, G>(a, t, lds, tid);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) write_phase<U, G>(a, t, lds, tid);
         delete[] lds;
@@ -102,12 +104,15 @@ static void run_batch_tile_ug(const BatchGroup& g, const uint8_t* table) {
 template <int W>
 static void run_batch_small(const BatchGroup& g, const uint8_t* table) {
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
+    const EntryRange* ranges = reinterpret_cast<const EntryRange*>(table + g.range_off);
     for (uint32_t b = 0; b < g.total_blocks; ++b)
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) {
             if (g.kind == K_COPY)
-                batch_copy_block<W>(reinterpret_cast<const CopyArgs*>(table + g.args_off), prefix, g.njobs, b, tid);
+                batch_copy_block<W>(reinterpret_cast<const CopyArgs*>(table + g.args_off), prefix, ranges,
+                                    g.njobs, b, tid);
             else
-                batch_run_block<W>(reinterpret_cast<const RunArgs*>(table + g.args_off), prefix, g.njobs, b, tid);
+                batch_run_block<W>(reinterpret_cast<const RunArgs*>(table + g.args_off), prefix, ranges,
+                                   g.njobs, b, tid);
         }
 }
 
@@ -240,8 +245,8 @@ int main(int argc, char** argv) {
             delete[] flat;
         } else if (op == "batched") {
             // batched k in_rb out_rb order : then k lines "job ndim dims.. perm.. esize infile outfile"
-            int k, order;
-            is >> k >> opt.in_row_bytes >> opt.out_row_bytes >> order;
+            int k, order, chunk = 0;
+            is >> k >> opt.in_row_bytes >> opt.out_row_bytes >> order >> chunk;
             opt.order_out = order;
             std::vector<rr_job> jobs((size_t)k);
             std::vector<uint8_t*> bufs;
@@ -275,7 +280,31 @@ int main(int argc, char** argv) {
             }
             BatchPlan bp;
             int bad = -1;
-            rr_status st = plan_batch(jobs.data(), k, opt, &bp, &why, &bad);
+            rr_status st = RR_OK;
+            std::vector<Plan> plans((size_t)k);
+            if (chunk > 0) {
+                // every job cut into ranges of `chunk` workgroups, ranges of all jobs interleaved
+                std::vector<BatchEntry> entries;
+                for (int i = 0; i < k && st == RR_OK; ++i) {
+                    st = plan_job(jobs[(size_t)i], opt, &plans[(size_t)i], &why);
+                    if (st != RR_OK) bad = i;
+                }
+                for (uint32_t round = 0; st == RR_OK; ++round) {
+                    bool any = false;
+                    for (int i = 0; i < k; ++i) {
+                        const Plan& p = plans[(size_t)i];
+                        const uint64_t first = (uint64_t)round * (uint64_t)chunk;
+                        if (p.kind == K_EMPTY || first >= p.grid) continue;
+                        const uint32_t n = (uint32_t)std::min<uint64_t>((uint64_t)chunk, p.grid - first);
+                        entries.push_back({&p, (uint32_t)first, n, 0});
+                        any = true;
+                    }
+                    if (!any) break;
+                }
+                if (st == RR_OK) st = build_batch(entries, &bp, &why);
+            } else {
+                st = plan_batch(jobs.data(), k, opt, &bp, &why, &bad);
+            }
             if (st != RR_OK) {
                 std::printf("err %d job %d %s\n", (int)st, bad, why.c_str());
             } else {

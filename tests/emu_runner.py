@@ -59,7 +59,7 @@ def run(jobs):
                 np.concatenate(j["planes"]).tofile(inf)
                 lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
             elif j["op"] == "batched":
-                lines.append(f"batched {len(j['jobs'])} {rb} {j.get('order', -1)}")
+                lines.append(f"batched {len(j['jobs'])} {rb} {j.get('order', -1)} {j.get('chunk', 0)}")
                 for k, sub in enumerate(j["jobs"]):
                     sf, of = os.path.join(td, f"b{i}_{k}"), os.path.join(td, f"bo{i}_{k}")
                     sub["input"].tofile(sf)

@@ -130,3 +130,31 @@ def test_plan_uses_widest_vectors_on_aligned_buffers():
     # misaligned base pointer -> narrower access, still a valid plan
     d = rr.plan_describe((1024, 1024), (1, 0), 4, dst=(1 << 20) + 2, src=1 << 30)
     assert d["unit"] == "2"
+
+
+def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
+    """A cached tile shape for a canonical problem is used by later plans of it."""
+    L = rr.lib()
+    rr.tune_clear()
+    dims, perm, e = (16384, 16384), (1, 0), 4
+    base = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    path = tmp_path / "tune.txt"
+    key_line = "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1\n"
+    path.write_text(key_line)
+    rr.tune_load(str(path))
+    tuned = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    assert (tuned["TA"], tuned["TB"]) != (base["TA"], base["TB"])
+    assert tuned["TA"] == "256"                      # 1024-byte input rows of 4-byte elements
+    out = tmp_path / "saved.txt"
+    rr.tune_save(str(out))
+    assert key_line.strip() in out.read_text()
+    # an explicit override wins over the cache
+    rr.set_tile_override(128, 128, None)
+    assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["TA"] == "32"
+    rr.set_tile_override(0, 0, None)
+    rr.tune_clear()
+    assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30) == base
+    bad = tmp_path / "bad.txt"
+    bad.write_text("key 99999 1 0\n")
+    with pytest.raises(rr.RRError):
+        rr.tune_load(str(bad))

@@ -196,3 +196,18 @@ def test_emu_batched_uneven_jobs(seed, opts):
     for j, out in zip(jobs, outs):
         assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
             (j["dims"], j["perm"], j["esize"])
+
+
+@pytest.mark.parametrize("chunk", [1, 3])
+def test_emu_chunked_entries(chunk):
+    """Jobs cut into ranges of their own workgroups, ranges of different jobs
+    interleaved in one batch table (how the server spreads a large job)."""
+    jobs = _batched_jobs(7 + chunk, 25)
+    jobs += [_perm_job((300, 200), (1, 0), 4, 70), _perm_job((64, 64, 32), (1, 0, 2), 4, 71),
+             _perm_job((50000,), (0,), 2, 72), _perm_job((40, 30, 20), (2, 1, 0), 8, 73)]
+    res = emu_runner.run([dict(op="batched", jobs=jobs, chunk=chunk)])
+    status, outs = res[0]
+    assert status.startswith("ok"), status
+    for j, out in zip(jobs, outs):
+        assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
+            (j["dims"], j["perm"], j["esize"])

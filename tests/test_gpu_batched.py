@@ -150,8 +150,9 @@ def test_sampled_uneven_workload(rr):
 def test_overlapping_jobs_rejected(rr):
     x = torch.zeros(1 << 16, dtype=torch.uint8, device="cuda")
     base = x.data_ptr()
+    # job 1 writes [2048, 6144), inside job 0's output [0, 4096)
     arr = rr.make_jobs([(base, base + 8192, (32, 32), (1, 0), 4),
-                        (base + 4096, base + 16384, (32, 32), (1, 0), 4)])
+                        (base + 2048, base + 16384, (32, 32), (1, 0), 4)])
     assert rr.permute_batched_raw(arr, 2, 0) == 3
     assert "overlap" in rr.last_error()
     # job 1 reads [2048, 6144), which overlaps job 0's output [0, 4096)

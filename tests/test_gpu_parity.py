@@ -224,3 +224,22 @@ def test_flat_read_and_merged_store_paths(rr):
     for i, (dims, perm, e) in enumerate([((4096, 3), (1, 0), 4), ((64, 48, 6), (2, 0, 1), 2),
                                          ((2048, 5, 2), (1, 2, 0), 8)]):
         check_permute(rr, dims, perm, e, 9500 + i)
+
+
+def test_autotuned_plans_stay_exact(rr):
+    """Tuning runs every candidate shape; the cached winner must still be bit-exact."""
+    try:
+        for i, (dims, perm, e) in enumerate([((512, 384), (1, 0), 4), ((96, 80, 72), (2, 0, 1), 1),
+                                             ((32, 32, 32, 32), (3, 1, 0, 2), 2), ((300, 7, 50), (2, 1, 0), 8)]):
+            _say("tune", dims, perm, e)
+            x = rr_synth.random_bytes(700 + i, int(np.prod(dims)) * e)
+            ts, ps = _upload(x)
+            td, pd = _dev_buf(x.size)
+            best, default = rr.tune_permute(pd, ps, dims, perm, e, torch.cuda.current_stream().cuda_stream)
+            assert best > 0 and default >= best * 0.999
+            td.zero_()
+            rr.check(rr.permute_raw(pd, ps, dims, perm, e, torch.cuda.current_stream().cuda_stream))
+            torch.cuda.synchronize()
+            assert np.array_equal(_download(td, 0, x.size), oracle.permute(x, dims, perm, e))
+    finally:
+        rr.tune_clear()
