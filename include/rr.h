@@ -252,6 +252,7 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * size).  Process-wide; affects plans made after the call. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
+#define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
 
 /* -------------------------------------------------------------------------

@@ -150,6 +150,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
+    o.force_ragged = (flags & RR_TILE_FORCE_RAGGED) ? 1 : 0;
     return RR_OK;
 }
 

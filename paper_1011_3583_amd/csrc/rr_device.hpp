@@ -57,25 +57,58 @@ typedef uint32_t rr_u32x2 __attribute__((ext_vector_type(2)));
 #define RR_NT_STORE 1
 #endif
 
-template <int W, bool NT_ACCESS>
+// Device pointers here come from integers, so without help the compiler would
+// use flat instructions, which also count against the LDS wait counter and make
+// every LDS access wait for outstanding global stores.  Global accesses are
+// therefore made through address-space-1 pointers (global_load/global_store).
+#if defined(__HIP_DEVICE_COMPILE__)
+#define RR_AS_GLOBAL __attribute__((address_space(1)))
+template <typename T>
+__device__ __forceinline__ const RR_AS_GLOBAL T* as_global(const uint8_t* p) {
+    return (const RR_AS_GLOBAL T*)(reinterpret_cast<uintptr_t>(p));
+}
+template <typename T>
+__device__ __forceinline__ RR_AS_GLOBAL T* as_global_mut(uint8_t* p) {
+    return (RR_AS_GLOBAL T*)(reinterpret_cast<uintptr_t>(p));
+}
+#endif
+
+template <int W, bool NT_ACCESS, bool GLOBAL>
 RR_HD void vload_t(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    if constexpr (W == 16) {
-        const rr_u32x4* q = reinterpret_cast<const rr_u32x4*>(p);
-        rr_u32x4 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
-        w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
-    } else if constexpr (W == 8) {
-        const rr_u32x2* q = reinterpret_cast<const rr_u32x2*>(p);
-        rr_u32x2 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
-        w[0] = v.x; w[1] = v.y;
-    } else if constexpr (W == 4) {
-        const uint32_t* q = reinterpret_cast<const uint32_t*>(p);
-        w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
-    } else if constexpr (W == 2) {
-        const uint16_t* q = reinterpret_cast<const uint16_t*>(p);
-        w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+    if constexpr (GLOBAL) {
+        if constexpr (W == 16) {
+            const RR_AS_GLOBAL rr_u32x4* q = as_global<rr_u32x4>(p);
+            rr_u32x4 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else if constexpr (W == 8) {
+            const RR_AS_GLOBAL rr_u32x2* q = as_global<rr_u32x2>(p);
+            rr_u32x2 v = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+            w[0] = v.x; w[1] = v.y;
+        } else if constexpr (W == 4) {
+            const RR_AS_GLOBAL uint32_t* q = as_global<uint32_t>(p);
+            w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+        } else if constexpr (W == 2) {
+            const RR_AS_GLOBAL uint16_t* q = as_global<uint16_t>(p);
+            w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+        } else {
+            const RR_AS_GLOBAL uint8_t* q = as_global<uint8_t>(p);
+            w[0] = NT_ACCESS ? __builtin_nontemporal_load(q) : *q;
+        }
     } else {
-        w[0] = NT_ACCESS ? __builtin_nontemporal_load(p) : *p;
+        if constexpr (W == 16) {
+            rr_u32x4 v = *reinterpret_cast<const rr_u32x4*>(p);
+            w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+        } else if constexpr (W == 8) {
+            rr_u32x2 v = *reinterpret_cast<const rr_u32x2*>(p);
+            w[0] = v.x; w[1] = v.y;
+        } else if constexpr (W == 4) {
+            w[0] = *reinterpret_cast<const uint32_t*>(p);
+        } else if constexpr (W == 2) {
+            w[0] = *reinterpret_cast<const uint16_t*>(p);
+        } else {
+            w[0] = *p;
+        }
     }
 #else
     uint8_t tmp[4 * NWords<W>::value] = {};
@@ -84,40 +117,81 @@ RR_HD void vload_t(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
 #endif
 }
 
-template <int W, bool NT_ACCESS>
+template <int W, bool NT_ACCESS, bool GLOBAL>
 RR_HD void vstore_t(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
 #if defined(__HIP_DEVICE_COMPILE__)
-    if constexpr (W == 16) {
-        rr_u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
-        rr_u32x4* q = reinterpret_cast<rr_u32x4*>(p);
-        if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
-    } else if constexpr (W == 8) {
-        rr_u32x2 v; v.x = w[0]; v.y = w[1];
-        rr_u32x2* q = reinterpret_cast<rr_u32x2*>(p);
-        if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
-    } else if constexpr (W == 4) {
-        uint32_t* q = reinterpret_cast<uint32_t*>(p);
-        if (NT_ACCESS) __builtin_nontemporal_store(w[0], q); else *q = w[0];
-    } else if constexpr (W == 2) {
-        uint16_t* q = reinterpret_cast<uint16_t*>(p);
-        if (NT_ACCESS) __builtin_nontemporal_store((uint16_t)w[0], q); else *q = (uint16_t)w[0];
+    if constexpr (GLOBAL) {
+        if constexpr (W == 16) {
+            rr_u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+            RR_AS_GLOBAL rr_u32x4* q = as_global_mut<rr_u32x4>(p);
+            if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
+        } else if constexpr (W == 8) {
+            rr_u32x2 v; v.x = w[0]; v.y = w[1];
+            RR_AS_GLOBAL rr_u32x2* q = as_global_mut<rr_u32x2>(p);
+            if (NT_ACCESS) __builtin_nontemporal_store(v, q); else *q = v;
+        } else if constexpr (W == 4) {
+            RR_AS_GLOBAL uint32_t* q = as_global_mut<uint32_t>(p);
+            if (NT_ACCESS) __builtin_nontemporal_store(w[0], q); else *q = w[0];
+        } else if constexpr (W == 2) {
+            RR_AS_GLOBAL uint16_t* q = as_global_mut<uint16_t>(p);
+            if (NT_ACCESS) __builtin_nontemporal_store((uint16_t)w[0], q); else *q = (uint16_t)w[0];
+        } else {
+            RR_AS_GLOBAL uint8_t* q = as_global_mut<uint8_t>(p);
+            if (NT_ACCESS) __builtin_nontemporal_store((uint8_t)w[0], q); else *q = (uint8_t)w[0];
+        }
     } else {
-        if (NT_ACCESS) __builtin_nontemporal_store((uint8_t)w[0], p); else *p = (uint8_t)w[0];
+        if constexpr (W == 16) {
+            rr_u32x4 v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+            *reinterpret_cast<rr_u32x4*>(p) = v;
+        } else if constexpr (W == 8) {
+            rr_u32x2 v; v.x = w[0]; v.y = w[1];
+            *reinterpret_cast<rr_u32x2*>(p) = v;
+        } else if constexpr (W == 4) {
+            *reinterpret_cast<uint32_t*>(p) = w[0];
+        } else if constexpr (W == 2) {
+            *reinterpret_cast<uint16_t*>(p) = (uint16_t)w[0];
+        } else {
+            *p = (uint8_t)w[0];
+        }
     }
 #else
     std::memcpy(p, w, W);
 #endif
 }
 
+// 16 bytes at any byte alignment: gfx950 issues one global_load/store_dwordx4
+// whatever the address alignment (the memory system runs in unaligned mode).
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef uint32_t rr_u32x4_u __attribute__((ext_vector_type(4), aligned(1)));
+#endif
+RR_HD void gload16u(const uint8_t* p, uint32_t (&w)[4]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    const RR_AS_GLOBAL rr_u32x4_u* q = as_global<rr_u32x4_u>(p);
+    rr_u32x4_u v = RR_NT_LOAD ? __builtin_nontemporal_load(q) : *q;
+    w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
+#else
+    std::memcpy(w, p, 16);
+#endif
+}
+RR_HD void gstore16u(uint8_t* p, const uint32_t (&w)[4]) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    rr_u32x4_u v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
+    RR_AS_GLOBAL rr_u32x4_u* q = as_global_mut<rr_u32x4_u>(p);
+    if (RR_NT_STORE) __builtin_nontemporal_store(v, q); else *q = v;
+#else
+    std::memcpy(p, w, 16);
+#endif
+}
+
 // global memory (streamed) and LDS (ordinary)
 template <int W>
-RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, RR_NT_LOAD != 0>(p, w); }
+RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, RR_NT_LOAD != 0, true>(p, w); }
 template <int W>
-RR_HD void gstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, RR_NT_STORE != 0>(p, w); }
+RR_HD void gstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, RR_NT_STORE != 0, true>(p, w); }
 template <int W>
-RR_HD void sload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, false>(p, w); }
+RR_HD void sload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, false, false>(p, w); }
 template <int W>
-RR_HD void sstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, false>(p, w); }
+RR_HD void sstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, false, false>(p, w); }
 
 // GxG transpose of U-byte elements held as G rows of W = U*G bytes:
 //   out[i] element j  =  in[j] element i.
@@ -176,10 +250,15 @@ RR_HD void copy_thread(const CopyArgs& a, uint32_t block, uint32_t nblocks, uint
     if (block == 0) {
         const uint8_t* s0 = reinterpret_cast<const uint8_t*>(a.src);
         uint8_t* d0 = reinterpret_cast<uint8_t*>(a.dst);
-        if (tid < a.head) d0[tid] = s0[tid];
+        uint32_t b[1];
+        if (tid < a.head) {
+            gload<1>(s0 + tid, b);
+            gstore<1>(d0 + tid, b);
+        }
         if (tid < a.tail) {
             const uint64_t off = a.head + a.nvec * W + tid;
-            d0[off] = s0[off];
+            gload<1>(s0 + off, b);
+            gstore<1>(d0 + off, b);
         }
     }
 }
@@ -359,9 +438,81 @@ RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t
     }
 }
 
+// Walk n items laid out as rows of `per` items with NT threads: item f = tid +
+// s*NT of a thread is (row, col); steps advance incrementally, no division per item.
+struct RowWalk {
+    uint32_t row, col, drow, dcol, per;
+    RR_HD RowWalk(uint32_t tid, uint32_t per_row) : per(per_row) {
+        row = tid / per_row;
+        col = tid - row * per_row;
+        drow = (uint32_t)NT / per_row;
+        dcol = (uint32_t)NT - drow * per_row;
+    }
+    RR_HD void step() {
+        row += drow;
+        col += dcol;
+        if (col >= per) { col -= per; ++row; }
+    }
+};
+
+// Ragged read: each input row (TAv*R bytes at any element alignment) moves as
+// whole 16-byte vectors plus its last (bytes % 16) / U elements one by one, so
+// nothing outside the row is ever touched.
+template <int U>
+RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    constexpr int B = 4;
+    const uint32_t rowbytes = t.TAv * a.R;
+    const uint32_t nfull = rowbytes >> 4;
+    const uint32_t per = nfull + ((rowbytes & 15u) / U);
+    if (per == 0 || t.TBv == 0) return;
+    RowWalk w(tid, per);
+    while (w.row < t.TBv) {
+        uint32_t v[B][4];
+        uint32_t lo[B];
+        uint8_t kind[B];   // 0: none, 1: 16-byte vector, 2: one U-byte element
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            kind[u] = 0;
+            lo[u] = 0;
+            if (w.row < t.TBv) {
+                const uint64_t rowp = t.bin + row_in(a, w.row);
+                if (w.col < nfull) {
+                    const uint32_t x = w.col << 4;
+                    gload16u(reinterpret_cast<const uint8_t*>(rowp + x), v[u]);
+                    lo[u] = lds_pos<1>(a, w.row, x);
+                    kind[u] = 1;
+                } else {
+                    const uint32_t x = (nfull << 4) + (w.col - nfull) * U;
+                    uint32_t e[NWords<U>::value];
+                    gload<U>(reinterpret_cast<const uint8_t*>(rowp + x), e);
+#pragma unroll
+                    for (int q = 0; q < NWords<U>::value; ++q) v[u][q] = e[q];
+                    lo[u] = lds_pos<1>(a, w.row, x);
+                    kind[u] = 2;
+                }
+                w.step();
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (kind[u] == 1) {
+                sstore<16>(lds + lo[u], v[u]);
+            } else if (kind[u] == 2) {
+                uint32_t e[NWords<U>::value];
+#pragma unroll
+                for (int q = 0; q < NWords<U>::value; ++q) e[q] = v[u][q];
+                sstore<U>(lds + lo[u], e);
+            }
+        }
+    }
+}
+
 template <int U, int G>
 RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int B = ReadBatch<U>::value;
+    if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
+        if (a.flags & TF_RAGGED_IN) { read_ragged<U>(a, t, lds, tid); return; }
+    }
     if (a.flags & TF_IN_FLAT) { read_flat<4>(a, t, lds, tid); return; }
     switch (a.win) {
         case 16: read_phase<16, G, B>(a, t, lds, tid); break;
@@ -375,10 +526,120 @@ RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint
 // Write phase: each work item is a GxG micro-tile (G rows of the LDS tile, G
 // elements each), transposed in registers into G output vectors that lie along
 // the output's fastest axis.  Elements of k > 1 units go one unit at a time.
+// Ragged write: each output row (TBv elements of U bytes along the output's
+// fastest axis, any alignment) is written as 16-byte vectors gathered element
+// by element from LDS, plus its last (bytes % 16) / U elements one by one.
+template <int U>
+RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+    constexpr int EPV = 16 / U;   // elements per 16-byte vector
+    const uint32_t rowbytes = t.TBv * U;
+    const uint32_t nfull = rowbytes >> 4;
+    const uint32_t per = nfull + ((rowbytes & 15u) / U);
+    if (per == 0 || t.TAv == 0) return;
+    for (RowWalk w(tid, per); w.row < t.TAv; w.step()) {
+        const uint32_t ia = w.row;
+        uint8_t* rowp = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia));
+        if (w.col < nfull) {
+            const uint32_t ib0 = w.col * EPV;
+            uint32_t o[4];
+            if constexpr (U >= 4) {
+#pragma unroll
+                for (int j = 0; j < EPV; ++j) {
+                    uint32_t e[NWords<U>::value];
+                    sload<U>(lds + lds_pos<1>(a, ib0 + j, ia * U), e);
+#pragma unroll
+                    for (int q = 0; q < U / 4; ++q) o[j * (U / 4) + q] = e[q];
+                }
+            } else {
+                constexpr int PER_WORD = 4 / U;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t acc = 0;
+#pragma unroll
+                    for (int b = 0; b < PER_WORD; ++b) {
+                        uint32_t e[1];
+                        sload<U>(lds + lds_pos<1>(a, ib0 + q * PER_WORD + b, ia * U), e);
+                        acc |= e[0] << (8 * U * b);
+                    }
+                    o[q] = acc;
+                }
+            }
+            gstore16u(rowp + (w.col << 4), o);
+        } else {
+            const uint32_t ib = nfull * EPV + (w.col - nfull);
+            uint32_t e[NWords<U>::value];
+            sload<U>(lds + lds_pos<1>(a, ib, ia * U), e);
+            gstore<U>(rowp + (uint64_t)ib * U, e);
+        }
+    }
+}
+
+// Flat write: the tile's output rows are back to back (row_out(ia) = ia*TB*U),
+// so the whole tile is one contiguous byte range, written as 16-byte vectors
+// whose elements come from LDS across row boundaries, plus an element tail.
+template <int U>
+RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+    constexpr int EPV = 16 / U;
+    const uint32_t nel = t.TAv * a.TB;            // output rows of the tile are full (TBv == TB)
+    const uint32_t nbytes = nel * U;
+    const uint32_t nfull = nbytes >> 4;
+    const uint32_t per = nfull + ((nbytes & 15u) / U);
+    uint8_t* base = reinterpret_cast<uint8_t*>(t.bout);
+    for (uint32_t c = tid; c < per; c += NT) {
+        if (c < nfull) {
+            uint32_t o[4];
+            const uint32_t q0 = c * EPV;
+            if constexpr (U >= 4) {
+#pragma unroll
+                for (int j = 0; j < EPV; ++j) {
+                    const uint32_t q = q0 + j;
+                    const uint32_t ia = mdiv(q, a.mtb);
+                    uint32_t e[NWords<U>::value];
+                    sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+#pragma unroll
+                    for (int k = 0; k < U / 4; ++k) o[j * (U / 4) + k] = e[k];
+                }
+            } else {
+                constexpr int PER_WORD = 4 / U;
+#pragma unroll
+                for (int w4 = 0; w4 < 4; ++w4) {
+                    uint32_t acc = 0;
+#pragma unroll
+                    for (int b = 0; b < PER_WORD; ++b) {
+                        const uint32_t q = q0 + w4 * PER_WORD + b;
+                        const uint32_t ia = mdiv(q, a.mtb);
+                        uint32_t e[1];
+                        sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+                        acc |= e[0] << (8 * U * b);
+                    }
+                    o[w4] = acc;
+                }
+            }
+            gstore16u(base + ((uint64_t)c << 4), o);
+        } else {
+            const uint32_t q = nfull * EPV + (c - nfull);
+            const uint32_t ia = mdiv(q, a.mtb);
+            uint32_t e[NWords<U>::value];
+            sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+            gstore<U>(base + (uint64_t)q * U, e);
+        }
+    }
+}
+
 template <int U, int G>
 RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int W = U * G;
     constexpr int NW = NWords<W>::value;
+    if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
+        if (a.flags & TF_OUT_FLAT) {
+            write_flat<U>(a, t, lds, tid);
+            return;
+        }
+        if (a.flags & TF_RAGGED_OUT) {
+            write_ragged<U>(a, t, lds, tid);
+            return;
+        }
+    }
     if (G > 1 || a.k == 1) {
         for (uint32_t gi = tid; gi < a.nwork; gi += NT) {
             const uint32_t ma = mdiv(gi, a.mnmb);

@@ -38,7 +38,7 @@ TileOptions& tile_override() {
 
 bool tile_override_active() {
     const TileOptions& o = tile_override();
-    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1;
+    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged;
 }
 
 namespace {
@@ -286,6 +286,7 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
     a.win = win;
     a.rch = (uint32_t)(rowbytes / win);
     a.mrch = make_magic(a.rch);
+    a.mtb = make_magic(a.TB);
     if (k == 1) {
         a.nmb = a.TB / G;
         a.nwork = a.nmb * (a.TA / G);
@@ -293,6 +294,17 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
         if (a.nmb == 1 && a.nA == 1 && !(a.flags & TF_OUT_TABLE) && a.soutA[0] == W && W >= 4 &&
             (W * G) % 16 == 0)
             a.flags |= TF_OUT_MERGE;
+        // G == 1 because extents or strides are odd: move rows as 16-byte vectors at any
+        // alignment instead of one element per access.  Short back-to-back output rows
+        // (interlace of a few sets) are written as one contiguous range.
+        if (G == 1 && U < 16) {
+            const bool out_rows_adjacent = a.nA == 1 && !(a.flags & TF_OUT_TABLE) &&
+                                           a.soutA[0] == (uint64_t)a.TB * a.R;
+            const bool tb_whole = a.grid_bO < 0;   // every tile holds all TB output columns
+            if (out_rows_adjacent && tb_whole && (uint64_t)a.TB * a.R < 64) a.flags |= TF_OUT_FLAT;
+            else a.flags |= TF_RAGGED_OUT;
+            if ((a.flags & TF_IN_FLAT) == 0) a.flags |= TF_RAGGED_IN;
+        }
     } else {
         a.nmb = a.TB * k;      // units per output row
         a.nwork = a.nmb * a.TA;
@@ -324,7 +336,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const int k = (int)(R / U);
     const int a1 = r - 1, b1 = pm[r - 1];
     int G = 1;
-    if (k == 1) {
+    if (k == 1 && !opt.force_ragged) {
         G = 16 / U;
         while (G > 1 && ((d[a1] % G) || (d[b1] % G) || addr_align(src) < U * G ||
                          addr_align(dst) < U * G))

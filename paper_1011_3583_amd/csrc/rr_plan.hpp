@@ -69,6 +69,12 @@ enum TileFlags : uint32_t {
     TF_OUT_TABLE = 2u,   // output rows are absolute plane pointers (de-interlace)
     TF_IN_FLAT = 4u,     // input tile is one contiguous range, LDS rows unpadded
     TF_OUT_MERGE = 8u,   // a micro-tile's G output rows are back to back (TB == G)
+    TF_RAGGED_IN = 16u,  // input rows move as 16-byte vectors at any element alignment
+                         // plus a per-element tail
+    TF_OUT_FLAT = 32u,   // output tile is one contiguous range of short rows: written as
+                         // 16-byte vectors gathered across row boundaries
+    TF_RAGGED_OUT = 64u, // output rows written as 16-byte vectors at any alignment,
+                         // gathered element by element from LDS, plus a tail
 };
 
 struct TileArgs {
@@ -103,6 +109,7 @@ struct TileArgs {
     uint32_t nmb;             // write micro-tiles per output row (TB / G); unit path: TB*k
     Magic mnmb;
     uint32_t nwork;           // write work items per tile
+    Magic mtb;                // divide by TB (flat output)
     uint32_t flags;
     uint32_t lds_bytes;
     uint32_t unit;            // U
@@ -115,6 +122,7 @@ struct TileOptions {
     int in_row_bytes = 0;   // 0 = default
     int out_row_bytes = 0;
     int order_out = -1;     // 1: traverse tiles in output order, 0: input order, -1: by unit size
+    int force_ragged = 0;   // plan odd-shape (ragged) tiles even where aligned micro-tiles fit
     int max_lds = 65536;
 };
 

@@ -284,6 +284,7 @@ struct rr_server {
     bool fail_next = false;
     int next_stream = 0;
     int nstreams = 1;
+    uint64_t last_activity = 0;   // last submission or launch (server thread's spin window)
     rr_serve_stats stats{};
     std::thread th;
 
@@ -409,12 +410,20 @@ struct rr_server {
                     }
                 }
                 if (slot < 0) {
-                    // nothing to launch now: sleep until a submission or the next poll
-                    const uint32_t us = inflight.empty() ? std::max<uint32_t>(cfg.tick_us, 1) * 50
-                                                         : std::max<uint32_t>(cfg.tick_us, 1);
-                    cv.wait_for(lk, std::chrono::microseconds(us));
+                    // Nothing to launch now.  While batches are in flight or work arrived
+                    // recently, poll without sleeping (a timed sleep costs tens of
+                    // microseconds of timer slack per poll); otherwise block until a
+                    // submission arrives or tick_us * 50 passes.
+                    const uint64_t tnow = now_ns();
+                    if (!inflight.empty() || tnow - last_activity < 2'000'000ull) {
+                        lk.unlock();
+                        std::this_thread::yield();
+                        continue;
+                    }
+                    cv.wait_for(lk, std::chrono::microseconds(std::max<uint32_t>(cfg.tick_us, 1) * 50));
                     continue;
                 }
+                last_activity = now_ns();
             }
             // build and launch outside the lock
             BatchPlan bp;
@@ -528,6 +537,7 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
         return RR_OK;
     }
     s->pending.push_back(raw);
+    s->last_activity = raw->t_submit;
     s->cv.notify_one();
     return RR_OK;
 }

@@ -158,3 +158,19 @@ def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
     bad.write_text("key 99999 1 0\n")
     with pytest.raises(rr.RRError):
         rr.tune_load(str(bad))
+
+
+def test_no_kernel_uses_scratch():
+    """Every kernel keeps its state in registers and LDS: a private-memory
+    copy of the argument struct or a register spill costs each wave dozens of
+    extra memory instructions per tile."""
+    import json
+    from paper_1011_3583_amd import build as rrbuild
+    path = os.path.join(rrbuild.OBJ, rrbuild.RESOURCES)
+    if not os.path.exists(path):
+        pytest.skip("library not built in-tree")
+    res = json.load(open(path))
+    kernels = {k: v for k, v in res.items() if "k_" in k}
+    assert any("k_tile" in k for k in kernels)
+    used = {k: v["ScratchSize [bytes/lane]"] for k, v in kernels.items() if v["ScratchSize [bytes/lane]"]}
+    assert not used, used

@@ -211,3 +211,21 @@ def test_emu_chunked_entries(chunk):
     for j, out in zip(jobs, outs):
         assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
             (j["dims"], j["perm"], j["esize"])
+
+
+def test_emu_ragged_and_flat_output_paths():
+    """Odd extents (no 16-byte micro-tiles possible) take the ragged 16-byte row paths;
+    interlace of three sets takes the flat output path; both stay bit-exact."""
+    jobs = [_perm_job((1001, 999), (1, 0), 4, 9600), _perm_job((257, 131), (1, 0), 2, 9601),
+            _perm_job((33, 45, 77), (2, 0, 1), 8, 9602), _perm_job((17, 19, 23), (1, 2, 0), 1, 9603),
+            _perm_job((301, 299), (1, 0), 2, 9604, src_off=2, dst_off=6),
+            _perm_job((45, 17, 3, 29), (3, 0, 2, 1), 4, 9605)]
+    res = _check(jobs)
+    flags = [int(s.split("flags=")[1].split()[0]) for s, _ in res]
+    assert all(f & 16 and f & (64 | 32) for f in flags), flags
+    assert any(f & 64 for f in flags) and any(f & 32 for f in flags), flags
+    count = 5000 + 7
+    planes = [rr_synth.random_bytes(9610 + c, count * 4) for c in range(3)]
+    res = _check([dict(op="interlace", n=3, count=count, esize=4, planes=planes),
+                  dict(op="deinterlace", n=3, count=count, esize=4, input=rr_synth.random_bytes(9620, 3 * count * 4))])
+    assert int(res[0][0].split("flags=")[1].split()[0]) & 32

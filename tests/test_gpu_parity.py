@@ -243,3 +243,19 @@ def test_autotuned_plans_stay_exact(rr):
             assert np.array_equal(_download(td, 0, x.size), oracle.permute(x, dims, perm, e))
     finally:
         rr.tune_clear()
+
+
+def test_ragged_and_flat_output_paths(rr):
+    """Odd extents take the ragged 16-byte row paths (unaligned vectors); three-set
+    interlace takes the flat output path."""
+    for i, (dims, perm, e, so, do) in enumerate([((1001, 999), (1, 0), 4, 0, 0), ((257, 131), (1, 0), 2, 0, 0),
+                                                 ((33, 45, 77), (2, 0, 1), 8, 0, 0), ((17, 19, 23), (1, 2, 0), 1, 0, 0),
+                                                 ((301, 299), (1, 0), 2, 2, 6), ((45, 17, 3, 29), (3, 0, 2, 1), 4, 4, 12),
+                                                 ((999, 1001), (1, 0), 1, 1, 3), ((63, 65, 67), (2, 1, 0), 2, 0, 2)]):
+        check_permute(rr, dims, perm, e, 9600 + i, soff=so, doff=do)
+    count = 5000 + 7
+    planes = [rr_synth.random_bytes(9610 + c, count * 4) for c in range(3)]
+    assert np.array_equal(gpu_interlace(rr, planes, 4), oracle.interlace(planes, 4))
+    x = rr_synth.random_bytes(9620, 3 * count * 4)
+    got = gpu_deinterlace(rr, x, 3, 4)
+    assert all(np.array_equal(g, r) for g, r in zip(got, oracle.deinterlace(x, 3, 4)))
