@@ -146,7 +146,10 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     clear_error();
     if (in_row_bytes < 0 || out_row_bytes < 0 || in_row_bytes > 4096 || out_row_bytes > 4096)
         return fail(RR_ERR_INVALID_ARG, "row bytes must be 0..4096");
+    const int max_g = (flags >> 8) & 0xff;
+    if (!valid_max_g(max_g)) return fail(RR_ERR_INVALID_ARG, "micro-tile cap must be 0, 1, 2, 4, 8 or 16");
     TileOptions& o = tile_override();
+    o.max_g = max_g;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
@@ -163,11 +166,16 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     if (best_us) *best_us = 0;
     if (default_us) *default_us = 0;
     if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
-    struct Cand { int in_rb, out_rb, order; };
-    static const Cand cands[] = {{0, 0, -1}, {0, 0, 1}, {0, 0, 0}, {128, 256, -1}, {256, 128, -1},
-                                 {256, 512, -1}, {512, 256, -1}, {512, 512, -1}, {1024, 256, -1},
-                                 {256, 1024, -1}, {1024, 1024, -1}, {2048, 512, -1}, {512, 2048, -1},
-                                 {256, 512, 1}, {512, 256, 1}, {256, 128, 1}, {128, 512, 0}};
+    // row targets, traversal order, micro-tile cap; candidates that plan to the
+    // same launch as an earlier one are skipped
+    struct Cand { int in_rb, out_rb, order, max_g; };
+    static const Cand cands[] = {
+        {0, 0, -1, 0},      {0, 0, 1, 0},       {0, 0, 0, 0},       {128, 256, -1, 0},  {256, 128, -1, 0},
+        {256, 512, -1, 0},  {512, 256, -1, 0},  {512, 512, -1, 0},  {1024, 256, -1, 0}, {256, 1024, -1, 0},
+        {1024, 1024, -1, 0}, {2048, 512, -1, 0}, {512, 2048, -1, 0}, {256, 512, 1, 0},  {512, 256, 1, 0},
+        {256, 128, 1, 0},   {128, 512, 0, 0},
+        {0, 0, -1, 8},      {0, 0, 1, 8},       {128, 128, -1, 8},  {128, 128, 1, 8},   {256, 128, -1, 8},
+        {0, 0, -1, 4},      {0, 0, 1, 4},       {128, 128, -1, 4},  {64, 128, 1, 4},    {128, 64, 1, 4}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
@@ -180,6 +188,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.in_row_bytes = cd.in_rb;
         o.out_row_bytes = cd.out_rb;
         o.order_out = cd.order;
+        o.max_g = cd.max_g;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;

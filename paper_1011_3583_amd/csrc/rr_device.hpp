@@ -41,14 +41,8 @@ typedef uint32_t rr_u32x2 __attribute__((ext_vector_type(2)));
 // Global memory is streamed: every byte is read once and written once, so both
 // sides use non-temporal accesses (they keep the streams from displacing each
 // other in L2 and the Infinity Cache).  LDS accesses are ordinary.
-#ifndef RR_RB_U1
-#define RR_RB_U1 16
-#endif
-#ifndef RR_RB_U2
-#define RR_RB_U2 8
-#endif
-#ifndef RR_RB_U4
-#define RR_RB_U4 4
+#ifndef RR_READ_BATCH
+#define RR_READ_BATCH 4
 #endif
 #ifndef RR_NT_LOAD
 #define RR_NT_LOAD 1
@@ -379,12 +373,10 @@ RR_HD uint32_t lds_pos(const TileArgs& a, uint32_t ib, uint32_t x) {
     return ib * a.pitch + (cc << 4) + (x & 15u);
 }
 
-// Loads each thread keeps in flight before writing any of them to LDS.  Tiles
-// are planned to need 16/U loads per thread for U = 1, 2 (64 and 32 KiB tiles,
-// where LDS already limits occupancy) and 4 for U >= 4 (16 KiB tiles, where the
-// register budget decides how many waves fit).
-template <int U>
-struct ReadBatch { static constexpr int value = U == 1 ? RR_RB_U1 : (U == 2 ? RR_RB_U2 : RR_RB_U4); };
+// Loads each thread keeps in flight before writing any of them to LDS.  Default
+// tiles are 16 KiB, i.e. four 16-byte vectors per thread: one batch, and few
+// enough registers that six waves fit per SIMD.  Larger tiles loop.
+constexpr int READ_BATCH = RR_READ_BATCH;
 
 // Read phase: rows of the tile (contiguous along the input's fastest axes) are
 // loaded with WIN-byte vectors and parked in LDS.
@@ -460,7 +452,7 @@ struct RowWalk {
 // nothing outside the row is ever touched.
 template <int U>
 RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
-    constexpr int B = 4;
+    constexpr int B = READ_BATCH;
     const uint32_t rowbytes = t.TAv * a.R;
     const uint32_t nfull = rowbytes >> 4;
     const uint32_t per = nfull + ((rowbytes & 15u) / U);
@@ -509,17 +501,17 @@ RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32
 
 template <int U, int G>
 RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
-    constexpr int B = ReadBatch<U>::value;
+    constexpr int B = READ_BATCH;
     if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
         if (a.flags & TF_RAGGED_IN) { read_ragged<U>(a, t, lds, tid); return; }
     }
-    if (a.flags & TF_IN_FLAT) { read_flat<4>(a, t, lds, tid); return; }
+    if (a.flags & TF_IN_FLAT) { read_flat<B>(a, t, lds, tid); return; }
     switch (a.win) {
         case 16: read_phase<16, G, B>(a, t, lds, tid); break;
         case 8: read_phase<8, G, B>(a, t, lds, tid); break;
-        case 4: read_phase<4, G, 4>(a, t, lds, tid); break;
-        case 2: read_phase<2, G, 4>(a, t, lds, tid); break;
-        default: read_phase<1, G, 4>(a, t, lds, tid); break;
+        case 4: read_phase<4, G, B>(a, t, lds, tid); break;
+        case 2: read_phase<2, G, B>(a, t, lds, tid); break;
+        default: read_phase<1, G, B>(a, t, lds, tid); break;
     }
 }
 

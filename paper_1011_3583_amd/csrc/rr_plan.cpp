@@ -38,7 +38,8 @@ TileOptions& tile_override() {
 
 bool tile_override_active() {
     const TileOptions& o = tile_override();
-    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged;
+    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
+           o.max_g != 0;
 }
 
 namespace {
@@ -83,18 +84,28 @@ std::string tune_dump() {
     std::ostringstream o;
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
-          << kv.second.order_out << "\n";
+          << kv.second.order_out << " " << kv.second.max_g << "\n";
     return o.str();
 }
 
+bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
+
+// One entry per line: key in_row_bytes out_row_bytes order_out [max_g]
 int tune_parse(const std::string& text) {
-    std::istringstream in(text);
-    std::string key;
+    std::istringstream lines(text);
+    std::string line;
     int n = 0;
-    TileOptions o;
-    while (in >> key >> o.in_row_bytes >> o.out_row_bytes >> o.order_out) {
+    while (std::getline(lines, line)) {
+        std::istringstream in(line);
+        std::string key;
+        if (!(in >> key)) continue;   // blank line
+        TileOptions o;
+        if (!(in >> o.in_row_bytes >> o.out_row_bytes >> o.order_out)) return -1;
+        if (!(in >> o.max_g)) o.max_g = 0;
+        std::string extra;
+        if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
-            o.order_out < -1 || o.order_out > 1)
+            o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g))
             return -1;
         tune_store(key, o);
         ++n;
@@ -243,8 +254,8 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
 
 static int default_row_bytes(int U, bool in_side) {
     switch (U) {
-        case 1: return 256;
-        case 2: return 256;
+        case 1: return 128;
+        case 2: return in_side ? 256 : 128;
         case 4: return 256;
         case 8: return in_side ? 256 : 512;
         default: return 512;
@@ -337,7 +348,10 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const int a1 = r - 1, b1 = pm[r - 1];
     int G = 1;
     if (k == 1 && !opt.force_ragged) {
-        G = 16 / U;
+        // 1- and 2-byte elements default to 8-byte micro-tile rows: 16 KiB tiles
+        // then still give every thread a micro-tile, and the transpose stays small
+        // enough in registers for six waves per SIMD.
+        G = opt.max_g > 0 ? std::min(16 / U, opt.max_g) : (U <= 2 ? 8 / U : 16 / U);
         while (G > 1 && ((d[a1] % G) || (d[b1] % G) || addr_align(src) < U * G ||
                          addr_align(dst) < U * G))
             G >>= 1;

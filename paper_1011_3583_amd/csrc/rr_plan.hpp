@@ -123,8 +123,11 @@ struct TileOptions {
     int out_row_bytes = 0;
     int order_out = -1;     // 1: traverse tiles in output order, 0: input order, -1: by unit size
     int force_ragged = 0;   // plan odd-shape (ragged) tiles even where aligned micro-tiles fit
+    int max_g = 0;          // cap on the micro-tile edge G (0 = none)
     int max_lds = 65536;
 };
+
+bool valid_max_g(int g);   // 0 or a power of two up to 16
 
 // Process-wide override (autotuner hook).
 TileOptions& tile_override();

@@ -123,7 +123,12 @@ def test_canonical_form_is_equivalent_to_the_original():
 
 
 def test_plan_uses_widest_vectors_on_aligned_buffers():
+    # 1-byte elements: 16-byte row reads, 8x8 micro-tiles (8-byte stores) by default
     d = rr.plan_describe((16384, 16384), (1, 0), 1, dst=1 << 20, src=1 << 30)
+    assert (d["unit"], d["g"], d["win"]) == ("1", "8", "16")
+    rr.set_tile_override(max_g=16)
+    d = rr.plan_describe((16384, 16384), (1, 0), 1, dst=1 << 20, src=1 << 30)
+    rr.set_tile_override()
     assert (d["unit"], d["g"], d["win"]) == ("1", "16", "16")
     d = rr.plan_describe((1024, 1024), (1, 0), 4, dst=1 << 20, src=1 << 30)
     assert (d["unit"], d["g"], d["win"]) == ("4", "4", "16")
@@ -158,6 +163,34 @@ def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
     bad.write_text("key 99999 1 0\n")
     with pytest.raises(rr.RRError):
         rr.tune_load(str(bad))
+
+
+def test_micro_tile_cap_from_override_and_cache(tmp_path):
+    """The micro-tile edge G can be capped by the override and by a cached entry."""
+    rr.tune_clear()
+    dims, perm, e = (4096, 4096), (1, 0), 1
+    assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["g"] == "8"
+    for g in (16, 8, 4, 2, 1):
+        rr.set_tile_override(max_g=g)
+        assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["g"] == str(g)
+    rr.set_tile_override()
+    with pytest.raises(rr.RRError):
+        rr.set_tile_override(max_g=3)
+    rr.set_tile_override()
+    path = tmp_path / "tune.txt"
+    path.write_text("r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8\n\n")
+    rr.tune_load(str(path))
+    d = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    assert (d["g"], d["TA"], d["TB"]) == ("8", "128", "128")
+    out = tmp_path / "saved.txt"
+    rr.tune_save(str(out))
+    assert "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8" in out.read_text()
+    rr.tune_clear()
+    for bad in ("k 0 0 0 3\n", "k 0 0 0 8 9\n", "k 0 0\n"):
+        (tmp_path / "bad.txt").write_text(bad)
+        with pytest.raises(rr.RRError):
+            rr.tune_load(str(tmp_path / "bad.txt"))
+    rr.tune_clear()
 
 
 def test_no_kernel_uses_scratch():

@@ -100,6 +100,34 @@ def test_emu_tile_overrides_and_orders():
     _check(jobs)
 
 
+@pytest.mark.parametrize("max_g", [16, 8, 4, 2, 1])
+def test_emu_micro_tile_caps(max_g):
+    """Every micro-tile edge the planner or tuner can choose, for every unit size,
+    with tiles that end part-way through a micro-tile row."""
+    jobs = []
+    k = 0
+    for dims, perm, e in [((96, 80), (1, 0), 1), ((64, 48, 40), (2, 0, 1), 2), ((48, 40, 32), (1, 2, 0), 4),
+                          ((32, 24, 16), (2, 1, 0), 8), ((96, 16, 80), (2, 1, 0), 1), ((16, 16, 16, 16), (3, 1, 0, 2), 2)]:
+        for rb in ((0, 0), (128, 128), (512, 64)):
+            k += 1
+            jobs.append(_perm_job(dims, perm, e, 7000 + 31 * max_g + k, in_rb=rb[0], out_rb=rb[1], max_g=max_g))
+    res = _check(jobs)
+    gs = {dict(t.split("=", 1) for t in st.split()[1:] if "=" in t)["g"] for st, _ in res}
+    assert str(max_g) in gs
+
+
+def test_emu_forced_ragged_on_aligned_shapes():
+    """The ragged row paths give the oracle's bytes on shapes that would take micro-tiles."""
+    jobs = []
+    for i, (dims, perm, e) in enumerate([((96, 80), (1, 0), 1), ((64, 48, 40), (2, 0, 1), 2),
+                                         ((48, 40, 32), (1, 2, 0), 4), ((32, 24, 16), (2, 1, 0), 8)]):
+        jobs.append(_perm_job(dims, perm, e, 7500 + i, ragged=True))
+    res = _check(jobs)
+    for st, _ in res:
+        flags = int(dict(t.split("=", 1) for t in st.split()[1:] if "=" in t)["flags"])
+        assert flags & 16 and flags & (32 | 64), st
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),

@@ -259,3 +259,28 @@ def test_ragged_and_flat_output_paths(rr):
     x = rr_synth.random_bytes(9620, 3 * count * 4)
     got = gpu_deinterlace(rr, x, 3, 4)
     assert all(np.array_equal(g, r) for g, r in zip(got, oracle.deinterlace(x, 3, 4)))
+
+
+@pytest.mark.parametrize("max_g", [16, 8, 4, 2, 1])
+def test_micro_tile_caps(rr, max_g):
+    """Every micro-tile edge the planner or tuner can choose, at each unit size,
+    with several tiles per launch and partial last tiles."""
+    rr.set_tile_override(max_g=max_g)
+    try:
+        for i, (dims, perm, e) in enumerate([((1024, 1040), (1, 0), 1), ((320, 272, 48), (2, 0, 1), 2),
+                                             ((96, 80, 160), (1, 2, 0), 4), ((64, 48, 112), (2, 1, 0), 8),
+                                             ((48, 16, 32, 80), (3, 1, 0, 2), 1)]):
+            check_permute(rr, dims, perm, e, 9700 + 10 * max_g + i)
+    finally:
+        rr.set_tile_override()
+
+
+def test_forced_ragged_on_aligned_shapes(rr):
+    """The ragged row paths give the oracle's bytes where micro-tiles would be chosen."""
+    rr.set_tile_override(force_ragged=True)
+    try:
+        for i, (dims, perm, e) in enumerate([((1024, 1040), (1, 0), 1), ((320, 272, 48), (2, 0, 1), 2),
+                                             ((96, 80, 160), (1, 2, 0), 4), ((64, 48, 112), (2, 1, 0), 8)]):
+            check_permute(rr, dims, perm, e, 9800 + i)
+    finally:
+        rr.set_tile_override()
