@@ -249,13 +249,16 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * input and output sides of the tiled kernel (0 = built-in choice, max 4096),
  * the order in which tiles are assigned to workgroups (flags:
  * RR_TILE_ORDER_OUT / RR_TILE_ORDER_IN, neither = built-in choice by element
- * size) and a cap on the register micro-tile edge G (RR_TILE_MAX_G(g), g one of
- * 1, 2, 4, 8, 16; 0 = no cap).  Process-wide; affects plans made after the
- * call.  RR_ERR_INVALID_ARG for row targets outside 0..4096 or a bad cap. */
+ * size), a cap on the register micro-tile edge G (RR_TILE_MAX_G(g), g one of
+ * 1, 2, 4, 8, 16; 0 = no cap) and the LDS size tiles are shrunk to
+ * (RR_TILE_KIB(k), 4..64 KiB; 0 = 16).  Process-wide; affects plans made after
+ * the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a bad cap or a
+ * bad tile size. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
 #define RR_TILE_MAX_G(g) ((g) << 8)
+#define RR_TILE_KIB(k) ((k) << 16)
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
 
 /* -------------------------------------------------------------------------

@@ -148,8 +148,11 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
         return fail(RR_ERR_INVALID_ARG, "row bytes must be 0..4096");
     const int max_g = (flags >> 8) & 0xff;
     if (!valid_max_g(max_g)) return fail(RR_ERR_INVALID_ARG, "micro-tile cap must be 0, 1, 2, 4, 8 or 16");
+    const int tile_kib = (flags >> 16) & 0xff;
+    if (!valid_tile_kib(tile_kib)) return fail(RR_ERR_INVALID_ARG, "tile size must be 0 or 4..64 KiB");
     TileOptions& o = tile_override();
     o.max_g = max_g;
+    o.tile_kib = tile_kib;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
@@ -168,14 +171,19 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
     // row targets, traversal order, micro-tile cap; candidates that plan to the
     // same launch as an earlier one are skipped
-    struct Cand { int in_rb, out_rb, order, max_g; };
+    // row targets, traversal order, micro-tile cap, tile size (KiB); candidates
+    // that plan to the same launch as an earlier one are skipped
+    struct Cand { int in_rb, out_rb, order, max_g, kib; };
     static const Cand cands[] = {
-        {0, 0, -1, 0},      {0, 0, 1, 0},       {0, 0, 0, 0},       {128, 256, -1, 0},  {256, 128, -1, 0},
-        {256, 512, -1, 0},  {512, 256, -1, 0},  {512, 512, -1, 0},  {1024, 256, -1, 0}, {256, 1024, -1, 0},
-        {1024, 1024, -1, 0}, {2048, 512, -1, 0}, {512, 2048, -1, 0}, {256, 512, 1, 0},  {512, 256, 1, 0},
-        {256, 128, 1, 0},   {128, 512, 0, 0},
-        {0, 0, -1, 8},      {0, 0, 1, 8},       {128, 128, -1, 8},  {128, 128, 1, 8},   {256, 128, -1, 8},
-        {0, 0, -1, 4},      {0, 0, 1, 4},       {128, 128, -1, 4},  {64, 128, 1, 4},    {128, 64, 1, 4}};
+        {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
+        {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
+        {512, 256, -1, 0, 64}, {512, 512, -1, 0, 64},  {1024, 256, -1, 0, 64}, {256, 1024, -1, 0, 64},
+        {1024, 1024, -1, 0, 64}, {2048, 512, -1, 0, 64}, {512, 2048, -1, 0, 64}, {256, 512, 1, 0, 64},
+        {512, 256, 1, 0, 64},  {256, 128, 1, 0, 64},   {128, 512, 0, 0, 64},   {512, 512, 1, 0, 32},
+        {0, 0, -1, 16, 64},    {0, 0, 1, 16, 64},      {512, 512, -1, 16, 64}, {0, 0, -1, 8, 0},
+        {0, 0, 1, 8, 0},       {128, 128, -1, 8, 0},   {128, 128, 1, 8, 0},    {256, 128, -1, 8, 0},
+        {0, 0, -1, 4, 0},      {0, 0, 1, 4, 0},        {128, 128, -1, 4, 0},   {64, 128, 1, 4, 0},
+        {128, 64, 1, 4, 0}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
@@ -189,6 +197,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.out_row_bytes = cd.out_rb;
         o.order_out = cd.order;
         o.max_g = cd.max_g;
+        o.tile_kib = cd.kib;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <tuple>
 
 #include "rr_batch.hpp"
 
@@ -89,8 +90,11 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
     out->groups.clear();
     out->bytes = 0;
     out->njobs = 0;
-    // group by kernel family, keeping entry order within a group
-    std::map<std::pair<int, int>, std::vector<size_t>> fam;
+    // group by kernel family and, for tiles, by LDS size class (a group launches
+    // with its largest tile's LDS, which sets how many workgroups share a CU),
+    // keeping entry order within a group
+    using Key = std::tuple<int, int, int>;
+    std::map<Key, std::vector<size_t>> fam;
     for (size_t i = 0; i < entries.size(); ++i) {
         const Plan& p = *entries[i].plan;
         if (p.kind == K_EMPTY || entries[i].nblocks == 0) continue;
@@ -98,7 +102,9 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
         if (p.kind == K_COPY) variant = (int)p.copy.wbytes;
         else if (p.kind == K_RUN) variant = (int)p.run.wbytes;
         else variant = (int)(p.tile.unit * 100 + p.tile.g);
-        fam[{(int)p.kind, variant}].push_back(i);
+        int lds_class = 0;
+        if (p.kind == K_TILE) lds_class = p.tile.lds_bytes <= 16384 ? 0 : p.tile.lds_bytes <= 32768 ? 1 : 2;
+        fam[Key{(int)p.kind, variant, lds_class}].push_back(i);
         out->bytes += entries[i].bytes;
         out->njobs++;
     }
@@ -106,8 +112,8 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
     for (auto& kv : fam) {
         BatchGroup g;
         std::memset(&g, 0, sizeof g);
-        g.kind = kv.first.first;
-        g.variant = kv.first.second;
+        g.kind = std::get<0>(kv.first);
+        g.variant = std::get<1>(kv.first);
         g.njobs = (uint32_t)kv.second.size();
         size_t asz = g.kind == K_COPY ? sizeof(CopyArgs) : g.kind == K_RUN ? sizeof(RunArgs) : sizeof(TileArgs);
         g.args_off = off;
@@ -119,8 +125,10 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
         out->groups.push_back(g);
     }
     out->table.assign(off, 0);
-    for (BatchGroup& g : out->groups) {
-        const std::vector<size_t>& members = fam[{g.kind, g.variant}];
+    size_t gi = 0;
+    for (auto& kv : fam) {
+        BatchGroup& g = out->groups[gi++];
+        const std::vector<size_t>& members = kv.second;
         uint32_t* prefix = reinterpret_cast<uint32_t*>(out->table.data() + g.prefix_off);
         EntryRange* ranges = reinterpret_cast<EntryRange*>(out->table.data() + g.range_off);
         uint8_t* argp = out->table.data() + g.args_off;

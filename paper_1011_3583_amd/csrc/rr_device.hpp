@@ -298,6 +298,7 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
 struct TileCtx {
     uint64_t bin, bout;   // byte bases of the tile (absolute unless in table mode)
     uint32_t TAv, TBv;    // valid row length / row count of this tile
+    uint32_t TCv;         // stacked sub-tiles in this tile (1 unless stacked)
 };
 
 RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
@@ -306,6 +307,7 @@ RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
     t.bout = a.dst;
     t.TAv = a.TA;
     t.TBv = a.TB;
+    t.TCv = a.cO_t;
     uint32_t rem = tile;
 #pragma unroll
     for (int g = MAXR - 1; g >= 0; --g) {
@@ -317,6 +319,7 @@ RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
             t.bout += (uint64_t)c * a.gsout[g];
             if (g == a.grid_aO) t.TAv = a.TAinner * umin(a.aO_t, a.aO_len - c * a.aO_t);
             if (g == a.grid_bO) t.TBv = a.TBinner * umin(a.bO_t, a.bO_len - c * a.bO_t);
+            if (g == a.grid_cO) t.TCv = umin(a.cO_t, a.cO_len - c * a.cO_t);
         }
     }
     return t;
@@ -447,18 +450,20 @@ struct RowWalk {
     }
 };
 
-// Ragged read: each input row (TAv*R bytes at any element alignment) moves as
-// whole 16-byte vectors plus its last (bytes % 16) / U elements one by one, so
-// nothing outside the row is ever touched.
-template <int U>
-RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+// Copy nrows rows of rowbytes bytes (a multiple of U, any alignment) from
+// global memory into LDS: whole 16-byte vectors plus each row's last
+// (rowbytes % 16) / U elements one by one, so nothing outside a row is touched.
+//   src_row(r)      -> global byte address of row r
+//   lds_at(r, x)    -> LDS byte offset of byte x of row r
+template <int U, class SrcRow, class LdsAt>
+RR_HD void read_rows(uint32_t nrows, uint32_t rowbytes, SrcRow src_row, LdsAt lds_at, uint8_t* lds,
+                     uint32_t tid) {
     constexpr int B = READ_BATCH;
-    const uint32_t rowbytes = t.TAv * a.R;
     const uint32_t nfull = rowbytes >> 4;
     const uint32_t per = nfull + ((rowbytes & 15u) / U);
-    if (per == 0 || t.TBv == 0) return;
+    if (per == 0 || nrows == 0) return;
     RowWalk w(tid, per);
-    while (w.row < t.TBv) {
+    while (w.row < nrows) {
         uint32_t v[B][4];
         uint32_t lo[B];
         uint8_t kind[B];   // 0: none, 1: 16-byte vector, 2: one U-byte element
@@ -466,12 +471,12 @@ RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32
         for (int u = 0; u < B; ++u) {
             kind[u] = 0;
             lo[u] = 0;
-            if (w.row < t.TBv) {
-                const uint64_t rowp = t.bin + row_in(a, w.row);
+            if (w.row < nrows) {
+                const uint64_t rowp = src_row(w.row);
                 if (w.col < nfull) {
                     const uint32_t x = w.col << 4;
                     gload16u(reinterpret_cast<const uint8_t*>(rowp + x), v[u]);
-                    lo[u] = lds_pos<1>(a, w.row, x);
+                    lo[u] = lds_at(w.row, x);
                     kind[u] = 1;
                 } else {
                     const uint32_t x = (nfull << 4) + (w.col - nfull) * U;
@@ -479,7 +484,7 @@ RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32
                     gload<U>(reinterpret_cast<const uint8_t*>(rowp + x), e);
 #pragma unroll
                     for (int q = 0; q < NWords<U>::value; ++q) v[u][q] = e[q];
-                    lo[u] = lds_pos<1>(a, w.row, x);
+                    lo[u] = lds_at(w.row, x);
                     kind[u] = 2;
                 }
                 w.step();
@@ -499,10 +504,34 @@ RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32
     }
 }
 
+// Ragged read: each input row (TAv*R bytes at any element alignment) of the
+// tile, into its padded LDS row.
+template <int U>
+RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    read_rows<U>(
+        t.TBv, t.TAv * a.R, [&](uint32_t r) { return t.bin + row_in(a, r); },
+        [&](uint32_t r, uint32_t x) { return lds_pos<1>(a, r, x); }, lds, tid);
+}
+
+// Stacked read: TCv sub-tiles of msub input bytes each; when they are back to
+// back in the input (sinC == msub) the whole range is one row.
+template <int U>
+RR_HD void read_stack(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    if (a.sinC == a.msub)
+        read_rows<U>(
+            1, t.TCv * a.msub, [&](uint32_t) { return t.bin; }, [&](uint32_t, uint32_t x) { return x; }, lds,
+            tid);
+    else
+        read_rows<U>(
+            t.TCv, a.msub, [&](uint32_t r) { return t.bin + (uint64_t)r * a.sinC; },
+            [&](uint32_t r, uint32_t x) { return r * a.msubp + x; }, lds, tid);
+}
+
 template <int U, int G>
 RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int B = READ_BATCH;
     if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
+        if (a.flags & TF_STACK) { read_stack<U>(a, t, lds, tid); return; }
         if (a.flags & TF_RAGGED_IN) { read_ragged<U>(a, t, lds, tid); return; }
     }
     if (a.flags & TF_IN_FLAT) { read_flat<B>(a, t, lds, tid); return; }
@@ -618,11 +647,79 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
     }
 }
 
+// Stacked write: the output of sub-tile c is TA rows of TB elements back to
+// back (msub bytes at c * soutC); when the sub-tiles are back to back too
+// (soutC == msub) the whole tile is one row.  Element (c, ia, ib) of the output
+// is element (c, ib, ia) of the input, at LDS c * msubp + (ib * TA + ia) * U.
+// Each 16-byte output vector gathers its elements from LDS, walking (c, ia, ib)
+// incrementally from one division per vector.
+template <int U>
+RR_HD void write_stack(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+    constexpr int EPV = 16 / U;
+    const bool one = a.soutC == a.msub;
+    const uint32_t nrows = one ? 1u : t.TCv;
+    const uint32_t rowbytes = one ? t.TCv * a.msub : a.msub;
+    const uint32_t row_el = rowbytes / U;
+    const uint32_t nfull = rowbytes >> 4;
+    const uint32_t per = nfull + ((rowbytes & 15u) / U);
+    for (RowWalk w(tid, per); w.row < nrows; w.step()) {
+        uint8_t* rowp = reinterpret_cast<uint8_t*>(t.bout + (uint64_t)w.row * a.soutC);
+        const bool vec = w.col < nfull;
+        const uint32_t q0 = vec ? w.col * EPV : nfull * EPV + (w.col - nfull);
+        // element q of the whole tile -> (c, ia, ib)
+        const uint32_t qg = w.row * row_el + q0;
+        uint32_t c = mdiv(qg, a.msubel);
+        const uint32_t rem = qg - c * (a.TA * a.TB);
+        uint32_t ia = mdiv(rem, a.mtb);
+        uint32_t ib = rem - ia * a.TB;
+        auto at = [&]() { return lds + c * a.msubp + (ib * a.TA + ia) * U; };
+        auto next = [&]() {
+            if (++ib == a.TB) { ib = 0; if (++ia == a.TA) { ia = 0; ++c; } }
+        };
+        if (vec) {
+            uint32_t o[4];
+            if constexpr (U >= 4) {
+#pragma unroll
+                for (int j = 0; j < EPV; ++j) {
+                    uint32_t e[NWords<U>::value];
+                    sload<U>(at(), e);
+#pragma unroll
+                    for (int q = 0; q < U / 4; ++q) o[j * (U / 4) + q] = e[q];
+                    next();
+                }
+            } else {
+                constexpr int PER_WORD = 4 / U;
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    uint32_t acc = 0;
+#pragma unroll
+                    for (int b = 0; b < PER_WORD; ++b) {
+                        uint32_t e[1];
+                        sload<U>(at(), e);
+                        acc |= e[0] << (8 * U * b);
+                        next();
+                    }
+                    o[q] = acc;
+                }
+            }
+            gstore16u(rowp + (w.col << 4), o);
+        } else {
+            uint32_t e[NWords<U>::value];
+            sload<U>(at(), e);
+            gstore<U>(rowp + (uint64_t)q0 * U, e);
+        }
+    }
+}
+
 template <int U, int G>
 RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int W = U * G;
     constexpr int NW = NWords<W>::value;
     if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
+        if (a.flags & TF_STACK) {
+            write_stack<U>(a, t, lds, tid);
+            return;
+        }
         if (a.flags & TF_OUT_FLAT) {
             write_flat<U>(a, t, lds, tid);
             return;

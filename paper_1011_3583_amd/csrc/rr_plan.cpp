@@ -39,7 +39,7 @@ TileOptions& tile_override() {
 bool tile_override_active() {
     const TileOptions& o = tile_override();
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0;
+           o.max_g != 0 || o.tile_kib != 0;
 }
 
 namespace {
@@ -84,13 +84,14 @@ std::string tune_dump() {
     std::ostringstream o;
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
-          << kv.second.order_out << " " << kv.second.max_g << "\n";
+          << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << "\n";
     return o.str();
 }
 
 bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
+bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 
-// One entry per line: key in_row_bytes out_row_bytes order_out [max_g]
+// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib]]
 int tune_parse(const std::string& text) {
     std::istringstream lines(text);
     std::string line;
@@ -102,10 +103,11 @@ int tune_parse(const std::string& text) {
         TileOptions o;
         if (!(in >> o.in_row_bytes >> o.out_row_bytes >> o.order_out)) return -1;
         if (!(in >> o.max_g)) o.max_g = 0;
+        else if (!(in >> o.tile_kib)) o.tile_kib = 0;
         std::string extra;
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
-            o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g))
+            o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib))
             return -1;
         tune_store(key, o);
         ++n;
@@ -273,6 +275,19 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
                              std::string* why) {
     a.unit = U; a.g = G; a.k = k;
     a.mk = make_magic(k);
+    if (a.flags & TF_STACK) {
+        a.pitch = a.TA * a.R;
+        a.nch16 = 0xffffffffu;
+        a.rotmask = 0;
+        a.lds_bytes = (a.cO_t * a.msubp + 15) / 16 * 16;
+        if (a.lds_bytes > (uint32_t)opt.max_lds) { *why = "tile does not fit LDS"; return RR_ERR_UNSUPPORTED; }
+        a.win = 16;
+        a.mtb = make_magic(a.TB);
+        a.msubel = make_magic(a.TA * a.TB);
+        a.nmb = a.TB;
+        a.mnmb = make_magic(a.nmb);
+        return RR_OK;
+    }
     const uint64_t rowbytes = (uint64_t)a.TA * a.R;
     const bool flat = flat_ok && (rowbytes % 16 != 0 || rowbytes < 64) && (flat_base % 16) == 0 &&
                       ((uint64_t)a.TB * rowbytes) % 16 == 0 && (total_rows * rowbytes) % 16 == 0;
@@ -358,21 +373,43 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     }
     const int in_rb = opt.in_row_bytes > 0 ? opt.in_row_bytes : default_row_bytes(U, true);
     const int out_rb = opt.out_row_bytes > 0 ? opt.out_row_bytes : default_row_bytes(U, false);
-    const int64_t targetA = std::max<int64_t>(G, cdiv(in_rb, R));
-    const int64_t targetB = std::max<int64_t>(G, cdiv(out_rb, R));
+    int64_t targetA = std::max<int64_t>(G, cdiv(in_rb, R));
+    int64_t targetB = std::max<int64_t>(G, cdiv(out_rb, R));
+    const int64_t soft_bytes = (int64_t)(opt.tile_kib > 0 ? opt.tile_kib : DEFAULT_TILE_KIB) * 1024;
+    const int64_t tile_el = std::max<int64_t>(1, soft_bytes / R);
 
+    // A: trailing input axes, B: trailing output axes; each grows by whole
+    // axes (the slowest one partially) until its row target is met or the next
+    // axis belongs to the other side.
     int A[MAXS], B[MAXS];
     int nA = 0, nB = 0;
     bool inA[MAXR] = {}, inB[MAXR] = {};
     A[nA++] = a1; inA[a1] = true;
-    int64_t prodA = d[a1];
-    for (int nx = r - 2; prodA < targetA && nx >= 0 && nx != b1 && nA < MAXS; --nx) {
-        A[nA++] = nx; inA[nx] = true; prodA *= d[nx];
-    }
     B[nB++] = b1; inB[b1] = true;
-    int64_t prodB = d[b1];
-    for (int jn = r - 2; prodB < targetB && jn >= 0 && !inA[pm[jn]] && nB < MAXS; --jn) {
-        B[nB++] = pm[jn]; inB[pm[jn]] = true; prodB *= d[pm[jn]];
+    int64_t prodA = d[a1], prodB = d[b1];
+    int nxA = r - 2, nxB = r - 2;
+    auto growA = [&]() {
+        for (; prodA < targetA && nxA >= 0 && !inB[nxA] && nA < MAXS; --nxA) {
+            A[nA++] = nxA; inA[nxA] = true; prodA *= d[nxA];
+        }
+    };
+    auto growB = [&]() {
+        for (; prodB < targetB && nxB >= 0 && !inA[pm[nxB]] && nB < MAXS; --nxB) {
+            B[nB++] = pm[nxB]; inB[pm[nxB]] = true; prodB *= d[pm[nxB]];
+        }
+    };
+    growA();
+    growB();
+    // A side that ran out of axes short of its target leaves a thin tile (few
+    // elements per input row): the other side then grows to keep about
+    // soft_bytes per tile, so short rows come in long runs of the long side.
+    const bool shortA = prodA < targetA, shortB = prodB < targetB;
+    if (shortA && !shortB) {
+        targetB = std::max(targetB, cdiv(tile_el, prodA));
+        growB();
+    } else if (shortB && !shortA) {
+        targetA = std::max(targetA, cdiv(tile_el, prodB));
+        growA();
     }
     int64_t t[MAXR];
     for (int i = 0; i < r; ++i) t[i] = 1;
@@ -396,18 +433,45 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         const int x = pm[r - 1 - nB];
         if (x == aO) t[aO] = d[aO];
     }
-    // shrink until the tile fits in LDS
+    // shrink toward the soft tile size (an LDS row is padded to 16 bytes)
+    const int64_t soft_lds = std::min<int64_t>(soft_bytes, opt.max_lds);
     for (int guard = 0; guard < 64; ++guard) {
         int64_t TA = innerA * t[aO], TB = innerB * t[bO];
         int64_t bytes = TB * ((TA * R + 15) / 16 * 16);
-        if (bytes <= opt.max_lds) break;
+        if (bytes <= soft_lds) break;
         int64_t stepA = nA == 1 ? G : 1, stepB = nB == 1 ? G : 1;
         bool canA = t[aO] > stepA, canB = t[bO] > stepB;
-        if (!canA && !canB) { *why = "cannot fit a tile in LDS"; return RR_ERR_UNSUPPORTED; }
+        if (!canA && !canB) {
+            if (bytes <= opt.max_lds) break;
+            *why = "cannot fit a tile in LDS";
+            return RR_ERR_UNSUPPORTED;
+        }
         bool shrinkA = canA && (!canB || TA * R >= TB * R);
         if (shrinkA) t[aO] = std::max(stepA, (t[aO] / 2 + stepA - 1) / stepA * stepA);
         else t[bO] = std::max(stepB, (t[bO] / 2 + stepB - 1) / stepB * stepB);
     }
+    // Stacked tiles: when the last two axes are swapped and the tile holds both
+    // whole, a tile would be one small transpose; the next slower input axis C
+    // (whose stride is exactly one such transpose) then stacks several of them,
+    // so a tile reads one contiguous range and writes one contiguous run per
+    // transpose (one range when C is also the next output axis).
+    int cax = -1;
+    {
+        const int64_t msub = innerA * t[aO] * innerB * t[bO] * R;
+        if (k == 1 && U < 16 && r >= 3 && nA == 1 && nB == 1 && t[a1] == d[a1] && t[b1] == d[b1] &&
+            b1 == r - 2 && pm[r - 2] == a1 && msub * 2 <= soft_bytes) {
+            cax = r - 3;
+            G = 1;
+            t[cax] = std::min<int64_t>(d[cax], std::max<int64_t>(1, soft_bytes / msub));
+            a.flags |= TF_STACK;
+            a.msub = a.msubp = (uint32_t)msub;
+            a.sinC = (uint64_t)(sin_el[cax] * R);
+            a.soutC = (uint64_t)(sout_el[cax] * R);
+        }
+    }
+    a.grid_cO = -1;
+    a.cO_len = 1;
+    a.cO_t = 1;
     a.TA = (uint32_t)(innerA * t[aO]);
     a.TB = (uint32_t)(innerB * t[bO]);
     a.TAinner = (uint32_t)innerA;
@@ -435,7 +499,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     uint64_t ntiles = 1;
     for (int oi = 0; oi < r; ++oi) {
         int s = order[oi];
-        bool tiled = inA[s] || inB[s];
+        bool tiled = inA[s] || inB[s] || s == cax;
         int64_t n = tiled ? cdiv(d[s], t[s]) : d[s];
         if (n <= 1) continue;
         int g = a.ngrid++;
@@ -445,11 +509,13 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         a.gsout[g] = (uint64_t)(step * sout_el[s] * R);
         if (s == aO) a.grid_aO = g;
         if (s == bO) a.grid_bO = g;
+        if (s == cax) a.grid_cO = g;
         ntiles *= (uint64_t)n;
         if (ntiles > 0x7fffffffULL) { *why = "too many tiles for one launch"; return RR_ERR_UNSUPPORTED; }
     }
     a.aO_len = (uint32_t)d[aO]; a.aO_t = (uint32_t)t[aO];
     a.bO_len = (uint32_t)d[bO]; a.bO_t = (uint32_t)t[bO];
+    if (cax >= 0) { a.cO_len = (uint32_t)d[cax]; a.cO_t = (uint32_t)t[cax]; }
     a.ntiles = (uint32_t)ntiles;
     // input rows start at multiples of d[a1]*R plus the tile's column offset
     uint64_t ra = src | (uint64_t)(d[a1] * R);
@@ -511,7 +577,8 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     while (L > G && (int64_t)((L * R + 15) / 16 * 16) * n > opt.max_lds && !de) L = std::max<int64_t>(G, L / 2 / G * G);
     while (L > G && (int64_t)(((int64_t)n * R + 15) / 16 * 16) * L > opt.max_lds && de) L = std::max<int64_t>(G, L / 2 / G * G);
     a.R = (uint32_t)R;
-    a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1;
+    a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1; a.grid_cO = -1;
+    a.cO_len = 1; a.cO_t = 1;
     int64_t nt = cdiv(count, L);
     if (nt > 0x7fffffffLL) { *why = "too many tiles"; return RR_ERR_UNSUPPORTED; }
     if (!de) {
@@ -573,7 +640,7 @@ std::string describe(const Plan& p) {
         o << " unit=" << a.unit << " g=" << a.g << " k=" << a.k << " TA=" << a.TA << " TB=" << a.TB
           << " nA=" << a.nA << " nB=" << a.nB << " win=" << a.win << " pitch=" << a.pitch
           << " lds=" << a.lds_bytes << " ntiles=" << a.ntiles << " ngrid=" << a.ngrid
-          << " flags=" << a.flags;
+          << " tc=" << a.cO_t << " flags=" << a.flags;
     }
     return o.str();
 }

@@ -75,6 +75,8 @@ enum TileFlags : uint32_t {
                          // 16-byte vectors gathered across row boundaries
     TF_RAGGED_OUT = 64u, // output rows written as 16-byte vectors at any alignment,
                          // gathered element by element from LDS, plus a tail
+    TF_STACK = 128u,     // tile = cO_t whole TA x TB transposes stacked along axis C,
+                         // each contiguous (msub bytes) in input and output
 };
 
 struct TileArgs {
@@ -114,7 +116,13 @@ struct TileArgs {
     uint32_t lds_bytes;
     uint32_t unit;            // U
     uint32_t g;               // G
-    uint32_t pad_;
+    int32_t grid_cO;          // stacked: grid index of the C axis (-1: none)
+    uint32_t cO_len, cO_t;    // extent of C and sub-tiles per tile (cO_t = 1 unless stacked)
+    uint32_t msub;            // stacked: bytes of one sub-tile (TA * TB * R)
+    uint32_t msubp;           // stacked: LDS bytes per sub-tile (msub if back to back in
+                              // the input, else msub rounded up to 16)
+    Magic msubel;             // stacked: divide by TA * TB
+    uint64_t sinC, soutC;     // stacked: byte stride of C in input and output
     uint64_t table[RR_MAX_PLANES];
 };
 
@@ -124,10 +132,13 @@ struct TileOptions {
     int order_out = -1;     // 1: traverse tiles in output order, 0: input order, -1: by unit size
     int force_ragged = 0;   // plan odd-shape (ragged) tiles even where aligned micro-tiles fit
     int max_g = 0;          // cap on the micro-tile edge G (0 = none)
-    int max_lds = 65536;
+    int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
+    int max_lds = 65536;    // hard limit
 };
 
-bool valid_max_g(int g);   // 0 or a power of two up to 16
+bool valid_max_g(int g);      // 0 or a power of two up to 16
+bool valid_tile_kib(int k);   // 0 or 4..64
+constexpr int DEFAULT_TILE_KIB = 16;
 
 // Process-wide override (autotuner hook).
 TileOptions& tile_override();

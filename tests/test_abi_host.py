@@ -144,7 +144,7 @@ def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
     dims, perm, e = (16384, 16384), (1, 0), 4
     base = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
     path = tmp_path / "tune.txt"
-    key_line = "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1\n"
+    key_line = "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1 0 64\n"
     path.write_text(key_line)
     rr.tune_load(str(path))
     tuned = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
@@ -186,7 +186,7 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
     rr.tune_save(str(out))
     assert "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8" in out.read_text()
     rr.tune_clear()
-    for bad in ("k 0 0 0 3\n", "k 0 0 0 8 9\n", "k 0 0\n"):
+    for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 1\n", "k 0 0\n"):
         (tmp_path / "bad.txt").write_text(bad)
         with pytest.raises(rr.RRError):
             rr.tune_load(str(tmp_path / "bad.txt"))

@@ -128,6 +128,35 @@ def test_emu_forced_ragged_on_aligned_shapes():
         assert flags & 16 and flags & (32 | 64), st
 
 
+STACKED_CASES = [((1000, 3, 3), (0, 2, 1), 2), ((2000, 4, 6), (0, 2, 1), 8), ((777, 5, 7), (0, 2, 1), 1),
+                 ((3000, 2, 2), (0, 2, 1), 4), ((100, 17, 13), (0, 2, 1), 8), ((50, 64, 48), (0, 2, 1), 1),
+                 ((5, 7, 3, 4), (1, 0, 3, 2), 4), ((6, 50, 9, 11), (1, 0, 3, 2), 2),
+                 ((3, 4, 40, 5, 6), (2, 0, 1, 4, 3), 1), ((9, 11, 30, 2, 3), (0, 2, 1, 4, 3), 8)]
+
+
+def test_emu_stacked_small_transposes():
+    """Last two axes swapped and small: several whole transposes share a tile,
+    read as one contiguous range; written as one range (C also next in the
+    output) or one run per transpose; partial last tile along C."""
+    jobs = [_perm_job(d, p, e, 7800 + i) for i, (d, p, e) in enumerate(STACKED_CASES)]
+    res = _check(jobs)
+    for st, _ in res:
+        kv = dict(t.split("=", 1) for t in st.split()[1:] if "=" in t)
+        assert int(kv["flags"]) & 128 and int(kv["tc"]) > 1, st
+
+
+def test_emu_stacked_in_batches_and_chunks():
+    """Stacked tiles inside a batch, whole and cut into workgroup ranges."""
+    sub = [_perm_job(d, p, e, 7900 + i) for i, (d, p, e) in enumerate(STACKED_CASES[:6])]
+    sub.append(_perm_job((40, 24, 48), (2, 0, 1), 4, 7990))
+    for chunk in (0, 3):
+        res = emu_runner.run([dict(op="batched", jobs=sub, chunk=chunk)])
+        st, outs = res[0]
+        assert st.startswith("ok"), st
+        for j, o in zip(sub, outs):
+            assert np.array_equal(o, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), (j["dims"], chunk)
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),

@@ -284,3 +284,15 @@ def test_forced_ragged_on_aligned_shapes(rr):
             check_permute(rr, dims, perm, e, 9800 + i)
     finally:
         rr.set_tile_override()
+
+
+def test_stacked_small_transposes(rr):
+    """Batches of small transposes along a leading axis share tiles (stacked
+    mode), including the shapes of the uneven-job workload's worst cases."""
+    from tests.test_emulated_kernels import STACKED_CASES
+    cases = list(STACKED_CASES) + [((487424, 3, 3), (0, 2, 1), 2), ((225498, 4, 6), (0, 2, 1), 8),
+                                   ((454, 63, 2, 120), (1, 0, 3, 2), 4), ((20480, 2, 2), (0, 2, 1), 2)]
+    for i, (dims, perm, e) in enumerate(cases):
+        d = rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)
+        assert int(d["flags"]) & 128, (dims, d)
+        check_permute(rr, dims, perm, e, 9900 + i)
