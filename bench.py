@@ -46,7 +46,21 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per arrival rate")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps and exit (for rocprofv3 runs)")
+    ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
+                    help="turn the counter_collection.csv files of two rocprofv3 --pmc runs of "
+                         "'--profile-only --steps 1 --warmup 0' (FETCH_SIZE, then WRITE_SIZE) into "
+                         "profiles/counters.json, calibrated on the step's plain copies; no GPU needed")
     return ap.parse_args()
+
+
+# The counter runs that --ingest-counters expects (one dispatch per case, tuned
+# shapes loaded from the cache the timed run wrote).
+PMC_COMMANDS = [
+    "rocprofv3 --pmc FETCH_SIZE --output-format csv -d <dir> -o fetch -- "
+    "python3 bench.py --profile-only --steps 1 --warmup 0 --tune-cache <cache>",
+    "rocprofv3 --pmc WRITE_SIZE --output-format csv -d <dir> -o write -- "
+    "python3 bench.py --profile-only --steps 1 --warmup 0 --tune-cache <cache>",
+]
 
 
 def kernel_source_hash() -> str:
@@ -55,6 +69,79 @@ def kernel_source_hash() -> str:
         with open(os.path.join(ROOT, "paper_1011_3583_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
     return h.hexdigest()[:16]
+
+
+def dense_cases():
+    """(name, dims, perm, elem_size, bytes per side) of every launch of one step."""
+    import rr_synth
+    cases = []
+    for name, dims, perm in rr_synth.DENSE_CASES:
+        for e in sorted(rr_synth.ESIZES, reverse=True):
+            n = 1
+            for d in dims:
+                n *= d
+            cases.append((name, dims, perm, e, n * e))
+    return cases
+
+
+def _pmc_rows(path: str, counter: str):
+    """(dispatch id, kernel name as k_x<a,b>, counter KiB) of the library's kernels."""
+    import csv
+    out = []
+    with open(path, newline="") as fh:
+        for r in csv.DictReader(fh):
+            name = r["Kernel_Name"]
+            if r["Counter_Name"] != counter or not name.startswith("void rr::k_"):
+                continue
+            out.append((int(r["Dispatch_Id"]), name[len("void rr::"):].split("(")[0].replace(" ", ""),
+                        float(r["Counter_Value"])))
+    out.sort()
+    return out
+
+
+def ingest_counters(fetch_csv: str, write_csv: str, out_path: str | None = None) -> dict:
+    """HBM bytes per launch of each kernel of the step, from FETCH_SIZE and
+    WRITE_SIZE (KiB per dispatch), each scaled by what it reads for the step's
+    plain copies (identity permutes: k_copy, a known number of bytes each way)."""
+    cases = dense_cases()
+    f = _pmc_rows(fetch_csv, "FETCH_SIZE")
+    w = _pmc_rows(write_csv, "WRITE_SIZE")
+    n = len(cases)
+    if not f or len(f) % n or len(w) != len(f):
+        raise SystemExit(f"expected a multiple of {n} library dispatches in each run, got {len(f)} and {len(w)}")
+    for (_, kf, _), (_, kw, _) in zip(f, w):
+        if kf != kw:
+            raise SystemExit(f"the two runs launched different kernels ({kf} vs {kw})")
+    algo = [cases[i % n][4] for i in range(len(f))]
+    copies = [i for i in range(len(f)) if f[i][1].startswith("k_copy")]
+    if not copies:
+        raise SystemExit("no plain copy in the step to calibrate against")
+    rf = sum(algo[i] for i in copies) / sum(f[i][2] * 1024 for i in copies)
+    wf = sum(algo[i] for i in copies) / sum(w[i][2] * 1024 for i in copies)
+    kernels = {}
+    for i, (_, k, fk) in enumerate(f):
+        e = kernels.setdefault(k, {"launches": 0, "algorithmic": 0.0, "fetch": 0.0, "write": 0.0})
+        e["launches"] += 1
+        e["algorithmic"] += 2 * algo[i]
+        e["fetch"] += fk * 1024 * rf
+        e["write"] += w[i][2] * 1024 * wf
+    out = {}
+    for k, e in sorted(kernels.items()):
+        m = e["launches"]
+        hbm = (e["fetch"] + e["write"]) / m
+        out[k] = {"launches": m, "algorithmic_bytes_per_launch": round(e["algorithmic"] / m),
+                  "read_bytes_per_launch": round(e["fetch"] / m), "write_bytes_per_launch": round(e["write"] / m),
+                  "hbm_bytes_per_launch": round(hbm), "traffic_over_algorithmic": round(hbm / (e["algorithmic"] / m), 4)}
+    prof = {"source_hash": kernel_source_hash(), "commands": PMC_COMMANDS,
+            "calibration": {"kernel": "k_copy (identity permutes of the step)", "launches": len(copies),
+                            "fetch_scale": round(rf, 5), "write_scale": round(wf, 5)},
+            "kernels": out}
+    if out_path is None:
+        os.makedirs(os.path.join(ROOT, "profiles"), exist_ok=True)
+        out_path = os.path.join(ROOT, "profiles", "counters.json")
+    with open(out_path, "w") as fh:
+        json.dump(prof, fh, indent=1)
+    return prof
 
 
 def kernel_name(d: dict) -> str:
@@ -69,9 +156,12 @@ def kernel_name(d: dict) -> str:
 
 def main():
     args = parse()
+    if args.ingest_counters:
+        print(json.dumps(ingest_counters(*args.ingest_counters), indent=1))
+        return
     if args.gpus != 1:
-        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported (this library "
-              f"has no multi-GPU path; see the sharding note in the design document).", file=sys.stderr)
+        print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
+              f"has no multi-GPU path (each GPU would run its own share of the jobs).", file=sys.stderr)
         sys.exit(2)
     import torch
     import paper_1011_3583_amd as rr
@@ -83,13 +173,7 @@ def main():
     stream = torch.cuda.current_stream()
     sh = stream.cuda_stream
 
-    cases = []
-    for name, dims, perm in rr_synth.DENSE_CASES:
-        for e in sorted(rr_synth.ESIZES, reverse=True):
-            n = 1
-            for d in dims:
-                n *= d
-            cases.append((name, dims, perm, e, n * e))
+    cases = dense_cases()
     max_nb = max(c[4] for c in cases)
     # two input regions alternate so a case never re-reads what the previous one touched
     pool = torch.empty(2 * max_nb, dtype=torch.uint8, device=dev)
