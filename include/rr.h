@@ -251,12 +251,14 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * RR_TILE_ORDER_OUT / RR_TILE_ORDER_IN, neither = built-in choice by element
  * size), a cap on the register micro-tile edge G (RR_TILE_MAX_G(g), g one of
  * 1, 2, 4, 8, 16; 0 = no cap) and the LDS size tiles are shrunk to
- * (RR_TILE_KIB(k), 4..64 KiB; 0 = 16).  Process-wide; affects plans made after
+ * (RR_TILE_KIB(k), 4..64 KiB; 0 = 16); RR_TILE_XCD hands each of the 8 XCDs a
+ * contiguous range of tiles instead of every 8th one.  Process-wide; affects plans made after
  * the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a bad cap or a
  * bad tile size. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
+#define RR_TILE_XCD 8           /* each XCD takes a contiguous range of tiles (single launches) */
 #define RR_TILE_MAX_G(g) ((g) << 8)
 #define RR_TILE_KIB(k) ((k) << 16)
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);

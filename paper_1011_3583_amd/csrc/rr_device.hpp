@@ -325,6 +325,18 @@ RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
     return t;
 }
 
+// Workgroups of a launch are dispatched round-robin over the XCDs (8 on
+// MI355X, each with its own L2).  Plain order gives XCD x every 8th tile; with
+// TF_XCD it takes the contiguous range [x*q + min(x, r), +q + (x < r)) of the
+// ntiles = 8q + r tiles instead.  Either way a bijection on [0, ntiles).
+constexpr uint32_t NXCD = 8;
+RR_HD uint32_t block_to_tile(const TileArgs& a, uint32_t b) {
+    if (!(a.flags & TF_XCD)) return b;
+    const uint32_t q = a.ntiles / NXCD, r = a.ntiles % NXCD;
+    const uint32_t x = b % NXCD, k = b / NXCD;
+    return x * q + umin(x, r) + k;
+}
+
 RR_HD uint64_t row_in(const TileArgs& a, uint32_t ib) {
     if (a.flags & TF_IN_TABLE) return a.table[ib];
     if (a.nB == 1) return (uint64_t)ib * a.sinB[0];

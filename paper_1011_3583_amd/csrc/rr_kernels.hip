@@ -36,7 +36,7 @@ __global__ __launch_bounds__(NT) void k_run(const RunArgs a) {
 template <int U, int G>
 __global__ __launch_bounds__(NT) void k_tile(const TileArgs a) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
-    const TileCtx t = tile_decode(a, blockIdx.x);
+    const TileCtx t = tile_decode(a, block_to_tile(a, blockIdx.x));
     read_dispatch<U, G>(a, t, smem, threadIdx.x);
     __syncthreads();
     write_phase<U, G>(a, t, smem, threadIdx.x);

@@ -39,7 +39,7 @@ TileOptions& tile_override() {
 bool tile_override_active() {
     const TileOptions& o = tile_override();
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0;
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != 0;
 }
 
 namespace {
@@ -84,14 +84,15 @@ std::string tune_dump() {
     std::ostringstream o;
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
-          << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << "\n";
+          << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << " "
+          << kv.second.xcd << "\n";
     return o.str();
 }
 
 bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
 bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 
-// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib]]
+// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd]]]
 int tune_parse(const std::string& text) {
     std::istringstream lines(text);
     std::string line;
@@ -104,10 +105,12 @@ int tune_parse(const std::string& text) {
         if (!(in >> o.in_row_bytes >> o.out_row_bytes >> o.order_out)) return -1;
         if (!(in >> o.max_g)) o.max_g = 0;
         else if (!(in >> o.tile_kib)) o.tile_kib = 0;
+        else if (!(in >> o.xcd)) o.xcd = 0;
         std::string extra;
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
-            o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib))
+            o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib) ||
+            o.xcd < 0 || o.xcd > 1)
             return -1;
         tune_store(key, o);
         ++n;
@@ -525,6 +528,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA;
     rr_status st = finish_tile(a, U, G, k, ra, flat_ok, src, (uint64_t)d[b1], opt, why);
     if (st != RR_OK) return st;
+    if (opt.xcd) a.flags |= TF_XCD;
     p->grid = a.ntiles;
     p->bytes = (uint64_t)c.total_bytes;
     return RR_OK;

@@ -77,6 +77,7 @@ enum TileFlags : uint32_t {
                          // gathered element by element from LDS, plus a tail
     TF_STACK = 128u,     // tile = cO_t whole TA x TB transposes stacked along axis C,
                          // each contiguous (msub bytes) in input and output
+    TF_XCD = 256u,       // single launches: each XCD takes a contiguous range of tiles
 };
 
 struct TileArgs {
@@ -133,6 +134,7 @@ struct TileOptions {
     int force_ragged = 0;   // plan odd-shape (ragged) tiles even where aligned micro-tiles fit
     int max_g = 0;          // cap on the micro-tile edge G (0 = none)
     int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
+    int xcd = 0;            // 1: contiguous tile range per XCD (single launches)
     int max_lds = 65536;    // hard limit
 };
 

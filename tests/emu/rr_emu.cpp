@@ -10,7 +10,7 @@
 // read of a never-written LDS byte shows up as a wrong output byte.
 //
 // Input: a manifest, one job per line:
-//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged infile outfile
+//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd infile outfile
 //   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
 //   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
@@ -41,7 +41,10 @@ static void write_file(const std::string& path, const uint8_t* p, size_t n) {
 
 template <int U, int G>
 static void run_tile_ug(const TileArgs& a, uint32_t grid) {
-    for (uint32_t tile = 0; tile < grid; ++tile) {
+    std::vector<uint8_t> seen(grid, 0);
+    for (uint32_t b = 0; b < grid; ++b) {
+        const uint32_t tile = block_to_tile(a, b);
+        if (tile >= grid || seen[tile]++) { std::fprintf(stderr, "block %u -> bad tile %u\n", b, tile); std::abort(); }
         uint8_t* lds = new uint8_t[a.lds_bytes];
         std::memset(lds, 0xA5, a.lds_bytes);
         const TileCtx t = tile_decode(a, tile);
@@ -191,7 +194,7 @@ int main(int argc, char** argv) {
             for (auto& q : perm) is >> q;
             int esize, soff, doff, order; std::string inf, outf;
             is >> esize >> soff >> doff >> opt.in_row_bytes >> opt.out_row_bytes >> order >> opt.max_g >>
-                opt.force_ragged >> inf >> outf;
+                opt.force_ragged >> opt.xcd >> inf >> outf;
             opt.order_out = order;
             Canon c;
             rr_status st = canonicalize(ndim, dims.data(), perm.data(), esize, &c, &why);

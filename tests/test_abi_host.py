@@ -186,7 +186,12 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
     rr.tune_save(str(out))
     assert "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8" in out.read_text()
     rr.tune_clear()
-    for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 1\n", "k 0 0\n"):
+    path.write_text("r2:e1:a16/16:d4096,4096:p1,0 0 0 -1 0 0 1\n")
+    rr.tune_load(str(path))
+    assert int(rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["flags"]) & 256
+    rr.tune_clear()
+    for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 2\n", "k 0 0 0 8 16 1 1\n",
+                "k 0 0\n"):
         (tmp_path / "bad.txt").write_text(bad)
         with pytest.raises(rr.RRError):
             rr.tune_load(str(tmp_path / "bad.txt"))

@@ -157,6 +157,20 @@ def test_emu_stacked_in_batches_and_chunks():
             assert np.array_equal(o, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), (j["dims"], chunk)
 
 
+def test_emu_xcd_tile_ranges():
+    """Tiles handed out as one contiguous range per XCD cover every tile once
+    (the emulator checks the block -> tile map is a bijection), for tile counts
+    below, at and above a multiple of 8."""
+    jobs = []
+    for i, (dims, perm, e) in enumerate([((96, 80), (1, 0), 1), ((64, 48, 40), (2, 0, 1), 2),
+                                         ((300, 37), (1, 0), 4), ((32, 24, 16), (2, 1, 0), 8),
+                                         ((1000, 3, 3), (0, 2, 1), 2), ((130, 130), (1, 0), 4)]):
+        jobs.append(_perm_job(dims, perm, e, 7700 + i, xcd=True, in_rb=64, out_rb=64))
+    res = _check(jobs)
+    for st, _ in res:
+        assert int(dict(t.split("=", 1) for t in st.split()[1:] if "=" in t)["flags"]) & 256, st
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),

@@ -296,3 +296,17 @@ def test_stacked_small_transposes(rr):
         d = rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)
         assert int(d["flags"]) & 128, (dims, d)
         check_permute(rr, dims, perm, e, 9900 + i)
+
+
+def test_xcd_tile_ranges(rr):
+    """Contiguous tile ranges per XCD give the same bytes (tile counts not a
+    multiple of 8 included)."""
+    rr.set_tile_override(xcd=True)
+    try:
+        for i, (dims, perm, e) in enumerate([((1024, 1040), (1, 0), 1), ((320, 272, 48), (2, 0, 1), 2),
+                                             ((1001, 999), (1, 0), 4), ((64, 48, 112), (2, 1, 0), 8),
+                                             ((20000, 3, 3), (0, 2, 1), 2)]):
+            assert int(rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)["flags"]) & 256
+            check_permute(rr, dims, perm, e, 9950 + i)
+    finally:
+        rr.set_tile_override()
