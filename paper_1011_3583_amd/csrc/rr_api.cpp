@@ -154,6 +154,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.max_g = max_g;
     o.tile_kib = tile_kib;
     o.xcd = (flags & RR_TILE_XCD) ? 1 : 0;
+    o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
@@ -174,7 +175,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     // same launch as an earlier one are skipped
     // row targets, traversal order, micro-tile cap, tile size (KiB); candidates
     // that plan to the same launch as an earlier one are skipped
-    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = 0; };
+    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = 0, umt = 0; };
     static const Cand cands[] = {
         {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
         {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
@@ -185,7 +186,8 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, 1, 8, 0},       {128, 128, -1, 8, 0},   {128, 128, 1, 8, 0},    {256, 128, -1, 8, 0},
         {0, 0, -1, 4, 0},      {0, 0, 1, 4, 0},        {128, 128, -1, 4, 0},   {64, 128, 1, 4, 0},
         {128, 64, 1, 4, 0},    {0, 0, -1, 0, 0, 1},    {0, 0, 1, 0, 0, 1},     {0, 0, 0, 0, 0, 1},
-        {0, 0, -1, 0, 64, 1},  {512, 512, -1, 16, 64, 1}};
+        {0, 0, -1, 0, 64, 1},  {512, 512, -1, 16, 64, 1}, {0, 0, -1, 0, 0, 0, 1}, {0, 0, 1, 0, 0, 0, 1},
+        {0, 0, 0, 0, 0, 0, 1}, {512, 512, -1, 0, 64, 0, 1}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
@@ -201,6 +203,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.max_g = cd.max_g;
         o.tile_kib = cd.kib;
         o.xcd = cd.xcd;
+        o.umt = cd.umt;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;

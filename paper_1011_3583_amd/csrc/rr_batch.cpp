@@ -145,10 +145,12 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
 }
 
 rr_status tune(rr_batch* b) {
-    struct Cand { int in_rb, out_rb, order; bool persistent; };
+    // row targets, traversal order, persistent grid, tile size (KiB), unaligned micro-tiles
+    struct Cand { int in_rb, out_rb, order; bool persistent; int kib = 0, umt = 0; };
     const Cand cands[] = {{0, 0, 0, false}, {0, 0, 1, false}, {0, 0, 0, true}, {256, 512, 0, false},
                           {512, 256, 0, false}, {512, 512, 0, false}, {1024, 256, 0, false},
-                          {256, 1024, 0, false}, {512, 256, 1, false}, {128, 256, 0, false}};
+                          {256, 1024, 0, false}, {512, 256, 1, false}, {128, 256, 0, false},
+                          {0, 0, 0, false, 0, 1}, {512, 512, 0, false, 32, 0}};
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(RR_ERR_HIP, "stream");
     double best = 1e300;
@@ -159,6 +161,8 @@ rr_status tune(rr_batch* b) {
         o.in_row_bytes = c.in_rb;
         o.out_row_bytes = c.out_rb;
         o.order_out = c.order;
+        o.tile_kib = c.kib;
+        o.umt = c.umt;
         BatchPlan p;
         std::string why;
         int bad;
@@ -175,6 +179,8 @@ rr_status tune(rr_batch* b) {
     b->opt.in_row_bytes = bestc.in_rb;
     b->opt.out_row_bytes = bestc.out_rb;
     b->opt.order_out = bestc.order;
+    b->opt.tile_kib = bestc.kib;
+    b->opt.umt = bestc.umt;
     b->persistent = bestc.persistent;
     b->tuned_us = best;
     rs = plan_or_fail(b->jobs.data(), (int)b->jobs.size(), b->opt, &b->plan);

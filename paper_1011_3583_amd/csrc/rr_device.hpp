@@ -177,6 +177,37 @@ RR_HD void gstore16u(uint8_t* p, const uint32_t (&w)[4]) {
 #endif
 }
 
+// W bytes (2, 4, 8, 16) at any byte alignment.
+#if defined(__HIP_DEVICE_COMPILE__)
+typedef uint32_t rr_u32x2_u __attribute__((ext_vector_type(2), aligned(1)));
+typedef uint32_t rr_u32_u __attribute__((aligned(1)));
+typedef uint16_t rr_u16_u __attribute__((aligned(1)));
+#endif
+template <int W>
+RR_HD void gstore_u(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
+    if constexpr (W == 16) {
+        gstore16u(p, w);
+    } else {
+#if defined(__HIP_DEVICE_COMPILE__)
+        if constexpr (W == 8) {
+            rr_u32x2_u v; v.x = w[0]; v.y = w[1];
+            RR_AS_GLOBAL rr_u32x2_u* q = as_global_mut<rr_u32x2_u>(p);
+            if (RR_NT_STORE) __builtin_nontemporal_store(v, q); else *q = v;
+        } else if constexpr (W == 4) {
+            RR_AS_GLOBAL rr_u32_u* q = as_global_mut<rr_u32_u>(p);
+            if (RR_NT_STORE) __builtin_nontemporal_store((rr_u32_u)w[0], q); else *q = w[0];
+        } else if constexpr (W == 2) {
+            RR_AS_GLOBAL rr_u16_u* q = as_global_mut<rr_u16_u>(p);
+            if (RR_NT_STORE) __builtin_nontemporal_store((rr_u16_u)w[0], q); else *q = (uint16_t)w[0];
+        } else {
+            vstore_t<1, RR_NT_STORE != 0, true>(p, w);
+        }
+#else
+        std::memcpy(p, w, W);
+#endif
+    }
+}
+
 // global memory (streamed) and LDS (ordinary)
 template <int W>
 RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, RR_NT_LOAD != 0, true>(p, w); }
@@ -546,6 +577,14 @@ RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint
         if (a.flags & TF_STACK) { read_stack<U>(a, t, lds, tid); return; }
         if (a.flags & TF_RAGGED_IN) { read_ragged<U>(a, t, lds, tid); return; }
     }
+    if constexpr (G > 1 && U < 16) {
+        if (a.flags & TF_UMT) {
+            read_rows<U>(
+                t.TBv, t.TAv * a.R, [&](uint32_t r) { return t.bin + row_in(a, r); },
+                [&](uint32_t r, uint32_t x) { return lds_pos<G>(a, r, x); }, lds, tid);
+            return;
+        }
+    }
     if (a.flags & TF_IN_FLAT) { read_flat<B>(a, t, lds, tid); return; }
     switch (a.win) {
         case 16: read_phase<16, G, B>(a, t, lds, tid); break;
@@ -723,6 +762,41 @@ RR_HD void write_stack(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
     }
 }
 
+// Unaligned micro-tiles: full G x G micro-tiles are transposed in registers and
+// stored as G unaligned W-byte vectors (row starts at any element offset); a
+// micro-tile cut by the tile's valid extent moves element by element.
+template <int U, int G>
+RR_HD void write_umt(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+    constexpr int W = U * G;
+    constexpr int NW = NWords<W>::value;
+    for (uint32_t gi = tid; gi < a.nwork; gi += NT) {
+        const uint32_t ma = mdiv(gi, a.mnmb);
+        const uint32_t mb = gi - ma * a.nmb;
+        const uint32_t ia0 = ma * G, ib0 = mb * G;
+        if (ia0 >= t.TAv || ib0 >= t.TBv) continue;
+        if (ia0 + G <= t.TAv && ib0 + G <= t.TBv) {
+            uint32_t r[G][NW];
+#pragma unroll
+            for (int j = 0; j < G; ++j) sload<W>(lds + lds_pos<G>(a, ib0 + j, ia0 * U), r[j]);
+            uint32_t o[G][NW];
+            xpose<U, G>(r, o);
+#pragma unroll
+            for (int i = 0; i < G; ++i)
+                gstore_u<W>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0 + i) + (uint64_t)ib0 * U), o[i]);
+        } else {
+            const uint32_t ni = umin(G, t.TAv - ia0), nj = umin(G, t.TBv - ib0);
+            for (uint32_t i = 0; i < ni; ++i) {
+                uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0 + i) + (uint64_t)ib0 * U);
+                for (uint32_t j = 0; j < nj; ++j) {
+                    uint32_t e[NWords<U>::value];
+                    sload<U>(lds + lds_pos<G>(a, ib0 + j, (ia0 + i) * U), e);
+                    gstore<U>(q + j * U, e);
+                }
+            }
+        }
+    }
+}
+
 template <int U, int G>
 RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int W = U * G;
@@ -738,6 +812,12 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
         }
         if (a.flags & TF_RAGGED_OUT) {
             write_ragged<U>(a, t, lds, tid);
+            return;
+        }
+    }
+    if constexpr (G > 1 && U < 16) {
+        if (a.flags & TF_UMT) {
+            write_umt<U, G>(a, t, lds, tid);
             return;
         }
     }

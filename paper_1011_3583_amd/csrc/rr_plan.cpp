@@ -39,7 +39,7 @@ TileOptions& tile_override() {
 bool tile_override_active() {
     const TileOptions& o = tile_override();
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0 || o.xcd != 0;
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != 0 || o.umt != 0;
 }
 
 namespace {
@@ -85,14 +85,14 @@ std::string tune_dump() {
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
           << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << " "
-          << kv.second.xcd << "\n";
+          << kv.second.xcd << " " << kv.second.umt << "\n";
     return o.str();
 }
 
 bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
 bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 
-// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd]]]
+// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt]]]]
 int tune_parse(const std::string& text) {
     std::istringstream lines(text);
     std::string line;
@@ -106,11 +106,12 @@ int tune_parse(const std::string& text) {
         if (!(in >> o.max_g)) o.max_g = 0;
         else if (!(in >> o.tile_kib)) o.tile_kib = 0;
         else if (!(in >> o.xcd)) o.xcd = 0;
+        else if (!(in >> o.umt)) o.umt = 0;
         std::string extra;
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
             o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib) ||
-            o.xcd < 0 || o.xcd > 1)
+            o.xcd < 0 || o.xcd > 1 || o.umt < 0 || o.umt > 2)
             return -1;
         tune_store(key, o);
         ++n;
@@ -316,7 +317,10 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
     a.rch = (uint32_t)(rowbytes / win);
     a.mrch = make_magic(a.rch);
     a.mtb = make_magic(a.TB);
-    if (k == 1) {
+    if (k == 1 && (a.flags & TF_UMT)) {
+        a.nmb = (a.TB + G - 1) / G;
+        a.nwork = a.nmb * ((a.TA + G - 1) / G);
+    } else if (k == 1) {
         a.nmb = a.TB / G;
         a.nwork = a.nmb * (a.TA / G);
         const uint32_t W = (uint32_t)(U * G);
@@ -365,15 +369,28 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const int k = (int)(R / U);
     const int a1 = r - 1, b1 = pm[r - 1];
     int G = 1;
+    bool umt = false;
     if (k == 1 && !opt.force_ragged) {
         // 1- and 2-byte elements default to 8-byte micro-tile rows: 16 KiB tiles
         // then still give every thread a micro-tile, and the transpose stays small
         // enough in registers for six waves per SIMD.
-        G = opt.max_g > 0 ? std::min(16 / U, opt.max_g) : (U <= 2 ? 8 / U : 16 / U);
+        const int Gdef = opt.max_g > 0 ? std::min(16 / U, opt.max_g) : (U <= 2 ? 8 / U : 16 / U);
+        G = Gdef;
         while (G > 1 && ((d[a1] % G) || (d[b1] % G) || addr_align(src) < U * G ||
                          addr_align(dst) < U * G))
             G >>= 1;
+        // Odd extents or pointers rule out aligned micro-tiles: on request keep them
+        // anyway with unaligned vector accesses when both fastest extents hold one
+        // (the ragged G = 1 paths measured faster on most shapes, so this is a
+        // tuner candidate, not the default).
+        if (((G == 1 && opt.umt == 1) || opt.umt == 2) && Gdef > 1 && d[a1] >= Gdef && d[b1] >= Gdef) {
+            G = Gdef;
+            umt = true;
+        }
     }
+    // a micro-tile's G outputs along B must be one contiguous run: with unaligned
+    // micro-tiles on an extent that G does not divide, B stays a single axis
+    const bool b_single = umt && (d[b1] % G) != 0;
     const int in_rb = opt.in_row_bytes > 0 ? opt.in_row_bytes : default_row_bytes(U, true);
     const int out_rb = opt.out_row_bytes > 0 ? opt.out_row_bytes : default_row_bytes(U, false);
     int64_t targetA = std::max<int64_t>(G, cdiv(in_rb, R));
@@ -397,7 +414,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         }
     };
     auto growB = [&]() {
-        for (; prodB < targetB && nxB >= 0 && !inA[pm[nxB]] && nB < MAXS; --nxB) {
+        for (; !b_single && prodB < targetB && nxB >= 0 && !inA[pm[nxB]] && nB < MAXS; --nxB) {
             B[nB++] = pm[nxB]; inB[pm[nxB]] = true; prodB *= d[pm[nxB]];
         }
     };
@@ -465,6 +482,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
             b1 == r - 2 && pm[r - 2] == a1 && msub * 2 <= soft_bytes) {
             cax = r - 3;
             G = 1;
+            umt = false;
             t[cax] = std::min<int64_t>(d[cax], std::max<int64_t>(1, soft_bytes / msub));
             a.flags |= TF_STACK;
             a.msub = a.msubp = (uint32_t)msub;
@@ -526,7 +544,8 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     // rows are back to back when every A axis is whole and the single B axis is
     // the next slower input axis
     const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA;
-    rr_status st = finish_tile(a, U, G, k, ra, flat_ok, src, (uint64_t)d[b1], opt, why);
+    if (umt) a.flags |= TF_UMT;
+    rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, (uint64_t)d[b1], opt, why);
     if (st != RR_OK) return st;
     if (opt.xcd) a.flags |= TF_XCD;
     p->grid = a.ntiles;

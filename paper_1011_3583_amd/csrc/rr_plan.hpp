@@ -78,6 +78,8 @@ enum TileFlags : uint32_t {
     TF_STACK = 128u,     // tile = cO_t whole TA x TB transposes stacked along axis C,
                          // each contiguous (msub bytes) in input and output
     TF_XCD = 256u,       // single launches: each XCD takes a contiguous range of tiles
+    TF_UMT = 512u,       // G x G micro-tiles on rows of any alignment: unaligned 16-byte row
+                         // reads, unaligned G*U-byte stores, element-wise partial micro-tiles
 };
 
 struct TileArgs {
@@ -135,6 +137,8 @@ struct TileOptions {
     int max_g = 0;          // cap on the micro-tile edge G (0 = none)
     int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
     int xcd = 0;            // 1: contiguous tile range per XCD (single launches)
+    int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead
+                            // of the G = 1 ragged paths), 2 everywhere (testing)
     int max_lds = 65536;    // hard limit
 };
 

@@ -10,7 +10,7 @@
 // read of a never-written LDS byte shows up as a wrong output byte.
 //
 // Input: a manifest, one job per line:
-//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd infile outfile
+//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt infile outfile
 //   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
 //   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
@@ -194,7 +194,7 @@ int main(int argc, char** argv) {
             for (auto& q : perm) is >> q;
             int esize, soff, doff, order; std::string inf, outf;
             is >> esize >> soff >> doff >> opt.in_row_bytes >> opt.out_row_bytes >> order >> opt.max_g >>
-                opt.force_ragged >> opt.xcd >> inf >> outf;
+                opt.force_ragged >> opt.xcd >> opt.umt >> inf >> outf;
             opt.order_out = order;
             Canon c;
             rr_status st = canonicalize(ndim, dims.data(), perm.data(), esize, &c, &why);
@@ -248,10 +248,11 @@ int main(int argc, char** argv) {
             for (int c = 0; c < n; ++c) delete[] planes[c];
             delete[] flat;
         } else if (op == "batched") {
-            // batched k in_rb out_rb order chunk max_g ragged : then k lines
+            // batched k in_rb out_rb order chunk max_g ragged umt : then k lines
             //   "job ndim dims.. perm.. esize infile outfile"
             int k, order, chunk = 0;
-            is >> k >> opt.in_row_bytes >> opt.out_row_bytes >> order >> chunk >> opt.max_g >> opt.force_ragged;
+            is >> k >> opt.in_row_bytes >> opt.out_row_bytes >> order >> chunk >> opt.max_g >> opt.force_ragged >>
+                opt.umt;
             opt.order_out = order;
             std::vector<rr_job> jobs((size_t)k);
             std::vector<uint8_t*> bufs;

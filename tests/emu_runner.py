@@ -39,7 +39,7 @@ def build():
 def run(jobs):
     """Run jobs through the emulator.  Each job is a dict:
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
-                    max_g, ragged, xcd
+                    max_g, ragged, xcd, umt
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
        deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb
     Returns a list of (status_line, output) with output a uint8 array or list of planes."""
@@ -57,13 +57,13 @@ def run(jobs):
                                        str(j["esize"]), str(j.get("src_off", 0)), str(j.get("dst_off", 0)),
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))), str(int(j.get("xcd", False))),
-                                       inf, outf]))
+                                       str(int(j.get("umt", 0))), inf, outf]))
             elif j["op"] == "interlace":
                 np.concatenate(j["planes"]).tofile(inf)
                 lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
             elif j["op"] == "batched":
                 lines.append(f"batched {len(j['jobs'])} {rb} {j.get('order', -1)} {j.get('chunk', 0)} "
-                             f"{j.get('max_g', 0)} {int(j.get('ragged', False))}")
+                             f"{j.get('max_g', 0)} {int(j.get('ragged', False))} {int(j.get('umt', 0))}")
                 for k, sub in enumerate(j["jobs"]):
                     sf, of = os.path.join(td, f"b{i}_{k}"), os.path.join(td, f"bo{i}_{k}")
                     sub["input"].tofile(sf)

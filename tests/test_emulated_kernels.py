@@ -171,6 +171,39 @@ def test_emu_xcd_tile_ranges():
         assert int(dict(t.split("=", 1) for t in st.split()[1:] if "=" in t)["flags"]) & 256, st
 
 
+UMT_CASES = [((1001, 999), (1, 0), 4, 0, 0), ((257, 131), (1, 0), 2, 0, 0), ((33, 45, 77), (2, 0, 1), 8, 0, 0),
+             ((17, 19, 23), (1, 2, 0), 1, 0, 0), ((301, 299), (1, 0), 2, 2, 6), ((45, 17, 3, 29), (3, 0, 2, 1), 4, 0, 0),
+             ((96, 80), (1, 0), 4, 4, 8), ((64, 48, 40), (2, 0, 1), 1, 1, 3), ((9, 7, 33, 13), (2, 3, 1, 0), 2, 0, 0),
+             ((5, 16, 11, 24), (0, 3, 2, 1), 1, 0, 0), ((129, 67), (1, 0), 8, 8, 0), ((31, 37, 41), (2, 1, 0), 1, 0, 0)]
+
+
+def test_emu_unaligned_micro_tiles():
+    """Odd extents and misaligned pointers keep G x G micro-tiles with unaligned
+    vector accesses; partial micro-tiles at tile edges move element by element."""
+    jobs = [_perm_job(d, p, e, 9650 + i, src_off=so, dst_off=do, umt=1) for i, (d, p, e, so, do) in enumerate(UMT_CASES)]
+    res = _check(jobs)
+    flags = [int(st.split("flags=")[1].split()[0]) for st, _ in res]
+    assert sum(bool(f & 512) for f in flags) >= len(flags) - 2, flags
+    # multi-axis A sides, tiles whose extents G does not divide
+    assert any(f & 512 and int(st.split("nA=")[1].split()[0]) > 1 for f, (st, _) in zip(flags, res)), res
+    for rb in ((64, 64), (512, 128)):
+        _check([_perm_job(d, p, e, 9680 + i, src_off=so, dst_off=do, in_rb=rb[0], out_rb=rb[1], umt=1)
+                for i, (d, p, e, so, do) in enumerate(UMT_CASES)])
+    # everywhere, aligned shapes included
+    res = _check([_perm_job(d, p, e, 9690 + i, umt=2) for i, (d, p, e) in enumerate(
+        [((96, 80), (1, 0), 1), ((64, 48, 40), (2, 0, 1), 2), ((48, 40, 32), (1, 2, 0), 4), ((32, 24, 16), (2, 1, 0), 8)])])
+    assert all(int(st.split("flags=")[1].split()[0]) & 512 for st, _ in res), res
+
+
+def test_emu_unaligned_micro_tiles_in_batches():
+    jobs = [_perm_job(d, p, e, 9700 + i) for i, (d, p, e, so, do) in enumerate(UMT_CASES)]
+    for chunk in (0, 2):
+        st, outs = emu_runner.run([dict(op="batched", jobs=jobs, chunk=chunk, umt=1)])[0]
+        assert st.startswith("ok"), st
+        for j, o in zip(jobs, outs):
+            assert np.array_equal(o, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), (j["dims"], chunk)
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),

@@ -310,3 +310,27 @@ def test_xcd_tile_ranges(rr):
             check_permute(rr, dims, perm, e, 9950 + i)
     finally:
         rr.set_tile_override()
+
+
+def test_unaligned_micro_tiles(rr):
+    """Odd extents and misaligned pointers on G x G micro-tiles with unaligned
+    vector accesses (and partial micro-tiles), at several tiles per launch."""
+    from tests.test_emulated_kernels import UMT_CASES
+    big = [((4095, 4097), (1, 0), e, 0, 0) for e in (1, 2, 4, 8)] + \
+          [((255, 257, 259), (2, 1, 0), 4, 0, 0), ((255, 257, 259), (1, 2, 0), 2, 2, 2),
+           ((255, 257, 259), (2, 0, 1), 1, 1, 0), ((1000, 999), (1, 0), 8, 8, 16)]
+    rr.set_tile_override(umt=1)
+    try:
+        nu = 0
+        for i, (dims, perm, e, so, do) in enumerate(list(UMT_CASES) + big):
+            d = rr.plan_describe(dims, perm, e, (1 << 20) + do, (1 << 30) + so)
+            nu += bool(int(d["flags"]) & 512)
+            check_permute(rr, dims, perm, e, 9960 + i, soff=so, doff=do)
+        assert nu >= len(UMT_CASES) + len(big) - 2
+        rr.set_tile_override(umt=2)
+        for i, (dims, perm, e) in enumerate([((4096, 4096), (1, 0), 4), ((512, 512, 256), (2, 0, 1), 2),
+                                             ((64, 128, 128, 64), (0, 3, 1, 2), 1)]):
+            assert int(rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)["flags"]) & 512
+            check_permute(rr, dims, perm, e, 9990 + i)
+    finally:
+        rr.set_tile_override()
