@@ -51,11 +51,13 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
         lib.oracle_permute_at.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int,
                                           i64p, ctypes.c_int64]
         lib.oracle_reorder_paper.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int]
+        lib.oracle_reorder_slice.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, i64p, ctypes.c_int, ip,
+                                             ctypes.c_int]
         lib.oracle_interlace.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int,
                                          ctypes.c_int64, ctypes.c_int]
         lib.oracle_deinterlace.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int]
-        for f in ("oracle_permute", "oracle_permute_at", "oracle_reorder_paper",
+        for f in ("oracle_permute", "oracle_permute_at", "oracle_reorder_paper", "oracle_reorder_slice",
                   "oracle_interlace", "oracle_deinterlace", "oracle_mutant_id"):
             getattr(lib, f).restype = ctypes.c_int
         _libs[mutant] = lib
@@ -120,6 +122,25 @@ def reorder_paper(src: np.ndarray, sizes, order, esize: int, mutant: int = 0) ->
                                            _i64(sizes), _i32(order), esize)
     if rc != 0:
         raise ValueError("oracle_reorder_paper rejected its arguments")
+    return out
+
+
+def reorder_slice(src: np.ndarray, dims, base, range_, order, esize: int, mutant: int = 0) -> np.ndarray:
+    """N-to-M reorder: output axis j runs over input axis order[j] from base for
+    range steps; unlisted input axes stay at their base (flat uint8 result)."""
+    dims = [int(d) for d in dims]
+    base = [int(b) for b in base]
+    range_ = [int(r) for r in range_]
+    order = [int(o) for o in order]
+    n = int(np.prod([range_[o] for o in order], dtype=np.int64)) if order else 1
+    sb = _as_bytes(src)
+    if sb.size != int(np.prod(dims, dtype=np.int64)) * esize:
+        raise ValueError("src does not hold prod(dims) elements")
+    out = np.empty(n * esize, dtype=np.uint8)
+    rc = _lib(mutant).oracle_reorder_slice(out.ctypes.data, sb.ctypes.data, len(dims), _i64(dims), _i64(base),
+                                           _i64(range_), len(order), _i32(order), esize)
+    if rc != 0:
+        raise ValueError("oracle_reorder_slice rejected its arguments")
     return out
 
 

@@ -18,6 +18,10 @@
  *   that notation (oracle_reorder_paper) and the row-major / NumPy notation
  *   (oracle_permute), so that the mapping between the two is itself checked.
  *
+ *   The same section's N-to-M reorder (oracle_reorder_slice) reads a box of
+ *   the input given by a base index and a range per dimension, keeps only the
+ *   dimensions the order lists and fixes the others at their base.
+ *
  *   Sec. III.C ("Interlace, De-Interlace Kernels"): n equally long data sets are
  *   joined so that the set index varies fastest (interlace), or one such set is
  *   split back into n (de-interlace), e.g. complex numbers into real and
@@ -231,6 +235,72 @@ int oracle_deinterlace(void* const* dsts, const void* src, int n, int64_t count,
         unsigned char* d = (unsigned char*)dsts[c];
         for (int64_t i = 0; i < count; ++i)
             memcpy(d + i * esize, s + (i * n + c) * esize, (size_t)esize);
+    }
+    return 0;
+}
+
+/*
+ * N-to-M reorder with base and range (Sec. III.B: the reorder kernel's
+ * N-to-M form keeps a base index and a range per dimension, and the output has
+ * fewer dimensions than the input).  Row-major / NumPy convention:
+ *   output axis j (0 <= j < out_ndim) runs over input axis order[j], from
+ *   base[order[j]] for range[order[j]] steps; every input axis d that order
+ *   does not list stays fixed at base[d].
+ *   dst has shape (range[order[0]], ..., range[order[out_ndim-1]]), row-major;
+ *   dst[J] = src[I] with I[order[j]] = base[order[j]] + J[j] and I[d] = base[d]
+ *   for the other axes.
+ * out_ndim = 0 copies the single element at base.  Returns 0 on success, -1 on
+ * bad arguments (order not distinct, base or range outside dims).
+ */
+int oracle_reorder_slice(void* dst, const void* src, int ndim, const int64_t* dims,
+                         const int64_t* base, const int64_t* range, int out_ndim,
+                         const int* order, int esize)
+{
+    if (ndim < 1 || ndim > ORACLE_MAX_DIMS || out_ndim < 0 || out_ndim > ndim || esize < 1) return -1;
+    int kept[ORACLE_MAX_DIMS] = {0};
+    for (int j = 0; j < out_ndim; ++j) {
+        if (order[j] < 0 || order[j] >= ndim || kept[order[j]]) return -1;
+        kept[order[j]] = 1;
+    }
+    for (int d = 0; d < ndim; ++d) {
+        if (dims[d] < 0 || base[d] < 0) return -1;
+        if (kept[d]) {
+            if (range[d] < 0 || base[d] + range[d] > dims[d]) return -1;
+        } else if (base[d] >= dims[d]) {
+            return -1;
+        }
+    }
+    int64_t in_strides[ORACLE_MAX_DIMS];
+    row_major_strides(ndim, dims, in_strides);
+    /* offset of the element every output element starts from: the fixed axes
+       at their base, the kept axes at the start of their range */
+    int64_t start = 0;
+    for (int d = 0; d < ndim; ++d) {
+#if RR_ORACLE_MUTANT == 5
+        /* planted mistake: fixed axes read at index 0 instead of their base */
+        if (!kept[d]) continue;
+#elif RR_ORACLE_MUTANT == 6
+        /* planted mistake: kept axes start at 0 instead of their base */
+        if (kept[d]) continue;
+#endif
+        start += base[d] * in_strides[d];
+    }
+    int64_t out_dims[ORACLE_MAX_DIMS];
+    int64_t J[ORACLE_MAX_DIMS];
+    int64_t total = 1;
+    for (int j = 0; j < out_ndim; ++j) { out_dims[j] = range[order[j]]; J[j] = 0; total *= out_dims[j]; }
+    if (total == 0) return 0;
+
+    unsigned char* o = (unsigned char*)dst;
+    const unsigned char* s = (const unsigned char*)src;
+    for (int64_t t = 0; t < total; ++t) {
+        int64_t i = start;
+        for (int j = 0; j < out_ndim; ++j) i += J[j] * in_strides[order[j]];
+        memcpy(o + t * esize, s + i * esize, (size_t)esize);
+        for (int j = out_ndim - 1; j >= 0; --j) {
+            if (++J[j] < out_dims[j]) break;
+            J[j] = 0;
+        }
     }
     return 0;
 }

@@ -55,6 +55,12 @@ def pin_golden(golden_dir, m=0):
             got2 = oracle.permute(_iota(n), dims, case["numpy_perm"], e, mutant=m)
             if got2.tolist() != case["expect"]:
                 return False
+        elif op == "reorder_slice":
+            n = int(np.prod(case["dims"])) * e
+            got = oracle.reorder_slice(_iota(n), case["dims"], case["base"], case["range"],
+                                       case.get("order", []), e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
         elif op == "interlace":
             planes = [np.array(p, dtype=np.uint8) for p in case["planes"]]
             got = oracle.interlace(planes, e, mutant=m)
@@ -179,6 +185,60 @@ def pin_paper_notation(m=0):
     return True
 
 
+def _np_reorder_slice(x_bytes, dims, base, range_, order, esize):
+    """NumPy slicing + transpose on a (dims..., esize) byte view; independent of the oracle."""
+    a = x_bytes.reshape(tuple(dims) + (esize,))
+    idx = tuple(slice(base[d], base[d] + range_[d]) if d in order else base[d] for d in range(len(dims)))
+    sub = a[idx]                                # kept axes, in input order, then the byte axis
+    kept = sorted(order)
+    axes = tuple(kept.index(o) for o in order) + (len(order),)
+    return np.ascontiguousarray(np.transpose(sub, axes)).reshape(-1)
+
+
+def _random_slices(seed, count, max_rank=5):
+    g = rr_synth.rng(seed)
+    out = []
+    for _ in range(count):
+        nd = int(g.integers(1, max_rank + 1))
+        dims = [int(g.integers(1, 7)) for _ in range(nd)]
+        m = int(g.integers(0, nd + 1))
+        order = [int(v) for v in g.permutation(nd)[:m]]
+        base, range_ = [], []
+        for d in range(nd):
+            b = int(g.integers(0, dims[d]))
+            base.append(b)
+            range_.append(int(g.integers(0, dims[d] - b + 1)) if d in order else 1)
+        out.append((dims, base, range_, order, int(g.choice([1, 2, 3, 4, 8]))))
+    return out
+
+
+def pin_reorder_slice_numpy(m=0):
+    """N-to-M reorder == NumPy slicing (fixed axes indexed, kept axes sliced) + transpose."""
+    for i, (dims, base, range_, order, e) in enumerate(_random_slices(31, 300)):
+        x = rr_synth.random_bytes(600 + i, int(np.prod(dims)) * e)
+        got = oracle.reorder_slice(x, dims, base, range_, order, e, mutant=m)
+        if not np.array_equal(got, _np_reorder_slice(x, dims, base, range_, order, e)):
+            return False
+    return True
+
+
+def pin_reorder_slice_reduces_to_permute(m=0):
+    """With every axis kept at full range the N-to-M reorder is the permute; a box is
+    the permute of the box cut out first (NumPy copy)."""
+    for dims, perm, e in [((5, 7, 3), (2, 0, 1), 4), ((2, 3, 4, 5), (3, 1, 0, 2), 2)]:
+        x = rr_synth.random_bytes(41, int(np.prod(dims)) * e)
+        full = oracle.reorder_slice(x, dims, [0] * len(dims), dims, perm, e, mutant=m)
+        if not np.array_equal(full, oracle.permute(x, dims, perm, e, mutant=m)):
+            return False
+        base = [1] * len(dims)
+        rng = [d - 1 for d in dims]
+        box = np.ascontiguousarray(x.reshape(tuple(dims) + (e,))[tuple(slice(1, d) for d in dims)]).reshape(-1)
+        got = oracle.reorder_slice(x, dims, base, rng, perm, e, mutant=m)
+        if not np.array_equal(got, oracle.permute(box, rng, perm, e, mutant=m)):
+            return False
+    return True
+
+
 def pin_permute_at(m=0):
     dims, perm, e = (6, 5, 7, 3), (3, 0, 2, 1), 4
     x = rr_synth.random_bytes(21, int(np.prod(dims)) * e)
@@ -197,6 +257,8 @@ ALL_PINS = {
     "interlace": lambda gd, m: pin_interlace_numpy(m),
     "paper_notation": lambda gd, m: pin_paper_notation(m),
     "permute_at": lambda gd, m: pin_permute_at(m),
+    "reorder_slice_numpy": lambda gd, m: pin_reorder_slice_numpy(m),
+    "reorder_slice_permute": lambda gd, m: pin_reorder_slice_reduces_to_permute(m),
 }
 
 
@@ -206,10 +268,11 @@ def test_oracle_pin(name, golden_dir):
     assert ALL_PINS[name](golden_dir, 0), f"oracle fails pin {name}"
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
 def test_planted_mistake_is_caught(mutant, golden_dir):
     """Each planted oracle mistake (gather/scatter swap, dropped term, wrong stride,
-    transposed interlace) must fail at least one pin."""
+    transposed interlace, fixed axes read at 0, box start ignored) must fail at
+    least one pin."""
     oracle.build(mutant, force=False)
     assert oracle.mutant_id(mutant) == mutant
     failed = []
