@@ -346,6 +346,10 @@ def main():
             side["interlace"] = bench_interlace(rr, rr_synth, pool, out, stream, timed)
         except Exception as ex:  # side measurements never hide the main line
             side["interlace"] = {"error": str(ex)}
+        try:
+            side["reorder"] = bench_reorder(rr, pool, out, stream, timed)
+        except Exception as ex:
+            side["reorder"] = {"error": str(ex)}
         del pool, out, flush
         torch.cuda.empty_cache()
         try:
@@ -364,6 +368,36 @@ def main():
         result["cpu_baseline"] = cpu
 
     print(json.dumps(result), flush=True)
+
+
+# N-to-M reorders (base and range): name, input dims, base, range, order, element bytes
+REORDER_CASES = [
+    ("crop_transpose_3d", (512, 512, 256), (16, 16, 0), (480, 480, 256), (2, 0, 1), 4),
+    ("nhwc_to_nchw_batch_slice", (64, 128, 128, 64), (8, 0, 0, 0), (48, 128, 128, 64), (0, 3, 1, 2), 2),
+    ("fixed_axis_4d", (4, 16, 2048, 2048), (0, 5, 0, 0), (4, 1, 2048, 2048), (2, 0, 3), 4),
+    ("row_slab", (16384, 16384), (4096, 0), (8192, 16384), (0, 1), 4),
+    ("hwc_channel_2", (16384, 16384, 4), (0, 0, 2), (16384, 16384, 1), (0, 1), 1),
+]
+
+
+def bench_reorder(rr, pool, out, stream, timed):
+    """Effective GB/s (2 x output bytes / time) of N-to-M reorders of pool data; the
+    plan class says whether the box tiled, copied or had to gather."""
+    res = {}
+    for name, dims, base, rng, order, e in REORDER_CASES:
+        nout = 1
+        for o in order:
+            nout *= rng[o]
+        nin = e
+        for d in dims:
+            nin *= d
+        assert nin <= pool.numel() and nout * e <= out.numel()
+        src = pool.data_ptr()
+        d = rr.reorder_describe(dims, base, rng, order, e, out.data_ptr(), src)
+        t = timed(lambda: rr.check(rr.reorder_raw(out.data_ptr(), src, dims, base, rng, order, e, stream.cuda_stream)), 5)
+        res[name] = {"GBps": round(2 * nout * e / t / 1e9, 1), "class": d["class"],
+                     "out_bytes": nout * e, "kernel": kernel_name(d)}
+    return res
 
 
 def bench_interlace(rr, rr_synth, pool, out, stream, timed):

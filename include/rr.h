@@ -69,6 +69,33 @@ rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims,
                      const int* perm, int elem_size, rr_stream_t stream);
 
 /* -------------------------------------------------------------------------
+ * N-to-M reorder with base and range (Sec. III.B, the reorder kernel's N-to-M
+ * form): a box of the input, fewer dimensions out.
+ *   Output axis j (0 <= j < out_ndim) runs over input axis order[j] from
+ *   base[order[j]] for range[order[j]] steps; every input axis d not listed in
+ *   order stays fixed at base[d]:
+ *     dst[J] = src[I],  I[order[j]] = base[order[j]] + J[j],  I[d] = base[d].
+ *   dst     device buffer of prod_j range[order[j]] * elem_size bytes, row-major
+ *           over (range[order[0]], ..., range[order[out_ndim-1]]).
+ *   src     device buffer of prod(dims)*elem_size bytes, row-major over dims
+ *           (only the box is read).
+ *   ndim    1..RR_MAX_DIMS; out_ndim 0..ndim (0: the single element at base).
+ *   base    host array of ndim offsets, or NULL for all zeros; a fixed axis
+ *           needs 0 <= base < dims.
+ *   range   host array of ndim extents (entries of fixed axes are ignored), or
+ *           NULL for "to the end"; a kept axis needs base + range <= dims.
+ *   order   host array of out_ndim distinct axes of 0..ndim-1.
+ * A box whose fastest input axis is kept and contiguous is tiled like
+ * rr_permute; one that drops or cuts the input's fastest axis is gathered
+ * element by element (reads cannot be coalesced there).
+ * Errors: RR_ERR_INVALID_ARG, RR_ERR_OVERFLOW, RR_ERR_ALIAS (dst overlaps the
+ * byte range spanned by the box), RR_ERR_UNSUPPORTED, RR_ERR_HIP.
+ */
+rr_status rr_reorder(void* dst, const void* src, int ndim, const int64_t* dims, const int64_t* base,
+                     const int64_t* range, int out_ndim, const int* order, int elem_size,
+                     rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
  * Interlace (Sec. III.C): join n equally long data sets, set index fastest:
  *   dst[i*n + c] = srcs[c][i]    for 0 <= i < count, 0 <= c < n.
  *   dst   device buffer of n*count*elem_size bytes.
@@ -242,6 +269,11 @@ rr_status rr_order_to_perm(int ndim, const int* paper_order, int* perm_out);
  * "class=... rank=... dims=... perm=... esize_bytes=... unit=... ..." into buf.
  * Alignment is taken from the two pointer values (which need not be valid).
  */
+/* The same for the plan rr_reorder would use (alignment from dst and from src
+ * plus the box's offset). */
+rr_status rr_reorder_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
+                              const int64_t* base, const int64_t* range, int out_ndim, const int* order,
+                              int elem_size, char* buf, int buflen);
 rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
                            const int* perm, int elem_size, char* buf, int buflen);
 

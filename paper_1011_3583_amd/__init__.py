@@ -25,12 +25,12 @@ STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_
 STATUS_CODE = {v: k for k, v in STATUS.items()}
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
-EXPORTS = ("rr_permute", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
+EXPORTS = ("rr_permute", "rr_reorder", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
            "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
            "rr_serve_get_stats", "rr_serve_fail_next_batch",
-           "rr_order_to_perm", "rr_plan_describe", "rr_set_tile_override",
+           "rr_order_to_perm", "rr_plan_describe", "rr_reorder_describe", "rr_set_tile_override",
            "rr_tune_permute", "rr_tune_save", "rr_tune_load", "rr_tune_clear",
            "rr_status_string", "rr_last_error", "rr_version")
 
@@ -111,6 +111,8 @@ def lib() -> ctypes.CDLL:
     L.rr_serve_get_stats.argtypes = [vp, ctypes.POINTER(ServeStats)]
     L.rr_order_to_perm.argtypes = [i32, i32p, i32p]
     L.rr_plan_describe.argtypes = [vp, vp, i32, i64p, i32p, i32, ctypes.c_char_p, i32]
+    L.rr_reorder.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, vp]
+    L.rr_reorder_describe.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
     L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
@@ -160,6 +162,17 @@ def permute_raw(dst: int, src: int, dims, perm, elem_size: int, stream=0) -> int
     """rr_permute on raw device addresses; returns the rr_status (no raise)."""
     return lib().rr_permute(dst, src, len(dims), _i64(dims), _i32(perm), int(elem_size),
                             _stream_handle(stream))
+
+
+def _opt_i64(seq):
+    return None if seq is None else _i64(seq)
+
+
+def reorder_raw(dst: int, src: int, dims, base, range_, order, elem_size: int, stream=0) -> int:
+    """rr_reorder (N-to-M box reorder) on raw device addresses; returns the rr_status.
+    base / range_ may be None (zeros / to the end)."""
+    return lib().rr_reorder(dst, src, len(dims), _i64(dims), _opt_i64(base), _opt_i64(range_), len(order),
+                            _i32(order), int(elem_size), _stream_handle(stream))
 
 
 def interlace_raw(dst: int, srcs, count: int, elem_size: int, stream=0) -> int:
@@ -245,6 +258,13 @@ def plan_describe(dims, perm, elem_size: int, dst: int = 0, src: int = 0) -> dic
         k, v = tok.split("=", 1)
         out[k] = v
     return out
+
+
+def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, src: int = 0) -> dict:
+    buf = ctypes.create_string_buffer(1024)
+    check(lib().rr_reorder_describe(dst, src, len(dims), _i64(dims), _opt_i64(base), _opt_i64(range_), len(order),
+                                    _i32(order), int(elem_size), buf, 1024))
+    return dict(tok.split("=", 1) for tok in buf.value.decode().split())
 
 
 def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None,

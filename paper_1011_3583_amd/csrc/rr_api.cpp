@@ -67,6 +67,56 @@ rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims, 
     return RR_OK;
 }
 
+static rr_status validate_reorder(const void* dst, const void* src, int ndim, const int64_t* dims,
+                                  const int64_t* base, const int64_t* range, int out_ndim, const int* order,
+                                  int elem_size, Canon* c, uint64_t* off) {
+    std::string why;
+    uint64_t span = 0;
+    rr_status st = canonicalize_view(ndim, dims, base, range, out_ndim, order, elem_size, c, off, &span, &why);
+    if (st != RR_OK) return fail(st, why);
+    if (c->total_bytes == 0) return RR_OK;
+    if (!dst || !src) return fail(RR_ERR_INVALID_ARG, "NULL buffer for a non-empty problem");
+    if (ranges_overlap((uint64_t)dst, (uint64_t)c->total_bytes, (uint64_t)src + *off, span))
+        return fail(RR_ERR_ALIAS, "destination overlaps the box read from the source");
+    return RR_OK;
+}
+
+rr_status rr_reorder(void* dst, const void* src, int ndim, const int64_t* dims, const int64_t* base,
+                     const int64_t* range, int out_ndim, const int* order, int elem_size,
+                     rr_stream_t stream) {
+    clear_error();
+    Canon c;
+    uint64_t off = 0;
+    rr_status st = validate_reorder(dst, src, ndim, dims, base, range, out_ndim, order, elem_size, &c, &off);
+    if (st != RR_OK) return st;
+    if (c.total_bytes == 0) return RR_OK;
+    Plan p;
+    std::string why;
+    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, tile_override(), &p, &why);
+    if (st != RR_OK) return fail(st, why);
+    hipError_t e = launch_plan(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rr_reorder launch");
+    return RR_OK;
+}
+
+rr_status rr_reorder_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
+                              const int64_t* base, const int64_t* range, int out_ndim, const int* order,
+                              int elem_size, char* buf, int buflen) {
+    clear_error();
+    if (!buf || buflen < 1) return fail(RR_ERR_INVALID_ARG, "NULL output buffer");
+    Canon c;
+    uint64_t off = 0, span = 0;
+    std::string why;
+    rr_status st = canonicalize_view(ndim, dims, base, range, out_ndim, order, elem_size, &c, &off, &span, &why);
+    if (st != RR_OK) return fail(st, why);
+    Plan p;
+    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, tile_override(), &p, &why);
+    if (st != RR_OK) return fail(st, why);
+    std::string s = describe(p);
+    std::snprintf(buf, (size_t)buflen, "%s", s.c_str());
+    return RR_OK;
+}
+
 static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
                                   int elem_size, rr_stream_t stream, bool de) {
     clear_error();

@@ -56,6 +56,10 @@ std::string tune_key(const Canon& c, uint64_t dst, uint64_t src) {
     for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.dims[i]);
     k += ":p";
     for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.perm[i]);
+    if (c.strided) {
+        k += ":s";
+        for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.sinb[i]);
+    }
     return k;
 }
 
@@ -197,6 +201,121 @@ rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_
     c.elem_bytes = R;
     c.count = 1;
     for (int k = 0; k < rc; ++k) { c.dims[k] = cd[k]; c.perm[k] = cp[k]; c.count *= cd[k]; }
+    int64_t s = R;
+    for (int k = rc - 1; k >= 0; --k) { c.sinb[k] = s; s *= cd[k]; }
+    *out = c;
+    return RR_OK;
+}
+
+rr_status canonicalize_view(int ndim, const int64_t* dims, const int64_t* base, const int64_t* range,
+                            int out_ndim, const int* order, int elem_size, Canon* out, uint64_t* src_off,
+                            uint64_t* span, std::string* why) {
+    if (ndim > RR_MAX_DIMS) { *why = "ndim exceeds RR_MAX_DIMS"; return RR_ERR_UNSUPPORTED; }
+    if (ndim < 1) { *why = "ndim must be >= 1"; return RR_ERR_INVALID_ARG; }
+    if (out_ndim < 0 || out_ndim > ndim) { *why = "out_ndim must be 0..ndim"; return RR_ERR_INVALID_ARG; }
+    if (!dims || (out_ndim > 0 && !order)) { *why = "dims and order must be non-NULL"; return RR_ERR_INVALID_ARG; }
+    if (elem_size < 1 || elem_size > 16) { *why = "elem_size must be 1..16"; return RR_ERR_INVALID_ARG; }
+    bool kept[MAXR] = {};
+    for (int j = 0; j < out_ndim; ++j) {
+        if (order[j] < 0 || order[j] >= ndim || kept[order[j]]) {
+            *why = "order must list distinct axes of 0..ndim-1";
+            return RR_ERR_INVALID_ARG;
+        }
+        kept[order[j]] = true;
+    }
+    int64_t b[MAXR], ext[MAXR];
+    int64_t total_in = 1;
+    for (int d = 0; d < ndim; ++d) {
+        if (dims[d] < 0) { *why = "negative extent"; return RR_ERR_INVALID_ARG; }
+        if (mul_ovf(total_in, dims[d], &total_in)) { *why = "element count overflows int64"; return RR_ERR_OVERFLOW; }
+        b[d] = base ? base[d] : 0;
+        if (b[d] < 0) { *why = "negative base"; return RR_ERR_INVALID_ARG; }
+        if (kept[d]) {
+            ext[d] = range ? range[d] : dims[d] - b[d];
+            if (ext[d] < 0 || b[d] > dims[d] || ext[d] > dims[d] - b[d]) {
+                *why = "base + range exceeds the extent of a kept axis";
+                return RR_ERR_INVALID_ARG;
+            }
+        } else {
+            ext[d] = 1;
+            if (b[d] >= dims[d]) { *why = "base of a fixed axis is outside its extent"; return RR_ERR_INVALID_ARG; }
+        }
+    }
+    int64_t in_bytes;
+    if (mul_ovf(total_in, elem_size, &in_bytes)) { *why = "byte count overflows int64"; return RR_ERR_OVERFLOW; }
+    int64_t st[MAXR];   // element strides of the whole input
+    {
+        int64_t s = 1;
+        for (int d = ndim - 1; d >= 0; --d) { st[d] = s; s *= std::max<int64_t>(dims[d], 1); }
+    }
+    int64_t count = 1;
+    for (int j = 0; j < out_ndim; ++j) count *= ext[order[j]];
+    Canon c;
+    c.total_bytes = count * elem_size;
+    *src_off = 0;
+    *span = 0;
+    if (count == 0) {
+        c.rank = 0; c.count = 0; c.elem_bytes = elem_size;
+        *out = c;
+        return RR_OK;
+    }
+    int64_t off = 0, last = 0;
+    for (int d = 0; d < ndim; ++d) {
+        off += b[d] * st[d];
+        last += (ext[d] - 1) * st[d];
+    }
+    *src_off = (uint64_t)(off * elem_size);
+    *span = (uint64_t)((last + 1) * elem_size);
+    // kept axes of extent > 1, in input order, with their strides
+    int newidx[MAXR];
+    int64_t d2[MAXR], s2[MAXR];
+    int r = 0;
+    for (int d = 0; d < ndim; ++d) {
+        if (kept[d] && ext[d] != 1) { newidx[d] = r; d2[r] = ext[d]; s2[r] = st[d]; ++r; } else newidx[d] = -1;
+    }
+    int p[MAXR];
+    int j2 = 0;
+    for (int j = 0; j < out_ndim; ++j)
+        if (newidx[order[j]] >= 0) p[j2++] = newidx[order[j]];
+    // fuse output-consecutive axes that are input-consecutive and contiguous in the box
+    int gstart[MAXR], glen[MAXR];
+    int ng = 0;
+    for (int j = 0; j < r; ++j) {
+        if (j > 0 && p[j] == p[j - 1] + 1 && s2[p[j - 1]] == s2[p[j]] * d2[p[j]]) glen[ng - 1]++;
+        else { gstart[ng] = p[j]; glen[ng] = 1; ++ng; }
+    }
+    int rank_of[MAXR];
+    for (int g = 0; g < ng; ++g) {
+        int rk = 0;
+        for (int h = 0; h < ng; ++h) if (gstart[h] < gstart[g]) ++rk;
+        rank_of[g] = rk;
+    }
+    int64_t cd[MAXR], cs[MAXR];
+    int cp[MAXR];
+    for (int g = 0; g < ng; ++g) {
+        int64_t e = 1;
+        for (int a = 0; a < glen[g]; ++a) e *= d2[gstart[g] + a];
+        cd[rank_of[g]] = e;
+        cs[rank_of[g]] = s2[gstart[g] + glen[g] - 1] * elem_size;   // innermost member's stride
+        cp[g] = rank_of[g];
+    }
+    // fold trailing axes that are fastest on both sides and contiguous into the element
+    int64_t R = elem_size;
+    int rc = ng;
+    while (rc >= 1 && cp[rc - 1] == rc - 1 && cs[rc - 1] == R) {
+        R *= cd[rc - 1];
+        --rc;
+    }
+    c.rank = rc;
+    c.elem_bytes = R;
+    c.count = 1;
+    int64_t dense = R;
+    c.strided = false;
+    for (int k = rc - 1; k >= 0; --k) {
+        c.dims[k] = cd[k]; c.perm[k] = cp[k]; c.sinb[k] = cs[k]; c.count *= cd[k];
+        if (cs[k] != dense) c.strided = true;
+        dense *= cd[k];
+    }
     *out = c;
     return RR_OK;
 }
@@ -233,22 +352,23 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
     const int r = c.rank;
     const int64_t R = c.elem_bytes;
     uint32_t W = 16;
-    while (W > 1 && (src % W || dst % W || R % W)) W >>= 1;
+    auto strides_ok = [&](uint32_t w) {
+        for (int k = 0; k < r; ++k) if (c.sinb[k] % w) return false;
+        return true;
+    };
+    while (W > 1 && (src % W || dst % W || R % W || !strides_ok(W))) W >>= 1;
     int64_t vpr = R / W;
     int64_t nvec = c.count * vpr;
     if (vpr > 0xffffffffLL || nvec > 0xffffffffLL) {
         *why = "run-copy problem exceeds 2^32 vectors per launch";
         return RR_ERR_UNSUPPORTED;
     }
-    int64_t sin_el[MAXR];
-    int64_t s = 1;
-    for (int k = r - 1; k >= 0; --k) { sin_el[k] = s; s *= c.dims[k]; }
     a.src = src; a.dst = dst; a.nvec = (uint32_t)nvec; a.vpr = (uint32_t)vpr;
     a.mvpr = make_magic((uint32_t)vpr); a.wbytes = W; a.nax = r; a.run_bytes = (uint64_t)R;
     for (int j = 0; j < r; ++j) {
         a.on[j] = (uint32_t)c.dims[c.perm[j]];
         a.om[j] = make_magic(a.on[j]);
-        a.sin[j] = (uint64_t)(sin_el[c.perm[j]] * R);
+        a.sin[j] = (uint64_t)c.sinb[c.perm[j]];
     }
     uint64_t per_block = (uint64_t)NT * 4;
     uint64_t g = ((uint64_t)nvec + per_block - 1) / per_block;
@@ -355,19 +475,20 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const int64_t* d = c.dims;
     const int* pm = c.perm;
     const int64_t R = c.elem_bytes;
-    int pos[MAXR];
-    for (int j = 0; j < r; ++j) pos[pm[j]] = j;
-    int64_t sin_el[MAXR], sout_el[MAXR];
+    const int64_t* sinb = c.sinb;   // input byte strides (the fastest axis's is R)
+    int64_t sout_el[MAXR];
     {
         int64_t s = 1;
-        for (int k = r - 1; k >= 0; --k) { sin_el[k] = s; s *= d[k]; }
-        s = 1;
         for (int j = r - 1; j >= 0; --j) { sout_el[pm[j]] = s; s *= d[pm[j]]; }
     }
     int U = pow2_divisor_cap16(R);
     U = std::min(U, std::min(addr_align(src), addr_align(dst)));
+    for (int q = 0; q < r; ++q) U = std::min(U, addr_align((uint64_t)sinb[q]));
     const int k = (int)(R / U);
     const int a1 = r - 1, b1 = pm[r - 1];
+    // every input row starts at a multiple of this (plus the tile's column offset)
+    uint64_t row_starts = 0;
+    for (int q = 0; q < r; ++q) if (q != a1) row_starts |= (uint64_t)sinb[q];
     int G = 1;
     bool umt = false;
     if (k == 1 && !opt.force_ragged) {
@@ -377,7 +498,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         const int Gdef = opt.max_g > 0 ? std::min(16 / U, opt.max_g) : (U <= 2 ? 8 / U : 16 / U);
         G = Gdef;
         while (G > 1 && ((d[a1] % G) || (d[b1] % G) || addr_align(src) < U * G ||
-                         addr_align(dst) < U * G))
+                         addr_align(dst) < U * G || (row_starts % (uint64_t)(U * G))))
             G >>= 1;
         // Odd extents or pointers rule out aligned micro-tiles: on request keep them
         // anyway with unaligned vector accesses when both fastest extents hold one
@@ -408,8 +529,8 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     B[nB++] = b1; inB[b1] = true;
     int64_t prodA = d[a1], prodB = d[b1];
     int nxA = r - 2, nxB = r - 2;
-    auto growA = [&]() {
-        for (; prodA < targetA && nxA >= 0 && !inB[nxA] && nA < MAXS; --nxA) {
+    auto growA = [&]() {   // A's axes must stay one contiguous input run
+        for (; prodA < targetA && nxA >= 0 && !inB[nxA] && nA < MAXS && sinb[nxA] == prodA * R; --nxA) {
             A[nA++] = nxA; inA[nxA] = true; prodA *= d[nxA];
         }
     };
@@ -479,14 +600,14 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     {
         const int64_t msub = innerA * t[aO] * innerB * t[bO] * R;
         if (k == 1 && U < 16 && r >= 3 && nA == 1 && nB == 1 && t[a1] == d[a1] && t[b1] == d[b1] &&
-            b1 == r - 2 && pm[r - 2] == a1 && msub * 2 <= soft_bytes) {
+            b1 == r - 2 && pm[r - 2] == a1 && sinb[b1] == d[a1] * R && msub * 2 <= soft_bytes) {
             cax = r - 3;
             G = 1;
             umt = false;
             t[cax] = std::min<int64_t>(d[cax], std::max<int64_t>(1, soft_bytes / msub));
             a.flags |= TF_STACK;
             a.msub = a.msubp = (uint32_t)msub;
-            a.sinC = (uint64_t)(sin_el[cax] * R);
+            a.sinC = (uint64_t)sinb[cax];
             a.soutC = (uint64_t)(sout_el[cax] * R);
         }
     }
@@ -504,7 +625,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     }
     for (int i = 0; i < nB; ++i) {
         a.tB[i] = (uint32_t)t[B[i]]; a.mB[i] = make_magic(a.tB[i]);
-        a.sinB[i] = (uint64_t)(sin_el[B[i]] * R);
+        a.sinB[i] = (uint64_t)sinb[B[i]];
     }
     a.R = (uint32_t)R;
     a.src = src; a.dst = dst;
@@ -526,7 +647,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         int g = a.ngrid++;
         a.gn[g] = (uint32_t)n; a.gm[g] = make_magic((uint32_t)n);
         int64_t step = tiled ? t[s] : 1;
-        a.gsin[g] = (uint64_t)(step * sin_el[s] * R);
+        a.gsin[g] = (uint64_t)(step * sinb[s]);
         a.gsout[g] = (uint64_t)(step * sout_el[s] * R);
         if (s == aO) a.grid_aO = g;
         if (s == bO) a.grid_bO = g;
@@ -538,12 +659,12 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     a.bO_len = (uint32_t)d[bO]; a.bO_t = (uint32_t)t[bO];
     if (cax >= 0) { a.cO_len = (uint32_t)d[cax]; a.cO_t = (uint32_t)t[cax]; }
     a.ntiles = (uint32_t)ntiles;
-    // input rows start at multiples of d[a1]*R plus the tile's column offset
-    uint64_t ra = src | (uint64_t)(d[a1] * R);
+    // input rows start at multiples of the other axes' strides plus the tile's column offset
+    uint64_t ra = src | row_starts;
     if (nA == 1) ra |= (uint64_t)(t[a1] * R);
     // rows are back to back when every A axis is whole and the single B axis is
-    // the next slower input axis
-    const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA;
+    // the next slower input axis, adjacent to them
+    const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA && sinb[b1] == innerA * t[aO] * R;
     if (umt) a.flags |= TF_UMT;
     rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, (uint64_t)d[b1], opt, why);
     if (st != RR_OK) return st;
@@ -560,6 +681,9 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.count == 0 || c.total_bytes == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (c.rank == 0) { plan_copy(dst, src, (uint64_t)c.total_bytes, p); return RR_OK; }
     if (c.elem_bytes >= RUN_MIN_BYTES) return plan_run(dst, src, c, p, why);
+    // a box whose fastest input axis is not contiguous (a dropped or cut innermost
+    // axis) has no input rows to tile: gather its elements (one run each)
+    if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
     // a tuned shape for this problem replaces the built-in choice (not an explicit override)
     TileOptions tuned;
     if (!tile_override_active() && &opt == &tile_override() && tune_lookup(tune_key(c, dst, src), &tuned)) {

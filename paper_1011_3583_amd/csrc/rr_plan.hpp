@@ -32,8 +32,10 @@ inline uint32_t magic_div_host(uint32_t x, Magic m) {
 // and in order, and folding the trailing unpermuted axis into the element.
 struct Canon {
     int rank = 0;              // 0 means "plain copy of elem_bytes * count bytes"
-    int64_t dims[MAXR] = {};   // row-major input extents
+    int64_t dims[MAXR] = {};   // input extents, slowest axis first
     int perm[MAXR] = {};       // out axis j reads input axis perm[j]
+    int64_t sinb[MAXR] = {};   // input byte stride of each axis (row-major for a dense input)
+    bool strided = false;      // sinb differs from the dense row-major strides of dims
     int64_t elem_bytes = 0;    // bytes per canonical element (run length)
     int64_t count = 0;         // canonical elements (product of dims)
     int64_t total_bytes = 0;   // bytes per side
@@ -161,6 +163,13 @@ int tune_parse(const std::string& text);
 // Validation + canonicalisation.  Writes a human-readable reason on failure.
 rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_size,
                        Canon* out, std::string* why);
+// N-to-M reorder: the box of a dense input given by base and range (NULL base =
+// zeros, NULL range = up to the end) with only the axes listed in order kept.
+// On success *src_off is the byte offset of the box's first element and *span
+// the byte length from there to the end of its last element.
+rr_status canonicalize_view(int ndim, const int64_t* dims, const int64_t* base, const int64_t* range,
+                            int out_ndim, const int* order, int elem_size, Canon* out, uint64_t* src_off,
+                            uint64_t* span, std::string* why);
 
 // Alignment (largest power of two <= 16 dividing the address).
 inline int addr_align(uint64_t p) {

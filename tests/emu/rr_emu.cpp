@@ -11,6 +11,7 @@
 //
 // Input: a manifest, one job per line:
 //   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt infile outfile
+//   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
 //   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
 //   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
@@ -207,6 +208,39 @@ int main(int argc, char** argv) {
             if (nb) std::memcpy(sbuf + soff, in.data(), nb);
             std::memset(dbuf, 0x5A, doff + nb + 1);
             st = plan_permute((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff), c, opt, &plan, &why);
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); delete[] sbuf; delete[] dbuf; continue; }
+            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); delete[] sbuf; delete[] dbuf; continue; }
+            if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+            for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
+            write_file(outf, dbuf + doff, nb);
+            std::printf("ok %s\n", describe(plan).c_str());
+            delete[] sbuf;
+            delete[] dbuf;
+        } else if (op == "reorder") {
+            int ndim; is >> ndim;
+            std::vector<int64_t> dims(ndim), base(ndim), range(ndim);
+            for (auto& d : dims) is >> d;
+            for (auto& d : base) is >> d;
+            for (auto& d : range) is >> d;
+            int m; is >> m;
+            std::vector<int> order(std::max(m, 1));
+            for (int j = 0; j < m; ++j) is >> order[j];
+            int esize, soff, doff; std::string inf, outf;
+            is >> esize >> soff >> doff >> opt.umt >> opt.max_g >> inf >> outf;
+            Canon c;
+            uint64_t off = 0, span = 0;
+            rr_status st = canonicalize_view(ndim, dims.data(), base.data(), range.data(), m, order.data(), esize, &c,
+                                             &off, &span, &why);
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); continue; }
+            std::vector<uint8_t> in = read_file(inf);
+            const size_t ni = in.size();
+            const size_t nb = (size_t)c.total_bytes;
+            uint8_t* sbuf = new uint8_t[soff + ni + 1];
+            uint8_t* dbuf = new uint8_t[doff + nb + 1];
+            if (ni) std::memcpy(sbuf + soff, in.data(), ni);
+            std::memset(dbuf, 0x5A, doff + nb + 1);
+            if (nb && off + span > ni) { std::printf("err -3 box outside the input\n"); return 3; }
+            st = plan_permute((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff) + off, c, opt, &plan, &why);
             if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); delete[] sbuf; delete[] dbuf; continue; }
             if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); delete[] sbuf; delete[] dbuf; continue; }
             if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }

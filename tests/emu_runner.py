@@ -40,6 +40,7 @@ def run(jobs):
     """Run jobs through the emulator.  Each job is a dict:
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
                     max_g, ragged, xcd, umt
+       reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
        deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb
     Returns a list of (status_line, output) with output a uint8 array or list of planes."""
@@ -58,6 +59,13 @@ def run(jobs):
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))), str(int(j.get("xcd", False))),
                                        str(int(j.get("umt", 0))), inf, outf]))
+            elif j["op"] == "reorder":
+                j["input"].tofile(inf)
+                nd = len(j["dims"])
+                lines.append(" ".join(["reorder", str(nd), *map(str, j["dims"]), *map(str, j["base"]),
+                                       *map(str, j["range"]), str(len(j["order"])), *map(str, j["order"]),
+                                       str(j["esize"]), str(j.get("src_off", 0)), str(j.get("dst_off", 0)),
+                                       str(int(j.get("umt", 0))), str(j.get("max_g", 0)), inf, outf]))
             elif j["op"] == "interlace":
                 np.concatenate(j["planes"]).tofile(inf)
                 lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")

@@ -217,3 +217,43 @@ def test_no_kernel_uses_scratch():
     assert any("k_tile" in k for k in kernels)
     used = {k: v["ScratchSize [bytes/lane]"] for k, v in kernels.items() if v["ScratchSize [bytes/lane]"]}
     assert not used, used
+
+
+def test_reorder_validation_and_aliasing():
+    """rr_reorder (N-to-M with base and range) rejects bad boxes before any launch."""
+    dims = (4, 5, 6)
+    ok = dict(dst=0x100000, src=0x1000)
+    st = lambda b, r, o, e=4, **kw: rr.reorder_raw(kw.get("dst", ok["dst"]), kw.get("src", ok["src"]), dims, b, r, o, e)
+    assert st((0, 0, 0), (4, 5, 6), (2, 0, 0)) == 1       # repeated axis
+    assert st((0, 0, 0), (4, 5, 6), (3, 0)) == 1          # axis out of range
+    assert st((0, 0, 0), (4, 5, 7), (2, 1, 0)) == 1       # range past the extent
+    assert st((0, 0, 5), (4, 5, 2), (2, 1, 0)) == 1       # base + range past the extent
+    assert st((0, 5, 0), (4, 1, 6), (2, 0)) == 1          # fixed axis base outside
+    assert st((-1, 0, 0), (4, 5, 6), (2, 1, 0)) == 1      # negative base
+    assert st((0, 0, 0), (4, 5, 6), (2, 1, 0), 0) == 1    # elem_size
+    assert rr.reorder_raw(0x1000, 0x1000, (2,) * 9, None, None, tuple(range(9)), 1) == 4   # rank > 8
+    assert st((0, 0, 0), (4, 5, 6), (2, 1, 0), dst=0, src=0x1000) == 1   # NULL
+    # aliasing: the box (rows 2..3: bytes 240..479 from src) against dst's 240 bytes
+    assert st((2, 0, 0), (2, 5, 6), (1, 2, 0), dst=0x1000, src=0x1000 - 100) == 3
+    assert st((2, 0, 0), (2, 5, 6), (1, 2, 0), dst=0x1000 + 300, src=0x1000) == 3
+    assert st((2, 0, 0), (2, 5, 6), (1, 2, 0), dst=0x1000 + 479, src=0x1000) == 3
+    # empty boxes are a no-op even with NULL pointers
+    assert rr.reorder_raw(0, 0, dims, (0, 0, 0), (0, 5, 6), (0, 1, 2), 4) == 0
+
+
+def test_reorder_plans_match_permute_and_classes():
+    """A full box with every axis kept plans exactly like rr_permute; boxes that
+    keep the input's fastest axis contiguous tile; dropping or cutting it gathers."""
+    for dims, perm, e in [((512, 512, 256), (2, 0, 1), 4), ((64, 128, 128, 64), (0, 3, 1, 2), 2), ((4096, 4096), (1, 0), 1)]:
+        a = rr.reorder_describe(dims, None, None, perm, e, dst=1 << 20, src=1 << 30)
+        b = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+        assert a == b
+    # a 2-D crop of a 3-D array, transposed: strided box, tile class
+    d = rr.reorder_describe((70, 90, 40), (3, 5, 7), (60, 80, 30), (2, 1, 0), 4, dst=1 << 20, src=1 << 30)
+    assert d["class"] == "tile" and d["dims"] == "60,80,30"
+    # channel 2 of an HWC image: the fastest axis is dropped -> gather
+    d = rr.reorder_describe((256, 256, 4), (0, 0, 2), None, (0, 1), 1, dst=1 << 20, src=1 << 30)
+    assert d["class"] == "run" and d["dims"] == "65536"
+    # rows 10..19 of a matrix: one contiguous range -> copy
+    d = rr.reorder_describe((100, 64), (10, 0), (10, 64), (0, 1), 4, dst=1 << 20, src=1 << 30)
+    assert d["class"] == "copy" and d["bytes"] == str(10 * 64 * 4)

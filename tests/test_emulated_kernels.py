@@ -204,6 +204,71 @@ def test_emu_unaligned_micro_tiles_in_batches():
             assert np.array_equal(o, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), (j["dims"], chunk)
 
 
+def _reorder_job(dims, base, range_, order, e, seed, **kw):
+    n = int(np.prod(dims, dtype=np.int64)) * e
+    return dict(op="reorder", dims=tuple(dims), base=tuple(base), range=tuple(range_), order=tuple(order), esize=e,
+                input=rr_synth.random_bytes(seed, n), **kw)
+
+
+def random_boxes(seed, count, max_rank=5, max_dim=40, max_in_bytes=4 << 20):
+    """Random N-to-M reorders: rank 1..max_rank, a random subset and order of kept
+    axes, random base and range inside each extent (fixed axes at a random index);
+    inputs of at most max_in_bytes at 16-byte elements."""
+    g = rr_synth.rng(seed)
+    out = []
+    for _ in range(count):
+        nd = int(g.integers(1, max_rank + 1))
+        dims = [int(g.integers(1, max_dim + 1)) for _ in range(nd)]
+        while int(np.prod(dims)) * 16 > max_in_bytes:
+            k = int(np.argmax(dims))
+            dims[k] = max(1, dims[k] // 2)
+        m = int(g.integers(0, nd + 1))
+        order = [int(v) for v in g.permutation(nd)[:m]]
+        base, rng = [], []
+        for d in range(nd):
+            b = int(g.integers(0, dims[d]))
+            if d in order:
+                b = int(g.integers(0, max(1, dims[d] // 3)))
+                rng.append(int(g.integers(1, dims[d] - b + 1)))
+            else:
+                rng.append(1)
+            base.append(b)
+        out.append((dims, base, rng, order, int(g.choice([1, 2, 4, 8, 3, 12]))))
+    return out
+
+
+REORDER_CASES = [((5, 7, 3), (1, 2, 0), (3, 4, 3), (1, 0, 2), 4), ((6, 8), (1, 2), (4, 5), (1, 0), 2),
+                 ((4, 5, 6), (0, 1, 2), (4, 1, 3), (2, 0), 1), ((4, 5, 6), (1, 1, 1), (1, 1, 1), (), 8),
+                 ((3, 4, 5, 6), (0, 1, 0, 2), (3, 2, 5, 1), (2, 0, 1), 4), ((8, 9), (0, 3), (8, 1), (0,), 4),
+                 ((10, 4), (0, 0), (10, 4), (0, 1), 2), ((70, 90, 4), (3, 5, 1), (60, 80, 1), (1, 0), 4),
+                 ((64, 96, 3), (0, 0, 0), (64, 96, 3), (2, 0, 1), 2), ((40, 50, 60), (2, 3, 4), (30, 40, 50), (2, 1, 0), 1),
+                 ((128, 130), (1, 1), (120, 127), (1, 0), 8), ((9, 40, 33, 8), (1, 2, 3, 0), (7, 30, 28, 8), (3, 1, 2, 0), 2)]
+
+
+def test_emu_reorder_boxes():
+    """N-to-M reorders (Sec. III.B's base and range): tiled boxes, gathered boxes
+    (innermost axis dropped or cut), copies, single elements, all against the oracle."""
+    jobs = [_reorder_job(*c[:4], c[4], 8100 + i) for i, c in enumerate(REORDER_CASES)]
+    jobs += [_reorder_job(d, b, r, o, e, 8200 + i) for i, (d, b, r, o, e) in enumerate(random_boxes(77, 80))]
+    res = emu_runner.run(jobs)
+    classes = set()
+    for j, (st, out) in zip(jobs, res):
+        assert st.startswith("ok"), (j["dims"], j["base"], j["range"], j["order"], st)
+        ref = oracle.reorder_slice(j["input"], j["dims"], j["base"], j["range"], j["order"], j["esize"])
+        assert np.array_equal(out, ref), (j["dims"], j["base"], j["range"], j["order"], j["esize"], st)
+        classes.add(st.split("class=")[1].split()[0])
+    assert {"tile", "run", "copy"} <= classes, classes
+
+
+def test_emu_reorder_offsets_and_unaligned_micro_tiles():
+    jobs = [_reorder_job(*c[:4], c[4], 8300 + i, src_off=3, dst_off=5) for i, c in enumerate(REORDER_CASES)]
+    jobs += [_reorder_job(*c[:4], c[4], 8400 + i, umt=1) for i, c in enumerate(REORDER_CASES)]
+    for j, (st, out) in zip(jobs, emu_runner.run(jobs)):
+        assert st.startswith("ok"), st
+        ref = oracle.reorder_slice(j["input"], j["dims"], j["base"], j["range"], j["order"], j["esize"])
+        assert np.array_equal(out, ref), (j["dims"], j["base"], j["range"], j["order"], st)
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),
