@@ -53,11 +53,15 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
         lib.oracle_reorder_paper.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int]
         lib.oracle_reorder_slice.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, i64p, ctypes.c_int, ip,
                                              ctypes.c_int]
+        lib.oracle_gather.argtypes = [vp, vp, ctypes.c_int64, i64p, ctypes.c_int64, ctypes.c_int]
+        lib.oracle_copy_range.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
+                                          ctypes.c_int64, ctypes.c_int]
         lib.oracle_interlace.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int,
                                          ctypes.c_int64, ctypes.c_int]
         lib.oracle_deinterlace.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int]
         for f in ("oracle_permute", "oracle_permute_at", "oracle_reorder_paper", "oracle_reorder_slice",
+                  "oracle_gather", "oracle_copy_range",
                   "oracle_interlace", "oracle_deinterlace", "oracle_mutant_id"):
             getattr(lib, f).restype = ctypes.c_int
         _libs[mutant] = lib
@@ -141,6 +145,29 @@ def reorder_slice(src: np.ndarray, dims, base, range_, order, esize: int, mutant
                                            _i64(range_), len(order), _i32(order), esize)
     if rc != 0:
         raise ValueError("oracle_reorder_slice rejected its arguments")
+    return out
+
+
+def gather(src: np.ndarray, idx, esize: int, mutant: int = 0) -> np.ndarray:
+    """dst[i] = src[idx[i]] over elements of esize bytes (flat uint8 result)."""
+    sb = _as_bytes(src)
+    ix = np.ascontiguousarray(np.asarray(idx, dtype=np.int64))
+    out = np.empty(ix.size * esize, dtype=np.uint8)
+    rc = _lib(mutant).oracle_gather(out.ctypes.data, sb.ctypes.data, sb.size // esize,
+                                    ix.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), ix.size, esize)
+    if rc != 0:
+        raise ValueError("oracle_gather rejected its arguments")
+    return out
+
+
+def copy_range(src: np.ndarray, start: int, stride: int, count: int, esize: int, mutant: int = 0) -> np.ndarray:
+    """dst[i] = src[start + i*stride] over elements of esize bytes (flat uint8 result)."""
+    sb = _as_bytes(src)
+    out = np.empty(count * esize, dtype=np.uint8)
+    rc = _lib(mutant).oracle_copy_range(out.ctypes.data, sb.ctypes.data, sb.size // esize, int(start), int(stride),
+                                        int(count), esize)
+    if rc != 0:
+        raise ValueError("oracle_copy_range rejected its arguments")
     return out
 
 

@@ -22,6 +22,9 @@
  *   the input given by a base index and a range per dimension, keeps only the
  *   dimensions the order lists and fixes the others at their base.
  *
+ *   Sec. III.A's read/write kernels move data by an access pattern: over a
+ *   given set of indices (oracle_gather) or a given range (oracle_copy_range).
+ *
  *   Sec. III.C ("Interlace, De-Interlace Kernels"): n equally long data sets are
  *   joined so that the set index varies fastest (interlace), or one such set is
  *   split back into n (de-interlace), e.g. complex numbers into real and
@@ -301,6 +304,57 @@ int oracle_reorder_slice(void* dst, const void* src, int ndim, const int64_t* di
             if (++J[j] < out_dims[j]) break;
             J[j] = 0;
         }
+    }
+    return 0;
+}
+
+/*
+ * Read kernel over an index set (Sec. III.A: the read/write kernels take access
+ * patterns such as a given set of indices): dst[i] = src[idx[i]] for
+ * 0 <= i < count.  Indices outside [0, src_count) are rejected (-1).
+ */
+int oracle_gather(void* dst, const void* src, int64_t src_count, const int64_t* idx, int64_t count,
+                  int esize)
+{
+    if (count < 0 || src_count < 0 || esize < 1) return -1;
+    for (int64_t i = 0; i < count; ++i)
+        if (idx[i] < 0 || idx[i] >= src_count) return -1;
+    unsigned char* d = (unsigned char*)dst;
+    const unsigned char* s = (const unsigned char*)src;
+    for (int64_t i = 0; i < count; ++i) {
+#if RR_ORACLE_MUTANT == 7
+        /* planted mistake: reads the index array one position late */
+        int64_t k = (i + 1 < count) ? idx[i + 1] : idx[i];
+        memcpy(d + i * esize, s + k * esize, (size_t)esize);
+#else
+        memcpy(d + i * esize, s + idx[i] * esize, (size_t)esize);
+#endif
+    }
+    return 0;
+}
+
+/*
+ * Read kernel over a range (Sec. III.A: access based on a specified range):
+ * dst[i] = src[start + i*stride] for 0 <= i < count (stride may be negative or
+ * zero).  Every read index must lie in [0, src_count), else -1.
+ */
+int oracle_copy_range(void* dst, const void* src, int64_t src_count, int64_t start, int64_t stride,
+                      int64_t count, int esize)
+{
+    if (count < 0 || src_count < 0 || esize < 1) return -1;
+    if (count == 0) return 0;
+    int64_t last = start + (count - 1) * stride;
+    if (start < 0 || start >= src_count || last < 0 || last >= src_count) return -1;
+    unsigned char* d = (unsigned char*)dst;
+    const unsigned char* s = (const unsigned char*)src;
+    for (int64_t i = 0; i < count; ++i) {
+#if RR_ORACLE_MUTANT == 8
+        /* planted mistake: ignores the start of the range */
+        int64_t k = i * stride + (stride < 0 ? start : 0);
+#else
+        int64_t k = start + i * stride;
+#endif
+        memcpy(d + i * esize, s + k * esize, (size_t)esize);
     }
     return 0;
 }

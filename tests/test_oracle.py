@@ -61,6 +61,16 @@ def pin_golden(golden_dir, m=0):
                                        case.get("order", []), e, mutant=m)
             if got.tolist() != case["expect"]:
                 return False
+        elif op == "gather":
+            n = case["src_count"][0] * e
+            got = oracle.gather(_iota(n), case["idx"], e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
+        elif op == "copy_range":
+            n = case["src_count"][0] * e
+            got = oracle.copy_range(_iota(n), case["start"][0], case["stride"][0], case["count"][0], e, mutant=m)
+            if got.tolist() != case["expect"]:
+                return False
         elif op == "interlace":
             planes = [np.array(p, dtype=np.uint8) for p in case["planes"]]
             got = oracle.interlace(planes, e, mutant=m)
@@ -239,6 +249,49 @@ def pin_reorder_slice_reduces_to_permute(m=0):
     return True
 
 
+def pin_gather_and_range_numpy(m=0):
+    """Index-set and range reads == NumPy take / strided slicing on an (n, esize) byte view."""
+    g = rr_synth.rng(53)
+    for t in range(60):
+        e = int(g.choice([1, 2, 3, 4, 8, 16]))
+        n = int(g.integers(1, 500))
+        x = rr_synth.random_bytes(700 + t, n * e)
+        v = x.reshape(n, e)
+        idx = g.integers(0, n, int(g.integers(0, 800)))
+        if not np.array_equal(oracle.gather(x, idx, e, mutant=m), v[idx].reshape(-1)):
+            return False
+        start = int(g.integers(0, n))
+        stride = int(g.integers(-5, 6))
+        if stride > 0:
+            count = int(g.integers(0, (n - 1 - start) // stride + 2))
+        elif stride < 0:
+            count = int(g.integers(0, start // -stride + 2))
+        else:
+            count = int(g.integers(0, 20))
+        ref = np.stack([v[start + i * stride] for i in range(count)]).reshape(-1) if count else np.empty(0, np.uint8)
+        if not np.array_equal(oracle.copy_range(x, start, stride, count, e, mutant=m), ref):
+            return False
+    return True
+
+
+def pin_gather_invariants(m=0):
+    """Identity indices = memcpy; a permutation followed by its inverse = identity;
+    a range read equals the gather of the same arithmetic progression."""
+    e, n = 4, 257
+    x = rr_synth.random_bytes(61, n * e)
+    if not np.array_equal(oracle.gather(x, np.arange(n), e, mutant=m), x):
+        return False
+    p = rr_synth.rng(62).permutation(n)
+    y = oracle.gather(x, p, e, mutant=m)
+    if not np.array_equal(oracle.gather(y, np.argsort(p), e, mutant=m), x):
+        return False
+    for start, stride, count in [(3, 7, 30), (250, -4, 60), (9, 0, 5)]:
+        prog = start + stride * np.arange(count)
+        if not np.array_equal(oracle.copy_range(x, start, stride, count, e, mutant=m), oracle.gather(x, prog, e, mutant=m)):
+            return False
+    return True
+
+
 def pin_permute_at(m=0):
     dims, perm, e = (6, 5, 7, 3), (3, 0, 2, 1), 4
     x = rr_synth.random_bytes(21, int(np.prod(dims)) * e)
@@ -259,6 +312,8 @@ ALL_PINS = {
     "permute_at": lambda gd, m: pin_permute_at(m),
     "reorder_slice_numpy": lambda gd, m: pin_reorder_slice_numpy(m),
     "reorder_slice_permute": lambda gd, m: pin_reorder_slice_reduces_to_permute(m),
+    "gather_range_numpy": lambda gd, m: pin_gather_and_range_numpy(m),
+    "gather_invariants": lambda gd, m: pin_gather_invariants(m),
 }
 
 
@@ -268,11 +323,11 @@ def test_oracle_pin(name, golden_dir):
     assert ALL_PINS[name](golden_dir, 0), f"oracle fails pin {name}"
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7, 8])
 def test_planted_mistake_is_caught(mutant, golden_dir):
     """Each planted oracle mistake (gather/scatter swap, dropped term, wrong stride,
-    transposed interlace, fixed axes read at 0, box start ignored) must fail at
-    least one pin."""
+    transposed interlace, fixed axes read at 0, box start ignored, index set read
+    one late, range start ignored) must fail at least one pin."""
     oracle.build(mutant, force=False)
     assert oracle.mutant_id(mutant) == mutant
     failed = []
