@@ -350,6 +350,10 @@ def main():
             side["reorder"] = bench_reorder(rr, pool, out, stream, timed)
         except Exception as ex:
             side["reorder"] = {"error": str(ex)}
+        try:
+            side["access_patterns"] = bench_access_patterns(rr, torch, pool, out, stream, timed)
+        except Exception as ex:
+            side["access_patterns"] = {"error": str(ex)}
         del pool, out, flush
         torch.cuda.empty_cache()
         try:
@@ -397,6 +401,32 @@ def bench_reorder(rr, pool, out, stream, timed):
         t = timed(lambda: rr.check(rr.reorder_raw(out.data_ptr(), src, dims, base, rng, order, e, stream.cuda_stream)), 5)
         res[name] = {"GBps": round(2 * nout * e / t / 1e9, 1), "class": d["class"],
                      "out_bytes": nout * e, "kernel": kernel_name(d)}
+    return res
+
+
+def bench_access_patterns(rr, torch, pool, out, stream, timed):
+    """Index-set and range reads of pool data (a 1 GiB table): GB/s counts the
+    algorithmic bytes (indices read + elements read + elements written)."""
+    res = {}
+    sh = stream.cuda_stream
+    table = 1 << 30
+    g = torch.Generator(device=pool.device)
+    g.manual_seed(3583)
+    count = 1 << 26
+    for e in (4, 16):
+        n = table // e
+        idx = torch.randint(0, n, (count,), generator=g, device=pool.device, dtype=torch.int64)
+        for name, ix in (("random", idx), ("sorted", torch.sort(idx).values)):
+            t = timed(lambda: rr.check(rr.gather_raw(out.data_ptr(), pool.data_ptr(), n, ix.data_ptr(), count, e, 0,
+                                                     sh)), 5)
+            res[f"gather_{name}_e{e}"] = {"GBps": round(count * (8 + 2 * e) / t / 1e9, 1), "elements": count}
+        del idx
+        for stride in (2, -1, 7):
+            start = 0 if stride > 0 else n - 1
+            cnt = min(count, (n - 1) // abs(stride) + 1)
+            t = timed(lambda: rr.check(rr.copy_range_raw(out.data_ptr(), pool.data_ptr(), n, start, stride, cnt, e,
+                                                         sh)), 5)
+            res[f"range_stride{stride}_e{e}"] = {"GBps": round(2 * cnt * e / t / 1e9, 1), "elements": cnt}
     return res
 
 

@@ -96,6 +96,36 @@ rr_status rr_reorder(void* dst, const void* src, int ndim, const int64_t* dims, 
                      rr_stream_t stream);
 
 /* -------------------------------------------------------------------------
+ * Read kernel over an index set (Sec. III.A, read/write kernels with an access
+ * pattern given as a set of indices):
+ *   dst[i] = src[idx[i]]   for 0 <= i < count, elements of elem_size bytes.
+ *   dst        device buffer of count*elem_size bytes.
+ *   src        device buffer of src_count elements.
+ *   idx        device array of count int64 indices (any order, repeats allowed).
+ *   bad_count  optional device uint64 (may be NULL): incremented by the number of
+ *              indices outside [0, src_count); such elements are written as zeros.
+ * Four elements per thread; each element is read with the widest access its
+ * size and the pointers allow.  Host-side validation cannot see the indices
+ * (they live on the device), hence the counter instead of an error status.
+ * Errors: RR_ERR_INVALID_ARG, RR_ERR_OVERFLOW, RR_ERR_ALIAS (dst overlaps src,
+ * idx or the counter), RR_ERR_HIP.
+ */
+rr_status rr_gather(void* dst, const void* src, int64_t src_count, const int64_t* idx, int64_t count,
+                    int elem_size, uint64_t* bad_count, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
+ * Read kernel over a range (Sec. III.A, access based on a specified range):
+ *   dst[i] = src[start + i*stride]   for 0 <= i < count (stride may be negative
+ *   or zero); every index read must lie in [0, src_count).
+ *   dst  device buffer of count*elem_size bytes; src device buffer of src_count
+ *        elements.  stride 1 is a plain copy of the range.
+ * Errors: RR_ERR_INVALID_ARG (range outside the source, bad sizes, NULL),
+ * RR_ERR_OVERFLOW, RR_ERR_ALIAS (dst overlaps the bytes read), RR_ERR_HIP.
+ */
+rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t start, int64_t stride,
+                        int64_t count, int elem_size, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
  * Interlace (Sec. III.C): join n equally long data sets, set index fastest:
  *   dst[i*n + c] = srcs[c][i]    for 0 <= i < count, 0 <= c < n.
  *   dst   device buffer of n*count*elem_size bytes.

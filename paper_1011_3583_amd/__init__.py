@@ -25,7 +25,8 @@ STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_
 STATUS_CODE = {v: k for k, v in STATUS.items()}
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
-EXPORTS = ("rr_permute", "rr_reorder", "rr_interlace", "rr_deinterlace", "rr_permute_batched",
+EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_interlace", "rr_deinterlace",
+           "rr_permute_batched",
            "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
@@ -112,6 +113,8 @@ def lib() -> ctypes.CDLL:
     L.rr_order_to_perm.argtypes = [i32, i32p, i32p]
     L.rr_plan_describe.argtypes = [vp, vp, i32, i64p, i32p, i32, ctypes.c_char_p, i32]
     L.rr_reorder.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, vp]
+    L.rr_gather.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
+    L.rr_copy_range.argtypes = [vp, vp, i64, i64, i64, i64, i32, vp]
     L.rr_reorder_describe.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
     L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
@@ -173,6 +176,21 @@ def reorder_raw(dst: int, src: int, dims, base, range_, order, elem_size: int, s
     base / range_ may be None (zeros / to the end)."""
     return lib().rr_reorder(dst, src, len(dims), _i64(dims), _opt_i64(base), _opt_i64(range_), len(order),
                             _i32(order), int(elem_size), _stream_handle(stream))
+
+
+def gather_raw(dst: int, src: int, src_count: int, idx: int, count: int, elem_size: int, bad: int = 0,
+               stream=0) -> int:
+    """rr_gather on raw device addresses (idx: device int64 array; bad: device
+    uint64 counter or 0); returns the rr_status."""
+    return lib().rr_gather(dst, src, int(src_count), idx, int(count), int(elem_size), bad or None,
+                           _stream_handle(stream))
+
+
+def copy_range_raw(dst: int, src: int, src_count: int, start: int, stride: int, count: int, elem_size: int,
+                   stream=0) -> int:
+    """rr_copy_range on raw device addresses; returns the rr_status."""
+    return lib().rr_copy_range(dst, src, int(src_count), int(start), int(stride), int(count), int(elem_size),
+                               _stream_handle(stream))
 
 
 def interlace_raw(dst: int, srcs, count: int, elem_size: int, stream=0) -> int:

@@ -117,6 +117,55 @@ rr_status rr_reorder_describe(const void* dst, const void* src, int ndim, const 
     return RR_OK;
 }
 
+rr_status rr_gather(void* dst, const void* src, int64_t src_count, const int64_t* idx, int64_t count,
+                    int elem_size, uint64_t* bad_count, rr_stream_t stream) {
+    clear_error();
+    if (elem_size < 1 || elem_size > 16) return fail(RR_ERR_INVALID_ARG, "elem_size must be 1..16");
+    if (count < 0 || src_count < 0) return fail(RR_ERR_INVALID_ARG, "count and src_count must be >= 0");
+    int64_t out_bytes, in_bytes, idx_bytes;
+    if (__builtin_mul_overflow(count, (int64_t)elem_size, &out_bytes) ||
+        __builtin_mul_overflow(src_count, (int64_t)elem_size, &in_bytes) ||
+        __builtin_mul_overflow(count, (int64_t)8, &idx_bytes))
+        return fail(RR_ERR_OVERFLOW, "byte count overflows int64");
+    if (count == 0) return RR_OK;
+    if (!dst || !idx || (!src && src_count > 0)) return fail(RR_ERR_INVALID_ARG, "NULL buffer for a non-empty problem");
+    if (ranges_overlap((uint64_t)dst, out_bytes, (uint64_t)src, in_bytes) ||
+        ranges_overlap((uint64_t)dst, out_bytes, (uint64_t)idx, idx_bytes) ||
+        (bad_count && ranges_overlap((uint64_t)dst, out_bytes, (uint64_t)bad_count, 8)))
+        return fail(RR_ERR_ALIAS, "destination overlaps the source, the indices or the counter");
+    Plan p;
+    plan_gather((uint64_t)dst, (uint64_t)src, (uint64_t)idx, (uint64_t)bad_count, count, src_count, 0, 0, elem_size, &p);
+    hipError_t e = launch_plan(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rr_gather launch");
+    return RR_OK;
+}
+
+rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t start, int64_t stride,
+                        int64_t count, int elem_size, rr_stream_t stream) {
+    clear_error();
+    if (elem_size < 1 || elem_size > 16) return fail(RR_ERR_INVALID_ARG, "elem_size must be 1..16");
+    if (count < 0 || src_count < 0) return fail(RR_ERR_INVALID_ARG, "count and src_count must be >= 0");
+    int64_t out_bytes, in_bytes, span, last;
+    if (__builtin_mul_overflow(count, (int64_t)elem_size, &out_bytes) ||
+        __builtin_mul_overflow(src_count, (int64_t)elem_size, &in_bytes))
+        return fail(RR_ERR_OVERFLOW, "byte count overflows int64");
+    if (count == 0) return RR_OK;
+    if (__builtin_mul_overflow(count - 1, stride, &span) || __builtin_add_overflow(start, span, &last))
+        return fail(RR_ERR_OVERFLOW, "range end overflows int64");
+    if (start < 0 || start >= src_count || last < 0 || last >= src_count)
+        return fail(RR_ERR_INVALID_ARG, "range reads outside the source");
+    if (!dst || !src) return fail(RR_ERR_INVALID_ARG, "NULL buffer for a non-empty problem");
+    const int64_t lo = std::min(start, last), hi = std::max(start, last);
+    if (ranges_overlap((uint64_t)dst, out_bytes, (uint64_t)src + lo * elem_size, (hi - lo + 1) * elem_size))
+        return fail(RR_ERR_ALIAS, "destination overlaps the range read");
+    Plan p;
+    if (stride == 1) plan_copy((uint64_t)dst, (uint64_t)src + start * elem_size, (uint64_t)out_bytes, &p);
+    else plan_gather((uint64_t)dst, (uint64_t)src, 0, 0, count, src_count, start, stride, elem_size, &p);
+    hipError_t e = launch_plan(p, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rr_copy_range launch");
+    return RR_OK;
+}
+
 static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
                                   int elem_size, rr_stream_t stream, bool de) {
     clear_error();

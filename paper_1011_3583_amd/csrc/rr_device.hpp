@@ -288,6 +288,76 @@ RR_HD void copy_thread(const CopyArgs& a, uint32_t block, uint32_t nblocks, uint
     }
 }
 
+// ----------------------------------------------------------------- index-set / range read
+// One thread's share of an index-set or range read: four elements per thread
+// per step (indices first, then their elements, then the stores), grid-stride
+// over the output.  Loads are unconditional at clamped in-bounds addresses
+// (results masked afterwards) so the four of each kind are in flight together.
+// Returns how many indices fell outside the source.
+template <int W>
+RR_HD uint32_t gather_thread(const GatherArgs& a, uint64_t block, uint64_t nblocks, uint32_t tid) {
+    constexpr int NW = NWords<W>::value;
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(a.src);
+    uint8_t* dst = reinterpret_cast<uint8_t*>(a.dst);
+    const uint8_t* idx = reinterpret_cast<const uint8_t*>(a.idx);
+    const uint64_t n = (uint64_t)a.count;   // >= 1 when launched
+    uint32_t nbad = 0;
+    for (uint64_t base = block * NT * 4 + tid; base < n; base += nblocks * NT * 4) {
+        int64_t s[4];
+        bool ok[4], valid[4];
+        uint32_t w[4][2];
+        if (a.idx) {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                const uint64_t i = base + (uint64_t)u * NT;
+                gload<8>(idx + (i < n ? i : n - 1) * 8, w[u]);
+            }
+        }
+#pragma unroll
+        for (int u = 0; u < 4; ++u) {
+            const uint64_t i = base + (uint64_t)u * NT;
+            ok[u] = i < n;
+            s[u] = a.idx ? (int64_t)(((uint64_t)w[u][1] << 32) | w[u][0]) : a.start + (int64_t)i * a.stride;
+            valid[u] = ok[u] && s[u] >= 0 && s[u] < a.src_count;
+            nbad += ok[u] && !valid[u];
+            if (!valid[u]) s[u] = 0;   // element 0 is read instead and discarded
+        }
+        const bool any_src = a.src_count > 0;
+        if (a.k == 1) {
+            uint32_t v[4][NW];
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (any_src) gload<W>(src + (uint64_t)s[u] * W, v[u]);
+                else
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) v[u][q] = 0;
+            }
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!valid[u])
+#pragma unroll
+                    for (int q = 0; q < NW; ++q) v[u][q] = 0;
+                if (ok[u]) gstore<W>(dst + (base + (uint64_t)u * NT) * W, v[u]);
+            }
+        } else {
+#pragma unroll
+            for (int u = 0; u < 4; ++u) {
+                if (!ok[u]) continue;
+                const uint8_t* ps = src + (uint64_t)s[u] * a.esize;
+                uint8_t* pd = dst + (base + (uint64_t)u * NT) * a.esize;
+                for (uint32_t q = 0; q < a.k; ++q) {
+                    uint32_t v[NW];
+#pragma unroll
+                    for (int c = 0; c < NW; ++c) v[c] = 0;
+                    if (valid[u]) gload<W>(ps + q * W, v);
+                    gstore<W>(pd + q * W, v);
+                }
+            }
+        }
+    }
+    return nbad;
+}
+
 // ----------------------------------------------------------------- run copy
 // Output is written contiguously; each W-byte vector is read from the input run
 // its output run maps to.

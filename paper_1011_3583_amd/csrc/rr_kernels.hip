@@ -29,6 +29,12 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyArgs a) {
 }
 
 template <int W>
+__global__ __launch_bounds__(NT) void k_gather(const GatherArgs a) {
+    const uint32_t nbad = gather_thread<W>(a, blockIdx.x, gridDim.x, threadIdx.x);
+    if (nbad && a.bad) atomicAdd(reinterpret_cast<unsigned long long*>(a.bad), (unsigned long long)nbad);
+}
+
+template <int W>
 __global__ __launch_bounds__(NT) void k_run(const RunArgs a) {
     run_thread<W>(a, blockIdx.x, threadIdx.x);
 }
@@ -202,6 +208,15 @@ hipError_t launch_plan(const Plan& p, hipStream_t st) {
             return hipGetLastError();
         case K_TILE:
             return launch_tile(p.tile, p.grid, st);
+        case K_GATHER:
+            switch (p.gather.wbytes) {
+                case 16: hipLaunchKernelGGL(k_gather<16>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;
+                case 8: hipLaunchKernelGGL(k_gather<8>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;
+                case 4: hipLaunchKernelGGL(k_gather<4>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;
+                case 2: hipLaunchKernelGGL(k_gather<2>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;
+                default: hipLaunchKernelGGL(k_gather<1>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;
+            }
+            return hipGetLastError();
     }
     return hipErrorInvalidValue;
 }

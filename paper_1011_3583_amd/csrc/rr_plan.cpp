@@ -320,6 +320,24 @@ rr_status canonicalize_view(int ndim, const int64_t* dims, const int64_t* base, 
     return RR_OK;
 }
 
+void plan_gather(uint64_t dst, uint64_t src, uint64_t idx, uint64_t bad, int64_t count, int64_t src_count,
+                 int64_t start, int64_t stride, int esize, Plan* p) {
+    p->kind = K_GATHER;
+    p->bytes = (uint64_t)count * (uint64_t)esize;
+    GatherArgs& a = p->gather;
+    std::memset(&a, 0, sizeof(a));
+    uint32_t W = 16;
+    while (W > 1 && (esize % W || src % W || dst % W)) W >>= 1;
+    a.src = src; a.dst = dst; a.idx = idx; a.bad = bad;
+    a.count = count; a.src_count = src_count; a.start = start; a.stride = stride;
+    a.esize = (uint32_t)esize; a.wbytes = W; a.k = (uint32_t)esize / W;
+    uint64_t per_block = (uint64_t)NT * 4;
+    uint64_t g = ((uint64_t)count + per_block - 1) / per_block;
+    if (g < 1) g = 1;
+    if (g > 0x7fffffffULL) g = 0x7fffffffULL;   // grid-stride beyond this
+    p->grid = (uint32_t)g;
+}
+
 void plan_copy(uint64_t dst, uint64_t src, uint64_t nbytes, Plan* p) {
     p->kind = K_COPY;
     p->bytes = nbytes;
@@ -772,7 +790,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
 
 std::string describe(const Plan& p) {
     std::ostringstream o;
-    static const char* names[] = {"empty", "copy", "run", "tile"};
+    static const char* names[] = {"empty", "copy", "run", "tile", "gather"};
     o << "class=" << names[p.kind];
     const Canon& c = p.c;
     o << " rank=" << c.rank << " dims=";
@@ -782,6 +800,7 @@ std::string describe(const Plan& p) {
     o << " esize_bytes=" << c.elem_bytes << " bytes=" << p.bytes << " grid=" << p.grid;
     if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
     if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr;
+    if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
     if (p.kind == K_TILE) {
         const TileArgs& a = p.tile;
         o << " unit=" << a.unit << " g=" << a.g << " k=" << a.k << " TA=" << a.TA << " TB=" << a.TB

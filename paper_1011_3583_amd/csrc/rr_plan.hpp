@@ -41,7 +41,7 @@ struct Canon {
     int64_t total_bytes = 0;   // bytes per side
 };
 
-enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3 };
+enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3, K_GATHER = 4 };
 
 // ---------------------------------------------------------------- kernel args
 struct CopyArgs {
@@ -50,6 +50,20 @@ struct CopyArgs {
     uint32_t head;      // bytes copied one by one before the body
     uint32_t tail;      // bytes copied one by one after the body
     uint32_t wbytes;    // W
+    uint32_t pad_;
+};
+
+// Index-set or range read, one element per index (Sec. III.A):
+//   dst[i] = src[ix(i)],  ix(i) = idx[i] (idx != 0) or start + i*stride.
+// An index outside [0, src_count) reads as zeros and is counted in *bad.
+struct GatherArgs {
+    uint64_t src, dst;
+    uint64_t idx;          // device array of count int64 indices (0: range mode)
+    uint64_t bad;          // device uint64 counter of rejected indices (0: none)
+    int64_t count, src_count, start, stride;
+    uint32_t esize;        // bytes per element
+    uint32_t wbytes;       // W: bytes per access
+    uint32_t k;            // accesses per element (esize / W)
     uint32_t pad_;
 };
 
@@ -187,12 +201,16 @@ struct Plan {
     CopyArgs copy;
     RunArgs run;
     TileArgs tile;
+    GatherArgs gather;
     uint32_t grid = 0;       // workgroups to launch
     uint64_t bytes = 0;      // bytes per side
 };
 
 rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
                        Plan* p, std::string* why);
+// Index-set read (idx != 0) or range read (idx == 0: start, stride).
+void plan_gather(uint64_t dst, uint64_t src, uint64_t idx, uint64_t bad, int64_t count, int64_t src_count,
+                 int64_t start, int64_t stride, int esize, Plan* p);
 // flat = joined buffer (interlace output / de-interlace input); planes = the n sets.
 rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
                          bool deinterlace, const TileOptions& opt, Plan* p, std::string* why);

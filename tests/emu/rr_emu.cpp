@@ -12,6 +12,7 @@
 // Input: a manifest, one job per line:
 //   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt infile outfile
 //   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
+//   gather   src_count count esize indexed start stride src_off dst_off infile idxfile outfile
 //   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
 //   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
@@ -150,6 +151,14 @@ static bool emulate_group(const BatchGroup& g, const uint8_t* table) {
     return false;
 }
 
+static uint64_t g_bad = 0;   // rejected indices of the last gather
+
+template <int W>
+static void run_gather_w(const GatherArgs& a, uint32_t grid) {
+    for (uint32_t b = 0; b < grid; ++b)
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) g_bad += gather_thread<W>(a, b, grid, tid);
+}
+
 static bool emulate(const Plan& p) {
     switch (p.kind) {
         case K_EMPTY: return true;
@@ -171,6 +180,14 @@ static bool emulate(const Plan& p) {
             }
         case K_TILE:
             return run_tile(p.tile, p.grid);
+        case K_GATHER:
+            switch (p.gather.wbytes) {
+                case 16: run_gather_w<16>(p.gather, p.grid); return true;
+                case 8: run_gather_w<8>(p.gather, p.grid); return true;
+                case 4: run_gather_w<4>(p.gather, p.grid); return true;
+                case 2: run_gather_w<2>(p.gather, p.grid); return true;
+                default: run_gather_w<1>(p.gather, p.grid); return true;
+            }
     }
     return false;
 }
@@ -216,6 +233,30 @@ int main(int argc, char** argv) {
             std::printf("ok %s\n", describe(plan).c_str());
             delete[] sbuf;
             delete[] dbuf;
+        } else if (op == "gather") {
+            // gather src_count count esize indexed start stride src_off dst_off infile idxfile outfile
+            int64_t src_count, count, start, stride; int esize, indexed, soff, doff; std::string inf, idxf, outf;
+            is >> src_count >> count >> esize >> indexed >> start >> stride >> soff >> doff >> inf >> idxf >> outf;
+            std::vector<uint8_t> in = read_file(inf);
+            std::vector<uint8_t> ix = indexed ? read_file(idxf) : std::vector<uint8_t>();
+            const size_t nb = (size_t)(count * esize);
+            uint8_t* sbuf = new uint8_t[soff + in.size() + 1];
+            uint8_t* dbuf = new uint8_t[doff + nb + 1];
+            uint8_t* ibuf = new uint8_t[ix.size() + 1];
+            if (!in.empty()) std::memcpy(sbuf + soff, in.data(), in.size());
+            if (!ix.empty()) std::memcpy(ibuf, ix.data(), ix.size());
+            std::memset(dbuf, 0x5A, doff + nb + 1);
+            plan_gather((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff), indexed ? (uint64_t)ibuf : 0, 0, count,
+                        src_count, start, stride, esize, &plan);
+            g_bad = 0;
+            if (count > 0 && !emulate(plan)) { std::printf("err -1 no kernel for plan\n"); return 3; }
+            if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+            for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
+            write_file(outf, dbuf + doff, nb);
+            std::printf("ok %s bad=%llu\n", describe(plan).c_str(), (unsigned long long)g_bad);
+            delete[] sbuf;
+            delete[] dbuf;
+            delete[] ibuf;
         } else if (op == "reorder") {
             int ndim; is >> ndim;
             std::vector<int64_t> dims(ndim), base(ndim), range(ndim);

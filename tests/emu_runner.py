@@ -41,6 +41,7 @@ def run(jobs):
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
                     max_g, ragged, xcd, umt
        reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
+       gather:      op, src_count, esize, input (uint8), idx (int64) or start/stride/count, src_off, dst_off
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
        deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb
     Returns a list of (status_line, output) with output a uint8 array or list of planes."""
@@ -59,6 +60,16 @@ def run(jobs):
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))), str(int(j.get("xcd", False))),
                                        str(int(j.get("umt", 0))), inf, outf]))
+            elif j["op"] == "gather":
+                j["input"].tofile(inf)
+                idxf = os.path.join(td, f"idx{i}")
+                indexed = "idx" in j
+                if indexed:
+                    np.asarray(j["idx"], dtype=np.int64).tofile(idxf)
+                count = len(j["idx"]) if indexed else j["count"]
+                lines.append(" ".join(map(str, ["gather", j["src_count"], count, j["esize"], int(indexed),
+                                                 j.get("start", 0), j.get("stride", 0), j.get("src_off", 0),
+                                                 j.get("dst_off", 0), inf, idxf, outf])))
             elif j["op"] == "reorder":
                 j["input"].tofile(inf)
                 nd = len(j["dims"])

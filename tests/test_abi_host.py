@@ -257,3 +257,19 @@ def test_reorder_plans_match_permute_and_classes():
     # rows 10..19 of a matrix: one contiguous range -> copy
     d = rr.reorder_describe((100, 64), (10, 0), (10, 64), (0, 1), 4, dst=1 << 20, src=1 << 30)
     assert d["class"] == "copy" and d["bytes"] == str(10 * 64 * 4)
+
+
+def test_gather_and_range_validation():
+    assert rr.gather_raw(0x100000, 0x1000, 10, 0x200000, 5, 0) == 1          # elem_size
+    assert rr.gather_raw(0x100000, 0x1000, 10, 0x200000, -1, 4) == 1         # count
+    assert rr.gather_raw(0x100000, 0x1000, 10, 0, 5, 4) == 1                 # NULL idx
+    assert rr.gather_raw(0x1000, 0x1000, 10, 0x200000, 5, 4) == 3            # dst overlaps src
+    assert rr.gather_raw(0x200010, 0x1000, 10, 0x200000, 5, 4) == 3          # dst overlaps idx
+    assert rr.gather_raw(0, 0, 10, 0, 0, 4) == 0                             # empty: no-op
+    assert rr.copy_range_raw(0x100000, 0x1000, 10, 0, 1, 11, 4) == 1         # past the end
+    assert rr.copy_range_raw(0x100000, 0x1000, 10, 9, 2, 2, 4) == 1
+    assert rr.copy_range_raw(0x100000, 0x1000, 10, 2, -1, 4, 4) == 1         # before the start
+    assert rr.copy_range_raw(0x100000, 0x1000, 10, -1, 1, 1, 4) == 1
+    assert rr.copy_range_raw(0x1000 + 8, 0x1000, 10, 0, 1, 5, 4) == 3        # dst inside the bytes read
+    assert rr.copy_range_raw(0, 0, 10, 3, 1, 0, 4) == 0                      # empty: no-op
+    assert rr.copy_range_raw(0x100000, 0x1000, 1 << 62, 0, 1 << 40, 1 << 30, 4) == 2   # overflow
