@@ -56,12 +56,13 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
         lib.oracle_gather.argtypes = [vp, vp, ctypes.c_int64, i64p, ctypes.c_int64, ctypes.c_int]
         lib.oracle_copy_range.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int64,
                                           ctypes.c_int64, ctypes.c_int]
+        lib.oracle_stencil2d.argtypes = [vp, vp, ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, vp]
         lib.oracle_interlace.argtypes = [vp, ctypes.POINTER(vp), ctypes.c_int,
                                          ctypes.c_int64, ctypes.c_int]
         lib.oracle_deinterlace.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int]
         for f in ("oracle_permute", "oracle_permute_at", "oracle_reorder_paper", "oracle_reorder_slice",
-                  "oracle_gather", "oracle_copy_range",
+                  "oracle_gather", "oracle_copy_range", "oracle_stencil2d",
                   "oracle_interlace", "oracle_deinterlace", "oracle_mutant_id"):
             getattr(lib, f).restype = ctypes.c_int
         _libs[mutant] = lib
@@ -168,6 +169,29 @@ def copy_range(src: np.ndarray, start: int, stride: int, count: int, esize: int,
                                         int(count), esize)
     if rc != 0:
         raise ValueError("oracle_copy_range rejected its arguments")
+    return out
+
+
+# stencil shapes: star (weights: center, then one weight per distance along the
+# axes) and box (a full (2r+1) x (2r+1) weight matrix)
+STENCIL_STAR, STENCIL_BOX = 0, 1
+
+
+def stencil2d(src: np.ndarray, radius: int, weights, shape: int = STENCIL_STAR, mutant: int = 0) -> np.ndarray:
+    """2-D stencil of a (rows, cols) float32 array, evaluated in float64; points
+    closer than radius to an edge keep their input value.  Returns float64."""
+    x = np.ascontiguousarray(src, dtype=np.float32)
+    if x.ndim != 2:
+        raise ValueError("stencil2d needs a 2-D array")
+    w = np.ascontiguousarray(np.asarray(weights, dtype=np.float32).reshape(-1))
+    need = radius + 1 if shape == STENCIL_STAR else (2 * radius + 1) ** 2
+    if w.size != need:
+        raise ValueError(f"expected {need} weights")
+    out = np.empty(x.shape, dtype=np.float64)
+    rc = _lib(mutant).oracle_stencil2d(out.ctypes.data, x.ctypes.data, x.shape[0], x.shape[1], int(radius),
+                                       int(shape), w.ctypes.data)
+    if rc != 0:
+        raise ValueError("oracle_stencil2d rejected its arguments")
     return out
 
 

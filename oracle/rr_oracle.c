@@ -25,6 +25,9 @@
  *   Sec. III.A's read/write kernels move data by an access pattern: over a
  *   given set of indices (oracle_gather) or a given range (oracle_copy_range).
  *
+ *   Sec. III.D's generic 2-D stencil (oracle_stencil2d) is the one operation
+ *   that computes: a weighted sum of each point's neighbours, in double.
+ *
  *   Sec. III.C ("Interlace, De-Interlace Kernels"): n equally long data sets are
  *   joined so that the set index varies fastest (interlace), or one such set is
  *   split back into n (de-interlace), e.g. complex numbers into real and
@@ -355,6 +358,55 @@ int oracle_copy_range(void* dst, const void* src, int64_t src_count, int64_t sta
         int64_t k = start + i * stride;
 #endif
         memcpy(d + i * esize, s + k * esize, (size_t)esize);
+    }
+    return 0;
+}
+
+/*
+ * 2-D stencil (Sec. III.D: each grid point is updated with weighted
+ * contributions of its neighbours; the measured case is a finite-difference
+ * stencil of orders I-IV on single-precision data).  Evaluated in double from
+ * float inputs and float weights, in the order written here.
+ *   src, dst: rows x cols floats, row-major.  radius r in 1..4.
+ *   shape 0 (star): weights[0..r]; out = w0*x[i][j] + sum_{k=1..r} wk *
+ *     (x[i-k][j] + x[i+k][j] + x[i][j-k] + x[i][j+k]).
+ *   shape 1 (box): weights[(2r+1)^2], row-major over dy = -r..r, dx = -r..r;
+ *     out = sum w[dy][dx] * x[i+dy][j+dx].
+ *   Points closer than r to an edge keep their input value.
+ * Returns 0, or -1 on bad arguments.
+ */
+int oracle_stencil2d(double* dst, const float* src, int64_t rows, int64_t cols, int radius, int shape,
+                     const float* weights)
+{
+    if (rows < 0 || cols < 0 || radius < 1 || radius > 4 || (shape != 0 && shape != 1)) return -1;
+    const int r = radius;
+    for (int64_t i = 0; i < rows; ++i) {
+        for (int64_t j = 0; j < cols; ++j) {
+            const float* x = src + i * cols + j;
+            if (i < r || i >= rows - r || j < r || j >= cols - r) {
+                dst[i * cols + j] = (double)*x;
+                continue;
+            }
+            double acc = 0.0;
+            if (shape == 0) {
+                acc = (double)weights[0] * (double)x[0];
+                for (int k = 1; k <= r; ++k) {
+#if RR_ORACLE_MUTANT == 9
+                    /* planted mistake: the vertical neighbours use the horizontal offset */
+                    double ring = (double)x[-k] + (double)x[k] + (double)x[-k] + (double)x[k];
+#else
+                    double ring = (double)x[-k * cols] + (double)x[k * cols] + (double)x[-k] + (double)x[k];
+#endif
+                    acc += (double)weights[k] * ring;
+                }
+            } else {
+                const int n = 2 * r + 1;
+                for (int dy = -r; dy <= r; ++dy)
+                    for (int dx = -r; dx <= r; ++dx)
+                        acc += (double)weights[(dy + r) * n + (dx + r)] * (double)x[dy * cols + dx];
+            }
+            dst[i * cols + j] = acc;
+        }
     }
     return 0;
 }

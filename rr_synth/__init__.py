@@ -141,3 +141,24 @@ def poisson_arrivals(seed: int, rate_hz: float, count: int) -> np.ndarray:
     g = rng(seed)
     gaps = g.exponential(1.0 / rate_hz, size=count)
     return np.cumsum(gaps)
+
+
+# 2-D finite-difference stencils of orders I-IV (the paper's measured stencil
+# family, Sec. III.D / Fig. 2): the 2-D Laplacian from the textbook central
+# differences of the second derivative with accuracy 2, 4, 6 and 8, as star
+# weights (center, then one weight per distance along the axes).  They are
+# workload parameters (the user's stencil), handed to the library and the oracle alike.
+FD_LAPLACIAN = {
+    1: (-4.0, 1.0),
+    2: (-5.0, 4.0 / 3.0, -1.0 / 12.0),
+    3: (-49.0 / 9.0, 3.0 / 2.0, -3.0 / 20.0, 1.0 / 90.0),
+    4: (-205.0 / 36.0, 8.0 / 5.0, -1.0 / 5.0, 8.0 / 315.0, -1.0 / 560.0),
+}
+
+# stencil grids: Table 4's 4096 x 4096 single-precision data set, and a larger one
+STENCIL_GRIDS = [(4096, 4096), (16384, 16384)]
+
+
+def random_grid(seed: int, rows: int, cols: int) -> np.ndarray:
+    """float32 grid of values uniform in [-1, 1) (seeded)."""
+    return rng(seed).uniform(-1.0, 1.0, size=(rows, cols)).astype(np.float32)

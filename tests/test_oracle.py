@@ -40,7 +40,7 @@ def paper_order_to_numpy_perm(order):
 def pin_golden(golden_dir, m=0):
     for case in golden_io.load_all(golden_dir):
         op = case["op"]
-        e = case["esize"][0]
+        e = case.get("esize", [4])[0]
         if op == "permute":
             n = int(np.prod(case["dims"])) * e
             got = oracle.permute(_iota(n), case["dims"], case["perm"], e, mutant=m)
@@ -70,6 +70,12 @@ def pin_golden(golden_dir, m=0):
             n = case["src_count"][0] * e
             got = oracle.copy_range(_iota(n), case["start"][0], case["stride"][0], case["count"][0], e, mutant=m)
             if got.tolist() != case["expect"]:
+                return False
+        elif op == "stencil":
+            rows, cols = case["rows"][0], case["cols"][0]
+            x = np.arange(rows * cols, dtype=np.float32).reshape(rows, cols)
+            got = oracle.stencil2d(x, case["radius"][0], case["weights"], case["shape"][0], mutant=m)
+            if got.reshape(-1).tolist() != [float(v) for v in case["expect"]]:
                 return False
         elif op == "interlace":
             planes = [np.array(p, dtype=np.uint8) for p in case["planes"]]
@@ -292,6 +298,66 @@ def pin_gather_invariants(m=0):
     return True
 
 
+def _interior(a, r):
+    return a[r:a.shape[0] - r, r:a.shape[1] - r]
+
+
+def pin_stencil_closed_forms(m=0):
+    """FD stencils of orders I-IV against closed forms evaluated with the very
+    float32 weights given: u = i^2 + j^2 (ring k = 4u + 4k^2), u = i^4 and
+    u = j^4 (ring k = 4u + 12 i^2 k^2 + 2 k^4); with exact weights these are the
+    Laplacians 4 and 12 i^2 (the order-I weights are exact, so 4 exactly)."""
+    rows, cols = 24, 20
+    i = np.arange(rows, dtype=np.float64)[:, None] * np.ones((1, cols))
+    j = np.ones((rows, 1)) * np.arange(cols, dtype=np.float64)[None, :]
+    for r, c in rr_synth.FD_LAPLACIAN.items():
+        w = np.asarray(c, dtype=np.float32).astype(np.float64)
+        s0 = w[0] + 4 * w[1:].sum()
+        k = np.arange(1, r + 1, dtype=np.float64)
+        wk, kk = w[1:, None, None], k[:, None, None]
+        for u, expect in ((i ** 2 + j ** 2, lambda u: u * s0 + 4 * (w[1:] * k ** 2).sum()),
+                          (i ** 4, lambda u: u * s0 + (wk * (12 * i ** 2 * kk ** 2 + 2 * kk ** 4)).sum(axis=0)),
+                          (j ** 4, lambda u: u * s0 + (wk * (12 * j ** 2 * kk ** 2 + 2 * kk ** 4)).sum(axis=0))):
+            got = oracle.stencil2d(u.astype(np.float32), r, c, mutant=m)
+            ref = expect(u)
+            ref = ref if np.ndim(ref) else np.full(u.shape, ref)
+            if not np.allclose(_interior(got, r), _interior(ref, r), rtol=1e-12, atol=1e-9):
+                return False
+            if not np.array_equal(got[:r], u[:r]) or not np.array_equal(got[:, -r:], u[:, -r:]):
+                return False
+        if r == 1 and not np.array_equal(_interior(oracle.stencil2d((i ** 2 + j ** 2).astype(np.float32), 1, c,
+                                                                    mutant=m), 1), np.full((rows - 2, cols - 2), 4.0)):
+            return False
+    return True
+
+
+def pin_stencil_scipy(m=0):
+    """Star and box stencils == scipy.ndimage.correlate (float64) on the interior;
+    a star equals the box with the star's weights embedded."""
+    from scipy import ndimage
+    g = rr_synth.rng(81)
+    for t in range(12):
+        r = int(g.integers(1, 5))
+        rows, cols = int(g.integers(2 * r + 1, 40)), int(g.integers(2 * r + 1, 40))
+        x = rr_synth.random_grid(90 + t, rows, cols)
+        n = 2 * r + 1
+        box = g.uniform(-1, 1, (n, n)).astype(np.float32)
+        got = oracle.stencil2d(x, r, box, oracle.STENCIL_BOX, mutant=m)
+        ref = ndimage.correlate(x.astype(np.float64), box.astype(np.float64), mode="constant")
+        if not np.allclose(_interior(got, r), _interior(ref, r), rtol=1e-12, atol=1e-12):
+            return False
+        star = g.uniform(-1, 1, r + 1).astype(np.float32)
+        sbox = np.zeros((n, n), dtype=np.float32)
+        sbox[r, r] = star[0]
+        for k in range(1, r + 1):
+            sbox[r - k, r] = sbox[r + k, r] = sbox[r, r - k] = sbox[r, r + k] = star[k]
+        a = oracle.stencil2d(x, r, star, oracle.STENCIL_STAR, mutant=m)
+        b = ndimage.correlate(x.astype(np.float64), sbox.astype(np.float64), mode="constant")
+        if not np.allclose(_interior(a, r), _interior(b, r), rtol=1e-12, atol=1e-12):
+            return False
+    return True
+
+
 def pin_permute_at(m=0):
     dims, perm, e = (6, 5, 7, 3), (3, 0, 2, 1), 4
     x = rr_synth.random_bytes(21, int(np.prod(dims)) * e)
@@ -314,6 +380,8 @@ ALL_PINS = {
     "reorder_slice_permute": lambda gd, m: pin_reorder_slice_reduces_to_permute(m),
     "gather_range_numpy": lambda gd, m: pin_gather_and_range_numpy(m),
     "gather_invariants": lambda gd, m: pin_gather_invariants(m),
+    "stencil_closed_forms": lambda gd, m: pin_stencil_closed_forms(m),
+    "stencil_scipy": lambda gd, m: pin_stencil_scipy(m),
 }
 
 
@@ -323,11 +391,12 @@ def test_oracle_pin(name, golden_dir):
     assert ALL_PINS[name](golden_dir, 0), f"oracle fails pin {name}"
 
 
-@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7, 8])
+@pytest.mark.parametrize("mutant", [1, 2, 3, 4, 5, 6, 7, 8, 9])
 def test_planted_mistake_is_caught(mutant, golden_dir):
     """Each planted oracle mistake (gather/scatter swap, dropped term, wrong stride,
     transposed interlace, fixed axes read at 0, box start ignored, index set read
-    one late, range start ignored) must fail at least one pin."""
+    one late, range start ignored, stencil's vertical neighbours taken along the
+    row) must fail at least one pin."""
     oracle.build(mutant, force=False)
     assert oracle.mutant_id(mutant) == mutant
     failed = []
