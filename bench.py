@@ -354,6 +354,10 @@ def main():
             side["access_patterns"] = bench_access_patterns(rr, torch, pool, out, stream, timed)
         except Exception as ex:
             side["access_patterns"] = {"error": str(ex)}
+        try:
+            side["stencil"] = bench_stencil(rr, rr_synth, pool, out, stream, timed)
+        except Exception as ex:
+            side["stencil"] = {"error": str(ex)}
         del pool, out, flush
         torch.cuda.empty_cache()
         try:
@@ -427,6 +431,25 @@ def bench_access_patterns(rr, torch, pool, out, stream, timed):
             t = timed(lambda: rr.check(rr.copy_range_raw(out.data_ptr(), pool.data_ptr(), n, start, stride, cnt, e,
                                                          sh)), 5)
             res[f"range_stride{stride}_e{e}"] = {"GBps": round(2 * cnt * e / t / 1e9, 1), "elements": cnt}
+    return res
+
+
+def bench_stencil(rr, rr_synth, pool, out, stream, timed):
+    """2-D stencils on float grids of pool data: FD orders I-IV (star) and 3x3 /
+    5x5 boxes on Table 4's 4096 x 4096 grid and on 16384 x 16384; GB/s counts one
+    read and one write of the grid (the paper's accounting)."""
+    res = {}
+    g = rr_synth.rng(4)
+    for rows, cols in rr_synth.STENCIL_GRIDS:
+        nb = rows * cols * 4
+        assert nb <= pool.numel() and nb <= out.numel()
+        cases = [(f"fd_order{r}", r, c, 0) for r, c in rr_synth.FD_LAPLACIAN.items()]
+        cases += [(f"box{2 * r + 1}x{2 * r + 1}", r, g.uniform(-1, 1, (2 * r + 1) ** 2).astype("float32"), 1)
+                  for r in (1, 2)]
+        for name, r, w, shape in cases:
+            t = timed(lambda: rr.check(rr.stencil2d_raw(out.data_ptr(), pool.data_ptr(), rows, cols, r, w, shape,
+                                                        stream.cuda_stream)), 5)
+            res[f"{rows}x{cols}_{name}"] = round(2 * nb / t / 1e9, 1)
     return res
 
 

@@ -126,6 +126,27 @@ rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t s
                         int64_t count, int elem_size, rr_stream_t stream);
 
 /* -------------------------------------------------------------------------
+ * 2-D stencil (Sec. III.D, generic stencil kernel; its measured case is a
+ * finite-difference stencil of orders I-IV on single-precision grids).  Each
+ * point of a rows x cols float grid (row-major) becomes a weighted sum of its
+ * neighbours, evaluated with fp32 fused multiply-adds:
+ *   RR_STENCIL_STAR: weights[0..radius]; out = w0*x[i][j] + sum_{k=1..radius}
+ *     wk * ((x[i-k][j] + x[i+k][j]) + (x[i][j-k] + x[i][j+k])).
+ *   RR_STENCIL_BOX: weights[(2*radius+1)^2], row-major over dy = -r..r,
+ *     dx = -r..r; out = sum w[dy][dx] * x[i+dy][j+dx].
+ * Points closer than radius to an edge keep their input value.
+ *   dst, src   device grids of rows*cols floats, 4-byte aligned, not overlapping.
+ *   radius     1..4.  weights: host array (copied at the call).
+ * Each workgroup produces a 64 x 128 tile from LDS holding it plus its halo.
+ * Errors: RR_ERR_INVALID_ARG, RR_ERR_OVERFLOW, RR_ERR_ALIAS, RR_ERR_UNSUPPORTED,
+ * RR_ERR_HIP.
+ */
+#define RR_STENCIL_STAR 0
+#define RR_STENCIL_BOX 1
+rr_status rr_stencil2d(float* dst, const float* src, int64_t rows, int64_t cols, int radius, int shape,
+                       const float* weights, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
  * Interlace (Sec. III.C): join n equally long data sets, set index fastest:
  *   dst[i*n + c] = srcs[c][i]    for 0 <= i < count, 0 <= c < n.
  *   dst   device buffer of n*count*elem_size bytes.

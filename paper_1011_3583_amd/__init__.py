@@ -25,7 +25,7 @@ STATUS = {0: "RR_OK", 1: "RR_ERR_INVALID_ARG", 2: "RR_ERR_OVERFLOW", 3: "RR_ERR_
 STATUS_CODE = {v: k for k, v in STATUS.items()}
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
-EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_interlace", "rr_deinterlace",
+EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_stencil2d", "rr_interlace", "rr_deinterlace",
            "rr_permute_batched",
            "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
@@ -115,6 +115,7 @@ def lib() -> ctypes.CDLL:
     L.rr_reorder.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, vp]
     L.rr_gather.argtypes = [vp, vp, i64, vp, i64, i32, vp, vp]
     L.rr_copy_range.argtypes = [vp, vp, i64, i64, i64, i64, i32, vp]
+    L.rr_stencil2d.argtypes = [vp, vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
     L.rr_reorder_describe.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
     L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
@@ -191,6 +192,16 @@ def copy_range_raw(dst: int, src: int, src_count: int, start: int, stride: int, 
     """rr_copy_range on raw device addresses; returns the rr_status."""
     return lib().rr_copy_range(dst, src, int(src_count), int(start), int(stride), int(count), int(elem_size),
                                _stream_handle(stream))
+
+
+STENCIL_STAR, STENCIL_BOX = 0, 1
+
+
+def stencil2d_raw(dst: int, src: int, rows: int, cols: int, radius: int, weights, shape: int = STENCIL_STAR,
+                  stream=0) -> int:
+    """rr_stencil2d on raw device addresses of float grids; returns the rr_status."""
+    w = (ctypes.c_float * max(1, len(weights)))(*[float(x) for x in weights])
+    return lib().rr_stencil2d(dst, src, int(rows), int(cols), int(radius), int(shape), w, _stream_handle(stream))
 
 
 def interlace_raw(dst: int, srcs, count: int, elem_size: int, stream=0) -> int:

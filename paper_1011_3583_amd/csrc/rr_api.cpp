@@ -166,6 +166,35 @@ rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t s
     return RR_OK;
 }
 
+rr_status rr_stencil2d(float* dst, const float* src, int64_t rows, int64_t cols, int radius, int shape,
+                       const float* weights, rr_stream_t stream) {
+    clear_error();
+    if (rows < 0 || cols < 0) return fail(RR_ERR_INVALID_ARG, "rows and cols must be >= 0");
+    if (radius < 1 || radius > ST_MAXR) return fail(RR_ERR_INVALID_ARG, "radius must be 1..4");
+    if (shape != RR_STENCIL_STAR && shape != RR_STENCIL_BOX) return fail(RR_ERR_INVALID_ARG, "unknown stencil shape");
+    if (!weights) return fail(RR_ERR_INVALID_ARG, "NULL weights");
+    int64_t n, bytes;
+    if (__builtin_mul_overflow(rows, cols, &n) || __builtin_mul_overflow(n, (int64_t)4, &bytes))
+        return fail(RR_ERR_OVERFLOW, "grid size overflows int64");
+    if (n == 0) return RR_OK;
+    if (!dst || !src) return fail(RR_ERR_INVALID_ARG, "NULL grid");
+    if (((uint64_t)dst | (uint64_t)src) % 4) return fail(RR_ERR_INVALID_ARG, "grids must be 4-byte aligned");
+    if (ranges_overlap((uint64_t)dst, bytes, (uint64_t)src, bytes)) return fail(RR_ERR_ALIAS, "grids overlap");
+    StencilArgs a;
+    std::memset(&a, 0, sizeof a);
+    a.src = (uint64_t)src; a.dst = (uint64_t)dst; a.rows = rows; a.cols = cols;
+    a.radius = radius; a.shape = shape;
+    const int nw = shape == RR_STENCIL_STAR ? radius + 1 : (2 * radius + 1) * (2 * radius + 1);
+    for (int k = 0; k < nw; ++k) a.w[k] = weights[k];
+    const int64_t tx = (cols + ST_TW - 1) / ST_TW, ty = (rows + ST_TH - 1) / ST_TH;
+    if (tx > 0x7fffffffLL / std::max<int64_t>(ty, 1)) return fail(RR_ERR_UNSUPPORTED, "grid needs too many tiles");
+    a.tiles_x = (uint32_t)tx;
+    a.ntiles = (uint32_t)(tx * ty);
+    hipError_t e = launch_stencil(a, (hipStream_t)stream);
+    if (e != hipSuccess) return hip_fail(e, "rr_stencil2d launch");
+    return RR_OK;
+}
+
 static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
                                   int elem_size, rr_stream_t stream, bool de) {
     clear_error();

@@ -358,6 +358,119 @@ RR_HD uint32_t gather_thread(const GatherArgs& a, uint64_t block, uint64_t nbloc
     return nbad;
 }
 
+// ----------------------------------------------------------------- 2-D stencil
+RR_HD float bits_to_float(uint32_t u) { return __builtin_bit_cast(float, u); }
+RR_HD uint32_t float_to_bits(float f) { return __builtin_bit_cast(uint32_t, f); }
+
+// Load phase: the tile's rows plus R halo rows above and below, each as
+// ST_PITCH floats starting ST_HALO columns left of the tile, into LDS as 16-byte
+// vectors (element by element where a vector crosses the grid's edge; points
+// outside the grid are zero and never used).
+template <int R>
+RR_HD void stencil_load(const StencilArgs& a, uint32_t tile, uint32_t* lds, uint32_t tid) {
+    constexpr int LR = ST_TH + 2 * R;
+    constexpr int NV = ST_PITCH / 4;
+    const int64_t ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const int64_t i0 = ty * ST_TH - R, j0 = tx * ST_TW - ST_HALO;
+    const uint8_t* src = reinterpret_cast<const uint8_t*>(a.src);
+    for (uint32_t v = tid; v < (uint32_t)(LR * NV); v += NT) {
+        const int lr = (int)(v / NV), lc = (int)(v - (uint32_t)lr * NV) * 4;
+        const int64_t gi = i0 + lr, gj = j0 + lc;
+        uint32_t w[4] = {0, 0, 0, 0};
+        if (gi >= 0 && gi < a.rows) {
+            const uint8_t* row = src + (uint64_t)gi * (uint64_t)a.cols * 4;
+            if (gj >= 0 && gj + 4 <= a.cols) {
+                gload16u(row + gj * 4, w);
+            } else {
+                for (int e = 0; e < 4; ++e)
+                    if (gj + e >= 0 && gj + e < a.cols) {
+                        uint32_t one[1];
+                        gload<4>(row + (gj + e) * 4, one);
+                        w[e] = one[0];
+                    }
+            }
+        }
+        sstore<16>(reinterpret_cast<uint8_t*>(lds + lr * ST_PITCH + lc), w);
+    }
+}
+
+// Compute phase: thread (cx = tid % 32, ry = tid / 32) produces the four points
+// at columns 4cx..4cx+3 of tile rows ry, ry+8, ... (ST_TH / 8 rows).  Every
+// LDS read is an aligned 16-byte vector: three for the horizontal window, one
+// per vertical neighbour row.  Accumulation is fp32 FMA: center first, then
+// ring k = (up + down) + (left + right) for a star, row by row for a box.
+template <int R, int SHAPE>
+RR_HD void stencil_compute(const StencilArgs& a, uint32_t tile, const uint32_t* lds, uint32_t tid) {
+    constexpr int N = 2 * R + 1;
+    const int64_t ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
+    const uint32_t cx = tid % 32, ry = tid / 32;
+    const int64_t gj = tx * ST_TW + cx * 4;
+    if (gj >= a.cols) return;
+    const int lc = ST_HALO + (int)cx * 4;
+    uint8_t* dst = reinterpret_cast<uint8_t*>(a.dst);
+    for (int s = 0; s < ST_TH / 8; ++s) {
+        const int li = (int)ry + s * 8;
+        const int64_t gi = ty * ST_TH + li;
+        if (gi >= a.rows) break;
+        const uint32_t* c = lds + (li + R) * ST_PITCH + lc;   // first output point's center
+        float acc[4];
+        uint32_t ctr[4];
+        sload<16>(reinterpret_cast<const uint8_t*>(c), ctr);
+        if constexpr (SHAPE == 0) {
+            uint32_t hw[12];   // columns lc-4 .. lc+7 of the center row
+            sload<16>(reinterpret_cast<const uint8_t*>(c - 4), *reinterpret_cast<uint32_t(*)[4]>(&hw[0]));
+            sload<16>(reinterpret_cast<const uint8_t*>(c + 4), *reinterpret_cast<uint32_t(*)[4]>(&hw[8]));
+#pragma unroll
+            for (int e = 0; e < 4; ++e) { hw[4 + e] = ctr[e]; acc[e] = a.w[0] * bits_to_float(ctr[e]); }
+#pragma unroll
+            for (int k = 1; k <= R; ++k) {
+                uint32_t up[4], dn[4];
+                sload<16>(reinterpret_cast<const uint8_t*>(c - k * ST_PITCH), up);
+                sload<16>(reinterpret_cast<const uint8_t*>(c + k * ST_PITCH), dn);
+#pragma unroll
+                for (int e = 0; e < 4; ++e) {
+                    const float ring = (bits_to_float(up[e]) + bits_to_float(dn[e])) +
+                                       (bits_to_float(hw[4 + e - k]) + bits_to_float(hw[4 + e + k]));
+                    acc[e] = __builtin_fmaf(a.w[k], ring, acc[e]);
+                }
+            }
+        } else {
+#pragma unroll
+            for (int e = 0; e < 4; ++e) acc[e] = 0.0f;
+#pragma unroll
+            for (int dy = -R; dy <= R; ++dy) {
+                uint32_t hw[12];
+                const uint32_t* rowp = c + dy * ST_PITCH;
+                sload<16>(reinterpret_cast<const uint8_t*>(rowp - 4), *reinterpret_cast<uint32_t(*)[4]>(&hw[0]));
+                sload<16>(reinterpret_cast<const uint8_t*>(rowp), *reinterpret_cast<uint32_t(*)[4]>(&hw[4]));
+                sload<16>(reinterpret_cast<const uint8_t*>(rowp + 4), *reinterpret_cast<uint32_t(*)[4]>(&hw[8]));
+#pragma unroll
+                for (int dx = -R; dx <= R; ++dx)
+#pragma unroll
+                    for (int e = 0; e < 4; ++e)
+                        acc[e] = __builtin_fmaf(a.w[(dy + R) * N + dx + R], bits_to_float(hw[4 + e + dx]), acc[e]);
+            }
+        }
+        uint32_t o[4];
+        const bool row_edge = gi < R || gi >= a.rows - R;
+#pragma unroll
+        for (int e = 0; e < 4; ++e) {
+            const int64_t j = gj + e;
+            o[e] = (row_edge || j < R || j >= a.cols - R) ? ctr[e] : float_to_bits(acc[e]);
+        }
+        uint8_t* q = dst + ((uint64_t)gi * (uint64_t)a.cols + (uint64_t)gj) * 4;
+        if (gj + 4 <= a.cols) {
+            gstore16u(q, o);
+        } else {
+            for (int e = 0; e < 4; ++e)
+                if (gj + e < a.cols) {
+                    uint32_t one[1] = {o[e]};
+                    gstore<4>(q + e * 4, one);
+                }
+        }
+    }
+}
+
 // ----------------------------------------------------------------- run copy
 // Output is written contiguously; each W-byte vector is read from the input run
 // its output run maps to.

@@ -28,6 +28,14 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyArgs a) {
     copy_thread<W>(a, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
+template <int R, int SHAPE>
+__global__ __launch_bounds__(NT) void k_stencil(const StencilArgs a) {
+    __shared__ __attribute__((aligned(16))) uint32_t lds[(ST_TH + 2 * R) * ST_PITCH];
+    stencil_load<R>(a, blockIdx.x, lds, threadIdx.x);
+    __syncthreads();
+    stencil_compute<R, SHAPE>(a, blockIdx.x, lds, threadIdx.x);
+}
+
 template <int W>
 __global__ __launch_bounds__(NT) void k_gather(const GatherArgs a) {
     const uint32_t nbad = gather_thread<W>(a, blockIdx.x, gridDim.x, threadIdx.x);
@@ -182,6 +190,23 @@ hipError_t launch_batch_group(const BatchGroup& g, const uint8_t* table, uint32_
         case 1601: return launch_batch_tile_ug<16, 1>(g, table, grid, st);
         default: return hipErrorInvalidValue;
     }
+}
+
+hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    const dim3 g(a.ntiles), b(NT);
+    switch (a.radius * 2 + a.shape) {
+        case 2: hipLaunchKernelGGL((k_stencil<1, 0>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_stencil<1, 1>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_stencil<2, 0>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_stencil<2, 1>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_stencil<3, 0>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_stencil<3, 1>), g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_stencil<4, 0>), g, b, 0, st, a); break;
+        case 9: hipLaunchKernelGGL((k_stencil<4, 1>), g, b, 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
 }
 
 hipError_t launch_plan(const Plan& p, hipStream_t st) {

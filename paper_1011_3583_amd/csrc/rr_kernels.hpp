@@ -11,6 +11,9 @@ namespace rr {
 // Enqueue the kernel a plan selects on `st`.  Returns the launch status.
 hipError_t launch_plan(const Plan& p, hipStream_t st);
 
+// Enqueue the 2-D stencil kernel for radius 1..4 and shape 0/1.
+hipError_t launch_stencil(const StencilArgs& a, hipStream_t st);
+
 // Enqueue one batch group whose table (argument blocks + prefix sums) is
 // resident in device memory at `table`.  grid = 0 launches one workgroup per
 // block of work; a smaller grid makes the launch persistent (grid-stride).

@@ -67,6 +67,23 @@ struct GatherArgs {
     uint32_t pad_;
 };
 
+// 2-D stencil over a rows x cols float grid (Sec. III.D).  shape 0 (star):
+// w[0] center, w[k] the four points at distance k along the axes; shape 1
+// (box): w[(dy+r)*(2r+1) + dx+r].  Points closer than r to an edge keep
+// their input.  Output tiles are ST_TH x ST_TW points, tile t at row
+// (t / tiles_x) * ST_TH, column (t % tiles_x) * ST_TW.
+constexpr int ST_TW = 128, ST_TH = 64;      // output tile (columns x rows)
+constexpr int ST_HALO = 4;                  // columns loaded on each side (>= radius)
+constexpr int ST_PITCH = ST_TW + 2 * ST_HALO;   // floats per LDS row
+constexpr int ST_MAXR = 4;
+struct StencilArgs {
+    uint64_t src, dst;
+    int64_t rows, cols;
+    uint32_t tiles_x, ntiles;
+    int32_t radius, shape;
+    float w[(2 * ST_MAXR + 1) * (2 * ST_MAXR + 1)];
+};
+
 struct RunArgs {
     uint64_t src, dst;
     uint32_t nvec;        // total W-byte vectors

@@ -13,6 +13,7 @@
 //   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt infile outfile
 //   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
 //   gather   src_count count esize indexed start stride src_off dst_off infile idxfile outfile
+//   stencil  rows cols radius shape nweights w... infile outfile             (float grids)
 //   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
 //   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
@@ -151,6 +152,32 @@ static bool emulate_group(const BatchGroup& g, const uint8_t* table) {
     return false;
 }
 
+template <int R, int SHAPE>
+static void run_stencil_rs(const StencilArgs& a) {
+    const size_t nl = (size_t)(ST_TH + 2 * R) * ST_PITCH;
+    for (uint32_t tile = 0; tile < a.ntiles; ++tile) {
+        uint32_t* lds = new uint32_t[nl];
+        std::memset(lds, 0xA5, nl * 4);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_load<R>(a, tile, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_compute<R, SHAPE>(a, tile, lds, tid);
+        delete[] lds;
+    }
+}
+
+static bool run_stencil(const StencilArgs& a) {
+    switch (a.radius * 2 + a.shape) {
+        case 2: run_stencil_rs<1, 0>(a); return true;
+        case 3: run_stencil_rs<1, 1>(a); return true;
+        case 4: run_stencil_rs<2, 0>(a); return true;
+        case 5: run_stencil_rs<2, 1>(a); return true;
+        case 6: run_stencil_rs<3, 0>(a); return true;
+        case 7: run_stencil_rs<3, 1>(a); return true;
+        case 8: run_stencil_rs<4, 0>(a); return true;
+        case 9: run_stencil_rs<4, 1>(a); return true;
+    }
+    return false;
+}
+
 static uint64_t g_bad = 0;   // rejected indices of the last gather
 
 template <int W>
@@ -231,6 +258,30 @@ int main(int argc, char** argv) {
             for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
             write_file(outf, dbuf + doff, nb);
             std::printf("ok %s\n", describe(plan).c_str());
+            delete[] sbuf;
+            delete[] dbuf;
+        } else if (op == "stencil") {
+            // stencil rows cols radius shape nweights w... infile outfile  (float grids)
+            int64_t rows, cols; int radius, shape, nw; std::string inf, outf;
+            is >> rows >> cols >> radius >> shape >> nw;
+            StencilArgs a;
+            std::memset(&a, 0, sizeof a);
+            for (int k = 0; k < nw; ++k) is >> a.w[k];
+            is >> inf >> outf;
+            std::vector<uint8_t> in = read_file(inf);
+            const size_t nb = (size_t)(rows * cols * 4);
+            uint32_t* sbuf = new uint32_t[nb / 4 + 1];
+            uint32_t* dbuf = new uint32_t[nb / 4 + 1];
+            if (nb) std::memcpy(sbuf, in.data(), nb);
+            std::memset(dbuf, 0x5A, nb + 4);
+            a.src = (uint64_t)sbuf; a.dst = (uint64_t)dbuf; a.rows = rows; a.cols = cols;
+            a.radius = radius; a.shape = shape;
+            a.tiles_x = (uint32_t)((cols + ST_TW - 1) / ST_TW);
+            a.ntiles = (uint32_t)(a.tiles_x * ((rows + ST_TH - 1) / ST_TH));
+            if (nb && !run_stencil(a)) { std::printf("err -1 no kernel\n"); return 3; }
+            if (reinterpret_cast<uint8_t*>(dbuf)[nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+            write_file(outf, reinterpret_cast<uint8_t*>(dbuf), nb);
+            std::printf("ok stencil tiles=%u\n", a.ntiles);
             delete[] sbuf;
             delete[] dbuf;
         } else if (op == "gather") {

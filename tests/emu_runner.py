@@ -60,6 +60,11 @@ def run(jobs):
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))), str(int(j.get("xcd", False))),
                                        str(int(j.get("umt", 0))), inf, outf]))
+            elif j["op"] == "stencil":
+                np.ascontiguousarray(j["grid"], dtype=np.float32).tofile(inf)
+                w = [repr(float(v)) for v in np.asarray(j["weights"], dtype=np.float32).reshape(-1)]
+                lines.append(" ".join(map(str, ["stencil", j["grid"].shape[0], j["grid"].shape[1], j["radius"],
+                                                 j.get("shape", 0), len(w), *w, inf, outf])))
             elif j["op"] == "gather":
                 j["input"].tofile(inf)
                 idxf = os.path.join(td, f"idx{i}")
@@ -110,6 +115,9 @@ def run(jobs):
             if j["op"] == "batched":
                 out.append((s, [np.fromfile(os.path.join(td, f"bo{i}_{k}"), dtype=np.uint8)
                                 for k in range(len(j["jobs"]))]))
+                continue
+            if j["op"] == "stencil":
+                out.append((s, np.fromfile(outf, dtype=np.float32).reshape(j["grid"].shape)))
                 continue
             data = np.fromfile(outf, dtype=np.uint8)
             if j["op"] == "deinterlace":

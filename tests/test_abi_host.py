@@ -18,7 +18,7 @@ ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
 def _header_functions():
     src = open(os.path.join(ROOT, "include", "rr.h")).read()
     src = re.sub(r"/\*.*?\*/", "", src, flags=re.S)
-    return sorted(set(re.findall(r"\b(rr_[a-z_]+)\s*\(", src)))
+    return sorted(set(re.findall(r"\b(rr_[a-z0-9_]+)\s*\(", src)))
 
 
 def test_library_exports_every_declared_symbol():
@@ -273,3 +273,15 @@ def test_gather_and_range_validation():
     assert rr.copy_range_raw(0x1000 + 8, 0x1000, 10, 0, 1, 5, 4) == 3        # dst inside the bytes read
     assert rr.copy_range_raw(0, 0, 10, 3, 1, 0, 4) == 0                      # empty: no-op
     assert rr.copy_range_raw(0x100000, 0x1000, 1 << 62, 0, 1 << 40, 1 << 30, 4) == 2   # overflow
+
+
+def test_stencil_validation():
+    w = [-4.0, 1.0]
+    assert rr.stencil2d_raw(0x100000, 0x200000, 16, 16, 0, w) == 1          # radius
+    assert rr.stencil2d_raw(0x100000, 0x200000, 16, 16, 5, w) == 1
+    assert rr.stencil2d_raw(0x100000, 0x200000, 16, 16, 1, w, shape=2) == 1
+    assert rr.stencil2d_raw(0x100000, 0x200000, -1, 16, 1, w) == 1          # rows
+    assert rr.stencil2d_raw(0x100002, 0x200000, 16, 16, 1, w) == 1          # alignment
+    assert rr.stencil2d_raw(0x100000, 0x100000 + 512, 16, 16, 1, w) == 3    # overlap
+    assert rr.stencil2d_raw(0, 0, 0, 16, 1, w) == 0                         # empty grid
+    assert rr.stencil2d_raw(0x100000, 0x200000, 1 << 40, 1 << 40, 1, w) == 2

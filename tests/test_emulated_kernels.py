@@ -455,3 +455,54 @@ def test_emu_gather_and_range():
         ref, nbad = gather_ref(j)
         assert np.array_equal(out, ref), (j.get("start"), j.get("stride"), j["esize"], st)
         assert int(st.split("bad=")[1]) == nbad, st
+
+
+def stencil_tolerance(x, radius, weights, shape):
+    """Per-point bound on |fp32 result - exact|: the fp32 evaluation of n products
+    (n = 4r + 1 for a star, (2r + 1)^2 for a box) and the final rounding add at most
+    (n + 2) * 2^-24 * sum |w * x| over the stencil's points."""
+    from scipy import ndimage
+    r = radius
+    n = 4 * r + 1 if shape == 0 else (2 * r + 1) ** 2
+    w = np.abs(np.asarray(weights, dtype=np.float32).astype(np.float64))
+    if shape == 0:
+        k = np.zeros((2 * r + 1, 2 * r + 1))
+        k[r, r] = w[0]
+        for d in range(1, r + 1):
+            k[r - d, r] = k[r + d, r] = k[r, r - d] = k[r, r + d] = w[d]
+    else:
+        k = w.reshape(2 * r + 1, 2 * r + 1)
+    s = ndimage.correlate(np.abs(x.astype(np.float64)), k, mode="constant")
+    return (n + 2) * 2.0 ** -24 * s + 1e-30
+
+
+def check_stencil(out, x, radius, weights, shape):
+    ref = oracle.stencil2d(x, radius, weights, shape)
+    tol = stencil_tolerance(x, radius, weights, shape)
+    err = np.abs(out.astype(np.float64) - ref)
+    r = radius
+    edge = np.ones(x.shape, dtype=bool)
+    edge[r:x.shape[0] - r, r:x.shape[1] - r] = False
+    assert np.array_equal(out[edge], x[edge]), "edge points must keep their input"
+    bad = err > tol
+    assert not bad.any(), (int(bad.sum()), float((err / tol).max()))
+
+
+STENCIL_GRIDS_SMALL = [(1, 1), (3, 3), (9, 9), (64, 128), (65, 129), (130, 300), (200, 131), (7, 500)]
+
+
+def test_emu_stencil_fd_orders_and_box():
+    """FD stencils of orders I-IV and random box stencils on grids spanning several
+    64 x 128 tiles, ragged edges and grids smaller than the stencil."""
+    jobs = []
+    g = rr_synth.rng(17)
+    for t, (rows, cols) in enumerate(STENCIL_GRIDS_SMALL):
+        x = rr_synth.random_grid(300 + t, rows, cols)
+        for r, c in rr_synth.FD_LAPLACIAN.items():
+            jobs.append(dict(op="stencil", grid=x, radius=r, weights=c, shape=0))
+        r = int(g.integers(1, 5))
+        jobs.append(dict(op="stencil", grid=x, radius=r, shape=1,
+                         weights=g.uniform(-1, 1, (2 * r + 1) ** 2).astype(np.float32)))
+    for j, (st, out) in zip(jobs, emu_runner.run(jobs)):
+        assert st.startswith("ok"), st
+        check_stencil(out, j["grid"], j["radius"], j["weights"], j["shape"])
