@@ -60,7 +60,7 @@ rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims, 
     if (c.total_bytes == 0) return RR_OK;
     Plan p;
     std::string why;
-    st = plan_permute((uint64_t)dst, (uint64_t)src, c, tile_override(), &p, &why);
+    st = plan_permute((uint64_t)dst, (uint64_t)src, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_permute launch");
@@ -92,7 +92,7 @@ rr_status rr_reorder(void* dst, const void* src, int ndim, const int64_t* dims, 
     if (c.total_bytes == 0) return RR_OK;
     Plan p;
     std::string why;
-    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, tile_override(), &p, &why);
+    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_reorder launch");
@@ -110,7 +110,7 @@ rr_status rr_reorder_describe(const void* dst, const void* src, int ndim, const 
     rr_status st = canonicalize_view(ndim, dims, base, range, out_ndim, order, elem_size, &c, &off, &span, &why);
     if (st != RR_OK) return fail(st, why);
     Plan p;
-    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, tile_override(), &p, &why);
+    st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
     std::string s = describe(p);
     std::snprintf(buf, (size_t)buflen, "%s", s.c_str());
@@ -222,7 +222,7 @@ static rr_status interlace_common(void* flat, const void* const* planes, int n, 
                     return fail(RR_ERR_ALIAS, "output planes overlap");
     Plan p;
     std::string why;
-    rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, tile_override(), &p, &why);
+    rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, de ? "rr_deinterlace launch" : "rr_interlace launch");
@@ -263,7 +263,7 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
     rr_status st = canonicalize(ndim, dims, perm, elem_size, &c, &why);
     if (st != RR_OK) return fail(st, why);
     Plan p;
-    st = plan_permute((uint64_t)dst, (uint64_t)src, c, tile_override(), &p, &why);
+    st = plan_permute((uint64_t)dst, (uint64_t)src, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
     std::string s = describe(p);
     std::snprintf(buf, (size_t)buflen, "%s", s.c_str());
@@ -278,7 +278,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     if (!valid_max_g(max_g)) return fail(RR_ERR_INVALID_ARG, "micro-tile cap must be 0, 1, 2, 4, 8 or 16");
     const int tile_kib = (flags >> 16) & 0xff;
     if (!valid_tile_kib(tile_kib)) return fail(RR_ERR_INVALID_ARG, "tile size must be 0 or 4..64 KiB");
-    TileOptions& o = tile_override();
+    TileOptions o;
     o.max_g = max_g;
     o.tile_kib = tile_kib;
     o.xcd = (flags & RR_TILE_XCD) ? 1 : 0;
@@ -287,6 +287,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.out_row_bytes = out_row_bytes;
     o.order_out = (flags & RR_TILE_ORDER_IN) ? 0 : (flags & RR_TILE_ORDER_OUT) ? 1 : -1;
     o.force_ragged = (flags & RR_TILE_FORCE_RAGGED) ? 1 : 0;
+    set_tile_override(o);
     return RR_OK;
 }
 

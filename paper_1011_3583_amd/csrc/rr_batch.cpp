@@ -176,6 +176,7 @@ rr_status tune(rr_batch* b) {
     }
     (void)hipStreamDestroy(st);
     if (rs != RR_OK) return rs;
+    b->opt = TileOptions();
     b->opt.in_row_bytes = bestc.in_rb;
     b->opt.out_row_bytes = bestc.out_rb;
     b->opt.order_out = bestc.order;
@@ -195,7 +196,7 @@ extern "C" {
 rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) {
     clear_error();
     BatchPlan bp;
-    rr_status st = plan_or_fail(jobs, njobs, tile_override(), &bp);
+    rr_status st = plan_or_fail(jobs, njobs, current_tile_options(), &bp);
     if (st != RR_OK) return st;
     if (bp.groups.empty()) return RR_OK;
     int device = 0;
@@ -251,6 +252,7 @@ rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** o
     if (njobs > 0 && jobs) b->jobs.assign(jobs, jobs + njobs);
     hipError_t e = hipGetDevice(&b->device);
     rr_status st = e == hipSuccess ? RR_OK : hip_fail(e, "hipGetDevice");
+    b->opt = current_tile_options();   // the override if set, else built-in shapes + tuning cache
     if (st == RR_OK) st = plan_or_fail(jobs, njobs, b->opt, &b->plan);
     if (st == RR_OK) st = upload_table(b);
     if (st == RR_OK && (flags & RR_BATCH_TUNE) && !b->plan.groups.empty()) st = tune(b);

@@ -31,15 +31,27 @@ Magic make_magic(uint32_t d) {
     return Magic{(uint32_t)mul, l};
 }
 
-TileOptions& tile_override() {
-    static TileOptions o;
+namespace {
+std::mutex g_override_mu;
+TileOptions g_override;
+}  // namespace
+
+bool override_active(const TileOptions& o) {
+    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != 0 || o.umt != 0;
+}
+
+TileOptions current_tile_options() {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    TileOptions o = g_override;
+    o.use_tuned = !override_active(o);
     return o;
 }
 
-bool tile_override_active() {
-    const TileOptions& o = tile_override();
-    return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0 || o.xcd != 0 || o.umt != 0;
+void set_tile_override(const TileOptions& o) {
+    std::lock_guard<std::mutex> lk(g_override_mu);
+    g_override = o;
+    g_override.use_tuned = false;
 }
 
 namespace {
@@ -704,7 +716,7 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
     // a tuned shape for this problem replaces the built-in choice (not an explicit override)
     TileOptions tuned;
-    if (!tile_override_active() && &opt == &tile_override() && tune_lookup(tune_key(c, dst, src), &tuned)) {
+    if (opt.use_tuned && tune_lookup(tune_key(c, dst, src), &tuned)) {
         tuned.max_lds = opt.max_lds;
         return plan_tile(dst, src, c, tuned, p, why);
     }

@@ -173,15 +173,19 @@ struct TileOptions {
     int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead
                             // of the G = 1 ragged paths), 2 everywhere (testing)
     int max_lds = 65536;    // hard limit
+    bool use_tuned = false; // a tuned shape cached for the problem replaces these options
 };
 
 bool valid_max_g(int g);      // 0 or a power of two up to 16
 bool valid_tile_kib(int k);   // 0 or 4..64
 constexpr int DEFAULT_TILE_KIB = 16;
 
-// Process-wide override (autotuner hook).
-TileOptions& tile_override();
-bool tile_override_active();
+// Process-wide override (autotuner hook), read and written under a lock.
+// current_tile_options() is a snapshot: the override if one is set, else the
+// built-in defaults with use_tuned (tuning-cache lookups) enabled.
+TileOptions current_tile_options();
+void set_tile_override(const TileOptions& o);
+bool override_active(const TileOptions& o);
 
 // Tuning cache: canonical problem + alignment class -> tile options.
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src);

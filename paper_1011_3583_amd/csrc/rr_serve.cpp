@@ -307,7 +307,7 @@ struct rr_server {
         }
         j->t_admit = now_ns();
         std::string why;
-        rr_status st = plan_job(j->job, tile_override(), &j->plan, &why);
+        rr_status st = plan_job(j->job, current_tile_options(), &j->plan, &why);
         if (st != RR_OK) { j->status = st; return true; }
         if (!(cfg.flags & RR_SERVE_DIRECT) && cfg.chunk_bytes > 0 && j->plan.grid > 1 &&
             j->plan.bytes > cfg.chunk_bytes) {

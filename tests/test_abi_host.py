@@ -285,3 +285,38 @@ def test_stencil_validation():
     assert rr.stencil2d_raw(0x100000, 0x100000 + 512, 16, 16, 1, w) == 3    # overlap
     assert rr.stencil2d_raw(0, 0, 0, 16, 1, w) == 0                         # empty grid
     assert rr.stencil2d_raw(0x100000, 0x200000, 1 << 40, 1 << 40, 1, w) == 2
+
+
+def test_override_is_safe_across_threads():
+    """Planning on several threads while another flips the process-wide override:
+    every plan is one of the two consistent outcomes (the override is read as a
+    locked snapshot)."""
+    import threading
+    dims, perm, e = (4096, 4096), (1, 0), 1
+    rr.set_tile_override()
+    base = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    rr.set_tile_override(max_g=4)
+    capped = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    rr.set_tile_override()
+    ok = {base["g"] + base["TA"] + base["TB"], capped["g"] + capped["TA"] + capped["TB"]}
+    seen, errors = set(), []
+
+    def plan():
+        try:
+            for _ in range(400):
+                d = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+                seen.add(d["g"] + d["TA"] + d["TB"])
+        except Exception as ex:   # pragma: no cover - reported below
+            errors.append(ex)
+
+    def flip():
+        for k in range(400):
+            rr.set_tile_override(max_g=4 if k % 2 else 0)
+
+    ts = [threading.Thread(target=plan) for _ in range(4)] + [threading.Thread(target=flip)]
+    for t in ts:
+        t.start()
+    for t in ts:
+        t.join()
+    rr.set_tile_override()
+    assert not errors and seen <= ok, (errors, seen, ok)
