@@ -1,11 +1,14 @@
 /*
  * rr.h -- C ABI of librr, an MI355X (gfx950) library of data-rearrangement
- * kernels: N-D permute/transpose/reorder, interlace and de-interlace, a batched
- * launch for many uneven permutes, and a continuous-batching server.
+ * kernels: N-D permute/transpose/reorder (also of a box, N-to-M), index-set and
+ * range reads, interlace and de-interlace, a 2-D stencil, a batched launch for
+ * many uneven permutes, and a continuous-batching server.
  *
  * The operations are those of "Fast GPGPU Data Rearrangement Kernels using
- * CUDA" (arXiv:1011.3583), Sec. III.B (re-ordering an N-dimensional array under
- * a given order of its axes) and Sec. III.C (interlace / de-interlace).
+ * CUDA" (arXiv:1011.3583): Sec. III.A (read/write kernels with access
+ * patterns), Sec. III.B (re-ordering an N-dimensional array under a given order
+ * of its axes, N-to-N and N-to-M), Sec. III.C (interlace / de-interlace) and
+ * Sec. III.D (generic 2-D stencil).
  *
  * Conventions
  *  - Arrays are dense and row-major ("linearized storage", Sec. III.B): the LAST
@@ -13,8 +16,9 @@
  *    the output has shape out_dims[j] = dims[perm[j]] and
  *        out[J] = in[I]  with  I[perm[j]] = J[j].
  *    The paper lists orders fastest-dimension-first; rr_order_to_perm converts.
- *  - Elements are opaque runs of elem_size bytes (1..16).  No arithmetic is
- *    ever done on values: results are bit-exact copies (NaN payloads survive).
+ *  - Elements are opaque runs of elem_size bytes (1..16).  Apart from the
+ *    stencil (fp32 arithmetic, see rr_stencil2d) no arithmetic is ever done on
+ *    values: results are bit-exact copies (NaN payloads survive).
  *  - Device pointers are plain HIP device addresses (hipMalloc, or any torch
  *    CUDA tensor's data_ptr()).  The caller owns every buffer passed in; the
  *    library never frees caller memory.
@@ -206,8 +210,10 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
  *          RR_BATCH_PERSISTENT persistent grids (a few workgroups per CU that
  *                              loop over the group's work) instead of one
  *                              workgroup per block of work.
- * The handle's device is the current HIP device at creation.  Launches on
- * different streams must not overlap in time (they write the same outputs).
+ * Jobs are planned like rr_permute (the tile override if one is set, else the
+ * built-in shapes and the tuning cache).  The handle's device is the current
+ * HIP device at creation.  Launches on different streams must not overlap in
+ * time (they write the same outputs).
  * Errors: as rr_permute_batched; RR_ERR_NO_MEMORY if the table cannot be
  * allocated.
  */
@@ -218,7 +224,8 @@ typedef struct rr_batch rr_batch;
 
 typedef struct {
     int32_t njobs;             /* jobs with a non-empty problem                */
-    int32_t ngroups;           /* kernel families = launches per batch          */
+    int32_t ngroups;           /* groups (kernel family x LDS size class) =
+                                  launches per batch                           */
     int32_t in_row_bytes;      /* tile shape chosen (0 = built-in)              */
     int32_t out_row_bytes;
     int32_t order_out;         /* tile traversal in output order                */
