@@ -429,7 +429,11 @@ struct rr_server {
             BatchPlan bp;
             std::string why;
             rr_status st = RR_ERR_HIP;
-            if (!fail_this && direct) {
+            // a batch of one whole job needs no job table: launch it with its
+            // arguments by value (what one launch per request does)
+            const bool one_whole = entries.size() == 1 && entries[0].first_block == 0 &&
+                                   entries[0].nblocks == entries[0].plan->grid;
+            if (!fail_this && (direct || one_whole)) {
                 st = be->launch_single(slot, stream, *entries[0].plan);
                 bp.bytes = entries[0].bytes;
             } else if (!fail_this) {
