@@ -358,6 +358,10 @@ def main():
             side["stencil"] = bench_stencil(rr, rr_synth, pool, out, stream, timed)
         except Exception as ex:
             side["stencil"] = {"error": str(ex)}
+        try:
+            side["paper_tables"] = bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d)
+        except Exception as ex:
+            side["paper_tables"] = {"error": str(ex)}
         del pool, out, flush
         torch.cuda.empty_cache()
         try:
@@ -431,6 +435,52 @@ def bench_access_patterns(rr, torch, pool, out, stream, timed):
             t = timed(lambda: rr.check(rr.copy_range_raw(out.data_ptr(), pool.data_ptr(), n, start, stride, cnt, e,
                                                          sh)), 5)
             res[f"range_stride{stride}_e{e}"] = {"GBps": round(2 * cnt * e / t / 1e9, 1), "elements": cnt}
+    return res
+
+
+# The paper's own results on a Tesla C1060 (GB/s, read + write): Table 1
+# (3D permute of 128x256x512 floats; its memcpy row is 77.82), Table 2 (reorder)
+# and Table 3 (interlace / de-interlace of n arrays).  Context only.
+PAPER_MEMCPY_GBPS = 77.82
+PAPER_TABLE1 = {(0, 2, 1): 62.55, (1, 0, 2): 63.17, (1, 2, 0): 57.38, (2, 0, 1): 59.63, (2, 1, 0): 58.42}
+PAPER_TABLE2 = {(1, 0, 2): 76.00, (1, 0, 2, 3): 75.41, (3, 2, 0, 1): 56.24, (3, 0, 2, 1, 4): 43.40}
+PAPER_TABLE3 = {4: (70.93, 68.87), 5: (73.95, 68.50), 6: (71.51, 67.61), 7: (72.14, 60.21), 8: (58.58, 60.55),
+                9: (70.60, 58.25)}
+
+
+def bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d):
+    """The paper's Table 1-3 workloads (4-byte elements, its fastest-first order
+    notation), as % of this box's measured D2D copy next to the paper's % of its
+    memcpy."""
+    sh = stream.cuda_stream
+    res = {}
+
+    def row(gbps, paper):
+        return {"GBps": round(gbps, 1), "pct_of_d2d": round(100 * gbps / d2d, 1),
+                "paper_GBps_C1060": paper, "paper_pct_of_memcpy": round(100 * paper / PAPER_MEMCPY_GBPS, 1)}
+
+    sizes = rr_synth.PAPER_TABLE1_SIZES
+    dims = tuple(reversed(sizes))
+    for order, paper in PAPER_TABLE1.items():
+        perm = rr.order_to_perm(order)
+        nb = 4 * sizes[0] * sizes[1] * sizes[2]
+        t = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), dims, perm, 4, sh)), 5)
+        res[f"table1_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, paper)
+    for sz, order in rr_synth.PAPER_TABLE2:
+        dims = tuple(reversed(sz))
+        perm = rr.order_to_perm(order)
+        nb = 4
+        for d in sz:
+            nb *= d
+        t = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), dims, perm, 4, sh)), 5)
+        res[f"table2_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, PAPER_TABLE2[tuple(order)])
+    count = 1 << 24
+    for n, (pi, pd) in PAPER_TABLE3.items():
+        planes = [pool.data_ptr() + c * count * 4 for c in range(n)]
+        ti = timed(lambda: rr.check(rr.interlace_raw(out.data_ptr(), planes, count, 4, sh)), 5)
+        td = timed(lambda: rr.check(rr.deinterlace_raw(planes, out.data_ptr(), count, 4, sh)), 5)
+        res[f"table3_interlace_{n}"] = row(2 * n * count * 4 / ti / 1e9, pi)
+        res[f"table3_deinterlace_{n}"] = row(2 * n * count * 4 / td / 1e9, pd)
     return res
 
 

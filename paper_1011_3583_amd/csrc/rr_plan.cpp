@@ -424,6 +424,62 @@ static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 //   row_align_in : OR of every input row start offset (alignment probe)
 //   flat_ok      : input rows are back to back (row stride == row bytes) and the
 //                  whole extent along the row axis is total_rows
+// Share of each 128-byte line touched by one wave's store instruction that the
+// instruction writes, for a tile whose output rows hold TB units of U bytes,
+// row_stride bytes apart (0: rows lie in unrelated places, e.g. separate planes).
+// G > 1: lanes take micro-tiles B-fastest, so a wave writes runs of
+// min(TB / G, 64) * G * U contiguous bytes, one per micro-tile row, G output rows
+// apart; merged micro-tiles (TB == G, rows back to back) store their G rows as
+// 16-byte vectors, one vector per lane and instruction.  G == 1: 16-byte vectors
+// along each row, rows back to back when row_stride == TB * U.
+static double store_line_fill(int U, int G, uint32_t TB, uint64_t row_stride, bool merge) {
+    constexpr uint64_t LINE = 128, LANES = 64;
+    const uint64_t W = (uint64_t)U * G;
+    uint64_t run, nrun, step;
+    if (G == 1) {
+        const uint64_t rowb = (uint64_t)TB * U;
+        run = std::min<uint64_t>(rowb, 16 * LANES);
+        nrun = std::max<uint64_t>(1, 16 * LANES / rowb);
+        step = row_stride;
+    } else if (merge) {
+        run = 16; nrun = LANES; step = W * G;
+    } else {
+        const uint64_t nmb = TB / G;
+        run = std::min<uint64_t>(nmb, LANES) * W;
+        nrun = std::max<uint64_t>(1, LANES / nmb);
+        step = row_stride * G;
+    }
+    uint64_t lines;
+    if (nrun == 1 || step == 0 || step >= LINE) lines = nrun * ((run + LINE - 1) / LINE);
+    else lines = ((nrun - 1) * step + run + LINE - 1) / LINE;
+    if (step != 0 && step < run) lines = (nrun * run + LINE - 1) / LINE;   // runs overlap: contiguous
+    return (double)(nrun * run) / (double)(lines * LINE);
+}
+
+// Register micro-tiles on short output rows store partial lines (a 4 x 4 tile of
+// 4-byte elements whose output rows are 16 bytes writes one quarter of each line
+// it touches per instruction), which costs up to 3x against the G = 1 paths that
+// write whole 16-byte vectors along the output.  Walk G down while the best line
+// fill so far is poor and a smaller G fills strictly more; 4..16-byte elements
+// need more than half-filled lines, 1- and 2-byte elements (whose G = 1 paths
+// assemble vectors byte by byte from LDS) accept half.
+static int line_friendly_g(int U, int G, uint32_t TB, int nA, uint64_t row_stride, bool out_table) {
+    if (G <= 1) return G;
+    auto fill = [&](int g) {
+        const bool merge = g > 1 && !out_table && nA == 1 && TB == (uint32_t)g && row_stride == (uint64_t)U * g &&
+                           U * g >= 4 && (U * g * g) % 16 == 0;
+        return store_line_fill(U, g, TB, out_table ? 0 : row_stride, merge);
+    };
+    auto good = [&](double f) { return U >= 4 ? f > 0.5 : f >= 0.5; };
+    int best = G;
+    double fb = fill(G);
+    for (int g = G >> 1; g >= 1 && !good(fb); g >>= 1) {
+        const double f = fill(g);
+        if (f > fb) { best = g; fb = f; }
+    }
+    return best;
+}
+
 static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_align_in, bool flat_ok,
                              uint64_t flat_base, uint64_t total_rows, const TileOptions& opt,
                              std::string* why) {
@@ -696,6 +752,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     // the next slower input axis, adjacent to them
     const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA && sinb[b1] == innerA * t[aO] * R;
     if (umt) a.flags |= TF_UMT;
+    else G = line_friendly_g(U, G, a.TB, nA, a.soutA[0], false);
     rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, (uint64_t)d[b1], opt, why);
     if (st != RR_OK) return st;
     if (opt.xcd) a.flags |= TF_XCD;
@@ -753,6 +810,9 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     L = std::min<int64_t>(count, (L + 15) / 16 * 16);  // whole 16-byte vectors per row
     while (L > G && (int64_t)((L * R + 15) / 16 * 16) * n > opt.max_lds && !de) L = std::max<int64_t>(G, L / 2 / G * G);
     while (L > G && (int64_t)(((int64_t)n * R + 15) / 16 * 16) * L > opt.max_lds && de) L = std::max<int64_t>(G, L / 2 / G * G);
+    // interlaced output rows are n elements: keep micro-tiles only where they
+    // still write well-filled lines (de-interlace writes long plane rows)
+    if (!de) G = line_friendly_g(U, G, (uint32_t)n, 1, (uint64_t)(n * R), false);
     a.R = (uint32_t)R;
     a.ngrid = 0; a.grid_aO = -1; a.grid_bO = -1; a.grid_cO = -1;
     a.cO_len = 1; a.cO_t = 1;

@@ -335,6 +335,33 @@ def test_emu_flat_read_and_merged_store_paths():
     _check(jobs)
 
 
+# Micro-tile edge the planner keeps for interlace-shaped problems (n short output
+# rows of e-byte elements): micro-tiles survive only where a wave's stores still
+# fill at least half (1-2-byte elements) or more than half (4-16-byte elements)
+# of each line they touch, else G falls back toward the G = 1 vector paths.
+SHORT_ROW_G = {(1, 2): 2, (1, 4): 4, (1, 8): 2, (1, 16): 2,
+               (2, 2): 2, (2, 4): 4, (2, 8): 2, (2, 16): 2,
+               (4, 2): 2, (4, 4): 1, (4, 8): 1, (4, 16): 1,
+               (8, 2): 1, (8, 4): 1, (8, 8): 1, (8, 16): 2}
+
+
+def test_emu_short_output_rows_line_fill():
+    """Interlace-shaped permutes and interlaces of 2..16 sets of 1..8-byte elements:
+    the planner's micro-tile edge follows the store line-fill rule and every plan
+    stays bit-exact (several tiles plus a partial one)."""
+    count = 4104
+    jobs, keys = [], []
+    for (e, n), g in SHORT_ROW_G.items():
+        jobs.append(_perm_job((n, count), (1, 0), e, 9600 + 17 * n + e))
+        planes = [rr_synth.random_bytes(9700 + 17 * n + e + 1000 * c, count * e) for c in range(n)]
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
+        keys += [(e, n, g)] * 2
+    res = _check(jobs)
+    for (e, n, g), (status, _) in zip(keys, res):
+        got = int(status.split(" g=")[1].split()[0])
+        assert got == g, (e, n, got, g, status)
+
+
 def _batched_jobs(seed, njobs, max_elems=20000):
     g = rr_synth.rng(seed)
     jobs = []
