@@ -657,6 +657,12 @@ RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t
         for (int u = 0; u < B; ++u)
             if (ok[u]) sstore<16>(lds + (base + u * NT + tid) * 16, w[u]);
     }
+    // the input's last tile may end inside a 16-byte vector: its last bytes one by one
+    const uint32_t tail = nbytes - nvec * 16;
+    if (tid < tail) {
+        const uint32_t x = nvec * 16 + tid;
+        lds[x] = reinterpret_cast<const uint8_t*>(t.bin)[x];
+    }
 }
 
 // Walk n items laid out as rows of `per` items with NT threads: item f = tid +

@@ -420,10 +420,6 @@ static int default_row_bytes(int U, bool in_side) {
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
 
-// Fill the LDS / read / write geometry of a tile plan whose extents are set.
-//   row_align_in : OR of every input row start offset (alignment probe)
-//   flat_ok      : input rows are back to back (row stride == row bytes) and the
-//                  whole extent along the row axis is total_rows
 // Share of each 128-byte line touched by one wave's store instruction that the
 // instruction writes, for a tile whose output rows hold TB units of U bytes,
 // row_stride bytes apart (0: rows lie in unrelated places, e.g. separate planes).
@@ -480,6 +476,12 @@ static int line_friendly_g(int U, int G, uint32_t TB, int nA, uint64_t row_strid
     return best;
 }
 
+// Fill the LDS / read / write geometry of a tile plan whose extents are set.
+//   row_align_in : OR of every input row start offset (alignment probe)
+//   flat_ok      : input rows are back to back (row stride == row bytes), so a
+//                  tile's input is one contiguous range starting at flat_base
+//                  plus a multiple of TB rows; total_rows is the row axis's whole
+//                  extent when slower axes follow it (0 when none do)
 static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_align_in, bool flat_ok,
                              uint64_t flat_base, uint64_t total_rows, const TileOptions& opt,
                              std::string* why) {
@@ -499,6 +501,8 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
         return RR_OK;
     }
     const uint64_t rowbytes = (uint64_t)a.TA * a.R;
+    // every tile's range starts on a 16-byte boundary (also across slower axes);
+    // the input's last tile may end inside a vector (its tail moves byte by byte)
     const bool flat = flat_ok && (rowbytes % 16 != 0 || rowbytes < 64) && (flat_base % 16) == 0 &&
                       ((uint64_t)a.TB * rowbytes) % 16 == 0 && (total_rows * rowbytes) % 16 == 0;
     if (flat) {
@@ -697,6 +701,17 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
             a.soutC = (uint64_t)(sout_el[cax] * R);
         }
     }
+    // Rows back to back (A whole, B the next slower input axis): a tile's input is
+    // one range, read as 16-byte vectors when every tile starts on a 16-byte
+    // boundary, so short rows take B in multiples of 16 / gcd(row bytes, 16).
+    if (cax < 0 && !umt && nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA && sinb[b1] == innerA * t[aO] * R) {
+        const int64_t rowb = innerA * t[aO] * R;
+        if (rowb % 16 != 0 || rowb < 64) {
+            const int64_t low = std::min<int64_t>(rowb & -rowb, 16);
+            const int64_t m = std::max<int64_t>(G, 16 / low);
+            if (t[b1] < d[b1] && t[b1] >= m) t[b1] = t[b1] / m * m;
+        }
+    }
     a.grid_cO = -1;
     a.cO_len = 1;
     a.cO_t = 1;
@@ -753,7 +768,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     const bool flat_ok = nB == 1 && t[aO] == d[aO] && b1 == r - 1 - nA && sinb[b1] == innerA * t[aO] * R;
     if (umt) a.flags |= TF_UMT;
     else G = line_friendly_g(U, G, a.TB, nA, a.soutA[0], false);
-    rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, (uint64_t)d[b1], opt, why);
+    rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, b1 > 0 ? (uint64_t)d[b1] : 0, opt, why);
     if (st != RR_OK) return st;
     if (opt.xcd) a.flags |= TF_XCD;
     p->grid = a.ntiles;
@@ -852,7 +867,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
         a.bO_len = (uint32_t)count; a.bO_t = (uint32_t)L;
         for (int c = 0; c < n; ++c) a.table[c] = planes[c];
         uint64_t ra = a.src | (uint64_t)(n * R);
-        rr_status st = finish_tile(a, U, G, k, ra, true, a.src, (uint64_t)count, opt, why);
+        rr_status st = finish_tile(a, U, G, k, ra, true, a.src, 0, opt, why);
         if (st != RR_OK) return st;
     }
     a.ntiles = (uint32_t)nt;

@@ -362,6 +362,25 @@ def test_emu_short_output_rows_line_fill():
         assert got == g, (e, n, got, g, status)
 
 
+def test_emu_flat_read_byte_tail():
+    """De-interlace-shaped permutes and de-interlaces whose input is not a whole number
+    of 16-byte vectors: tiles read their range as vectors and the last tile's final
+    bytes one by one (flat read), bit-exact; a slower axis whose stride is not a
+    multiple of 16 bytes keeps the per-row read."""
+    jobs = []
+    for n, e in [(3, 1), (5, 1), (6, 1), (3, 2), (5, 2), (3, 4), (5, 4), (7, 8)]:
+        count = 2 * 4096 + 1 + 2 * n
+        jobs.append(_perm_job((count, n), (1, 0), e, 9800 + 10 * n + e))
+        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e,
+                         input=rr_synth.random_bytes(9900 + 10 * n + e, n * count * e)))
+    res = _check(jobs)
+    for j, (status, _) in zip(jobs, res):
+        assert int(status.split("flags=")[1].split()[0]) & 4, (j.get("dims"), j.get("n"), status)
+    res = _check([_perm_job((5, 999, 5), (0, 2, 1), 2, 9990), _perm_job((3, 2001, 3), (0, 2, 1), 1, 9991)])
+    for status, _ in res:
+        assert not int(status.split("flags=")[1].split()[0]) & 4, status
+
+
 def _batched_jobs(seed, njobs, max_elems=20000):
     g = rr_synth.rng(seed)
     jobs = []

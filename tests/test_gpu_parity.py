@@ -226,6 +226,32 @@ def test_flat_read_and_merged_store_paths(rr):
         check_permute(rr, dims, perm, e, 9500 + i)
 
 
+def test_short_output_rows_line_fill(rr):
+    """Interlace-shaped permutes and interlaces of 2..16 sets of 1..8-byte elements,
+    whose micro-tile edge the planner picks by store line fill, over several tiles."""
+    from tests.test_emulated_kernels import SHORT_ROW_G
+    count = 4104
+    for (e, n), g in SHORT_ROW_G.items():
+        assert rr.plan_describe((n, count), (1, 0), e, 1 << 30, 1 << 31)["g"] == str(g)
+        check_permute(rr, (n, count), (1, 0), e, 9600 + 17 * n + e)
+        _say("interlace line fill", n, e)
+        planes = [rr_synth.random_bytes(9700 + 17 * n + e + 1000 * c, count * e) for c in range(n)]
+        assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e)), (n, e)
+
+
+def test_flat_read_byte_tail(rr):
+    """Inputs that end inside a 16-byte vector: the flat read's last tile copies its
+    final bytes one by one."""
+    for n, e in [(3, 1), (5, 1), (6, 1), (3, 2), (5, 2), (3, 4), (5, 4), (7, 8)]:
+        count = 2 * 4096 + 1 + 2 * n
+        assert int(rr.plan_describe((count, n), (1, 0), e, 1 << 30, 1 << 31)["flags"]) & 4
+        check_permute(rr, (count, n), (1, 0), e, 9800 + 10 * n + e)
+        _say("deinterlace byte tail", n, e)
+        x = rr_synth.random_bytes(9900 + 10 * n + e, n * count * e)
+        got = gpu_deinterlace(rr, x, n, e)
+        assert all(np.array_equal(g, r) for g, r in zip(got, oracle.deinterlace(x, n, e))), (n, e)
+
+
 def test_autotuned_plans_stay_exact(rr):
     """Tuning runs every candidate shape; the cached winner must still be bit-exact."""
     try:
