@@ -300,8 +300,6 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     if (best_us) *best_us = 0;
     if (default_us) *default_us = 0;
     if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
-    // row targets, traversal order, micro-tile cap; candidates that plan to the
-    // same launch as an earlier one are skipped
     // row targets, traversal order, micro-tile cap, tile size (KiB); candidates
     // that plan to the same launch as an earlier one are skipped
     struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = 0, umt = 0; };

@@ -258,16 +258,17 @@ RR_HD void copy_thread(const CopyArgs& a, uint32_t block, uint32_t nblocks, uint
     constexpr int NW = NWords<W>::value;
     const uint8_t* s = reinterpret_cast<const uint8_t*>(a.src) + a.head;
     uint8_t* d = reinterpret_cast<uint8_t*>(a.dst) + a.head;
-    const uint64_t stride = (uint64_t)nblocks * NT * 4;
-    for (uint64_t i = (uint64_t)block * NT * 4 + tid; i < a.nvec; i += stride) {
-        uint32_t w[4][NW];
+    constexpr int V = copy_vpt(W);
+    const uint64_t stride = (uint64_t)nblocks * NT * V;
+    for (uint64_t i = (uint64_t)block * NT * V + tid; i < a.nvec; i += stride) {
+        uint32_t w[V][NW];
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < V; ++u) {
             const uint64_t v = i + (uint64_t)u * NT;
             if (v < a.nvec) gload<W>(s + v * W, w[u]);
         }
 #pragma unroll
-        for (int u = 0; u < 4; ++u) {
+        for (int u = 0; u < V; ++u) {
             const uint64_t v = i + (uint64_t)u * NT;
             if (v < a.nvec) gstore<W>(d + v * W, w[u]);
         }
@@ -479,10 +480,11 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
     constexpr int NW = NWords<W>::value;
     const uint8_t* src = reinterpret_cast<const uint8_t*>(a.src);
     uint8_t* dst = reinterpret_cast<uint8_t*>(a.dst);
-    const uint32_t base = block * (uint32_t)(NT * 4) + tid;
-    uint32_t w[4][NW];
+    constexpr int V = copy_vpt(W);
+    const uint32_t base = block * (uint32_t)(NT * V) + tid;
+    uint32_t w[V][NW];
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < V; ++u) {
         const uint32_t v = base + u * NT;
         if (v < a.nvec) {
             const uint32_t run = mdiv(v, a.mvpr);
@@ -502,7 +504,7 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
         }
     }
 #pragma unroll
-    for (int u = 0; u < 4; ++u) {
+    for (int u = 0; u < V; ++u) {
         const uint32_t v = base + u * NT;
         if (v < a.nvec) gstore<W>(dst + (uint64_t)v * W, w[u]);
     }

@@ -362,7 +362,7 @@ void plan_copy(uint64_t dst, uint64_t src, uint64_t nbytes, Plan* p) {
     uint64_t body = (nbytes - head) / W;
     uint64_t tail = nbytes - head - body * W;
     a.src = src; a.dst = dst; a.nvec = body; a.head = (uint32_t)head; a.tail = (uint32_t)tail; a.wbytes = W;
-    uint64_t per_block = (uint64_t)NT * 4;
+    uint64_t per_block = (uint64_t)NT * copy_vpt((int)W);
     uint64_t g = (body + per_block - 1) / per_block;
     if (g < 1) g = 1;
     if (g > 0x7fffffffULL) g = 0x7fffffffULL;  // grid-stride beyond this
@@ -400,7 +400,7 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
         a.om[j] = make_magic(a.on[j]);
         a.sin[j] = (uint64_t)c.sinb[c.perm[j]];
     }
-    uint64_t per_block = (uint64_t)NT * 4;
+    uint64_t per_block = (uint64_t)NT * copy_vpt((int)W);
     uint64_t g = ((uint64_t)nvec + per_block - 1) / per_block;
     if (g > 0x7fffffffULL) { *why = "grid too large"; return RR_ERR_UNSUPPORTED; }
     p->grid = (uint32_t)std::max<uint64_t>(1, g);

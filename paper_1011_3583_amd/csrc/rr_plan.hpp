@@ -13,6 +13,11 @@ namespace rr {
 constexpr int MAXR = RR_MAX_DIMS;  // canonical rank never exceeds the input rank
 constexpr int MAXS = 4;            // axes on one side of a tile
 constexpr int NT = 256;            // threads per workgroup of the tiled kernels
+// Vectors of W bytes each thread of the copy and run kernels moves.  16-byte
+// vectors go one per thread (a workgroup moves 4 KiB: 6.3 TB/s against 5.9 TB/s
+// at four per thread); narrower vectors keep several loads in flight per thread
+// (one-byte runs lose 40 % at one per thread).
+constexpr int copy_vpt(int W) { return W >= 16 ? 1 : W >= 8 ? 2 : 4; }
 
 // Unsigned division by an invariant 32-bit divisor d >= 1 (Granlund & Montgomery,
 // "Division by Invariant Integers using Multiplication", PLDI 1994):
