@@ -620,18 +620,18 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
         uint32_t w[B][NWI];
         uint32_t lo[B];
         bool ok[B];
+        // Every lane loads (a lane past the tile's valid extent re-reads the tile's
+        // first vector, which exists whenever the tile does): loads behind per-lane
+        // branches are issued one at a time, each waited for before the next.
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const uint32_t f = base + u * NT + tid;
-            const uint32_t ib = mdiv(f, a.mrch);
-            const uint32_t x = (f - ib * a.rch) * WIN;
+            uint32_t ib = mdiv(f, a.mrch);
+            uint32_t x = (f - ib * a.rch) * WIN;
             ok[u] = f < total && ib < t.TBv && x < rowvalid;
-            lo[u] = 0;
-            if (ok[u]) {
-                const uint8_t* p = reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x);
-                gload<WIN>(p, w[u]);
-                lo[u] = lds_pos<G>(a, ib, x);
-            }
+            if (!ok[u]) { ib = 0; x = 0; }
+            gload<WIN>(reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x), w[u]);
+            lo[u] = lds_pos<G>(a, ib, x);
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
