@@ -342,24 +342,34 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * size), a cap on the register micro-tile edge G (RR_TILE_MAX_G(g), g one of
  * 1, 2, 4, 8, 16; 0 = no cap) and the LDS size tiles are shrunk to
  * (RR_TILE_KIB(k), 4..64 KiB; 0 = 16); RR_TILE_XCD hands each of the 8 XCDs a
- * contiguous range of tiles instead of every 8th one.  Process-wide; affects plans made after
- * the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a bad cap or a
- * bad tile size. */
+ * contiguous range of tiles instead of every 8th one, RR_TILE_NO_XCD never does
+ * (neither: where tile rows share 128-byte lines with neighbouring tiles and a
+ * side goes through the caches); RR_TILE_CACHE(p) fixes how tiles access global
+ * memory: p = 0 both sides non-temporal, 1 reads cached, 2 writes cached, 3 both
+ * cached (0 in those bits: the planner's choice -- writes cached where tile
+ * rows share 128-byte lines, so neighbouring tiles' parts of a line meet in L2;
+ * both sides non-temporal where every row starts on a line, and for interlace).  Process-wide; affects plans
+ * made after the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a
+ * bad cap, a bad tile size or both XCD flags. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
 #define RR_TILE_XCD 8           /* each XCD takes a contiguous range of tiles (single launches) */
 #define RR_TILE_UMT 16          /* odd shapes: unaligned G x G micro-tiles instead of G = 1 rows */
 #define RR_TILE_UMT_ALWAYS 32   /* unaligned micro-tiles even where aligned ones fit (testing) */
+#define RR_TILE_NO_XCD 64       /* never hand XCDs contiguous tile ranges */
 #define RR_TILE_MAX_G(g) ((g) << 8)
 #define RR_TILE_KIB(k) ((k) << 16)
+#define RR_TILE_CACHE(p) (((p) + 1) << 24)
 rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
 
 /* -------------------------------------------------------------------------
  * Autotuner for single permutes: runs the problem (writing dst, so the buffers
- * must be valid) once per candidate tile shape and traversal order on `stream`,
- * times each with HIP events, and caches the fastest for the problem's
- * canonical form and pointer-alignment class.  Every later plan with the same
+ * must be valid) once per candidate tile shape, traversal order and
+ * global-access policy on `stream`, times each with HIP events after writing a
+ * 512 MiB scratch buffer the call allocates and frees (so no run finds the
+ * problem in the caches; without that memory it times warm runs), and caches
+ * the fastest for the problem's canonical form and pointer-alignment class.  Every later plan with the same
  * key (rr_permute, rr_permute_batched, batch handles, the server) uses it,
  * unless rr_set_tile_override is active.  Problems that plan to a copy or run
  * copy have nothing to tune and return at once.

@@ -278,10 +278,15 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     if (!valid_max_g(max_g)) return fail(RR_ERR_INVALID_ARG, "micro-tile cap must be 0, 1, 2, 4, 8 or 16");
     const int tile_kib = (flags >> 16) & 0xff;
     if (!valid_tile_kib(tile_kib)) return fail(RR_ERR_INVALID_ARG, "tile size must be 0 or 4..64 KiB");
+    if ((flags & RR_TILE_XCD) && (flags & RR_TILE_NO_XCD))
+        return fail(RR_ERR_INVALID_ARG, "RR_TILE_XCD and RR_TILE_NO_XCD together");
+    const int cache = ((flags >> 24) & 0xff) - 1;
+    if (cache > 3) return fail(RR_ERR_INVALID_ARG, "cache policy must be 0..3");
     TileOptions o;
     o.max_g = max_g;
     o.tile_kib = tile_kib;
-    o.xcd = (flags & RR_TILE_XCD) ? 1 : 0;
+    o.xcd = (flags & RR_TILE_XCD) ? 1 : (flags & RR_TILE_NO_XCD) ? 0 : -1;
+    o.cache = cache;
     o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
@@ -300,9 +305,10 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     if (best_us) *best_us = 0;
     if (default_us) *default_us = 0;
     if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
-    // row targets, traversal order, micro-tile cap, tile size (KiB); candidates
-    // that plan to the same launch as an earlier one are skipped
-    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = 0, umt = 0; };
+    // row targets, traversal order, micro-tile cap, tile size (KiB), XCD ranges,
+    // unaligned micro-tiles, cache policy; candidates that plan to the same launch
+    // as an earlier one are skipped
+    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1; };
     static const Cand cands[] = {
         {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
         {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
@@ -314,11 +320,20 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, -1, 4, 0},      {0, 0, 1, 4, 0},        {128, 128, -1, 4, 0},   {64, 128, 1, 4, 0},
         {128, 64, 1, 4, 0},    {0, 0, -1, 0, 0, 1},    {0, 0, 1, 0, 0, 1},     {0, 0, 0, 0, 0, 1},
         {0, 0, -1, 0, 64, 1},  {512, 512, -1, 16, 64, 1}, {0, 0, -1, 0, 0, 0, 1}, {0, 0, 1, 0, 0, 0, 1},
-        {0, 0, 0, 0, 0, 0, 1}, {512, 512, -1, 0, 64, 0, 1}};
+        {0, 0, 0, 0, 0, 0, 1}, {512, 512, -1, 0, 64, 0, 1},
+        {0, 0, -1, 0, 0, 0, 0, 0}, {0, 0, -1, 0, 0, 0, 0, 1}, {0, 0, -1, 0, 0, 1, 0, 1},
+        {0, 0, -1, 0, 0, 0, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 3},
+        {0, 0, 1, 0, 0, 1, 0, 1},  {0, 0, 0, 0, 0, 1, 0, 2}, {512, 512, -1, 0, 64, 1, 0, 1}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
     if (hipEventCreate(&e1) != hipSuccess) { (void)hipEventDestroy(e0); return fail(RR_ERR_HIP, "hipEventCreate"); }
+    // Every timed run starts from caches that hold none of the problem (a write of
+    // twice the Infinity Cache's 256 MB): re-running one problem back to back
+    // would otherwise find a small input still cached and favour cached loads.
+    constexpr size_t FLUSH_BYTES = size_t(512) << 20;
+    void* flush = nullptr;
+    if (hipMalloc(&flush, FLUSH_BYTES) != hipSuccess) { flush = nullptr; (void)hipGetLastError(); }
     double best = 1e300, def = 0;
     TileOptions bestopt;
     std::vector<std::string> seen;
@@ -331,17 +346,18 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.tile_kib = cd.kib;
         o.xcd = cd.xcd;
         o.umt = cd.umt;
+        o.cache = cd.cache;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;
         // skip candidates that plan to a launch already timed
         std::string sig = describe(p);
-        sig += " o" + std::to_string(cd.order < 0 ? (p.tile.unit >= 4 ? 1 : 0) : cd.order) + " x" +
-               std::to_string(cd.xcd);
+        sig += " o" + std::to_string(cd.order < 0 ? (p.tile.unit >= 4 ? 1 : 0) : cd.order);
         if (std::find(seen.begin(), seen.end(), sig) != seen.end()) continue;
         seen.push_back(sig);
         std::vector<float> ts;
         for (int r = 0; r < 4 && st == RR_OK; ++r) {
+            if (flush) (void)hipMemsetAsync(flush, r & 0xff, FLUSH_BYTES, hs);
             (void)hipEventRecord(e0, hs);
             hipError_t e = launch_plan(p, hs);
             (void)hipEventRecord(e1, hs);
@@ -359,6 +375,10 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     }
     (void)hipEventDestroy(e0);
     (void)hipEventDestroy(e1);
+    if (flush) {
+        (void)hipStreamSynchronize(hs);
+        (void)hipFree(flush);
+    }
     if (st != RR_OK) return st;
     tune_store(tune_key(c, (uint64_t)dst, (uint64_t)src), bestopt);
     if (best_us) *best_us = best;

@@ -38,9 +38,13 @@ typedef uint32_t rr_u32x2 __attribute__((ext_vector_type(2)));
 #endif
 
 // ----------------------------------------------------------------- vector I/O
-// Global memory is streamed: every byte is read once and written once, so both
-// sides use non-temporal accesses (they keep the streams from displacing each
-// other in L2 and the Infinity Cache).  LDS accesses are ordinary.
+// Global memory is streamed: every byte is read once and written once, so by
+// default both sides use non-temporal accesses (they keep the streams from
+// displacing each other in L2 and the Infinity Cache).  Tiles whose rows start
+// or end inside 128-byte lines share those lines with their neighbours; a plan
+// may then read (TF_LD_CACHED) or write (TF_ST_CACHED) through the caches so the
+// neighbour finds the line there.  The access helpers take S = streamed.  LDS
+// accesses are ordinary.
 #ifndef RR_READ_BATCH
 #define RR_READ_BATCH 4
 #endif
@@ -158,20 +162,22 @@ RR_HD void vstore_t(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
 #if defined(__HIP_DEVICE_COMPILE__)
 typedef uint32_t rr_u32x4_u __attribute__((ext_vector_type(4), aligned(1)));
 #endif
+template <bool S = true>
 RR_HD void gload16u(const uint8_t* p, uint32_t (&w)[4]) {
 #if defined(__HIP_DEVICE_COMPILE__)
     const RR_AS_GLOBAL rr_u32x4_u* q = as_global<rr_u32x4_u>(p);
-    rr_u32x4_u v = RR_NT_LOAD ? __builtin_nontemporal_load(q) : *q;
+    rr_u32x4_u v = (S && RR_NT_LOAD) ? __builtin_nontemporal_load(q) : *q;
     w[0] = v.x; w[1] = v.y; w[2] = v.z; w[3] = v.w;
 #else
     std::memcpy(w, p, 16);
 #endif
 }
+template <bool S = true>
 RR_HD void gstore16u(uint8_t* p, const uint32_t (&w)[4]) {
 #if defined(__HIP_DEVICE_COMPILE__)
     rr_u32x4_u v; v.x = w[0]; v.y = w[1]; v.z = w[2]; v.w = w[3];
     RR_AS_GLOBAL rr_u32x4_u* q = as_global_mut<rr_u32x4_u>(p);
-    if (RR_NT_STORE) __builtin_nontemporal_store(v, q); else *q = v;
+    if (S && RR_NT_STORE) __builtin_nontemporal_store(v, q); else *q = v;
 #else
     std::memcpy(p, w, 16);
 #endif
@@ -183,24 +189,25 @@ typedef uint32_t rr_u32x2_u __attribute__((ext_vector_type(2), aligned(1)));
 typedef uint32_t rr_u32_u __attribute__((aligned(1)));
 typedef uint16_t rr_u16_u __attribute__((aligned(1)));
 #endif
-template <int W>
+template <int W, bool S = true>
 RR_HD void gstore_u(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
     if constexpr (W == 16) {
-        gstore16u(p, w);
+        gstore16u<S>(p, w);
     } else {
 #if defined(__HIP_DEVICE_COMPILE__)
+        constexpr bool NTS = S && RR_NT_STORE;
         if constexpr (W == 8) {
             rr_u32x2_u v; v.x = w[0]; v.y = w[1];
             RR_AS_GLOBAL rr_u32x2_u* q = as_global_mut<rr_u32x2_u>(p);
-            if (RR_NT_STORE) __builtin_nontemporal_store(v, q); else *q = v;
+            if (NTS) __builtin_nontemporal_store(v, q); else *q = v;
         } else if constexpr (W == 4) {
             RR_AS_GLOBAL rr_u32_u* q = as_global_mut<rr_u32_u>(p);
-            if (RR_NT_STORE) __builtin_nontemporal_store((rr_u32_u)w[0], q); else *q = w[0];
+            if (NTS) __builtin_nontemporal_store((rr_u32_u)w[0], q); else *q = w[0];
         } else if constexpr (W == 2) {
             RR_AS_GLOBAL rr_u16_u* q = as_global_mut<rr_u16_u>(p);
-            if (RR_NT_STORE) __builtin_nontemporal_store((rr_u16_u)w[0], q); else *q = (uint16_t)w[0];
+            if (NTS) __builtin_nontemporal_store((rr_u16_u)w[0], q); else *q = (uint16_t)w[0];
         } else {
-            vstore_t<1, RR_NT_STORE != 0, true>(p, w);
+            vstore_t<1, NTS, true>(p, w);
         }
 #else
         std::memcpy(p, w, W);
@@ -208,11 +215,15 @@ RR_HD void gstore_u(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
     }
 }
 
-// global memory (streamed) and LDS (ordinary)
-template <int W>
-RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, RR_NT_LOAD != 0, true>(p, w); }
-template <int W>
-RR_HD void gstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, RR_NT_STORE != 0, true>(p, w); }
+// global memory (streamed unless S is false) and LDS (ordinary)
+template <int W, bool S = true>
+RR_HD void gload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) {
+    vload_t<W, S && RR_NT_LOAD != 0, true>(p, w);
+}
+template <int W, bool S = true>
+RR_HD void gstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) {
+    vstore_t<W, S && RR_NT_STORE != 0, true>(p, w);
+}
 template <int W>
 RR_HD void sload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W, false, false>(p, w); }
 template <int W>
@@ -611,7 +622,7 @@ constexpr int READ_BATCH = RR_READ_BATCH;
 
 // Read phase: rows of the tile (contiguous along the input's fastest axes) are
 // loaded with WIN-byte vectors and parked in LDS.
-template <int WIN, int G, int B>
+template <int WIN, int G, int B, bool S>
 RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int NWI = NWords<WIN>::value;
     const uint32_t total = a.TB * a.rch;
@@ -630,7 +641,7 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
             uint32_t x = (f - ib * a.rch) * WIN;
             ok[u] = f < total && ib < t.TBv && x < rowvalid;
             if (!ok[u]) { ib = 0; x = 0; }
-            gload<WIN>(reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x), w[u]);
+            gload<WIN, S>(reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x), w[u]);
             lo[u] = lds_pos<G>(a, ib, x);
         }
 #pragma unroll
@@ -642,7 +653,7 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
 // Flat read: the tile's input rows are back to back in memory (a contiguous
 // byte range), and LDS holds them unpadded, so the whole range moves with
 // 16-byte vectors however short or oddly sized a row is (de-interlace).
-template <int B>
+template <int B, bool S>
 RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     const uint32_t nbytes = t.TBv * a.pitch;
     const uint32_t nvec = nbytes / a.win;
@@ -653,7 +664,7 @@ RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t
         for (int u = 0; u < B; ++u) {
             const uint32_t v = base + u * NT + tid;
             ok[u] = v < nvec;
-            if (ok[u]) gload<16>(reinterpret_cast<const uint8_t*>(t.bin) + (uint64_t)v * 16, w[u]);
+            if (ok[u]) gload<16, S>(reinterpret_cast<const uint8_t*>(t.bin) + (uint64_t)v * 16, w[u]);
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
@@ -689,7 +700,7 @@ struct RowWalk {
 // (rowbytes % 16) / U elements one by one, so nothing outside a row is touched.
 //   src_row(r)      -> global byte address of row r
 //   lds_at(r, x)    -> LDS byte offset of byte x of row r
-template <int U, class SrcRow, class LdsAt>
+template <int U, bool S, class SrcRow, class LdsAt>
 RR_HD void read_rows(uint32_t nrows, uint32_t rowbytes, SrcRow src_row, LdsAt lds_at, uint8_t* lds,
                      uint32_t tid) {
     constexpr int B = READ_BATCH;
@@ -709,13 +720,13 @@ RR_HD void read_rows(uint32_t nrows, uint32_t rowbytes, SrcRow src_row, LdsAt ld
                 const uint64_t rowp = src_row(w.row);
                 if (w.col < nfull) {
                     const uint32_t x = w.col << 4;
-                    gload16u(reinterpret_cast<const uint8_t*>(rowp + x), v[u]);
+                    gload16u<S>(reinterpret_cast<const uint8_t*>(rowp + x), v[u]);
                     lo[u] = lds_at(w.row, x);
                     kind[u] = 1;
                 } else {
                     const uint32_t x = (nfull << 4) + (w.col - nfull) * U;
                     uint32_t e[NWords<U>::value];
-                    gload<U>(reinterpret_cast<const uint8_t*>(rowp + x), e);
+                    gload<U, S>(reinterpret_cast<const uint8_t*>(rowp + x), e);
 #pragma unroll
                     for (int q = 0; q < NWords<U>::value; ++q) v[u][q] = e[q];
                     lo[u] = lds_at(w.row, x);
@@ -740,50 +751,58 @@ RR_HD void read_rows(uint32_t nrows, uint32_t rowbytes, SrcRow src_row, LdsAt ld
 
 // Ragged read: each input row (TAv*R bytes at any element alignment) of the
 // tile, into its padded LDS row.
-template <int U>
+template <int U, bool S>
 RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
-    read_rows<U>(
+    read_rows<U, S>(
         t.TBv, t.TAv * a.R, [&](uint32_t r) { return t.bin + row_in(a, r); },
         [&](uint32_t r, uint32_t x) { return lds_pos<1>(a, r, x); }, lds, tid);
 }
 
 // Stacked read: TCv sub-tiles of msub input bytes each; when they are back to
 // back in the input (sinC == msub) the whole range is one row.
-template <int U>
+template <int U, bool S>
 RR_HD void read_stack(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     if (a.sinC == a.msub)
-        read_rows<U>(
+        read_rows<U, S>(
             1, t.TCv * a.msub, [&](uint32_t) { return t.bin; }, [&](uint32_t, uint32_t x) { return x; }, lds,
             tid);
     else
-        read_rows<U>(
+        read_rows<U, S>(
             t.TCv, a.msub, [&](uint32_t r) { return t.bin + (uint64_t)r * a.sinC; },
             [&](uint32_t r, uint32_t x) { return r * a.msubp + x; }, lds, tid);
 }
 
-template <int U, int G>
-RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+template <int U, int G, bool S>
+RR_HD void read_tile(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int B = READ_BATCH;
     if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
-        if (a.flags & TF_STACK) { read_stack<U>(a, t, lds, tid); return; }
-        if (a.flags & TF_RAGGED_IN) { read_ragged<U>(a, t, lds, tid); return; }
+        if (a.flags & TF_STACK) { read_stack<U, S>(a, t, lds, tid); return; }
+        if (a.flags & TF_RAGGED_IN) { read_ragged<U, S>(a, t, lds, tid); return; }
     }
     if constexpr (G > 1 && U < 16) {
         if (a.flags & TF_UMT) {
-            read_rows<U>(
+            read_rows<U, S>(
                 t.TBv, t.TAv * a.R, [&](uint32_t r) { return t.bin + row_in(a, r); },
                 [&](uint32_t r, uint32_t x) { return lds_pos<G>(a, r, x); }, lds, tid);
             return;
         }
     }
-    if (a.flags & TF_IN_FLAT) { read_flat<B>(a, t, lds, tid); return; }
+    if (a.flags & TF_IN_FLAT) { read_flat<B, S>(a, t, lds, tid); return; }
     switch (a.win) {
-        case 16: read_phase<16, G, B>(a, t, lds, tid); break;
-        case 8: read_phase<8, G, B>(a, t, lds, tid); break;
-        case 4: read_phase<4, G, B>(a, t, lds, tid); break;
-        case 2: read_phase<2, G, B>(a, t, lds, tid); break;
-        default: read_phase<1, G, B>(a, t, lds, tid); break;
+        case 16: read_phase<16, G, B, S>(a, t, lds, tid); break;
+        case 8: read_phase<8, G, B, S>(a, t, lds, tid); break;
+        case 4: read_phase<4, G, B, S>(a, t, lds, tid); break;
+        case 2: read_phase<2, G, B, S>(a, t, lds, tid); break;
+        default: read_phase<1, G, B, S>(a, t, lds, tid); break;
     }
+}
+
+// The access flavour is chosen once per tile (a uniform branch), so the loops
+// below it carry no per-load condition.
+template <int U, int G>
+RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
+    if (a.flags & TF_LD_CACHED) read_tile<U, G, false>(a, t, lds, tid);
+    else read_tile<U, G, true>(a, t, lds, tid);
 }
 
 // Write phase: each work item is a GxG micro-tile (G rows of the LDS tile, G
@@ -792,7 +811,7 @@ RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint
 // Ragged write: each output row (TBv elements of U bytes along the output's
 // fastest axis, any alignment) is written as 16-byte vectors gathered element
 // by element from LDS, plus its last (bytes % 16) / U elements one by one.
-template <int U>
+template <int U, bool S>
 RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int EPV = 16 / U;   // elements per 16-byte vector
     const uint32_t rowbytes = t.TBv * U;
@@ -827,12 +846,12 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
                     o[q] = acc;
                 }
             }
-            gstore16u(rowp + (w.col << 4), o);
+            gstore16u<S>(rowp + (w.col << 4), o);
         } else {
             const uint32_t ib = nfull * EPV + (w.col - nfull);
             uint32_t e[NWords<U>::value];
             sload<U>(lds + lds_pos<1>(a, ib, ia * U), e);
-            gstore<U>(rowp + (uint64_t)ib * U, e);
+            gstore<U, S>(rowp + (uint64_t)ib * U, e);
         }
     }
 }
@@ -840,7 +859,7 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
 // Flat write: the tile's output rows are back to back (row_out(ia) = ia*TB*U),
 // so the whole tile is one contiguous byte range, written as 16-byte vectors
 // whose elements come from LDS across row boundaries, plus an element tail.
-template <int U>
+template <int U, bool S>
 RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int EPV = 16 / U;
     const uint32_t nel = t.TAv * a.TB;            // output rows of the tile are full (TBv == TB)
@@ -878,13 +897,13 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
                     o[w4] = acc;
                 }
             }
-            gstore16u(base + ((uint64_t)c << 4), o);
+            gstore16u<S>(base + ((uint64_t)c << 4), o);
         } else {
             const uint32_t q = nfull * EPV + (c - nfull);
             const uint32_t ia = mdiv(q, a.mtb);
             uint32_t e[NWords<U>::value];
             sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
-            gstore<U>(base + (uint64_t)q * U, e);
+            gstore<U, S>(base + (uint64_t)q * U, e);
         }
     }
 }
@@ -895,7 +914,7 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
 // is element (c, ib, ia) of the input, at LDS c * msubp + (ib * TA + ia) * U.
 // Each 16-byte output vector gathers its elements from LDS, walking (c, ia, ib)
 // incrementally from one division per vector.
-template <int U>
+template <int U, bool S>
 RR_HD void write_stack(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int EPV = 16 / U;
     const bool one = a.soutC == a.msub;
@@ -944,11 +963,11 @@ RR_HD void write_stack(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
                     o[q] = acc;
                 }
             }
-            gstore16u(rowp + (w.col << 4), o);
+            gstore16u<S>(rowp + (w.col << 4), o);
         } else {
             uint32_t e[NWords<U>::value];
             sload<U>(at(), e);
-            gstore<U>(rowp + (uint64_t)q0 * U, e);
+            gstore<U, S>(rowp + (uint64_t)q0 * U, e);
         }
     }
 }
@@ -956,7 +975,7 @@ RR_HD void write_stack(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
 // Unaligned micro-tiles: full G x G micro-tiles are transposed in registers and
 // stored as G unaligned W-byte vectors (row starts at any element offset); a
 // micro-tile cut by the tile's valid extent moves element by element.
-template <int U, int G>
+template <int U, int G, bool S>
 RR_HD void write_umt(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int W = U * G;
     constexpr int NW = NWords<W>::value;
@@ -973,7 +992,7 @@ RR_HD void write_umt(const TileArgs& a, const TileCtx& t, const uint8_t* lds, ui
             xpose<U, G>(r, o);
 #pragma unroll
             for (int i = 0; i < G; ++i)
-                gstore_u<W>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0 + i) + (uint64_t)ib0 * U), o[i]);
+                gstore_u<W, S>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0 + i) + (uint64_t)ib0 * U), o[i]);
         } else {
             const uint32_t ni = umin(G, t.TAv - ia0), nj = umin(G, t.TBv - ib0);
             for (uint32_t i = 0; i < ni; ++i) {
@@ -981,34 +1000,34 @@ RR_HD void write_umt(const TileArgs& a, const TileCtx& t, const uint8_t* lds, ui
                 for (uint32_t j = 0; j < nj; ++j) {
                     uint32_t e[NWords<U>::value];
                     sload<U>(lds + lds_pos<G>(a, ib0 + j, (ia0 + i) * U), e);
-                    gstore<U>(q + j * U, e);
+                    gstore<U, S>(q + j * U, e);
                 }
             }
         }
     }
 }
 
-template <int U, int G>
-RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+template <int U, int G, bool S>
+RR_HD void write_tile(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
     constexpr int W = U * G;
     constexpr int NW = NWords<W>::value;
     if constexpr (G == 1 && U < 16) {   // 16-byte units are always aligned vectors
         if (a.flags & TF_STACK) {
-            write_stack<U>(a, t, lds, tid);
+            write_stack<U, S>(a, t, lds, tid);
             return;
         }
         if (a.flags & TF_OUT_FLAT) {
-            write_flat<U>(a, t, lds, tid);
+            write_flat<U, S>(a, t, lds, tid);
             return;
         }
         if (a.flags & TF_RAGGED_OUT) {
-            write_ragged<U>(a, t, lds, tid);
+            write_ragged<U, S>(a, t, lds, tid);
             return;
         }
     }
     if constexpr (G > 1 && U < 16) {
         if (a.flags & TF_UMT) {
-            write_umt<U, G>(a, t, lds, tid);
+            write_umt<U, G, S>(a, t, lds, tid);
             return;
         }
     }
@@ -1026,7 +1045,7 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
                 if (a.flags & TF_OUT_TABLE) {
 #pragma unroll
                     for (int i = 0; i < G; ++i)
-                        gstore<W>(reinterpret_cast<uint8_t*>(a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U), o[i]);
+                        gstore<W, S>(reinterpret_cast<uint8_t*>(a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U), o[i]);
                 } else if (W >= 4 && W * G >= 16 && (a.flags & TF_OUT_MERGE)) {
                     // the G output rows are back to back: store them as 16-byte vectors
                     constexpr int NV = (W * G >= 16) ? W * G / 16 : 1;
@@ -1041,12 +1060,12 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
 #pragma unroll
                     for (int v = 0; v < NV; ++v) {
                         const uint32_t(&fv)[4] = *reinterpret_cast<const uint32_t(*)[4]>(&flat[v * 4]);
-                        gstore<16>(q + v * 16, fv);
+                        gstore<16, S>(q + v * 16, fv);
                     }
                 } else {
                     uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0) + (uint64_t)ib0 * U);
 #pragma unroll
-                    for (int i = 0; i < G; ++i) gstore<W>(q + (uint64_t)i * a.soutA[0], o[i]);
+                    for (int i = 0; i < G; ++i) gstore<W, S>(q + (uint64_t)i * a.soutA[0], o[i]);
                 }
             }
         }
@@ -1059,10 +1078,16 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
             if (ia < t.TAv && ib < t.TBv) {
                 uint32_t v[NWords<U>::value];
                 sload<U>(lds + lds_pos<1>(a, ib, (ia * a.k + s) * U), v);
-                gstore<U>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
+                gstore<U, S>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
             }
         }
     }
+}
+
+template <int U, int G>
+RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
+    if (a.flags & TF_ST_CACHED) write_tile<U, G, false>(a, t, lds, tid);
+    else write_tile<U, G, true>(a, t, lds, tid);
 }
 
 // ----------------------------------------------------------------- batches

@@ -165,6 +165,48 @@ def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
         rr.tune_load(str(bad))
 
 
+def test_cache_policy_by_line_alignment():
+    """Tiles whose rows all start on 128-byte lines stream both sides
+    (non-temporal); when rows share lines with neighbouring tiles, stores go
+    through the caches with XCD tile ranges, whatever the element size;
+    interlace stays streamed; an explicit policy or XCD choice replaces the
+    planner's."""
+    LD, ST, XCD = 1024, 2048, 256
+
+    def flags(dims, perm, e):
+        return int(rr.plan_describe(dims, perm, e, dst=1 << 30, src=1 << 31)["flags"])
+
+    rr.set_tile_override()
+    for dims, perm, e in [((512, 512, 256), (0, 2, 1), 4), ((64, 16384, 64), (0, 2, 1), 16),
+                          ((512, 131072), (1, 0), 8), ((16384, 16384), (1, 0), 1),
+                          ((512, 512, 256), (2, 1, 0), 2)]:
+        assert flags(dims, perm, e) & (LD | ST | XCD) == 0, (dims, perm, e)
+    for dims, perm, e in [((1001, 999), (1, 0), 4), ((1398, 1000, 24), (2, 1, 0), 8),
+                          ((32761, 4097), (1, 0), 2), ((8651, 1001, 31), (2, 0, 1), 1),
+                          ((4095, 4097), (1, 0), 16)]:
+        assert flags(dims, perm, e) & (LD | ST | XCD) == ST | XCD, (dims, perm, e)
+    # a misaligned base alone splits lines too
+    assert int(rr.plan_describe((4096, 4096), (1, 0), 4, dst=(1 << 30) + 64, src=1 << 31)["flags"]) & ST
+    try:
+        for pol, want in [(0, 0), (1, LD), (2, ST), (3, LD | ST)]:
+            rr.set_tile_override(cache=pol)
+            assert flags((1001, 999), (1, 0), 4) & (LD | ST) == want
+            assert flags((512, 512, 256), (0, 2, 1), 4) & (LD | ST) == want
+        rr.set_tile_override(cache=1, xcd=False)
+        assert flags((1001, 999), (1, 0), 4) & (LD | XCD) == LD
+        rr.set_tile_override(xcd=True)
+        assert flags((512, 512, 256), (0, 2, 1), 4) & (LD | ST | XCD) == XCD
+        rr.set_tile_override(cache=1)      # cached on aligned rows: no automatic XCD ranges
+        assert flags((512, 512, 256), (0, 2, 1), 4) & (LD | ST | XCD) == LD
+        rr.set_tile_override(cache=1)      # rows that share lines: XCD ranges with the cached side
+        assert flags((1001, 999), (1, 0), 4) & (LD | ST | XCD) == LD | XCD
+        for bad in (8 | 64, 5 << 24):
+            with pytest.raises(rr.RRError):
+                rr.check(rr.lib().rr_set_tile_override(0, 0, bad))
+    finally:
+        rr.set_tile_override()
+
+
 def test_micro_tile_cap_from_override_and_cache(tmp_path):
     """The micro-tile edge G can be capped by the override and by a cached entry."""
     rr.tune_clear()
@@ -195,8 +237,16 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
     assert int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 512
     rr.tune_clear()
     assert not int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 512
+    # the cache-policy field: 2 = writes through the caches, and no XCD ranges (xcd 0)
+    path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2\n")
+    rr.tune_load(str(path))
+    f = int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"])
+    assert f & 2048 and not f & 1024 and not f & 256
+    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2" in (rr.tune_save(str(out)) or out.read_text())
+    rr.tune_clear()
     for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 2\n", "k 0 0 0 8 16 1 3\n",
-                "k 0 0 0 8 16 1 1 1\n", "k 0 0\n"):
+                "k 0 0 0 8 16 -2\n", "k 0 0 0 8 16 1 1 4\n", "k 0 0 0 8 16 1 1 -2\n",
+                "k 0 0 0 8 16 1 1 1 0\n", "k 0 0\n"):
         (tmp_path / "bad.txt").write_text(bad)
         with pytest.raises(rr.RRError):
             rr.tune_load(str(tmp_path / "bad.txt"))

@@ -357,9 +357,11 @@ def test_emu_short_output_rows_line_fill():
         jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
         keys += [(e, n, g)] * 2
     res = _check(jobs)
-    for (e, n, g), (status, _) in zip(keys, res):
+    for j, (e, n, g), (status, _) in zip(jobs, keys, res):
         got = int(status.split(" g=")[1].split()[0])
         assert got == g, (e, n, got, g, status)
+        if j["op"] == "interlace":   # plane-table plans stream both sides, no XCD ranges
+            assert int(status.split("flags=")[1].split()[0]) & (1024 | 2048 | 256) == 0, status
 
 
 def test_emu_flat_read_byte_tail():

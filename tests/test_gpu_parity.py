@@ -324,6 +324,41 @@ def test_stacked_small_transposes(rr):
         check_permute(rr, dims, perm, e, 9900 + i)
 
 
+CACHE_CASES = [((1001, 999), (1, 0), 4), ((777, 345, 9), (1, 2, 0), 8), ((3001, 257), (1, 0), 2),
+               ((301, 203, 41), (2, 0, 1), 1), ((139, 100, 12), (2, 1, 0), 16), ((512, 256, 64), (0, 2, 1), 4),
+               ((20000, 3, 3), (0, 2, 1), 2), ((96, 100, 104), (0, 2, 1), 1)]
+
+
+@pytest.mark.parametrize("xcd", [False, True])
+@pytest.mark.parametrize("cache", [0, 1, 2, 3])
+def test_cache_policies(rr, cache, xcd):
+    """Every global-access flavour (non-temporal / cached loads / cached stores /
+    both), with and without XCD tile ranges, gives the oracle's bytes: single
+    permutes (aligned, odd and stacked shapes), interlace and de-interlace, and a
+    batch of uneven jobs."""
+    rr.set_tile_override(cache=cache, xcd=xcd)
+    try:
+        for i, (dims, perm, e) in enumerate(CACHE_CASES):
+            f = int(rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)["flags"])
+            assert (f >> 10) & 3 == cache and bool(f & 256) == xcd, (dims, f)
+            check_permute(rr, dims, perm, e, 9960 + i)
+        for n, count, e in [(3, 5007, 4), (4, 4099, 1), (8, 3000, 2)]:
+            _say("interlace cache", cache, xcd, n, count, e)
+            planes = [rr_synth.random_bytes(9970 + 10 * n + c, count * e) for c in range(n)]
+            assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e))
+            x = rr_synth.random_bytes(9980 + n, n * count * e)
+            got = gpu_deinterlace(rr, x, n, e)
+            assert all(np.array_equal(g, r) for g, r in zip(got, oracle.deinterlace(x, n, e)))
+        _say("batched cache", cache, xcd)
+        from tests.test_gpu_batched import Jobs, _check_all_vs_oracle, _uneven
+        J = Jobs(rr, _uneven(7 + cache, 120, 20000), 7 + cache)
+        rr.check(rr.permute_batched_raw(J.arr, len(J.specs), torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        _check_all_vs_oracle(J)
+    finally:
+        rr.set_tile_override()
+
+
 def test_xcd_tile_ranges(rr):
     """Contiguous tile ranges per XCD give the same bytes (tile counts not a
     multiple of 8 included)."""
