@@ -1,4 +1,4 @@
-// rr_kernels.hpp -- launchers for the kernels in rr_kernels.hip.
+// rr_kernels.hpp -- launchers for the kernels in rr_kernels.hip and rr_batch_kernels.hip.
 #pragma once
 
 #include <hip/hip_runtime_api.h>
