@@ -354,7 +354,7 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
-#define RR_TILE_XCD 8           /* each XCD takes a contiguous range of tiles (single launches) */
+#define RR_TILE_XCD 8           /* each XCD takes a contiguous range of tiles (per job in batches) */
 #define RR_TILE_UMT 16          /* odd shapes: unaligned G x G micro-tiles instead of G = 1 rows */
 #define RR_TILE_UMT_ALWAYS 32   /* unaligned micro-tiles even where aligned ones fit (testing) */
 #define RR_TILE_NO_XCD 64       /* never hand XCDs contiguous tile ranges */

@@ -303,7 +303,7 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     force_ragged: plan the odd-shape tile path even where aligned micro-tiles fit.
     max_g: cap on the register micro-tile edge (0 = none, else 1, 2, 4, 8, 16).
     tile_kib: LDS size tiles are shrunk to (0 = 16 KiB, else 4..64).
-    xcd: True = each XCD takes a contiguous range of tiles (single launches), False =
+    xcd: True = each XCD takes a contiguous range of tiles (per job in batches), False =
     never, None = where the cache policy reads or writes through the caches.
     umt: unaligned micro-tiles, 1 on odd shapes (instead of G = 1 rows), 2 everywhere.
     cache: global accesses of tiles, 0 non-temporal, 1 loads cached, 2 stores cached,

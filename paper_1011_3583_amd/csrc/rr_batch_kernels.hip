@@ -23,7 +23,7 @@ __global__ __launch_bounds__(NT) void k_batch_tile(const TileArgs* __restrict__ 
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const uint32_t j = find_job(prefix, njobs, b);
         const TileArgs& a = args[j];
-        const TileCtx t = tile_decode(a, b - prefix[j] + ranges[j].first);
+        const TileCtx t = tile_decode(a, batch_block_to_tile(a, prefix, ranges, j, b));
         read_dispatch<U, G>(a, t, smem, threadIdx.x);
         __syncthreads();
         write_phase<U, G>(a, t, smem, threadIdx.x);

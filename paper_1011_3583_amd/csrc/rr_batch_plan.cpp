@@ -144,9 +144,7 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
             if (g.kind == K_COPY) std::memcpy(argp + m * sizeof(CopyArgs), &p.copy, sizeof(CopyArgs));
             else if (g.kind == K_RUN) std::memcpy(argp + m * sizeof(RunArgs), &p.run, sizeof(RunArgs));
             else {
-                TileArgs* ta = reinterpret_cast<TileArgs*>(argp + m * sizeof(TileArgs));
-                std::memcpy(ta, &p.tile, sizeof(TileArgs));
-                batched_cache_policy(*ta);
+                std::memcpy(argp + m * sizeof(TileArgs), &p.tile, sizeof(TileArgs));
                 g.lds_bytes = std::max(g.lds_bytes, p.tile.lds_bytes);
             }
         }

@@ -1102,6 +1102,27 @@ RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
     return lo;
 }
 
+// Tile of workgroup b of entry j in a batch group.  Workgroups reach the XCDs
+// round-robin (workgroup b on XCD b % 8); with TF_XCD each XCD takes a
+// contiguous run of the entry's tiles, as block_to_tile does for a single
+// launch.  The entry's workgroups [prefix[j], prefix[j+1]) map one to one onto
+// its tiles [first, first + n): workgroup b is virtual index v = b - prefix[j] +
+// prefix[j] % 8 (so v % 8 is its XCD), and XCD x's runs are laid out in x order.
+RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, const EntryRange* ranges,
+                                   uint32_t j, uint32_t b) {
+    const uint32_t lb = b - prefix[j];
+    if (!(a.flags & TF_XCD)) return ranges[j].first + lb;
+    const uint32_t n = prefix[j + 1] - prefix[j], q0 = prefix[j] % NXCD;
+    const uint32_t v = lb + q0, x = v % NXCD, k = v / NXCD;
+    uint32_t start = 0;   // tiles of the XCDs before x: y + 8k in [q0, q0 + n), k >= (y < q0)
+    for (uint32_t y = 0; y < x; ++y) {
+        const uint32_t kmin = y < q0 ? 1u : 0u;
+        const uint32_t upto = q0 + n > y ? (q0 + n - y + NXCD - 1) / NXCD : 0u;
+        start += upto > kmin ? upto - kmin : 0u;
+    }
+    return ranges[j].first + start + k - (x < q0 ? 1u : 0u);
+}
+
 template <int W>
 RR_HD void batch_copy_block(const CopyArgs* args, const uint32_t* prefix, const EntryRange* ranges,
                             uint32_t njobs, uint32_t b, uint32_t tid) {

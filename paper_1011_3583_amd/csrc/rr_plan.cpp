@@ -484,8 +484,10 @@ static int line_friendly_g(int U, int G, uint32_t TB, int nA, uint64_t row_strid
 // those lines with the neighbouring tile.  With non-temporal stores each tile
 // writes its part of such a line to HBM on its own; written through the caches,
 // with neighbouring tiles on one XCD (contiguous tile ranges, one L2), the parts
-// meet in L2 and leave as whole lines.  Measured with cold caches on odd shapes
-// of 1..16-byte elements: 1.1-2.6x over non-temporal stores; cached loads lose
+// meet in L2 and leave as whole lines (in a batch launch each entry's tiles are
+// grouped so).  Measured with cold caches on odd shapes of 1..16-byte elements:
+// 1.1-2.6x over non-temporal stores, +3.6 % on a 4096-job batch of small odd
+// jobs (few tiles per XCD); cached loads lose
 // (their apparent gains came from inputs still resident in the 256 MB Infinity
 // Cache).  Where every row starts on a line, and for interlace and de-interlace
 // (plane tables), both sides stream non-temporally.
@@ -532,23 +534,11 @@ static void cache_policy(TileArgs& a, const TileOptions& opt) {
     }
     const bool table = (a.flags & (TF_IN_TABLE | TF_OUT_TABLE)) != 0;
     int pol = opt.cache;
-    if (pol < 0) {
-        pol = split && !table ? 2 : 0;
-        if (pol) a.flags |= TF_AUTO_SPLIT;
-    }
+    if (pol < 0) pol = split && !table ? 2 : 0;
     if (pol & 1) a.flags |= TF_LD_CACHED;
     if (pol & 2) a.flags |= TF_ST_CACHED;
     const bool xcd = opt.xcd >= 0 ? opt.xcd > 0 : split && pol != 0 && !table;
     if (xcd) a.flags |= TF_XCD;
-}
-
-// Measured on a 4096-job batch of odd shapes: cached loads +2 % and cached
-// stores -2.5 % against non-temporal accesses when tiles are not grouped by XCD.
-void batched_cache_policy(TileArgs& a) {
-    if ((a.flags & TF_AUTO_SPLIT) && (a.flags & TF_ST_CACHED)) {
-        a.flags &= ~(TF_ST_CACHED | TF_XCD);
-        a.flags |= TF_LD_CACHED;
-    }
 }
 
 // Fill the LDS / read / write geometry of a tile plan whose extents are set.

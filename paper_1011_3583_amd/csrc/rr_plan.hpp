@@ -115,14 +115,12 @@ enum TileFlags : uint32_t {
                          // gathered element by element from LDS, plus a tail
     TF_STACK = 128u,     // tile = cO_t whole TA x TB transposes stacked along axis C,
                          // each contiguous (msub bytes) in input and output
-    TF_XCD = 256u,       // single launches: each XCD takes a contiguous range of tiles
+    TF_XCD = 256u,       // each XCD takes a contiguous range of the tiles (of each batch entry)
     TF_UMT = 512u,       // G x G micro-tiles on rows of any alignment: unaligned 16-byte row
                          // reads, unaligned G*U-byte stores, element-wise partial micro-tiles
     TF_LD_CACHED = 1024u,   // read through the caches (rows share 128-byte lines with
                             // neighbouring tiles); default: non-temporal
     TF_ST_CACHED = 2048u,   // write through the caches; default: non-temporal
-    TF_AUTO_SPLIT = 4096u,  // (planner note, not read by kernels) the cache policy was chosen
-                            // automatically because tile rows share lines
 };
 
 struct TileArgs {
@@ -179,7 +177,7 @@ struct TileOptions {
     int force_ragged = 0;   // plan odd-shape (ragged) tiles even where aligned micro-tiles fit
     int max_g = 0;          // cap on the micro-tile edge G (0 = none)
     int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
-    int xcd = -1;           // 1: contiguous tile range per XCD (single launches), 0: never,
+    int xcd = -1;           // 1: contiguous tile range per XCD (per entry in batches), 0: never,
                             // -1: where the cache policy reads or writes through the caches
     int cache = -1;         // global accesses of tiles: 0 non-temporal, 1 loads cached,
                             // 2 stores cached, 3 both; -1: by line alignment (cache_policy)
@@ -192,11 +190,6 @@ struct TileOptions {
 bool valid_max_g(int g);      // 0 or a power of two up to 16
 bool valid_tile_kib(int k);   // 0 or 4..64
 constexpr int DEFAULT_TILE_KIB = 16;
-
-// A tile plan about to run inside a batch launch, whose workgroups are not
-// grouped by XCD: an automatic write-through-cache choice (which needs
-// neighbouring tiles on one L2) becomes read-through-cache.
-void batched_cache_policy(TileArgs& a);
 
 // Process-wide override (autotuner hook), read and written under a lock.
 // current_tile_options() is a snapshot: the override if one is set, else the

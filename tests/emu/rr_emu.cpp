@@ -95,12 +95,20 @@ static void run_batch_tile_ug(const BatchGroup& g, const uint8_t* table) {
     const TileArgs* args = reinterpret_cast<const TileArgs*>(table + g.args_off);
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
     const EntryRange* ranges = reinterpret_cast<const EntryRange*>(table + g.range_off);
+    std::vector<std::vector<uint8_t>> seen(g.njobs);   // each entry's tiles taken once
+    for (uint32_t j = 0; j < g.njobs; ++j) seen[j].assign(prefix[j + 1] - prefix[j], 0);
     for (uint32_t b = 0; b < g.total_blocks; ++b) {
         const uint32_t j = find_job(prefix, g.njobs, b);
         const TileArgs& a = args[j];
+        const uint32_t tile = batch_block_to_tile(a, prefix, ranges, j, b);
+        const uint32_t rel = tile - ranges[j].first;
+        if (tile < ranges[j].first || rel >= seen[j].size() || seen[j][rel]++) {
+            std::fprintf(stderr, "batch block %u (entry %u) -> bad tile %u\n", b, j, tile);
+            std::abort();
+        }
         uint8_t* lds = new uint8_t[g.lds_bytes];
         std::memset(lds, 0xA5, g.lds_bytes);
-        const TileCtx t = tile_decode(a, b - prefix[j] + ranges[j].first);
+        const TileCtx t = tile_decode(a, tile);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) read_dispatch<U, G>(a, t, lds, tid);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) write_phase<U, G>(a, t, lds, tid);
         delete[] lds;
