@@ -263,7 +263,7 @@ RR_HD void xpose(const uint32_t (&r)[G][NWords<U * G>::value], uint32_t (&o)[G][
 }
 
 // ----------------------------------------------------------------- copy
-// One thread's share of a grid-stride streaming copy (4 vectors in flight).
+// One thread's share of a grid-stride streaming copy (copy_vpt(W) vectors in flight).
 template <int W>
 RR_HD void copy_thread(const CopyArgs& a, uint32_t block, uint32_t nblocks, uint32_t tid) {
     constexpr int NW = NWords<W>::value;
