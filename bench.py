@@ -46,6 +46,10 @@ def parse():
     ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per arrival rate")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps and exit (for rocprofv3 runs)")
+    ap.add_argument("--profile-odd", action="store_true",
+                    help="launch each odd-shaped permute of ODD_CASES once with both sides "
+                         "non-temporal, then once with the planner's cache policy, and exit "
+                         "(for rocprofv3 counter runs; prints the launch order)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="turn the counter_collection.csv files of two rocprofv3 --pmc runs of "
                          "'--profile-only --steps 1 --warmup 0' (FETCH_SIZE, then WRITE_SIZE) into "
@@ -154,10 +158,42 @@ def kernel_name(d: dict) -> str:
     return d["class"]
 
 
+# Permutes whose tile rows start inside 128-byte lines (odd extents), 2^28 bytes
+# per side or so: (dims, perm, element bytes).
+ODD_CASES = [((8191, 4097), (1, 0), 8), ((999, 1001, 61), (2, 1, 0), 4), ((32761, 4097), (1, 0), 2),
+             ((4095, 4097), (1, 0), 16), ((4325, 1001, 31), (2, 0, 1), 2)]
+
+
+def profile_odd():
+    """One launch per (case, policy): both sides non-temporal, then the planner's
+    own choice (cached stores and XCD tile ranges where rows share lines)."""
+    import torch
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    sh = torch.cuda.current_stream().cuda_stream
+    nmax = max(int(__import__("numpy").prod(d)) * e for d, _, e in ODD_CASES)
+    src = torch.empty(nmax, dtype=torch.uint8, device="cuda")
+    src.random_(0, 256)
+    dst = torch.empty(nmax, dtype=torch.uint8, device="cuda")
+    torch.cuda.synchronize()
+    for dims, perm, e in ODD_CASES:
+        for name, kw in (("streamed", dict(cache=0, xcd=False)), ("planner", {})):
+            rr.set_tile_override(**kw)
+            d = rr.plan_describe(dims, perm, e, dst.data_ptr(), src.data_ptr())
+            rr.check(rr.permute_raw(dst.data_ptr(), src.data_ptr(), dims, perm, e, sh))
+            torch.cuda.synchronize()
+            print(json.dumps({"dims": dims, "perm": perm, "esize": e, "policy": name, "flags": int(d["flags"]),
+                              "kernel": kernel_name(d)}), flush=True)
+    rr.set_tile_override()
+
+
 def main():
     args = parse()
     if args.ingest_counters:
         print(json.dumps(ingest_counters(*args.ingest_counters), indent=1))
+        return
+    if args.profile_odd:
+        profile_odd()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
