@@ -94,3 +94,30 @@ def test_interlace_full_size(rr, pool, case):
     torch.cuda.synchronize()
     for c in range(n):
         assert torch.equal(outs[c], planes_dev[c]), (name, c)
+
+
+def test_batched_workload_full_size(rr):
+    """The benchmark's 4096-job batch (7.54 GB per side, seeded inputs on the device),
+    through a tuned handle replayed as a hipGraph as the benchmark runs it; every job
+    compared with the oracle on its first and last elements plus 256 random ones."""
+    import bench
+    specs = rr_synth.sample_jobs(4096_0001, njobs=4096)
+    src, dst, offs, sizes = bench._job_buffers(torch, specs)
+    jobs = rr.make_jobs([(dst.data_ptr() + o, src.data_ptr() + o, s["dims"], s["perm"], s["esize"])
+                         for o, s in zip(offs, specs)])
+    _say("batched full size", len(specs), sum(sizes))
+    h = rr.Batch(jobs, rr.RR_BATCH_TUNE | rr.RR_BATCH_GRAPH)
+    try:
+        dst.zero_()
+        h.launch(torch.cuda.current_stream())
+        torch.cuda.synchronize()
+    finally:
+        h.close()
+    for i, (s, o, nb) in enumerate(zip(specs, offs, sizes)):
+        n = nb // s["esize"]
+        x = src[o:o + nb].cpu().numpy()
+        y = dst[o:o + nb].cpu().numpy().reshape(n, s["esize"])
+        g = rr_synth.rng(7000 + i)
+        idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, 256)])).astype(np.int64)
+        ref = oracle.permute_at(x, s["dims"], s["perm"], s["esize"], idx)
+        assert np.array_equal(y[idx], ref), (i, s)
