@@ -121,3 +121,59 @@ def test_batched_workload_full_size(rr):
         idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, 256)])).astype(np.int64)
         ref = oracle.permute_at(x, s["dims"], s["perm"], s["esize"], idx)
         assert np.array_equal(y[idx], ref), (i, s)
+
+
+def test_serving_workload_full_size(rr):
+    """The serving benchmark's configuration (96 GiB budget, 64 MiB chunks, up to 1024
+    jobs per batch, 4 streams) and job mix at full size: 3000 requests drawn from the
+    4096-job distribution plus its four 1-4 GiB permutes, arriving in bursts while
+    earlier batches run; every result sampled against the oracle."""
+    import time
+    small = rr_synth.sample_jobs(5_0001, njobs=4096)
+    large = rr_synth.large_jobs(5_0002, count=4)
+    g = rr_synth.rng(77)
+    picks = [small[int(k)] for k in g.integers(0, len(small), 3000)] + large
+    order = [int(k) for k in g.permutation(len(picks))]
+    sh = torch.cuda.current_stream().cuda_stream
+    with rr.Server(96 << 30, max_inflight=4, max_batch_jobs=1024, chunk_bytes=64 << 20, tick_us=5) as srv:
+        inputs = []
+        for k, s in enumerate(picks):
+            nb = int(np.prod(s["dims"])) * s["esize"]
+            t = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            t.random_(0, 256, generator=torch.Generator(device="cuda").manual_seed(k))
+            p = srv.alloc(nb)
+            rr.check(rr.permute_raw(p, t.data_ptr(), (nb,), (0,), 1, sh))
+            inputs.append((p, t, nb))
+        torch.cuda.synchronize()
+        _say("serving full size", len(picks), sum(nb for _, _, nb in inputs))
+        tickets = {}
+        for n, k in enumerate(order):
+            s = picks[k]
+            tickets[k] = srv.submit(0, inputs[k][0], s["dims"], s["perm"], s["esize"])
+            if n % 50 == 0:
+                time.sleep(0.0005)
+        left, res, t0 = set(tickets.values()), {}, time.time()
+        while left and time.time() - t0 < 300:
+            for t in srv.completions():
+                if t in left:
+                    res[t] = srv.poll(t)
+                    left.discard(t)
+            time.sleep(0.0002)
+        assert not left, f"{len(left)} requests did not complete"
+        assert srv.stats()["batches"] > 1
+        for k, s in enumerate(picks):
+            r = res[tickets[k]]
+            assert r.status == 0, (k, s)
+            _, t, nb = inputs[k]
+            n = nb // s["esize"]
+            out = torch.empty(nb, dtype=torch.uint8, device="cuda")
+            rr.check(rr.permute_raw(out.data_ptr(), r.dst, (nb,), (0,), 1, sh))
+            torch.cuda.synchronize()
+            gi = rr_synth.rng(9000 + k)
+            idx = np.unique(np.concatenate([[0, n - 1], gi.integers(0, n, 256)])).astype(np.int64)
+            ref = oracle.permute_at(t.cpu().numpy(), s["dims"], s["perm"], s["esize"], idx)
+            got = out.view(n, s["esize"])[torch.from_numpy(idx).cuda()].cpu().numpy()
+            assert np.array_equal(got, ref), (k, s)
+            srv.release(tickets[k])
+        for p, _, _ in inputs:
+            srv.free(p)
