@@ -212,8 +212,12 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
  *                              workgroup per block of work.
  * Jobs are planned like rr_permute (the tile override if one is set, else the
  * built-in shapes and the tuning cache).  The handle's device is the current
- * HIP device at creation.  Launches on different streams must not overlap in
- * time (they write the same outputs).
+ * HIP device at creation.  A launch runs its groups side by side on `stream`
+ * and three streams the handle owns (default priority): they start after the
+ * work queued on `stream` before the call, and work queued on `stream` after
+ * the call waits for all of them.  Launches on different streams must not
+ * overlap in time (they write the same outputs), and one handle is launched
+ * from one thread at a time.
  * Errors: as rr_permute_batched; RR_ERR_NO_MEMORY if the table cannot be
  * allocated.
  */

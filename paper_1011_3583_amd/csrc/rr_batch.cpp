@@ -66,11 +66,71 @@ rr_status plan_or_fail(const rr_job* jobs, int njobs, const TileOptions& opt, Ba
 
 }  // namespace
 
+rr_status fanout_init(GroupFanout* f) {
+    if (f->fork) return RR_OK;
+    for (int k = 0; k < FANOUT_SIDE; ++k) {
+        if (hipStreamCreateWithFlags(&f->side[k], hipStreamNonBlocking) != hipSuccess ||
+            hipEventCreateWithFlags(&f->join[k], hipEventDisableTiming) != hipSuccess) {
+            fanout_destroy(f);
+            return fail(RR_ERR_HIP, "side streams for batch groups");
+        }
+    }
+    if (hipEventCreateWithFlags(&f->fork, hipEventDisableTiming) != hipSuccess) {
+        fanout_destroy(f);
+        return fail(RR_ERR_HIP, "side streams for batch groups");
+    }
+    return RR_OK;
+}
+
+void fanout_destroy(GroupFanout* f) {
+    for (int k = 0; k < FANOUT_SIDE; ++k) {
+        if (f->side[k]) (void)hipStreamDestroy(f->side[k]);
+        if (f->join[k]) (void)hipEventDestroy(f->join[k]);
+        f->side[k] = nullptr;
+        f->join[k] = nullptr;
+    }
+    if (f->fork) (void)hipEventDestroy(f->fork);
+    f->fork = nullptr;
+}
+
 rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
-                            hipStream_t st) {
-    for (const BatchGroup& g : p.groups) {
-        hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), st);
+                            hipStream_t st, GroupFanout* fan) {
+    if (!fan || !fan->fork || p.groups.size() < 2) {
+        for (const BatchGroup& g : p.groups) {
+            hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), st);
+            if (e != hipSuccess) return hip_fail(e, "batched launch");
+        }
+        return RR_OK;
+    }
+    // largest groups first, each to the stream with the fewest bytes queued
+    std::vector<size_t> order(p.groups.size());
+    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+    std::stable_sort(order.begin(), order.end(),
+                     [&](size_t a, size_t b) { return p.groups[a].bytes > p.groups[b].bytes; });
+    hipStream_t streams[FANOUT_SIDE + 1] = {st};
+    for (int k = 0; k < FANOUT_SIDE; ++k) streams[k + 1] = fan->side[k];
+    uint64_t load[FANOUT_SIDE + 1] = {};
+    bool used[FANOUT_SIDE + 1] = {true};
+    hipError_t e = hipEventRecord(fan->fork, st);
+    if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
+    for (size_t i : order) {
+        int s = 0;
+        for (int k = 1; k <= FANOUT_SIDE; ++k) if (load[k] < load[s]) s = k;
+        if (!used[s]) {
+            e = hipStreamWaitEvent(streams[s], fan->fork, 0);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+            used[s] = true;
+        }
+        const BatchGroup& g = p.groups[i];
+        e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), streams[s]);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
+        load[s] += std::max<uint64_t>(g.bytes, 1);
+    }
+    for (int k = 1; k <= FANOUT_SIDE; ++k) {
+        if (!used[k]) continue;
+        e = hipEventRecord(fan->join[k - 1], streams[k]);
+        if (e == hipSuccess) e = hipStreamWaitEvent(st, fan->join[k - 1], 0);
+        if (e != hipSuccess) return hip_fail(e, "joining batch groups");
     }
     return RR_OK;
 }
@@ -91,6 +151,7 @@ struct rr_batch {
     hipStream_t cap_stream = nullptr;
     hipGraph_t graph = nullptr;
     hipGraphExec_t exec = nullptr;
+    GroupFanout fan;      // groups run side by side on these
     double tuned_us = 0.0;
 };
 
@@ -129,7 +190,7 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
     rr_status rs = RR_OK;
     for (int r = 0; r < 4 && rs == RR_OK; ++r) {
         (void)hipEventRecord(e0, st);
-        rs = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st);
+        rs = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st, &b->fan);
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0;
@@ -258,10 +319,12 @@ rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** o
     rr_status st = e == hipSuccess ? RR_OK : hip_fail(e, "hipGetDevice");
     b->opt = current_tile_options();   // the override if set, else built-in shapes + tuning cache
     if (st == RR_OK) st = plan_or_fail(jobs, njobs, b->opt, &b->plan);
+    if (st == RR_OK) st = fanout_init(&b->fan);
     if (st == RR_OK) st = upload_table(b);
     if (st == RR_OK && (flags & RR_BATCH_TUNE) && !b->plan.groups.empty()) st = tune(b);
     if (st != RR_OK) {
         if (b->dev_table) (void)hipFree(b->dev_table);
+        fanout_destroy(&b->fan);
         delete b;
         return st;
     }
@@ -275,13 +338,14 @@ rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream) {
     if (b->plan.groups.empty()) return RR_OK;
     hipStream_t hs = (hipStream_t)stream;
     if (!(b->flags & RR_BATCH_GRAPH))
-        return launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs);
+        return launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs, &b->fan);
     if (!b->exec) {
         if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(RR_ERR_HIP, "capture stream");
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
-        rr_status st = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream);
+        rr_status st = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream,
+                                         &b->fan);
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != RR_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -314,6 +378,7 @@ rr_status rr_batch_destroy(rr_batch* b) {
     clear_error();
     if (!b) return RR_OK;
     drop_graph(b);
+    fanout_destroy(&b->fan);
     if (b->cap_stream) (void)hipStreamDestroy(b->cap_stream);
     if (b->dev_table) (void)hipFree(b->dev_table);
     delete b;

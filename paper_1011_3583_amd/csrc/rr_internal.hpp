@@ -18,8 +18,23 @@ bool ranges_overlap(uint64_t a, uint64_t na, uint64_t b, uint64_t nb);
 rr_status validate_permute(const void* dst, const void* src, int ndim, const int64_t* dims,
                            const int* perm, int elem_size, Canon* c);
 
-// Launch every group of a batch whose table is resident at dev_table.
+// Side streams that let the groups of one batch run side by side.  Groups touch
+// disjoint memory, so each may start once the work queued before the batch is
+// done; the caller's stream continues after all of them.  Streams keep the
+// default priority.
+constexpr int FANOUT_SIDE = 3;
+struct GroupFanout {
+    hipStream_t side[FANOUT_SIDE] = {};
+    hipEvent_t fork = nullptr;
+    hipEvent_t join[FANOUT_SIDE] = {};
+};
+rr_status fanout_init(GroupFanout* f);
+void fanout_destroy(GroupFanout* f);
+
+// Launch every group of a batch whose table is resident at dev_table: one after
+// another on st, or (with a fanout) spread over st and the side streams, largest
+// groups first, each to the stream with the least work queued so far.
 rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
-                            hipStream_t st);
+                            hipStream_t st, GroupFanout* fan = nullptr);
 
 }  // namespace rr
