@@ -513,10 +513,9 @@ static void cache_policy(TileArgs& a, const TileOptions& opt) {
     uint64_t in_starts = a.src, out_starts = a.dst;
     for (int g = 0; g < a.ngrid; ++g) { in_starts |= a.gsin[g]; out_starts |= a.gsout[g]; }
     bool split;
-    if (a.flags & TF_STACK) {   // sub-tiles of msub bytes, contiguous on both sides
-        const uint32_t one = 1;
+    if (a.flags & TF_STACK) {   // cO_t sub-tiles of msub bytes, each contiguous on both sides
         split = shares_lines(in_starts, a.msub, 1, &a.cO_t, &a.sinC) ||
-                shares_lines(out_starts, a.msub, 1, &one, &a.soutC);
+                shares_lines(out_starts, a.msub, 1, &a.cO_t, &a.soutC);
     } else {
         const uint64_t in_rb = (uint64_t)a.TA * a.R, out_rb = (uint64_t)a.TB * a.R;
         if (a.flags & TF_IN_TABLE) {

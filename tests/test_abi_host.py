@@ -185,6 +185,9 @@ def test_cache_policy_by_line_alignment():
                           ((32761, 4097), (1, 0), 2), ((8651, 1001, 31), (2, 0, 1), 1),
                           ((4095, 4097), (1, 0), 16)]:
         assert flags(dims, perm, e) & (LD | ST | XCD) == ST | XCD, (dims, perm, e)
+    # stacked small transposes: a tile's sub-tiles are one contiguous block on both sides
+    assert flags((1 << 20, 4, 8), (0, 2, 1), 4) & (128 | LD | ST | XCD) == 128
+    assert flags((1000, 3, 3), (0, 2, 1), 2) & (128 | LD | ST | XCD) == 128 | ST | XCD
     # a misaligned base alone splits lines too
     assert int(rr.plan_describe((4096, 4096), (1, 0), 4, dst=(1 << 30) + 64, src=1 << 31)["flags"]) & ST
     try:
