@@ -16,6 +16,7 @@
 #include "rr_plan.hpp"
 
 #include <algorithm>
+#include <atomic>
 #include <cstring>
 #include <map>
 #include <mutex>
@@ -56,11 +57,14 @@ void set_tile_override(const TileOptions& o) {
 
 namespace {
 std::mutex g_tune_mu;
+std::atomic<size_t> g_tune_entries{0};   // lets lookups skip building a key while empty
 std::map<std::string, TileOptions>& tune_cache() {
     static std::map<std::string, TileOptions> m;
     return m;
 }
 }  // namespace
+
+bool tune_cache_empty() { return g_tune_entries.load(std::memory_order_relaxed) == 0; }
 
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src) {
     std::string k = "r" + std::to_string(c.rank) + ":e" + std::to_string(c.elem_bytes) + ":a" +
@@ -88,11 +92,13 @@ bool tune_lookup(const std::string& key, TileOptions* out) {
 void tune_store(const std::string& key, const TileOptions& o) {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache()[key] = o;
+    g_tune_entries.store(tune_cache().size(), std::memory_order_relaxed);
 }
 
 void tune_clear() {
     std::lock_guard<std::mutex> lk(g_tune_mu);
     tune_cache().clear();
+    g_tune_entries.store(0, std::memory_order_relaxed);
 }
 
 std::string tune_dump() {
@@ -852,7 +858,7 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
     // a tuned shape for this problem replaces the built-in choice (not an explicit override)
     TileOptions tuned;
-    if (opt.use_tuned && tune_lookup(tune_key(c, dst, src), &tuned)) {
+    if (opt.use_tuned && !tune_cache_empty() && tune_lookup(tune_key(c, dst, src), &tuned)) {
         tuned.max_lds = opt.max_lds;
         return plan_tile(dst, src, c, tuned, p, why);
     }

@@ -201,6 +201,7 @@ bool override_active(const TileOptions& o);
 // Tuning cache: canonical problem + alignment class -> tile options.
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src);
 bool tune_lookup(const std::string& key, TileOptions* out);
+bool tune_cache_empty();   // no entry stored (cheap: no lock, no key)
 void tune_store(const std::string& key, const TileOptions& o);
 void tune_clear();
 std::string tune_dump();
