@@ -17,7 +17,9 @@
 
 #include <algorithm>
 #include <atomic>
+#include <charconv>
 #include <cstring>
+#include <string_view>
 #include <map>
 #include <mutex>
 #include <sstream>
@@ -58,31 +60,43 @@ void set_tile_override(const TileOptions& o) {
 namespace {
 std::mutex g_tune_mu;
 std::atomic<size_t> g_tune_entries{0};   // lets lookups skip building a key while empty
-std::map<std::string, TileOptions>& tune_cache() {
-    static std::map<std::string, TileOptions> m;
+// transparent comparison: lookups pass a string_view formatted on the stack
+std::map<std::string, TileOptions, std::less<>>& tune_cache() {
+    static std::map<std::string, TileOptions, std::less<>> m;
     return m;
+}
+
+// The key of a canonical problem, written into buf (no allocation):
+// r<rank>:e<bytes>:a<src align>/<dst align>:d<dims>:p<perm>[:s<input strides>]
+std::string_view format_tune_key(const Canon& c, uint64_t dst, uint64_t src, char (&buf)[768]) {
+    char* p = buf;
+    char* const end = buf + sizeof buf;
+    auto put = [&](char ch) { if (p < end) *p++ = ch; };
+    auto num = [&](int64_t v) { p = std::to_chars(p, end, v).ptr; };
+    put('r'); num(c.rank); put(':'); put('e'); num(c.elem_bytes); put(':'); put('a');
+    num(addr_align(src)); put('/'); num(addr_align(dst)); put(':'); put('d');
+    for (int i = 0; i < c.rank; ++i) { if (i) put(','); num(c.dims[i]); }
+    put(':'); put('p');
+    for (int i = 0; i < c.rank; ++i) { if (i) put(','); num(c.perm[i]); }
+    if (c.strided) {
+        put(':'); put('s');
+        for (int i = 0; i < c.rank; ++i) { if (i) put(','); num(c.sinb[i]); }
+    }
+    return std::string_view(buf, (size_t)(p - buf));
 }
 }  // namespace
 
-bool tune_cache_empty() { return g_tune_entries.load(std::memory_order_relaxed) == 0; }
-
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src) {
-    std::string k = "r" + std::to_string(c.rank) + ":e" + std::to_string(c.elem_bytes) + ":a" +
-                    std::to_string(addr_align(src)) + "/" + std::to_string(addr_align(dst)) + ":d";
-    for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.dims[i]);
-    k += ":p";
-    for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.perm[i]);
-    if (c.strided) {
-        k += ":s";
-        for (int i = 0; i < c.rank; ++i) k += (i ? "," : "") + std::to_string(c.sinb[i]);
-    }
-    return k;
+    char buf[768];
+    return std::string(format_tune_key(c, dst, src, buf));
 }
 
-bool tune_lookup(const std::string& key, TileOptions* out) {
+bool tune_lookup(const Canon& c, uint64_t dst, uint64_t src, TileOptions* out) {
+    if (g_tune_entries.load(std::memory_order_relaxed) == 0) return false;
+    char buf[768];
+    const std::string_view key = format_tune_key(c, dst, src, buf);
     std::lock_guard<std::mutex> lk(g_tune_mu);
     auto& m = tune_cache();
-    if (m.empty()) return false;
     auto it = m.find(key);
     if (it == m.end()) return false;
     *out = it->second;
@@ -858,7 +872,7 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
     // a tuned shape for this problem replaces the built-in choice (not an explicit override)
     TileOptions tuned;
-    if (opt.use_tuned && !tune_cache_empty() && tune_lookup(tune_key(c, dst, src), &tuned)) {
+    if (opt.use_tuned && tune_lookup(c, dst, src, &tuned)) {
         tuned.max_lds = opt.max_lds;
         return plan_tile(dst, src, c, tuned, p, why);
     }

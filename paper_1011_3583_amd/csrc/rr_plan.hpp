@@ -200,8 +200,9 @@ bool override_active(const TileOptions& o);
 
 // Tuning cache: canonical problem + alignment class -> tile options.
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src);
-bool tune_lookup(const std::string& key, TileOptions* out);
-bool tune_cache_empty();   // no entry stored (cheap: no lock, no key)
+// The tuned options cached for a canonical problem at these pointer
+// alignments, if any (the key is formatted on the stack: no allocation).
+bool tune_lookup(const Canon& c, uint64_t dst, uint64_t src, TileOptions* out);
 void tune_store(const std::string& key, const TileOptions& o);
 void tune_clear();
 std::string tune_dump();
