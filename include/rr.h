@@ -362,6 +362,7 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
 #define RR_TILE_UMT 16          /* odd shapes: unaligned G x G micro-tiles instead of G = 1 rows */
 #define RR_TILE_UMT_ALWAYS 32   /* unaligned micro-tiles even where aligned ones fit (testing) */
 #define RR_TILE_NO_XCD 64       /* never hand XCDs contiguous tile ranges */
+#define RR_TILE_DIAG 128        /* diagonal tile order: consecutive tiles step along both tile-grid axes */
 #define RR_TILE_MAX_G(g) ((g) << 8)
 #define RR_TILE_KIB(k) ((k) << 16)
 #define RR_TILE_CACHE(p) (((p) + 1) << 24)

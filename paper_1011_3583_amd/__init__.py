@@ -298,7 +298,7 @@ def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, sr
 
 def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None,
                       force_ragged: bool = False, max_g: int = 0, tile_kib: int = 0, xcd=None,
-                      umt: int = 0, cache=None):
+                      umt: int = 0, cache=None, diag: bool = False):
     """order_out: True = output order, False = input order, None = built-in choice.
     force_ragged: plan the odd-shape tile path even where aligned micro-tiles fit.
     max_g: cap on the register micro-tile edge (0 = none, else 1, 2, 4, 8, 16).
@@ -315,6 +315,7 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     flags |= 0 if xcd is None else (8 if xcd else 64)
     flags |= {0: 0, 1: 16, 2: 32}[int(umt)]
     flags |= 0 if cache is None else (int(cache) + 1) << 24
+    flags |= 128 if diag else 0
     check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))
 
 

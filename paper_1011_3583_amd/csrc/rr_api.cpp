@@ -287,6 +287,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.tile_kib = tile_kib;
     o.xcd = (flags & RR_TILE_XCD) ? 1 : (flags & RR_TILE_NO_XCD) ? 0 : -1;
     o.cache = cache;
+    o.diag = (flags & RR_TILE_DIAG) ? 1 : 0;
     o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
@@ -308,7 +309,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     // row targets, traversal order, micro-tile cap, tile size (KiB), XCD ranges,
     // unaligned micro-tiles, cache policy; candidates that plan to the same launch
     // as an earlier one are skipped
-    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1; };
+    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1, diag = 0; };
     static const Cand cands[] = {
         {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
         {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
@@ -323,7 +324,8 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, 0, 0, 0, 0, 1}, {512, 512, -1, 0, 64, 0, 1},
         {0, 0, -1, 0, 0, 0, 0, 0}, {0, 0, -1, 0, 0, 0, 0, 1}, {0, 0, -1, 0, 0, 1, 0, 1},
         {0, 0, -1, 0, 0, 0, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 3},
-        {0, 0, 1, 0, 0, 1, 0, 1},  {0, 0, 0, 0, 0, 1, 0, 2}, {512, 512, -1, 0, 64, 1, 0, 1}};
+        {0, 0, 1, 0, 0, 1, 0, 1},  {0, 0, 0, 0, 0, 1, 0, 2}, {512, 512, -1, 0, 64, 1, 0, 1},
+        {0, 0, -1, 0, 0, -1, 0, -1, 1}, {0, 0, 0, 0, 0, -1, 0, -1, 1}, {0, 0, -1, 0, 64, -1, 0, -1, 1}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
@@ -347,6 +349,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.xcd = cd.xcd;
         o.umt = cd.umt;
         o.cache = cd.cache;
+        o.diag = cd.diag;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;

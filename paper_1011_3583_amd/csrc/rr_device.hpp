@@ -535,13 +535,20 @@ RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
     t.TAv = a.TA;
     t.TBv = a.TB;
     t.TCv = a.cO_t;
-    uint32_t rem = tile;
+    uint32_t rem = tile, cfast = 0;
 #pragma unroll
     for (int g = MAXR - 1; g >= 0; --g) {
         if (g < a.ngrid) {
             const uint32_t q = mdiv(rem, a.gm[g]);
-            const uint32_t c = rem - q * a.gn[g];
+            uint32_t c = rem - q * a.gn[g];
             rem = q;
+            // diagonal order: the second-fastest tile coordinate advances with the
+            // fastest one, so consecutive tiles differ in both (a bijection per slab)
+            if (g == a.ngrid - 1) cfast = c;
+            else if (g == a.ngrid - 2 && (a.flags & TF_DIAG)) {
+                const uint32_t s = c + cfast;
+                c = s - mdiv(s, a.gm[g]) * a.gn[g];
+            }
             t.bin += (uint64_t)c * a.gsin[g];
             t.bout += (uint64_t)c * a.gsout[g];
             if (g == a.grid_aO) t.TAv = a.TAinner * umin(a.aO_t, a.aO_len - c * a.aO_t);

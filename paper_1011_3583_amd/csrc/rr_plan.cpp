@@ -41,7 +41,7 @@ TileOptions g_override;
 
 bool override_active(const TileOptions& o) {
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1;
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != 0;
 }
 
 TileOptions current_tile_options() {
@@ -121,14 +121,14 @@ std::string tune_dump() {
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
           << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << " "
-          << kv.second.xcd << " " << kv.second.umt << " " << kv.second.cache << "\n";
+          << kv.second.xcd << " " << kv.second.umt << " " << kv.second.cache << " " << kv.second.diag << "\n";
     return o.str();
 }
 
 bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
 bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 
-// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache]]]]]
+// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache [diag]]]]]]
 // (an entry without the xcd field never uses XCD ranges, one without cache plans
 // its accesses by line alignment)
 int tune_parse(const std::string& text) {
@@ -146,11 +146,13 @@ int tune_parse(const std::string& text) {
         else if (!(in >> o.xcd)) o.xcd = 0;
         else if (!(in >> o.umt)) o.umt = 0;
         else if (!(in >> o.cache)) o.cache = -1;
+        else if (!(in >> o.diag)) o.diag = 0;
         std::string extra;
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
             o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib) ||
-            o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3)
+            o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3 || o.diag < 0 ||
+            o.diag > 1)
             return -1;
         tune_store(key, o);
         ++n;
@@ -855,6 +857,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, b1 > 0 ? (uint64_t)d[b1] : 0, opt, why);
     if (st != RR_OK) return st;
     cache_policy(a, opt);
+    if (opt.diag && a.ngrid >= 2) a.flags |= TF_DIAG;
     p->grid = a.ntiles;
     p->bytes = (uint64_t)c.total_bytes;
     return RR_OK;

@@ -121,6 +121,7 @@ enum TileFlags : uint32_t {
     TF_LD_CACHED = 1024u,   // read through the caches (rows share 128-byte lines with
                             // neighbouring tiles); default: non-temporal
     TF_ST_CACHED = 2048u,   // write through the caches; default: non-temporal
+    TF_DIAG = 4096u,        // diagonal tile order over the two fastest tile-grid axes
 };
 
 struct TileArgs {
@@ -179,6 +180,7 @@ struct TileOptions {
     int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
     int xcd = -1;           // 1: contiguous tile range per XCD (per entry in batches), 0: never,
                             // -1: where the cache policy reads or writes through the caches
+    int diag = 0;           // 1: diagonal tile order (the paper's answer to partition camping)
     int cache = -1;         // global accesses of tiles: 0 non-temporal, 1 loads cached,
                             // 2 stores cached, 3 both; -1: by line alignment (cache_policy)
     int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead

@@ -39,7 +39,7 @@ def build():
 def run(jobs):
     """Run jobs through the emulator.  Each job is a dict:
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
-                    max_g, ragged, xcd, umt
+                    max_g, ragged, xcd (None: the planner's choice), umt, diag
        reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
        gather:      op, src_count, esize, input (uint8), idx (int64) or start/stride/count, src_off, dst_off
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
@@ -58,8 +58,9 @@ def run(jobs):
                 lines.append(" ".join(["permute", str(nd), *map(str, j["dims"]), *map(str, j["perm"]),
                                        str(j["esize"]), str(j.get("src_off", 0)), str(j.get("dst_off", 0)),
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
-                                       str(int(j.get("ragged", False))), str(int(j.get("xcd", False))),
-                                       str(int(j.get("umt", 0))), inf, outf]))
+                                       str(int(j.get("ragged", False))),
+                                       str(-1 if j.get("xcd") is None else int(j["xcd"])),
+                                       str(int(j.get("umt", 0))), str(int(j.get("diag", False))), inf, outf]))
             elif j["op"] == "stencil":
                 np.ascontiguousarray(j["grid"], dtype=np.float32).tofile(inf)
                 w = [repr(float(v)) for v in np.asarray(j["weights"], dtype=np.float32).reshape(-1)]

@@ -245,11 +245,15 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
     rr.tune_load(str(path))
     f = int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"])
     assert f & 2048 and not f & 1024 and not f & 256
-    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2" in (rr.tune_save(str(out)) or out.read_text())
+    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 0" in (rr.tune_save(str(out)) or out.read_text())
+    path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 1\n")   # diagonal tile order
+    rr.tune_clear()
+    rr.tune_load(str(path))
+    assert int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 4096
     rr.tune_clear()
     for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 2\n", "k 0 0 0 8 16 1 3\n",
                 "k 0 0 0 8 16 -2\n", "k 0 0 0 8 16 1 1 4\n", "k 0 0 0 8 16 1 1 -2\n",
-                "k 0 0 0 8 16 1 1 1 0\n", "k 0 0\n"):
+                "k 0 0 0 8 16 1 1 1 2\n", "k 0 0 0 8 16 1 1 1 0 0\n", "k 0 0\n"):
         (tmp_path / "bad.txt").write_text(bad)
         with pytest.raises(rr.RRError):
             rr.tune_load(str(tmp_path / "bad.txt"))

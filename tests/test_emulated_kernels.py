@@ -177,6 +177,22 @@ UMT_CASES = [((1001, 999), (1, 0), 4, 0, 0), ((257, 131), (1, 0), 2, 0, 0), ((33
              ((5, 16, 11, 24), (0, 3, 2, 1), 1, 0, 0), ((129, 67), (1, 0), 8, 8, 0), ((31, 37, 41), (2, 1, 0), 1, 0, 0)]
 
 
+def test_emu_diagonal_tile_order():
+    """Diagonal tile order (second-fastest tile coordinate skewed by the fastest)
+    covers every tile once: tile grids of 2-4 axes, partial tiles, both traversal
+    orders, with and without XCD ranges."""
+    jobs = []
+    cases = [((1000, 1000), (1, 0), 4), ((130, 70, 90), (2, 0, 1), 2), ((64, 48, 40), (1, 2, 0), 8),
+             ((20, 30, 40, 50), (3, 1, 0, 2), 1), ((33, 47), (1, 0), 16), ((512, 384), (1, 0), 1)]
+    for i, (dims, perm, e) in enumerate(cases):
+        for order in (0, 1):
+            for xcd in (False, True):
+                jobs.append(_perm_job(dims, perm, e, 7600 + 10 * i + 2 * order + xcd, diag=True, order=order,
+                                      xcd=xcd, in_rb=64, out_rb=64))
+    res = _check(jobs)
+    assert any(int(st.split("flags=")[1].split()[0]) & 4096 for st, _ in res)
+
+
 def test_emu_unaligned_micro_tiles():
     """Odd extents and misaligned pointers keep G x G micro-tiles with unaligned
     vector accesses; partial micro-tiles at tile edges move element by element."""

@@ -359,6 +359,23 @@ def test_cache_policies(rr, cache, xcd):
         rr.set_tile_override()
 
 
+@pytest.mark.parametrize("xcd", [False, True])
+def test_diagonal_tile_order(rr, xcd):
+    """Diagonal tile order (with and without XCD ranges) gives the oracle's bytes on
+    tile grids of two and three axes with partial tiles (a one-axis grid has no
+    diagonal and keeps plain order)."""
+    rr.set_tile_override(diag=True, xcd=xcd)
+    try:
+        for i, (dims, perm, e) in enumerate([((1000, 1000), (1, 0), 4), ((130, 70, 90), (2, 0, 1), 2),
+                                             ((64, 48, 40), (1, 2, 0), 8), ((20, 30, 40, 50), (3, 1, 0, 2), 1),
+                                             ((2048, 2048), (1, 0), 16)]):
+            d = rr.plan_describe(dims, perm, e, 1 << 20, 1 << 30)
+            assert bool(int(d["flags"]) & 4096) == (int(d["ngrid"]) >= 2), (dims, d)
+            check_permute(rr, dims, perm, e, 9990 + i)
+    finally:
+        rr.set_tile_override()
+
+
 def test_xcd_tile_ranges(rr):
     """Contiguous tile ranges per XCD give the same bytes (tile counts not a
     multiple of 8 included)."""
