@@ -354,7 +354,12 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * rows share 128-byte lines, so neighbouring tiles' parts of a line meet in L2;
  * both sides non-temporal where every row starts on a line, and for interlace).  Process-wide; affects plans
  * made after the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a
- * bad cap, a bad tile size or both XCD flags. */
+ * bad cap, a bad tile size or both XCD flags.
+ * RR_TILE_FILL / RR_TILE_NO_FILL switch the odd-extent refit on or off (neither:
+ * the built-in choice): where a tile does not divide an outer tile axis, the
+ * planner evens out both outer extents for the fewest tiles that fit the tile size,
+ * keeping each side's rows at least half their target.  RR_ERR_INVALID_ARG also
+ * for both fill flags. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
@@ -363,6 +368,8 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
 #define RR_TILE_UMT_ALWAYS 32   /* unaligned micro-tiles even where aligned ones fit (testing) */
 #define RR_TILE_NO_XCD 64       /* never hand XCDs contiguous tile ranges */
 #define RR_TILE_DIAG 128        /* diagonal tile order: consecutive tiles step along both tile-grid axes */
+#define RR_TILE_FILL (1 << 27)  /* odd extents: refit tile extents for the fewest tiles within the tile size */
+#define RR_TILE_NO_FILL (1 << 28) /* keep the row-target tile extents on odd extents */
 #define RR_TILE_MAX_G(g) ((g) << 8)
 #define RR_TILE_KIB(k) ((k) << 16)
 #define RR_TILE_CACHE(p) (((p) + 1) << 24)

@@ -298,7 +298,7 @@ def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, sr
 
 def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None,
                       force_ragged: bool = False, max_g: int = 0, tile_kib: int = 0, xcd=None,
-                      umt: int = 0, cache=None, diag: bool = False):
+                      umt: int = 0, cache=None, diag: bool = False, fill=None):
     """order_out: True = output order, False = input order, None = built-in choice.
     force_ragged: plan the odd-shape tile path even where aligned micro-tiles fit.
     max_g: cap on the register micro-tile edge (0 = none, else 1, 2, 4, 8, 16).
@@ -307,7 +307,9 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     never, None = where the cache policy reads or writes through the caches.
     umt: unaligned micro-tiles, 1 on odd shapes (instead of G = 1 rows), 2 everywhere.
     cache: global accesses of tiles, 0 non-temporal, 1 loads cached, 2 stores cached,
-    3 both; None = the planner's choice by 128-byte line alignment."""
+    3 both; None = the planner's choice by 128-byte line alignment.
+    diag: diagonal tile order.  fill: True / False switch the odd-extent refit (fewer,
+    fuller tiles where a tile does not divide an outer axis) on / off, None = built-in."""
     flags = 0 if order_out is None else (1 if order_out else 2)
     flags |= 4 if force_ragged else 0
     flags |= int(max_g) << 8
@@ -316,6 +318,7 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     flags |= {0: 0, 1: 16, 2: 32}[int(umt)]
     flags |= 0 if cache is None else (int(cache) + 1) << 24
     flags |= 128 if diag else 0
+    flags |= 0 if fill is None else ((1 << 27) if fill else (1 << 28))
     check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))
 
 

@@ -280,7 +280,9 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     if (!valid_tile_kib(tile_kib)) return fail(RR_ERR_INVALID_ARG, "tile size must be 0 or 4..64 KiB");
     if ((flags & RR_TILE_XCD) && (flags & RR_TILE_NO_XCD))
         return fail(RR_ERR_INVALID_ARG, "RR_TILE_XCD and RR_TILE_NO_XCD together");
-    const int cache = ((flags >> 24) & 0xff) - 1;
+    if ((flags & RR_TILE_FILL) && (flags & RR_TILE_NO_FILL))
+        return fail(RR_ERR_INVALID_ARG, "RR_TILE_FILL and RR_TILE_NO_FILL together");
+    const int cache = ((flags >> 24) & 0x7) - 1;   // bits 24..26; 27, 28: fill flags
     if (cache > 3) return fail(RR_ERR_INVALID_ARG, "cache policy must be 0..3");
     TileOptions o;
     o.max_g = max_g;
@@ -288,6 +290,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.xcd = (flags & RR_TILE_XCD) ? 1 : (flags & RR_TILE_NO_XCD) ? 0 : -1;
     o.cache = cache;
     o.diag = (flags & RR_TILE_DIAG) ? 1 : 0;
+    o.fill = (flags & RR_TILE_FILL) ? 1 : (flags & RR_TILE_NO_FILL) ? 0 : -1;
     o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;
@@ -307,9 +310,10 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     if (default_us) *default_us = 0;
     if (c.total_bytes == 0 || c.rank == 0 || c.elem_bytes >= RUN_MIN_BYTES) return RR_OK;
     // row targets, traversal order, micro-tile cap, tile size (KiB), XCD ranges,
-    // unaligned micro-tiles, cache policy; candidates that plan to the same launch
+    // unaligned micro-tiles, cache policy, diagonal order, odd-extent refit (the
+    // first candidate is the built-in plan); candidates that plan to the same launch
     // as an earlier one are skipped
-    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1, diag = 0; };
+    struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1, diag = 0, fill = -1; };
     static const Cand cands[] = {
         {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
         {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
@@ -325,7 +329,9 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, -1, 0, 0, 0, 0, 0}, {0, 0, -1, 0, 0, 0, 0, 1}, {0, 0, -1, 0, 0, 1, 0, 1},
         {0, 0, -1, 0, 0, 0, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 3},
         {0, 0, 1, 0, 0, 1, 0, 1},  {0, 0, 0, 0, 0, 1, 0, 2}, {512, 512, -1, 0, 64, 1, 0, 1},
-        {0, 0, -1, 0, 0, -1, 0, -1, 1}, {0, 0, 0, 0, 0, -1, 0, -1, 1}, {0, 0, -1, 0, 64, -1, 0, -1, 1}};
+        {0, 0, -1, 0, 0, -1, 0, -1, 1}, {0, 0, 0, 0, 0, -1, 0, -1, 1}, {0, 0, -1, 0, 64, -1, 0, -1, 1},
+        {0, 0, -1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 0, 0, 0, -1, 0, -1, 0, 0},
+        {512, 512, -1, 0, 64, -1, 0, -1, 0, 0}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");
@@ -350,6 +356,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         o.umt = cd.umt;
         o.cache = cd.cache;
         o.diag = cd.diag;
+        o.fill = cd.fill;
         Plan p;
         std::string why;
         if (plan_permute((uint64_t)dst, (uint64_t)src, c, o, &p, &why) != RR_OK) continue;
@@ -373,7 +380,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         if (st != RR_OK) break;
         std::sort(ts.begin(), ts.end());
         const double us = ts[ts.size() / 2] * 1e3;
-        if (cd.in_rb == 0 && cd.out_rb == 0 && cd.order == -1) def = us;
+        if (&cd == &cands[0]) def = us;
         if (us < best) { best = us; bestopt = o; }
     }
     (void)hipEventDestroy(e0);

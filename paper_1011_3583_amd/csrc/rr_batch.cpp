@@ -207,13 +207,15 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
 
 rr_status tune(rr_batch* b) {
     // row targets, traversal order, persistent grid, tile size (KiB), unaligned
-    // micro-tiles, cache policy (-1: each job's own by line alignment)
-    struct Cand { int in_rb, out_rb, order; bool persistent; int kib = 0, umt = 0, cache = -1; };
+    // micro-tiles, cache policy (-1: each job's own by line alignment), odd-extent
+    // refit (-1: built-in)
+    struct Cand { int in_rb, out_rb, order; bool persistent; int kib = 0, umt = 0, cache = -1, fill = -1; };
     const Cand cands[] = {{0, 0, 0, false}, {0, 0, 1, false}, {0, 0, 0, true}, {256, 512, 0, false},
                           {512, 256, 0, false}, {512, 512, 0, false}, {1024, 256, 0, false},
                           {256, 1024, 0, false}, {512, 256, 1, false}, {128, 256, 0, false},
                           {0, 0, 0, false, 0, 1}, {512, 512, 0, false, 32, 0},
-                          {0, 0, 0, false, 0, 0, 0}, {0, 0, 0, false, 0, 0, 1}, {0, 0, 0, false, 0, 0, 2}};
+                          {0, 0, 0, false, 0, 0, 0}, {0, 0, 0, false, 0, 0, 1}, {0, 0, 0, false, 0, 0, 2},
+                          {0, 0, 0, false, 0, 0, -1, 0}, {512, 256, 1, false, 0, 0, -1, 0}};
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(RR_ERR_HIP, "stream");
     double best = 1e300;
@@ -227,6 +229,7 @@ rr_status tune(rr_batch* b) {
         o.tile_kib = c.kib;
         o.umt = c.umt;
         o.cache = c.cache;
+        o.fill = c.fill;
         BatchPlan p;
         std::string why;
         int bad;
@@ -247,6 +250,7 @@ rr_status tune(rr_batch* b) {
     b->opt.tile_kib = bestc.kib;
     b->opt.umt = bestc.umt;
     b->opt.cache = bestc.cache;
+    b->opt.fill = bestc.fill;
     b->persistent = bestc.persistent;
     b->tuned_us = best;
     rs = plan_or_fail(b->jobs.data(), (int)b->jobs.size(), b->opt, &b->plan);

@@ -19,6 +19,7 @@
 #include <atomic>
 #include <charconv>
 #include <cstring>
+#include <numeric>
 #include <string_view>
 #include <map>
 #include <mutex>
@@ -41,7 +42,8 @@ TileOptions g_override;
 
 bool override_active(const TileOptions& o) {
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != 0;
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != 0 ||
+           o.fill != -1;
 }
 
 TileOptions current_tile_options() {
@@ -121,16 +123,18 @@ std::string tune_dump() {
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "
           << kv.second.order_out << " " << kv.second.max_g << " " << kv.second.tile_kib << " "
-          << kv.second.xcd << " " << kv.second.umt << " " << kv.second.cache << " " << kv.second.diag << "\n";
+          << kv.second.xcd << " " << kv.second.umt << " " << kv.second.cache << " " << kv.second.diag << " "
+          << kv.second.fill << "\n";
     return o.str();
 }
 
 bool valid_max_g(int g) { return g == 0 || g == 1 || g == 2 || g == 4 || g == 8 || g == 16; }
 bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 
-// One entry per line: key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache [diag]]]]]]
+// One entry per line:
+//   key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache [diag [fill]]]]]]]
 // (an entry without the xcd field never uses XCD ranges, one without cache plans
-// its accesses by line alignment)
+// its accesses by line alignment, one without fill takes the built-in refit)
 int tune_parse(const std::string& text) {
     std::istringstream lines(text);
     std::string line;
@@ -147,12 +151,13 @@ int tune_parse(const std::string& text) {
         else if (!(in >> o.umt)) o.umt = 0;
         else if (!(in >> o.cache)) o.cache = -1;
         else if (!(in >> o.diag)) o.diag = 0;
+        else if (!(in >> o.fill)) o.fill = -1;
         std::string extra;
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
             o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib) ||
             o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3 || o.diag < 0 ||
-            o.diag > 1)
+            o.diag > 1 || o.fill < -1 || o.fill > 1)
             return -1;
         tune_store(key, o);
         ++n;
@@ -444,6 +449,9 @@ static int default_row_bytes(int U, bool in_side) {
 }
 
 static int64_t cdiv(int64_t a, int64_t b) { return (a + b - 1) / b; }
+
+// Whether plan_tile refits odd extents for fewer, fuller tiles (TileOptions::fill).
+static bool fill_refit(const TileOptions& o) { return o.fill != 0; }
 
 // Share of each 128-byte line touched by one wave's store instruction that the
 // instruction writes, for a tile whose output rows hold TB units of U bytes,
@@ -766,6 +774,66 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         bool shrinkA = canA && (!canB || TA * R >= TB * R);
         if (shrinkA) t[aO] = std::max(stepA, (t[aO] / 2 + stepA - 1) / stepA * stepA);
         else t[bO] = std::max(stepB, (t[bO] / 2 + stepB - 1) / stepB * stepB);
+    }
+    // Fill refit for odd extents.  Halving toward the soft size and splitting an
+    // outer axis at its row target leave the last tile along it mostly empty on
+    // extents that the tile does not divide (an A axis of 39 at a target of 32
+    // gives tiles of 32 and 7), and small problems then spend most of their
+    // workgroups on thin tiles.  Where an outer axis ends in such a partial tile,
+    // try every tile count along A's outer axis (an even split of it), give B's
+    // outer axis the longest even split that keeps the tile within the soft size,
+    // and keep the shape with the fewest tiles if that saves at least an eighth
+    // of them.  Rows on either side stay at least half their target (or whole)
+    // and a multiple of 16 bytes, so they end in no per-element tail (which costs
+    // up to 15 one-byte accesses per row for 1-byte units); a whole axis may end
+    // in one where units are 4..16 bytes (at most three accesses) or where the
+    // row-target shape already held it whole.  Evenly divided axes are left alone.
+    if (fill_refit(opt) && !umt) {
+        const int64_t stepA = nA == 1 ? G : 1, stepB = nB == 1 ? G : 1;
+        auto quantum = [&](int64_t step, int64_t inner) {   // tile extents with 16-byte rows
+            const int64_t b = inner * step * R;
+            return step * (16 / std::gcd<int64_t>(b, 16));
+        };
+        const int64_t qA = quantum(stepA, innerA), qB = quantum(stepB, innerB);
+        const bool wholeA_ok = U >= 4 || (innerA * d[aO] * R) % 16 == 0 || t[aO] == d[aO];
+        const bool wholeB_ok = U >= 4 || (innerB * d[bO] * R) % 16 == 0 || t[bO] == d[bO];
+        // an extent of at least lo covering the axis in n pieces: a multiple of q,
+        // or the whole axis where allowed; 0 if neither
+        auto split = [&](int64_t len, int64_t n, int64_t q, bool whole_ok) -> int64_t {
+            const int64_t v = cdiv(cdiv(len, n), q) * q;
+            if (v < len) return v;
+            return whole_ok ? len : 0;
+        };
+        auto lds_of = [&](int64_t ta, int64_t tb) { return innerB * tb * ((innerA * ta * R + 15) / 16 * 16); };
+        const bool ragged = (d[aO] % t[aO]) != 0 || (d[bO] % t[bO]) != 0;
+        if (ragged && lds_of(t[aO], t[bO]) <= soft_lds) {
+            const int64_t minA = std::min<int64_t>(d[aO], std::max<int64_t>(stepA, cdiv(in_rb / 2, innerA * R)));
+            const int64_t minB = std::min<int64_t>(d[bO], std::max<int64_t>(stepB, cdiv(out_rb / 2, innerB * R)));
+            const int64_t ncur = cdiv(d[aO], t[aO]), cur = ncur * cdiv(d[bO], t[bO]);
+            int64_t best = cur, bestA = t[aO], bestB = t[bO];
+            for (int64_t na = 1; na <= ncur; ++na) {
+                const int64_t ta = split(d[aO], na, qA, wholeA_ok);
+                if (ta == 0 || ta < minA) continue;
+                const int64_t row = innerB * ((innerA * ta * R + 15) / 16 * 16);
+                const int64_t fit = soft_lds / row;   // B extent that fits the soft size
+                int64_t tb;
+                if (fit >= d[bO] && wholeB_ok) {
+                    tb = d[bO];
+                } else {
+                    const int64_t cap = std::min<int64_t>(fit, d[bO] - 1) / qB * qB;
+                    if (cap < qB) continue;
+                    tb = split(d[bO], cdiv(d[bO], cap), qB, false);
+                    if (tb == 0) continue;
+                }
+                if (tb < minB || lds_of(ta, tb) > soft_lds) continue;
+                const int64_t n = na * cdiv(d[bO], tb);
+                if (n < best) { best = n; bestA = ta; bestB = tb; }
+            }
+            if (best * 8 <= cur * 7) {   // at least an eighth fewer tiles
+                t[aO] = bestA;
+                t[bO] = bestB;
+            }
+        }
     }
     // Stacked tiles: when the last two axes are swapped and the tile holds both
     // whole, a tile would be one small transpose; the next slower input axis C

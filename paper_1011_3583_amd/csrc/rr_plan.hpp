@@ -185,6 +185,7 @@ struct TileOptions {
                             // 2 stores cached, 3 both; -1: by line alignment (cache_policy)
     int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead
                             // of the G = 1 ragged paths), 2 everywhere (testing)
+    int fill = -1;          // refit odd extents for fewer, fuller tiles: 1 on, 0 off, -1 built-in
     int max_lds = 65536;    // hard limit
     bool use_tuned = false; // a tuned shape cached for the problem replaces these options
 };

@@ -10,7 +10,7 @@
 // read of a never-written LDS byte shows up as a wrong output byte.
 //
 // Input: a manifest, one job per line:
-//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt diag infile outfile
+//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt diag fill infile outfile
 //   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
 //   gather   src_count count esize indexed start stride src_off dst_off infile idxfile outfile
 //   stencil  rows cols radius shape nweights w... infile outfile             (float grids)
@@ -247,7 +247,7 @@ int main(int argc, char** argv) {
             for (auto& q : perm) is >> q;
             int esize, soff, doff, order; std::string inf, outf;
             is >> esize >> soff >> doff >> opt.in_row_bytes >> opt.out_row_bytes >> order >> opt.max_g >>
-                opt.force_ragged >> opt.xcd >> opt.umt >> opt.diag >> inf >> outf;
+                opt.force_ragged >> opt.xcd >> opt.umt >> opt.diag >> opt.fill >> inf >> outf;
             opt.order_out = order;
             Canon c;
             rr_status st = canonicalize(ndim, dims.data(), perm.data(), esize, &c, &why);

@@ -39,7 +39,8 @@ def build():
 def run(jobs):
     """Run jobs through the emulator.  Each job is a dict:
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
-                    max_g, ragged, xcd (None: the planner's choice), umt, diag
+                    max_g, ragged, xcd (None: the planner's choice), umt, diag,
+                    fill (None: the planner's choice)
        reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
        gather:      op, src_count, esize, input (uint8), idx (int64) or start/stride/count, src_off, dst_off
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
@@ -60,7 +61,8 @@ def run(jobs):
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))),
                                        str(-1 if j.get("xcd") is None else int(j["xcd"])),
-                                       str(int(j.get("umt", 0))), str(int(j.get("diag", False))), inf, outf]))
+                                       str(int(j.get("umt", 0))), str(int(j.get("diag", False))),
+                                       str(-1 if j.get("fill") is None else int(j["fill"])), inf, outf]))
             elif j["op"] == "stencil":
                 np.ascontiguousarray(j["grid"], dtype=np.float32).tofile(inf)
                 w = [repr(float(v)) for v in np.asarray(j["weights"], dtype=np.float32).reshape(-1)]

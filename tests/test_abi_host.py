@@ -210,6 +210,40 @@ def test_cache_policy_by_line_alignment():
         rr.set_tile_override()
 
 
+def test_fill_refit_plans():
+    """Odd extents: the refit takes a short axis whole and evens out the other for
+    fewer tiles within the tile size; evenly divided (dense) shapes keep their plans;
+    both fill flags together are rejected."""
+    rr.tune_clear()
+
+    def desc(dims, perm, e, fill):
+        rr.set_tile_override(fill=fill)
+        try:
+            return rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+        finally:
+            rr.set_tile_override()
+
+    off, on = desc((611, 39), (1, 0), 8, False), desc((611, 39), (1, 0), 8, True)
+    assert (off["TA"], off["TB"], off["ntiles"]) == ("32", "64", "20")
+    ta, tb = int(on["TA"]), int(on["TB"])
+    assert int(on["ntiles"]) <= 13 and int(on["ntiles"]) == -(-39 // ta) * -(-611 // tb)
+    assert ta * 8 >= 128 and tb * 8 >= 256                 # rows at least half their targets
+    assert (ta * 8) % 16 == 0 or ta == 39                  # 16-byte rows unless whole
+    assert (tb * 8) % 16 == 0 and tb * ((ta * 8 + 15) // 16 * 16) <= 16384   # tile within 16 KiB
+    # 1-byte units: refit rows stay multiples of 16 bytes (no per-byte tails)
+    on1, off1 = desc((4325, 1001, 31), (2, 0, 1), 2, True), desc((4325, 1001, 31), (2, 0, 1), 2, False)
+    assert int(on1["ntiles"]) * 8 <= int(off1["ntiles"]) * 7 and (int(on1["TB"]) * 2) % 16 == 0
+    assert rr.plan_describe((611, 39), (1, 0), 8, dst=1 << 20, src=1 << 30)["ntiles"] == on["ntiles"]
+    for dims, perm, e in [((4096, 4096), (1, 0), 4), ((512, 512, 256), (2, 0, 1), 2),
+                          ((32, 32, 32, 32, 32), (4, 2, 0, 3, 1), 16), ((1000, 1000), (1, 0), 4)]:
+        assert desc(dims, perm, e, True) == desc(dims, perm, e, False), dims
+    # a saving under an eighth keeps the row-target shape
+    assert desc((32761, 4097), (1, 0), 2, True) == desc((32761, 4097), (1, 0), 2, False)
+    with pytest.raises(rr.RRError):
+        rr.check(rr.lib().rr_set_tile_override(0, 0, (1 << 27) | (1 << 28)))
+    rr.set_tile_override()
+
+
 def test_micro_tile_cap_from_override_and_cache(tmp_path):
     """The micro-tile edge G can be capped by the override and by a cached entry."""
     rr.tune_clear()
@@ -245,15 +279,23 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
     rr.tune_load(str(path))
     f = int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"])
     assert f & 2048 and not f & 1024 and not f & 256
-    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 0" in (rr.tune_save(str(out)) or out.read_text())
+    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 0 -1" in (rr.tune_save(str(out)) or out.read_text())
     path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 1\n")   # diagonal tile order
     rr.tune_clear()
     rr.tune_load(str(path))
     assert int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 4096
     rr.tune_clear()
+    # the fill field: 0 keeps the row-target tiles of an odd extent
+    refit = rr.plan_describe((611, 39), (1, 0), 8, dst=1 << 20, src=1 << 30)
+    path.write_text("r2:e8:a16/16:d611,39:p1,0 0 0 -1 0 0 -1 0 -1 0 0\n")
+    rr.tune_load(str(path))
+    d = rr.plan_describe((611, 39), (1, 0), 8, dst=1 << 20, src=1 << 30)
+    assert (d["TA"], d["TB"], d["ntiles"]) == ("32", "64", "20") and d["ntiles"] != refit["ntiles"]
+    rr.tune_clear()
     for bad in ("k 0 0 0 3\n", "k 0 0 0 8 65\n", "k 0 0 0 8 2\n", "k 0 0 0 8 16 2\n", "k 0 0 0 8 16 1 3\n",
                 "k 0 0 0 8 16 -2\n", "k 0 0 0 8 16 1 1 4\n", "k 0 0 0 8 16 1 1 -2\n",
-                "k 0 0 0 8 16 1 1 1 2\n", "k 0 0 0 8 16 1 1 1 0 0\n", "k 0 0\n"):
+                "k 0 0 0 8 16 1 1 1 2\n", "k 0 0 0 8 16 1 1 1 0 2\n", "k 0 0 0 8 16 1 1 1 0 -2\n",
+                "k 0 0 0 8 16 1 1 1 0 0 0\n", "k 0 0\n"):
         (tmp_path / "bad.txt").write_text(bad)
         with pytest.raises(rr.RRError):
             rr.tune_load(str(tmp_path / "bad.txt"))

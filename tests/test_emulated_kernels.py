@@ -193,6 +193,33 @@ def test_emu_diagonal_tile_order():
     assert any(int(st.split("flags=")[1].split()[0]) & 4096 for st, _ in res)
 
 
+FILL_CASES = [((611, 39), (1, 0), 8), ((3, 7, 94, 117), (0, 3, 2, 1), 8), ((257, 131), (1, 0), 2),
+              ((1, 1, 427, 81, 15), (1, 4, 0, 2, 3), 4), ((13, 2, 21, 69), (1, 3, 2, 0), 2),
+              ((17, 2, 1024, 3, 4), (3, 0, 4, 1, 2), 2), ((1024, 48), (1, 0), 8), ((57, 8, 2, 7), (3, 2, 0, 1), 8),
+              ((95, 214, 1, 77), (3, 2, 0, 1), 16), ((333, 71), (1, 0), 1)]
+
+
+def test_emu_fill_refit():
+    """Odd extents refit for fewer, fuller tiles (whole short axes, even splits) move
+    every element once, with the refit on and off, on aligned and offset pointers."""
+    def ntiles(st):
+        return int(st.split("ntiles=")[1].split()[0])
+
+    jobs = []
+    for i, (dims, perm, e) in enumerate(FILL_CASES):
+        for fill in (False, True):
+            jobs.append(_perm_job(dims, perm, e, 7700 + 2 * i + fill, fill=fill))
+            jobs.append(_perm_job(dims, perm, e, 7750 + 2 * i + fill, fill=fill,
+                                  src_off=e % 16 or 4, dst_off=(3 * e) % 16 or 12))
+    res = _check(jobs)
+    fewer = 0
+    for k in range(0, len(res), 4):
+        off_plain, on_plain = ntiles(res[k][0]), ntiles(res[k + 2][0])
+        assert on_plain <= off_plain, (FILL_CASES[k // 4], res[k][0], res[k + 2][0])
+        fewer += on_plain * 8 <= off_plain * 7
+    assert fewer >= len(FILL_CASES) // 2, fewer
+
+
 def test_emu_unaligned_micro_tiles():
     """Odd extents and misaligned pointers keep G x G micro-tiles with unaligned
     vector accesses; partial micro-tiles at tile edges move element by element."""
@@ -447,15 +474,17 @@ def test_emu_chunked_entries(chunk):
 
 
 def test_emu_ragged_and_flat_output_paths():
-    """Odd extents (no 16-byte micro-tiles possible) take the ragged 16-byte row paths;
-    interlace of three sets takes the flat output path; both stay bit-exact."""
+    """Odd extents (no 16-byte micro-tiles possible) take the ragged 16-byte row paths
+    (or a flat input range where a refit tile holds whole input rows); interlace of
+    three sets takes the flat output path; both stay bit-exact."""
     jobs = [_perm_job((1001, 999), (1, 0), 4, 9600), _perm_job((257, 131), (1, 0), 2, 9601),
             _perm_job((33, 45, 77), (2, 0, 1), 8, 9602), _perm_job((17, 19, 23), (1, 2, 0), 1, 9603),
             _perm_job((301, 299), (1, 0), 2, 9604, src_off=2, dst_off=6),
             _perm_job((45, 17, 3, 29), (3, 0, 2, 1), 4, 9605)]
     res = _check(jobs)
     flags = [int(s.split("flags=")[1].split()[0]) for s, _ in res]
-    assert all(f & 16 and f & (64 | 32) for f in flags), flags
+    assert all(f & (16 | 4) and f & (64 | 32) for f in flags), flags
+    assert any(f & 16 for f in flags), flags
     assert any(f & 64 for f in flags) and any(f & 32 for f in flags), flags
     count = 5000 + 7
     planes = [rr_synth.random_bytes(9610 + c, count * 4) for c in range(3)]

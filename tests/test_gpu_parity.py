@@ -376,6 +376,26 @@ def test_diagonal_tile_order(rr, xcd):
         rr.set_tile_override()
 
 
+FILL_CASES = [((611, 39), (1, 0), 8), ((3, 7, 94, 117), (0, 3, 2, 1), 8), ((257, 131), (1, 0), 2),
+              ((1, 1, 427, 81, 15), (1, 4, 0, 2, 3), 4), ((13, 2, 21, 69), (1, 3, 2, 0), 2),
+              ((17, 2, 1024, 3, 4), (3, 0, 4, 1, 2), 2), ((1024, 48), (1, 0), 8), ((57, 8, 2, 7), (3, 2, 0, 1), 8),
+              ((95, 214, 1, 77), (3, 2, 0, 1), 16), ((333, 71), (1, 0), 1), ((431, 1001, 31), (2, 0, 1), 2),
+              ((223, 100, 100, 12), (3, 1, 0, 2), 16), ((559, 1000, 24), (2, 1, 0), 4)]
+
+
+@pytest.mark.parametrize("fill", [False, True])
+def test_fill_refit(rr, fill):
+    """Odd extents with and without the fill refit (fewer, fuller tiles: whole short
+    axes, even splits), on aligned and offset pointers, give the oracle's bytes."""
+    rr.set_tile_override(fill=fill)
+    try:
+        for i, (dims, perm, e) in enumerate(FILL_CASES):
+            check_permute(rr, dims, perm, e, 9900 + i)
+            check_permute(rr, dims, perm, e, 9950 + i, soff=e % 16 or 4, doff=(3 * e) % 16 or 12)
+    finally:
+        rr.set_tile_override()
+
+
 def test_xcd_tile_ranges(rr):
     """Contiguous tile ranges per XCD give the same bytes (tile counts not a
     multiple of 8 included)."""
