@@ -50,6 +50,10 @@ def parse():
                     help="launch each odd-shaped permute of ODD_CASES once with both sides "
                          "non-temporal, then once with the planner's cache policy, and exit "
                          "(for rocprofv3 counter runs; prints the launch order)")
+    ap.add_argument("--profile-batch", action="store_true",
+                    help="build the 4096-job batch as a tuned, graph-replayed handle, replay it three "
+                         "times (each after a 512 MiB cache-flush write), print the replay times and "
+                         "exit (for rocprofv3 kernel traces of the batch's kernel groups)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="turn the counter_collection.csv files of two rocprofv3 --pmc runs of "
                          "'--profile-only --steps 1 --warmup 0' (FETCH_SIZE, then WRITE_SIZE) into "
@@ -194,6 +198,9 @@ def main():
         return
     if args.profile_odd:
         profile_odd()
+        return
+    if args.profile_batch:
+        profile_batch()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -602,6 +609,33 @@ def _job_buffers(torch, specs, dev="cuda"):
     for i in range(0, src.numel(), 1 << 30):
         src[i:i + (1 << 30)].random_(0, 256)
     return src, dst, offs, sizes
+
+
+def profile_batch():
+    """The batch bench's tuned, graph-replayed handle, replayed three times from cold
+    caches; one JSON line per replay (wall time) and one with the handle's choices."""
+    import torch
+    import rr_synth
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    specs = rr_synth.sample_jobs(4096_0001, njobs=4096)
+    src, dst, offs, sizes = _job_buffers(torch, specs)
+    stream = torch.cuda.Stream()
+    jobs = rr.make_jobs([(dst.data_ptr() + o, src.data_ptr() + o, s["dims"], s["perm"], s["esize"])
+                         for o, s in zip(offs, specs)])
+    b = rr.Batch(jobs, rr.RR_BATCH_TUNE | rr.RR_BATCH_GRAPH)
+    print(json.dumps({"batch": b.info()}), flush=True)
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    for i in range(3):
+        flush.fill_(i)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        b.launch(stream)
+        torch.cuda.synchronize()
+        t = time.perf_counter() - t0
+        print(json.dumps({"replay": i, "ms": round(t * 1e3, 3), "GBps": round(2 * sum(sizes) / t / 1e9, 1)}),
+              flush=True)
+    b.close()
 
 
 def bench_batched(rr, rr_synth, torch, stream):

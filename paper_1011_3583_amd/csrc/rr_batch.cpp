@@ -93,6 +93,15 @@ void fanout_destroy(GroupFanout* f) {
     f->fork = nullptr;
 }
 
+// Estimated run time of a group, for placing groups on streams: its workgroups,
+// a tile workgroup (up to 16 KiB through LDS in two dependent phases) weighted as
+// eight copy or run workgroups (4 KiB streamed each), the ratio of their average
+// durations in the 4096-job batch's kernel trace.  Bytes alone rank odd-extent
+// tile groups far too cheap: they move a byte 2-5x slower than copies.
+static uint64_t group_cost(const BatchGroup& g) {
+    return (uint64_t)std::max<uint32_t>(g.total_blocks, 1) * (g.kind == K_TILE ? 8 : 1);
+}
+
 rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
                             hipStream_t st, GroupFanout* fan) {
     if (!fan || !fan->fork || p.groups.size() < 2) {
@@ -102,11 +111,11 @@ rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool p
         }
         return RR_OK;
     }
-    // largest groups first, each to the stream with the fewest bytes queued
+    // costliest groups first, each to the stream with the least estimated work queued
     std::vector<size_t> order(p.groups.size());
     for (size_t i = 0; i < order.size(); ++i) order[i] = i;
     std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return p.groups[a].bytes > p.groups[b].bytes; });
+                     [&](size_t a, size_t b) { return group_cost(p.groups[a]) > group_cost(p.groups[b]); });
     hipStream_t streams[FANOUT_SIDE + 1] = {st};
     for (int k = 0; k < FANOUT_SIDE; ++k) streams[k + 1] = fan->side[k];
     uint64_t load[FANOUT_SIDE + 1] = {};
@@ -124,7 +133,7 @@ rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool p
         const BatchGroup& g = p.groups[i];
         e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), streams[s]);
         if (e != hipSuccess) return hip_fail(e, "batched launch");
-        load[s] += std::max<uint64_t>(g.bytes, 1);
+        load[s] += group_cost(g);
     }
     for (int k = 1; k <= FANOUT_SIDE; ++k) {
         if (!used[k]) continue;
