@@ -184,6 +184,12 @@ rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t coun
  * The job table is staged through pinned host and device buffers the library
  * owns (a small ring per device, grown on demand and held until process exit);
  * a call waits only if it would reuse a slot whose batch is still running.
+ * The groups run side by side on `stream` and three side streams per device
+ * that the library owns (default priority, held until process exit): they start
+ * after the work queued on `stream` before the call, and work queued on `stream`
+ * after the call waits for all of them.  Calls on one device share those side
+ * streams, so batched calls issued on different streams may run one after the
+ * other.
  * Errors: the first invalid job's error (nothing is launched), RR_ERR_NO_MEMORY,
  * RR_ERR_HIP.
  */

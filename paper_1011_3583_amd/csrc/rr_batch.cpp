@@ -30,6 +30,7 @@ constexpr int RING = 4;
 struct Ring {
     Slot slots[RING];
     int next = 0;
+    GroupFanout fan;   // side streams the groups of one-shot batched calls fan out on
 };
 std::mutex g_ring_mu;
 std::map<int, Ring> g_rings;
@@ -283,6 +284,8 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) 
     hipStream_t hs = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_ring_mu);
     Ring& ring = g_rings[device];
+    st = fanout_init(&ring.fan);
+    if (st != RR_OK) return st;
     Slot& s = ring.slots[ring.next];
     ring.next = (ring.next + 1) % RING;
     if (s.used) {
@@ -310,7 +313,7 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) 
     std::memcpy(s.host, bp.table.data(), need);
     e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "job table upload");
-    st = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device, hs);
+    st = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device, hs, &ring.fan);
     e = hipEventRecord(s.done, hs);
     s.used = true;
     if (st != RR_OK) return st;
