@@ -274,7 +274,9 @@ extern "C" {
 
 rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) {
     clear_error();
-    BatchPlan bp;
+    // the plan's table is copied to the staging ring below: each calling thread
+    // keeps one plan so its multi-megabyte table is not allocated per call
+    static thread_local BatchPlan bp;
     rr_status st = plan_or_fail(jobs, njobs, current_tile_options(), &bp);
     if (st != RR_OK) return st;
     if (bp.groups.empty()) return RR_OK;

@@ -3,6 +3,7 @@
 #include <algorithm>
 #include <cstring>
 #include <map>
+#include <thread>
 #include <tuple>
 
 #include "rr_batch.hpp"
@@ -48,6 +49,14 @@ rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string
     return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, p, why);
 }
 
+// Host threads that plan a batch of njobs: one below 1024 jobs (starting threads
+// costs more than it saves), else one per 512 jobs up to 8 and the host's cores.
+static int planning_threads(int njobs) {
+    if (njobs < 1024) return 1;
+    const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
+    return std::max(1, std::min({8, hw, njobs / 512}));
+}
+
 rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
                      std::string* why, int* bad_job) {
     *bad_job = -1;
@@ -58,15 +67,46 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
     if (njobs < 0) { *why = "njobs < 0"; return RR_ERR_INVALID_ARG; }
     if (njobs > 0 && !jobs) { *why = "jobs is NULL"; return RR_ERR_INVALID_ARG; }
 
-    std::vector<Plan> plans((size_t)njobs);
+    // A Plan is over a kilobyte: a fresh array for thousands of jobs costs more in
+    // page faults and zero fill than planning them, so each calling thread keeps
+    // its array (grown on demand; only the members a plan's kind uses are read).
+    static thread_local std::vector<Plan> tl_plans;
+    if (tl_plans.size() < (size_t)njobs) tl_plans.resize((size_t)njobs);
+    Plan* const plans = tl_plans.data();   // the planning threads fill this thread's array
+    // Jobs plan independently (about a microsecond each): large batches split
+    // them into contiguous slices over a few host threads.  The lowest failing
+    // job is reported, as in a sequential pass.
+    const int nt = planning_threads(njobs);
+    std::vector<int> bad((size_t)nt, -1);
+    std::vector<rr_status> sts((size_t)nt, RR_OK);
+    std::vector<std::string> whys((size_t)nt);
+    auto slice = [&](int t) {
+        const int lo = (int)((int64_t)njobs * t / nt), hi = (int)((int64_t)njobs * (t + 1) / nt);
+        for (int i = lo; i < hi; ++i) {
+            const rr_status st = plan_job(jobs[i], opt, &plans[i], &whys[(size_t)t]);
+            if (st != RR_OK) { sts[(size_t)t] = st; bad[(size_t)t] = i; return; }
+        }
+    };
+    std::vector<std::thread> th;
+    std::vector<int> inline_slices;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            th.emplace_back(slice, t);
+        } catch (...) {   // no thread available: plan that slice here
+            inline_slices.push_back(t);
+        }
+    }
+    slice(0);
+    for (int t : inline_slices) slice(t);
+    for (std::thread& x : th) x.join();
+    for (int t = 0; t < nt; ++t)
+        if (sts[(size_t)t] != RR_OK) { *why = whys[(size_t)t]; *bad_job = bad[(size_t)t]; return sts[(size_t)t]; }
     std::vector<Interval> dsts, srcs;
     dsts.reserve((size_t)njobs);
     srcs.reserve((size_t)njobs);
     for (int i = 0; i < njobs; ++i) {
-        rr_status st = plan_job(jobs[i], opt, &plans[(size_t)i], why);
-        if (st != RR_OK) { *bad_job = i; return st; }
-        const uint64_t n = plans[(size_t)i].bytes;
-        if (plans[(size_t)i].kind != K_EMPTY && n > 0) {
+        const uint64_t n = plans[i].bytes;
+        if (plans[i].kind != K_EMPTY && n > 0) {
             const uint64_t d = (uint64_t)jobs[i].dst, s = (uint64_t)jobs[i].src;
             dsts.push_back({d, d + n, i});
             srcs.push_back({s, s + n, i});
@@ -80,8 +120,10 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
     }
     std::vector<BatchEntry> entries;
     entries.reserve((size_t)njobs);
-    for (const Plan& p : plans)
+    for (int i = 0; i < njobs; ++i) {   // the array may be longer than this batch
+        const Plan& p = plans[i];
         if (p.kind != K_EMPTY && p.grid > 0) entries.push_back({&p, 0, p.grid, p.bytes});
+    }
     return build_batch(entries, out, why);
 }
 

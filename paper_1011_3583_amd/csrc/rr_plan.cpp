@@ -23,6 +23,7 @@
 #include <string_view>
 #include <map>
 #include <mutex>
+#include <shared_mutex>
 #include <sstream>
 
 namespace rr {
@@ -60,7 +61,7 @@ void set_tile_override(const TileOptions& o) {
 }
 
 namespace {
-std::mutex g_tune_mu;
+std::shared_mutex g_tune_mu;   // lookups share it (batches plan on several threads)
 std::atomic<size_t> g_tune_entries{0};   // lets lookups skip building a key while empty
 // transparent comparison: lookups pass a string_view formatted on the stack
 std::map<std::string, TileOptions, std::less<>>& tune_cache() {
@@ -97,7 +98,7 @@ bool tune_lookup(const Canon& c, uint64_t dst, uint64_t src, TileOptions* out) {
     if (g_tune_entries.load(std::memory_order_relaxed) == 0) return false;
     char buf[768];
     const std::string_view key = format_tune_key(c, dst, src, buf);
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::shared_lock<std::shared_mutex> lk(g_tune_mu);
     auto& m = tune_cache();
     auto it = m.find(key);
     if (it == m.end()) return false;
@@ -106,19 +107,19 @@ bool tune_lookup(const Canon& c, uint64_t dst, uint64_t src, TileOptions* out) {
 }
 
 void tune_store(const std::string& key, const TileOptions& o) {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::lock_guard<std::shared_mutex> lk(g_tune_mu);
     tune_cache()[key] = o;
     g_tune_entries.store(tune_cache().size(), std::memory_order_relaxed);
 }
 
 void tune_clear() {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::lock_guard<std::shared_mutex> lk(g_tune_mu);
     tune_cache().clear();
     g_tune_entries.store(0, std::memory_order_relaxed);
 }
 
 std::string tune_dump() {
-    std::lock_guard<std::mutex> lk(g_tune_mu);
+    std::lock_guard<std::shared_mutex> lk(g_tune_mu);
     std::ostringstream o;
     for (const auto& kv : tune_cache())
         o << kv.first << " " << kv.second.in_row_bytes << " " << kv.second.out_row_bytes << " "

@@ -244,6 +244,25 @@ def test_fill_refit_plans():
     rr.set_tile_override()
 
 
+def test_batched_planning_reports_lowest_invalid_job():
+    """Batches of 1024 jobs or more plan on several host threads; validation still
+    names the lowest invalid job, and nothing is launched (no GPU is touched)."""
+    specs = []
+    for i in range(2048):
+        src = (1 << 32) + i * 4096
+        specs.append([src + (1 << 36), src, (16, 32), (1, 0), 4])
+    specs[1900][3] = (0, 0)          # not a permutation
+    specs[700][2] = (16, -3)         # negative extent
+    specs[1201][4] = 17              # element size out of range
+    with pytest.raises(rr.RRError) as ei:
+        rr.check(rr.permute_batched_raw([tuple(s) for s in specs]))
+    assert "job 700" in str(ei.value), str(ei.value)
+    specs[700][2] = (16, 32)
+    with pytest.raises(rr.RRError) as ei:
+        rr.check(rr.permute_batched_raw([tuple(s) for s in specs]))
+    assert "job 1201" in str(ei.value), str(ei.value)
+
+
 def test_micro_tile_cap_from_override_and_cache(tmp_path):
     """The micro-tile edge G can be capped by the override and by a cached entry."""
     rr.tune_clear()

@@ -441,6 +441,23 @@ def _batched_jobs(seed, njobs, max_elems=20000):
     return jobs
 
 
+def test_emu_batched_many_jobs_threaded_planning():
+    """1200 small jobs (planned on several host threads, as batches of 1024 jobs or
+    more are) of every element size and ranks 2-4: each equals the oracle alone."""
+    g = rr_synth.rng(4242)
+    jobs = []
+    for i in range(1200):
+        nd = int(g.integers(2, 5))
+        dims = tuple(int(x) for x in g.integers(1, 13, nd))
+        perm = tuple(int(x) for x in g.permutation(nd))
+        jobs.append(_perm_job(dims, perm, int(g.choice([1, 2, 4, 8, 16])), 50000 + i))
+    status, outs = emu_runner.run([dict(op="batched", jobs=jobs)])[0]
+    assert status.startswith("ok"), status
+    for j, out in zip(jobs, outs):
+        assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
+            (j["dims"], j["perm"], j["esize"])
+
+
 @pytest.mark.parametrize("seed,opts", [(1, (0, 0, 0)), (2, (512, 256, 0)), (3, (256, 1024, 1))])
 def test_emu_batched_uneven_jobs(seed, opts):
     """A batch of uneven jobs of every kernel family: each job equals the oracle alone."""
