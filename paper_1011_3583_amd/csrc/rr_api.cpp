@@ -330,6 +330,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, -1, 0, 0, 0, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 2}, {0, 0, -1, 0, 0, 1, 0, 3},
         {0, 0, 1, 0, 0, 1, 0, 1},  {0, 0, 0, 0, 0, 1, 0, 2}, {512, 512, -1, 0, 64, 1, 0, 1},
         {0, 0, -1, 0, 0, -1, 0, -1, 1}, {0, 0, 0, 0, 0, -1, 0, -1, 1}, {0, 0, -1, 0, 64, -1, 0, -1, 1},
+        {1024, 256, 1, 0, 0, -1, 0, -1, 1}, {256, 1024, 1, 0, 0, -1, 0, -1, 1}, {512, 512, 0, 0, 0, -1, 0, -1, 1},
         {0, 0, -1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 0, 0, 0, -1, 0, -1, 0, 0},
         {512, 512, -1, 0, 64, -1, 0, -1, 0, 0}};
     hipStream_t hs = (hipStream_t)stream;
