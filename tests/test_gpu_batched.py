@@ -113,6 +113,26 @@ def test_batched_repeated_calls_reuse_staging(rr):
         _check_all_vs_oracle(J)
 
 
+def test_batched_calls_on_two_streams_share_side_streams(rr):
+    """One-shot batched calls fan their groups out on side streams shared per device:
+    calls issued alternately on two streams (each after its own input upload on that
+    stream) all finish with every job equal to the oracle."""
+    specs = _uneven(4, 64, 8000)
+    Js = [Jobs(rr, specs, 30 + k) for k in range(6)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream(), torch.cuda.Stream()]
+    for k, J in enumerate(Js):
+        st = streams[k % 2]
+        _say("two streams, call", k)
+        with torch.cuda.stream(st):
+            J.dst.zero_()   # queued on this stream: the batch must run after it
+        rr.check(rr.permute_batched_raw(J.arr, len(specs), st.cuda_stream))
+    for st in streams:
+        st.synchronize()
+    for J in Js:
+        _check_all_vs_oracle(J)
+
+
 @pytest.mark.parametrize("flags", [0, 4, 2, 1, 1 | 4, 1 | 2])
 def test_batch_handle_modes(rr, flags):
     specs = _uneven(3, 120, 20000)
