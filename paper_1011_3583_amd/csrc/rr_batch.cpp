@@ -313,6 +313,7 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) 
     if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
         return fail(RR_ERR_HIP, "hipEventCreate");
     std::memcpy(s.host, bp.table.data(), need);
+    if (bp.table.capacity() > (size_t(32) << 20)) std::vector<uint8_t>().swap(bp.table);   // keep at most 32 MB
     e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, hs);
     if (e != hipSuccess) return hip_fail(e, "job table upload");
     st = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device, hs, &ring.fan);

@@ -70,8 +70,15 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
     // A Plan is over a kilobyte: a fresh array for thousands of jobs costs more in
     // page faults and zero fill than planning them, so each calling thread keeps
     // its array (grown on demand; only the members a plan's kind uses are read).
+    // A batch larger than KEEP_PLANS jobs gives its array back when it is done.
+    constexpr size_t KEEP_PLANS = 16384;   // about 20 MB
     static thread_local std::vector<Plan> tl_plans;
     if (tl_plans.size() < (size_t)njobs) tl_plans.resize((size_t)njobs);
+    struct Release {
+        ~Release() {
+            if (tl_plans.size() > KEEP_PLANS) std::vector<Plan>().swap(tl_plans);
+        }
+    } release;
     Plan* const plans = tl_plans.data();   // the planning threads fill this thread's array
     // Jobs plan independently (about a microsecond each): large batches split
     // them into contiguous slices over a few host threads.  The lowest failing
