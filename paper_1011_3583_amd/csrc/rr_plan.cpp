@@ -781,11 +781,12 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     // extents that the tile does not divide (an A axis of 39 at a target of 32
     // gives tiles of 32 and 7), and small problems then spend most of their
     // workgroups on thin tiles.  Where an outer axis ends in such a partial tile,
-    // try every tile count along A's outer axis (an even split of it), give B's
-    // outer axis the longest even split that keeps the tile within the soft size,
-    // and keep the shape with the fewest tiles if that saves at least an eighth
-    // of them.  Rows on either side stay at least half their target (or whole)
-    // and a multiple of 16 bytes, so they end in no per-element tail (which costs
+    // try every extent of A's outer axis that leaves B room for half its row
+    // target, give B's outer axis the longest even split that keeps the tile
+    // within the soft size, and keep the shape with the fewest tiles (evened out
+    // along A) if that saves at least an eighth of them.  Rows on either side stay
+    // at least half their target and one 128-byte line (or whole) and a multiple
+    // of 16 bytes, so they end in no per-element tail (which costs
     // up to 15 one-byte accesses per row for 1-byte units); a whole axis may end
     // in one where units are 4..16 bytes (at most three accesses) or where the
     // row-target shape already held it whole.  Evenly divided axes are left alone.
@@ -798,8 +799,8 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         const int64_t qA = quantum(stepA, innerA), qB = quantum(stepB, innerB);
         const bool wholeA_ok = U >= 4 || (innerA * d[aO] * R) % 16 == 0 || t[aO] == d[aO];
         const bool wholeB_ok = U >= 4 || (innerB * d[bO] * R) % 16 == 0 || t[bO] == d[bO];
-        // an extent of at least lo covering the axis in n pieces: a multiple of q,
-        // or the whole axis where allowed; 0 if neither
+        // an extent covering len in n pieces: a multiple of q, or the whole axis
+        // where allowed; 0 if neither
         auto split = [&](int64_t len, int64_t n, int64_t q, bool whole_ok) -> int64_t {
             const int64_t v = cdiv(cdiv(len, n), q) * q;
             if (v < len) return v;
@@ -808,13 +809,15 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
         auto lds_of = [&](int64_t ta, int64_t tb) { return innerB * tb * ((innerA * ta * R + 15) / 16 * 16); };
         const bool ragged = (d[aO] % t[aO]) != 0 || (d[bO] % t[bO]) != 0;
         if (ragged && lds_of(t[aO], t[bO]) <= soft_lds) {
-            const int64_t minA = std::min<int64_t>(d[aO], std::max<int64_t>(stepA, cdiv(in_rb / 2, innerA * R)));
-            const int64_t minB = std::min<int64_t>(d[bO], std::max<int64_t>(stepB, cdiv(out_rb / 2, innerB * R)));
-            const int64_t ncur = cdiv(d[aO], t[aO]), cur = ncur * cdiv(d[bO], t[bO]);
+            // rows of at least half their target and at least one 128-byte line
+            const int64_t minA = std::min<int64_t>(
+                d[aO], std::max<int64_t>(stepA, cdiv(std::max(in_rb / 2, 128), innerA * R)));
+            const int64_t minB = std::min<int64_t>(
+                d[bO], std::max<int64_t>(stepB, cdiv(std::max(out_rb / 2, 128), innerB * R)));
+            const int64_t cur = cdiv(d[aO], t[aO]) * cdiv(d[bO], t[bO]);
             int64_t best = cur, bestA = t[aO], bestB = t[bO];
-            for (int64_t na = 1; na <= ncur; ++na) {
-                const int64_t ta = split(d[aO], na, qA, wholeA_ok);
-                if (ta == 0 || ta < minA) continue;
+            // tiles for A extent ta: B takes the longest even split that fits
+            auto consider = [&](int64_t ta) {
                 const int64_t row = innerB * ((innerA * ta * R + 15) / 16 * 16);
                 const int64_t fit = soft_lds / row;   // B extent that fits the soft size
                 int64_t tb;
@@ -822,13 +825,26 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
                     tb = d[bO];
                 } else {
                     const int64_t cap = std::min<int64_t>(fit, d[bO] - 1) / qB * qB;
-                    if (cap < qB) continue;
+                    if (cap < qB) return;
                     tb = split(d[bO], cdiv(d[bO], cap), qB, false);
-                    if (tb == 0) continue;
+                    if (tb == 0) return;
                 }
-                if (tb < minB || lds_of(ta, tb) > soft_lds) continue;
-                const int64_t n = na * cdiv(d[bO], tb);
+                if (tb < minB || lds_of(ta, tb) > soft_lds) return;
+                const int64_t n = cdiv(d[aO], ta) * cdiv(d[bO], tb);
                 if (n < best) { best = n; bestA = ta; bestB = tb; }
+            };
+            // A extents that leave B at least minB rows: the whole axis (where
+            // allowed), then every multiple of qA from the longest down (longer
+            // input rows win ties) -- at most a few thousand steps, whatever
+            // the extent
+            const int64_t amax_row = soft_lds / (innerB * minB);   // padded A row bytes
+            if (wholeA_ok && d[aO] >= minA && (innerA * d[aO] * R + 15) / 16 * 16 <= amax_row) consider(d[aO]);
+            int64_t ta = std::min<int64_t>(d[aO] - 1, amax_row / (innerA * R)) / qA * qA;
+            for (; ta >= std::max<int64_t>(qA, minA); ta -= qA) consider(ta);
+            // same tile count, evened out along A (never longer, so it still fits)
+            if (bestA != t[aO] || bestB != t[bO]) {
+                const int64_t even = split(d[aO], cdiv(d[aO], bestA), qA, wholeA_ok);
+                if (even != 0 && even >= minA && even <= bestA) bestA = even;
             }
             if (best * 8 <= cur * 7) {   // at least an eighth fewer tiles
                 t[aO] = bestA;
