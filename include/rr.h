@@ -362,10 +362,11 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * made after the call.  RR_ERR_INVALID_ARG for row targets outside 0..4096, a
  * bad cap, a bad tile size or both XCD flags.
  * RR_TILE_FILL / RR_TILE_NO_FILL switch the odd-extent refit on or off (neither:
- * the built-in choice): where a tile does not divide an outer tile axis, the
+ * the built-in choice, on): where a tile does not divide an outer tile axis, the
  * planner evens out both outer extents for the fewest tiles that fit the tile size,
- * keeping each side's rows at least half their target.  RR_ERR_INVALID_ARG also
- * for both fill flags. */
+ * keeping each side's rows at least half their target, one 128-byte line and a
+ * multiple of 16 bytes (or the whole axis).  RR_ERR_INVALID_ARG also for both fill
+ * flags. */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
