@@ -24,10 +24,19 @@ struct BatchGroup {
     uint32_t lds_bytes;    // largest tile of the group
     uint32_t pad_;
     uint64_t args_off;     // byte offset of the argument array in the table
-    uint64_t prefix_off;   // byte offset of the njobs+1 prefix sums (uint32)
+    uint64_t prefix_off;   // byte offset of the njobs+1 prefix sums (uint32), followed
+                           // by the group's bucket index (batch_buckets entries)
     uint64_t range_off;    // byte offset of njobs EntryRange records
     uint64_t bytes;        // bytes per side moved by the group
 };
+
+// Bucket index after a group's prefix sums: entry k is the job that holds
+// workgroup k * BATCH_BUCKET (the last job where that is past the end), so a
+// workgroup's job lies between its bucket's entry and the next one's.
+constexpr uint32_t BATCH_BUCKET = 32;
+constexpr uint64_t batch_buckets(uint64_t total_blocks) {
+    return total_blocks ? (total_blocks - 1) / BATCH_BUCKET + 2 : 1;
+}
 
 // Which of its job's workgroups an entry runs: blocks [first, first + count)
 // of a launch of `job_blocks` workgroups.  A whole job is {0, grid, grid}.

@@ -167,8 +167,10 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
         size_t asz = g.kind == K_COPY ? sizeof(CopyArgs) : g.kind == K_RUN ? sizeof(RunArgs) : sizeof(TileArgs);
         g.args_off = off;
         off = align_up(off + asz * g.njobs, 256);
+        uint64_t blocks = 0;
+        for (size_t m : kv.second) blocks += entries[m].nblocks;
         g.prefix_off = off;
-        off = align_up(off + 4ull * (g.njobs + 1), 256);
+        off = align_up(off + 4ull * (g.njobs + 1) + 4ull * batch_buckets(blocks), 256);
         g.range_off = off;
         off = align_up(off + sizeof(EntryRange) * g.njobs, 256);
         out->groups.push_back(g);
@@ -200,6 +202,16 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
         if (acc > 0x7fffffffULL) { *why = "batch group exceeds 2^31 workgroups"; return RR_ERR_UNSUPPORTED; }
         prefix[members.size()] = (uint32_t)acc;
         g.total_blocks = (uint32_t)acc;
+        // bucket index: the job of every BATCH_BUCKET-th workgroup
+        uint32_t* bucket = prefix + members.size() + 1;
+        const uint64_t nbk = batch_buckets(acc);
+        uint32_t j = 0;
+        for (uint64_t k = 0; k < nbk; ++k) {
+            const uint64_t first = k * BATCH_BUCKET;
+            if (first >= acc) { bucket[k] = g.njobs - 1; continue; }
+            while (j + 1 < g.njobs && prefix[j + 1] <= first) ++j;
+            bucket[k] = j;
+        }
     }
     return RR_OK;
 }

@@ -1099,9 +1099,15 @@ RR_HD void write_phase(const TileArgs& a, const TileCtx& t, const uint8_t* lds, 
 
 // ----------------------------------------------------------------- batches
 // Job of workgroup b in a batch group: the largest j with prefix[j] <= b
-// (prefix holds njobs+1 exclusive sums of the jobs' workgroup counts).
+// (prefix holds njobs+1 exclusive sums of the jobs' workgroup counts, then the
+// bucket index).  The bucket bounds the search to the jobs between the ones
+// holding workgroups k * BATCH_BUCKET and (k + 1) * BATCH_BUCKET: one or two
+// dependent loads for most workgroups instead of log2(njobs).
 RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
-    uint32_t lo = 0, hi = njobs;
+    const uint32_t* bucket = prefix + njobs + 1;
+    const uint32_t k = b / BATCH_BUCKET;
+    uint32_t lo = bucket[k], hi = bucket[k + 1] + 1;
+    if (hi > njobs) hi = njobs;
     while (hi - lo > 1) {
         const uint32_t mid = (lo + hi) >> 1;
         if (prefix[mid] <= b) lo = mid; else hi = mid;
