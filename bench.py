@@ -50,6 +50,10 @@ def parse():
                     help="launch each odd-shaped permute of ODD_CASES once with both sides "
                          "non-temporal, then once with the planner's cache policy, and exit "
                          "(for rocprofv3 counter runs; prints the launch order)")
+    ap.add_argument("--profile-access", action="store_true",
+                    help="run each index-set and range read of the access-pattern side run once "
+                         "(each after a 512 MiB cache-flush write), print one JSON line per launch "
+                         "in launch order and exit (for rocprofv3 kernel traces and HBM counters)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="build the 4096-job batch as a tuned, graph-replayed handle, replay it three "
                          "times (each after a 512 MiB cache-flush write), print the replay times and "
@@ -201,6 +205,9 @@ def main():
         return
     if args.profile_batch:
         profile_batch()
+        return
+    if args.profile_access:
+        profile_access()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -609,6 +616,45 @@ def _job_buffers(torch, specs, dev="cuda"):
     for i in range(0, src.numel(), 1 << 30):
         src[i:i + (1 << 30)].random_(0, 256)
     return src, dst, offs, sizes
+
+
+def profile_access():
+    """The access-pattern side run's index-set and range reads of a 1 GiB table, one
+    launch each from cold caches; one JSON line per launch (name, element size,
+    elements, algorithmic bytes = indices read + elements read + elements written)."""
+    import torch
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    sh = torch.cuda.current_stream().cuda_stream
+    table, count = 1 << 30, 1 << 26
+    pool = torch.empty(table, dtype=torch.uint8, device="cuda")
+    pool.random_(0, 256)
+    out = torch.empty(count * 16, dtype=torch.uint8, device="cuda")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    g = torch.Generator(device="cuda")
+    g.manual_seed(3583)
+
+    def launch(name, e, n_el, alg, fn):
+        flush.fill_(1)
+        torch.cuda.synchronize()
+        fn()
+        torch.cuda.synchronize()
+        print(json.dumps({"case": name, "esize": e, "elements": n_el, "algorithmic_bytes": alg}), flush=True)
+
+    for e in (4, 16):
+        n = table // e
+        idx = torch.randint(0, n, (count,), generator=g, device="cuda", dtype=torch.int64)
+        for name, ix in (("random", idx), ("sorted", torch.sort(idx).values)):
+            launch(f"gather_{name}_e{e}", e, count, count * (8 + 2 * e),
+                   lambda: rr.check(rr.gather_raw(out.data_ptr(), pool.data_ptr(), n, ix.data_ptr(), count, e, 0,
+                                                  sh)))
+        del idx
+        for stride in (2, -1, 7):
+            start = 0 if stride > 0 else n - 1
+            cnt = min(count, (n - 1) // abs(stride) + 1)
+            launch(f"range_stride{stride}_e{e}", e, cnt, 2 * cnt * e,
+                   lambda: rr.check(rr.copy_range_raw(out.data_ptr(), pool.data_ptr(), n, start, stride, cnt, e,
+                                                      sh)))
 
 
 def profile_batch():
