@@ -54,6 +54,10 @@ def parse():
                     help="run each index-set and range read of the access-pattern side run once "
                          "(each after a 512 MiB cache-flush write), print one JSON line per launch "
                          "in launch order and exit (for rocprofv3 kernel traces and HBM counters)")
+    ap.add_argument("--profile-stencil", action="store_true",
+                    help="run each stencil of the stencil side run once (each after a 512 MiB "
+                         "cache-flush write), print one JSON line per launch in launch order and "
+                         "exit (for rocprofv3 kernel traces and HBM counters)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="build the 4096-job batch as a tuned, graph-replayed handle, replay it three "
                          "times (each after a 512 MiB cache-flush write), print the replay times and "
@@ -208,6 +212,9 @@ def main():
         return
     if args.profile_access:
         profile_access()
+        return
+    if args.profile_stencil:
+        profile_stencil()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -655,6 +662,33 @@ def profile_access():
             launch(f"range_stride{stride}_e{e}", e, cnt, 2 * cnt * e,
                    lambda: rr.check(rr.copy_range_raw(out.data_ptr(), pool.data_ptr(), n, start, stride, cnt, e,
                                                       sh)))
+
+
+def profile_stencil():
+    """The stencil side run's cases (FD orders I-IV, 3x3 and 5x5 boxes on 4096^2 and
+    16384^2 float grids), one launch each from cold caches; one JSON line per launch
+    (algorithmic bytes = one read and one write of the grid)."""
+    import torch
+    import rr_synth
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    sh = torch.cuda.current_stream().cuda_stream
+    nmax = max(r * c for r, c in rr_synth.STENCIL_GRIDS)
+    src = torch.randn(nmax, dtype=torch.float32, device="cuda")
+    dst = torch.empty(nmax, dtype=torch.float32, device="cuda")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    g = rr_synth.rng(4)
+    for rows, cols in rr_synth.STENCIL_GRIDS:
+        cases = [(f"fd_order{r}", r, c, 0) for r, c in rr_synth.FD_LAPLACIAN.items()]
+        cases += [(f"box{2 * r + 1}x{2 * r + 1}", r, g.uniform(-1, 1, (2 * r + 1) ** 2).astype("float32"), 1)
+                  for r in (1, 2)]
+        for name, r, w, shape in cases:
+            flush.fill_(1)
+            torch.cuda.synchronize()
+            rr.check(rr.stencil2d_raw(dst.data_ptr(), src.data_ptr(), rows, cols, r, w, shape, sh))
+            torch.cuda.synchronize()
+            print(json.dumps({"case": f"{rows}x{cols}_{name}", "radius": r, "shape": shape,
+                              "algorithmic_bytes": 2 * rows * cols * 4}), flush=True)
 
 
 def profile_batch():

@@ -564,11 +564,13 @@ RR_HD TileCtx tile_decode(const TileArgs& a, uint32_t tile) {
 // TF_XCD it takes the contiguous range [x*q + min(x, r), +q + (x < r)) of the
 // ntiles = 8q + r tiles instead.  Either way a bijection on [0, ntiles).
 constexpr uint32_t NXCD = 8;
-RR_HD uint32_t block_to_tile(const TileArgs& a, uint32_t b) {
-    if (!(a.flags & TF_XCD)) return b;
-    const uint32_t q = a.ntiles / NXCD, r = a.ntiles % NXCD;
+RR_HD uint32_t xcd_range(uint32_t b, uint32_t ntiles) {
+    const uint32_t q = ntiles / NXCD, r = ntiles % NXCD;
     const uint32_t x = b % NXCD, k = b / NXCD;
     return x * q + umin(x, r) + k;
+}
+RR_HD uint32_t block_to_tile(const TileArgs& a, uint32_t b) {
+    return (a.flags & TF_XCD) ? xcd_range(b, a.ntiles) : b;
 }
 
 RR_HD uint64_t row_in(const TileArgs& a, uint32_t ib) {

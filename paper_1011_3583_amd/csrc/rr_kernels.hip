@@ -28,12 +28,17 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyArgs a) {
     copy_thread<W>(a, blockIdx.x, gridDim.x, threadIdx.x);
 }
 
+// Each XCD takes a contiguous range of tiles (whole tile rows on large grids):
+// a tile row's 16-byte side halos touch the 128-byte lines its neighbours load,
+// and its halo rows the rows above and below, so neighbours share them in one L2
+// instead of each XCD fetching them again.
 template <int R, int SHAPE>
 __global__ __launch_bounds__(NT) void k_stencil(const StencilArgs a) {
     __shared__ __attribute__((aligned(16))) uint32_t lds[(ST_TH + 2 * R) * ST_PITCH];
-    stencil_load<R>(a, blockIdx.x, lds, threadIdx.x);
+    const uint32_t tile = xcd_range(blockIdx.x, a.ntiles);
+    stencil_load<R>(a, tile, lds, threadIdx.x);
     __syncthreads();
-    stencil_compute<R, SHAPE>(a, blockIdx.x, lds, threadIdx.x);
+    stencil_compute<R, SHAPE>(a, tile, lds, threadIdx.x);
 }
 
 template <int W>

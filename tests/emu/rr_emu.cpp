@@ -163,7 +163,13 @@ static bool emulate_group(const BatchGroup& g, const uint8_t* table) {
 template <int R, int SHAPE>
 static void run_stencil_rs(const StencilArgs& a) {
     const size_t nl = (size_t)(ST_TH + 2 * R) * ST_PITCH;
-    for (uint32_t tile = 0; tile < a.ntiles; ++tile) {
+    std::vector<uint8_t> seen(a.ntiles, 0);   // the workgroup -> tile map takes each tile once
+    for (uint32_t b = 0; b < a.ntiles; ++b) {
+        const uint32_t tile = xcd_range(b, a.ntiles);
+        if (tile >= a.ntiles || seen[tile]++) {
+            std::fprintf(stderr, "stencil block %u -> bad tile %u\n", b, tile);
+            std::abort();
+        }
         uint32_t* lds = new uint32_t[nl];
         std::memset(lds, 0xA5, nl * 4);
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_load<R>(a, tile, lds, tid);
