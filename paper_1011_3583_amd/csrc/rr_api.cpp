@@ -186,7 +186,8 @@ rr_status rr_stencil2d(float* dst, const float* src, int64_t rows, int64_t cols,
     a.radius = radius; a.shape = shape;
     const int nw = shape == RR_STENCIL_STAR ? radius + 1 : (2 * radius + 1) * (2 * radius + 1);
     for (int k = 0; k < nw; ++k) a.w[k] = weights[k];
-    const int64_t tx = (cols + ST_TW - 1) / ST_TW, ty = (rows + ST_TH - 1) / ST_TH;
+    a.th = stencil_tile_rows(rows, cols);
+    const int64_t tx = (cols + ST_TW - 1) / ST_TW, ty = (rows + a.th - 1) / a.th;
     if (tx > 0x7fffffffLL / std::max<int64_t>(ty, 1)) return fail(RR_ERR_UNSUPPORTED, "grid needs too many tiles");
     a.tiles_x = (uint32_t)tx;
     a.ntiles = (uint32_t)(tx * ty);

@@ -378,12 +378,12 @@ RR_HD uint32_t float_to_bits(float f) { return __builtin_bit_cast(uint32_t, f); 
 // ST_PITCH floats starting ST_HALO columns left of the tile, into LDS as 16-byte
 // vectors (element by element where a vector crosses the grid's edge; points
 // outside the grid are zero and never used).
-template <int R>
+template <int R, int TH>
 RR_HD void stencil_load(const StencilArgs& a, uint32_t tile, uint32_t* lds, uint32_t tid) {
-    constexpr int LR = ST_TH + 2 * R;
+    constexpr int LR = TH + 2 * R;
     constexpr int NV = ST_PITCH / 4;
     const int64_t ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
-    const int64_t i0 = ty * ST_TH - R, j0 = tx * ST_TW - ST_HALO;
+    const int64_t i0 = ty * TH - R, j0 = tx * ST_TW - ST_HALO;
     const uint8_t* src = reinterpret_cast<const uint8_t*>(a.src);
     for (uint32_t v = tid; v < (uint32_t)(LR * NV); v += NT) {
         const int lr = (int)(v / NV), lc = (int)(v - (uint32_t)lr * NV) * 4;
@@ -407,11 +407,11 @@ RR_HD void stencil_load(const StencilArgs& a, uint32_t tile, uint32_t* lds, uint
 }
 
 // Compute phase: thread (cx = tid % 32, ry = tid / 32) produces the four points
-// at columns 4cx..4cx+3 of tile rows ry, ry+8, ... (ST_TH / 8 rows).  Every
+// at columns 4cx..4cx+3 of tile rows ry, ry+8, ... (TH / 8 rows).  Every
 // LDS read is an aligned 16-byte vector: three for the horizontal window, one
 // per vertical neighbour row.  Accumulation is fp32 FMA: center first, then
 // ring k = (up + down) + (left + right) for a star, row by row for a box.
-template <int R, int SHAPE>
+template <int R, int SHAPE, int TH>
 RR_HD void stencil_compute(const StencilArgs& a, uint32_t tile, const uint32_t* lds, uint32_t tid) {
     constexpr int N = 2 * R + 1;
     const int64_t ty = tile / a.tiles_x, tx = tile - ty * a.tiles_x;
@@ -420,9 +420,9 @@ RR_HD void stencil_compute(const StencilArgs& a, uint32_t tile, const uint32_t* 
     if (gj >= a.cols) return;
     const int lc = ST_HALO + (int)cx * 4;
     uint8_t* dst = reinterpret_cast<uint8_t*>(a.dst);
-    for (int s = 0; s < ST_TH / 8; ++s) {
+    for (int s = 0; s < TH / 8; ++s) {
         const int li = (int)ry + s * 8;
-        const int64_t gi = ty * ST_TH + li;
+        const int64_t gi = ty * TH + li;
         if (gi >= a.rows) break;
         const uint32_t* c = lds + (li + R) * ST_PITCH + lc;   // first output point's center
         float acc[4];

@@ -32,13 +32,13 @@ __global__ __launch_bounds__(NT) void k_copy(const CopyArgs a) {
 // a tile row's 16-byte side halos touch the 128-byte lines its neighbours load,
 // and its halo rows the rows above and below, so neighbours share them in one L2
 // instead of each XCD fetching them again.
-template <int R, int SHAPE>
+template <int R, int SHAPE, int TH>
 __global__ __launch_bounds__(NT) void k_stencil(const StencilArgs a) {
-    __shared__ __attribute__((aligned(16))) uint32_t lds[(ST_TH + 2 * R) * ST_PITCH];
+    __shared__ __attribute__((aligned(16))) uint32_t lds[(TH + 2 * R) * ST_PITCH];
     const uint32_t tile = xcd_range(blockIdx.x, a.ntiles);
-    stencil_load<R>(a, tile, lds, threadIdx.x);
+    stencil_load<R, TH>(a, tile, lds, threadIdx.x);
     __syncthreads();
-    stencil_compute<R, SHAPE>(a, tile, lds, threadIdx.x);
+    stencil_compute<R, SHAPE, TH>(a, tile, lds, threadIdx.x);
 }
 
 template <int W>
@@ -96,21 +96,30 @@ static hipError_t launch_tile(const TileArgs& a, uint32_t grid, hipStream_t st) 
     }
 }
 
-hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
-    if (a.ntiles == 0) return hipSuccess;
+template <int TH>
+static hipError_t launch_stencil_th(const StencilArgs& a, hipStream_t st) {
     const dim3 g(a.ntiles), b(NT);
     switch (a.radius * 2 + a.shape) {
-        case 2: hipLaunchKernelGGL((k_stencil<1, 0>), g, b, 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_stencil<1, 1>), g, b, 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_stencil<2, 0>), g, b, 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_stencil<2, 1>), g, b, 0, st, a); break;
-        case 6: hipLaunchKernelGGL((k_stencil<3, 0>), g, b, 0, st, a); break;
-        case 7: hipLaunchKernelGGL((k_stencil<3, 1>), g, b, 0, st, a); break;
-        case 8: hipLaunchKernelGGL((k_stencil<4, 0>), g, b, 0, st, a); break;
-        case 9: hipLaunchKernelGGL((k_stencil<4, 1>), g, b, 0, st, a); break;
+        case 2: hipLaunchKernelGGL((k_stencil<1, 0, TH>), g, b, 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_stencil<1, 1, TH>), g, b, 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_stencil<2, 0, TH>), g, b, 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_stencil<2, 1, TH>), g, b, 0, st, a); break;
+        case 6: hipLaunchKernelGGL((k_stencil<3, 0, TH>), g, b, 0, st, a); break;
+        case 7: hipLaunchKernelGGL((k_stencil<3, 1, TH>), g, b, 0, st, a); break;
+        case 8: hipLaunchKernelGGL((k_stencil<4, 0, TH>), g, b, 0, st, a); break;
+        case 9: hipLaunchKernelGGL((k_stencil<4, 1, TH>), g, b, 0, st, a); break;
         default: return hipErrorInvalidValue;
     }
     return hipGetLastError();
+}
+
+hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
+    if (a.ntiles == 0) return hipSuccess;
+    switch (a.th) {
+        case 16: return launch_stencil_th<16>(a, st);
+        case 32: return launch_stencil_th<32>(a, st);
+        default: return hipErrorInvalidValue;
+    }
 }
 
 hipError_t launch_plan(const Plan& p, hipStream_t st) {

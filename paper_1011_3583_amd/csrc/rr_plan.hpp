@@ -75,9 +75,17 @@ struct GatherArgs {
 // 2-D stencil over a rows x cols float grid (Sec. III.D).  shape 0 (star):
 // w[0] center, w[k] the four points at distance k along the axes; shape 1
 // (box): w[(dy+r)*(2r+1) + dx+r].  Points closer than r to an edge keep
-// their input.  Output tiles are ST_TH x ST_TW points, tile t at row
-// (t / tiles_x) * ST_TH, column (t % tiles_x) * ST_TW.
-constexpr int ST_TW = 128, ST_TH = 64;      // output tile (columns x rows)
+// their input.  Output tiles are th x ST_TW points, tile t at row
+// (t / tiles_x) * th, column (t % tiles_x) * ST_TW.
+constexpr int ST_TW = 128;                  // output tile columns
+// Output tile rows: 32 up to 2^24 grid points (Table 4's 4096 x 4096 grid), 16 on
+// larger grids.  Shorter tiles use less LDS, so more workgroups overlap their loads
+// and stores on a CU; with each XCD taking a contiguous range of tiles, the extra
+// halo rows are mostly found in L2 (measured: 4096^2 +7 % at 32 rows over 64,
+// 16384^2 +8.5 % at 16 rows).
+inline int stencil_tile_rows(int64_t rows, int64_t cols) {
+    return rows * cols > (int64_t(1) << 24) ? 16 : 32;
+}
 constexpr int ST_HALO = 4;                  // columns loaded on each side (>= radius)
 constexpr int ST_PITCH = ST_TW + 2 * ST_HALO;   // floats per LDS row
 constexpr int ST_MAXR = 4;
@@ -86,6 +94,7 @@ struct StencilArgs {
     int64_t rows, cols;
     uint32_t tiles_x, ntiles;
     int32_t radius, shape;
+    int32_t th, pad_;      // tile rows (16 or 32)
     float w[(2 * ST_MAXR + 1) * (2 * ST_MAXR + 1)];
 };
 

@@ -160,9 +160,9 @@ static bool emulate_group(const BatchGroup& g, const uint8_t* table) {
     return false;
 }
 
-template <int R, int SHAPE>
+template <int R, int SHAPE, int TH>
 static void run_stencil_rs(const StencilArgs& a) {
-    const size_t nl = (size_t)(ST_TH + 2 * R) * ST_PITCH;
+    const size_t nl = (size_t)(TH + 2 * R) * ST_PITCH;
     std::vector<uint8_t> seen(a.ntiles, 0);   // the workgroup -> tile map takes each tile once
     for (uint32_t b = 0; b < a.ntiles; ++b) {
         const uint32_t tile = xcd_range(b, a.ntiles);
@@ -172,22 +172,31 @@ static void run_stencil_rs(const StencilArgs& a) {
         }
         uint32_t* lds = new uint32_t[nl];
         std::memset(lds, 0xA5, nl * 4);
-        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_load<R>(a, tile, lds, tid);
-        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_compute<R, SHAPE>(a, tile, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_load<R, TH>(a, tile, lds, tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) stencil_compute<R, SHAPE, TH>(a, tile, lds, tid);
         delete[] lds;
     }
 }
 
-static bool run_stencil(const StencilArgs& a) {
+template <int TH>
+static bool run_stencil_th(const StencilArgs& a) {
     switch (a.radius * 2 + a.shape) {
-        case 2: run_stencil_rs<1, 0>(a); return true;
-        case 3: run_stencil_rs<1, 1>(a); return true;
-        case 4: run_stencil_rs<2, 0>(a); return true;
-        case 5: run_stencil_rs<2, 1>(a); return true;
-        case 6: run_stencil_rs<3, 0>(a); return true;
-        case 7: run_stencil_rs<3, 1>(a); return true;
-        case 8: run_stencil_rs<4, 0>(a); return true;
-        case 9: run_stencil_rs<4, 1>(a); return true;
+        case 2: run_stencil_rs<1, 0, TH>(a); return true;
+        case 3: run_stencil_rs<1, 1, TH>(a); return true;
+        case 4: run_stencil_rs<2, 0, TH>(a); return true;
+        case 5: run_stencil_rs<2, 1, TH>(a); return true;
+        case 6: run_stencil_rs<3, 0, TH>(a); return true;
+        case 7: run_stencil_rs<3, 1, TH>(a); return true;
+        case 8: run_stencil_rs<4, 0, TH>(a); return true;
+        case 9: run_stencil_rs<4, 1, TH>(a); return true;
+    }
+    return false;
+}
+
+static bool run_stencil(const StencilArgs& a) {
+    switch (a.th) {
+        case 16: return run_stencil_th<16>(a);
+        case 32: return run_stencil_th<32>(a);
     }
     return false;
 }
@@ -291,9 +300,17 @@ int main(int argc, char** argv) {
             a.src = (uint64_t)sbuf; a.dst = (uint64_t)dbuf; a.rows = rows; a.cols = cols;
             a.radius = radius; a.shape = shape;
             a.tiles_x = (uint32_t)((cols + ST_TW - 1) / ST_TW);
-            a.ntiles = (uint32_t)(a.tiles_x * ((rows + ST_TH - 1) / ST_TH));
-            if (nb && !run_stencil(a)) { std::printf("err -1 no kernel\n"); return 3; }
-            if (reinterpret_cast<uint8_t*>(dbuf)[nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+            // both tile heights, whichever the grid size picks: the results must agree
+            std::vector<uint8_t> first;
+            for (int th : {16, 32}) {
+                a.th = th;
+                a.ntiles = (uint32_t)(a.tiles_x * ((rows + th - 1) / th));
+                std::memset(dbuf, 0x5A, nb + 4);
+                if (nb && !run_stencil(a)) { std::printf("err -1 no kernel\n"); return 3; }
+                if (reinterpret_cast<uint8_t*>(dbuf)[nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
+                if (th == 16) first.assign(reinterpret_cast<uint8_t*>(dbuf), reinterpret_cast<uint8_t*>(dbuf) + nb);
+                else if (nb && std::memcmp(first.data(), dbuf, nb) != 0) { std::printf("err -3 tile heights differ\n"); return 3; }
+            }
             write_file(outf, reinterpret_cast<uint8_t*>(dbuf), nb);
             std::printf("ok stencil tiles=%u\n", a.ntiles);
             delete[] sbuf;

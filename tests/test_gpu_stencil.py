@@ -50,6 +50,17 @@ def test_stencil_paper_grid_4096(rr):
     check_stencil(gpu_stencil(rr, x, 2, w, 1), x, 2, w, 1)
 
 
+def test_stencil_grid_above_2_24_points(rr):
+    """A grid just above 2^24 points takes the 16-row tiles (smaller grids take
+    32-row tiles): FD orders I and IV and a 3x3 box against the oracle."""
+    x = rr_synth.random_grid(4100, 4100, 4100)
+    for r in (1, 4):
+        c = rr_synth.FD_LAPLACIAN[r]
+        check_stencil(gpu_stencil(rr, x, r, c), x, r, c, 0)
+    w = rr_synth.rng(6).uniform(-1, 1, 9).astype(np.float32)
+    check_stencil(gpu_stencil(rr, x, 1, w, 1), x, 1, w, 1)
+
+
 def test_stencil_polynomial_field(rr):
     """The order-I Laplacian of i^2 + j^2 is exactly 4 in fp32 (exact weights, exact
     sums of integers below 2^24)."""
