@@ -141,7 +141,8 @@ rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t s
  * Points closer than radius to an edge keep their input value.
  *   dst, src   device grids of rows*cols floats, 4-byte aligned, not overlapping.
  *   radius     1..4.  weights: host array (copied at the call).
- * Each workgroup produces a 64 x 128 tile from LDS holding it plus its halo.
+ * Each workgroup produces a 32 x 128 tile (16 x 128 on grids above 2^24 points)
+ * from LDS holding it plus its halo.
  * Errors: RR_ERR_INVALID_ARG, RR_ERR_OVERFLOW, RR_ERR_ALIAS, RR_ERR_UNSUPPORTED,
  * RR_ERR_HIP.
  */
