@@ -58,6 +58,10 @@ def parse():
                     help="run each stencil of the stencil side run once (each after a 512 MiB "
                          "cache-flush write), print one JSON line per launch in launch order and "
                          "exit (for rocprofv3 kernel traces and HBM counters)")
+    ap.add_argument("--profile-interlace", action="store_true",
+                    help="run each interlace and de-interlace workload once (each after a 512 MiB "
+                         "cache-flush write), print one JSON line per launch in launch order and "
+                         "exit (for rocprofv3 kernel traces and HBM counters)")
     ap.add_argument("--profile-batch", action="store_true",
                     help="build the 4096-job batch as a tuned, graph-replayed handle, replay it three "
                          "times (each after a 512 MiB cache-flush write), print the replay times and "
@@ -215,6 +219,9 @@ def main():
         return
     if args.profile_stencil:
         profile_stencil()
+        return
+    if args.profile_interlace:
+        profile_interlace()
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -689,6 +696,34 @@ def profile_stencil():
             torch.cuda.synchronize()
             print(json.dumps({"case": f"{rows}x{cols}_{name}", "radius": r, "shape": shape,
                               "algorithmic_bytes": 2 * rows * cols * 4}), flush=True)
+
+
+def profile_interlace():
+    """The interlace workloads (n planes of count elements joined set index fastest,
+    and split back), one launch each from cold caches; one JSON line per launch
+    (algorithmic bytes = every plane read and written once)."""
+    import torch
+    import rr_synth
+    import paper_1011_3583_amd as rr
+    rr.lib()
+    sh = torch.cuda.current_stream().cuda_stream
+    nmax = max(n * count * e for _, n, count, e in rr_synth.INTERLACE_CASES)
+    pool = torch.empty(nmax, dtype=torch.uint8, device="cuda")
+    pool.random_(0, 256)
+    out = torch.empty(nmax, dtype=torch.uint8, device="cuda")
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
+    for name, n, count, e in rr_synth.INTERLACE_CASES:
+        pb = count * e
+        planes = [pool.data_ptr() + c * pb for c in range(n)]
+        for op, fn in (("interlace", lambda: rr.interlace_raw(out.data_ptr(), planes, count, e, sh)),
+                       ("deinterlace", lambda: rr.deinterlace_raw(planes, out.data_ptr(), count, e, sh))):
+            flush.fill_(1)
+            torch.cuda.synchronize()
+            rr.check(fn())
+            torch.cuda.synchronize()
+            d = rr.plan_describe((n, count) if op == "interlace" else (count, n), (1, 0), e, 1 << 20, 1 << 30)
+            print(json.dumps({"case": f"{name}_{op}", "n": n, "esize": e, "algorithmic_bytes": 2 * n * pb,
+                              "flags": int(d["flags"])}), flush=True)
 
 
 def profile_batch():
