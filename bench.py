@@ -43,7 +43,9 @@ def parse():
                          "else tune and save them there")
     ap.add_argument("--no-side", action="store_true", help="skip interlace/batched/serve side runs")
     ap.add_argument("--no-serve", action="store_true", help="skip the serving-loop side run")
-    ap.add_argument("--serve-requests", type=int, default=100_000, help="requests per arrival rate")
+    ap.add_argument("--serve-requests", type=int, default=100_000, help="most requests per arrival rate")
+    ap.add_argument("--side-only", choices=("serve", "batched"), default=None,
+                    help="run only this side measurement and print its JSON (no dense step)")
     ap.add_argument("--profile-only", action="store_true",
                     help="run warmup+steps and exit (for rocprofv3 runs)")
     ap.add_argument("--profile-odd", action="store_true",
@@ -62,10 +64,13 @@ def parse():
                     help="run each interlace and de-interlace workload once (each after a 512 MiB "
                          "cache-flush write), print one JSON line per launch in launch order and "
                          "exit (for rocprofv3 kernel traces and HBM counters)")
-    ap.add_argument("--profile-batch", action="store_true",
-                    help="build the 4096-job batch as a tuned, graph-replayed handle, replay it three "
-                         "times (each after a 512 MiB cache-flush write), print the replay times and "
-                         "exit (for rocprofv3 kernel traces of the batch's kernel groups)")
+    ap.add_argument("--profile-batch", nargs="?", const="graph", default=None, choices=("graph", "serial"),
+                    help="build the 4096-job batch as a tuned handle -- graph: graph-replayed with its "
+                         "groups side by side (what the batch bench times); serial: its groups one after "
+                         "another on one stream -- replay it three times (each after a 512 MiB "
+                         "cache-flush write), print the handle's groups (bytes per side each) and the "
+                         "replay times, and exit (for rocprofv3 kernel traces and HBM counters of the "
+                         "kernel groups: the replays are the last 3 x groups dispatches)")
     ap.add_argument("--ingest-counters", nargs=2, metavar=("FETCH_CSV", "WRITE_CSV"), default=None,
                     help="turn the counter_collection.csv files of two rocprofv3 --pmc runs of "
                          "'--profile-only --steps 1 --warmup 0' (FETCH_SIZE, then WRITE_SIZE) into "
@@ -102,6 +107,22 @@ def dense_cases():
                 n *= d
             cases.append((name, dims, perm, e, n * e))
     return cases
+
+
+# Consecutive launches of the step read and write places this far apart (modulo
+# the buffers), so no case finds its input or output lines still in the 256 MB
+# Infinity Cache from the launches just before it.
+STEP_STRIDE = 768 << 20
+
+
+def step_addresses(pool: int, out: int, max_nb: int, i: int, nb: int):
+    """(src, dst) of case i: the input somewhere in the two-region pool (2 * max_nb
+    bytes), the output somewhere in out (max_nb bytes), both 4 KiB aligned and
+    STEP_STRIDE further on than case i-1's (wrapping)."""
+    def at(base, size, k):
+        room = size - nb
+        return base + ((k * STEP_STRIDE) % (room + 1)) // 4096 * 4096 if room > 0 else base
+    return at(pool, 2 * max_nb, i), at(out, max_nb, i + 1)
 
 
 def _pmc_rows(path: str, counter: str):
@@ -212,7 +233,7 @@ def main():
         profile_odd()
         return
     if args.profile_batch:
-        profile_batch()
+        profile_batch(args.profile_batch)
         return
     if args.profile_access:
         profile_access()
@@ -222,6 +243,18 @@ def main():
         return
     if args.profile_interlace:
         profile_interlace()
+        return
+    if args.side_only:
+        import torch
+        import paper_1011_3583_amd as rr
+        import rr_synth
+        rr.lib()
+        torch.cuda.set_device(0)
+        if args.side_only == "serve":
+            out = bench_serve(rr, rr_synth, torch, args.serve_requests)
+        else:
+            out = bench_batched(rr, rr_synth, torch, torch.cuda.current_stream())
+        print(json.dumps({args.side_only: out}), flush=True)
         return
     if args.gpus != 1:
         print(f"bench.py measures one GPU only; --gpus {args.gpus} is not supported: the library "
@@ -242,7 +275,6 @@ def main():
 
     cases = dense_cases()
     max_nb = max(c[4] for c in cases)
-    # two input regions alternate so a case never re-reads what the previous one touched
     pool = torch.empty(2 * max_nb, dtype=torch.uint8, device=dev)
     g = torch.Generator(device=dev)
     g.manual_seed(1011_3583)
@@ -251,19 +283,23 @@ def main():
     out = torch.empty(max_nb, dtype=torch.uint8, device=dev)
     plans = []
     for i, (name, dims, perm, e, nb) in enumerate(cases):
-        src = pool.data_ptr() + (i % 2) * max_nb
-        d = rr.plan_describe(dims, perm, e, out.data_ptr(), src)
-        plans.append((src, kernel_name(d)))
+        src, dst = step_addresses(pool.data_ptr(), out.data_ptr(), max_nb, i, nb)
+        d = rr.plan_describe(dims, perm, e, dst, src)
+        plans.append((src, kernel_name(d), dst))
+
+    def retag():
+        plans[:] = [(p[0], kernel_name(rr.plan_describe(c[1], c[2], c[3], p[2], p[0])), p[2])
+                    for p, c in zip(plans, cases)]
 
     def step(events=None, only=None):
         """One pass of the 50 permutes; with `events`, a pair of HIP events brackets
         each launch (of kernel `only` alone when given)."""
         for i, (name, dims, perm, e, nb) in enumerate(cases):
-            src = plans[i][0]
+            src, dst = plans[i][0], plans[i][2]
             ev = events is not None and (only is None or plans[i][1] == only)
             if ev:
                 events[i][0].record(stream)
-            st = rr.permute_raw(out.data_ptr(), src, dims, perm, e, sh)
+            st = rr.permute_raw(dst, src, dims, perm, e, sh)
             if st != 0:
                 raise rr.RRError(st, rr.last_error())
             if ev:
@@ -291,8 +327,7 @@ def main():
     cached = bool(args.tune_cache) and os.path.exists(args.tune_cache) and not args.no_tune
     if cached:
         rr.tune_load(args.tune_cache)
-        plans[:] = [(plans[i][0], kernel_name(rr.plan_describe(c[1], c[2], c[3], out.data_ptr(), plans[i][0])))
-                    for i, c in enumerate(cases)]
+        retag()
     elif not args.no_tune:
         rr.tune_clear()
         step()
@@ -305,9 +340,8 @@ def main():
         untuned_ms = a.elapsed_time(b)
         # autotune every case once (runs each candidate tile shape; cached for the timed steps)
         for i, (name, dims, perm, e, nb) in enumerate(cases):
-            rr.tune_permute(out.data_ptr(), plans[i][0], dims, perm, e, sh)
-        plans[:] = [(plans[i][0], kernel_name(rr.plan_describe(c[1], c[2], c[3], out.data_ptr(), plans[i][0])))
-                    for i, c in enumerate(cases)]
+            rr.tune_permute(plans[i][2], plans[i][0], dims, perm, e, sh)
+        retag()
         if args.tune_cache:
             rr.tune_save(args.tune_cache)
     # Warm-up: the first step is instrumented (every launch between HIP events) to
@@ -393,11 +427,44 @@ def main():
         ts = sorted(ts[2:])
         return ts[len(ts) // 2]
 
-    nb = 1 << 30
-    t_d2d = timed(lambda: hip.hipMemcpyAsync(out.data_ptr(), pool.data_ptr(), nb, 3, sh))
-    t_cpy = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), (nb,), (0,), 1, sh)))
-    d2d = 2 * nb / t_d2d / 1e9
-    rrcopy = 2 * nb / t_cpy / 1e9
+    # Ceilings at every per-side size of the step, same protocol (cache flush, HIP
+    # events around one launch, median): hipMemcpyAsync D2D (the runtime's blit
+    # kernel) and the library's own copy kernel.  Each case is compared with the
+    # better of the two at its own size; the step with the time it would take if
+    # every case ran at that ceiling.
+    ceilings = {}
+    for nb in sorted({c[4] for c in cases}):
+        t_d2d = timed(lambda: hip.hipMemcpyAsync(out.data_ptr(), pool.data_ptr(), nb, 3, sh), 5)
+        t_cpy = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), (nb,), (0,), 1, sh)), 5)
+        ceilings[nb] = {"d2d": 2 * nb / t_d2d / 1e9, "rr_copy": 2 * nb / t_cpy / 1e9}
+    best_copy = {nb: max(v.values()) for nb, v in ceilings.items()}
+    step_time_at = lambda key: sum(2 * c[4] / (ceilings[c[4]][key] if key else best_copy[c[4]]) for c in cases)
+    d2d = bytes_per_step / step_time_at("d2d") / 1e9           # the step at D2D speed, size by size
+    rrcopy = bytes_per_step / step_time_at("rr_copy") / 1e9
+    bestc = bytes_per_step / step_time_at(None) / 1e9
+    pct_case = {f"{n} {tuple(p)} e{e}": round(100 * detail[f"{n} {tuple(p)} e{e}"] / best_copy[nb], 1)
+                for n, d, p, e, nb in cases}
+    # the small case: 1024 x 1024 4-byte transpose, 4 MiB per side -- resident in
+    # the caches when repeated back to back (warm), and from a flushed cache (cold)
+    sd, sp, se = rr_synth.SMALL_CASE[1], rr_synth.SMALL_CASE[2], rr_synth.SMALL_CASE[3]
+    snb = 1024 * 1024 * se
+    run_small = lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), sd, sp, se, sh))
+    for _ in range(5):
+        run_small()
+    a, b = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+    a.record(stream)
+    for _ in range(50):
+        run_small()
+    b.record(stream)
+    b.synchronize()
+    t_warm = a.elapsed_time(b) * 1e-3 / 50
+    t_cold = timed(run_small, 7)
+    small_case = {"workload": "2-D 1024x1024 4-byte transpose (1,0), 4 MiB per side",
+                  "warm_cache_resident_GBps": round(2 * snb / t_warm / 1e9, 1),
+                  "cold_GBps": round(2 * snb / t_cold / 1e9, 1),
+                  "note": "cache-resident: 4 MiB per side fits the L2 and the 256 MB Infinity Cache, so the "
+                          "warm figure is not an HBM rate; cold = after a 512 MiB flush, HIP events around one "
+                          "launch (launch overhead included)"}
 
     result = {
         "metric": METRIC,
@@ -420,6 +487,8 @@ def main():
             "bytes_per_side_per_step": bytes_per_step // 2,
         },
         "pct_of_d2d_memcpy": round(100 * value / d2d, 1),
+        "pct_of_best_copy": round(100 * value / bestc, 1),
+        "pct_of_rr_copy": round(100 * value / rrcopy, 1),
         "pct_of_hbm_peak": round(100 * value / HBM_PEAK_GBPS, 1),
         "kernel_only_GBps": round(bytes_per_step / (kernel_time_ms * 1e-3) / 1e9, 1),
         "instrumentation": "timed steps: HIP events around the dominant kernel's launches only; "
@@ -427,8 +496,19 @@ def main():
                            "launch between events",
         "autotuned": not args.no_tune,
         "untuned_step_GBps": round(bytes_per_step / (untuned_ms * 1e-3) / 1e9, 1) if untuned_ms else None,
-        "ceilings_GBps": {"d2d_hipMemcpyAsync_1GiB": round(d2d, 1), "rr_copy_1GiB": round(rrcopy, 1),
-                          "hbm_peak": HBM_PEAK_GBPS},
+        "ceilings_GBps": {"step_at_d2d_hipMemcpyAsync": round(d2d, 1), "step_at_rr_copy": round(rrcopy, 1),
+                          "step_at_best_copy": round(bestc, 1), "hbm_peak": HBM_PEAK_GBPS,
+                          "by_bytes_per_side": {str(nb): {k: round(v, 1) for k, v in c.items()}
+                                                for nb, c in sorted(ceilings.items())},
+                          "protocol": "512 MiB cache-flush write before each run, HIP events around one "
+                                      "launch, median of 5; per size, hipMemcpyAsync D2D and the library's "
+                                      "copy kernel; step_at_x = step bytes / (sum over cases of 2 * bytes / "
+                                      "ceiling at the case's size)"},
+        "pct_of_best_copy_by_case": pct_case,
+        "small_case": small_case,
+        "cache_state": "timed steps: each case reads and writes lines 768 MiB away from the launches just "
+                       "before it (no input or output of a case is in the 256 MB Infinity Cache when it "
+                       "starts); no flush inside the timed region",
         "roofline": {"bound": "hbm", "kernel": dom, "achieved": round(achieved, 1),
                      "peak": HBM_PEAK_GBPS, "unit": "GB/s", "frac": round(achieved / HBM_PEAK_GBPS, 4),
                      "traffic": traffic, "launches": dk["launches"],
@@ -462,7 +542,7 @@ def main():
         except Exception as ex:
             side["stencil"] = {"error": str(ex)}
         try:
-            side["paper_tables"] = bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d)
+            side["paper_tables"] = bench_paper_tables(rr, rr_synth, pool, out, stream, timed)
         except Exception as ex:
             side["paper_tables"] = {"error": str(ex)}
         del pool, out, flush
@@ -551,15 +631,22 @@ PAPER_TABLE3 = {4: (70.93, 68.87), 5: (73.95, 68.50), 6: (71.51, 67.61), 7: (72.
                 9: (70.60, 58.25)}
 
 
-def bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d):
+def bench_paper_tables(rr, rr_synth, pool, out, stream, timed):
     """The paper's Table 1-3 workloads (4-byte elements, its fastest-first order
-    notation), as % of this box's measured D2D copy next to the paper's % of its
-    memcpy."""
+    notation), as % of this box's hipMemcpyAsync D2D copy of the same bytes (same
+    protocol) next to the paper's % of its memcpy."""
+    import ctypes
     sh = stream.cuda_stream
     res = {}
+    hip = ctypes.CDLL("libamdhip64.so")
+    hip.hipMemcpyAsync.argtypes = [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_size_t, ctypes.c_int, ctypes.c_void_p]
+    d2d_at = {}
 
-    def row(gbps, paper):
-        return {"GBps": round(gbps, 1), "pct_of_d2d": round(100 * gbps / d2d, 1),
+    def row(gbps, paper, nb):
+        if nb not in d2d_at:
+            d2d_at[nb] = 2 * nb / timed(lambda: hip.hipMemcpyAsync(out.data_ptr(), pool.data_ptr(), nb, 3, sh), 5) / 1e9
+        return {"GBps": round(gbps, 1), "pct_of_d2d": round(100 * gbps / d2d_at[nb], 1),
+                "d2d_GBps_same_bytes": round(d2d_at[nb], 1),
                 "paper_GBps_C1060": paper, "paper_pct_of_memcpy": round(100 * paper / PAPER_MEMCPY_GBPS, 1)}
 
     sizes = rr_synth.PAPER_TABLE1_SIZES
@@ -568,7 +655,7 @@ def bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d):
         perm = rr.order_to_perm(order)
         nb = 4 * sizes[0] * sizes[1] * sizes[2]
         t = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), dims, perm, 4, sh)), 5)
-        res[f"table1_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, paper)
+        res[f"table1_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, paper, nb)
     for sz, order in rr_synth.PAPER_TABLE2:
         dims = tuple(reversed(sz))
         perm = rr.order_to_perm(order)
@@ -576,14 +663,14 @@ def bench_paper_tables(rr, rr_synth, pool, out, stream, timed, d2d):
         for d in sz:
             nb *= d
         t = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), dims, perm, 4, sh)), 5)
-        res[f"table2_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, PAPER_TABLE2[tuple(order)])
+        res[f"table2_{''.join(map(str, order))}"] = row(2 * nb / t / 1e9, PAPER_TABLE2[tuple(order)], nb)
     count = 1 << 24
     for n, (pi, pd) in PAPER_TABLE3.items():
         planes = [pool.data_ptr() + c * count * 4 for c in range(n)]
         ti = timed(lambda: rr.check(rr.interlace_raw(out.data_ptr(), planes, count, 4, sh)), 5)
         td = timed(lambda: rr.check(rr.deinterlace_raw(planes, out.data_ptr(), count, 4, sh)), 5)
-        res[f"table3_interlace_{n}"] = row(2 * n * count * 4 / ti / 1e9, pi)
-        res[f"table3_deinterlace_{n}"] = row(2 * n * count * 4 / td / 1e9, pd)
+        res[f"table3_interlace_{n}"] = row(2 * n * count * 4 / ti / 1e9, pi, n * count * 4)
+        res[f"table3_deinterlace_{n}"] = row(2 * n * count * 4 / td / 1e9, pd, n * count * 4)
     return res
 
 
@@ -726,9 +813,11 @@ def profile_interlace():
                               "flags": int(d["flags"])}), flush=True)
 
 
-def profile_batch():
-    """The batch bench's tuned, graph-replayed handle, replayed three times from cold
-    caches; one JSON line per replay (wall time) and one with the handle's choices."""
+def profile_batch(mode: str = "graph"):
+    """The batch bench's tuned handle (graph-replayed, groups side by side; or with
+    its groups one after another on one stream), replayed three times from cold
+    caches; one JSON line with the handle's choices and groups (in storage order,
+    which is the launch order of a serial handle), one per replay (wall time)."""
     import torch
     import rr_synth
     import paper_1011_3583_amd as rr
@@ -738,8 +827,9 @@ def profile_batch():
     stream = torch.cuda.Stream()
     jobs = rr.make_jobs([(dst.data_ptr() + o, src.data_ptr() + o, s["dims"], s["perm"], s["esize"])
                          for o, s in zip(offs, specs)])
-    b = rr.Batch(jobs, rr.RR_BATCH_TUNE | rr.RR_BATCH_GRAPH)
-    print(json.dumps({"batch": b.info()}), flush=True)
+    flags = rr.RR_BATCH_TUNE | (rr.RR_BATCH_GRAPH if mode == "graph" else rr.RR_BATCH_SERIAL)
+    b = rr.Batch(jobs, flags)
+    print(json.dumps({"mode": mode, "batch": b.info(), "groups": b.groups()}), flush=True)
     flush = torch.empty(512 << 20, dtype=torch.uint8, device="cuda")
     for i in range(3):
         flush.fill_(i)
@@ -860,6 +950,13 @@ def _serve_run(rr, rr_synth, torch, rate, nreq, direct, small_specs, large_specs
     finally:
         srv.close()
     lat_us = np.array([(lat[i][1] - sched[i]) / 1e3 for i in range(nreq)])
+    # where the time goes: client lag (scheduled arrival -> submit), submit -> admit
+    # (queued for memory or a slot), admit -> launch (waiting to join a batch),
+    # launch -> done (on the device, including the wait behind earlier batches)
+    parts = {"client_lag": [(lat[i][0] - sched[i]) / 1e3 for i in range(nreq)],
+             "submit_to_admit": [(lat[i][2] - lat[i][0]) / 1e3 for i in range(nreq)],
+             "admit_to_launch": [(lat[i][3] - lat[i][2]) / 1e3 for i in range(nreq)],
+             "launch_to_done": [(lat[i][1] - lat[i][3]) / 1e3 for i in range(nreq)]}
     small_mask = ~is_large
     moved = sum(nbytes_large[pick_l[i]] if is_large[i] else nbytes_small[pick_s[i]] for i in range(nreq))
     span = (t_end - sched[0]) / 1e9
@@ -869,7 +966,9 @@ def _serve_run(rr, rr_synth, torch, rate, nreq, direct, small_specs, large_specs
             "large_p50_us": pct(lat_us[is_large], 50) if is_large.any() else None,
             "aggregate_GBps": round(2 * moved / span / 1e9, 1), "offered_GBps": round(2 * moved / (arrivals[-1]) / 1e9, 1),
             "requests": nreq, "large_requests": int(is_large.sum()), "batches": stats["batches"],
-            "budget_peak_GiB": round(stats["budget_peak"] / 2**30, 2), "busy_retries": busy}
+            "budget_peak_GiB": round(stats["budget_peak"] / 2**30, 2),
+            "reserved_peak_GiB": round(stats["reserved"] / 2**30, 2), "busy_retries": busy,
+            "breakdown_us": {k: {"p50": pct(np.array(v), 50), "p99": pct(np.array(v), 99)} for k, v in parts.items()}}
 
 
 def _drain(srv, lat, tick_of):
@@ -877,21 +976,45 @@ def _drain(srv, lat, tick_of):
         r = srv.poll(t)
         if r.status != 0:
             raise RuntimeError(f"served job failed with status {r.status}")
-        lat[tick_of.pop(t)] = (r.t_submit_ns, r.t_done_ns)
+        lat[tick_of.pop(t)] = (r.t_submit_ns, r.t_done_ns, r.t_admit_ns, r.t_launch_ns)
         srv.release(t)
+
+
+SERVE_RATES = (5_000, 20_000, 50_000, 100_000, 200_000, 400_000)
+SERVE_P99_BOUNDS_US = (1_000, 5_000)
+
+
+def _serve_requests(rate, nreq_cap):
+    """Requests at one arrival rate: about two seconds of arrivals, 10k..nreq_cap."""
+    return int(max(10_000, min(nreq_cap, rate * 2)))
 
 
 def bench_serve(rr, rr_synth, torch, nreq):
     """Config: Poisson arrivals of batched-workload jobs plus 1% large 1-4 GiB transposes,
-    served by the continuous-batching server vs one rr_permute launch per request."""
+    served by the continuous-batching server vs one rr_permute launch per request, over
+    a sweep of arrival rates; per mode, the highest rate of the sweep whose p99 latency
+    stays within 1 ms and within 5 ms (all requests, and the small requests alone),
+    with the aggregate GB/s served there."""
     small_specs = rr_synth.sample_jobs(5_0001, njobs=4096)
     large_specs = rr_synth.large_jobs(5_0002, count=4)
-    res = {"large_job_shapes": [(s["dims"], s["perm"], s["esize"]) for s in large_specs]}
-    for rate in (5_000, 20_000, 50_000):
+    res = {"large_job_shapes": [(s["dims"], s["perm"], s["esize"]) for s in large_specs],
+           "rates_per_s": list(SERVE_RATES)}
+    for rate in SERVE_RATES:
+        n = _serve_requests(rate, nreq)
         res[f"{rate}_per_s"] = {
-            "batched": _serve_run(rr, rr_synth, torch, rate, nreq, False, small_specs, large_specs),
-            "per_request": _serve_run(rr, rr_synth, torch, rate, nreq, True, small_specs, large_specs),
+            "batched": _serve_run(rr, rr_synth, torch, rate, n, False, small_specs, large_specs),
+            "per_request": _serve_run(rr, rr_synth, torch, rate, n, True, small_specs, large_specs),
         }
+    best = {}
+    for mode in ("batched", "per_request"):
+        for key, label in (("p99_us", "all"), ("small_p99_us", "small")):
+            for bound in SERVE_P99_BOUNDS_US:
+                ok = [r for r in SERVE_RATES if res[f"{r}_per_s"][mode][key] <= bound]
+                top = max(ok) if ok else None
+                best[f"{mode}_{label}_p99_le_{bound}us"] = (
+                    {"rate_per_s": top, "aggregate_GBps": res[f"{top}_per_s"][mode]["aggregate_GBps"],
+                     "p99_us": res[f"{top}_per_s"][mode][key]} if top else None)
+    res["highest_rate_within_p99"] = best
     # beyond what one launch per request sustains: arrivals at 1M/s (a burst)
     nsat = min(nreq, 20_000)
     res["saturated_1M_per_s"] = {
@@ -933,7 +1056,12 @@ def cpu_baseline():
     import multiprocessing as mp
     s0, s1, b1 = _oracle_timed(CPU_SAMPLE, 100)
     t1 = s1 - s0
-    ncores = max(1, min(os.cpu_count() or 1, int(os.environ.get("OMP_NUM_THREADS") or 16)))
+    # every core this process may run on, up to the host's CPU share for one GPU
+    # (OMP_NUM_THREADS, which the GPU hosts set to that share): more processes than
+    # the share would only time-slice the same cores
+    affinity = len(os.sched_getaffinity(0))
+    share = int(os.environ.get("OMP_NUM_THREADS") or affinity)
+    ncores = max(1, min(affinity, share))
     ctx = mp.get_context("fork")
     barrier = ctx.Barrier(ncores)
     q = ctx.Queue()
@@ -951,7 +1079,15 @@ def cpu_baseline():
     bn = sum(r[2] for r in res)
     tn = max(r[1] for r in res) - min(r[0] for r in res)
     names = "; ".join(f"{n} {p} e{e}" for n, _, p, e in CPU_SAMPLE)
+    model = None
+    try:
+        with open("/proc/cpuinfo") as fh:
+            model = next((l.split(":", 1)[1].strip() for l in fh if l.startswith("model name")), None)
+    except OSError:
+        pass
     return {"value": round(bn / tn / 1e9, 3), "unit": "GB/s", "cores": ncores, "kind": "oracle",
+            "host": {"cpu_model": model, "nproc": os.cpu_count(), "affinity_cpus": affinity,
+                     "cpu_share_OMP_NUM_THREADS": os.environ.get("OMP_NUM_THREADS")},
             "sample": f"{ncores} processes, each running [{names}] from case k mod 6 "
                       f"({bn / 2 / 2**30:.2f} GiB per side in {tn:.1f} s wall)",
             "single_thread": {"value": round(b1 / t1 / 1e9, 3), "unit": "GB/s", "cores": 1,

@@ -213,10 +213,17 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
  *          RR_BATCH_TUNE       rr_batch_create times candidate tile shapes and
  *                              grid modes (running the batch, so it writes the
  *                              job outputs) on the current device and keeps the
- *                              fastest; needs the job buffers to be valid;
+ *                              fastest; needs the job buffers to be valid; it
+ *                              first waits for all work queued on the device
+ *                              (hipDeviceSynchronize), so the candidates never
+ *                              overlap work that still uses the job buffers;
  *          RR_BATCH_PERSISTENT persistent grids (a few workgroups per CU that
  *                              loop over the group's work) instead of one
- *                              workgroup per block of work.
+ *                              workgroup per block of work;
+ *          RR_BATCH_SERIAL     the groups run one after another on the
+ *                              launch stream alone (no side streams), in the
+ *                              order rr_batch_describe lists them: each group's
+ *                              kernel time can then be read on its own.
  * Jobs are planned like rr_permute (the tile override if one is set, else the
  * built-in shapes and the tuning cache).  The handle's device is the current
  * HIP device at creation.  A launch runs its groups side by side on `stream`
@@ -232,6 +239,7 @@ typedef struct rr_batch rr_batch;
 #define RR_BATCH_GRAPH 1
 #define RR_BATCH_TUNE 2
 #define RR_BATCH_PERSISTENT 4
+#define RR_BATCH_SERIAL 8
 
 typedef struct {
     int32_t njobs;             /* jobs with a non-empty problem                */
@@ -248,6 +256,12 @@ typedef struct {
 rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** out);
 rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream);
 rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out);
+/* One text line per kernel group of the batch as currently planned, in the order
+ * the groups are stored (and launched under RR_BATCH_SERIAL):
+ *   "kernel=k_batch_tile<8,1> jobs=622 workgroups=194744 bytes=2179800000 lds=16384"
+ * (bytes per side moved by the group).  Host only.  Errors: RR_ERR_INVALID_ARG
+ * (NULL argument, or buf shorter than the text; buflen counts the final NUL). */
+rr_status rr_batch_describe(const rr_batch* b, char* buf, int buflen);
 rr_status rr_batch_destroy(rr_batch* b);
 
 /* -------------------------------------------------------------------------
@@ -260,6 +274,15 @@ rr_status rr_batch_destroy(rr_batch* b);
  * (each range rewrites a disjoint part of the output), at most one range per
  * batch, so small jobs keep flowing past it.  Results are identical to
  * rr_permute run alone.
+ * Jobs are validated and planned by rr_serve_submit on the calling thread.  When
+ * the server has nothing queued and a slot is free, rr_serve_submit also admits
+ * and launches a job that needs no chunking itself (on the server's streams and
+ * device).  The budget caps the device memory the server reserves (slabs of its
+ * arena, up to 256 MiB each, kept for reuse and given back when a job would
+ * otherwise not fit), not only the bytes handed out.  A job whose output the
+ * device refuses to allocate within the budget while no batch is in flight
+ * completes with RR_ERR_NO_MEMORY; rr_serve_destroy fails every job still
+ * waiting for memory once nothing is in flight.
  */
 typedef struct rr_server rr_server;
 
@@ -280,6 +303,8 @@ typedef struct {
     uint32_t tick_us;           /* longest idle wait of the server thread            */
     uint32_t flags;             /* RR_SERVE_SIMULATED                                */
     double sim_bytes_per_us;    /* simulated read+write bandwidth (simulated mode)   */
+    uint64_t sim_device_bytes;  /* simulated device memory, 0 = unlimited: a
+                                   reservation past it fails as hipMalloc would     */
 } rr_serve_config;
 
 typedef struct {
@@ -316,6 +341,7 @@ rr_status rr_serve_destroy(rr_server* s);
 /* Counters since creation. */
 typedef struct {
     uint64_t submitted, completed, failed, batches, chunks, bytes_moved, budget_peak, budget_used;
+    uint64_t reserved;   /* device memory the server holds (arena slabs), <= the budget */
 } rr_serve_stats;
 rr_status rr_serve_get_stats(rr_server* s, rr_serve_stats* out);
 /* Failure-handling hook: the next batch the server forms is not launched and
@@ -398,13 +424,26 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags);
  */
 rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* dims, const int* perm,
                           int elem_size, rr_stream_t stream, double* best_us, double* default_us);
-/* Persist / restore / forget the tuning cache (one text line per key). */
+/* Persist / restore / forget the tuning cache (one text line per key).  Every
+ * key starts with the process's tuning context, "<gcnArchName>@hip<runtime
+ * version>|" (the device current at the first tuning-cache call and the HIP
+ * runtime loaded): a shape was timed on one device and runtime, so rr_tune_load
+ * skips lines of another context (RR_LOG=1 reports how many) and stores the
+ * others; a malformed line fails the whole load (RR_ERR_INVALID_ARG) and stores
+ * nothing. */
 rr_status rr_tune_save(const char* path);
 rr_status rr_tune_load(const char* path);
 rr_status rr_tune_clear(void);
+/* The tuning context of this process as a NUL-terminated string (for building
+ * or checking tuning files).  Errors: RR_ERR_INVALID_ARG (NULL or short buffer). */
+rr_status rr_tune_context(char* buf, int buflen);
 
 const char* rr_status_string(rr_status s);
-/* Detail of the last error on the calling thread ("" if none). */
+/* Detail of the last error on the calling thread ("" if none).  With the
+ * environment variable RR_LOG set, the library also writes diagnostics to stderr:
+ * 1 every error a call returns, 2 also the plan of every single launch and the
+ * kernel groups of every batch handle, 3 also the server's admission and batch
+ * events. */
 const char* rr_last_error(void);
 /* Library version string. */
 const char* rr_version(void);

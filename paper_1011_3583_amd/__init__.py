@@ -27,12 +27,12 @@ RR_OK, RR_ERR_NOT_READY = 0, 7
 
 EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_stencil2d", "rr_interlace", "rr_deinterlace",
            "rr_permute_batched",
-           "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_destroy",
+           "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_describe", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
            "rr_serve_get_stats", "rr_serve_fail_next_batch",
            "rr_order_to_perm", "rr_plan_describe", "rr_reorder_describe", "rr_set_tile_override",
-           "rr_tune_permute", "rr_tune_save", "rr_tune_load", "rr_tune_clear",
+           "rr_tune_permute", "rr_tune_save", "rr_tune_load", "rr_tune_clear", "rr_tune_context",
            "rr_status_string", "rr_last_error", "rr_version")
 
 
@@ -53,7 +53,7 @@ class ServeConfig(ctypes.Structure):
                 ("max_batch_jobs", ctypes.c_int32), ("queue_capacity", ctypes.c_int32),
                 ("hbm_budget_bytes", ctypes.c_uint64), ("chunk_bytes", ctypes.c_uint64),
                 ("tick_us", ctypes.c_uint32), ("flags", ctypes.c_uint32),
-                ("sim_bytes_per_us", ctypes.c_double)]
+                ("sim_bytes_per_us", ctypes.c_double), ("sim_device_bytes", ctypes.c_uint64)]
 
 
 RR_SERVE_SIMULATED, RR_SERVE_DIRECT = 1, 2
@@ -71,12 +71,12 @@ class BatchInfo(ctypes.Structure):
                 ("persistent", ctypes.c_int32), ("bytes", ctypes.c_uint64), ("tuned_us", ctypes.c_double)]
 
 
-RR_BATCH_GRAPH, RR_BATCH_TUNE, RR_BATCH_PERSISTENT = 1, 2, 4
+RR_BATCH_GRAPH, RR_BATCH_TUNE, RR_BATCH_PERSISTENT, RR_BATCH_SERIAL = 1, 2, 4, 8
 
 
 class ServeStats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_uint64) for n in ("submitted", "completed", "failed", "batches", "chunks",
-                                               "bytes_moved", "budget_peak", "budget_used")]
+                                               "bytes_moved", "budget_peak", "budget_used", "reserved")]
 
 
 _lib = None
@@ -99,6 +99,7 @@ def lib() -> ctypes.CDLL:
     L.rr_batch_create.argtypes = [ctypes.POINTER(Job), i32, i32, ctypes.POINTER(vp)]
     L.rr_batch_launch.argtypes = [vp, vp]
     L.rr_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
+    L.rr_batch_describe.argtypes = [vp, ctypes.c_char_p, i32]
     L.rr_batch_destroy.argtypes = [vp]
     L.rr_serve_create.argtypes = [ctypes.POINTER(ServeConfig), ctypes.POINTER(vp)]
     L.rr_serve_alloc.argtypes = [vp, ctypes.c_uint64, ctypes.POINTER(vp)]
@@ -118,6 +119,7 @@ def lib() -> ctypes.CDLL:
     L.rr_stencil2d.argtypes = [vp, vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
     L.rr_reorder_describe.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
+    L.rr_tune_context.argtypes = [ctypes.c_char_p, i32]
     L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
                                   ctypes.POINTER(ctypes.c_double)]
     L.rr_tune_save.argtypes = [ctypes.c_char_p]
@@ -260,6 +262,17 @@ class Batch:
         check(lib().rr_batch_get_info(self.h, ctypes.byref(i)))
         return {n: getattr(i, n) for n, _ in BatchInfo._fields_}
 
+    def groups(self) -> list:
+        """One dict per kernel group (kernel, jobs, workgroups, bytes per side, lds),
+        in storage order (the launch order under RR_BATCH_SERIAL)."""
+        buf = ctypes.create_string_buffer(1 << 16)
+        check(lib().rr_batch_describe(self.h, buf, len(buf)))
+        out = []
+        for line in buf.value.decode().splitlines():
+            d = dict(kv.split("=", 1) for kv in line.split())
+            out.append({k: (v if k == "kernel" else int(v)) for k, v in d.items()})
+        return out
+
     def close(self):
         if self.h:
             check(lib().rr_batch_destroy(self.h))
@@ -338,6 +351,13 @@ def tune_load(path: str):
     check(lib().rr_tune_load(path.encode()))
 
 
+def tune_context() -> str:
+    """The prefix of this process's tuning-cache keys ("<arch>@hip<version>")."""
+    buf = ctypes.create_string_buffer(256)
+    check(lib().rr_tune_context(buf, len(buf)))
+    return buf.value.decode()
+
+
 def tune_clear():
     check(lib().rr_tune_clear())
 
@@ -383,10 +403,10 @@ class Server:
     def __init__(self, hbm_budget_bytes: int, max_inflight: int = 4, max_batch_jobs: int = 1024,
                  queue_capacity: int = 1 << 16, chunk_bytes: int = 64 << 20, tick_us: int = 20,
                  device: int = 0, simulated: bool = False, sim_bytes_per_us: float = 0.0,
-                 direct: bool = False):
+                 direct: bool = False, sim_device_bytes: int = 0):
         flags = (RR_SERVE_SIMULATED if simulated else 0) | (RR_SERVE_DIRECT if direct else 0)
         cfg = ServeConfig(device, max_inflight, max_batch_jobs, queue_capacity, hbm_budget_bytes,
-                          chunk_bytes, tick_us, flags, float(sim_bytes_per_us))
+                          chunk_bytes, tick_us, flags, float(sim_bytes_per_us), int(sim_device_bytes))
         h = ctypes.c_void_p()
         check(lib().rr_serve_create(ctypes.byref(cfg), ctypes.byref(h)))
         self.h = h

@@ -3,7 +3,9 @@
 
 #include <algorithm>
 #include <cstdio>
+#include <cstdlib>
 #include <cstring>
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -15,9 +17,41 @@ namespace rr {
 
 static thread_local std::string g_last_error;
 
+int log_level() {
+    static const int level = [] {
+        const char* v = std::getenv("RR_LOG");
+        return v ? std::max(0, std::min(3, std::atoi(v))) : 0;
+    }();
+    return level;
+}
+
+void log_line(int level, const std::string& msg) {
+    if (log_level() < level) return;
+    static std::mutex mu;   // whole lines from concurrent callers
+    std::lock_guard<std::mutex> lk(mu);
+    std::fprintf(stderr, "[rr] %s\n", msg.c_str());
+}
+
 rr_status fail(rr_status s, const std::string& why) {
     g_last_error = why;
+    if (log_level() >= 1) log_line(1, std::string("error ") + rr_status_string(s) + ": " + why);
     return s;
+}
+
+void ensure_tune_context() {
+    static std::once_flag once;
+    std::call_once(once, [] {
+        std::string arch = "nodevice";
+        int dev = 0;
+        hipDeviceProp_t prop;
+        if (hipGetDevice(&dev) == hipSuccess && hipGetDeviceProperties(&prop, dev) == hipSuccess)
+            arch = prop.gcnArchName;
+        (void)hipGetLastError();   // a host without a GPU leaves an error behind
+        int ver = 0;
+        if (hipRuntimeGetVersion(&ver) != hipSuccess) ver = HIP_VERSION;
+        (void)hipGetLastError();
+        tune_set_context(arch + "@hip" + std::to_string(ver));
+    });
 }
 
 void clear_error() { g_last_error.clear(); }
@@ -62,6 +96,7 @@ rr_status rr_permute(void* dst, const void* src, int ndim, const int64_t* dims, 
     std::string why;
     st = plan_permute((uint64_t)dst, (uint64_t)src, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
+    if (log_level() >= 2) log_line(2, "rr_permute " + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_permute launch");
     return RR_OK;
@@ -94,6 +129,7 @@ rr_status rr_reorder(void* dst, const void* src, int ndim, const int64_t* dims, 
     std::string why;
     st = plan_permute((uint64_t)dst, (uint64_t)src + off, c, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
+    if (log_level() >= 2) log_line(2, std::string("rr_reorder ") + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_reorder launch");
     return RR_OK;
@@ -135,6 +171,7 @@ rr_status rr_gather(void* dst, const void* src, int64_t src_count, const int64_t
         return fail(RR_ERR_ALIAS, "destination overlaps the source, the indices or the counter");
     Plan p;
     plan_gather((uint64_t)dst, (uint64_t)src, (uint64_t)idx, (uint64_t)bad_count, count, src_count, 0, 0, elem_size, &p);
+    if (log_level() >= 2) log_line(2, std::string("rr_gather ") + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_gather launch");
     return RR_OK;
@@ -161,6 +198,7 @@ rr_status rr_copy_range(void* dst, const void* src, int64_t src_count, int64_t s
     Plan p;
     if (stride == 1) plan_copy((uint64_t)dst, (uint64_t)src + start * elem_size, (uint64_t)out_bytes, &p);
     else plan_gather((uint64_t)dst, (uint64_t)src, 0, 0, count, src_count, start, stride, elem_size, &p);
+    if (log_level() >= 2) log_line(2, std::string("rr_copy_range ") + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, "rr_copy_range launch");
     return RR_OK;
@@ -225,6 +263,7 @@ static rr_status interlace_common(void* flat, const void* const* planes, int n, 
     std::string why;
     rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, current_tile_options(), &p, &why);
     if (st != RR_OK) return fail(st, why);
+    if (log_level() >= 2) log_line(2, std::string("interlace_common ") + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, de ? "rr_deinterlace launch" : "rr_interlace launch");
     return RR_OK;
@@ -304,6 +343,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
 rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* dims, const int* perm,
                           int elem_size, rr_stream_t stream, double* best_us, double* default_us) {
     clear_error();
+    ensure_tune_context();
     Canon c;
     rr_status st = validate_permute(dst, src, ndim, dims, perm, elem_size, &c);
     if (st != RR_OK) return st;
@@ -403,6 +443,7 @@ rr_status rr_tune_save(const char* path) {
     if (!path) return fail(RR_ERR_INVALID_ARG, "NULL path");
     FILE* f = std::fopen(path, "w");
     if (!f) return fail(RR_ERR_INVALID_ARG, std::string("cannot write ") + path);
+    ensure_tune_context();
     const std::string s = tune_dump();
     std::fwrite(s.data(), 1, s.size(), f);
     std::fclose(f);
@@ -419,7 +460,22 @@ rr_status rr_tune_load(const char* path) {
     size_t n;
     while ((n = std::fread(buf, 1, sizeof buf, f)) > 0) s.append(buf, n);
     std::fclose(f);
-    if (tune_parse(s) < 0) return fail(RR_ERR_INVALID_ARG, "malformed tuning file");
+    ensure_tune_context();
+    int skipped = 0;
+    if (tune_parse(s, &skipped) < 0) return fail(RR_ERR_INVALID_ARG, "malformed tuning file");
+    if (skipped && log_level() >= 1)
+        log_line(1, std::string(path) + ": " + std::to_string(skipped) + " tuned shapes of another device or HIP "
+                    "version skipped (this process: " + tune_context() + ")");
+    return RR_OK;
+}
+
+rr_status rr_tune_context(char* buf, int buflen) {
+    clear_error();
+    if (!buf || buflen < 1) return fail(RR_ERR_INVALID_ARG, "NULL buffer");
+    ensure_tune_context();
+    const std::string c = tune_context();
+    if ((int)c.size() + 1 > buflen) return fail(RR_ERR_INVALID_ARG, "buffer too short");
+    std::memcpy(buf, c.c_str(), c.size() + 1);
     return RR_OK;
 }
 

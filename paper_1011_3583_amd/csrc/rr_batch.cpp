@@ -167,6 +167,9 @@ struct rr_batch {
 
 namespace {
 
+// Side streams of a handle, or none when its groups run one after another.
+GroupFanout* fan_of(rr_batch* b) { return (b->flags & RR_BATCH_SERIAL) ? nullptr : &b->fan; }
+
 rr_status upload_table(rr_batch* b) {
     const size_t need = std::max<size_t>(b->plan.table.size(), 256);
     if (need > b->dev_cap) {
@@ -200,7 +203,7 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
     rr_status rs = RR_OK;
     for (int r = 0; r < 4 && rs == RR_OK; ++r) {
         (void)hipEventRecord(e0, st);
-        rs = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st, &b->fan);
+        rs = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, st, fan_of(b));
         (void)hipEventRecord(e1, st);
         (void)hipEventSynchronize(e1);
         float ms = 0;
@@ -226,6 +229,10 @@ rr_status tune(rr_batch* b) {
                           {0, 0, 0, false, 0, 1}, {512, 512, 0, false, 32, 0},
                           {0, 0, 0, false, 0, 0, 0}, {0, 0, 0, false, 0, 0, 1}, {0, 0, 0, false, 0, 0, 2},
                           {0, 0, 0, false, 0, 0, -1, 0}, {512, 256, 1, false, 0, 0, -1, 0}};
+    // the candidates run the batch on a stream of their own: let whatever the
+    // caller has queued on the device finish first
+    hipError_t se = hipDeviceSynchronize();
+    if (se != hipSuccess) return hip_fail(se, "hipDeviceSynchronize before tuning");
     hipStream_t st;
     if (hipStreamCreateWithFlags(&st, hipStreamNonBlocking) != hipSuccess) return fail(RR_ERR_HIP, "stream");
     double best = 1e300;
@@ -328,7 +335,7 @@ rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** o
     clear_error();
     if (!out) return fail(RR_ERR_INVALID_ARG, "out is NULL");
     *out = nullptr;
-    if (flags & ~(RR_BATCH_GRAPH | RR_BATCH_TUNE | RR_BATCH_PERSISTENT))
+    if (flags & ~(RR_BATCH_GRAPH | RR_BATCH_TUNE | RR_BATCH_PERSISTENT | RR_BATCH_SERIAL))
         return fail(RR_ERR_INVALID_ARG, "unknown flags");
     rr_batch* b = new rr_batch();
     b->flags = flags;
@@ -357,14 +364,14 @@ rr_status rr_batch_launch(rr_batch* b, rr_stream_t stream) {
     if (b->plan.groups.empty()) return RR_OK;
     hipStream_t hs = (hipStream_t)stream;
     if (!(b->flags & RR_BATCH_GRAPH))
-        return launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs, &b->fan);
+        return launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, hs, fan_of(b));
     if (!b->exec) {
         if (!b->cap_stream && hipStreamCreateWithFlags(&b->cap_stream, hipStreamNonBlocking) != hipSuccess)
             return fail(RR_ERR_HIP, "capture stream");
         hipError_t e = hipStreamBeginCapture(b->cap_stream, hipStreamCaptureModeThreadLocal);
         if (e != hipSuccess) return hip_fail(e, "hipStreamBeginCapture");
         rr_status st = launch_batch_plan(b->plan, (const uint8_t*)b->dev_table, b->persistent, b->device, b->cap_stream,
-                                         &b->fan);
+                                         fan_of(b));
         hipGraph_t g = nullptr;
         e = hipStreamEndCapture(b->cap_stream, &g);
         if (st != RR_OK) { if (g) (void)hipGraphDestroy(g); return st; }
@@ -390,6 +397,23 @@ rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out) {
     out->persistent = b->persistent ? 1 : 0;
     out->bytes = b->plan.bytes;
     out->tuned_us = b->tuned_us;
+    return RR_OK;
+}
+
+rr_status rr_batch_describe(const rr_batch* b, char* buf, int buflen) {
+    clear_error();
+    if (!b || !buf || buflen < 1) return fail(RR_ERR_INVALID_ARG, "NULL argument");
+    std::string text;
+    for (const BatchGroup& g : b->plan.groups) {
+        std::string k;
+        if (g.kind == K_COPY) k = "k_batch_copy<" + std::to_string(g.variant) + ">";
+        else if (g.kind == K_RUN) k = "k_batch_run<" + std::to_string(g.variant) + ">";
+        else k = "k_batch_tile<" + std::to_string(g.variant / 100) + "," + std::to_string(g.variant % 100) + ">";
+        text += "kernel=" + k + " jobs=" + std::to_string(g.njobs) + " workgroups=" + std::to_string(g.total_blocks) +
+                " bytes=" + std::to_string(g.bytes) + " lds=" + std::to_string(g.lds_bytes) + "\n";
+    }
+    if ((int)text.size() + 1 > buflen) return fail(RR_ERR_INVALID_ARG, "buffer too short");
+    std::memcpy(buf, text.c_str(), text.size() + 1);
     return RR_OK;
 }
 

@@ -229,11 +229,45 @@ RR_HD void sload(const uint8_t* p, uint32_t (&w)[NWords<W>::value]) { vload_t<W,
 template <int W>
 RR_HD void sstore(uint8_t* p, const uint32_t (&w)[NWords<W>::value]) { vstore_t<W, false, false>(p, w); }
 
+// Byte permute of two words (gfx950 v_perm_b32): the eight bytes hi:lo are
+// numbered 0..3 (lo) and 4..7 (hi); byte k of the result is the byte that
+// selector byte k names.  Selector bytes here are 0..7, or 12 for a zero byte.
+RR_HD uint32_t perm_b32(uint32_t hi, uint32_t lo, uint32_t sel) {
+#if defined(__HIP_DEVICE_COMPILE__)
+    return __builtin_amdgcn_perm(hi, lo, sel);
+#else
+    const uint64_t v = ((uint64_t)hi << 32) | lo;
+    uint32_t out = 0;
+    for (int k = 0; k < 4; ++k) {
+        const uint32_t s = (sel >> (8 * k)) & 0xffu;
+        const uint32_t byte = s < 8 ? (uint32_t)(v >> (8 * s)) & 0xffu : 0u;
+        out |= byte << (8 * k);
+    }
+    return out;
+#endif
+}
+
+// 4x4 byte transpose of the words a, b, c, d: result word k holds byte k of a,
+// b, c and d, in that order.  Two rounds of byte permutes: pairs interleave
+// (a0 b0 a1 b1 / a2 b2 a3 b3, likewise c with d), then the pairs combine.
+RR_HD void xpose4x4_b8(uint32_t a, uint32_t b, uint32_t c, uint32_t d, uint32_t& o0, uint32_t& o1, uint32_t& o2,
+                       uint32_t& o3) {
+    const uint32_t ab01 = perm_b32(b, a, 0x05010400u), ab23 = perm_b32(b, a, 0x07030602u);
+    const uint32_t cd01 = perm_b32(d, c, 0x05010400u), cd23 = perm_b32(d, c, 0x07030602u);
+    o0 = perm_b32(cd01, ab01, 0x05040100u);
+    o1 = perm_b32(cd01, ab01, 0x07060302u);
+    o2 = perm_b32(cd23, ab23, 0x05040100u);
+    o3 = perm_b32(cd23, ab23, 0x07060302u);
+}
+
 // GxG transpose of U-byte elements held as G rows of W = U*G bytes:
 //   out[i] element j  =  in[j] element i.
+// 4..16-byte elements are whole words (register renaming); 2-byte elements take
+// one byte permute per output word (half i of rows 2q and 2q+1), 1-byte
+// elements a 4x4 byte transpose per four output words (eight permutes), so an
+// 8x8 byte tile costs 32 permutes instead of masks, shifts and ors per byte.
 template <int U, int G>
 RR_HD void xpose(const uint32_t (&r)[G][NWords<U * G>::value], uint32_t (&o)[G][NWords<U * G>::value]) {
-    constexpr int W = U * G;
     if constexpr (U >= 4) {
         constexpr int EW = U / 4;
 #pragma unroll
@@ -242,23 +276,37 @@ RR_HD void xpose(const uint32_t (&r)[G][NWords<U * G>::value], uint32_t (&o)[G][
             for (int j = 0; j < G; ++j)
 #pragma unroll
                 for (int q = 0; q < EW; ++q) o[i][j * EW + q] = r[j][i * EW + q];
-    } else {
-        constexpr int EPW = (W >= 4 ? 4 : W) / U;  // elements per output word
-        constexpr int NWO = NWords<W>::value;
-        constexpr uint32_t MASK = U == 1 ? 0xffu : 0xffffu;
+    } else if constexpr (U == 2) {
+        // o[i][q] = { row 2q half i, row 2q+1 half i }; row j's half i sits in
+        // word i/2, low half when i is even
+        constexpr int NWO = NWords<2 * G>::value;
 #pragma unroll
         for (int i = 0; i < G; ++i)
 #pragma unroll
             for (int q = 0; q < NWO; ++q) {
-                uint32_t acc = 0;
-#pragma unroll
-                for (int b = 0; b < EPW; ++b) {
-                    const int j = q * EPW + b;
-                    const uint32_t e = (r[j][(i * U) / 4] >> (8 * ((i * U) % 4))) & MASK;
-                    acc |= e << (8 * U * b);
+                if constexpr (G == 1) {
+                    o[i][q] = r[0][0];
+                } else {
+                    const uint32_t sel = (i & 1) ? 0x07060302u : 0x05040100u;
+                    o[i][q] = perm_b32(r[2 * q + 1][i / 2], r[2 * q][i / 2], sel);
                 }
-                o[i][q] = acc;
             }
+    } else if constexpr (G == 1) {
+        o[0][0] = r[0][0];
+    } else if constexpr (G == 2) {
+        // two 2-byte rows: o[i] = { row 0 byte i, row 1 byte i }
+        o[0][0] = perm_b32(r[1][0], r[0][0], 0x0c0c0400u);
+        o[1][0] = perm_b32(r[1][0], r[0][0], 0x0c0c0501u);
+    } else {
+        // byte b of o[i][q] is byte i of row 4q+b, i.e. byte i%4 of word i/4 of
+        // that row: for each (q, h = i/4) a 4x4 byte transpose of rows 4q..4q+3
+        constexpr int NWO = G / 4;
+#pragma unroll
+        for (int q = 0; q < NWO; ++q)
+#pragma unroll
+            for (int h = 0; h < NWO; ++h)
+                xpose4x4_b8(r[4 * q][h], r[4 * q + 1][h], r[4 * q + 2][h], r[4 * q + 3][h], o[4 * h][q],
+                            o[4 * h + 1][q], o[4 * h + 2][q], o[4 * h + 3][q]);
     }
 }
 

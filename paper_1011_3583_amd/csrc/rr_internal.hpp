@@ -10,9 +10,19 @@
 
 namespace rr {
 
+// Diagnostics on stderr by level, from the RR_LOG environment variable (read
+// once): 0 or unset silent, 1 every error a call returns, 2 also the plan of
+// every single launch and the groups of every batch, 3 also the server's batch
+// and admission events.
+int log_level();
+void log_line(int level, const std::string& msg);
+
 rr_status fail(rr_status s, const std::string& why);
 void clear_error();
 rr_status hip_fail(hipError_t e, const char* what);
+// The tuning-cache context of this process (device architecture and HIP
+// runtime version), set on first use from the current device.
+void ensure_tune_context();
 bool ranges_overlap(uint64_t a, uint64_t na, uint64_t b, uint64_t nb);
 // Validate and canonicalise one permute request (no launch).
 rr_status validate_permute(const void* dst, const void* src, int ndim, const int64_t* dims,

@@ -25,6 +25,7 @@
 #include <mutex>
 #include <shared_mutex>
 #include <sstream>
+#include <vector>
 
 namespace rr {
 
@@ -69,13 +70,20 @@ std::map<std::string, TileOptions, std::less<>>& tune_cache() {
     return m;
 }
 
+// Context prefix of every key ("<arch>@hip<version>|"), fixed once per process.
+std::mutex g_ctx_mu;
+char g_ctx[128] = "";
+size_t g_ctx_len = 0;
+
 // The key of a canonical problem, written into buf (no allocation):
-// r<rank>:e<bytes>:a<src align>/<dst align>:d<dims>:p<perm>[:s<input strides>]
+// <context>|r<rank>:e<bytes>:a<src align>/<dst align>:d<dims>:p<perm>[:s<input strides>]
 std::string_view format_tune_key(const Canon& c, uint64_t dst, uint64_t src, char (&buf)[768]) {
     char* p = buf;
     char* const end = buf + sizeof buf;
     auto put = [&](char ch) { if (p < end) *p++ = ch; };
     auto num = [&](int64_t v) { p = std::to_chars(p, end, v).ptr; };
+    for (size_t i = 0; i < g_ctx_len; ++i) put(g_ctx[i]);
+    put('|');
     put('r'); num(c.rank); put(':'); put('e'); num(c.elem_bytes); put(':'); put('a');
     num(addr_align(src)); put('/'); num(addr_align(dst)); put(':'); put('d');
     for (int i = 0; i < c.rank; ++i) { if (i) put(','); num(c.dims[i]); }
@@ -88,6 +96,19 @@ std::string_view format_tune_key(const Canon& c, uint64_t dst, uint64_t src, cha
     return std::string_view(buf, (size_t)(p - buf));
 }
 }  // namespace
+
+void tune_set_context(const std::string& ctx) {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    if (g_ctx_len) return;
+    g_ctx_len = std::min(ctx.size(), sizeof g_ctx - 1);
+    std::memcpy(g_ctx, ctx.data(), g_ctx_len);
+    g_ctx[g_ctx_len] = 0;
+}
+
+std::string tune_context() {
+    std::lock_guard<std::mutex> lk(g_ctx_mu);
+    return std::string(g_ctx, g_ctx_len);
+}
 
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src) {
     char buf[768];
@@ -136,10 +157,12 @@ bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 //   key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache [diag [fill]]]]]]]
 // (an entry without the xcd field never uses XCD ranges, one without cache plans
 // its accesses by line alignment, one without fill takes the built-in refit)
-int tune_parse(const std::string& text) {
+int tune_parse(const std::string& text, int* skipped) {
     std::istringstream lines(text);
     std::string line;
-    int n = 0;
+    int n = 0, other = 0;
+    const std::string prefix = tune_context() + "|";
+    std::vector<std::pair<std::string, TileOptions>> keep;
     while (std::getline(lines, line)) {
         std::istringstream in(line);
         std::string key;
@@ -160,9 +183,12 @@ int tune_parse(const std::string& text) {
             o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3 || o.diag < 0 ||
             o.diag > 1 || o.fill < -1 || o.fill > 1)
             return -1;
-        tune_store(key, o);
-        ++n;
+        if (key.find('|') == std::string::npos) return -1;   // no context
+        if (key.compare(0, prefix.size(), prefix) != 0) { ++other; continue; }
+        keep.emplace_back(key, o);
     }
+    for (const auto& kv : keep) { tune_store(kv.first, kv.second); ++n; }   // all or nothing
+    if (skipped) *skipped = other;
     return n;
 }
 

@@ -210,7 +210,13 @@ TileOptions current_tile_options();
 void set_tile_override(const TileOptions& o);
 bool override_active(const TileOptions& o);
 
-// Tuning cache: canonical problem + alignment class -> tile options.
+// Tuning cache: device architecture and HIP runtime version (the context, one per
+// process) + canonical problem + alignment class -> tile options.  Keys read
+//   <arch>@hip<version>|r<rank>:e<bytes>:a<src align>/<dst align>:d<dims>:p<perm>[:s<strides>]
+// A tuned shape was timed on one device and runtime, so lines of another context
+// are skipped when a file is loaded.
+void tune_set_context(const std::string& ctx);   // first call wins
+std::string tune_context();
 std::string tune_key(const Canon& c, uint64_t dst, uint64_t src);
 // The tuned options cached for a canonical problem at these pointer
 // alignments, if any (the key is formatted on the stack: no allocation).
@@ -218,7 +224,10 @@ bool tune_lookup(const Canon& c, uint64_t dst, uint64_t src, TileOptions* out);
 void tune_store(const std::string& key, const TileOptions& o);
 void tune_clear();
 std::string tune_dump();
-int tune_parse(const std::string& text);
+// Entries of this process's context are stored; *skipped (if given) counts the
+// well-formed lines of another context.  Returns the entries stored, -1 if a line
+// is malformed.
+int tune_parse(const std::string& text, int* skipped = nullptr);
 
 // Validation + canonicalisation.  Writes a human-readable reason on failure.
 rr_status canonicalize(int ndim, const int64_t* dims, const int* perm, int elem_size,

@@ -11,7 +11,16 @@
 //     of output each, so one huge permute never blocks small jobs for long;
 //   * batches are launched through the batched kernels on streams taken in turn,
 //     so consecutive batches overlap on the device; completion is observed with
-//     events and published to a completion queue.
+//     events and published to a completion queue;
+//   * jobs are validated and planned by the submitting thread, outside the
+//     server's lock (a job whose output the server allocates is planned for a
+//     256-byte aligned placeholder and moved to its buffer at admission); when
+//     the server has nothing queued and a slot is free, the submitting thread
+//     also admits and launches a job that needs no chunking itself, sparing it
+//     the hand-over to the server thread;
+//   * the HBM budget caps the device memory the server has reserved (its arena
+//     slabs), not only the bytes in use; slabs with nothing left in them are
+//     given back when a job would otherwise not fit.
 // A simulated backend (RR_SERVE_SIMULATED) replaces memory and launches with
 // virtual addresses and synthetic durations, so the same policy code runs on a
 // machine without a GPU.
@@ -49,6 +58,10 @@ struct Backend {
     virtual ~Backend() {}
     virtual rr_status init(int device, int nslots, int nstreams) = 0;
     virtual void bind_thread() {}
+    // launch_single from a thread other than the server's (its own current device kept)
+    virtual rr_status launch_single_from_caller(int slot, int stream, const Plan& p) {
+        return launch_single(slot, stream, p);
+    }
     virtual void* reserve(uint64_t bytes) = 0;
     virtual void release(void* p) = 0;
     // stage the table and launch a batch in slot `slot` on stream `stream`
@@ -112,24 +125,39 @@ class HipBackend : public Backend {
         hipStream_t st = streams_[(size_t)stream];
         std::memcpy(s.host, bp.table.data(), need);
         hipError_t e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, st);
-        if (e != hipSuccess) return hip_fail(e, "server table upload");
-        rr_status rs = launch_batch_plan(bp, (const uint8_t*)s.dev, false, device_, st);
+        rr_status rs = e == hipSuccess ? launch_batch_plan(bp, (const uint8_t*)s.dev, false, device_, st)
+                                       : hip_fail(e, "server table upload");
         e = hipEventRecord(s.ev, st);
-        if (rs != RR_OK) return rs;
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        return RR_OK;
+        if (rs == RR_OK && e != hipSuccess) rs = hip_fail(e, "hipEventRecord");
+        // A failed launch may have queued the table copy and some groups: let them
+        // finish before the caller reuses the slot's buffers or the jobs' outputs.
+        if (rs != RR_OK) drain_stream(st, s.ev, e == hipSuccess);
+        return rs;
     }
     rr_status launch_single(int slot, int stream, const Plan& p) override {
         hipStream_t st = streams_[(size_t)stream];
+        hipEvent_t ev = slots_[(size_t)slot].ev;
         hipError_t e = launch_plan(p, st);
-        if (e != hipSuccess) return hip_fail(e, "server direct launch");
-        e = hipEventRecord(slots_[(size_t)slot].ev, st);
-        if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-        return RR_OK;
+        rr_status rs = e == hipSuccess ? RR_OK : hip_fail(e, "server direct launch");
+        e = hipEventRecord(ev, st);
+        if (rs == RR_OK && e != hipSuccess) rs = hip_fail(e, "hipEventRecord");
+        if (rs != RR_OK) drain_stream(st, ev, e == hipSuccess);
+        return rs;
+    }
+    rr_status launch_single_from_caller(int slot, int stream, const Plan& p) override {
+        int prev = 0;
+        const bool have_prev = hipGetDevice(&prev) == hipSuccess;
+        if (!have_prev || prev != device_) (void)hipSetDevice(device_);
+        const rr_status rs = launch_single(slot, stream, p);
+        if (have_prev && prev != device_) (void)hipSetDevice(prev);
+        return rs;
     }
     bool done(int slot) override { return hipEventQuery(slots_[(size_t)slot].ev) != hipErrorNotReady; }
 
    private:
+    static void drain_stream(hipStream_t st, hipEvent_t ev, bool recorded) {
+        if (!recorded || hipEventSynchronize(ev) != hipSuccess) (void)hipStreamSynchronize(st);
+    }
     struct Slot {
         void* host = nullptr;
         void* dev = nullptr;
@@ -143,69 +171,94 @@ class HipBackend : public Backend {
 
 class SimBackend : public Backend {
    public:
-    explicit SimBackend(double bytes_per_us) : bpus_(bytes_per_us > 0 ? bytes_per_us : 4e6) {}
+    // device_bytes: memory of the simulated device (0: unlimited); a reservation
+    // beyond it fails as hipMalloc would
+    SimBackend(double bytes_per_us, uint64_t device_bytes)
+        : bpus_(bytes_per_us > 0 ? bytes_per_us : 4e6), cap_(device_bytes) {}
     rr_status init(int, int nslots, int) override {
         done_at_.assign((size_t)nslots, 0);
         return RR_OK;
     }
     void* reserve(uint64_t bytes) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        if (cap_ && taken_ + bytes > cap_) return nullptr;
         const uint64_t p = next_;
         next_ += round_up(bytes, 1 << 20) + (1 << 20);
+        taken_ += bytes;
+        sizes_[p] = bytes;
         return reinterpret_cast<void*>(p);
     }
-    void release(void*) override {}
-    rr_status launch(int slot, int, const BatchPlan& bp) override {
-        const uint64_t t = now_ns();
-        const uint64_t dur = (uint64_t)(2.0 * (double)bp.bytes / bpus_ * 1e3) + 2000;  // + launch cost
-        busy_until_ = std::max(busy_until_, t) + dur;   // one device: batches share its bandwidth
-        done_at_[(size_t)slot] = busy_until_;
-        return RR_OK;
+    void release(void* p) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        auto it = sizes_.find((uint64_t)p);
+        if (it == sizes_.end()) return;
+        taken_ -= it->second;
+        sizes_.erase(it);
     }
-    rr_status launch_single(int slot, int, const Plan& p) override {
-        const uint64_t t = now_ns();
-        const uint64_t dur = (uint64_t)(2.0 * (double)p.bytes / bpus_ * 1e3) + 2000;
-        busy_until_ = std::max(busy_until_, t) + dur;
-        done_at_[(size_t)slot] = busy_until_;
-        return RR_OK;
+    rr_status launch(int slot, int, const BatchPlan& bp) override { return occupy(slot, bp.bytes); }
+    rr_status launch_single(int slot, int, const Plan& p) override { return occupy(slot, p.bytes); }
+    bool done(int slot) override {
+        std::lock_guard<std::mutex> lk(mu_);
+        return now_ns() >= done_at_[(size_t)slot];
     }
-    bool done(int slot) override { return now_ns() >= done_at_[(size_t)slot]; }
 
    private:
+    // one device: batches share its bandwidth, each costs its bytes plus a launch
+    rr_status occupy(int slot, uint64_t bytes) {
+        std::lock_guard<std::mutex> lk(mu_);
+        const uint64_t dur = (uint64_t)(2.0 * (double)bytes / bpus_ * 1e3) + 2000;
+        busy_until_ = std::max(busy_until_, now_ns()) + dur;
+        done_at_[(size_t)slot] = busy_until_;
+        return RR_OK;
+    }
     double bpus_;
+    uint64_t cap_;
+    std::mutex mu_;
+    uint64_t taken_ = 0;
+    std::unordered_map<uint64_t, uint64_t> sizes_;
     uint64_t next_ = 0x200000000000ull;
     uint64_t busy_until_ = 0;
     std::vector<uint64_t> done_at_;
 };
 
 // ----------------------------------------------------------------- arena
-// First-fit allocator with coalescing over slabs reserved from the backend.
+// First-fit allocator with coalescing over slabs reserved from the backend.  The
+// slabs themselves (not only what is handed out of them) stay within the budget:
+// a new slab takes at most what the budget has left, and when that is too little
+// the slabs with nothing allocated in them are given back first.
+enum class AllocFail { NONE, NO_ROOM, BACKEND };
+
 class Arena {
    public:
-    explicit Arena(Backend* be) : be_(be) {}
+    Arena(Backend* be, uint64_t budget) : be_(be), budget_(budget) {}
     ~Arena() {
         for (auto& s : slabs_) be_->release(reinterpret_cast<void*>(s.base));
     }
-    void* alloc(uint64_t bytes) {
+    // NO_ROOM: would take the reserved memory past the budget (wait for frees);
+    // BACKEND: the device refused memory although the budget had room
+    void* alloc(uint64_t bytes, AllocFail* why) {
+        *why = AllocFail::NONE;
         bytes = round_up(std::max<uint64_t>(bytes, 1), 256);
-        for (Slab& s : slabs_) {
-            for (auto it = s.free.begin(); it != s.free.end(); ++it) {
-                if (it->second >= bytes) {
-                    const uint64_t off = it->first, len = it->second;
-                    s.free.erase(it);
-                    if (len > bytes) s.free[off + bytes] = len - bytes;
-                    used_[s.base + off] = bytes;
-                    return reinterpret_cast<void*>(s.base + off);
-                }
+        if (void* p = fit(bytes)) return p;
+        for (int attempt = 0; attempt < 2; ++attempt) {
+            const uint64_t room = budget_ > reserved_ ? budget_ - reserved_ : 0;
+            if (room >= bytes) {
+                uint64_t slab = std::max<uint64_t>(bytes, std::min<uint64_t>(256ull << 20, room));
+                void* p = be_->reserve(slab);
+                if (!p && slab > bytes) p = be_->reserve(slab = bytes);   // the device is short: just this job
+                if (!p) { *why = AllocFail::BACKEND; return nullptr; }
+                reserved_ += slab;
+                slabs_.push_back(Slab{(uint64_t)p, slab, {}, 0});
+                Slab& s = slabs_.back();
+                if (slab > bytes) s.free[bytes] = slab - bytes;
+                used_[s.base] = bytes;
+                s.live = 1;
+                return p;
             }
+            if (attempt == 0 && !trim()) break;
         }
-        const uint64_t slab = std::max<uint64_t>(bytes, 256ull << 20);
-        void* p = be_->reserve(slab);
-        if (!p) return nullptr;
-        slabs_.push_back(Slab{(uint64_t)p, slab, {}});
-        Slab& s = slabs_.back();
-        if (slab > bytes) s.free[bytes] = slab - bytes;
-        used_[s.base] = bytes;
-        return p;
+        *why = AllocFail::NO_ROOM;
+        return nullptr;
     }
     // returns the bytes freed (0 if p is not an allocation of this arena)
     uint64_t free(void* p) {
@@ -215,6 +268,7 @@ class Arena {
         used_.erase(u);
         for (Slab& s : slabs_) {
             if (addr < s.base || addr >= s.base + s.size) continue;
+            s.live--;
             uint64_t off = addr - s.base, n = len;
             auto next = s.free.lower_bound(off);
             if (next != s.free.end() && next->first == off + n) { n += next->second; next = s.free.erase(next); }
@@ -227,13 +281,47 @@ class Arena {
         }
         return len;
     }
+    uint64_t reserved() const { return reserved_; }
 
    private:
     struct Slab {
         uint64_t base, size;
         std::map<uint64_t, uint64_t> free;  // offset -> length
+        uint64_t live;                      // allocations handed out of it
     };
+    void* fit(uint64_t bytes) {
+        for (Slab& s : slabs_) {
+            for (auto it = s.free.begin(); it != s.free.end(); ++it) {
+                if (it->second >= bytes) {
+                    const uint64_t off = it->first, len = it->second;
+                    s.free.erase(it);
+                    if (len > bytes) s.free[off + bytes] = len - bytes;
+                    used_[s.base + off] = bytes;
+                    s.live++;
+                    return reinterpret_cast<void*>(s.base + off);
+                }
+            }
+        }
+        return nullptr;
+    }
+    // give the slabs with no allocation back to the backend; whether any was
+    bool trim() {
+        bool any = false;
+        for (size_t i = 0; i < slabs_.size();) {
+            if (slabs_[i].live == 0) {
+                be_->release(reinterpret_cast<void*>(slabs_[i].base));
+                reserved_ -= slabs_[i].size;
+                slabs_.erase(slabs_.begin() + (long)i);
+                any = true;
+            } else {
+                ++i;
+            }
+        }
+        return any;
+    }
     Backend* be_;
+    uint64_t budget_;
+    uint64_t reserved_ = 0;
     std::vector<Slab> slabs_;
     std::unordered_map<uint64_t, uint64_t> used_;
 };
@@ -247,6 +335,7 @@ struct JobState {
     uint64_t out_bytes = 0;
     uint32_t next_block = 0;     // first workgroup not yet put in a batch
     uint32_t chunk_blocks = 0;   // workgroups per chunk (0: whole job)
+    uint32_t piece_mult = 1;     // chunks per piece: doubles while no other job waits
     uint32_t outstanding = 0;    // batches in flight holding a piece of this job
     int32_t chunks = 0;
     int32_t status = RR_OK;
@@ -258,7 +347,24 @@ struct InFlight {
     int slot;
     std::vector<JobState*> jobs;
     uint64_t bytes;
+    bool launched;   // false while a submitting thread is still launching it
 };
+
+// Placeholder output address a job is planned for when the server allocates its
+// output: arena blocks are 256-byte aligned, so the plan is the same as for the
+// real buffer up to the base address (moved at admission by rebase_dst).
+constexpr uint64_t PLACEHOLDER_DST = 256;
+
+void rebase_dst(Plan& p, uint64_t dst) {
+    switch (p.kind) {
+        case K_COPY: p.copy.dst = p.copy.dst - PLACEHOLDER_DST + dst; break;
+        case K_RUN: p.run.dst = p.run.dst - PLACEHOLDER_DST + dst; break;
+        case K_TILE: p.tile.dst = p.tile.dst - PLACEHOLDER_DST + dst; break;
+        default: break;
+    }
+}
+
+enum class Admit { OK, WAIT, NO_MEMORY };
 
 }  // namespace
 }  // namespace rr
@@ -295,31 +401,52 @@ struct rr_server {
         completions.push_back(j->ticket);
     }
 
-    // Admit job j (lock held): allocate its output if needed and plan it.
-    bool admit(JobState* j) {
+    // Admit planned job j (lock held): allocate its output if the server owns it.
+    // WAIT: the budget has no room now (a release may make some); NO_MEMORY: the
+    // device refused memory within the budget while nothing was in flight, so no
+    // completion can change that -- the job fails instead of waiting forever.
+    Admit admit(JobState* j) {
         if (j->own_dst) {
-            if (budget_used + round_up(j->out_bytes, 256) > cfg.hbm_budget_bytes) return false;
-            void* p = arena->alloc(j->out_bytes);
-            if (!p) return false;
+            AllocFail why;
+            void* p = arena->alloc(j->out_bytes, &why);
+            if (!p) {
+                if (why == AllocFail::BACKEND && inflight.empty()) {
+                    j->status = RR_ERR_NO_MEMORY;
+                    return Admit::NO_MEMORY;
+                }
+                return Admit::WAIT;
+            }
             budget_used += round_up(j->out_bytes, 256);
             stats.budget_peak = std::max(stats.budget_peak, budget_used);
             j->job.dst = p;
+            rebase_dst(j->plan, (uint64_t)p);
         }
         j->t_admit = now_ns();
-        std::string why;
-        rr_status st = plan_job(j->job, current_tile_options(), &j->plan, &why);
-        if (st != RR_OK) { j->status = st; return true; }
-        if (!(cfg.flags & RR_SERVE_DIRECT) && cfg.chunk_bytes > 0 && j->plan.grid > 1 &&
-            j->plan.bytes > cfg.chunk_bytes) {
-            const uint64_t per_block = std::max<uint64_t>(1, j->plan.bytes / j->plan.grid);
-            j->chunk_blocks = (uint32_t)std::max<uint64_t>(1, cfg.chunk_bytes / per_block);
+        return Admit::OK;
+    }
+
+    int free_slot() const {
+        if ((int)inflight.size() >= std::max(1, cfg.max_inflight)) return -1;
+        for (int s = 0; s < std::max(1, cfg.max_inflight); ++s) if (!slot_busy[(size_t)s]) return s;
+        return -1;
+    }
+
+    // Finish a batch whose launch failed (lock held): release its slot, fail its jobs.
+    void fail_batch(int slot, std::vector<JobState*>& members) {
+        slot_busy[(size_t)slot] = false;
+        const uint64_t t = now_ns();
+        for (JobState* j : members) {
+            j->status = RR_ERR_HIP;
+            j->outstanding--;
+            // stop issuing the rest of a failed large job
+            auto it = std::find(large.begin(), large.end(), j);
+            if (it != large.end()) large.erase(it);
+            if (j->outstanding == 0 && !j->done) complete(j, t);
         }
-        return true;
     }
 
     void loop() {
         be->bind_thread();
-        const int maxin = std::max(1, cfg.max_inflight);
         const bool direct = (cfg.flags & RR_SERVE_DIRECT) != 0;
         const size_t maxjobs = direct ? 1 : (size_t)std::max(1, cfg.max_batch_jobs);
         for (;;) {
@@ -332,7 +459,7 @@ struct rr_server {
                 // retire finished batches
                 const uint64_t t = now_ns();
                 for (size_t i = 0; i < inflight.size();) {
-                    if (!be->done(inflight[i].slot)) { ++i; continue; }
+                    if (!inflight[i].launched || !be->done(inflight[i].slot)) { ++i; continue; }
                     InFlight f = std::move(inflight[i]);
                     inflight.erase(inflight.begin() + (long)i);
                     slot_busy[(size_t)f.slot] = false;
@@ -344,30 +471,22 @@ struct rr_server {
                     }
                 }
                 if (stopping && pending.empty() && large.empty() && inflight.empty()) break;
-                if (stopping && large.empty() && inflight.empty()) {
-                    // shutting down and idle: whatever is still queued waits for memory that
-                    // only a release (which cannot come any more) would free
-                    bool any = false;
-                    for (JobState* j : pending) {
-                        if (j->own_dst && budget_used + round_up(j->out_bytes, 256) > cfg.hbm_budget_bytes) {
-                            j->status = RR_ERR_NO_MEMORY;
-                            complete(j, now_ns());
-                            any = true;
-                        }
-                    }
-                    if (any)
-                        pending.erase(std::remove_if(pending.begin(), pending.end(),
-                                                     [](JobState* j) { return j->done; }),
-                                      pending.end());
-                }
-                if ((int)inflight.size() < maxin) {
-                    for (int s = 0; s < maxin; ++s) if (!slot_busy[(size_t)s]) { slot = s; break; }
-                }
+                // Shutting down with nothing in flight: a job still waiting for memory
+                // would wait for a release that cannot come any more -- it fails.
+                const bool drain = stopping && large.empty() && inflight.empty();
+                slot = free_slot();
                 if (slot >= 0) {
-                    // one chunk of every large job in progress, oldest first
+                    // One piece of every large job in progress, oldest first.  A piece is
+                    // piece_mult chunks: while no other job is waiting the pieces double
+                    // (up to 16 chunks), since a lone large job gains nothing from fine
+                    // pieces and pays a batch launch for each; any waiting job brings the
+                    // pieces back to one chunk, so it is launched after at most one.
+                    const bool others_waiting = !pending.empty() || large.size() > 1;
                     for (size_t k = 0; k < large.size() && entries.size() < maxjobs;) {
                         JobState* j = large[k];
-                        const uint32_t n = std::min(j->chunk_blocks, j->plan.grid - j->next_block);
+                        j->piece_mult = others_waiting ? 1u : std::min<uint32_t>(j->piece_mult * 2, 16);
+                        const uint32_t n = (uint32_t)std::min<uint64_t>((uint64_t)j->chunk_blocks * j->piece_mult,
+                                                                        j->plan.grid - j->next_block);
                         const uint64_t bytes = (uint64_t)((double)j->plan.bytes * n / j->plan.grid);
                         entries.push_back({&j->plan, j->next_block, n, bytes});
                         members.push_back(j);
@@ -381,9 +500,11 @@ struct rr_server {
                     bool head_blocked = false;
                     for (auto it = pending.begin(); it != pending.end() && entries.size() < maxjobs;) {
                         JobState* j = *it;
-                        if (head_blocked && j->own_dst) { ++it; continue; }
-                        if (!admit(j)) { head_blocked = true; ++it; continue; }
+                        if (head_blocked && j->own_dst && !drain) { ++it; continue; }
+                        const Admit a = admit(j);
+                        if (a == Admit::WAIT && !drain) { head_blocked = true; ++it; continue; }
                         it = pending.erase(it);
+                        if (a == Admit::WAIT) j->status = RR_ERR_NO_MEMORY;
                         if (j->status != RR_OK) { complete(j, now_ns()); continue; }
                         if (j->plan.kind == K_EMPTY || j->plan.grid == 0) { complete(j, now_ns()); continue; }
                         const uint32_t n = j->chunk_blocks ? j->chunk_blocks : j->plan.grid;
@@ -441,20 +562,12 @@ struct rr_server {
                 if (st == RR_OK) st = be->launch(slot, stream, bp);
             }
             std::lock_guard<std::mutex> lk(mu);
-            if (st != RR_OK) {
-                slot_busy[(size_t)slot] = false;
-                const uint64_t t = now_ns();
-                for (JobState* j : members) {
-                    j->status = RR_ERR_HIP;
-                    j->outstanding--;
-                    // stop issuing the rest of a failed large job
-                    auto it = std::find(large.begin(), large.end(), j);
-                    if (it != large.end()) large.erase(it);
-                    if (j->outstanding == 0 && !j->done) complete(j, t);
-                }
-            } else {
-                inflight.push_back(InFlight{slot, std::move(members), bp.bytes});
-            }
+            if (st != RR_OK) fail_batch(slot, members);
+            else inflight.push_back(InFlight{slot, std::move(members), bp.bytes, true});
+            if (log_level() >= 3)
+                log_line(3, "serve: batch of " + std::to_string(entries.size()) + " entries, " +
+                                std::to_string(bp.bytes) + " bytes per side, slot " + std::to_string(slot) +
+                                (st == RR_OK ? "" : " (launch failed)"));
         }
     }
 };
@@ -470,12 +583,13 @@ rr_status rr_serve_create(const rr_serve_config* cfg, rr_server** out) {
         return fail(RR_ERR_INVALID_ARG, "bad server configuration");
     auto s = std::make_unique<rr_server>();
     s->cfg = *cfg;
-    if (cfg->flags & RR_SERVE_SIMULATED) s->be = std::make_unique<SimBackend>(cfg->sim_bytes_per_us);
+    if (cfg->flags & RR_SERVE_SIMULATED)
+        s->be = std::make_unique<SimBackend>(cfg->sim_bytes_per_us, cfg->sim_device_bytes);
     else s->be = std::make_unique<HipBackend>();
     s->nstreams = std::min(cfg->max_inflight, 4);
     rr_status st = s->be->init(cfg->device, cfg->max_inflight, s->nstreams);
     if (st != RR_OK) return st;
-    s->arena = std::make_unique<Arena>(s->be.get());
+    s->arena = std::make_unique<Arena>(s->be.get(), cfg->hbm_budget_bytes);
     s->slot_busy.assign((size_t)cfg->max_inflight, false);
     rr_server* raw = s.release();
     raw->th = std::thread([raw] { raw->loop(); });
@@ -488,9 +602,9 @@ rr_status rr_serve_alloc(rr_server* s, uint64_t bytes, void** dptr) {
     if (!s || !dptr || bytes == 0) return fail(RR_ERR_INVALID_ARG, "bad argument");
     std::lock_guard<std::mutex> lk(s->mu);
     const uint64_t b = round_up(bytes, 256);
-    if (s->budget_used + b > s->cfg.hbm_budget_bytes) return fail(RR_ERR_NO_MEMORY, "over the HBM budget");
-    void* p = s->arena->alloc(bytes);
-    if (!p) return fail(RR_ERR_NO_MEMORY, "device allocation failed");
+    AllocFail why;
+    void* p = s->arena->alloc(bytes, &why);
+    if (!p) return fail(RR_ERR_NO_MEMORY, why == AllocFail::BACKEND ? "device allocation failed" : "over the HBM budget");
     s->budget_used += b;
     s->stats.budget_peak = std::max(s->stats.budget_peak, s->budget_used);
     s->user_allocs[(uint64_t)p] = b;
@@ -523,25 +637,75 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
         return fail(RR_ERR_ALIAS, "source and destination overlap");
     const bool own = job->dst == nullptr && nb > 0;
     if (own && round_up(nb, 256) > s->cfg.hbm_budget_bytes) return fail(RR_ERR_NO_MEMORY, "job exceeds the budget");
-    std::lock_guard<std::mutex> lk(s->mu);
-    if (s->stopping) return fail(RR_ERR_INVALID_ARG, "server is shutting down");
-    if (nb > 0 && (int)s->pending.size() >= s->cfg.queue_capacity) return fail(RR_ERR_BUSY, "queue full");
+    // plan here, on the submitting thread, outside the server's lock
     auto j = std::make_unique<JobState>();
-    j->ticket = s->next_ticket++;
     j->job = *job;
     j->own_dst = own;
     j->out_bytes = nb;
+    if (nb > 0) {
+        const uint64_t dst = own ? PLACEHOLDER_DST : (uint64_t)job->dst;
+        st = plan_permute(dst, (uint64_t)job->src, c, current_tile_options(), &j->plan, &why);
+        if (st != RR_OK) return fail(st, why);
+        if (!(s->cfg.flags & RR_SERVE_DIRECT) && s->cfg.chunk_bytes > 0 && j->plan.grid > 1 &&
+            j->plan.bytes > s->cfg.chunk_bytes) {
+            const uint64_t per_block = std::max<uint64_t>(1, j->plan.bytes / j->plan.grid);
+            j->chunk_blocks = (uint32_t)std::max<uint64_t>(1, s->cfg.chunk_bytes / per_block);
+        }
+    }
+    std::unique_lock<std::mutex> lk(s->mu);
+    if (s->stopping) return fail(RR_ERR_INVALID_ARG, "server is shutting down");
+    if (nb > 0 && (int)s->pending.size() >= s->cfg.queue_capacity) return fail(RR_ERR_BUSY, "queue full");
+    j->ticket = s->next_ticket++;
     j->t_submit = now_ns();
     JobState* raw = j.get();
     s->jobs[j->ticket] = std::move(j);
     s->stats.submitted++;
     *ticket = raw->ticket;
-    if (nb == 0) {
+    if (nb == 0 || raw->plan.kind == K_EMPTY || raw->plan.grid == 0) {
         s->complete(raw, raw->t_submit);
         return RR_OK;
     }
-    s->pending.push_back(raw);
     s->last_activity = raw->t_submit;
+    // Idle fast path: nothing queued, a slot free, no chunking -- admit and launch
+    // here instead of handing the job to the server thread.
+    int slot = -1;
+    if (s->pending.empty() && s->large.empty() && raw->chunk_blocks == 0 && !s->fail_next &&
+        (slot = s->free_slot()) >= 0) {
+        const Admit a = s->admit(raw);
+        if (a == Admit::NO_MEMORY) {
+            s->complete(raw, now_ns());
+            return RR_OK;
+        }
+        if (a == Admit::OK) {
+            s->slot_busy[(size_t)slot] = true;
+            const int stream = s->next_stream;
+            s->next_stream = (s->next_stream + 1) % s->nstreams;
+            raw->next_block = raw->plan.grid;
+            raw->outstanding = 1;
+            raw->chunks = 1;
+            raw->t_launch = now_ns();
+            s->stats.batches++;
+            s->stats.chunks++;
+            s->inflight.push_back(InFlight{slot, {raw}, raw->plan.bytes, false});
+            lk.unlock();
+            const rr_status ls = s->be->launch_single_from_caller(slot, stream, raw->plan);
+            lk.lock();
+            for (size_t i = 0; i < s->inflight.size(); ++i) {
+                if (s->inflight[i].slot != slot || s->inflight[i].launched) continue;
+                if (ls == RR_OK) {
+                    s->inflight[i].launched = true;
+                } else {
+                    std::vector<JobState*> members = std::move(s->inflight[i].jobs);
+                    s->inflight.erase(s->inflight.begin() + (long)i);
+                    s->fail_batch(slot, members);
+                }
+                break;
+            }
+            s->cv.notify_one();
+            return RR_OK;
+        }
+    }
+    s->pending.push_back(raw);
     s->cv.notify_one();
     return RR_OK;
 }
@@ -610,6 +774,7 @@ rr_status rr_serve_get_stats(rr_server* s, rr_serve_stats* out) {
     std::lock_guard<std::mutex> lk(s->mu);
     *out = s->stats;
     out->budget_used = s->budget_used;
+    out->reserved = s->arena->reserved();
     return RR_OK;
 }
 

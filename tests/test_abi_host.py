@@ -139,12 +139,13 @@ def test_plan_uses_widest_vectors_on_aligned_buffers():
 
 def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
     """A cached tile shape for a canonical problem is used by later plans of it."""
+    K = rr.tune_context() + "|"
     L = rr.lib()
     rr.tune_clear()
     dims, perm, e = (16384, 16384), (1, 0), 4
     base = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
     path = tmp_path / "tune.txt"
-    key_line = "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1 0 64\n"
+    key_line = K + "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1 0 64\n"
     path.write_text(key_line)
     rr.tune_load(str(path))
     tuned = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
@@ -265,6 +266,7 @@ def test_batched_planning_reports_lowest_invalid_job():
 
 def test_micro_tile_cap_from_override_and_cache(tmp_path):
     """The micro-tile edge G can be capped by the override and by a cached entry."""
+    K = rr.tune_context() + "|"
     rr.tune_clear()
     dims, perm, e = (4096, 4096), (1, 0), 1
     assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["g"] == "8"
@@ -276,37 +278,37 @@ def test_micro_tile_cap_from_override_and_cache(tmp_path):
         rr.set_tile_override(max_g=3)
     rr.set_tile_override()
     path = tmp_path / "tune.txt"
-    path.write_text("r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8\n\n")
+    path.write_text(K + "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8\n\n")
     rr.tune_load(str(path))
     d = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
     assert (d["g"], d["TA"], d["TB"]) == ("8", "128", "128")
     out = tmp_path / "saved.txt"
     rr.tune_save(str(out))
-    assert "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8" in out.read_text()
+    assert K + "r2:e1:a16/16:d4096,4096:p1,0 128 128 1 8" in out.read_text()
     rr.tune_clear()
-    path.write_text("r2:e1:a16/16:d4096,4096:p1,0 0 0 -1 0 0 1\n")
+    path.write_text(K + "r2:e1:a16/16:d4096,4096:p1,0 0 0 -1 0 0 1\n")
     rr.tune_load(str(path))
     assert int(rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["flags"]) & 256
     rr.tune_clear()
-    path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 1\n")
+    path.write_text(K + "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 1\n")
     rr.tune_load(str(path))
     assert int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 512
     rr.tune_clear()
     assert not int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 512
     # the cache-policy field: 2 = writes through the caches, and no XCD ranges (xcd 0)
-    path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2\n")
+    path.write_text(K + "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2\n")
     rr.tune_load(str(path))
     f = int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"])
     assert f & 2048 and not f & 1024 and not f & 256
-    assert "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 0 -1" in (rr.tune_save(str(out)) or out.read_text())
-    path.write_text("r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 1\n")   # diagonal tile order
+    assert K + "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 0 -1" in (rr.tune_save(str(out)) or out.read_text())
+    path.write_text(K + "r2:e4:a16/16:d1001,999:p1,0 0 0 -1 0 0 0 0 2 1\n")   # diagonal tile order
     rr.tune_clear()
     rr.tune_load(str(path))
     assert int(rr.plan_describe((1001, 999), (1, 0), 4, dst=1 << 20, src=1 << 30)["flags"]) & 4096
     rr.tune_clear()
     # the fill field: 0 keeps the row-target tiles of an odd extent
     refit = rr.plan_describe((611, 39), (1, 0), 8, dst=1 << 20, src=1 << 30)
-    path.write_text("r2:e8:a16/16:d611,39:p1,0 0 0 -1 0 0 -1 0 -1 0 0\n")
+    path.write_text(K + "r2:e8:a16/16:d611,39:p1,0 0 0 -1 0 0 -1 0 -1 0 0\n")
     rr.tune_load(str(path))
     d = rr.plan_describe((611, 39), (1, 0), 8, dst=1 << 20, src=1 << 30)
     assert (d["TA"], d["TB"], d["ntiles"]) == ("32", "64", "20") and d["ntiles"] != refit["ntiles"]
@@ -438,3 +440,33 @@ def test_override_is_safe_across_threads():
         t.join()
     rr.set_tile_override()
     assert not errors and seen <= ok, (errors, seen, ok)
+
+
+def test_tuning_file_of_another_device_or_runtime_is_skipped(tmp_path):
+    """Tuned shapes were timed on one device and HIP runtime: lines keyed with
+    another architecture or runtime version are skipped on load, lines of this
+    process's context are used, and a malformed line stores nothing."""
+    ctx = rr.tune_context()
+    arch, ver = ctx.split("@hip")
+    assert arch and ver.isdigit(), ctx
+    rr.tune_clear()
+    dims, perm, e = (16384, 16384), (1, 0), 4
+    base = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
+    body = "r2:e4:a16/16:d16384,16384:p1,0 1024 256 1 0 64\n"
+    path = tmp_path / "tune.txt"
+    for other in ("gfx942:sramecc+:xnack-@hip" + ver, arch + "@hip" + str(int(ver) + 1)):
+        path.write_text(other + "|" + body)
+        rr.tune_load(str(path))
+        assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30) == base, other
+    path.write_text("gfx942:sramecc+:xnack-@hip1|" + body + ctx + "|" + body)
+    rr.tune_load(str(path))
+    assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)["TA"] == "256"
+    out = tmp_path / "saved.txt"
+    rr.tune_save(str(out))
+    assert out.read_text() == ctx + "|" + body.replace("64\n", "64 0 0 -1 0 -1\n")
+    rr.tune_clear()
+    # a key without any context is malformed; nothing of the file is stored
+    path.write_text(ctx + "|" + body + body)
+    with pytest.raises(rr.RRError):
+        rr.tune_load(str(path))
+    assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30) == base
