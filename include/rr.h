@@ -206,6 +206,30 @@ typedef struct {
 rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
 
 /* -------------------------------------------------------------------------
+ * rr_permute_batched without any memory allocation, for callers that cannot
+ * allocate device or pinned host memory (serving loops that must not call
+ * hipMalloc, harnesses that forbid it).  Same jobs, validation, planning and
+ * kernels as rr_permute_batched, and the same result for every job; the
+ * differences:
+ *  - the job table lives in a fixed 4 MiB device array of the library (one copy
+ *    per GPU, held until the process ends) instead of a staging ring; a batch
+ *    whose table exceeds it (about 6000 tiled jobs) fails with
+ *    RR_ERR_UNSUPPORTED before anything is enqueued;
+ *  - the table is copied from pageable host memory with a stream-ordered copy
+ *    on `stream` (the call may block until the work already queued on `stream`
+ *    has finished), and every group runs on `stream` itself (no side streams);
+ *  - all calls on one GPU share that GPU's table: calls on the same stream are
+ *    ordered, but calls that overlap in time on different streams of one GPU
+ *    race on the table and must be ordered by the caller (events or one
+ *    stream).  Not for graph capture (the copy would be recorded as a node that
+ *    reads the calling thread's staging buffer).
+ * Host planning uses per-thread buffers kept across calls.
+ * Errors: the first invalid job's error (nothing is launched), RR_ERR_UNSUPPORTED,
+ * RR_ERR_HIP.
+ */
+rr_status rr_permute_batched_noalloc(const rr_job* jobs, int njobs, rr_stream_t stream);
+
+/* -------------------------------------------------------------------------
  * Reusable batch: validate, plan and group the jobs once, keep the job table
  * resident in device memory owned by the handle, launch many times.
  *   flags  RR_BATCH_GRAPH      launches replay a hipGraph captured on the

@@ -26,7 +26,7 @@ STATUS_CODE = {v: k for k, v in STATUS.items()}
 RR_OK, RR_ERR_NOT_READY = 0, 7
 
 EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_stencil2d", "rr_interlace", "rr_deinterlace",
-           "rr_permute_batched",
+           "rr_permute_batched", "rr_permute_batched_noalloc",
            "rr_batch_create", "rr_batch_launch", "rr_batch_get_info", "rr_batch_describe", "rr_batch_destroy",
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
@@ -96,6 +96,7 @@ def lib() -> ctypes.CDLL:
     L.rr_interlace.argtypes = [vp, ctypes.POINTER(vp), i32, i64, i32, vp]
     L.rr_deinterlace.argtypes = [ctypes.POINTER(vp), vp, i32, i64, i32, vp]
     L.rr_permute_batched.argtypes = [ctypes.POINTER(Job), i32, vp]
+    L.rr_permute_batched_noalloc.argtypes = [ctypes.POINTER(Job), i32, vp]
     L.rr_batch_create.argtypes = [ctypes.POINTER(Job), i32, i32, ctypes.POINTER(vp)]
     L.rr_batch_launch.argtypes = [vp, vp]
     L.rr_batch_get_info.argtypes = [vp, ctypes.POINTER(BatchInfo)]
@@ -240,6 +241,16 @@ def permute_batched_raw(jobs, njobs: int | None = None, stream=0) -> int:
     else:
         n = len(jobs) if njobs is None else njobs
     return lib().rr_permute_batched(jobs, n, _stream_handle(stream))
+
+
+def permute_batched_noalloc_raw(jobs, njobs: int | None = None, stream=0) -> int:
+    """rr_permute_batched_noalloc: the job table in the library's fixed device array."""
+    if not isinstance(jobs, ctypes.Array):
+        n = len(jobs)
+        jobs = make_jobs(jobs)
+    else:
+        n = len(jobs) if njobs is None else njobs
+    return lib().rr_permute_batched_noalloc(jobs, n, _stream_handle(stream))
 
 
 class Batch:
