@@ -50,6 +50,8 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
         lib.oracle_permute.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int]
         lib.oracle_permute_at.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int,
                                           i64p, ctypes.c_int64]
+        lib.oracle_permute_range.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int,
+                                             ctypes.c_int64, ctypes.c_int64]
         lib.oracle_reorder_paper.argtypes = [vp, vp, ctypes.c_int, i64p, ip, ctypes.c_int]
         lib.oracle_reorder_slice.argtypes = [vp, vp, ctypes.c_int, i64p, i64p, i64p, ctypes.c_int, ip,
                                              ctypes.c_int]
@@ -61,7 +63,7 @@ def _lib(mutant: int = 0) -> ctypes.CDLL:
                                          ctypes.c_int64, ctypes.c_int]
         lib.oracle_deinterlace.argtypes = [ctypes.POINTER(vp), vp, ctypes.c_int,
                                            ctypes.c_int64, ctypes.c_int]
-        for f in ("oracle_permute", "oracle_permute_at", "oracle_reorder_paper", "oracle_reorder_slice",
+        for f in ("oracle_permute", "oracle_permute_at", "oracle_permute_range", "oracle_reorder_paper", "oracle_reorder_slice",
                   "oracle_gather", "oracle_copy_range", "oracle_stencil2d",
                   "oracle_interlace", "oracle_deinterlace", "oracle_mutant_id"):
             getattr(lib, f).restype = ctypes.c_int
@@ -114,6 +116,22 @@ def permute_at(src: np.ndarray, dims, perm, esize: int, out_index, mutant: int =
         idx.ctypes.data_as(ctypes.POINTER(ctypes.c_int64)), idx.size)
     if rc != 0:
         raise ValueError("oracle_permute_at rejected its arguments")
+    return out
+
+
+def permute_range(src: np.ndarray, dims, perm, esize: int, o_begin: int, o_count: int,
+                  mutant: int = 0) -> np.ndarray:
+    """Output elements o_begin .. o_begin + o_count - 1 of the permute, as a flat
+    uint8 array of o_count * esize bytes.  The C call releases the GIL, so
+    several ranges can be computed at once from threads."""
+    dims = [int(d) for d in dims]
+    perm = [int(p) for p in perm]
+    sb = _as_bytes(src)
+    out = np.empty(int(o_count) * esize, dtype=np.uint8)
+    rc = _lib(mutant).oracle_permute_range(out.ctypes.data, sb.ctypes.data, len(dims), _i64(dims), _i32(perm),
+                                           esize, int(o_begin), int(o_count))
+    if rc != 0:
+        raise ValueError("oracle_permute_range rejected its arguments")
     return out
 
 

@@ -135,6 +135,49 @@ int oracle_permute(void* dst, const void* src, int ndim, const int64_t* dims,
 }
 
 /*
+ * Permute, restricted to the output elements o_begin .. o_begin + o_count - 1
+ * (the same definition as oracle_permute: dst[J] = src[I] with I[perm[j]] =
+ * J[j]).  The odometer starts at the decoded coordinates of o_begin; dst holds
+ * just those o_count elements.  Lets a test compute a huge output piece by
+ * piece (and several pieces at once) without holding all of it.
+ * Returns 0 on success, -1 on bad arguments or a range outside the output.
+ */
+int oracle_permute_range(void* dst, const void* src, int ndim, const int64_t* dims,
+                         const int* perm, int esize, int64_t o_begin, int64_t o_count)
+{
+    if (ndim < 1 || ndim > ORACLE_MAX_DIMS || esize < 1 || !is_permutation(ndim, perm))
+        return -1;
+    int64_t in_strides[ORACLE_MAX_DIMS];
+    int64_t out_dims[ORACLE_MAX_DIMS];
+    int64_t J[ORACLE_MAX_DIMS];
+    int64_t total = 1;
+    for (int k = 0; k < ndim; ++k) {
+        if (dims[k] < 0) return -1;
+        total *= dims[k];
+    }
+    if (o_count < 0 || o_begin < 0 || o_begin > total || o_count > total - o_begin) return -1;
+    if (o_count == 0) return 0;
+    row_major_strides(ndim, dims, in_strides);
+    for (int j = 0; j < ndim; ++j) out_dims[j] = dims[perm[j]];
+    int64_t o = o_begin;
+    for (int j = ndim - 1; j >= 0; --j) {   /* mixed-radix decode of the first index */
+        J[j] = o % out_dims[j];
+        o /= out_dims[j];
+    }
+    unsigned char* d = (unsigned char*)dst;
+    const unsigned char* s = (const unsigned char*)src;
+    for (int64_t t = 0; t < o_count; ++t) {
+        int64_t i = source_index(ndim, perm, in_strides, J);
+        memcpy(d + t * esize, s + i * esize, (size_t)esize);
+        for (int j = ndim - 1; j >= 0; --j) {   /* odometer, last axis fastest */
+            if (++J[j] < out_dims[j]) break;
+            J[j] = 0;
+        }
+    }
+    return 0;
+}
+
+/*
  * Same definition evaluated only at chosen output linear indices, for checking
  * huge outputs element by element.  out_index[t] is a linear index into dst;
  * the element's bytes go to samples + t*esize.

@@ -366,6 +366,35 @@ def pin_permute_at(m=0):
     return np.array_equal(oracle.permute_at(x, dims, perm, e, idx, mutant=m), full[idx])
 
 
+def pin_permute_range(m=0, golden_dir=None):
+    """Output pieces: every split of the hand-worked permute fixtures, and random
+    [a, b) ranges of random shapes against NumPy's transpose."""
+    if golden_dir is not None:
+        for case in golden_io.load_all(golden_dir):
+            if case["op"] != "permute":
+                continue
+            e = case.get("esize", [4])[0]
+            n = int(np.prod(case["dims"]))
+            x = _iota(n * e)
+            for k in range(n + 1):
+                a = oracle.permute_range(x, case["dims"], case["perm"], e, 0, k, mutant=m)
+                b = oracle.permute_range(x, case["dims"], case["perm"], e, k, n - k, mutant=m)
+                if np.concatenate([a, b]).tolist() != case["expect"]:
+                    return False
+    g = rr_synth.rng(44)
+    for dims, perm, e in [((6, 5, 7, 3), (3, 0, 2, 1), 4), ((9, 11), (1, 0), 3), ((4, 3, 5, 2, 3), (4, 2, 0, 3, 1), 2),
+                          ((17, 13, 5), (2, 0, 1), 8)]:
+        n = int(np.prod(dims))
+        x = rr_synth.random_bytes(22, n * e)
+        full = _np_permute(x, dims, perm, e)
+        for _ in range(6):
+            a = int(g.integers(0, n))
+            c = int(g.integers(0, n - a + 1))
+            if not np.array_equal(oracle.permute_range(x, dims, perm, e, a, c, mutant=m), full[a * e:(a + c) * e]):
+                return False
+    return True
+
+
 ALL_PINS = {
     "identity": lambda gd, m: pin_identity_is_memcpy(m),
     "golden": lambda gd, m: pin_golden(gd, m),
@@ -376,6 +405,7 @@ ALL_PINS = {
     "interlace": lambda gd, m: pin_interlace_numpy(m),
     "paper_notation": lambda gd, m: pin_paper_notation(m),
     "permute_at": lambda gd, m: pin_permute_at(m),
+    "permute_range": lambda gd, m: pin_permute_range(m, gd),
     "reorder_slice_numpy": lambda gd, m: pin_reorder_slice_numpy(m),
     "reorder_slice_permute": lambda gd, m: pin_reorder_slice_reduces_to_permute(m),
     "gather_range_numpy": lambda gd, m: pin_gather_and_range_numpy(m),
