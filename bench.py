@@ -438,7 +438,8 @@ def main():
         t_cpy = timed(lambda: rr.check(rr.permute_raw(out.data_ptr(), pool.data_ptr(), (nb,), (0,), 1, sh)), 5)
         ceilings[nb] = {"d2d": 2 * nb / t_d2d / 1e9, "rr_copy": 2 * nb / t_cpy / 1e9}
     best_copy = {nb: max(v.values()) for nb, v in ceilings.items()}
-    step_time_at = lambda key: sum(2 * c[4] / (ceilings[c[4]][key] if key else best_copy[c[4]]) for c in cases)
+    step_time_at = lambda key: sum(2 * c[4] / ((ceilings[c[4]][key] if key else best_copy[c[4]]) * 1e9)
+                                   for c in cases)   # seconds
     d2d = bytes_per_step / step_time_at("d2d") / 1e9           # the step at D2D speed, size by size
     rrcopy = bytes_per_step / step_time_at("rr_copy") / 1e9
     bestc = bytes_per_step / step_time_at(None) / 1e9

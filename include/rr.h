@@ -299,9 +299,10 @@ rr_status rr_batch_destroy(rr_batch* b);
  * batch, so small jobs keep flowing past it.  Results are identical to
  * rr_permute run alone.
  * Jobs are validated and planned by rr_serve_submit on the calling thread.  When
- * the server has nothing queued and a slot is free, rr_serve_submit also admits
- * and launches a job that needs no chunking itself (on the server's streams and
- * device).  The budget caps the device memory the server reserves (slabs of its
+ * the server is idle (nothing queued, nothing in flight), rr_serve_submit also
+ * admits and launches a job that needs no chunking itself (on the server's
+ * streams and device).  Pieces of large jobs never take the last free slot on
+ * their own, so a job that arrives meanwhile starts beside them.  The budget caps the device memory the server reserves (slabs of its
  * arena, up to 256 MiB each, kept for reuse and given back when a job would
  * otherwise not fit), not only the bytes handed out.  A job whose output the
  * device refuses to allocate within the budget while no batch is in flight

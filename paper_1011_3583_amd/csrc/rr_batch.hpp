@@ -33,7 +33,10 @@ struct BatchGroup {
 // Bucket index after a group's prefix sums: entry k is the job that holds
 // workgroup k * BATCH_BUCKET (the last job where that is past the end), so a
 // workgroup's job lies between its bucket's entry and the next one's.
-constexpr uint32_t BATCH_BUCKET = 32;
+#ifndef RR_BATCH_BUCKET
+#define RR_BATCH_BUCKET 32
+#endif
+constexpr uint32_t BATCH_BUCKET = RR_BATCH_BUCKET;
 constexpr uint64_t batch_buckets(uint64_t total_blocks) {
     return total_blocks ? (total_blocks - 1) / BATCH_BUCKET + 2 : 1;
 }

@@ -147,6 +147,10 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
     for (size_t i = 0; i < entries.size(); ++i) {
         const Plan& p = *entries[i].plan;
         if (p.kind == K_EMPTY || entries[i].nblocks == 0) continue;
+        if (p.kind != K_COPY && p.kind != K_RUN && p.kind != K_TILE) {   // dense jobs plan to these only
+            *why = "batch entry of a kind the batched kernels do not run";
+            return RR_ERR_UNSUPPORTED;
+        }
         int variant = 0;
         if (p.kind == K_COPY) variant = (int)p.copy.wbytes;
         else if (p.kind == K_RUN) variant = (int)p.run.wbytes;

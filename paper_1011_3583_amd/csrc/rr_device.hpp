@@ -569,6 +569,137 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
     }
 }
 
+// ----------------------------------------------------------------- strided select
+// Bytes of the R-byte element j of a span of M consecutive 16-byte vectors whose
+// elements lie S = M * R bytes apart, packed into one 16-byte output vector
+// (16 / R elements).  All positions are compile-time constants.
+template <int R, int M>
+RR_HD void select_pack(const uint32_t (&in)[4 * M], uint32_t (&o)[4]) {
+    constexpr int V = 16 / R, S = M * R;
+    if constexpr (R >= 4) {
+#pragma unroll
+        for (int j = 0; j < V; ++j)
+#pragma unroll
+            for (int t = 0; t < R / 4; ++t) o[j * (R / 4) + t] = in[(j * S) / 4 + t];
+    } else {
+        constexpr int PER_WORD = 4 / R;
+        constexpr uint32_t MASK = R == 1 ? 0xffu : 0xffffu;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            uint32_t acc = 0;
+#pragma unroll
+            for (int b = 0; b < PER_WORD; ++b) {
+                const int byte = (q * PER_WORD + b) * S;   // element start in the span (never crosses a word)
+                acc |= ((in[byte / 4] >> (8 * (byte % 4))) & MASK) << (8 * R * b);
+            }
+            o[q] = acc;
+        }
+    }
+}
+
+// One thread's output vector of a strided select: 16 / R consecutive elements of
+// one output row, read as M 16-byte vectors at any alignment when the whole span
+// lies inside the box (loads through the caches: neighbouring lanes' spans share
+// lines), element by element at a row's end or the box's end.
+template <int R, int M>
+RR_HD void select_thread(const SelectArgs& a, uint32_t block, uint32_t tid) {
+    constexpr int V = 16 / R, S = M * R;
+    const uint32_t v = block * (uint32_t)NT + tid;
+    if (v >= a.nvec) return;
+    const uint32_t row = mdiv(v, a.mvpr);
+    const uint32_t col = v - row * a.vpr;
+    uint64_t off = 0;
+    uint32_t rem = row;
+#pragma unroll
+    for (int j = MAXR - 1; j >= 1; --j) {
+        if (j < a.nax) {
+            const uint32_t q = mdiv(rem, a.om[j]);
+            off += (uint64_t)(rem - q * a.on[j]) * a.sin[j];
+            rem = q;
+        }
+    }
+    if (a.nax >= 1) off += (uint64_t)rem * a.sin[0];
+    const uint32_t e0 = col * V;
+    const uint32_t cnt = umin(V, a.n - e0);
+    const uint8_t* p = reinterpret_cast<const uint8_t*>(a.src) + off + (uint64_t)e0 * S;
+    uint8_t* q = reinterpret_cast<uint8_t*>(a.dst) + ((uint64_t)row * a.n + e0) * R;
+    if (cnt == (uint32_t)V && reinterpret_cast<uint64_t>(p) + 16u * M <= a.src_end) {
+        uint32_t in[4 * M];
+#pragma unroll
+        for (int u = 0; u < M; ++u) gload16u<false>(p + 16 * u, *reinterpret_cast<uint32_t(*)[4]>(&in[4 * u]));
+        uint32_t o[4];
+        select_pack<R, M>(in, o);
+        gstore16u<true>(q, o);
+    } else {
+        for (uint32_t j = 0; j < cnt; ++j) {
+            uint32_t e[NWords<R>::value];
+            gload<R, false>(p + (uint64_t)j * S, e);
+            gstore<R>(q + (uint64_t)j * R, e);
+        }
+    }
+}
+
+// Workgroup-staged select for a box whose kept elements lie S bytes apart along
+// one run (no outer rows: nax == 0).  Workgroup `block` covers elements
+// [block * NT * V, +NT * V) of the run, whose input is one contiguous span of
+// NT * 16 * M bytes: the stage phase loads it with 16-byte vectors, lane after
+// lane (each load instruction of a wave reads 1 KiB of consecutive bytes), into
+// LDS; after the barrier the pack phase reads each thread's M vectors back from
+// LDS and writes its output vector.  Bytes of the span past the box's end are
+// not loaded.  lds: NT * 16 * M bytes.
+template <int R, int M>
+RR_HD void select_stage(const SelectArgs& a, uint32_t block, uint8_t* lds, uint32_t tid) {
+    const uint8_t* base = reinterpret_cast<const uint8_t*>(a.src) + (uint64_t)block * NT * 16u * M;
+    const uint64_t end = a.src_end;
+    uint32_t w[M][4];
+    bool full[M];
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+        const uint8_t* p = base + 16u * (u * NT + tid);
+        full[u] = reinterpret_cast<uint64_t>(p) + 16u <= end;
+        if (full[u]) gload16u<true>(p, w[u]);
+    }
+#pragma unroll
+    for (int u = 0; u < M; ++u) {
+        uint8_t* q = lds + 16u * (u * NT + tid);
+        if (full[u]) {
+            sstore<16>(q, w[u]);
+        } else {
+            const uint8_t* p = base + 16u * (u * NT + tid);
+            for (uint32_t i = 0; i < 16u && reinterpret_cast<uint64_t>(p + i) < end; ++i) {
+                uint32_t b[1];
+                gload<1, true>(p + i, b);
+                q[i] = (uint8_t)b[0];
+            }
+        }
+    }
+}
+
+template <int R, int M>
+RR_HD void select_pack_store(const SelectArgs& a, uint32_t block, const uint8_t* lds, uint32_t tid) {
+    constexpr int V = 16 / R;
+    const uint32_t v = block * (uint32_t)NT + tid;   // output vector of the run
+    if (v >= a.nvec) return;
+    const uint32_t e0 = v * V;
+    const uint32_t cnt = umin(V, a.n - e0);
+    const uint8_t* p = lds + 16u * M * tid;
+    uint8_t* q = reinterpret_cast<uint8_t*>(a.dst) + (uint64_t)e0 * R;
+    if (cnt == (uint32_t)V) {
+        uint32_t in[4 * M];
+#pragma unroll
+        for (int u = 0; u < M; ++u) sload<16>(p + 16 * u, *reinterpret_cast<uint32_t(*)[4]>(&in[4 * u]));
+        uint32_t o[4];
+        select_pack<R, M>(in, o);
+        gstore16u<true>(q, o);
+    } else {
+        for (uint32_t j = 0; j < cnt; ++j) {
+            uint32_t e[NWords<R>::value];
+            sload<R>(p + j * (uint32_t)(M * R), e);
+            gstore<R>(q + (uint64_t)j * R, e);
+        }
+    }
+}
+
 // ----------------------------------------------------------------- tiles
 struct TileCtx {
     uint64_t bin, bout;   // byte bases of the tile (absolute unless in table mode)
@@ -662,15 +793,25 @@ RR_HD uint64_t row_out(const TileArgs& a, uint32_t ia) {
 }
 
 // LDS byte address of (row ib, byte x): the 16-byte chunks of a row are rotated
-// by (ib / G) so that the G-row column reads of the write phase, made by lanes
-// on consecutive row groups, fall on different banks.
-template <int G>
+// by (ib / RG) so that the column reads of the write phase, where each lane reads
+// RG consecutive rows and neighbouring lanes the next groups of RG rows, fall on
+// different banks.
+template <int RG>
 RR_HD uint32_t lds_pos(const TileArgs& a, uint32_t ib, uint32_t x) {
-    const uint32_t rot = (ib / G) & a.rotmask;
+    const uint32_t rot = (ib / RG) & a.rotmask;
     uint32_t cc = (x >> 4) + rot;
     if (cc >= a.nch16) cc -= a.nch16;
     return ib * a.pitch + (cc << 4) + (x & 15u);
 }
+
+// Rows that share one chunk rotation in a tile of U-byte units and G x G
+// micro-tiles: G rows for micro-tiles; 16 / U rows when G = 1, where a lane
+// gathers one 16-byte output vector from 16 / U consecutive rows (with one row
+// per rotation step, lanes 16 / U rows apart would meet on a few banks: 6-9
+// conflict cycles per LDS read for 2- and 4-byte units).  Read and write phases
+// of a kernel use the same value.
+template <int U, int G>
+constexpr int rot_group() { return G > 1 ? G : 16 / U; }
 
 // Loads each thread keeps in flight before writing any of them to LDS.  Default
 // tiles are 16 KiB, i.e. four 16-byte vectors per thread: one batch, and few
@@ -679,7 +820,7 @@ constexpr int READ_BATCH = RR_READ_BATCH;
 
 // Read phase: rows of the tile (contiguous along the input's fastest axes) are
 // loaded with WIN-byte vectors and parked in LDS.
-template <int WIN, int G, int B, bool S>
+template <int WIN, int RG, int B, bool S>
 RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     constexpr int NWI = NWords<WIN>::value;
     const uint32_t total = a.TB * a.rch;
@@ -699,7 +840,7 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
             ok[u] = f < total && ib < t.TBv && x < rowvalid;
             if (!ok[u]) { ib = 0; x = 0; }
             gload<WIN, S>(reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x), w[u]);
-            lo[u] = lds_pos<G>(a, ib, x);
+            lo[u] = lds_pos<RG>(a, ib, x);
         }
 #pragma unroll
         for (int u = 0; u < B; ++u)
@@ -812,7 +953,7 @@ template <int U, bool S>
 RR_HD void read_ragged(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t tid) {
     read_rows<U, S>(
         t.TBv, t.TAv * a.R, [&](uint32_t r) { return t.bin + row_in(a, r); },
-        [&](uint32_t r, uint32_t x) { return lds_pos<1>(a, r, x); }, lds, tid);
+        [&](uint32_t r, uint32_t x) { return lds_pos<rot_group<U, 1>()>(a, r, x); }, lds, tid);
 }
 
 // Stacked read: TCv sub-tiles of msub input bytes each; when they are back to
@@ -846,11 +987,11 @@ RR_HD void read_tile(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t
     }
     if (a.flags & TF_IN_FLAT) { read_flat<B, S>(a, t, lds, tid); return; }
     switch (a.win) {
-        case 16: read_phase<16, G, B, S>(a, t, lds, tid); break;
-        case 8: read_phase<8, G, B, S>(a, t, lds, tid); break;
-        case 4: read_phase<4, G, B, S>(a, t, lds, tid); break;
-        case 2: read_phase<2, G, B, S>(a, t, lds, tid); break;
-        default: read_phase<1, G, B, S>(a, t, lds, tid); break;
+        case 16: read_phase<16, rot_group<U, G>(), B, S>(a, t, lds, tid); break;
+        case 8: read_phase<8, rot_group<U, G>(), B, S>(a, t, lds, tid); break;
+        case 4: read_phase<4, rot_group<U, G>(), B, S>(a, t, lds, tid); break;
+        case 2: read_phase<2, rot_group<U, G>(), B, S>(a, t, lds, tid); break;
+        default: read_phase<1, rot_group<U, G>(), B, S>(a, t, lds, tid); break;
     }
 }
 
@@ -864,28 +1005,41 @@ RR_HD void read_dispatch(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint
 
 // Write phase: each work item is a GxG micro-tile (G rows of the LDS tile, G
 // elements each), transposed in registers into G output vectors that lie along
-// the output's fastest axis.  Elements of k > 1 units go one unit at a time.
-// Ragged write: each output row (TBv elements of U bytes along the output's
-// fastest axis, any alignment) is written as 16-byte vectors gathered element
-// by element from LDS, plus its last (bytes % 16) / U elements one by one.
+// the output's fastest axis.
+// Ragged write: each output row (TBv elements of k units of U bytes along the
+// output's fastest axis, any alignment) is written as 16-byte vectors gathered
+// unit by unit from LDS, plus its last (bytes % 16) / U units one by one.  Unit
+// q of an output row is unit q % k of element q / k (an LDS row).
 template <int U, bool S>
 RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds, uint32_t tid) {
-    constexpr int EPV = 16 / U;   // elements per 16-byte vector
-    const uint32_t rowbytes = t.TBv * U;
+    constexpr int EPV = 16 / U;   // units per 16-byte vector
+    const uint32_t k = a.k;
+    const uint32_t rowbytes = t.TBv * a.R;
     const uint32_t nfull = rowbytes >> 4;
     const uint32_t per = nfull + ((rowbytes & 15u) / U);
     if (per == 0 || t.TAv == 0) return;
+    constexpr int RG = rot_group<U, 1>();   // == EPV: one output vector's rows share a rotation
+    // LDS address of unit q of output row ia
+    auto unit_at = [&](uint32_t ia, uint32_t q) {
+        if (k == 1) return lds_pos<RG>(a, q, ia * U);
+        const uint32_t ib = mdiv(q, a.mk);
+        return lds_pos<RG>(a, ib, (ia * k + (q - ib * k)) * U);
+    };
     for (RowWalk w(tid, per); w.row < t.TAv; w.step()) {
         const uint32_t ia = w.row;
         uint8_t* rowp = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia));
         if (w.col < nfull) {
-            const uint32_t ib0 = w.col * EPV;
+            const uint32_t q0 = w.col * EPV;
+            // element j of the vector: rows q0 + j (single-unit elements, one
+            // rotation group: one address, then a pitch per row) or unit q0 + j
+            const uint32_t base0 = k == 1 ? lds_pos<RG>(a, q0, ia * U) : 0u;
+            auto at = [&](uint32_t j) { return k == 1 ? base0 + j * a.pitch : unit_at(ia, q0 + j); };
             uint32_t o[4];
             if constexpr (U >= 4) {
 #pragma unroll
                 for (int j = 0; j < EPV; ++j) {
                     uint32_t e[NWords<U>::value];
-                    sload<U>(lds + lds_pos<1>(a, ib0 + j, ia * U), e);
+                    sload<U>(lds + at(j), e);
 #pragma unroll
                     for (int q = 0; q < U / 4; ++q) o[j * (U / 4) + q] = e[q];
                 }
@@ -897,7 +1051,7 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
 #pragma unroll
                     for (int b = 0; b < PER_WORD; ++b) {
                         uint32_t e[1];
-                        sload<U>(lds + lds_pos<1>(a, ib0 + q * PER_WORD + b, ia * U), e);
+                        sload<U>(lds + at(q * PER_WORD + b), e);
                         acc |= e[0] << (8 * U * b);
                     }
                     o[q] = acc;
@@ -905,10 +1059,10 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
             }
             gstore16u<S>(rowp + (w.col << 4), o);
         } else {
-            const uint32_t ib = nfull * EPV + (w.col - nfull);
+            const uint32_t q = nfull * EPV + (w.col - nfull);
             uint32_t e[NWords<U>::value];
-            sload<U>(lds + lds_pos<1>(a, ib, ia * U), e);
-            gstore<U, S>(rowp + (uint64_t)ib * U, e);
+            sload<U>(lds + unit_at(ia, q), e);
+            gstore<U, S>(rowp + (uint64_t)q * U, e);
         }
     }
 }
@@ -934,7 +1088,7 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
                     const uint32_t q = q0 + j;
                     const uint32_t ia = mdiv(q, a.mtb);
                     uint32_t e[NWords<U>::value];
-                    sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+                    sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, q - ia * a.TB, ia * U), e);
 #pragma unroll
                     for (int k = 0; k < U / 4; ++k) o[j * (U / 4) + k] = e[k];
                 }
@@ -948,7 +1102,7 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
                         const uint32_t q = q0 + w4 * PER_WORD + b;
                         const uint32_t ia = mdiv(q, a.mtb);
                         uint32_t e[1];
-                        sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+                        sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, q - ia * a.TB, ia * U), e);
                         acc |= e[0] << (8 * U * b);
                     }
                     o[w4] = acc;
@@ -959,7 +1113,7 @@ RR_HD void write_flat(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
             const uint32_t q = nfull * EPV + (c - nfull);
             const uint32_t ia = mdiv(q, a.mtb);
             uint32_t e[NWords<U>::value];
-            sload<U>(lds + lds_pos<1>(a, q - ia * a.TB, ia * U), e);
+            sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, q - ia * a.TB, ia * U), e);
             gstore<U, S>(base + (uint64_t)q * U, e);
         }
     }
@@ -1096,7 +1250,7 @@ RR_HD void write_tile(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
             if (ia0 < t.TAv && ib0 < t.TBv) {
                 uint32_t r[G][NW];
 #pragma unroll
-                for (int j = 0; j < G; ++j) sload<W>(lds + lds_pos<G>(a, ib0 + j, ia0 * U), r[j]);
+                for (int j = 0; j < G; ++j) sload<W>(lds + lds_pos<rot_group<U, G>()>(a, ib0 + j, ia0 * U), r[j]);
                 uint32_t o[G][NW];
                 xpose<U, G>(r, o);
                 if (a.flags & TF_OUT_TABLE) {
@@ -1134,7 +1288,7 @@ RR_HD void write_tile(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
             const uint32_t s = m - ib * a.k;
             if (ia < t.TAv && ib < t.TBv) {
                 uint32_t v[NWords<U>::value];
-                sload<U>(lds + lds_pos<1>(a, ib, (ia * a.k + s) * U), v);
+                sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, ib, (ia * a.k + s) * U), v);
                 gstore<U, S>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
             }
         }
@@ -1177,12 +1331,10 @@ RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, co
     if (!(a.flags & TF_XCD)) return ranges[j].first + lb;
     const uint32_t n = prefix[j + 1] - prefix[j], q0 = prefix[j] % NXCD;
     const uint32_t v = lb + q0, x = v % NXCD, k = v / NXCD;
-    uint32_t start = 0;   // tiles of the XCDs before x: y + 8k in [q0, q0 + n), k >= (y < q0)
-    for (uint32_t y = 0; y < x; ++y) {
-        const uint32_t kmin = y < q0 ? 1u : 0u;
-        const uint32_t upto = q0 + n > y ? (q0 + n - y + NXCD - 1) / NXCD : 0u;
-        start += upto > kmin ? upto - kmin : 0u;
-    }
+    // tiles of the XCDs before x: the virtual indices in [q0, q0 + n) whose XCD is
+    // below x, i.e. #{u < q0 + n : u % 8 < x} - #{u < q0 : u % 8 < x} (q0 < 8)
+    const uint32_t m = q0 + n;
+    const uint32_t start = (m / NXCD) * x + umin(m % NXCD, x) - umin(q0, x);
     return ranges[j].first + start + k - (x < q0 ? 1u : 0u);
 }
 

@@ -9,6 +9,9 @@
 //               Table 1, which the paper measures as a memcpy).
 //  * k_run   -- permutes whose fastest axis stays fastest: every output run is
 //               a contiguous input run, copied with vector loads and stores.
+//  * k_select -- boxes that keep a strided fastest axis (one component of
+//               interleaved records): whole records are read with 16-byte
+//               vectors and the kept bytes packed in registers.
 //  * k_tile  -- a true transpose between the input's fastest axis (or axes) and
 //               the output's fastest axis (or axes), staged through an LDS
 //               tile (Sec. III.B's shared-memory tile; Sec. III.C's shared
@@ -50,6 +53,18 @@ __global__ __launch_bounds__(NT) void k_gather(const GatherArgs a) {
 template <int W>
 __global__ __launch_bounds__(NT) void k_run(const RunArgs a) {
     run_thread<W>(a, blockIdx.x, threadIdx.x);
+}
+
+template <int R, int M>
+__global__ __launch_bounds__(NT) void k_select(const SelectArgs a) {
+    if (a.nax == 0) {   // one run: stage the workgroup's span through LDS
+        __shared__ __attribute__((aligned(16))) uint8_t lds[NT * 16 * M];
+        select_stage<R, M>(a, blockIdx.x, lds, threadIdx.x);
+        __syncthreads();
+        select_pack_store<R, M>(a, blockIdx.x, lds, threadIdx.x);
+    } else {
+        select_thread<R, M>(a, blockIdx.x, threadIdx.x);
+    }
 }
 
 template <int U, int G>
@@ -122,6 +137,27 @@ hipError_t launch_stencil(const StencilArgs& a, hipStream_t st) {
     }
 }
 
+template <int R>
+static hipError_t launch_select_r(const SelectArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.M) {
+        case 2: hipLaunchKernelGGL((k_select<R, 2>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_select<R, 3>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_select<R, 4>), dim3(grid), dim3(NT), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+static hipError_t launch_select(const SelectArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.R) {
+        case 1: return launch_select_r<1>(a, grid, st);
+        case 2: return launch_select_r<2>(a, grid, st);
+        case 4: return launch_select_r<4>(a, grid, st);
+        case 8: return launch_select_r<8>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_plan(const Plan& p, hipStream_t st) {
     switch (p.kind) {
         case K_EMPTY:
@@ -146,6 +182,8 @@ hipError_t launch_plan(const Plan& p, hipStream_t st) {
             return hipGetLastError();
         case K_TILE:
             return launch_tile(p.tile, p.grid, st);
+        case K_SELECT:
+            return launch_select(p.select, p.grid, st);
         case K_GATHER:
             switch (p.gather.wbytes) {
                 case 16: hipLaunchKernelGGL(k_gather<16>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;

@@ -465,6 +465,40 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
     return RR_OK;
 }
 
+// Strided select: the fastest output axis is the fastest input axis, whose input
+// stride S is 2..4 elements of R = 1, 2, 4 or 8 bytes.  Returns false (nothing
+// planned) for any other shape, alignment or size.
+static bool plan_select(uint64_t dst, uint64_t src, const Canon& c, Plan* p) {
+    const int r = c.rank;
+    const int64_t R = c.elem_bytes, S = c.sinb[r - 1];
+    if (!(R == 1 || R == 2 || R == 4 || R == 8) || S % R != 0) return false;
+    const int64_t M = S / R;
+    if (M < 2 || M > 4 || addr_align(src) < R || addr_align(dst) < R) return false;
+    const int64_t n = c.dims[r - 1];
+    const int64_t V = 16 / R;
+    const int64_t vpr = (n + V - 1) / V;
+    const int64_t rows = c.count / n;
+    if (n > 0xffffffffLL || vpr * rows > 0x7fffffffLL) return false;
+    SelectArgs& a = p->select;
+    std::memset(&a, 0, sizeof a);
+    int64_t last = 0;   // byte offset of the box's last element
+    for (int k = 0; k < r; ++k) last += (c.dims[k] - 1) * c.sinb[k];
+    a.src = src; a.dst = dst; a.src_end = src + (uint64_t)(last + R);
+    a.n = (uint32_t)n; a.vpr = (uint32_t)vpr; a.mvpr = make_magic((uint32_t)vpr);
+    a.nvec = (uint32_t)(vpr * rows);
+    a.nax = r - 1;
+    for (int j = 0; j < r - 1; ++j) {   // outer output axes read input axes perm[j] (perm[r-1] = r-1)
+        a.on[j] = (uint32_t)c.dims[c.perm[j]];
+        a.om[j] = make_magic(a.on[j]);
+        a.sin[j] = (uint64_t)c.sinb[c.perm[j]];
+    }
+    a.S = (uint32_t)S; a.R = (uint32_t)R; a.M = (uint32_t)M;
+    p->kind = K_SELECT;
+    p->grid = (a.nvec + NT - 1) / NT;
+    p->bytes = (uint64_t)c.total_bytes;
+    return true;
+}
+
 static int default_row_bytes(int U, bool in_side) {
     switch (U) {
         case 1: return 128;
@@ -672,6 +706,12 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
     } else {
         a.nmb = a.TB * k;      // units per output row
         a.nwork = a.nmb * a.TA;
+        // Elements of k > 1 units (6, 12, 24 ... bytes): rows of any length move as
+        // 16-byte vectors at any alignment instead of one unit per access.
+        if (G == 1 && U < 16 && !(a.flags & (TF_OUT_TABLE | TF_IN_TABLE))) {
+            a.flags |= TF_RAGGED_OUT;
+            if ((a.flags & TF_IN_FLAT) == 0) a.flags |= TF_RAGGED_IN;
+        }
     }
     a.mnmb = make_magic(a.nmb);
     return RR_OK;
@@ -981,6 +1021,9 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     if (c.count == 0 || c.total_bytes == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (c.rank == 0) { plan_copy(dst, src, (uint64_t)c.total_bytes, p); return RR_OK; }
     if (c.elem_bytes >= RUN_MIN_BYTES) return plan_run(dst, src, c, p, why);
+    // a box whose fastest input axis is kept but strided (one component of
+    // interleaved records): whole records read with 16-byte vectors
+    if (c.perm[c.rank - 1] == c.rank - 1 && plan_select(dst, src, c, p)) return RR_OK;
     // a box whose fastest input axis is not contiguous (a dropped or cut innermost
     // axis) has no input rows to tile: gather its elements (one run each)
     if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
@@ -1076,7 +1119,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
 
 std::string describe(const Plan& p) {
     std::ostringstream o;
-    static const char* names[] = {"empty", "copy", "run", "tile", "gather"};
+    static const char* names[] = {"empty", "copy", "run", "tile", "gather", "select"};
     o << "class=" << names[p.kind];
     const Canon& c = p.c;
     o << " rank=" << c.rank << " dims=";
@@ -1087,6 +1130,7 @@ std::string describe(const Plan& p) {
     if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
     if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr;
     if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
+    if (p.kind == K_SELECT) o << " vec=16 stride=" << p.select.S << " m=" << p.select.M << " n=" << p.select.n;
     if (p.kind == K_TILE) {
         const TileArgs& a = p.tile;
         o << " unit=" << a.unit << " g=" << a.g << " k=" << a.k << " TA=" << a.TA << " TB=" << a.TB

@@ -46,7 +46,7 @@ struct Canon {
     int64_t total_bytes = 0;   // bytes per side
 };
 
-enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3, K_GATHER = 4 };
+enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3, K_GATHER = 4, K_SELECT = 5 };
 
 // ---------------------------------------------------------------- kernel args
 struct CopyArgs {
@@ -109,6 +109,28 @@ struct RunArgs {
     Magic om[MAXR];
     uint64_t sin[MAXR];   // input byte stride of output axis j
     uint64_t run_bytes;
+};
+
+// Strided select (a box that keeps the input's fastest axis but not every element
+// along it, e.g. one component of interleaved pixels): output rows of n elements
+// of R bytes, contiguous, whose input elements lie S = M * R bytes apart.  Each
+// thread reads the M 16-byte vectors that span 16 / R consecutive elements and
+// keeps one R-byte piece of every S bytes (M in 2..4, R in 1, 2, 4, 8).
+struct SelectArgs {
+    uint64_t src, dst;        // first element of the box; output
+    uint64_t src_end;         // one past the box's last byte: no load reaches beyond
+    uint32_t n;               // elements per output row (along the strided axis)
+    uint32_t vpr;             // 16-byte output vectors per row, ceil(n * R / 16)
+    Magic mvpr;
+    uint32_t nvec;            // output vectors in all rows
+    int32_t nax;              // outer axes (rows are their combinations)
+    uint32_t on[MAXR];        // outer output extents, slowest first
+    Magic om[MAXR];
+    uint64_t sin[MAXR];       // input byte stride of outer output axis j
+    uint32_t S;               // input byte stride of the strided axis
+    uint32_t R;               // bytes per element
+    uint32_t M;               // S / R
+    uint32_t pad_;
 };
 
 enum TileFlags : uint32_t {
@@ -257,6 +279,7 @@ struct Plan {
     RunArgs run;
     TileArgs tile;
     GatherArgs gather;
+    SelectArgs select;
     uint32_t grid = 0;       // workgroups to launch
     uint64_t bytes = 0;      // bytes per side
 };

@@ -15,9 +15,9 @@
 //   * jobs are validated and planned by the submitting thread, outside the
 //     server's lock (a job whose output the server allocates is planned for a
 //     256-byte aligned placeholder and moved to its buffer at admission); when
-//     the server has nothing queued and a slot is free, the submitting thread
-//     also admits and launches a job that needs no chunking itself, sparing it
-//     the hand-over to the server thread;
+//     the server is idle, the submitting thread also admits and launches a job
+//     that needs no chunking itself, sparing it the hand-over to the server
+//     thread;
 //   * the HBM budget caps the device memory the server has reserved (its arena
 //     slabs), not only the bytes in use; slabs with nothing left in them are
 //     given back when a job would otherwise not fit.
@@ -482,7 +482,11 @@ struct rr_server {
                     // pieces and pays a batch launch for each; any waiting job brings the
                     // pieces back to one chunk, so it is launched after at most one.
                     const bool others_waiting = !pending.empty() || large.size() > 1;
-                    for (size_t k = 0; k < large.size() && entries.size() < maxjobs;) {
+                    // pieces alone never take the last free slot: a job arriving next
+                    // starts at once beside them instead of waiting for a piece to end
+                    const bool pieces_may_go = !pending.empty() || (int)inflight.size() + 1 < std::max(1, cfg.max_inflight) ||
+                                               cfg.max_inflight == 1;
+                    for (size_t k = 0; pieces_may_go && k < large.size() && entries.size() < maxjobs;) {
                         JobState* j = large[k];
                         j->piece_mult = others_waiting ? 1u : std::min<uint32_t>(j->piece_mult * 2, 16);
                         const uint32_t n = (uint32_t)std::min<uint64_t>((uint64_t)j->chunk_blocks * j->piece_mult,
@@ -666,11 +670,13 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
         return RR_OK;
     }
     s->last_activity = raw->t_submit;
-    // Idle fast path: nothing queued, a slot free, no chunking -- admit and launch
-    // here instead of handing the job to the server thread.
+    // Idle fast path: nothing queued or in flight, no chunking -- admit and launch
+    // here instead of handing the job to the server thread.  Only when the server
+    // is idle: under load the launch would cost the submitting thread its time
+    // while the server thread batches it just as fast.
     int slot = -1;
-    if (s->pending.empty() && s->large.empty() && raw->chunk_blocks == 0 && !s->fail_next &&
-        (slot = s->free_slot()) >= 0) {
+    if (s->pending.empty() && s->large.empty() && s->inflight.empty() && raw->chunk_blocks == 0 &&
+        !s->fail_next && (slot = s->free_slot()) >= 0) {
         const Admit a = s->admit(raw);
         if (a == Admit::NO_MEMORY) {
             s->complete(raw, now_ns());

@@ -209,6 +209,29 @@ static void run_gather_w(const GatherArgs& a, uint32_t grid) {
         for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) g_bad += gather_thread<W>(a, b, grid, tid);
 }
 
+template <int R, int M>
+static void run_select_rm(const SelectArgs& a, uint32_t grid) {
+    for (uint32_t b = 0; b < grid; ++b) {
+        if (a.nax == 0) {
+            std::vector<uint8_t> lds(NT * 16 * M, 0xA5);
+            for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) select_stage<R, M>(a, b, lds.data(), tid);
+            for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) select_pack_store<R, M>(a, b, lds.data(), tid);
+        } else {
+            for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) select_thread<R, M>(a, b, tid);
+        }
+    }
+}
+
+template <int R>
+static bool run_select_r(const SelectArgs& a, uint32_t grid) {
+    switch (a.M) {
+        case 2: run_select_rm<R, 2>(a, grid); return true;
+        case 3: run_select_rm<R, 3>(a, grid); return true;
+        case 4: run_select_rm<R, 4>(a, grid); return true;
+    }
+    return false;
+}
+
 static bool emulate(const Plan& p) {
     switch (p.kind) {
         case K_EMPTY: return true;
@@ -230,6 +253,14 @@ static bool emulate(const Plan& p) {
             }
         case K_TILE:
             return run_tile(p.tile, p.grid);
+        case K_SELECT:
+            switch (p.select.R) {
+                case 1: return run_select_r<1>(p.select, p.grid);
+                case 2: return run_select_r<2>(p.select, p.grid);
+                case 4: return run_select_r<4>(p.select, p.grid);
+                case 8: return run_select_r<8>(p.select, p.grid);
+            }
+            return false;
         case K_GATHER:
             switch (p.gather.wbytes) {
                 case 16: run_gather_w<16>(p.gather, p.grid); return true;

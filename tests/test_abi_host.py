@@ -363,7 +363,8 @@ def test_reorder_validation_and_aliasing():
 
 def test_reorder_plans_match_permute_and_classes():
     """A full box with every axis kept plans exactly like rr_permute; boxes that
-    keep the input's fastest axis contiguous tile; dropping or cutting it gathers."""
+    keep the input's fastest axis contiguous tile; keeping it strided by 2-4 elements
+    selects; dropping it or a wider stride gathers."""
     for dims, perm, e in [((512, 512, 256), (2, 0, 1), 4), ((64, 128, 128, 64), (0, 3, 1, 2), 2), ((4096, 4096), (1, 0), 1)]:
         a = rr.reorder_describe(dims, None, None, perm, e, dst=1 << 20, src=1 << 30)
         b = rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30)
@@ -371,9 +372,15 @@ def test_reorder_plans_match_permute_and_classes():
     # a 2-D crop of a 3-D array, transposed: strided box, tile class
     d = rr.reorder_describe((70, 90, 40), (3, 5, 7), (60, 80, 30), (2, 1, 0), 4, dst=1 << 20, src=1 << 30)
     assert d["class"] == "tile" and d["dims"] == "60,80,30"
-    # channel 2 of an HWC image: the fastest axis is dropped -> gather
+    # channel 2 of an HWC image: the kept fastest axis is strided (4 bytes apart) -> select
     d = rr.reorder_describe((256, 256, 4), (0, 0, 2), None, (0, 1), 1, dst=1 << 20, src=1 << 30)
-    assert d["class"] == "run" and d["dims"] == "65536"
+    assert d["class"] == "select" and d["dims"] == "65536" and d["stride"] == "4" and d["m"] == "4"
+    # one channel of 5-channel records (stride of 5 elements): gathered element by element
+    d = rr.reorder_describe((256, 256, 5), (0, 0, 2), None, (0, 1), 1, dst=1 << 20, src=1 << 30)
+    assert d["class"] == "run"
+    # a column of a matrix (the fastest axis dropped) -> gather
+    d = rr.reorder_describe((100, 64), (0, 7), (100, 1), (0,), 4, dst=1 << 20, src=1 << 30)
+    assert d["class"] == "run"
     # rows 10..19 of a matrix: one contiguous range -> copy
     d = rr.reorder_describe((100, 64), (10, 0), (10, 64), (0, 1), 4, dst=1 << 20, src=1 << 30)
     assert d["class"] == "copy" and d["bytes"] == str(10 * 64 * 4)

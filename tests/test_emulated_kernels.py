@@ -312,6 +312,36 @@ def test_emu_reorder_offsets_and_unaligned_micro_tiles():
         assert np.array_equal(out, ref), (j["dims"], j["base"], j["range"], j["order"], st)
 
 
+SELECT_CASES = [
+    # one channel of interleaved records: (dims, base, range, order, element bytes)
+    ((64, 96, 4), (0, 0, 2), (64, 96, 1), (0, 1), 1),          # RGBA plane, fused to one row
+    ((64, 96, 4), (0, 0, 3), (64, 96, 1), (0, 1), 1),          # last channel: the span ends at the buffer's end
+    ((50, 64, 4), (3, 5, 1), (40, 50, 1), (0, 1), 1),          # a crop: rows of 50, not a multiple of 16
+    ((33, 17, 3), (0, 0, 1), (33, 17, 1), (0, 1), 4),          # xyz floats, M = 3
+    ((40, 37, 2), (0, 0, 1), (40, 37, 1), (0, 1), 8),          # complex doubles, M = 2
+    ((7, 9, 11, 4), (1, 0, 2, 0), (5, 9, 9, 1), (1, 0, 2), 2),  # outer axes transposed
+    ((300, 3), (0, 2), (300, 1), (0,), 2),                      # rank-1 output
+    ((31, 29, 2), (0, 0, 0), (31, 29, 1), (0, 1), 4),
+]
+
+
+def test_emu_reorder_strided_select():
+    """Boxes that keep a strided fastest axis (one component of interleaved
+    records) plan to the select kernel and match the oracle, at aligned and
+    offset pointers (an offset below the element size falls back to the gather)."""
+    jobs = [_reorder_job(*c[:4], c[4], 8600 + i) for i, c in enumerate(SELECT_CASES)]
+    jobs += [_reorder_job(*c[:4], c[4], 8700 + i, src_off=c[4] * 3, dst_off=c[4]) for i, c in enumerate(SELECT_CASES)]
+    jobs += [_reorder_job(*c[:4], c[4], 8800 + i, src_off=1, dst_off=3) for i, c in enumerate(SELECT_CASES)]
+    classes = []
+    for j, (st, out) in zip(jobs, emu_runner.run(jobs)):
+        assert st.startswith("ok"), st
+        ref = oracle.reorder_slice(j["input"], j["dims"], j["base"], j["range"], j["order"], j["esize"])
+        assert np.array_equal(out, ref), (j["dims"], j["base"], j["range"], j["order"], st)
+        classes.append(st.split("class=")[1].split()[0])
+    n = len(SELECT_CASES)
+    assert classes[:2 * n] == ["select"] * (2 * n), classes
+
+
 def test_emu_size_zero_and_one():
     jobs = [_perm_job((0, 5), (1, 0), 4, 1), _perm_job((5, 0, 3), (2, 0, 1), 2, 2),
             _perm_job((1, 1, 1), (2, 1, 0), 8, 3), _perm_job((1,), (0,), 16, 4),

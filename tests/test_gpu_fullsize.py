@@ -1,10 +1,14 @@
 """GPU parity at the full benchmark sizes, in the launch configuration the benchmark times.
 
-Outputs of up to 4 GiB are checked on sampled elements the oracle computes one
-by one (random positions plus the first and last 64 Ki elements), and the
-interlace workloads additionally round-trip through de-interlace.
+Every output element is compared with the oracle: outputs of up to 4 GiB are
+copied to the host whole and the oracle recomputes them piece by piece
+(oracle.permute_range, several pieces at once on host threads); interlace and
+de-interlace outputs likewise, plane range by plane range; every job of the
+4096-job batch and every served request whole.
 """
+import os
 import sys
+from concurrent.futures import ThreadPoolExecutor
 
 import numpy as np
 import pytest
@@ -16,7 +20,9 @@ pytestmark = [pytest.mark.gpu, pytest.mark.slow]
 
 torch = pytest.importorskip("torch")
 
-NSAMPLE = 200_000
+# host threads for the oracle (the host's share of cores for one GPU)
+WORKERS = max(1, min(16, len(os.sched_getaffinity(0))))
+PIECE = 1 << 23          # output elements per oracle piece
 
 
 def _say(*a):
@@ -40,12 +46,23 @@ def pool():
     return host, dev
 
 
-def _sample_idx(n, seed):
-    g = rr_synth.rng(seed)
-    head = np.arange(min(n, 65536), dtype=np.int64)
-    tail = np.arange(max(0, n - 65536), n, dtype=np.int64)
-    rnd = g.integers(0, n, size=min(n, NSAMPLE), dtype=np.int64)
-    return np.unique(np.concatenate([head, tail, rnd]))
+def first_mismatch(x, dims, perm, e, got):
+    """Compare a whole permute output (flat host bytes) with the oracle, piece by
+    piece on WORKERS threads; the first mismatching output element, or None."""
+    n = int(np.prod(dims, dtype=np.int64))
+    assert got.size == n * e
+
+    def piece(a):
+        c = min(PIECE, n - a)
+        ref = oracle.permute_range(x, dims, perm, e, a, c)
+        mine = got[a * e:(a + c) * e]
+        if np.array_equal(mine, ref):
+            return None
+        return a + int(np.nonzero((mine.reshape(c, e) != ref.reshape(c, e)).any(axis=1))[0][0])
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        bad = [r for r in ex.map(piece, range(0, n, PIECE)) if r is not None]
+    return min(bad) if bad else None
 
 
 @pytest.mark.parametrize("case", list(range(len(rr_synth.DENSE_CASES))))
@@ -63,33 +80,51 @@ def test_dense_full_size(rr, pool, case):
                             stream=torch.cuda.current_stream().cuda_stream)
         assert st == 0, rr.last_error()
         torch.cuda.synchronize()
-        idx = _sample_idx(n, case * 100 + e)
-        got = out.view(n, e)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
-        ref = oracle.permute_at(host[:nb], dims, perm, e, idx)
-        assert np.array_equal(got, ref), (name, perm, e)
+        bad = first_mismatch(host[:nb], dims, perm, e, out.cpu().numpy())
+        assert bad is None, (name, perm, e, "first wrong output element", bad)
 
 
 @pytest.mark.parametrize("case", list(range(len(rr_synth.INTERLACE_CASES))))
 def test_interlace_full_size(rr, pool, case):
+    """Interlace of n planes of the pool, and de-interlace of the pool's first n
+    planes' bytes read as one joined buffer: every output byte against the
+    oracle, plane range by plane range; the joined output also round-trips."""
     host, dev = pool
     name, n, count, e = rr_synth.INTERLACE_CASES[case]
     pb = count * e
+    sh = torch.cuda.current_stream().cuda_stream
     _say(name, n, count, e)
     planes_dev = [dev[c * pb:(c + 1) * pb] for c in range(n)]
     joined = torch.empty(n * pb, dtype=torch.uint8, device="cuda")
-    st = rr.interlace_raw(joined.data_ptr(), [p.data_ptr() for p in planes_dev], count, e,
-                          stream=torch.cuda.current_stream().cuda_stream)
-    assert st == 0, rr.last_error()
+    assert rr.interlace_raw(joined.data_ptr(), [p.data_ptr() for p in planes_dev], count, e, stream=sh) == 0, \
+        rr.last_error()
     torch.cuda.synchronize()
-    idx = _sample_idx(count, 900 + case)
-    j = joined.view(count, n, e)[torch.from_numpy(idx).to("cuda")].cpu().numpy()
-    for c in range(n):
-        ref = host[c * pb:(c + 1) * pb].reshape(count, e)[idx]
-        assert np.array_equal(j[:, c, :], ref), (name, c)
-    # de-interlace the joined buffer back into planes: must equal the originals exactly
+    got = joined.cpu().numpy()
+
+    def inter(a):
+        b = min(count, a + PIECE)
+        ref = oracle.interlace([host[c * pb + a * e:c * pb + b * e] for c in range(n)], e)
+        return np.array_equal(got[a * n * e:b * n * e], ref)
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        assert all(ex.map(inter, range(0, count, PIECE))), (name, "interlace")
+    del got
+    # de-interlace of the pool's first n*pb bytes (random bits) into n planes
     outs = [torch.empty(pb, dtype=torch.uint8, device="cuda") for _ in range(n)]
-    st = rr.deinterlace_raw([o.data_ptr() for o in outs], joined.data_ptr(), count, e,
-                            stream=torch.cuda.current_stream().cuda_stream)
+    assert rr.deinterlace_raw([o.data_ptr() for o in outs], dev.data_ptr(), count, e, stream=sh) == 0, \
+        rr.last_error()
+    torch.cuda.synchronize()
+    planes = [o.cpu().numpy() for o in outs]
+
+    def deinter(a):
+        b = min(count, a + PIECE)
+        ref = oracle.deinterlace(host[a * n * e:b * n * e], n, e)
+        return all(np.array_equal(planes[c][a * e:b * e], ref[c]) for c in range(n))
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        assert all(ex.map(deinter, range(0, count, PIECE))), (name, "de-interlace")
+    # and the interlaced buffer splits back into the original planes
+    st = rr.deinterlace_raw([o.data_ptr() for o in outs], joined.data_ptr(), count, e, stream=sh)
     assert st == 0, rr.last_error()
     torch.cuda.synchronize()
     for c in range(n):
@@ -99,7 +134,7 @@ def test_interlace_full_size(rr, pool, case):
 def test_batched_workload_full_size(rr):
     """The benchmark's 4096-job batch (7.54 GB per side, seeded inputs on the device),
     through a tuned handle replayed as a hipGraph as the benchmark runs it; every job
-    compared with the oracle on its first and last elements plus 256 random ones."""
+    compared whole with the oracle."""
     import bench
     specs = rr_synth.sample_jobs(4096_0001, njobs=4096)
     src, dst, offs, sizes = bench._job_buffers(torch, specs)
@@ -113,21 +148,23 @@ def test_batched_workload_full_size(rr):
         torch.cuda.synchronize()
     finally:
         h.close()
-    for i, (s, o, nb) in enumerate(zip(specs, offs, sizes)):
-        n = nb // s["esize"]
-        x = src[o:o + nb].cpu().numpy()
-        y = dst[o:o + nb].cpu().numpy().reshape(n, s["esize"])
-        g = rr_synth.rng(7000 + i)
-        idx = np.unique(np.concatenate([[0, n - 1], g.integers(0, n, 256)])).astype(np.int64)
-        ref = oracle.permute_at(x, s["dims"], s["perm"], s["esize"], idx)
-        assert np.array_equal(y[idx], ref), (i, s)
+    xs, ys = src.cpu().numpy(), dst.cpu().numpy()
+
+    def job_ok(i):
+        s, o, nb = specs[i], offs[i], sizes[i]
+        return np.array_equal(ys[o:o + nb], oracle.permute(xs[o:o + nb], s["dims"], s["perm"], s["esize"]))
+
+    with ThreadPoolExecutor(WORKERS) as ex:
+        ok = list(ex.map(job_ok, range(len(specs))))
+    bad = [i for i, v in enumerate(ok) if not v]
+    assert not bad, [(i, specs[i]) for i in bad[:5]]
 
 
 def test_serving_workload_full_size(rr):
     """The serving benchmark's configuration (96 GiB budget, 64 MiB chunks, up to 1024
     jobs per batch, 4 streams) and job mix at full size: 3000 requests drawn from the
     4096-job distribution plus its four 1-4 GiB permutes, arriving in bursts while
-    earlier batches run; every result sampled against the oracle."""
+    earlier batches run; every result compared whole with the oracle."""
     import time
     small = rr_synth.sample_jobs(5_0001, njobs=4096)
     large = rr_synth.large_jobs(5_0002, count=4)
@@ -165,15 +202,11 @@ def test_serving_workload_full_size(rr):
             r = res[tickets[k]]
             assert r.status == 0, (k, s)
             _, t, nb = inputs[k]
-            n = nb // s["esize"]
             out = torch.empty(nb, dtype=torch.uint8, device="cuda")
             rr.check(rr.permute_raw(out.data_ptr(), r.dst, (nb,), (0,), 1, sh))
             torch.cuda.synchronize()
-            gi = rr_synth.rng(9000 + k)
-            idx = np.unique(np.concatenate([[0, n - 1], gi.integers(0, n, 256)])).astype(np.int64)
-            ref = oracle.permute_at(t.cpu().numpy(), s["dims"], s["perm"], s["esize"], idx)
-            got = out.view(n, s["esize"])[torch.from_numpy(idx).cuda()].cpu().numpy()
-            assert np.array_equal(got, ref), (k, s)
+            bad = first_mismatch(t.cpu().numpy(), s["dims"], s["perm"], s["esize"], out.cpu().numpy())
+            assert bad is None, (k, s, "first wrong output element", bad)
             srv.release(tickets[k])
         for p, _, _ in inputs:
             srv.free(p)

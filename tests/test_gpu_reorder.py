@@ -5,7 +5,7 @@ import pytest
 
 import oracle
 import rr_synth
-from tests.test_emulated_kernels import REORDER_CASES, random_boxes
+from tests.test_emulated_kernels import REORDER_CASES, SELECT_CASES, random_boxes
 
 pytestmark = pytest.mark.gpu
 
@@ -74,3 +74,21 @@ def test_reorder_with_unaligned_micro_tiles(rr):
             check(rr, d, b, r, o, e, 11400 + i)
     finally:
         rr.set_tile_override()
+
+
+def test_reorder_strided_select(rr):
+    """One component of interleaved records (the select kernel): every case at
+    aligned pointers, at element-aligned offsets, and at odd offsets (the gather)."""
+    for i, (d, b, r, o, e) in enumerate(SELECT_CASES):
+        assert rr.reorder_describe(d, b, r, o, e, 1 << 20, 1 << 30)["class"] == "select"
+        check(rr, d, b, r, o, e, 12000 + i)
+        check(rr, d, b, r, o, e, 12050 + i, soff=3 * e, doff=e)
+        check(rr, d, b, r, o, e, 12100 + i, soff=1, doff=3)
+
+
+def test_channel_of_rgba_image_full_size(rr):
+    """The benchmark's channel extraction: channel 2 of a 16384 x 16384 RGBA image
+    (1 GiB in, 256 MiB out), every output byte against the oracle."""
+    dims, base, rng, order, e = (16384, 16384, 4), (0, 0, 2), (16384, 16384, 1), (0, 1), 1
+    assert rr.reorder_describe(dims, base, rng, order, e, 1 << 20, 1 << 30)["class"] == "select"
+    check(rr, dims, base, rng, order, e, 12200)
