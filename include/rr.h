@@ -275,6 +275,10 @@ typedef struct {
     int32_t persistent;        /* persistent grids chosen                       */
     uint64_t bytes;            /* bytes per side moved by one launch            */
     double tuned_us;           /* best measured time of one launch (0 if untuned) */
+    int32_t tile_kib;          /* tile LDS size the planner shrinks to (0 = 16) */
+    int32_t cache;             /* tile cache policy, -1 = each job's own         */
+    int32_t fill;              /* odd-extent refit, -1 = built-in                */
+    int32_t force_ragged;      /* G = 1 rows of any alignment for every tile job */
 } rr_batch_info;
 
 rr_status rr_batch_create(const rr_job* jobs, int njobs, int flags, rr_batch** out);
@@ -292,17 +296,19 @@ rr_status rr_batch_destroy(rr_batch* b);
  * Serving: a background thread that owns HIP streams and an HBM budget. It
  * admits submitted permute jobs as budget and in-flight slots free up, and
  * keeps forming batches from whatever has arrived while earlier batches are
- * still running (continuous batching); consecutive batches go to different
- * streams so their work overlaps on the device.  A job whose launch would need
- * more than chunk_bytes of output is cut into ranges of its own workgroups
- * (each range rewrites a disjoint part of the output), at most one range per
- * batch, so small jobs keep flowing past it.  Results are identical to
- * rr_permute run alone.
+ * still running (continuous batching); each batch goes to the stream with the
+ * fewest batches in flight, so their work overlaps on the device.  A job with
+ * more than chunk_bytes of output is large: with max_inflight >= 2 it is
+ * launched whole, alone, on a stream of its own, beside the small jobs' batches
+ * (kernels on several streams share the device's compute units), and large
+ * jobs hold at most max_inflight - 1 slots; with max_inflight == 1 it is cut
+ * into ranges of its own workgroups (each rewrites a disjoint part of the
+ * output), one range per batch, so small jobs keep flowing past it.  Results
+ * are identical to rr_permute run alone.
  * Jobs are validated and planned by rr_serve_submit on the calling thread.  When
  * the server is idle (nothing queued, nothing in flight), rr_serve_submit also
- * admits and launches a job that needs no chunking itself (on the server's
- * streams and device).  Pieces of large jobs never take the last free slot on
- * their own, so a job that arrives meanwhile starts beside them.  The budget caps the device memory the server reserves (slabs of its
+ * admits and launches the job itself (on the server's streams and device) unless
+ * it is to be cut into ranges.  The budget caps the device memory the server reserves (slabs of its
  * arena, up to 256 MiB each, kept for reuse and given back when a job would
  * otherwise not fit), not only the bytes handed out.  A job whose output the
  * device refuses to allocate within the budget while no batch is in flight
@@ -311,9 +317,11 @@ rr_status rr_batch_destroy(rr_batch* b);
  */
 typedef struct rr_server rr_server;
 
-#define RR_SERVE_SIMULATED 1u  /* no GPU: memory is virtual, a batch "completes"
-                                  after bytes / sim_bytes_per_us microseconds;
-                                  exercises admission and batching on a host. */
+#define RR_SERVE_SIMULATED 1u  /* no GPU: memory is virtual, and the batches in
+                                  flight share a simulated sim_bytes_per_us of
+                                  read+write bandwidth equally, each costing its
+                                  bytes plus 2 us of launch; exercises admission
+                                  and batching on a host. */
 #define RR_SERVE_DIRECT 2u     /* baseline: every job is launched alone, in arrival
                                   order, exactly as rr_permute launches it (no
                                   batching, no chunking). */
@@ -324,7 +332,8 @@ typedef struct {
     int32_t max_batch_jobs;     /* whole jobs or chunks per batch (>= 1)             */
     int32_t queue_capacity;     /* pending submissions before RR_ERR_BUSY            */
     uint64_t hbm_budget_bytes;  /* cap on server-allocated device memory             */
-    uint64_t chunk_bytes;       /* output bytes per chunk of a large job (0 = never) */
+    uint64_t chunk_bytes;       /* output bytes above which a job is large (0 = none);
+                                   with one slot, bytes per range of a large job    */
     uint32_t tick_us;           /* longest idle wait of the server thread            */
     uint32_t flags;             /* RR_SERVE_SIMULATED                                */
     double sim_bytes_per_us;    /* simulated read+write bandwidth (simulated mode)   */

@@ -68,7 +68,9 @@ class JobResult(ctypes.Structure):
 class BatchInfo(ctypes.Structure):
     _fields_ = [("njobs", ctypes.c_int32), ("ngroups", ctypes.c_int32), ("in_row_bytes", ctypes.c_int32),
                 ("out_row_bytes", ctypes.c_int32), ("order_out", ctypes.c_int32),
-                ("persistent", ctypes.c_int32), ("bytes", ctypes.c_uint64), ("tuned_us", ctypes.c_double)]
+                ("persistent", ctypes.c_int32), ("bytes", ctypes.c_uint64), ("tuned_us", ctypes.c_double),
+                ("tile_kib", ctypes.c_int32), ("cache", ctypes.c_int32), ("fill", ctypes.c_int32),
+                ("force_ragged", ctypes.c_int32)]
 
 
 RR_BATCH_GRAPH, RR_BATCH_TUNE, RR_BATCH_PERSISTENT, RR_BATCH_SERIAL = 1, 2, 4, 8

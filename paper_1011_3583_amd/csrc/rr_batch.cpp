@@ -221,14 +221,16 @@ rr_status time_batch(rr_batch* b, hipStream_t st, double* us) {
 rr_status tune(rr_batch* b) {
     // row targets, traversal order, persistent grid, tile size (KiB), unaligned
     // micro-tiles, cache policy (-1: each job's own by line alignment), odd-extent
-    // refit (-1: built-in)
-    struct Cand { int in_rb, out_rb, order; bool persistent; int kib = 0, umt = 0, cache = -1, fill = -1; };
+    // refit (-1: built-in), G = 1 rows of any alignment for every tile job
+    struct Cand { int in_rb, out_rb, order; bool persistent; int kib = 0, umt = 0, cache = -1, fill = -1, ragged = 0; };
     const Cand cands[] = {{0, 0, 0, false}, {0, 0, 1, false}, {0, 0, 0, true}, {256, 512, 0, false},
                           {512, 256, 0, false}, {512, 512, 0, false}, {1024, 256, 0, false},
                           {256, 1024, 0, false}, {512, 256, 1, false}, {128, 256, 0, false},
                           {0, 0, 0, false, 0, 1}, {512, 512, 0, false, 32, 0},
                           {0, 0, 0, false, 0, 0, 0}, {0, 0, 0, false, 0, 0, 1}, {0, 0, 0, false, 0, 0, 2},
-                          {0, 0, 0, false, 0, 0, -1, 0}, {512, 256, 1, false, 0, 0, -1, 0}};
+                          {0, 0, 0, false, 0, 0, -1, 0}, {512, 256, 1, false, 0, 0, -1, 0},
+                          {512, 256, 1, false, 0, 0, -1, -1, 1}, {512, 256, 1, false, 0, 0, 3, -1, 1},
+                          {0, 0, -1, false, 0, 0, -1, -1, 1}};
     // the candidates run the batch on a stream of their own: let whatever the
     // caller has queued on the device finish first
     hipError_t se = hipDeviceSynchronize();
@@ -247,6 +249,7 @@ rr_status tune(rr_batch* b) {
         o.umt = c.umt;
         o.cache = c.cache;
         o.fill = c.fill;
+        o.force_ragged = c.ragged;
         BatchPlan p;
         std::string why;
         int bad;
@@ -268,6 +271,7 @@ rr_status tune(rr_batch* b) {
     b->opt.umt = bestc.umt;
     b->opt.cache = bestc.cache;
     b->opt.fill = bestc.fill;
+    b->opt.force_ragged = bestc.ragged;
     b->persistent = bestc.persistent;
     b->tuned_us = best;
     rs = plan_or_fail(b->jobs.data(), (int)b->jobs.size(), b->opt, &b->plan);
@@ -397,6 +401,10 @@ rr_status rr_batch_get_info(const rr_batch* b, rr_batch_info* out) {
     out->persistent = b->persistent ? 1 : 0;
     out->bytes = b->plan.bytes;
     out->tuned_us = b->tuned_us;
+    out->tile_kib = b->opt.tile_kib;
+    out->cache = b->opt.cache;
+    out->fill = b->opt.fill;
+    out->force_ragged = b->opt.force_ragged;
     return RR_OK;
 }
 

@@ -533,7 +533,10 @@ RR_HD void stencil_compute(const StencilArgs& a, uint32_t tile, const uint32_t* 
 
 // ----------------------------------------------------------------- run copy
 // Output is written contiguously; each W-byte vector is read from the input run
-// its output run maps to.
+// its output run maps to.  With a.ua (W = 16) runs of any length and alignment
+// move as unaligned 16-byte vectors, vector `part` of a run at byte
+// min(16 * part, run_bytes - 16): the last one overlaps its neighbour and
+// rewrites the same bytes.
 template <int W>
 RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
     constexpr int NW = NWords<W>::value;
@@ -542,9 +545,11 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
     constexpr int V = copy_vpt(W);
     const uint32_t base = block * (uint32_t)(NT * V) + tid;
     uint32_t w[V][NW];
+    uint64_t out[V];
 #pragma unroll
     for (int u = 0; u < V; ++u) {
         const uint32_t v = base + u * NT;
+        out[u] = (uint64_t)v * W;
         if (v < a.nvec) {
             const uint32_t run = mdiv(v, a.mvpr);
             const uint32_t part = v - run * a.vpr;
@@ -559,13 +564,27 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
                 }
             }
             off += (uint64_t)rem * a.sin[0];
+            if constexpr (W == 16) {
+                if (a.ua) {
+                    const uint64_t pos = (uint64_t)part * 16u < a.run_bytes - 16u ? (uint64_t)part * 16u
+                                                                                 : a.run_bytes - 16u;
+                    out[u] = (uint64_t)run * a.run_bytes + pos;
+                    gload16u<true>(src + off + pos, w[u]);
+                    continue;
+                }
+            }
             gload<W>(src + off + (uint64_t)part * W, w[u]);
         }
     }
 #pragma unroll
     for (int u = 0; u < V; ++u) {
         const uint32_t v = base + u * NT;
-        if (v < a.nvec) gstore<W>(dst + (uint64_t)v * W, w[u]);
+        if (v < a.nvec) {
+            if constexpr (W == 16) {
+                if (a.ua) { gstore16u<true>(dst + out[u], w[u]); continue; }
+            }
+            gstore<W>(dst + out[u], w[u]);
+        }
     }
 }
 

@@ -444,7 +444,11 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
         return true;
     };
     while (W > 1 && (src % W || dst % W || R % W || !strides_ok(W))) W >>= 1;
-    int64_t vpr = R / W;
+    // Runs that aligned 16-byte vectors do not fit (odd lengths or starts): 16-byte
+    // vectors at any alignment, the run's last vector ending at its last byte.
+    const bool ua = W < 16 && R >= 16;
+    if (ua) W = 16;
+    int64_t vpr = ua ? (R + 15) / 16 : R / W;
     int64_t nvec = c.count * vpr;
     if (vpr > 0xffffffffLL || nvec > 0xffffffffLL) {
         *why = "run-copy problem exceeds 2^32 vectors per launch";
@@ -452,6 +456,7 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
     }
     a.src = src; a.dst = dst; a.nvec = (uint32_t)nvec; a.vpr = (uint32_t)vpr;
     a.mvpr = make_magic((uint32_t)vpr); a.wbytes = W; a.nax = r; a.run_bytes = (uint64_t)R;
+    a.ua = ua ? 1u : 0u;
     for (int j = 0; j < r; ++j) {
         a.on[j] = (uint32_t)c.dims[c.perm[j]];
         a.om[j] = make_magic(a.on[j]);
@@ -1128,7 +1133,7 @@ std::string describe(const Plan& p) {
     for (int k = 0; k < c.rank; ++k) o << (k ? "," : "") << c.perm[k];
     o << " esize_bytes=" << c.elem_bytes << " bytes=" << p.bytes << " grid=" << p.grid;
     if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
-    if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr;
+    if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr << " ua=" << p.run.ua;
     if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
     if (p.kind == K_SELECT) o << " vec=16 stride=" << p.select.S << " m=" << p.select.M << " n=" << p.select.n;
     if (p.kind == K_TILE) {

@@ -109,6 +109,9 @@ struct RunArgs {
     Magic om[MAXR];
     uint64_t sin[MAXR];   // input byte stride of output axis j
     uint64_t run_bytes;
+    uint32_t ua;          // runs move as 16-byte vectors at any alignment, the last one
+                          // ending at the run's end (overlapping its neighbour: same bytes)
+    uint32_t pad_;
 };
 
 // Strided select (a box that keeps the input's fastest axis but not every element

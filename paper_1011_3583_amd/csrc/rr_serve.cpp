@@ -5,19 +5,23 @@
 //     server allocates it) fits in the HBM budget -- jobs that need no memory may
 //     pass a job that is waiting for memory;
 //   * while fewer than max_inflight batches are on the device, the thread forms
-//     the next batch from every admitted piece of work (at most max_batch_jobs):
-//     one chunk of each large job in progress, then newly admitted jobs;
-//   * a large job is cut into ranges of its own workgroups of about chunk_bytes
-//     of output each, so one huge permute never blocks small jobs for long;
-//   * batches are launched through the batched kernels on streams taken in turn,
-//     so consecutive batches overlap on the device; completion is observed with
-//     events and published to a completion queue;
+//     the next batch from the admitted jobs (at most max_batch_jobs);
+//   * a large job (output above chunk_bytes) with max_inflight >= 2 goes whole,
+//     in a launch of its own on its own stream: the device runs the small jobs'
+//     batches beside it (workgroups of kernels on several hardware queues share
+//     the CUs), so it delays them only by the bandwidth it takes, and large jobs
+//     hold at most max_inflight - 1 slots.  With one slot a batch blocks the
+//     device while it runs, so a large job is cut into ranges of its own
+//     workgroups (pieces of chunk_bytes of output and up), each batched with
+//     the jobs that arrived meanwhile;
+//   * each batch goes on the stream with the fewest batches in flight, so
+//     batches overlap on the device; completion is observed with events and
+//     published to a completion queue;
 //   * jobs are validated and planned by the submitting thread, outside the
 //     server's lock (a job whose output the server allocates is planned for a
 //     256-byte aligned placeholder and moved to its buffer at admission); when
-//     the server is idle, the submitting thread also admits and launches a job
-//     that needs no chunking itself, sparing it the hand-over to the server
-//     thread;
+//     the server is idle, the submitting thread also admits and launches the
+//     job itself, sparing it the hand-over to the server thread;
 //   * the HBM budget caps the device memory the server has reserved (its arena
 //     slabs), not only the bytes in use; slabs with nothing left in them are
 //     given back when a job would otherwise not fit.
@@ -87,9 +91,17 @@ class HipBackend : public Backend {
         hipError_t e = hipSetDevice(device);
         if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
         slots_.resize((size_t)nslots);
-        for (Slot& s : slots_)
+        for (Slot& s : slots_) {
             if ((e = hipEventCreateWithFlags(&s.ev, hipEventDisableTiming)) != hipSuccess)
                 return hip_fail(e, "hipEventCreate");
+            // job-table staging for batches of up to a few thousand jobs, allocated
+            // here: growing it while serving frees and pins memory, which waits for
+            // the whole device
+            if ((e = hipHostMalloc(&s.host, TABLE_BYTES, hipHostMallocDefault)) != hipSuccess)
+                return hip_fail(e, "pinned staging");
+            if ((e = hipMalloc(&s.dev, TABLE_BYTES)) != hipSuccess) return hip_fail(e, "device job table");
+            s.cap = TABLE_BYTES;
+        }
         streams_.resize((size_t)nstreams);
         for (hipStream_t& st : streams_)
             if ((e = hipStreamCreateWithFlags(&st, hipStreamNonBlocking)) != hipSuccess)
@@ -155,6 +167,7 @@ class HipBackend : public Backend {
     bool done(int slot) override { return hipEventQuery(slots_[(size_t)slot].ev) != hipErrorNotReady; }
 
    private:
+    static constexpr size_t TABLE_BYTES = 2u << 20;
     static void drain_stream(hipStream_t st, hipEvent_t ev, bool recorded) {
         if (!recorded || hipEventSynchronize(ev) != hipSuccess) (void)hipStreamSynchronize(st);
     }
@@ -176,7 +189,7 @@ class SimBackend : public Backend {
     SimBackend(double bytes_per_us, uint64_t device_bytes)
         : bpus_(bytes_per_us > 0 ? bytes_per_us : 4e6), cap_(device_bytes) {}
     rr_status init(int, int nslots, int) override {
-        done_at_.assign((size_t)nslots, 0);
+        left_.assign((size_t)nslots, 0.0);
         return RR_OK;
     }
     void* reserve(uint64_t bytes) override {
@@ -199,17 +212,36 @@ class SimBackend : public Backend {
     rr_status launch_single(int slot, int, const Plan& p) override { return occupy(slot, p.bytes); }
     bool done(int slot) override {
         std::lock_guard<std::mutex> lk(mu_);
-        return now_ns() >= done_at_[(size_t)slot];
+        advance(now_ns());
+        return left_[(size_t)slot] <= 0.0;
     }
 
    private:
-    // one device: batches share its bandwidth, each costs its bytes plus a launch
+    // One device whose bandwidth the batches in flight share equally (as
+    // workgroups of kernels on several streams share the CUs): a batch costs
+    // reading and writing its bytes plus 2 us of launch at the full rate.
     rr_status occupy(int slot, uint64_t bytes) {
         std::lock_guard<std::mutex> lk(mu_);
-        const uint64_t dur = (uint64_t)(2.0 * (double)bytes / bpus_ * 1e3) + 2000;
-        busy_until_ = std::max(busy_until_, now_ns()) + dur;
-        done_at_[(size_t)slot] = busy_until_;
+        advance(now_ns());
+        left_[(size_t)slot] = 2.0 * (double)bytes + 2.0 * bpus_;
         return RR_OK;
+    }
+    // run the simulated device up to time t (ns)
+    void advance(uint64_t t) {
+        if (t_ == 0 || t < t_) { t_ = t; return; }
+        const double per_ns = bpus_ * 1e-3;
+        while (t_ < t) {
+            int n = 0;
+            double first = 0.0;
+            for (double l : left_)
+                if (l > 0.0) { first = n == 0 ? l : std::min(first, l); ++n; }
+            if (n == 0) { t_ = t; break; }
+            const double rate = per_ns / n;               // bytes per ns for each batch
+            const double dt = std::min((double)(t - t_), first / rate);
+            for (double& l : left_)
+                if (l > 0.0) { l -= rate * dt; if (l < 1e-6 * bpus_) l = 0.0; }
+            t_ += std::max<uint64_t>(1, (uint64_t)dt);
+        }
     }
     double bpus_;
     uint64_t cap_;
@@ -217,8 +249,8 @@ class SimBackend : public Backend {
     uint64_t taken_ = 0;
     std::unordered_map<uint64_t, uint64_t> sizes_;
     uint64_t next_ = 0x200000000000ull;
-    uint64_t busy_until_ = 0;
-    std::vector<uint64_t> done_at_;
+    uint64_t t_ = 0;                  // simulated time reached (ns)
+    std::vector<double> left_;        // bytes each slot's batch has still to move
 };
 
 // ----------------------------------------------------------------- arena
@@ -345,9 +377,11 @@ struct JobState {
 
 struct InFlight {
     int slot;
+    int stream;
     std::vector<JobState*> jobs;
     uint64_t bytes;
     bool launched;   // false while a submitting thread is still launching it
+    bool large;      // a large job launched whole, alone
 };
 
 // Placeholder output address a job is planned for when the server allocates its
@@ -360,6 +394,7 @@ void rebase_dst(Plan& p, uint64_t dst) {
         case K_COPY: p.copy.dst = p.copy.dst - PLACEHOLDER_DST + dst; break;
         case K_RUN: p.run.dst = p.run.dst - PLACEHOLDER_DST + dst; break;
         case K_TILE: p.tile.dst = p.tile.dst - PLACEHOLDER_DST + dst; break;
+        case K_SELECT: p.select.dst = p.select.dst - PLACEHOLDER_DST + dst; break;
         default: break;
     }
 }
@@ -390,6 +425,8 @@ struct rr_server {
     bool fail_next = false;
     int next_stream = 0;
     int nstreams = 1;
+    std::vector<int> stream_load;   // batches in flight (or being launched) per stream
+    int large_inflight = 0;         // large jobs launched whole, not yet retired
     uint64_t last_activity = 0;   // last submission or launch (server thread's spin window)
     rr_serve_stats stats{};
     std::thread th;
@@ -425,6 +462,20 @@ struct rr_server {
         return Admit::OK;
     }
 
+    // The stream with the fewest batches in flight, in turn among equals (lock
+    // held): a batch queued behind a long one on its stream would wait for it
+    // even with other streams idle.
+    int take_stream() {
+        int best = next_stream;
+        for (int i = 1; i < nstreams; ++i) {
+            const int s = (next_stream + i) % nstreams;
+            if (stream_load[(size_t)s] < stream_load[(size_t)best]) best = s;
+        }
+        next_stream = (best + 1) % nstreams;
+        stream_load[(size_t)best]++;
+        return best;
+    }
+
     int free_slot() const {
         if ((int)inflight.size() >= std::max(1, cfg.max_inflight)) return -1;
         for (int s = 0; s < std::max(1, cfg.max_inflight); ++s) if (!slot_busy[(size_t)s]) return s;
@@ -432,8 +483,10 @@ struct rr_server {
     }
 
     // Finish a batch whose launch failed (lock held): release its slot, fail its jobs.
-    void fail_batch(int slot, std::vector<JobState*>& members) {
+    void fail_batch(int slot, int stream, bool large_launch, std::vector<JobState*>& members) {
         slot_busy[(size_t)slot] = false;
+        stream_load[(size_t)stream]--;
+        if (large_launch) large_inflight--;
         const uint64_t t = now_ns();
         for (JobState* j : members) {
             j->status = RR_ERR_HIP;
@@ -454,6 +507,7 @@ struct rr_server {
             std::vector<JobState*> members;
             int slot = -1, stream = 0;
             bool fail_this = false;
+            bool launch_large = false;
             {
                 std::unique_lock<std::mutex> lk(mu);
                 // retire finished batches
@@ -463,6 +517,8 @@ struct rr_server {
                     InFlight f = std::move(inflight[i]);
                     inflight.erase(inflight.begin() + (long)i);
                     slot_busy[(size_t)f.slot] = false;
+                    stream_load[(size_t)f.stream]--;
+                    if (f.large) large_inflight--;
                     stats.bytes_moved += f.bytes;
                     for (JobState* j : f.jobs) {
                         j->outstanding--;
@@ -476,17 +532,51 @@ struct rr_server {
                 const bool drain = stopping && large.empty() && inflight.empty();
                 slot = free_slot();
                 if (slot >= 0) {
+                    const int nslots = std::max(1, cfg.max_inflight);
+                    if (nslots > 1) {
+                        // Several slots: the device runs batches of different streams side
+                        // by side (their workgroups share the CUs), so a large job goes
+                        // whole, in a launch of its own, and the small jobs' batches run
+                        // beside it.  New jobs first; a large one is admitted and queued.
+                        // Large jobs hold at most nslots - 1 slots: one stays for the rest.
+                        bool head_blocked = false;
+                        for (auto it = pending.begin(); it != pending.end() && entries.size() < maxjobs;) {
+                            JobState* j = *it;
+                            if (head_blocked && j->own_dst && !drain) { ++it; continue; }
+                            const Admit a = admit(j);
+                            if (a == Admit::WAIT && !drain) { head_blocked = true; ++it; continue; }
+                            it = pending.erase(it);
+                            if (a == Admit::WAIT) j->status = RR_ERR_NO_MEMORY;
+                            if (j->status != RR_OK) { complete(j, now_ns()); continue; }
+                            if (j->plan.kind == K_EMPTY || j->plan.grid == 0) { complete(j, now_ns()); continue; }
+                            if (j->chunk_blocks) { large.push_back(j); continue; }
+                            entries.push_back({&j->plan, 0, j->plan.grid, j->plan.bytes});
+                            members.push_back(j);
+                            j->next_block = j->plan.grid;
+                            j->outstanding++;
+                            j->chunks++;
+                        }
+                        if (entries.empty() && !large.empty() && large_inflight + 1 < nslots) {
+                            JobState* j = large.front();
+                            large.pop_front();
+                            entries.push_back({&j->plan, j->next_block, j->plan.grid - j->next_block,
+                                               j->plan.bytes});
+                            members.push_back(j);
+                            j->next_block = j->plan.grid;
+                            j->outstanding++;
+                            j->chunks++;
+                            launch_large = true;
+                        }
+                    } else {
+                    // One slot: a batch blocks the device until it ends, so a large job
+                    // goes in pieces, each in a batch with the jobs that arrived meanwhile.
                     // One piece of every large job in progress, oldest first.  A piece is
                     // piece_mult chunks: while no other job is waiting the pieces double
                     // (up to 16 chunks), since a lone large job gains nothing from fine
                     // pieces and pays a batch launch for each; any waiting job brings the
                     // pieces back to one chunk, so it is launched after at most one.
                     const bool others_waiting = !pending.empty() || large.size() > 1;
-                    // pieces alone never take the last free slot: a job arriving next
-                    // starts at once beside them instead of waiting for a piece to end
-                    const bool pieces_may_go = !pending.empty() || (int)inflight.size() + 1 < std::max(1, cfg.max_inflight) ||
-                                               cfg.max_inflight == 1;
-                    for (size_t k = 0; pieces_may_go && k < large.size() && entries.size() < maxjobs;) {
+                    for (size_t k = 0; k < large.size() && entries.size() < maxjobs;) {
                         JobState* j = large[k];
                         j->piece_mult = others_waiting ? 1u : std::min<uint32_t>(j->piece_mult * 2, 16);
                         const uint32_t n = (uint32_t)std::min<uint64_t>((uint64_t)j->chunk_blocks * j->piece_mult,
@@ -520,12 +610,13 @@ struct rr_server {
                         j->chunks++;
                         if (j->next_block < j->plan.grid) large.push_back(j);
                     }
+                    }
                     if (entries.empty()) {
                         slot = -1;
                     } else {
                         slot_busy[(size_t)slot] = true;
-                        stream = next_stream;
-                        next_stream = (next_stream + 1) % nstreams;
+                        stream = take_stream();
+                        if (launch_large) large_inflight++;
                         fail_this = fail_next;
                         fail_next = false;
                         const uint64_t tl = now_ns();
@@ -566,8 +657,8 @@ struct rr_server {
                 if (st == RR_OK) st = be->launch(slot, stream, bp);
             }
             std::lock_guard<std::mutex> lk(mu);
-            if (st != RR_OK) fail_batch(slot, members);
-            else inflight.push_back(InFlight{slot, std::move(members), bp.bytes, true});
+            if (st != RR_OK) fail_batch(slot, stream, launch_large, members);
+            else inflight.push_back(InFlight{slot, stream, std::move(members), bp.bytes, true, launch_large});
             if (log_level() >= 3)
                 log_line(3, "serve: batch of " + std::to_string(entries.size()) + " entries, " +
                                 std::to_string(bp.bytes) + " bytes per side, slot " + std::to_string(slot) +
@@ -591,6 +682,7 @@ rr_status rr_serve_create(const rr_serve_config* cfg, rr_server** out) {
         s->be = std::make_unique<SimBackend>(cfg->sim_bytes_per_us, cfg->sim_device_bytes);
     else s->be = std::make_unique<HipBackend>();
     s->nstreams = std::min(cfg->max_inflight, 4);
+    s->stream_load.assign((size_t)s->nstreams, 0);
     rr_status st = s->be->init(cfg->device, cfg->max_inflight, s->nstreams);
     if (st != RR_OK) return st;
     s->arena = std::make_unique<Arena>(s->be.get(), cfg->hbm_budget_bytes);
@@ -675,7 +767,8 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
     // is idle: under load the launch would cost the submitting thread its time
     // while the server thread batches it just as fast.
     int slot = -1;
-    if (s->pending.empty() && s->large.empty() && s->inflight.empty() && raw->chunk_blocks == 0 &&
+    const bool whole_large = s->cfg.max_inflight > 1;   // large jobs launch whole (see the server loop)
+    if (s->pending.empty() && s->large.empty() && s->inflight.empty() && (raw->chunk_blocks == 0 || whole_large) &&
         !s->fail_next && (slot = s->free_slot()) >= 0) {
         const Admit a = s->admit(raw);
         if (a == Admit::NO_MEMORY) {
@@ -684,15 +777,16 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
         }
         if (a == Admit::OK) {
             s->slot_busy[(size_t)slot] = true;
-            const int stream = s->next_stream;
-            s->next_stream = (s->next_stream + 1) % s->nstreams;
+            const int stream = s->take_stream();
+            const bool is_large = raw->chunk_blocks != 0;
+            if (is_large) s->large_inflight++;
             raw->next_block = raw->plan.grid;
             raw->outstanding = 1;
             raw->chunks = 1;
             raw->t_launch = now_ns();
             s->stats.batches++;
             s->stats.chunks++;
-            s->inflight.push_back(InFlight{slot, {raw}, raw->plan.bytes, false});
+            s->inflight.push_back(InFlight{slot, stream, {raw}, raw->plan.bytes, false, is_large});
             lk.unlock();
             const rr_status ls = s->be->launch_single_from_caller(slot, stream, raw->plan);
             lk.lock();
@@ -703,7 +797,7 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
                 } else {
                     std::vector<JobState*> members = std::move(s->inflight[i].jobs);
                     s->inflight.erase(s->inflight.begin() + (long)i);
-                    s->fail_batch(slot, members);
+                    s->fail_batch(slot, stream, is_large, members);
                 }
                 break;
             }

@@ -646,3 +646,24 @@ def test_emu_stencil_fd_orders_and_box():
     for j, (st, out) in zip(jobs, emu_runner.run(jobs)):
         assert st.startswith("ok"), st
         check_stencil(out, j["grid"], j["radius"], j["weights"], j["shape"])
+
+
+UA_RUN_CASES = [
+    # permutes that keep the fastest axis, with output runs of R >= 64 bytes that
+    # aligned 16-byte vectors do not fit.  (dims, perm, element bytes, src offset, dst offset)
+    ((7, 9, 33), (1, 0, 2), 2, 3, 1),          # R = 66, both sides misaligned
+    ((4, 3, 4097), (1, 0, 2), 1, 1, 0),        # long odd runs
+    ((5, 6, 100), (1, 0, 2), 1, 0, 0),         # R = 100
+    ((3, 4, 5, 24), (2, 0, 1, 3), 4, 4, 0),    # R = 96 at 4-byte alignment, rank 4
+    ((6, 5, 9), (1, 0, 2), 8, 8, 8),           # R = 72 at 8-byte alignment
+    ((2, 3, 5, 127), (3, 1, 0, 2), 1, 0, 0),   # not a run: stays exact on the tile path
+]
+
+
+def test_emu_unaligned_run_vectors():
+    """Runs moved as 16-byte vectors at any alignment, the last one overlapping
+    its neighbour, against the oracle."""
+    jobs = [_perm_job(d, p, e, 8900 + i, src_off=so, dst_off=do) for i, (d, p, e, so, do) in enumerate(UA_RUN_CASES)]
+    res = _check(jobs)
+    for st, _ in res[:-1]:
+        assert "class=run" in st and "vec=16" in st and "ua=1" in st, st

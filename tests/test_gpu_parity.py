@@ -432,3 +432,16 @@ def test_unaligned_micro_tiles(rr):
             check_permute(rr, dims, perm, e, 9990 + i)
     finally:
         rr.set_tile_override()
+
+
+def test_unaligned_run_vectors(rr):
+    """Output runs of R >= 64 bytes that aligned 16-byte vectors do not fit move as
+    unaligned 16-byte vectors, the last of each run overlapping its neighbour."""
+    from tests.test_emulated_kernels import UA_RUN_CASES
+    big = [((64, 48, 1001), (1, 0, 2), 1, 3, 5), ((300, 200, 70), (1, 0, 2), 1, 1, 0),
+           ((40, 50, 30, 24), (2, 0, 1, 3), 4, 4, 12), ((500, 400, 9), (1, 0, 2), 8, 8, 0)]
+    for i, (dims, perm, e, so, do) in enumerate(list(UA_RUN_CASES) + big):
+        check_permute(rr, dims, perm, e, 9700 + i, soff=so, doff=do)
+    for dims, perm, e, so, do in big:
+        d = rr.plan_describe(dims, perm, e, (1 << 20) + do, (1 << 30) + so)
+        assert d["class"] == "run" and d["vec"] == "16" and d["ua"] == "1", d

@@ -1,6 +1,7 @@
 """GPU tests of the serving loop: jobs arriving while others run are admitted and
-batched, a large job is chunked and interleaved, and each result equals the
-same job run alone with rr_permute and the oracle (tolerance 0)."""
+batched, a large job runs whole beside them (several slots) or is cut into pieces
+interleaved with them (one slot), and each result equals the same job run alone
+with rr_permute and the oracle (tolerance 0)."""
 import sys
 import time
 
@@ -40,12 +41,13 @@ def _drain(srv, tickets, timeout=60.0):
     return res
 
 
-def test_mixed_arrivals_alone_equals_in_mix(rr):
+@pytest.mark.parametrize("slots", [3, 1])
+def test_mixed_arrivals_alone_equals_in_mix(rr, slots):
     specs = rr_synth.sample_jobs(11, njobs=300, total_range=(1e3, 3e5), footprint_cap=1 << 30)
-    specs.append({"dims": (4096, 8192), "perm": (1, 0), "esize": 4})           # 128 MiB, chunked
-    specs.append({"dims": (256, 512, 256), "perm": (2, 1, 0), "esize": 2})     # 64 MiB, chunked
+    specs.append({"dims": (4096, 8192), "perm": (1, 0), "esize": 4})           # 128 MiB, large
+    specs.append({"dims": (256, 512, 256), "perm": (2, 1, 0), "esize": 2})     # 64 MiB, large
     host = [rr_synth.random_bytes(5000 + i, int(np.prod(s["dims"])) * s["esize"]) for i, s in enumerate(specs)]
-    with rr.Server(8 << 30, max_inflight=3, max_batch_jobs=64, chunk_bytes=8 << 20) as srv:
+    with rr.Server(8 << 30, max_inflight=slots, max_batch_jobs=64, chunk_bytes=8 << 20) as srv:
         srcs = []
         for h in host:
             p = srv.alloc(h.size)
@@ -59,7 +61,7 @@ def test_mixed_arrivals_alone_equals_in_mix(rr):
         g = rr_synth.rng(3)
         order = list(g.permutation(len(specs)))
         tickets = {}
-        _say("serving", len(specs), "jobs")
+        _say("serving", len(specs), "jobs,", slots, "slots")
         for k, i in enumerate(order):
             s = specs[i]
             tickets[i] = srv.submit(0, srcs[i][0], s["dims"], s["perm"], s["esize"])
@@ -68,7 +70,8 @@ def test_mixed_arrivals_alone_equals_in_mix(rr):
         res = _drain(srv, tickets.values())
         st = srv.stats()
         assert st["batches"] >= 3 and st["completed"] == len(specs)
-        assert res[tickets[len(specs) - 2]].chunks > 1
+        big = res[tickets[len(specs) - 2]].chunks
+        assert big > 1 if slots == 1 else big == 1, (slots, big)
         for i, s in enumerate(specs):
             r = res[tickets[i]]
             assert r.status == 0, (i, s)

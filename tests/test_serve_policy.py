@@ -51,8 +51,40 @@ def test_budget_is_never_exceeded_and_outputs_are_released():
         assert st["completed"] == 60 and st["batches"] >= 4
 
 
-def test_large_job_is_chunked_and_small_jobs_pass_it():
+def test_large_job_runs_whole_beside_small_jobs():
+    """Several slots: a large job is launched whole, alone, and the small jobs'
+    batches run beside it (the simulated device shares its bandwidth)."""
     with rr.Server(8 << 30, max_inflight=2, max_batch_jobs=64, chunk_bytes=16 * MiB, simulated=True,
+                   sim_bytes_per_us=2_000.0) as srv:
+        big = srv.submit(0, 0x7e0000000000, (8192, 8192), (1, 0), 4)           # 256 MiB
+        time.sleep(0.002)
+        small = [srv.submit(0, 0x7f0000000000 + i * MiB, (64, 64), (1, 0), 4) for i in range(20)]
+        res = _wait(srv, [big] + small)
+        assert res[big].chunks == 1
+        assert all(res[t].chunks == 1 for t in small)
+        # every small job finished before the large one
+        assert max(res[t].t_done_ns for t in small) < res[big].t_done_ns
+        assert all(res[t].status == 0 for t in [big] + small)
+
+
+def test_large_jobs_leave_a_slot_for_small_ones():
+    """Large jobs hold at most max_inflight - 1 slots: with two slots the second
+    large job waits for the first, and a small job arriving meanwhile runs."""
+    with rr.Server(8 << 30, max_inflight=2, max_batch_jobs=64, chunk_bytes=16 * MiB, simulated=True,
+                   sim_bytes_per_us=4_000.0) as srv:
+        big = [srv.submit(0, 0x7e0000000000 + i * (1 << 30), (4096, 8192), (1, 0), 4) for i in range(2)]
+        time.sleep(0.002)
+        small = srv.submit(0, 0x7f0000000000, (64, 64), (1, 0), 4)
+        res = _wait(srv, big + [small])
+        assert all(r.status == 0 and r.chunks == 1 for r in res.values())
+        assert res[small].t_done_ns < res[big[0]].t_done_ns
+        assert res[big[1]].t_launch_ns >= res[big[0]].t_done_ns
+
+
+def test_large_job_is_cut_into_pieces_with_one_slot():
+    """One slot: a batch blocks the device, so the large job goes in pieces and
+    the small jobs ride in the batches beside them."""
+    with rr.Server(8 << 30, max_inflight=1, max_batch_jobs=64, chunk_bytes=16 * MiB, simulated=True,
                    sim_bytes_per_us=2_000.0) as srv:
         big = srv.submit(0, 0x7e0000000000, (8192, 8192), (1, 0), 4)           # 256 MiB
         time.sleep(0.002)
@@ -60,7 +92,6 @@ def test_large_job_is_chunked_and_small_jobs_pass_it():
         res = _wait(srv, [big] + small)
         assert res[big].chunks >= 3    # pieces grow while it is alone, shrink when the small jobs arrive
         assert all(res[t].chunks == 1 for t in small)
-        # every small job finished before the large one
         assert max(res[t].t_done_ns for t in small) < res[big].t_done_ns
         assert all(res[t].status == 0 for t in [big] + small)
 
@@ -196,9 +227,9 @@ def test_lone_job_on_idle_server_is_launched_at_submit():
 
 
 def test_lone_large_job_takes_growing_pieces():
-    """With nothing else waiting, the pieces of a large job double (1, 2, 4, 8, 16
-    chunks): a 256 MiB job at 16 MiB chunks goes out in five pieces, not sixteen."""
-    with rr.Server(8 << 30, max_inflight=2, max_batch_jobs=64, chunk_bytes=16 * MiB, simulated=True,
+    """One slot, nothing else waiting: the pieces of a large job double (1, 2, 4, 8,
+    16 chunks): a 256 MiB job at 16 MiB chunks goes out in five pieces, not sixteen."""
+    with rr.Server(8 << 30, max_inflight=1, max_batch_jobs=64, chunk_bytes=16 * MiB, simulated=True,
                    sim_bytes_per_us=200_000.0) as srv:
         big = srv.submit(0, 0x7e0000000000, (8192, 8192), (1, 0), 4)           # 256 MiB
         r = _wait(srv, [big])[big]
