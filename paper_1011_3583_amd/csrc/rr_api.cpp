@@ -364,7 +364,8 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, -1, 16, 64},    {0, 0, 1, 16, 64},      {512, 512, -1, 16, 64}, {0, 0, -1, 8, 0},
         {0, 0, 1, 8, 0},       {128, 128, -1, 8, 0},   {128, 128, 1, 8, 0},    {256, 128, -1, 8, 0},
         {0, 0, -1, 4, 0},      {0, 0, 1, 4, 0},        {128, 128, -1, 4, 0},   {64, 128, 1, 4, 0},
-        {128, 64, 1, 4, 0},    {0, 0, -1, 0, 0, 1},    {0, 0, 1, 0, 0, 1},     {0, 0, 0, 0, 0, 1},
+        {128, 64, 1, 4, 0},    {64, 256, -1, 4, 0},    {64, 256, -1, 16, 0},   {64, 256, -1, 16, 32},
+        {128, 128, -1, 16, 0}, {0, 0, -1, 0, 0, 1},    {0, 0, 1, 0, 0, 1},     {0, 0, 0, 0, 0, 1},
         {0, 0, -1, 0, 64, 1},  {512, 512, -1, 16, 64, 1}, {0, 0, -1, 0, 0, 0, 1}, {0, 0, 1, 0, 0, 0, 1},
         {0, 0, 0, 0, 0, 0, 1}, {512, 512, -1, 0, 64, 0, 1},
         {0, 0, -1, 0, 0, 0, 0, 0}, {0, 0, -1, 0, 0, 0, 0, 1}, {0, 0, -1, 0, 0, 1, 0, 1},

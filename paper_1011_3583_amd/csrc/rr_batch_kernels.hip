@@ -12,21 +12,10 @@
 
 namespace rr {
 
-// Waves per SIMD the batched tile kernels are built for (the register budget
-// follows: 512 / waves VGPRs per lane); 0 leaves the choice to the compiler.
-#ifndef RR_BATCH_TILE_WAVES
-#define RR_BATCH_TILE_WAVES 0
-#endif
-#if RR_BATCH_TILE_WAVES > 0
-#define RR_BATCH_TILE_ATTR __attribute__((amdgpu_waves_per_eu(RR_BATCH_TILE_WAVES, RR_BATCH_TILE_WAVES)))
-#else
-#define RR_BATCH_TILE_ATTR
-#endif
-
 // One launch per kernel family covers every job of a batch group; the
 // workgroup index walks the concatenation of the jobs' own launch grids.
 template <int U, int G>
-__global__ __launch_bounds__(NT) RR_BATCH_TILE_ATTR void k_batch_tile(const TileArgs* __restrict__ args,
+__global__ __launch_bounds__(NT) void k_batch_tile(const TileArgs* __restrict__ args,
                                                    const uint32_t* __restrict__ prefix,
                                                    const EntryRange* __restrict__ ranges, uint32_t njobs,
                                                    uint32_t total) {
