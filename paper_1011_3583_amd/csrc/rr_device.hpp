@@ -537,8 +537,8 @@ RR_HD void stencil_compute(const StencilArgs& a, uint32_t tile, const uint32_t* 
 // move as unaligned 16-byte vectors, vector `part` of a run at byte
 // min(16 * part, run_bytes - 16): the last one overlaps its neighbour and
 // rewrites the same bytes.
-template <int W>
-RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
+template <int W, bool S>
+RR_HD void run_body(const RunArgs& a, uint32_t block, uint32_t tid) {
     constexpr int NW = NWords<W>::value;
     const uint8_t* src = reinterpret_cast<const uint8_t*>(a.src);
     uint8_t* dst = reinterpret_cast<uint8_t*>(a.dst);
@@ -569,11 +569,11 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
                     const uint64_t pos = (uint64_t)part * 16u < a.run_bytes - 16u ? (uint64_t)part * 16u
                                                                                  : a.run_bytes - 16u;
                     out[u] = (uint64_t)run * a.run_bytes + pos;
-                    gload16u<true>(src + off + pos, w[u]);
+                    gload16u<S>(src + off + pos, w[u]);
                     continue;
                 }
             }
-            gload<W>(src + off + (uint64_t)part * W, w[u]);
+            gload<W, S>(src + off + (uint64_t)part * W, w[u]);
         }
     }
 #pragma unroll
@@ -586,6 +586,13 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
             gstore<W>(dst + out[u], w[u]);
         }
     }
+}
+
+// The load flavour is chosen once per launch (a uniform branch).
+template <int W>
+RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
+    if (a.cached) run_body<W, false>(a, block, tid);
+    else run_body<W, true>(a, block, tid);
 }
 
 // ----------------------------------------------------------------- strided select
@@ -1338,16 +1345,15 @@ RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
     return lo;
 }
 
-// Tile of workgroup b of entry j in a batch group.  Workgroups reach the XCDs
-// round-robin (workgroup b on XCD b % 8); with TF_XCD each XCD takes a
-// contiguous run of the entry's tiles, as block_to_tile does for a single
-// launch.  The entry's workgroups [prefix[j], prefix[j+1]) map one to one onto
-// its tiles [first, first + n): workgroup b is virtual index v = b - prefix[j] +
+// Block (tile, or run-copy block) of workgroup b of entry j in a batch group,
+// each XCD taking a contiguous run of the entry's blocks.  Workgroups reach the
+// XCDs round-robin (workgroup b on XCD b % 8); this gives each XCD a contiguous
+// run of the entry's blocks instead, as xcd_range does for a single launch.
+// The entry's workgroups [prefix[j], prefix[j+1]) map one to one onto its
+// blocks [first, first + n): workgroup b is virtual index v = b - prefix[j] +
 // prefix[j] % 8 (so v % 8 is its XCD), and XCD x's runs are laid out in x order.
-RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, const EntryRange* ranges,
-                                   uint32_t j, uint32_t b) {
+RR_HD uint32_t batch_xcd_block(const uint32_t* prefix, const EntryRange* ranges, uint32_t j, uint32_t b) {
     const uint32_t lb = b - prefix[j];
-    if (!(a.flags & TF_XCD)) return ranges[j].first + lb;
     const uint32_t n = prefix[j + 1] - prefix[j], q0 = prefix[j] % NXCD;
     const uint32_t v = lb + q0, x = v % NXCD, k = v / NXCD;
     // tiles of the XCDs before x: the virtual indices in [q0, q0 + n) whose XCD is
@@ -1355,6 +1361,12 @@ RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, co
     const uint32_t m = q0 + n;
     const uint32_t start = (m / NXCD) * x + umin(m % NXCD, x) - umin(q0, x);
     return ranges[j].first + start + k - (x < q0 ? 1u : 0u);
+}
+// Tile of workgroup b of entry j: XCD ranges with TF_XCD, else in order.
+RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, const EntryRange* ranges,
+                                   uint32_t j, uint32_t b) {
+    if (!(a.flags & TF_XCD)) return ranges[j].first + (b - prefix[j]);
+    return batch_xcd_block(prefix, ranges, j, b);
 }
 
 template <int W>
@@ -1368,7 +1380,8 @@ template <int W>
 RR_HD void batch_run_block(const RunArgs* args, const uint32_t* prefix, const EntryRange* ranges,
                            uint32_t njobs, uint32_t b, uint32_t tid) {
     const uint32_t j = find_job(prefix, njobs, b);
-    run_thread<W>(args[j], b - prefix[j] + ranges[j].first, tid);
+    const RunArgs& a = args[j];
+    run_thread<W>(a, a.cached ? batch_xcd_block(prefix, ranges, j, b) : b - prefix[j] + ranges[j].first, tid);
 }
 
 }  // namespace rr

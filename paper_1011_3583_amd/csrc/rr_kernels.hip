@@ -52,7 +52,9 @@ __global__ __launch_bounds__(NT) void k_gather(const GatherArgs a) {
 
 template <int W>
 __global__ __launch_bounds__(NT) void k_run(const RunArgs a) {
-    run_thread<W>(a, blockIdx.x, threadIdx.x);
+    // runs that share input lines: each XCD takes a contiguous range of blocks,
+    // so neighbouring runs meet in one L2
+    run_thread<W>(a, a.cached ? xcd_range(blockIdx.x, gridDim.x) : blockIdx.x, threadIdx.x);
 }
 
 template <int R, int M>

@@ -457,6 +457,15 @@ static rr_status plan_run(uint64_t dst, uint64_t src, const Canon& c, Plan* p, s
     a.src = src; a.dst = dst; a.nvec = (uint32_t)nvec; a.vpr = (uint32_t)vpr;
     a.mvpr = make_magic((uint32_t)vpr); a.wbytes = W; a.nax = r; a.run_bytes = (uint64_t)R;
     a.ua = ua ? 1u : 0u;
+    // Runs shorter than a 128-byte line that start or end inside lines share
+    // those lines with the runs beside them in the input: loads through the
+    // caches (with XCD-contiguous block ranges, so a line's second reader is on
+    // the same L2) find them there instead of fetching them again.  Measured
+    // +14-21 % on runs of 66-72 bytes; longer runs gain nothing and a 256-byte
+    // run at a 4-byte offset lost 40 %, so they stay streamed.
+    bool shared = (src % 128) != 0 || (R % 128) != 0;
+    for (int k = 0; k < r; ++k) shared = shared || (c.sinb[k] % 128) != 0;
+    a.cached = shared && R < 128 ? 1u : 0u;
     for (int j = 0; j < r; ++j) {
         a.on[j] = (uint32_t)c.dims[c.perm[j]];
         a.om[j] = make_magic(a.on[j]);
@@ -1133,7 +1142,8 @@ std::string describe(const Plan& p) {
     for (int k = 0; k < c.rank; ++k) o << (k ? "," : "") << c.perm[k];
     o << " esize_bytes=" << c.elem_bytes << " bytes=" << p.bytes << " grid=" << p.grid;
     if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
-    if (p.kind == K_RUN) o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr << " ua=" << p.run.ua;
+    if (p.kind == K_RUN)
+        o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr << " ua=" << p.run.ua << " cached=" << p.run.cached;
     if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
     if (p.kind == K_SELECT) o << " vec=16 stride=" << p.select.S << " m=" << p.select.M << " n=" << p.select.n;
     if (p.kind == K_TILE) {

@@ -111,7 +111,8 @@ struct RunArgs {
     uint64_t run_bytes;
     uint32_t ua;          // runs move as 16-byte vectors at any alignment, the last one
                           // ending at the run's end (overlapping its neighbour: same bytes)
-    uint32_t pad_;
+    uint32_t cached;      // runs share 128-byte input lines: loads through the caches, and
+                          // in batches each XCD takes a contiguous range of the job's blocks
 };
 
 // Strided select (a box that keeps the input's fastest axis but not every element

@@ -667,3 +667,19 @@ def test_emu_unaligned_run_vectors():
     res = _check(jobs)
     for st, _ in res[:-1]:
         assert "class=run" in st and "vec=16" in st and "ua=1" in st, st
+    # runs shorter than a line that share lines load through the caches, each XCD
+    # taking a contiguous range of blocks (R = 66, 100, 96, 72 here)
+    assert sum("cached=1" in st for st, _ in res) >= 3, res
+
+
+@pytest.mark.parametrize("chunk", [0, 2])
+def test_emu_cached_runs_in_batches(chunk):
+    """Short runs that share input lines, batched (each XCD a contiguous range of a
+    job's blocks), whole and cut into workgroup ranges, next to other jobs."""
+    jobs = [_perm_job(d, p, e, 9750 + i, src_off=so, dst_off=do) for i, (d, p, e, so, do) in enumerate(UA_RUN_CASES)]
+    jobs += [_perm_job((60, 70, 33), (1, 0, 2), 2, 9760), _perm_job((90, 11, 9), (1, 0, 2), 8, 9761),
+             _perm_job((33, 45, 77), (2, 0, 1), 8, 9762)]
+    st, outs = emu_runner.run([dict(op="batched", jobs=jobs, chunk=chunk)])[0]
+    assert st.startswith("ok"), st
+    for j, o in zip(jobs, outs):
+        assert np.array_equal(o, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), (j["dims"], chunk)

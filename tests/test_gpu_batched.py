@@ -180,3 +180,29 @@ def test_overlapping_jobs_rejected(rr):
                         (base + 20000, base + 2048, (32, 32), (1, 0), 4)])
     assert rr.permute_batched_raw(arr, 2, 0) == 3
     assert not x.any()  # nothing was launched
+
+
+def test_batched_short_runs_sharing_lines(rr):
+    """Runs of 64-127 bytes that share input lines load through the caches with each
+    XCD taking a contiguous range of a job's blocks: a batch of such jobs (and the
+    same jobs launched alone) equals the oracle."""
+    specs = [{"dims": (60, 70, 33), "perm": (1, 0, 2), "esize": 2}, {"dims": (90, 110, 9), "perm": (1, 0, 2), "esize": 8},
+             {"dims": (300, 200, 100), "perm": (1, 0, 2), "esize": 1}, {"dims": (40, 50, 30, 24), "perm": (2, 0, 1, 3), "esize": 4},
+             {"dims": (1001, 999), "perm": (1, 0), "esize": 4}]
+    J = Jobs(rr, specs, 9)
+    for s, j in zip(specs, J.arr):
+        d = rr.plan_describe(s["dims"], s["perm"], s["esize"], j.dst, j.src)
+        if d["class"] == "run":
+            assert d["cached"] == "1", d
+    _say("batched short runs", len(specs))
+    b = rr.Batch(J.arr, 0)
+    b.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    b.close()
+    _check_all_vs_oracle(J)
+    J.dst.zero_()
+    for i, s in enumerate(specs):
+        j = J.arr[i]
+        rr.check(rr.permute_raw(j.dst, j.src, s["dims"], s["perm"], s["esize"], torch.cuda.current_stream().cuda_stream))
+    torch.cuda.synchronize()
+    _check_all_vs_oracle(J)
