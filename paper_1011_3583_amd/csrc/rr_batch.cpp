@@ -27,11 +27,47 @@ struct Slot {
     bool used = false;
 };
 constexpr int RING = 4;
+// One-shot batches of at least this many jobs are planned and launched in chunks.
+constexpr int PIPE_MIN_JOBS = 2048;
 struct Ring {
     Slot slots[RING];
     int next = 0;
-    GroupFanout fan;   // side streams the groups of one-shot batched calls fan out on
+    GroupFanout fan;                // side streams the groups of one-shot batched calls fan out on
+    hipStream_t upload = nullptr;   // table copies of pipelined calls
+    hipEvent_t ready[RING] = {};    // slot k's table is in place (pipelined calls)
 };
+
+// Take the ring's next slot (ring lock held): wait for the batch that last used
+// it, grow its pinned and device buffers to `need` bytes.
+rr_status take_slot(Ring& ring, size_t need, int* index) {
+    const int k = ring.next;
+    Slot& s = ring.slots[k];
+    ring.next = (ring.next + 1) % RING;
+    if (s.used) {
+        hipError_t e = hipEventSynchronize(s.done);
+        if (e != hipSuccess) return hip_fail(e, "waiting for a staging slot");
+        s.used = false;
+    }
+    if (need > s.cap) {
+        if (s.host) (void)hipHostFree(s.host);
+        if (s.dev) (void)hipFree(s.dev);
+        s.host = s.dev = nullptr;
+        s.cap = 0;
+        size_t cap = std::max<size_t>(need, 1 << 20);
+        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
+            return fail(RR_ERR_NO_MEMORY, "pinned staging buffer");
+        if (hipMalloc(&s.dev, cap) != hipSuccess) {
+            (void)hipHostFree(s.host);
+            s.host = nullptr;
+            return fail(RR_ERR_NO_MEMORY, "device job table");
+        }
+        s.cap = cap;
+    }
+    if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
+        return fail(RR_ERR_HIP, "hipEventCreate");
+    *index = k;
+    return RR_OK;
+}
 std::mutex g_ring_mu;
 std::map<int, Ring> g_rings;
 
@@ -103,6 +139,59 @@ static uint64_t group_cost(const BatchGroup& g) {
     return (uint64_t)std::max<uint32_t>(g.total_blocks, 1) * (g.kind == K_TILE ? 8 : 1);
 }
 
+// Groups of one or more batch plans spread over a stream and the side streams
+// of a fanout, each plan's groups costliest first, each group to the stream
+// with the least estimated work queued so far (over every plan added).  A
+// stream starts a plan's groups only after that plan's `ready` event (its table
+// in place, the caller's earlier work done); end() makes the caller's stream
+// wait for every side stream used.
+class FanSession {
+   public:
+    FanSession(GroupFanout* fan, hipStream_t st) : st_(st) {
+        streams_[0] = st;
+        for (int k = 0; k < FANOUT_SIDE; ++k) streams_[k + 1] = fan->side[k];
+        fan_ = fan;
+    }
+    rr_status add(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device, hipEvent_t ready) {
+        std::vector<size_t> order(p.groups.size());
+        for (size_t i = 0; i < order.size(); ++i) order[i] = i;
+        std::stable_sort(order.begin(), order.end(),
+                         [&](size_t a, size_t b) { return group_cost(p.groups[a]) > group_cost(p.groups[b]); });
+        bool waited[FANOUT_SIDE + 1] = {};
+        for (size_t i : order) {
+            int s = 0;
+            for (int k = 1; k <= FANOUT_SIDE; ++k) if (load_[k] < load_[s]) s = k;
+            if (!waited[s]) {
+                hipError_t e = hipStreamWaitEvent(streams_[s], ready, 0);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
+                waited[s] = true;
+                used_[s] = true;
+            }
+            const BatchGroup& g = p.groups[i];
+            hipError_t e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), streams_[s]);
+            if (e != hipSuccess) return hip_fail(e, "batched launch");
+            load_[s] += group_cost(g);
+        }
+        return RR_OK;
+    }
+    rr_status end() {
+        for (int k = 1; k <= FANOUT_SIDE; ++k) {
+            if (!used_[k]) continue;
+            hipError_t e = hipEventRecord(fan_->join[k - 1], streams_[k]);
+            if (e == hipSuccess) e = hipStreamWaitEvent(st_, fan_->join[k - 1], 0);
+            if (e != hipSuccess) return hip_fail(e, "joining batch groups");
+        }
+        return RR_OK;
+    }
+
+   private:
+    hipStream_t st_;
+    GroupFanout* fan_;
+    hipStream_t streams_[FANOUT_SIDE + 1];
+    uint64_t load_[FANOUT_SIDE + 1] = {};
+    bool used_[FANOUT_SIDE + 1] = {};
+};
+
 rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool persistent, int device,
                             hipStream_t st, GroupFanout* fan) {
     if (!fan || !fan->fork || p.groups.size() < 2) {
@@ -112,37 +201,12 @@ rr_status launch_batch_plan(const BatchPlan& p, const uint8_t* dev_table, bool p
         }
         return RR_OK;
     }
-    // costliest groups first, each to the stream with the least estimated work queued
-    std::vector<size_t> order(p.groups.size());
-    for (size_t i = 0; i < order.size(); ++i) order[i] = i;
-    std::stable_sort(order.begin(), order.end(),
-                     [&](size_t a, size_t b) { return group_cost(p.groups[a]) > group_cost(p.groups[b]); });
-    hipStream_t streams[FANOUT_SIDE + 1] = {st};
-    for (int k = 0; k < FANOUT_SIDE; ++k) streams[k + 1] = fan->side[k];
-    uint64_t load[FANOUT_SIDE + 1] = {};
-    bool used[FANOUT_SIDE + 1] = {true};
     hipError_t e = hipEventRecord(fan->fork, st);
     if (e != hipSuccess) return hip_fail(e, "hipEventRecord");
-    for (size_t i : order) {
-        int s = 0;
-        for (int k = 1; k <= FANOUT_SIDE; ++k) if (load[k] < load[s]) s = k;
-        if (!used[s]) {
-            e = hipStreamWaitEvent(streams[s], fan->fork, 0);
-            if (e != hipSuccess) return hip_fail(e, "hipStreamWaitEvent");
-            used[s] = true;
-        }
-        const BatchGroup& g = p.groups[i];
-        e = launch_batch_group(g, dev_table, group_grid(g, persistent, device), streams[s]);
-        if (e != hipSuccess) return hip_fail(e, "batched launch");
-        load[s] += group_cost(g);
-    }
-    for (int k = 1; k <= FANOUT_SIDE; ++k) {
-        if (!used[k]) continue;
-        e = hipEventRecord(fan->join[k - 1], streams[k]);
-        if (e == hipSuccess) e = hipStreamWaitEvent(st, fan->join[k - 1], 0);
-        if (e != hipSuccess) return hip_fail(e, "joining batch groups");
-    }
-    return RR_OK;
+    FanSession fs(fan, st);
+    rr_status rs = fs.add(p, dev_table, persistent, device, fan->fork);
+    const rr_status re = fs.end();
+    return rs != RR_OK ? rs : re;
 }
 
 }  // namespace rr
@@ -279,12 +343,83 @@ rr_status tune(rr_batch* b) {
     return upload_table(b);
 }
 
+// Large one-shot batches: every job is validated first (an invalid batch
+// enqueues nothing), then the jobs are planned, staged and launched in up to
+// RING contiguous chunks (an eighth, a quarter, a quarter, the rest), so the GPU
+// runs the first chunks while the host plans the next.  The chunks' groups
+// share one fan-out over the caller's stream and the side streams; each
+// chunk's table goes up on the ring's upload stream after the caller's earlier
+// work, and a stream starts a chunk's groups once that chunk's table is in place.
+rr_status permute_batched_pipelined(const rr_job* jobs, int njobs, hipStream_t hs) {
+    std::string why;
+    int bad = -1;
+    rr_status st = validate_batch(jobs, njobs, &why, &bad);
+    if (st != RR_OK) {
+        if (bad >= 0) why = "job " + std::to_string(bad) + ": " + why;
+        return fail(st, why);
+    }
+    const TileOptions opt = current_tile_options();
+    int device = 0;
+    hipError_t e = hipGetDevice(&device);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    std::lock_guard<std::mutex> lk(g_ring_mu);
+    Ring& ring = g_rings[device];
+    st = fanout_init(&ring.fan);
+    if (st != RR_OK) return st;
+    for (hipEvent_t& ev : ring.ready)
+        if (!ev && hipEventCreateWithFlags(&ev, hipEventDisableTiming) != hipSuccess) {
+            ev = nullptr;
+            return fail(RR_ERR_HIP, "hipEventCreate");
+        }
+    if (!ring.upload && hipStreamCreateWithFlags(&ring.upload, hipStreamNonBlocking) != hipSuccess) {
+        ring.upload = nullptr;
+        return fail(RR_ERR_HIP, "table upload stream");
+    }
+    // uploads (and so every chunk's start) follow the caller's earlier work
+    e = hipEventRecord(ring.fan.fork, hs);
+    if (e == hipSuccess) e = hipStreamWaitEvent(ring.upload, ring.fan.fork, 0);
+    if (e != hipSuccess) return hip_fail(e, "ordering the table uploads");
+    static thread_local BatchPlan cp;
+    FanSession fs(&ring.fan, hs);
+    std::vector<int> slots;
+    const int64_t n = njobs;
+    const int64_t bounds[RING + 1] = {0, n / 8, 3 * n / 8, 5 * n / 8, n};
+    for (int c = 0; c < RING && st == RR_OK; ++c) {
+        const int lo = (int)bounds[c], hi = (int)bounds[c + 1];
+        if (hi <= lo) continue;
+        st = plan_or_fail(jobs + lo, hi - lo, opt, &cp);
+        if (st != RR_OK) break;
+        if (cp.groups.empty()) continue;
+        int k = 0;
+        if ((st = take_slot(ring, cp.table.size(), &k)) != RR_OK) break;
+        Slot& s = ring.slots[k];
+        std::memcpy(s.host, cp.table.data(), cp.table.size());
+        e = hipMemcpyAsync(s.dev, s.host, cp.table.size(), hipMemcpyHostToDevice, ring.upload);
+        if (e == hipSuccess) e = hipEventRecord(ring.ready[k], ring.upload);
+        if (e != hipSuccess) { st = hip_fail(e, "job table upload"); break; }
+        slots.push_back(k);
+        st = fs.add(cp, (const uint8_t*)s.dev, false, device, ring.ready[k]);
+    }
+    if (cp.table.capacity() > (size_t(32) << 20)) std::vector<uint8_t>().swap(cp.table);
+    const rr_status je = fs.end();
+    // a slot is free again once the caller's stream, which now follows every
+    // group, gets past this point
+    for (int k : slots) {
+        e = hipEventRecord(ring.slots[k].done, hs);
+        ring.slots[k].used = true;
+        if (e != hipSuccess && st == RR_OK) st = hip_fail(e, "hipEventRecord");
+    }
+    return st != RR_OK ? st : je;
+}
+
 }  // namespace
 
 extern "C" {
 
 rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) {
     clear_error();
+    hipStream_t hs = (hipStream_t)stream;
+    if (njobs >= PIPE_MIN_JOBS) return permute_batched_pipelined(jobs, njobs, hs);
     // the plan's table is copied to the staging ring below: each calling thread
     // keeps one plan so its multi-megabyte table is not allocated per call
     static thread_local BatchPlan bp;
@@ -294,35 +429,15 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream) 
     int device = 0;
     hipError_t e = hipGetDevice(&device);
     if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
-    hipStream_t hs = (hipStream_t)stream;
     std::lock_guard<std::mutex> lk(g_ring_mu);
     Ring& ring = g_rings[device];
     st = fanout_init(&ring.fan);
     if (st != RR_OK) return st;
-    Slot& s = ring.slots[ring.next];
-    ring.next = (ring.next + 1) % RING;
-    if (s.used) {
-        e = hipEventSynchronize(s.done);
-        if (e != hipSuccess) return hip_fail(e, "waiting for a staging slot");
-    }
     const size_t need = bp.table.size();
-    if (need > s.cap) {
-        if (s.host) (void)hipHostFree(s.host);
-        if (s.dev) (void)hipFree(s.dev);
-        s.host = s.dev = nullptr;
-        s.cap = 0;
-        size_t cap = std::max<size_t>(need, 1 << 20);
-        if (hipHostMalloc(&s.host, cap, hipHostMallocDefault) != hipSuccess)
-            return fail(RR_ERR_NO_MEMORY, "pinned staging buffer");
-        if (hipMalloc(&s.dev, cap) != hipSuccess) {
-            (void)hipHostFree(s.host);
-            s.host = nullptr;
-            return fail(RR_ERR_NO_MEMORY, "device job table");
-        }
-        s.cap = cap;
-    }
-    if (!s.done && hipEventCreateWithFlags(&s.done, hipEventDisableTiming) != hipSuccess)
-        return fail(RR_ERR_HIP, "hipEventCreate");
+    int k = 0;
+    st = take_slot(ring, need, &k);
+    if (st != RR_OK) return st;
+    Slot& s = ring.slots[k];
     std::memcpy(s.host, bp.table.data(), need);
     if (bp.table.capacity() > (size_t(32) << 20)) std::vector<uint8_t>().swap(bp.table);   // keep at most 32 MB
     e = hipMemcpyAsync(s.dev, s.host, need, hipMemcpyHostToDevice, hs);

@@ -68,6 +68,10 @@ struct BatchPlan {
 rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
                      std::string* why, int* bad_job);
 
+// Validate every job (shape, buffers, its own aliasing) and the overlaps between
+// jobs, without planning them: what plan_batch reports, before any planning.
+rr_status validate_batch(const rr_job* jobs, int njobs, std::string* why, int* bad_job);
+
 // Validate one job and plan it (no overlap check against other jobs).
 rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string* why);
 

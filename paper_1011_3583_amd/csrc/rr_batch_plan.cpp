@@ -37,15 +37,21 @@ uint64_t align_up(uint64_t x, uint64_t a) { return (x + a - 1) / a * a; }
 
 }  // namespace
 
-rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string* why) {
-    Canon c;
-    rr_status st = canonicalize(j.ndim, j.dims, j.perm, j.elem_size, &c, why);
+static rr_status validate_job(const rr_job& j, Canon* c, std::string* why) {
+    rr_status st = canonicalize(j.ndim, j.dims, j.perm, j.elem_size, c, why);
     if (st != RR_OK) return st;
-    if (c.total_bytes > 0) {
+    if (c->total_bytes > 0) {
         if (!j.dst || !j.src) { *why = "NULL buffer for a non-empty job"; return RR_ERR_INVALID_ARG; }
-        const uint64_t d = (uint64_t)j.dst, s = (uint64_t)j.src, n = (uint64_t)c.total_bytes;
+        const uint64_t d = (uint64_t)j.dst, s = (uint64_t)j.src, n = (uint64_t)c->total_bytes;
         if (d < s + n && s < d + n) { *why = "job source and destination overlap"; return RR_ERR_ALIAS; }
     }
+    return RR_OK;
+}
+
+rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string* why) {
+    Canon c;
+    rr_status st = validate_job(j, &c, why);
+    if (st != RR_OK) return st;
     return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, p, why);
 }
 
@@ -132,6 +138,31 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
         if (p.kind != K_EMPTY && p.grid > 0) entries.push_back({&p, 0, p.grid, p.bytes});
     }
     return build_batch(entries, out, why);
+}
+
+rr_status validate_batch(const rr_job* jobs, int njobs, std::string* why, int* bad_job) {
+    *bad_job = -1;
+    if (njobs < 0) { *why = "njobs < 0"; return RR_ERR_INVALID_ARG; }
+    if (njobs > 0 && !jobs) { *why = "jobs is NULL"; return RR_ERR_INVALID_ARG; }
+    std::vector<Interval> dsts, srcs;
+    dsts.reserve((size_t)njobs);
+    srcs.reserve((size_t)njobs);
+    for (int i = 0; i < njobs; ++i) {
+        Canon c;
+        const rr_status st = validate_job(jobs[i], &c, why);
+        if (st != RR_OK) { *bad_job = i; return st; }
+        if (c.total_bytes > 0) {
+            const uint64_t d = (uint64_t)jobs[i].dst, s = (uint64_t)jobs[i].src, n = (uint64_t)c.total_bytes;
+            dsts.push_back({d, d + n, i});
+            srcs.push_back({s, s + n, i});
+        }
+    }
+    int ja, jb;
+    if (find_overlap(dsts, srcs, &ja, &jb)) {
+        *why = "jobs " + std::to_string(ja) + " and " + std::to_string(jb) + " overlap";
+        return RR_ERR_ALIAS;
+    }
+    return RR_OK;
 }
 
 rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, std::string* why) {

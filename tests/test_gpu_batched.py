@@ -206,3 +206,26 @@ def test_batched_short_runs_sharing_lines(rr):
         rr.check(rr.permute_raw(j.dst, j.src, s["dims"], s["perm"], s["esize"], torch.cuda.current_stream().cuda_stream))
     torch.cuda.synchronize()
     _check_all_vs_oracle(J)
+
+
+def test_large_one_shot_batch_in_chunks(rr):
+    """A one-shot batch of 2500 jobs is validated whole, then planned and launched
+    in chunks: every job equals the oracle; a batch whose last job is invalid
+    fails with that job's index and writes nothing."""
+    specs = _uneven(21, 2500, 6000)
+    J = Jobs(rr, specs, 21)
+    _say("one-shot chunked", len(specs))
+    for _ in range(2):   # twice: the second call reuses the ring slots
+        J.dst.zero_()
+        rr.check(rr.permute_batched_raw(J.arr, len(specs), torch.cuda.current_stream().cuda_stream))
+        torch.cuda.synchronize()
+        _check_all_vs_oracle(J)
+    J.dst.fill_(0x77)
+    torch.cuda.synchronize()
+    bad = rr.make_jobs([(J.arr[i].dst, J.arr[i].src, s["dims"], s["perm"], s["esize"]) for i, s in enumerate(specs[:-1])] +
+                       [(J.arr[len(specs) - 1].dst, J.arr[len(specs) - 1].src, (4, 4), (0, 0), 4)])
+    st = rr.permute_batched_raw(bad, len(specs), torch.cuda.current_stream().cuda_stream)
+    torch.cuda.synchronize()
+    assert st == rr.STATUS_CODE["RR_ERR_INVALID_ARG"], st
+    assert f"job {len(specs) - 1}" in rr.last_error()
+    assert bool((J.dst == 0x77).all())
