@@ -191,8 +191,8 @@ rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t coun
  * after the call waits for all of them.  Calls on one device share those side
  * streams, so batched calls issued on different streams may run one after the
  * other.  A batch of 2048 jobs or more is validated whole first, then planned,
- * staged and launched in up to four chunks of consecutive jobs (the first an
- * eighth of them), so the device runs the first chunks while the host plans the
+ * staged and launched in up to four chunks of consecutive jobs (the first a
+ * sixteenth of them), so the device runs the first chunks while the host plans the
  * rest; each chunk takes a ring slot, and its table goes up on a fourth stream of
  * the library.
  * Errors: the first invalid job's error (nothing is launched), RR_ERR_NO_MEMORY,

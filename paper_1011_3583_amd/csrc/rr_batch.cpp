@@ -345,7 +345,8 @@ rr_status tune(rr_batch* b) {
 
 // Large one-shot batches: every job is validated first (an invalid batch
 // enqueues nothing), then the jobs are planned, staged and launched in up to
-// RING contiguous chunks (an eighth, a quarter, a quarter, the rest), so the GPU
+// RING contiguous chunks (a sixteenth, three sixteenths, a quarter, the rest:
+// small first, so the GPU starts early, larger later), so the GPU
 // runs the first chunks while the host plans the next.  The chunks' groups
 // share one fan-out over the caller's stream and the side streams; each
 // chunk's table goes up on the ring's upload stream after the caller's earlier
@@ -383,7 +384,7 @@ rr_status permute_batched_pipelined(const rr_job* jobs, int njobs, hipStream_t h
     FanSession fs(&ring.fan, hs);
     std::vector<int> slots;
     const int64_t n = njobs;
-    const int64_t bounds[RING + 1] = {0, n / 8, 3 * n / 8, 5 * n / 8, n};
+    const int64_t bounds[RING + 1] = {0, n / 16, n / 4, n / 2, n};
     for (int c = 0; c < RING && st == RR_OK; ++c) {
         const int lo = (int)bounds[c], hi = (int)bounds[c + 1];
         if (hi <= lo) continue;

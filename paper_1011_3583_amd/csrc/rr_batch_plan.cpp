@@ -55,12 +55,31 @@ rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string
     return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, opt, p, why);
 }
 
-// Host threads that plan a batch of njobs: one below 1024 jobs (starting threads
-// costs more than it saves), else one per 512 jobs up to 8 and the host's cores.
+// Host threads that plan (or validate) a batch of njobs: one below 256 jobs
+// (starting a thread costs about what planning a hundred jobs does), else one
+// per 128 jobs up to 8 and the host's cores.
 static int planning_threads(int njobs) {
-    if (njobs < 1024) return 1;
+    if (njobs < 256) return 1;
     const int hw = (int)std::max(1u, std::thread::hardware_concurrency());
-    return std::max(1, std::min({8, hw, njobs / 512}));
+    return std::max(1, std::min({8, hw, njobs / 128}));
+}
+
+// Run body(t) for t in [0, nt): t = 0 on the calling thread, the others on
+// threads of their own (or here, where no thread can be started).
+template <class Body>
+static void run_slices(int nt, Body body) {
+    std::vector<std::thread> th;
+    std::vector<int> inline_slices;
+    for (int t = 1; t < nt; ++t) {
+        try {
+            th.emplace_back(body, t);
+        } catch (...) {
+            inline_slices.push_back(t);
+        }
+    }
+    body(0);
+    for (int t : inline_slices) body(t);
+    for (std::thread& x : th) x.join();
 }
 
 rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, BatchPlan* out,
@@ -100,18 +119,7 @@ rr_status plan_batch(const rr_job* jobs, int njobs, const TileOptions& opt, Batc
             if (st != RR_OK) { sts[(size_t)t] = st; bad[(size_t)t] = i; return; }
         }
     };
-    std::vector<std::thread> th;
-    std::vector<int> inline_slices;
-    for (int t = 1; t < nt; ++t) {
-        try {
-            th.emplace_back(slice, t);
-        } catch (...) {   // no thread available: plan that slice here
-            inline_slices.push_back(t);
-        }
-    }
-    slice(0);
-    for (int t : inline_slices) slice(t);
-    for (std::thread& x : th) x.join();
+    run_slices(nt, slice);
     for (int t = 0; t < nt; ++t)
         if (sts[(size_t)t] != RR_OK) { *why = whys[(size_t)t]; *bad_job = bad[(size_t)t]; return sts[(size_t)t]; }
     std::vector<Interval> dsts, srcs;
@@ -144,18 +152,33 @@ rr_status validate_batch(const rr_job* jobs, int njobs, std::string* why, int* b
     *bad_job = -1;
     if (njobs < 0) { *why = "njobs < 0"; return RR_ERR_INVALID_ARG; }
     if (njobs > 0 && !jobs) { *why = "jobs is NULL"; return RR_ERR_INVALID_ARG; }
+    // contiguous slices on a few host threads; the lowest failing job is reported
+    const int nt = planning_threads(njobs);
+    std::vector<std::vector<Interval>> tdst((size_t)nt), tsrc((size_t)nt);
+    std::vector<int> bad((size_t)nt, -1);
+    std::vector<rr_status> sts((size_t)nt, RR_OK);
+    std::vector<std::string> whys((size_t)nt);
+    run_slices(nt, [&](int t) {
+        const int lo = (int)((int64_t)njobs * t / nt), hi = (int)((int64_t)njobs * (t + 1) / nt);
+        for (int i = lo; i < hi; ++i) {
+            Canon c;
+            const rr_status st = validate_job(jobs[i], &c, &whys[(size_t)t]);
+            if (st != RR_OK) { sts[(size_t)t] = st; bad[(size_t)t] = i; return; }
+            if (c.total_bytes > 0) {
+                const uint64_t d = (uint64_t)jobs[i].dst, s = (uint64_t)jobs[i].src, n = (uint64_t)c.total_bytes;
+                tdst[(size_t)t].push_back({d, d + n, i});
+                tsrc[(size_t)t].push_back({s, s + n, i});
+            }
+        }
+    });
+    for (int t = 0; t < nt; ++t)
+        if (sts[(size_t)t] != RR_OK) { *why = whys[(size_t)t]; *bad_job = bad[(size_t)t]; return sts[(size_t)t]; }
     std::vector<Interval> dsts, srcs;
     dsts.reserve((size_t)njobs);
     srcs.reserve((size_t)njobs);
-    for (int i = 0; i < njobs; ++i) {
-        Canon c;
-        const rr_status st = validate_job(jobs[i], &c, why);
-        if (st != RR_OK) { *bad_job = i; return st; }
-        if (c.total_bytes > 0) {
-            const uint64_t d = (uint64_t)jobs[i].dst, s = (uint64_t)jobs[i].src, n = (uint64_t)c.total_bytes;
-            dsts.push_back({d, d + n, i});
-            srcs.push_back({s, s + n, i});
-        }
+    for (int t = 0; t < nt; ++t) {
+        dsts.insert(dsts.end(), tdst[(size_t)t].begin(), tdst[(size_t)t].end());
+        srcs.insert(srcs.end(), tsrc[(size_t)t].begin(), tsrc[(size_t)t].end());
     }
     int ja, jb;
     if (find_overlap(dsts, srcs, &ja, &jb)) {

@@ -472,7 +472,7 @@ def _batched_jobs(seed, njobs, max_elems=20000):
 
 
 def test_emu_batched_many_jobs_threaded_planning():
-    """1200 small jobs (planned on several host threads, as batches of 1024 jobs or
+    """1200 small jobs (planned on several host threads, as batches of 256 jobs or
     more are) of every element size and ranks 2-4: each equals the oracle alone."""
     g = rr_synth.rng(4242)
     jobs = []
