@@ -809,9 +809,9 @@ def profile_interlace():
             torch.cuda.synchronize()
             rr.check(fn())
             torch.cuda.synchronize()
-            d = rr.plan_describe((n, count) if op == "interlace" else (count, n), (1, 0), e, 1 << 20, 1 << 30)
+            d = rr.interlace_describe(out.data_ptr(), planes, count, e, op == "deinterlace")
             print(json.dumps({"case": f"{name}_{op}", "n": n, "esize": e, "algorithmic_bytes": 2 * n * pb,
-                              "flags": int(d["flags"])}), flush=True)
+                              "class": d["class"], "flags": int(d.get("flags", 0))}), flush=True)
 
 
 def profile_batch(mode: str = "graph"):

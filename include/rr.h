@@ -409,6 +409,12 @@ rr_status rr_reorder_describe(const void* dst, const void* src, int ndim, const 
                               int elem_size, char* buf, int buflen);
 rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int64_t* dims,
                            const int* perm, int elem_size, char* buf, int buflen);
+/* The same for the plan rr_interlace (de = 0) or rr_deinterlace (de = 1) would
+ * use with these pointers (flat: the joined buffer; planes: host array of n
+ * plane pointers, read for their values only).  Arguments are checked as by
+ * those calls; count = 0 describes an empty plan. */
+rr_status rr_interlace_describe(const void* flat, const void* const* planes, int n, int64_t count,
+                                int elem_size, int de, char* buf, int buflen);
 
 /* Tile-shape override (the autotuner's knobs): row targets in bytes for the
  * input and output sides of the tiled kernel (0 = built-in choice, max 4096),
@@ -431,7 +437,12 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
  * planner evens out both outer extents for the fewest tiles that fit the tile size,
  * keeping each side's rows at least half their target, one 128-byte line and a
  * multiple of 16 bytes (or the whole axis).  RR_ERR_INVALID_ARG also for both fill
- * flags. */
+ * flags.  RR_TILE_NO_WEAVE sends every interlace and de-interlace through the LDS
+ * tile (by default 2-4 sets of 1-, 2-, 4- or 8-byte elements, every pointer on a
+ * 16-byte boundary and every set a whole number of 16-byte vectors, are joined or
+ * split in registers, one 16-byte vector of each set per thread; the cache bits
+ * then say whether the joined side goes through the caches, streamed by
+ * default). */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
@@ -442,6 +453,7 @@ rr_status rr_plan_describe(const void* dst, const void* src, int ndim, const int
 #define RR_TILE_DIAG 128        /* diagonal tile order: consecutive tiles step along both tile-grid axes */
 #define RR_TILE_FILL (1 << 27)  /* odd extents: refit tile extents for the fewest tiles within the tile size */
 #define RR_TILE_NO_FILL (1 << 28) /* keep the row-target tile extents on odd extents */
+#define RR_TILE_NO_WEAVE (1 << 29) /* interlace through the LDS tile only */
 #define RR_TILE_MAX_G(g) ((g) << 8)
 #define RR_TILE_KIB(k) ((k) << 16)
 #define RR_TILE_CACHE(p) (((p) + 1) << 24)

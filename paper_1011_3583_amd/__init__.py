@@ -31,7 +31,8 @@ EXPORTS = ("rr_permute", "rr_reorder", "rr_gather", "rr_copy_range", "rr_stencil
            "rr_serve_create", "rr_serve_alloc", "rr_serve_free", "rr_serve_submit",
            "rr_serve_poll", "rr_serve_completions", "rr_serve_release", "rr_serve_destroy",
            "rr_serve_get_stats", "rr_serve_fail_next_batch",
-           "rr_order_to_perm", "rr_plan_describe", "rr_reorder_describe", "rr_set_tile_override",
+           "rr_order_to_perm", "rr_plan_describe", "rr_reorder_describe", "rr_interlace_describe",
+           "rr_set_tile_override",
            "rr_tune_permute", "rr_tune_save", "rr_tune_load", "rr_tune_clear", "rr_tune_context",
            "rr_status_string", "rr_last_error", "rr_version")
 
@@ -121,6 +122,7 @@ def lib() -> ctypes.CDLL:
     L.rr_copy_range.argtypes = [vp, vp, i64, i64, i64, i64, i32, vp]
     L.rr_stencil2d.argtypes = [vp, vp, i64, i64, i32, i32, ctypes.POINTER(ctypes.c_float), vp]
     L.rr_reorder_describe.argtypes = [vp, vp, i32, i64p, i64p, i64p, i32, i32p, i32, ctypes.c_char_p, i32]
+    L.rr_interlace_describe.argtypes = [vp, vp, i32, i64, i32, i32, ctypes.c_char_p, i32]
     L.rr_set_tile_override.argtypes = [i32, i32, i32]
     L.rr_tune_context.argtypes = [ctypes.c_char_p, i32]
     L.rr_tune_permute.argtypes = [vp, vp, i32, i64p, i32p, i32, vp, ctypes.POINTER(ctypes.c_double),
@@ -315,6 +317,14 @@ def plan_describe(dims, perm, elem_size: int, dst: int = 0, src: int = 0) -> dic
     return out
 
 
+def interlace_describe(flat: int, planes, count: int, elem_size: int, de: bool = False) -> dict:
+    """The plan rr_interlace (or, de=True, rr_deinterlace) would run for these pointers."""
+    buf = ctypes.create_string_buffer(1024)
+    arr = (ctypes.c_void_p * max(1, len(planes)))(*planes)
+    check(lib().rr_interlace_describe(flat, arr, len(planes), int(count), int(elem_size), int(bool(de)), buf, 1024))
+    return dict(tok.split("=", 1) for tok in buf.value.decode().split())
+
+
 def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, src: int = 0) -> dict:
     buf = ctypes.create_string_buffer(1024)
     check(lib().rr_reorder_describe(dst, src, len(dims), _i64(dims), _opt_i64(base), _opt_i64(range_), len(order),
@@ -324,7 +334,7 @@ def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, sr
 
 def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None,
                       force_ragged: bool = False, max_g: int = 0, tile_kib: int = 0, xcd=None,
-                      umt: int = 0, cache=None, diag: bool = False, fill=None):
+                      umt: int = 0, cache=None, diag: bool = False, fill=None, weave: bool = True):
     """order_out: True = output order, False = input order, None = built-in choice.
     force_ragged: plan the odd-shape tile path even where aligned micro-tiles fit.
     max_g: cap on the register micro-tile edge (0 = none, else 1, 2, 4, 8, 16).
@@ -335,7 +345,9 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     cache: global accesses of tiles, 0 non-temporal, 1 loads cached, 2 stores cached,
     3 both; None = the planner's choice by 128-byte line alignment.
     diag: diagonal tile order.  fill: True / False switch the odd-extent refit (fewer,
-    fuller tiles where a tile does not divide an outer axis) on / off, None = built-in."""
+    fuller tiles where a tile does not divide an outer axis) on / off, None = built-in.
+    weave: False sends every interlace and de-interlace through the LDS tile instead of
+    the register path for aligned sets of 1-8-byte elements."""
     flags = 0 if order_out is None else (1 if order_out else 2)
     flags |= 4 if force_ragged else 0
     flags |= int(max_g) << 8
@@ -345,6 +357,7 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     flags |= 0 if cache is None else (int(cache) + 1) << 24
     flags |= 128 if diag else 0
     flags |= 0 if fill is None else ((1 << 27) if fill else (1 << 28))
+    flags |= 0 if weave else (1 << 29)
     check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))
 
 

@@ -234,9 +234,10 @@ rr_status rr_stencil2d(float* dst, const float* src, int64_t rows, int64_t cols,
     return RR_OK;
 }
 
-static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
-                                  int elem_size, rr_stream_t stream, bool de) {
-    clear_error();
+// Checks an interlace call's arguments and plans it (no launch); *p is left empty
+// for count == 0.
+static rr_status interlace_plan(void* flat, const void* const* planes, int n, int64_t count, int elem_size,
+                                bool de, Plan* p) {
     if (n < 1 || n > RR_MAX_PLANES) return fail(RR_ERR_INVALID_ARG, "n must be 1..RR_MAX_PLANES");
     if (count < 0) return fail(RR_ERR_INVALID_ARG, "count must be >= 0");
     if (elem_size < 1 || elem_size > 16) return fail(RR_ERR_INVALID_ARG, "elem_size must be 1..16");
@@ -245,7 +246,7 @@ static rr_status interlace_common(void* flat, const void* const* planes, int n, 
     if (__builtin_mul_overflow(count, (int64_t)elem_size, &plane_bytes) ||
         __builtin_mul_overflow(plane_bytes, (int64_t)n, &total))
         return fail(RR_ERR_OVERFLOW, "byte count overflows int64");
-    if (count == 0) return RR_OK;
+    if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (!flat) return fail(RR_ERR_INVALID_ARG, "NULL joined buffer");
     uint64_t pl[RR_MAX_PLANES];
     for (int c = 0; c < n; ++c) {
@@ -259,10 +260,18 @@ static rr_status interlace_common(void* flat, const void* const* planes, int n, 
             for (int c2 = c + 1; c2 < n; ++c2)
                 if (ranges_overlap(pl[c], plane_bytes, pl[c2], plane_bytes))
                     return fail(RR_ERR_ALIAS, "output planes overlap");
-    Plan p;
     std::string why;
-    rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, current_tile_options(), &p, &why);
+    rr_status st = plan_interlace((uint64_t)flat, pl, n, count, elem_size, de, current_tile_options(), p, &why);
     if (st != RR_OK) return fail(st, why);
+    return RR_OK;
+}
+
+static rr_status interlace_common(void* flat, const void* const* planes, int n, int64_t count,
+                                  int elem_size, rr_stream_t stream, bool de) {
+    clear_error();
+    Plan p;
+    rr_status st = interlace_plan(flat, planes, n, count, elem_size, de, &p);
+    if (st != RR_OK || p.kind == K_EMPTY) return st;
     if (log_level() >= 2) log_line(2, std::string("interlace_common ") + describe(p));
     hipError_t e = launch_plan(p, (hipStream_t)stream);
     if (e != hipSuccess) return hip_fail(e, de ? "rr_deinterlace launch" : "rr_interlace launch");
@@ -278,6 +287,17 @@ rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t coun
                          rr_stream_t stream) {
     return interlace_common(const_cast<void*>(src), (const void* const*)dsts, n, count, elem_size,
                             stream, true);
+}
+
+rr_status rr_interlace_describe(const void* flat, const void* const* planes, int n, int64_t count,
+                                int elem_size, int de, char* buf, int buflen) {
+    clear_error();
+    if (!buf || buflen < 1) return fail(RR_ERR_INVALID_ARG, "NULL output buffer");
+    Plan p;
+    rr_status st = interlace_plan(const_cast<void*>(flat), planes, n, count, elem_size, de != 0, &p);
+    if (st != RR_OK) return st;
+    std::snprintf(buf, (size_t)buflen, "%s", describe(p).c_str());
+    return RR_OK;
 }
 
 rr_status rr_order_to_perm(int ndim, const int* paper_order, int* perm_out) {
@@ -322,7 +342,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
         return fail(RR_ERR_INVALID_ARG, "RR_TILE_XCD and RR_TILE_NO_XCD together");
     if ((flags & RR_TILE_FILL) && (flags & RR_TILE_NO_FILL))
         return fail(RR_ERR_INVALID_ARG, "RR_TILE_FILL and RR_TILE_NO_FILL together");
-    const int cache = ((flags >> 24) & 0x7) - 1;   // bits 24..26; 27, 28: fill flags
+    const int cache = ((flags >> 24) & 0x7) - 1;   // bits 24..26; 27, 28: fill flags; 29: weave
     if (cache > 3) return fail(RR_ERR_INVALID_ARG, "cache policy must be 0..3");
     TileOptions o;
     o.max_g = max_g;
@@ -331,6 +351,7 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
     o.cache = cache;
     o.diag = (flags & RR_TILE_DIAG) ? 1 : 0;
     o.fill = (flags & RR_TILE_FILL) ? 1 : (flags & RR_TILE_NO_FILL) ? 0 : -1;
+    o.weave = (flags & RR_TILE_NO_WEAVE) ? 0 : 1;
     o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
     o.in_row_bytes = in_row_bytes;
     o.out_row_bytes = out_row_bytes;

@@ -595,6 +595,186 @@ RR_HD void run_thread(const RunArgs& a, uint32_t block, uint32_t tid) {
     else run_body<W, true>(a, block, tid);
 }
 
+// ----------------------------------------------------------------- interlace in registers
+// One thread's share of an interlace of N sets of U-byte elements (Sec. III.C):
+// vector v of every set (16 / U elements each) and the N consecutive 16-byte
+// vectors of the joined array that hold the same elements, set index fastest.
+// in[][] holds the sets' vectors (interlace) or the joined vectors
+// (de-interlace); out[][] receives the other side.  Every byte position is a
+// compile-time constant, so the loops unroll to word moves (U >= 4) or byte
+// shifts the compiler folds into byte permutes (U = 1, 2).
+template <int U, int N, bool DE>
+RR_HD void weave_regs(const uint32_t (&in)[N][4], uint32_t (&out)[N][4]) {
+    constexpr int P = U < 4 ? U : 4;   // bytes moved per piece
+    constexpr uint32_t MASK = P == 4 ? 0xffffffffu : (1u << (8 * P)) - 1u;
+#pragma unroll
+    for (int ow = 0; ow < 4 * N; ++ow) {
+        uint32_t word = 0;
+#pragma unroll
+        for (int bb = 0; bb < 4; bb += P) {
+            const int ob = ow * 4 + bb;   // byte of the thread's output side
+            int sv, sb;                   // its source vector and byte
+            if constexpr (!DE) {
+                const int k = ob / U;     // element of the joined span
+                sv = k % N;
+                sb = (k / N) * U + ob % U;
+            } else {
+                const int jb = ((ob % 16 / U) * N + ob / 16) * U + ob % U;
+                sv = jb / 16;
+                sb = jb % 16;
+            }
+            const uint32_t piece = (in[sv][sb / 4] >> (8 * (sb % 4))) & MASK;
+            word |= P == 4 ? piece : piece << (8 * bb);
+        }
+        out[ow / 4][ow % 4] = word;
+    }
+}
+
+// LDS slot of vector m (0 .. 64 * N - 1) of a wave's joined span.  For even N
+// the low three bits are XORed with the next three, so the lane-strided side
+// (lane L at vector L * N + k) spreads over the banks; the consecutive side
+// (lane L at vector k * 64 + L) permutes within aligned groups of eight.
+template <int N>
+RR_HD uint32_t weave_slot(uint32_t m) {
+    return N % 2 == 0 ? m ^ ((m >> 3) & 7u) : m;
+}
+
+// Keeps the scheduler from moving instructions across this point: placed after
+// a thread's independent global loads so they all issue before the first use of
+// a result (otherwise a register reuse can make the second load wait for the
+// first).
+RR_HD void sched_fence() {
+#if defined(__HIP_DEVICE_COMPILE__)
+    __builtin_amdgcn_sched_barrier(0);
+#endif
+}
+
+// A wave's share of a weave: R chunks of 64 consecutive groups each (vector v of
+// every set, v = first group of the chunk + lane) and the 64 * N consecutive
+// joined vectors that hold them.  Both global sides are accessed one 16-byte
+// vector per lane with consecutive lanes at consecutive addresses: the set side
+// as group v, the joined side as vector k * 64 + lane of the chunk's span.  The
+// two numberings meet in a wave-private LDS region per chunk (64 * N vectors):
+// stage writes it, finish reads it back after a wave-level barrier (no
+// workgroup barrier: waves never share a region).  Workgroup b covers groups
+// [b * R * NT, (b + 1) * R * NT), chunk r of its wave w starting at
+// (b * R + r) * NT + w * 64.  The joined side goes through the caches when C is
+// true, else is streamed like the set side.  Only chunks that hold the last
+// group check vector bounds.  lds: R * NT * N * 16 bytes.
+RR_HD uint64_t weave_chunk(uint32_t block, int r, uint32_t wave, int R) {
+    return ((uint64_t)block * R + r) * NT + wave * 64u;
+}
+
+template <int U, int N, bool DE, bool C, int R>
+RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint8_t* lds, uint32_t tid) {
+    constexpr uint32_t WV = 64, NW = NT / WV;
+    const uint32_t wave = tid / WV, lane = tid % WV;
+    if constexpr (!DE) {
+        uint32_t in[R][N][4];
+        bool ok[R];
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t v = weave_chunk(block, r, wave, R) + lane;
+            ok[r] = v < a.nvec;
+            if (ok[r])
+#pragma unroll
+                for (int s = 0; s < N; ++s)
+                    gload<16>(reinterpret_cast<const uint8_t*>(a.planes[s]) + v * 16u, in[r][s]);
+        }
+        sched_fence();
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            if (!ok[r]) continue;
+            uint8_t* w = lds + (uint64_t)(r * NW + wave) * WV * N * 16u;
+            uint32_t out[N][4];
+            weave_regs<U, N, false>(in[r], out);
+#pragma unroll
+            for (int k = 0; k < N; ++k) sstore<16>(w + 16u * weave_slot<N>(lane * N + k), out[k]);
+        }
+    } else {
+        const uint64_t total = (uint64_t)a.nvec * N;
+        const uint8_t* joined = reinterpret_cast<const uint8_t*>(a.joined);
+        if (weave_chunk(block, R - 1, wave, R) + WV <= a.nvec) {
+            uint32_t x[R][N][4];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    gload<16, !C>(joined + (weave_chunk(block, r, wave, R) * N + k * WV + lane) * 16u, x[r][k]);
+            sched_fence();
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    sstore<16>(lds + (uint64_t)(r * NW + wave) * WV * N * 16u + 16u * weave_slot<N>(k * WV + lane),
+                               x[r][k]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const uint32_t m = k * WV + lane;
+                    const uint64_t j = weave_chunk(block, r, wave, R) * N + m;
+                    if (j < total) {
+                        uint32_t x[4];
+                        gload<16, !C>(joined + j * 16u, x);
+                        sstore<16>(lds + (uint64_t)(r * NW + wave) * WV * N * 16u + 16u * weave_slot<N>(m), x);
+                    }
+                }
+        }
+    }
+}
+
+template <int U, int N, bool DE, bool C, int R>
+RR_HD void weave_finish(const WeaveArgs& a, uint32_t block, const uint8_t* lds, uint32_t tid) {
+    constexpr uint32_t WV = 64, NW = NT / WV;
+    const uint32_t wave = tid / WV, lane = tid % WV;
+    if constexpr (!DE) {
+        const uint64_t total = (uint64_t)a.nvec * N;
+        uint8_t* joined = reinterpret_cast<uint8_t*>(a.joined);
+        if (weave_chunk(block, R - 1, wave, R) + WV <= a.nvec) {
+            uint32_t x[R][N][4];
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    sload<16>(lds + (uint64_t)(r * NW + wave) * WV * N * 16u + 16u * weave_slot<N>(k * WV + lane),
+                              x[r][k]);
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k)
+                    gstore<16, !C>(joined + (weave_chunk(block, r, wave, R) * N + k * WV + lane) * 16u, x[r][k]);
+        } else {
+#pragma unroll
+            for (int r = 0; r < R; ++r)
+#pragma unroll
+                for (int k = 0; k < N; ++k) {
+                    const uint32_t m = k * WV + lane;
+                    const uint64_t j = weave_chunk(block, r, wave, R) * N + m;
+                    if (j < total) {
+                        uint32_t x[4];
+                        sload<16>(lds + (uint64_t)(r * NW + wave) * WV * N * 16u + 16u * weave_slot<N>(m), x);
+                        gstore<16, !C>(joined + j * 16u, x);
+                    }
+                }
+        }
+    } else {
+#pragma unroll
+        for (int r = 0; r < R; ++r) {
+            const uint64_t v = weave_chunk(block, r, wave, R) + lane;
+            if (v >= a.nvec) continue;
+            const uint8_t* w = lds + (uint64_t)(r * NW + wave) * WV * N * 16u;
+            uint32_t in[N][4], out[N][4];
+#pragma unroll
+            for (int k = 0; k < N; ++k) sload<16>(w + 16u * weave_slot<N>(lane * N + k), in[k]);
+            weave_regs<U, N, true>(in, out);
+#pragma unroll
+            for (int s = 0; s < N; ++s) gstore<16>(reinterpret_cast<uint8_t*>(a.planes[s]) + v * 16u, out[s]);
+        }
+    }
+}
+
 // ----------------------------------------------------------------- strided select
 // Bytes of the R-byte element j of a span of M consecutive 16-byte vectors whose
 // elements lie S = M * R bytes apart, packed into one 16-byte output vector

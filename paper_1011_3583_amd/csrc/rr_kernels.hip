@@ -12,6 +12,11 @@
 //  * k_select -- boxes that keep a strided fastest axis (one component of
 //               interleaved records): whole records are read with 16-byte
 //               vectors and the kept bytes packed in registers.
+//  * k_weave -- interlace / de-interlace of 2-4 aligned sets of 1-8-byte
+//               elements joined or split in registers, one 16-byte vector of
+//               each set per thread; each wave swaps the joined vectors through
+//               its own LDS region so both sides are read and written with
+//               consecutive lanes at consecutive addresses.
 //  * k_tile  -- a true transpose between the input's fastest axis (or axes) and
 //               the output's fastest axis (or axes), staged through an LDS
 //               tile (Sec. III.B's shared-memory tile; Sec. III.C's shared
@@ -67,6 +72,25 @@ __global__ __launch_bounds__(NT) void k_select(const SelectArgs a) {
     } else {
         select_thread<R, M>(a, blockIdx.x, threadIdx.x);
     }
+}
+
+// Lanes of one wave exchange vectors through their own LDS region: LDS
+// operations of a wave complete in issue order, so a wave-level barrier (which
+// keeps the compiler from moving the reads above the writes) is enough.
+template <int U, int N, bool DE, bool C, int R>
+__device__ __forceinline__ void weave_block(const WeaveArgs& a, uint8_t* lds) {
+    weave_stage<U, N, DE, C, R>(a, blockIdx.x, lds, threadIdx.x);
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+    weave_finish<U, N, DE, C, R>(a, blockIdx.x, lds, threadIdx.x);
+}
+
+template <int U, int N, bool DE, int R>
+__global__ __launch_bounds__(NT) void k_weave(const WeaveArgs a) {
+    __shared__ __attribute__((aligned(16))) uint8_t lds[R * NT * N * 16];
+    if (a.cached) weave_block<U, N, DE, true, R>(a, lds);
+    else weave_block<U, N, DE, false, R>(a, lds);
 }
 
 template <int U, int G>
@@ -160,6 +184,38 @@ static hipError_t launch_select(const SelectArgs& a, uint32_t grid, hipStream_t 
     }
 }
 
+template <int U, int N>
+static hipError_t launch_weave_un(const WeaveArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.chunks * 2 + a.de) {
+        case 2: hipLaunchKernelGGL((k_weave<U, N, false, 1>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 3: hipLaunchKernelGGL((k_weave<U, N, true, 1>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 4: hipLaunchKernelGGL((k_weave<U, N, false, 2>), dim3(grid), dim3(NT), 0, st, a); break;
+        case 5: hipLaunchKernelGGL((k_weave<U, N, true, 2>), dim3(grid), dim3(NT), 0, st, a); break;
+        default: return hipErrorInvalidValue;
+    }
+    return hipGetLastError();
+}
+
+template <int U>
+static hipError_t launch_weave_u(const WeaveArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.n) {
+        case 2: return launch_weave_un<U, 2>(a, grid, st);
+        case 3: return launch_weave_un<U, 3>(a, grid, st);
+        case 4: return launch_weave_un<U, 4>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+static hipError_t launch_weave(const WeaveArgs& a, uint32_t grid, hipStream_t st) {
+    switch (a.unit) {
+        case 1: return launch_weave_u<1>(a, grid, st);
+        case 2: return launch_weave_u<2>(a, grid, st);
+        case 4: return launch_weave_u<4>(a, grid, st);
+        case 8: return launch_weave_u<8>(a, grid, st);
+        default: return hipErrorInvalidValue;
+    }
+}
+
 hipError_t launch_plan(const Plan& p, hipStream_t st) {
     switch (p.kind) {
         case K_EMPTY:
@@ -186,6 +242,8 @@ hipError_t launch_plan(const Plan& p, hipStream_t st) {
             return launch_tile(p.tile, p.grid, st);
         case K_SELECT:
             return launch_select(p.select, p.grid, st);
+        case K_WEAVE:
+            return launch_weave(p.weave, p.grid, st);
         case K_GATHER:
             switch (p.gather.wbytes) {
                 case 16: hipLaunchKernelGGL(k_gather<16>, dim3(p.grid), dim3(NT), 0, st, p.gather); break;

@@ -45,7 +45,7 @@ TileOptions g_override;
 bool override_active(const TileOptions& o) {
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
            o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != 0 ||
-           o.fill != -1;
+           o.fill != -1 || o.weave != 1;
 }
 
 TileOptions current_tile_options() {
@@ -1059,6 +1059,34 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     p->bytes = (uint64_t)(count * n * esize);
     if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (n == 1) { plan_copy(de ? planes[0] : flat, de ? flat : planes[0], (uint64_t)(count * esize), p); return RR_OK; }
+    // 2-4 sets of 1-8-byte elements on 16-byte boundaries, a whole number of
+    // 16-byte vectors each: joined and split in registers, vectors swapped
+    // between lanes through a wave-private LDS region (no tile, no workgroup
+    // barrier)
+    const bool pow2_unit = esize == 1 || esize == 2 || esize == 4 || esize == 8;
+    bool aligned = flat % 16 == 0 && (count * esize) % 16 == 0;
+    for (int c = 0; c < n; ++c) aligned = aligned && planes[c] % 16 == 0;
+    if (opt.weave && pow2_unit && n >= 2 && n <= 4 && aligned && (count * esize) / 16 <= 0x7fffffffLL) {
+        p->kind = K_WEAVE;
+        WeaveArgs& w = p->weave;
+        std::memset(&w, 0, sizeof(w));
+        for (int c = 0; c < n; ++c) w.planes[c] = planes[c];
+        w.joined = flat;
+        w.nvec = (uint32_t)((count * esize) / 16);
+        w.n = (uint32_t)n;
+        w.unit = (uint32_t)esize;
+        w.de = de ? 1u : 0u;
+        // cache override: bit 0 cached reads, bit 1 cached writes (joined side
+        // only); built in: both sides streamed, every access a whole line per
+        // eight lanes
+        w.cached = opt.cache < 0 ? 0u : (uint32_t)((opt.cache >> (de ? 0 : 1)) & 1);
+        // two chunks per wave (2 * n loads in flight per lane) except for a
+        // four-set interlace, whose 32 KiB of LDS per workgroup at two chunks
+        // would cut the waves per CU from 32 to 20
+        w.chunks = n == 4 && !de ? 1u : 2u;
+        p->grid = (uint32_t)((w.nvec + (uint64_t)NT * w.chunks - 1) / ((uint64_t)NT * w.chunks));
+        return RR_OK;
+    }
     p->kind = K_TILE;
     TileArgs& a = p->tile;
     std::memset(&a, 0, sizeof(a));
@@ -1133,7 +1161,7 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
 
 std::string describe(const Plan& p) {
     std::ostringstream o;
-    static const char* names[] = {"empty", "copy", "run", "tile", "gather", "select"};
+    static const char* names[] = {"empty", "copy", "run", "tile", "gather", "select", "weave"};
     o << "class=" << names[p.kind];
     const Canon& c = p.c;
     o << " rank=" << c.rank << " dims=";
@@ -1144,6 +1172,9 @@ std::string describe(const Plan& p) {
     if (p.kind == K_COPY) o << " vec=" << p.copy.wbytes << " head=" << p.copy.head << " tail=" << p.copy.tail;
     if (p.kind == K_RUN)
         o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr << " ua=" << p.run.ua << " cached=" << p.run.cached;
+    if (p.kind == K_WEAVE)
+        o << " n=" << p.weave.n << " unit=" << p.weave.unit << " de=" << p.weave.de << " nvec=" << p.weave.nvec
+          << " cached=" << p.weave.cached << " chunks=" << p.weave.chunks;
     if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
     if (p.kind == K_SELECT) o << " vec=16 stride=" << p.select.S << " m=" << p.select.M << " n=" << p.select.n;
     if (p.kind == K_TILE) {

@@ -46,7 +46,7 @@ struct Canon {
     int64_t total_bytes = 0;   // bytes per side
 };
 
-enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3, K_GATHER = 4, K_SELECT = 5 };
+enum Kind : int32_t { K_EMPTY = 0, K_COPY = 1, K_RUN = 2, K_TILE = 3, K_GATHER = 4, K_SELECT = 5, K_WEAVE = 6 };
 
 // ---------------------------------------------------------------- kernel args
 struct CopyArgs {
@@ -137,6 +137,21 @@ struct SelectArgs {
     uint32_t pad_;
 };
 
+// Interlace / de-interlace in registers: N planes of U-byte elements (N in 2..4,
+// U in 1, 2, 4, 8), every pointer 16-byte aligned and every plane a whole number
+// of 16-byte vectors.  Thread v joins (or splits) vector v of each plane and the
+// N consecutive 16-byte vectors of the joined array that hold the same elements.
+struct WeaveArgs {
+    uint64_t planes[4];       // interlace: the sets read; de-interlace: the sets written
+    uint64_t joined;          // interlace: output; de-interlace: input
+    uint32_t nvec;            // 16-byte vectors per plane
+    uint32_t n;               // planes
+    uint32_t unit;            // element bytes
+    uint32_t de;              // 1: de-interlace
+    uint32_t cached;          // 1: the joined side goes through the caches, 0: streamed
+    uint32_t chunks;          // chunks of 64 groups per wave (1 or 2)
+};
+
 enum TileFlags : uint32_t {
     TF_IN_TABLE = 1u,    // input rows are absolute plane pointers (interlace)
     TF_OUT_TABLE = 2u,   // output rows are absolute plane pointers (de-interlace)
@@ -221,6 +236,7 @@ struct TileOptions {
     int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead
                             // of the G = 1 ragged paths), 2 everywhere (testing)
     int fill = -1;          // refit odd extents for fewer, fuller tiles: 1 on, 0 off, -1 built-in
+    int weave = 1;          // interlace of 2-4 aligned sets of 1-8-byte elements in registers (0: LDS tile)
     int max_lds = 65536;    // hard limit
     bool use_tuned = false; // a tuned shape cached for the problem replaces these options
 };
@@ -284,6 +300,7 @@ struct Plan {
     TileArgs tile;
     GatherArgs gather;
     SelectArgs select;
+    WeaveArgs weave;
     uint32_t grid = 0;       // workgroups to launch
     uint64_t bytes = 0;      // bytes per side
 };

@@ -14,14 +14,17 @@
 //   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
 //   gather   src_count count esize indexed start stride src_off dst_off infile idxfile outfile
 //   stencil  rows cols radius shape nweights w... infile outfile             (float grids)
-//   interlace   n count esize off in_rb out_rb infile outfile    (infile: n planes back to back)
-//   deinterlace n count esize off in_rb out_rb infile outfile    (outfile: n planes back to back)
+//   interlace   n count esize off in_rb out_rb weave infile outfile    (infile: n planes back to back)
+//   deinterlace n count esize off in_rb out_rb weave infile outfile    (outfile: n planes back to back)
+// (interlace buffers start on 64-byte boundaries before the offset, as GPU
+// allocations do, so the aligned register path is planned where it applies)
 // Prints one line per job: "ok <plan description>" or "err <status> <reason>".
 #include <cstdio>
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
 #include <fstream>
+#include <new>
 #include <sstream>
 #include <string>
 #include <vector>
@@ -222,6 +225,46 @@ static void run_select_rm(const SelectArgs& a, uint32_t grid) {
     }
 }
 
+template <int U, int N, bool DE, int R>
+static void run_weave_undr(const WeaveArgs& a, uint32_t grid) {
+    for (uint32_t b = 0; b < grid; ++b) {
+        std::vector<uint8_t> lds((size_t)R * NT * N * 16, 0xA5);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_stage<U, N, DE, false, R>(a, b, lds.data(), tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_finish<U, N, DE, false, R>(a, b, lds.data(), tid);
+    }
+}
+
+template <int U, int N>
+static void run_weave_un(const WeaveArgs& a, uint32_t grid) {
+    if (a.chunks == 1) {
+        if (a.de) run_weave_undr<U, N, true, 1>(a, grid);
+        else run_weave_undr<U, N, false, 1>(a, grid);
+    } else {
+        if (a.de) run_weave_undr<U, N, true, 2>(a, grid);
+        else run_weave_undr<U, N, false, 2>(a, grid);
+    }
+}
+
+template <int U>
+static bool run_weave_u(const WeaveArgs& a, uint32_t grid) {
+    switch (a.n) {
+        case 2: run_weave_un<U, 2>(a, grid); return true;
+        case 3: run_weave_un<U, 3>(a, grid); return true;
+        case 4: run_weave_un<U, 4>(a, grid); return true;
+    }
+    return false;
+}
+
+static bool run_weave(const WeaveArgs& a, uint32_t grid) {
+    switch (a.unit) {
+        case 1: return run_weave_u<1>(a, grid);
+        case 2: return run_weave_u<2>(a, grid);
+        case 4: return run_weave_u<4>(a, grid);
+        case 8: return run_weave_u<8>(a, grid);
+    }
+    return false;
+}
+
 template <int R>
 static bool run_select_r(const SelectArgs& a, uint32_t grid) {
     switch (a.M) {
@@ -261,6 +304,8 @@ static bool emulate(const Plan& p) {
                 case 8: return run_select_r<8>(p.select, p.grid);
             }
             return false;
+        case K_WEAVE:
+            return run_weave(p.weave, p.grid);
         case K_GATHER:
             switch (p.gather.wbytes) {
                 case 16: run_gather_w<16>(p.gather, p.grid); return true;
@@ -406,15 +451,16 @@ int main(int argc, char** argv) {
         } else if (op == "interlace" || op == "deinterlace") {
             const bool de = op == "deinterlace";
             int n, esize, off; int64_t count; std::string inf, outf;
-            is >> n >> count >> esize >> off >> opt.in_row_bytes >> opt.out_row_bytes >> inf >> outf;
+            is >> n >> count >> esize >> off >> opt.in_row_bytes >> opt.out_row_bytes >> opt.weave >> inf >> outf;
             std::vector<uint8_t> in = read_file(inf);
             const size_t pb = (size_t)count * esize;
+            const std::align_val_t A64{64};
             std::vector<uint8_t*> planes(n);
             for (int c = 0; c < n; ++c) {
-                planes[c] = new uint8_t[off + pb + 1];
+                planes[c] = static_cast<uint8_t*>(::operator new[](off + pb + 1, A64));
                 std::memset(planes[c], 0x5A, off + pb + 1);
             }
-            uint8_t* flat = new uint8_t[off + pb * n + 1];
+            uint8_t* flat = static_cast<uint8_t*>(::operator new[](off + pb * n + 1, A64));
             std::memset(flat, 0x5A, off + pb * n + 1);
             if (!de) {
                 for (int c = 0; c < n; ++c) std::memcpy(planes[c] + off, in.data() + c * pb, pb);
@@ -432,9 +478,17 @@ int main(int argc, char** argv) {
                 std::ofstream f(outf, std::ios::binary);
                 for (int c = 0; c < n; ++c) f.write(reinterpret_cast<const char*>(planes[c] + off), (std::streamsize)pb);
             }
-            std::printf("ok %s\n", describe(plan).c_str());
-            for (int c = 0; c < n; ++c) delete[] planes[c];
-            delete[] flat;
+            // nothing written before or after any output buffer
+            bool clean = true;
+            for (int c = 0; c < n && de; ++c)
+                for (size_t i = 0; i < (size_t)off; ++i) clean = clean && planes[c][i] == 0x5A;
+            for (int c = 0; c < n && de; ++c) clean = clean && planes[c][off + pb] == 0x5A;
+            for (size_t i = 0; i < (size_t)off && !de; ++i) clean = clean && flat[i] == 0x5A;
+            if (!de) clean = clean && flat[off + pb * n] == 0x5A;
+            if (!clean) std::printf("err -2 wrote outside the output\n");
+            else std::printf("ok %s\n", describe(plan).c_str());
+            for (int c = 0; c < n; ++c) ::operator delete[](planes[c], A64);
+            ::operator delete[](flat, A64);
         } else if (op == "batched") {
             // batched k in_rb out_rb order chunk max_g ragged umt : then k lines
             //   "job ndim dims.. perm.. esize infile outfile"

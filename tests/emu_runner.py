@@ -43,8 +43,8 @@ def run(jobs):
                     fill (None: the planner's choice)
        reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
        gather:      op, src_count, esize, input (uint8), idx (int64) or start/stride/count, src_off, dst_off
-       interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb
-       deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb
+       interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb, weave
+       deinterlace: op, n, count, esize, input (uint8), off, in_rb, out_rb, weave
     Returns a list of (status_line, output) with output a uint8 array or list of planes."""
     exe = build()
     with tempfile.TemporaryDirectory() as td:
@@ -87,7 +87,8 @@ def run(jobs):
                                        str(int(j.get("umt", 0))), str(j.get("max_g", 0)), inf, outf]))
             elif j["op"] == "interlace":
                 np.concatenate(j["planes"]).tofile(inf)
-                lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
+                lines.append(f"interlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} "
+                             f"{int(j.get('weave', True))} {inf} {outf}")
             elif j["op"] == "batched":
                 lines.append(f"batched {len(j['jobs'])} {rb} {j.get('order', -1)} {j.get('chunk', 0)} "
                              f"{j.get('max_g', 0)} {int(j.get('ragged', False))} {int(j.get('umt', 0))}")
@@ -98,7 +99,8 @@ def run(jobs):
                                            *map(str, sub["perm"]), str(sub["esize"]), sf, of]))
             else:
                 j["input"].tofile(inf)
-                lines.append(f"deinterlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} {inf} {outf}")
+                lines.append(f"deinterlace {j['n']} {j['count']} {j['esize']} {j.get('off', 0)} {rb} "
+                             f"{int(j.get('weave', True))} {inf} {outf}")
         man = os.path.join(td, "manifest")
         with open(man, "w") as fh:
             fh.write("\n".join(lines) + "\n")

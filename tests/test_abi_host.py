@@ -137,6 +137,44 @@ def test_plan_uses_widest_vectors_on_aligned_buffers():
     assert d["unit"] == "2"
 
 
+def test_interlace_plan_classes():
+    """2-4 sets of 1-8-byte elements on 16-byte boundaries, a whole number of 16-byte
+    vectors each, are joined and split in registers (both sides streamed unless the
+    cache override sends the joined side through the caches); any other case keeps
+    the LDS tile, as does the override that switches the register path off."""
+    base = 1 << 40   # describe only reads pointer values
+
+    def cls(n, count, e, off=0, de=False, key="class"):
+        pb = count * e
+        planes = [base + n * pb + (c + 1) * (pb + 4096) + off for c in range(n)]
+        return rr.interlace_describe(base + off, planes, count, e, de)[key]
+
+    for n in (2, 3, 4):
+        for e in (1, 2, 4, 8):
+            count = 1000 * 16 // e
+            assert cls(n, count, e) == cls(n, count, e, de=True) == "weave"
+            assert cls(n, count, e, key="cached") == "0"
+            # two 64-group chunks per wave, one for a four-set interlace (LDS per workgroup)
+            assert cls(n, count, e, key="chunks") == ("1" if n == 4 else "2")
+            assert cls(n, count, e, de=True, key="chunks") == "2"
+            assert cls(n, count, e, off=4) == "tile"             # misaligned
+            assert cls(n, count + 1, e) == "tile"                # partial vector
+    assert cls(5, 4096, 4) == cls(2, 4096, 3) == cls(2, 4096, 16) == "tile"
+    assert cls(1, 4096, 4) == "copy"
+    assert cls(3, 0, 4) == "empty"
+    rr.set_tile_override(cache=3)
+    try:
+        assert cls(3, 4096, 4, key="cached") == cls(3, 4096, 4, de=True, key="cached") == "1"
+        rr.set_tile_override(cache=2)   # writes cached: the interlace's joined side only
+        assert cls(3, 4096, 4, key="cached") == "1" and cls(3, 4096, 4, de=True, key="cached") == "0"
+        rr.set_tile_override(weave=False)
+        assert cls(3, 4096, 4) == cls(3, 4096, 4, de=True) == "tile"
+    finally:
+        rr.set_tile_override()
+    with pytest.raises(rr.RRError):   # a plane overlapping the joined buffer
+        rr.interlace_describe(base, [base + 8, base + (1 << 30)], 1024, 4)
+
+
 def test_tuning_cache_changes_the_plan_and_round_trips(tmp_path):
     """A cached tile shape for a canonical problem is used by later plans of it."""
     K = rr.tune_context() + "|"

@@ -395,8 +395,8 @@ def test_emu_flat_read_and_merged_store_paths():
     for n, e in [(2, 4), (4, 1), (3, 4), (8, 2), (2, 8), (16, 1), (5, 4)]:
         count = 3 * 4096 + 48
         planes = [rr_synth.random_bytes(9300 + 10 * n + c, count * e) for c in range(n)]
-        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
-        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e,
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, weave=False))
+        jobs.append(dict(op="deinterlace", n=n, count=count, esize=e, weave=False,
                          input=rr_synth.random_bytes(9400 + n, n * count * e)))
     res = _check(jobs)
     flags = [int(s.split("flags=")[1].split()[0]) for s, _ in res]
@@ -427,7 +427,7 @@ def test_emu_short_output_rows_line_fill():
     for (e, n), g in SHORT_ROW_G.items():
         jobs.append(_perm_job((n, count), (1, 0), e, 9600 + 17 * n + e))
         planes = [rr_synth.random_bytes(9700 + 17 * n + e + 1000 * c, count * e) for c in range(n)]
-        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes))
+        jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, weave=False))
         keys += [(e, n, g)] * 2
     res = _check(jobs)
     for j, (e, n, g), (status, _) in zip(jobs, keys, res):
@@ -435,6 +435,28 @@ def test_emu_short_output_rows_line_fill():
         assert got == g, (e, n, got, g, status)
         if j["op"] == "interlace":   # plane-table plans stream both sides, no XCD ranges
             assert int(status.split("flags=")[1].split()[0]) & (1024 | 2048 | 256) == 0, status
+
+
+@pytest.mark.parametrize("e", [1, 2, 4, 8])
+def test_emu_register_interlace(e):
+    """Interlace and de-interlace of 2-4 sets on 16-byte boundaries with a whole number
+    of 16-byte vectors per set take the register path (several workgroups plus a
+    partial one) and match the oracle; a misaligned set, a partial vector or the
+    override keep the LDS tile, also bit-exact."""
+    jobs, want = [], []
+    for n in (2, 3, 4):
+        for off, count, weave, kind in [(0, 773 * 16 // e, True, "weave"), (16, 64 * 16 // e + 16 // e, True, "weave"),
+                                        (0, 773 * 16 // e, False, "tile"), (4, 300 * 16 // e, True, "tile"),
+                                        (0, 300 * 16 // e + 1, True, "tile")]:
+            seed = 11000 + 100 * n + 10 * e + off + count % 7 + int(weave)
+            planes = [rr_synth.random_bytes(seed + c, count * e) for c in range(n)]
+            jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, off=off, weave=weave))
+            jobs.append(dict(op="deinterlace", n=n, count=count, esize=e, off=off, weave=weave,
+                             input=rr_synth.random_bytes(seed + 50, n * count * e)))
+            want += [kind, kind]
+    res = _check(jobs)
+    for j, k, (status, _) in zip(jobs, want, res):
+        assert f"class={k}" in status, (j["op"], j["n"], j["count"], j["off"], status)
 
 
 def test_emu_flat_read_byte_tail():

@@ -211,16 +211,21 @@ def test_paper_table3_interlace_counts(rr):
 
 
 def test_flat_read_and_merged_store_paths(rr):
-    """Aligned interlace shapes that take the flat-read and merged-store paths."""
-    for n, e in [(2, 4), (4, 1), (3, 4), (8, 2), (2, 8), (16, 1), (5, 4)]:
-        count = 3 * 4096 + 48
-        _say("flat/merge", n, e)
-        planes = [rr_synth.random_bytes(9300 + 10 * n + c, count * e) for c in range(n)]
-        assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e))
-        x = rr_synth.random_bytes(9400 + n, n * count * e)
-        got = gpu_deinterlace(rr, x, n, e)
-        ref = oracle.deinterlace(x, n, e)
-        assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (n, e)
+    """Aligned interlace shapes that take the flat-read and merged-store paths (the
+    LDS tile, with the register path switched off)."""
+    rr.set_tile_override(weave=False)
+    try:
+        for n, e in [(2, 4), (4, 1), (3, 4), (8, 2), (2, 8), (16, 1), (5, 4)]:
+            count = 3 * 4096 + 48
+            _say("flat/merge", n, e)
+            planes = [rr_synth.random_bytes(9300 + 10 * n + c, count * e) for c in range(n)]
+            assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e))
+            x = rr_synth.random_bytes(9400 + n, n * count * e)
+            got = gpu_deinterlace(rr, x, n, e)
+            ref = oracle.deinterlace(x, n, e)
+            assert all(np.array_equal(g, r) for g, r in zip(got, ref)), (n, e)
+    finally:
+        rr.set_tile_override()
     for i, (dims, perm, e) in enumerate([((4096, 3), (1, 0), 4), ((64, 48, 6), (2, 0, 1), 2),
                                          ((2048, 5, 2), (1, 2, 0), 8)]):
         check_permute(rr, dims, perm, e, 9500 + i)
@@ -236,7 +241,40 @@ def test_short_output_rows_line_fill(rr):
         check_permute(rr, (n, count), (1, 0), e, 9600 + 17 * n + e)
         _say("interlace line fill", n, e)
         planes = [rr_synth.random_bytes(9700 + 17 * n + e + 1000 * c, count * e) for c in range(n)]
-        assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e)), (n, e)
+        rr.set_tile_override(weave=False)
+        try:
+            assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e)), (n, e)
+        finally:
+            rr.set_tile_override()
+
+
+@pytest.mark.parametrize("e", [1, 2, 4, 8])
+def test_register_interlace(rr, e):
+    """Interlace and de-interlace of 2-4 sets on 16-byte boundaries with a whole number
+    of 16-byte vectors each take the register path; bit-exact with the joined side
+    streamed (built in) or through the caches, over several workgroups plus a partial
+    one and at 2^16 + 3 vectors per set."""
+    base = 1 << 40   # describe only reads pointer values
+    try:
+        for cache in (None, 0, 3):
+            rr.set_tile_override(cache=cache)
+            for n in (2, 3, 4):
+                for nvec in (773, (1 << 16) + 3):
+                    count = nvec * 16 // e
+                    pb = count * e
+                    fake = [base + n * pb + (c + 1) * (pb + 4096) for c in range(n)]
+                    for de in (False, True):
+                        d = rr.interlace_describe(base, fake, count, e, de)
+                        assert d["class"] == "weave", d
+                        assert d["cached"] == ("1" if cache == 3 else "0"), (cache, d)
+                    _say("register interlace", cache, n, nvec, e)
+                    planes = [rr_synth.random_bytes(12000 + 100 * n + 10 * e + c, pb) for c in range(n)]
+                    assert np.array_equal(gpu_interlace(rr, planes, e), oracle.interlace(planes, e)), (n, e)
+                    x = rr_synth.random_bytes(12500 + 100 * n + e, n * pb)
+                    got = gpu_deinterlace(rr, x, n, e)
+                    assert all(np.array_equal(g, r) for g, r in zip(got, oracle.deinterlace(x, n, e))), (n, e)
+    finally:
+        rr.set_tile_override()
 
 
 def test_flat_read_byte_tail(rr):
