@@ -438,7 +438,7 @@ rr_status rr_interlace_describe(const void* flat, const void* const* planes, int
  * keeping each side's rows at least half their target, one 128-byte line and a
  * multiple of 16 bytes (or the whole axis).  RR_ERR_INVALID_ARG also for both fill
  * flags.  RR_TILE_NO_WEAVE sends every interlace and de-interlace through the LDS
- * tile (by default 2-4 sets of 1-, 2-, 4- or 8-byte elements, every pointer on a
+ * tile (by default 2-8 sets of 1-, 2-, 4- or 8-byte elements, every pointer on a
  * 16-byte boundary and every set a whole number of 16-byte vectors, are joined or
  * split in registers, one 16-byte vector of each set per thread; the cache bits
  * then say whether the joined side goes through the caches, streamed by

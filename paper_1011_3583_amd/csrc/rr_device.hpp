@@ -630,13 +630,14 @@ RR_HD void weave_regs(const uint32_t (&in)[N][4], uint32_t (&out)[N][4]) {
     }
 }
 
-// LDS slot of vector m (0 .. 64 * N - 1) of a wave's joined span.  For even N
-// the low three bits are XORed with the next three, so the lane-strided side
-// (lane L at vector L * N + k) spreads over the banks; the consecutive side
-// (lane L at vector k * 64 + L) permutes within aligned groups of eight.
+// LDS slot of vector m (0 .. 64 * N - 1) of a wave's joined span.  For N = 2,
+// 4, 8 the low three bits are XORed with the next three, so the lane-strided
+// side (lane L at vector L * N + k) spreads over the banks; the consecutive side
+// (lane L at vector k * 64 + L) permutes within aligned groups of eight.  Other
+// N are odd or leave at most two lanes of eight on one bank unswizzled.
 template <int N>
 RR_HD uint32_t weave_slot(uint32_t m) {
-    return N % 2 == 0 ? m ^ ((m >> 3) & 7u) : m;
+    return (N & (N - 1)) == 0 ? m ^ ((m >> 3) & 7u) : m;
 }
 
 // Keeps the scheduler from moving instructions across this point: placed after

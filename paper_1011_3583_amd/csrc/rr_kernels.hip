@@ -12,7 +12,7 @@
 //  * k_select -- boxes that keep a strided fastest axis (one component of
 //               interleaved records): whole records are read with 16-byte
 //               vectors and the kept bytes packed in registers.
-//  * k_weave -- interlace / de-interlace of 2-4 aligned sets of 1-8-byte
+//  * k_weave -- interlace / de-interlace of 2-8 aligned sets of 1-8-byte
 //               elements joined or split in registers, one 16-byte vector of
 //               each set per thread; each wave swaps the joined vectors through
 //               its own LDS region so both sides are read and written with
@@ -184,16 +184,22 @@ static hipError_t launch_select(const SelectArgs& a, uint32_t grid, hipStream_t 
     }
 }
 
+// Two chunks per wave are built for up to four sets only (the planner's choice).
 template <int U, int N>
 static hipError_t launch_weave_un(const WeaveArgs& a, uint32_t grid, hipStream_t st) {
-    switch (a.chunks * 2 + a.de) {
-        case 2: hipLaunchKernelGGL((k_weave<U, N, false, 1>), dim3(grid), dim3(NT), 0, st, a); break;
-        case 3: hipLaunchKernelGGL((k_weave<U, N, true, 1>), dim3(grid), dim3(NT), 0, st, a); break;
-        case 4: hipLaunchKernelGGL((k_weave<U, N, false, 2>), dim3(grid), dim3(NT), 0, st, a); break;
-        case 5: hipLaunchKernelGGL((k_weave<U, N, true, 2>), dim3(grid), dim3(NT), 0, st, a); break;
-        default: return hipErrorInvalidValue;
+    if (a.chunks == 1) {
+        if (a.de) hipLaunchKernelGGL((k_weave<U, N, true, 1>), dim3(grid), dim3(NT), 0, st, a);
+        else hipLaunchKernelGGL((k_weave<U, N, false, 1>), dim3(grid), dim3(NT), 0, st, a);
+        return hipGetLastError();
     }
-    return hipGetLastError();
+    if constexpr (N <= 4) {
+        if (a.chunks == 2) {
+            if (a.de) hipLaunchKernelGGL((k_weave<U, N, true, 2>), dim3(grid), dim3(NT), 0, st, a);
+            else hipLaunchKernelGGL((k_weave<U, N, false, 2>), dim3(grid), dim3(NT), 0, st, a);
+            return hipGetLastError();
+        }
+    }
+    return hipErrorInvalidValue;
 }
 
 template <int U>
@@ -202,6 +208,10 @@ static hipError_t launch_weave_u(const WeaveArgs& a, uint32_t grid, hipStream_t 
         case 2: return launch_weave_un<U, 2>(a, grid, st);
         case 3: return launch_weave_un<U, 3>(a, grid, st);
         case 4: return launch_weave_un<U, 4>(a, grid, st);
+        case 5: return launch_weave_un<U, 5>(a, grid, st);
+        case 6: return launch_weave_un<U, 6>(a, grid, st);
+        case 7: return launch_weave_un<U, 7>(a, grid, st);
+        case 8: return launch_weave_un<U, 8>(a, grid, st);
         default: return hipErrorInvalidValue;
     }
 }

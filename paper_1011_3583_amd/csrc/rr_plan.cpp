@@ -1059,14 +1059,14 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     p->bytes = (uint64_t)(count * n * esize);
     if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
     if (n == 1) { plan_copy(de ? planes[0] : flat, de ? flat : planes[0], (uint64_t)(count * esize), p); return RR_OK; }
-    // 2-4 sets of 1-8-byte elements on 16-byte boundaries, a whole number of
+    // 2-8 sets of 1-8-byte elements on 16-byte boundaries, a whole number of
     // 16-byte vectors each: joined and split in registers, vectors swapped
     // between lanes through a wave-private LDS region (no tile, no workgroup
     // barrier)
     const bool pow2_unit = esize == 1 || esize == 2 || esize == 4 || esize == 8;
     bool aligned = flat % 16 == 0 && (count * esize) % 16 == 0;
     for (int c = 0; c < n; ++c) aligned = aligned && planes[c] % 16 == 0;
-    if (opt.weave && pow2_unit && n >= 2 && n <= 4 && aligned && (count * esize) / 16 <= 0x7fffffffLL) {
+    if (opt.weave && pow2_unit && n >= 2 && n <= WEAVE_MAX_SETS && aligned && (count * esize) / 16 <= 0x7fffffffLL) {
         p->kind = K_WEAVE;
         WeaveArgs& w = p->weave;
         std::memset(&w, 0, sizeof(w));
@@ -1080,10 +1080,11 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
         // only); built in: both sides streamed, every access a whole line per
         // eight lanes
         w.cached = opt.cache < 0 ? 0u : (uint32_t)((opt.cache >> (de ? 0 : 1)) & 1);
-        // two chunks per wave (2 * n loads in flight per lane) except for a
-        // four-set interlace, whose 32 KiB of LDS per workgroup at two chunks
-        // would cut the waves per CU from 32 to 20
-        w.chunks = n == 4 && !de ? 1u : 2u;
+        // two chunks per wave (2 * n loads in flight per lane) up to three sets
+        // and for a four-set de-interlace; one from four sets on (two would take
+        // 32 KiB or more of LDS per workgroup, cutting the waves per CU to 20 or
+        // fewer)
+        w.chunks = n <= 3 || (n == 4 && de) ? 2u : 1u;
         p->grid = (uint32_t)((w.nvec + (uint64_t)NT * w.chunks - 1) / ((uint64_t)NT * w.chunks));
         return RR_OK;
     }

@@ -137,12 +137,14 @@ struct SelectArgs {
     uint32_t pad_;
 };
 
-// Interlace / de-interlace in registers: N planes of U-byte elements (N in 2..4,
-// U in 1, 2, 4, 8), every pointer 16-byte aligned and every plane a whole number
-// of 16-byte vectors.  Thread v joins (or splits) vector v of each plane and the
-// N consecutive 16-byte vectors of the joined array that hold the same elements.
+// Interlace / de-interlace in registers: N planes of U-byte elements (N in
+// 2..WEAVE_MAX_SETS, U in 1, 2, 4, 8), every pointer 16-byte aligned and every
+// plane a whole number of 16-byte vectors.  Thread v joins (or splits) vector v
+// of each plane and the N consecutive 16-byte vectors of the joined array that
+// hold the same elements.
+constexpr int WEAVE_MAX_SETS = 8;
 struct WeaveArgs {
-    uint64_t planes[4];       // interlace: the sets read; de-interlace: the sets written
+    uint64_t planes[WEAVE_MAX_SETS];   // interlace: the sets read; de-interlace: the sets written
     uint64_t joined;          // interlace: output; de-interlace: input
     uint32_t nvec;            // 16-byte vectors per plane
     uint32_t n;               // planes

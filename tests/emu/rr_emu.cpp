@@ -235,22 +235,32 @@ static void run_weave_undr(const WeaveArgs& a, uint32_t grid) {
 }
 
 template <int U, int N>
-static void run_weave_un(const WeaveArgs& a, uint32_t grid) {
+static bool run_weave_un(const WeaveArgs& a, uint32_t grid) {
     if (a.chunks == 1) {
         if (a.de) run_weave_undr<U, N, true, 1>(a, grid);
         else run_weave_undr<U, N, false, 1>(a, grid);
-    } else {
-        if (a.de) run_weave_undr<U, N, true, 2>(a, grid);
-        else run_weave_undr<U, N, false, 2>(a, grid);
+        return true;
     }
+    if constexpr (N <= 4) {
+        if (a.chunks == 2) {
+            if (a.de) run_weave_undr<U, N, true, 2>(a, grid);
+            else run_weave_undr<U, N, false, 2>(a, grid);
+            return true;
+        }
+    }
+    return false;
 }
 
 template <int U>
 static bool run_weave_u(const WeaveArgs& a, uint32_t grid) {
     switch (a.n) {
-        case 2: run_weave_un<U, 2>(a, grid); return true;
-        case 3: run_weave_un<U, 3>(a, grid); return true;
-        case 4: run_weave_un<U, 4>(a, grid); return true;
+        case 2: return run_weave_un<U, 2>(a, grid);
+        case 3: return run_weave_un<U, 3>(a, grid);
+        case 4: return run_weave_un<U, 4>(a, grid);
+        case 5: return run_weave_un<U, 5>(a, grid);
+        case 6: return run_weave_un<U, 6>(a, grid);
+        case 7: return run_weave_un<U, 7>(a, grid);
+        case 8: return run_weave_un<U, 8>(a, grid);
     }
     return false;
 }

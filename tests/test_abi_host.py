@@ -138,7 +138,7 @@ def test_plan_uses_widest_vectors_on_aligned_buffers():
 
 
 def test_interlace_plan_classes():
-    """2-4 sets of 1-8-byte elements on 16-byte boundaries, a whole number of 16-byte
+    """2-8 sets of 1-8-byte elements on 16-byte boundaries, a whole number of 16-byte
     vectors each, are joined and split in registers (both sides streamed unless the
     cache override sends the joined side through the caches); any other case keeps
     the LDS tile, as does the override that switches the register path off."""
@@ -149,17 +149,18 @@ def test_interlace_plan_classes():
         planes = [base + n * pb + (c + 1) * (pb + 4096) + off for c in range(n)]
         return rr.interlace_describe(base + off, planes, count, e, de)[key]
 
-    for n in (2, 3, 4):
+    for n in range(2, 9):
         for e in (1, 2, 4, 8):
             count = 1000 * 16 // e
             assert cls(n, count, e) == cls(n, count, e, de=True) == "weave"
             assert cls(n, count, e, key="cached") == "0"
-            # two 64-group chunks per wave, one for a four-set interlace (LDS per workgroup)
-            assert cls(n, count, e, key="chunks") == ("1" if n == 4 else "2")
-            assert cls(n, count, e, de=True, key="chunks") == "2"
+            # two 64-group chunks per wave up to three sets and for a four-set
+            # de-interlace, else one (LDS per workgroup)
+            assert cls(n, count, e, key="chunks") == ("2" if n <= 3 else "1")
+            assert cls(n, count, e, de=True, key="chunks") == ("2" if n <= 4 else "1")
             assert cls(n, count, e, off=4) == "tile"             # misaligned
             assert cls(n, count + 1, e) == "tile"                # partial vector
-    assert cls(5, 4096, 4) == cls(2, 4096, 3) == cls(2, 4096, 16) == "tile"
+    assert cls(9, 4096, 4) == cls(2, 4096, 3) == cls(2, 4096, 16) == "tile"
     assert cls(1, 4096, 4) == "copy"
     assert cls(3, 0, 4) == "empty"
     rr.set_tile_override(cache=3)

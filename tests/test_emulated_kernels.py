@@ -439,12 +439,12 @@ def test_emu_short_output_rows_line_fill():
 
 @pytest.mark.parametrize("e", [1, 2, 4, 8])
 def test_emu_register_interlace(e):
-    """Interlace and de-interlace of 2-4 sets on 16-byte boundaries with a whole number
+    """Interlace and de-interlace of 2-8 sets on 16-byte boundaries with a whole number
     of 16-byte vectors per set take the register path (several workgroups plus a
     partial one) and match the oracle; a misaligned set, a partial vector or the
     override keep the LDS tile, also bit-exact."""
     jobs, want = [], []
-    for n in (2, 3, 4):
+    for n in range(2, 9):
         for off, count, weave, kind in [(0, 773 * 16 // e, True, "weave"), (16, 64 * 16 // e + 16 // e, True, "weave"),
                                         (0, 773 * 16 // e, False, "tile"), (4, 300 * 16 // e, True, "tile"),
                                         (0, 300 * 16 // e + 1, True, "tile")]:

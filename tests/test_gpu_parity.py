@@ -250,7 +250,7 @@ def test_short_output_rows_line_fill(rr):
 
 @pytest.mark.parametrize("e", [1, 2, 4, 8])
 def test_register_interlace(rr, e):
-    """Interlace and de-interlace of 2-4 sets on 16-byte boundaries with a whole number
+    """Interlace and de-interlace of 2-8 sets on 16-byte boundaries with a whole number
     of 16-byte vectors each take the register path; bit-exact with the joined side
     streamed (built in) or through the caches, over several workgroups plus a partial
     one and at 2^16 + 3 vectors per set."""
@@ -258,7 +258,7 @@ def test_register_interlace(rr, e):
     try:
         for cache in (None, 0, 3):
             rr.set_tile_override(cache=cache)
-            for n in (2, 3, 4):
+            for n in range(2, 9):
                 for nvec in (773, (1 << 16) + 3):
                     count = nvec * 16 // e
                     pb = count * e
