@@ -192,6 +192,8 @@ def kernel_name(d: dict) -> str:
         return f"k_run<{d['vec']}>"
     if d["class"] == "copy":
         return f"k_copy<{d['vec']}>"
+    if d["class"] == "weave":
+        return f"k_weave<{d['unit']},{d['n']},{d['de']},{d['chunks']}>"
     return d["class"]
 
 

@@ -661,13 +661,14 @@ RR_HD void sched_fence() {
 // [b * R * NT, (b + 1) * R * NT), chunk r of its wave w starting at
 // (b * R + r) * NT + w * 64.  The joined side goes through the caches when C is
 // true, else is streamed like the set side.  Only chunks that hold the last
-// group check vector bounds.  lds: R * NT * N * 16 bytes.
+// group check vector bounds.  `off` is added to every set and joined pointer
+// (the batch's byte offset).  lds: R * NT * N * 16 bytes.
 RR_HD uint64_t weave_chunk(uint32_t block, int r, uint32_t wave, int R) {
     return ((uint64_t)block * R + r) * NT + wave * 64u;
 }
 
 template <int U, int N, bool DE, bool C, int R>
-RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint8_t* lds, uint32_t tid) {
+RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint64_t off, uint8_t* lds, uint32_t tid) {
     constexpr uint32_t WV = 64, NW = NT / WV;
     const uint32_t wave = tid / WV, lane = tid % WV;
     if constexpr (!DE) {
@@ -680,7 +681,7 @@ RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint8_t* lds, uint32_
             if (ok[r])
 #pragma unroll
                 for (int s = 0; s < N; ++s)
-                    gload<16>(reinterpret_cast<const uint8_t*>(a.planes[s]) + v * 16u, in[r][s]);
+                    gload<16>(reinterpret_cast<const uint8_t*>(a.planes[s]) + off + v * 16u, in[r][s]);
         }
         sched_fence();
 #pragma unroll
@@ -694,7 +695,7 @@ RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint8_t* lds, uint32_
         }
     } else {
         const uint64_t total = (uint64_t)a.nvec * N;
-        const uint8_t* joined = reinterpret_cast<const uint8_t*>(a.joined);
+        const uint8_t* joined = reinterpret_cast<const uint8_t*>(a.joined) + off;
         if (weave_chunk(block, R - 1, wave, R) + WV <= a.nvec) {
             uint32_t x[R][N][4];
 #pragma unroll
@@ -727,12 +728,12 @@ RR_HD void weave_stage(const WeaveArgs& a, uint32_t block, uint8_t* lds, uint32_
 }
 
 template <int U, int N, bool DE, bool C, int R>
-RR_HD void weave_finish(const WeaveArgs& a, uint32_t block, const uint8_t* lds, uint32_t tid) {
+RR_HD void weave_finish(const WeaveArgs& a, uint32_t block, uint64_t off, const uint8_t* lds, uint32_t tid) {
     constexpr uint32_t WV = 64, NW = NT / WV;
     const uint32_t wave = tid / WV, lane = tid % WV;
     if constexpr (!DE) {
         const uint64_t total = (uint64_t)a.nvec * N;
-        uint8_t* joined = reinterpret_cast<uint8_t*>(a.joined);
+        uint8_t* joined = reinterpret_cast<uint8_t*>(a.joined) + off;
         if (weave_chunk(block, R - 1, wave, R) + WV <= a.nvec) {
             uint32_t x[R][N][4];
 #pragma unroll
@@ -771,7 +772,7 @@ RR_HD void weave_finish(const WeaveArgs& a, uint32_t block, const uint8_t* lds, 
             for (int k = 0; k < N; ++k) sload<16>(w + 16u * weave_slot<N>(lane * N + k), in[k]);
             weave_regs<U, N, true>(in, out);
 #pragma unroll
-            for (int s = 0; s < N; ++s) gstore<16>(reinterpret_cast<uint8_t*>(a.planes[s]) + v * 16u, out[s]);
+            for (int s = 0; s < N; ++s) gstore<16>(reinterpret_cast<uint8_t*>(a.planes[s]) + off + v * 16u, out[s]);
         }
     }
 }

@@ -78,19 +78,23 @@ __global__ __launch_bounds__(NT) void k_select(const SelectArgs a) {
 // operations of a wave complete in issue order, so a wave-level barrier (which
 // keeps the compiler from moving the reads above the writes) is enough.
 template <int U, int N, bool DE, bool C, int R>
-__device__ __forceinline__ void weave_block(const WeaveArgs& a, uint8_t* lds) {
-    weave_stage<U, N, DE, C, R>(a, blockIdx.x, lds, threadIdx.x);
+__device__ __forceinline__ void weave_block(const WeaveArgs& a, uint32_t block, uint64_t off, uint8_t* lds) {
+    weave_stage<U, N, DE, C, R>(a, block, off, lds, threadIdx.x);
     __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
     __builtin_amdgcn_wave_barrier();
     __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-    weave_finish<U, N, DE, C, R>(a, blockIdx.x, lds, threadIdx.x);
+    weave_finish<U, N, DE, C, R>(a, block, off, lds, threadIdx.x);
 }
 
+// Workgroups [b * bpb, (b + 1) * bpb) cover batch b (one batch for rr_interlace).
 template <int U, int N, bool DE, int R>
 __global__ __launch_bounds__(NT) void k_weave(const WeaveArgs a) {
     __shared__ __attribute__((aligned(16))) uint8_t lds[R * NT * N * 16];
-    if (a.cached) weave_block<U, N, DE, true, R>(a, lds);
-    else weave_block<U, N, DE, false, R>(a, lds);
+    const uint32_t batch = blockIdx.x / a.bpb;
+    const uint32_t block = blockIdx.x - batch * a.bpb;
+    const uint64_t off = (uint64_t)batch * a.bstride;
+    if (a.cached) weave_block<U, N, DE, true, R>(a, block, off, lds);
+    else weave_block<U, N, DE, false, R>(a, block, off, lds);
 }
 
 template <int U, int G>

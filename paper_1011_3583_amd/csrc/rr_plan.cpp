@@ -1028,6 +1028,79 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     return RR_OK;
 }
 
+// 2-8 sets of 1-8-byte elements on 16-byte boundaries, a whole number of
+// 16-byte vectors each: joined and split in registers, vectors swapped between
+// lanes through a wave-private LDS region (no tile, no workgroup barrier).
+// nbatch problems lie bstride bytes apart on both sides.  False (nothing
+// planned) where these conditions do not hold.
+static bool plan_weave(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize, bool de,
+                       int64_t nbatch, uint64_t bstride, const TileOptions& opt, Plan* p) {
+    const bool pow2_unit = esize == 1 || esize == 2 || esize == 4 || esize == 8;
+    if (!opt.weave || !pow2_unit || n < 2 || n > WEAVE_MAX_SETS || count <= 0 || nbatch < 1) return false;
+    // eight-set de-interlaces, and interlaces of eight sets of 4-8-byte
+    // elements, stay on the tile (measured 4-10 % faster from cold caches)
+    if (n == 8 && (de || esize >= 4)) return false;
+    bool aligned = flat % 16 == 0 && (count * esize) % 16 == 0 && bstride % 16 == 0;
+    for (int c = 0; c < n; ++c) aligned = aligned && planes[c] % 16 == 0;
+    const int64_t nvec = count * esize / 16;
+    if (!aligned || nvec > 0x7fffffffLL) return false;
+    // two chunks per wave (2 * n loads in flight per lane) up to three sets and
+    // for a four-set de-interlace; one from four sets on (two would take 32 KiB
+    // or more of LDS per workgroup, cutting the waves per CU to 20 or fewer)
+    const uint32_t chunks = n <= 3 || (n == 4 && de) ? 2u : 1u;
+    const int64_t bpb = (nvec + (int64_t)NT * chunks - 1) / ((int64_t)NT * chunks);
+    if (bpb * nbatch > 0x7fffffffLL) return false;
+    p->kind = K_WEAVE;
+    WeaveArgs& w = p->weave;
+    std::memset(&w, 0, sizeof(w));
+    for (int c = 0; c < n; ++c) w.planes[c] = planes[c];
+    w.joined = flat;
+    w.bstride = nbatch > 1 ? bstride : 0;
+    w.nvec = (uint32_t)nvec;
+    w.n = (uint32_t)n;
+    w.unit = (uint32_t)esize;
+    w.de = de ? 1u : 0u;
+    // cache override: bit 0 cached reads, bit 1 cached writes (joined side
+    // only).  Built in: streamed, except the joined stores of an interlace of an
+    // odd number of sets, which measured 0.5-7 % faster through the caches from
+    // cold caches (even numbers of sets 0-5 % slower; cached joined loads of a
+    // de-interlace 15-40 % slower)
+    w.cached = opt.cache >= 0 ? (uint32_t)((opt.cache >> (de ? 0 : 1)) & 1) : (!de && n % 2 == 1) ? 1u : 0u;
+    w.chunks = chunks;
+    w.bpb = (uint32_t)bpb;
+    p->grid = (uint32_t)(bpb * nbatch);
+    return true;
+}
+
+// A dense permute that swaps the two fastest axes where one of them has 2-8
+// entries -- (n, L) -> (L, n), an interlace of n sets, or (L, n) -> (n, L), a
+// de-interlace -- optionally under one unpermuted slower axis (a batch of them):
+// the register interlace above with the sets at a fixed stride.  Batched sets
+// of fewer than 256 vectors (4 KiB) stay on the tile kernel, whose stacked
+// tiles hold several small transposes each; the register path would give each
+// one a whole workgroup.
+static bool plan_weave_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt, Plan* p) {
+    if (c.strided || !(c.elem_bytes == 1 || c.elem_bytes == 2 || c.elem_bytes == 4 || c.elem_bytes == 8)) return false;
+    const bool r2 = c.rank == 2 && c.perm[0] == 1 && c.perm[1] == 0;
+    const bool r3 = c.rank == 3 && c.perm[0] == 0 && c.perm[1] == 2 && c.perm[2] == 1;
+    if (!r2 && !r3) return false;
+    const int64_t e = c.elem_bytes;
+    const int64_t A = c.dims[c.rank - 2], B = c.dims[c.rank - 1];   // input: A rows of B elements
+    const int64_t nbatch = r3 ? c.dims[0] : 1;
+    const uint64_t bstride = (uint64_t)(A * B * e);
+    if (nbatch > 1 && std::max(A, B) * e < (int64_t)NT * 16) return false;
+    uint64_t planes[WEAVE_MAX_SETS];
+    if (A >= 2 && A <= WEAVE_MAX_SETS) {   // A sets of B elements -> joined
+        for (int k = 0; k < (int)A; ++k) planes[k] = src + (uint64_t)(k * B * e);
+        if (plan_weave(dst, planes, (int)A, B, (int)e, false, nbatch, bstride, opt, p)) return true;
+    }
+    if (B >= 2 && B <= WEAVE_MAX_SETS) {   // joined (A groups of B) -> B sets of A elements
+        for (int k = 0; k < (int)B; ++k) planes[k] = dst + (uint64_t)(k * A * e);
+        if (plan_weave(src, planes, (int)B, A, (int)e, true, nbatch, bstride, opt, p)) return true;
+    }
+    return false;
+}
+
 rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
                        Plan* p, std::string* why) {
     p->c = c;
@@ -1041,53 +1114,30 @@ rr_status plan_permute(uint64_t dst, uint64_t src, const Canon& c, const TileOpt
     // a box whose fastest input axis is not contiguous (a dropped or cut innermost
     // axis) has no input rows to tile: gather its elements (one run each)
     if (c.sinb[c.rank - 1] != c.elem_bytes || c.perm[c.rank - 1] == c.rank - 1) return plan_run(dst, src, c, p, why);
+    // small-axis transposes: the register interlace, for an interlace only where
+    // the tile would not merge its short output rows into whole 16-byte stores
+    Plan wv;
+    wv.c = c;
+    wv.bytes = p->bytes;
+    const bool weave = plan_weave_permute(dst, src, c, opt, &wv);
+    if (weave && wv.weave.de) { *p = wv; return RR_OK; }
     // a tuned shape for this problem replaces the built-in choice (not an explicit override)
     TileOptions tuned;
+    rr_status st;
     if (opt.use_tuned && tune_lookup(c, dst, src, &tuned)) {
         tuned.max_lds = opt.max_lds;
-        return plan_tile(dst, src, c, tuned, p, why);
+        st = plan_tile(dst, src, c, tuned, p, why);
+    } else {
+        st = plan_tile(dst, src, c, opt, p, why);
     }
-    return plan_tile(dst, src, c, opt, p, why);
+    if (st == RR_OK && weave && p->kind == K_TILE && !(p->tile.flags & TF_OUT_MERGE)) *p = wv;
+    return st;
 }
 
-// Interlace: virtual input (n planes, count) -> output (count, n).
-// De-interlace: input (count, n) -> virtual output (n planes, count).
-rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
-                         bool de, const TileOptions& opt, Plan* p, std::string* why) {
-    const uint64_t dst = flat;  // interlace: the joined output; de-interlace: the joined input
-    p->c = Canon{};
-    p->bytes = (uint64_t)(count * n * esize);
-    if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
-    if (n == 1) { plan_copy(de ? planes[0] : flat, de ? flat : planes[0], (uint64_t)(count * esize), p); return RR_OK; }
-    // 2-8 sets of 1-8-byte elements on 16-byte boundaries, a whole number of
-    // 16-byte vectors each: joined and split in registers, vectors swapped
-    // between lanes through a wave-private LDS region (no tile, no workgroup
-    // barrier)
-    const bool pow2_unit = esize == 1 || esize == 2 || esize == 4 || esize == 8;
-    bool aligned = flat % 16 == 0 && (count * esize) % 16 == 0;
-    for (int c = 0; c < n; ++c) aligned = aligned && planes[c] % 16 == 0;
-    if (opt.weave && pow2_unit && n >= 2 && n <= WEAVE_MAX_SETS && aligned && (count * esize) / 16 <= 0x7fffffffLL) {
-        p->kind = K_WEAVE;
-        WeaveArgs& w = p->weave;
-        std::memset(&w, 0, sizeof(w));
-        for (int c = 0; c < n; ++c) w.planes[c] = planes[c];
-        w.joined = flat;
-        w.nvec = (uint32_t)((count * esize) / 16);
-        w.n = (uint32_t)n;
-        w.unit = (uint32_t)esize;
-        w.de = de ? 1u : 0u;
-        // cache override: bit 0 cached reads, bit 1 cached writes (joined side
-        // only); built in: both sides streamed, every access a whole line per
-        // eight lanes
-        w.cached = opt.cache < 0 ? 0u : (uint32_t)((opt.cache >> (de ? 0 : 1)) & 1);
-        // two chunks per wave (2 * n loads in flight per lane) up to three sets
-        // and for a four-set de-interlace; one from four sets on (two would take
-        // 32 KiB or more of LDS per workgroup, cutting the waves per CU to 20 or
-        // fewer)
-        w.chunks = n <= 3 || (n == 4 && de) ? 2u : 1u;
-        p->grid = (uint32_t)((w.nvec + (uint64_t)NT * w.chunks - 1) / ((uint64_t)NT * w.chunks));
-        return RR_OK;
-    }
+// The tile plan of an interlace (plane-pointer table on the set side).
+static rr_status plan_interlace_tile(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
+                                     bool de, const TileOptions& opt, Plan* p, std::string* why) {
+    const uint64_t dst = flat;
     p->kind = K_TILE;
     TileArgs& a = p->tile;
     std::memset(&a, 0, sizeof(a));
@@ -1160,6 +1210,20 @@ rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t c
     return RR_OK;
 }
 
+// Interlace: virtual input (n planes, count) -> output (count, n).
+// De-interlace: input (count, n) -> virtual output (n planes, count).
+rr_status plan_interlace(uint64_t flat, const uint64_t* planes, int n, int64_t count, int esize,
+                         bool de, const TileOptions& opt, Plan* p, std::string* why) {
+    p->c = Canon{};
+    p->bytes = (uint64_t)(count * n * esize);
+    if (count == 0) { p->kind = K_EMPTY; p->grid = 0; return RR_OK; }
+    if (n == 1) { plan_copy(de ? planes[0] : flat, de ? flat : planes[0], (uint64_t)(count * esize), p); return RR_OK; }
+    if (de && plan_weave(flat, planes, n, count, esize, de, 1, 0, opt, p)) return RR_OK;
+    rr_status st = plan_interlace_tile(flat, planes, n, count, esize, de, opt, p, why);
+    if (st == RR_OK && !de && !(p->tile.flags & TF_OUT_MERGE)) plan_weave(flat, planes, n, count, esize, de, 1, 0, opt, p);
+    return st;
+}
+
 std::string describe(const Plan& p) {
     std::ostringstream o;
     static const char* names[] = {"empty", "copy", "run", "tile", "gather", "select", "weave"};
@@ -1175,7 +1239,8 @@ std::string describe(const Plan& p) {
         o << " vec=" << p.run.wbytes << " vpr=" << p.run.vpr << " ua=" << p.run.ua << " cached=" << p.run.cached;
     if (p.kind == K_WEAVE)
         o << " n=" << p.weave.n << " unit=" << p.weave.unit << " de=" << p.weave.de << " nvec=" << p.weave.nvec
-          << " cached=" << p.weave.cached << " chunks=" << p.weave.chunks;
+          << " cached=" << p.weave.cached << " chunks=" << p.weave.chunks
+          << " batches=" << (p.weave.bpb ? p.grid / p.weave.bpb : 0);
     if (p.kind == K_GATHER) o << " vec=" << p.gather.wbytes << " k=" << p.gather.k << " indexed=" << (p.gather.idx != 0);
     if (p.kind == K_SELECT) o << " vec=16 stride=" << p.select.S << " m=" << p.select.M << " n=" << p.select.n;
     if (p.kind == K_TILE) {

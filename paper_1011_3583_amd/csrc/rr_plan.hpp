@@ -146,12 +146,16 @@ constexpr int WEAVE_MAX_SETS = 8;
 struct WeaveArgs {
     uint64_t planes[WEAVE_MAX_SETS];   // interlace: the sets read; de-interlace: the sets written
     uint64_t joined;          // interlace: output; de-interlace: input
+    uint64_t bstride;         // bytes from one batch to the next on both sides (permutes of
+                              // (batch, n, L) <-> (batch, L, n)); 0 for one batch
     uint32_t nvec;            // 16-byte vectors per plane
     uint32_t n;               // planes
     uint32_t unit;            // element bytes
     uint32_t de;              // 1: de-interlace
     uint32_t cached;          // 1: the joined side goes through the caches, 0: streamed
     uint32_t chunks;          // chunks of 64 groups per wave (1 or 2)
+    uint32_t bpb;             // workgroups per batch
+    uint32_t pad_;
 };
 
 enum TileFlags : uint32_t {

@@ -10,7 +10,7 @@
 // read of a never-written LDS byte shows up as a wrong output byte.
 //
 // Input: a manifest, one job per line:
-//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt diag fill infile outfile
+//   permute  ndim d0..d{n-1} p0..p{n-1} esize src_off dst_off in_rb out_rb order max_g ragged xcd umt diag fill weave infile outfile
 //   reorder  ndim d.. base.. range.. m order.. esize src_off dst_off umt max_g infile outfile
 //   gather   src_count count esize indexed start stride src_off dst_off infile idxfile outfile
 //   stencil  rows cols radius shape nweights w... infile outfile             (float grids)
@@ -227,10 +227,12 @@ static void run_select_rm(const SelectArgs& a, uint32_t grid) {
 
 template <int U, int N, bool DE, int R>
 static void run_weave_undr(const WeaveArgs& a, uint32_t grid) {
-    for (uint32_t b = 0; b < grid; ++b) {
+    for (uint32_t g = 0; g < grid; ++g) {
+        const uint32_t batch = g / a.bpb, b = g - batch * a.bpb;
+        const uint64_t off = (uint64_t)batch * a.bstride;
         std::vector<uint8_t> lds((size_t)R * NT * N * 16, 0xA5);
-        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_stage<U, N, DE, false, R>(a, b, lds.data(), tid);
-        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_finish<U, N, DE, false, R>(a, b, lds.data(), tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_stage<U, N, DE, false, R>(a, b, off, lds.data(), tid);
+        for (uint32_t tid = 0; tid < (uint32_t)NT; ++tid) weave_finish<U, N, DE, false, R>(a, b, off, lds.data(), tid);
     }
 }
 
@@ -348,27 +350,31 @@ int main(int argc, char** argv) {
             for (auto& q : perm) is >> q;
             int esize, soff, doff, order; std::string inf, outf;
             is >> esize >> soff >> doff >> opt.in_row_bytes >> opt.out_row_bytes >> order >> opt.max_g >>
-                opt.force_ragged >> opt.xcd >> opt.umt >> opt.diag >> opt.fill >> inf >> outf;
+                opt.force_ragged >> opt.xcd >> opt.umt >> opt.diag >> opt.fill >> opt.weave >> inf >> outf;
             opt.order_out = order;
             Canon c;
             rr_status st = canonicalize(ndim, dims.data(), perm.data(), esize, &c, &why);
             if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); continue; }
             std::vector<uint8_t> in = read_file(inf);
             const size_t nb = (size_t)c.total_bytes;
-            uint8_t* sbuf = new uint8_t[soff + nb + 1];
-            uint8_t* dbuf = new uint8_t[doff + nb + 1];
+            // 16-byte-aligned bases, as GPU allocations are (at least)
+            uint8_t* sbuf = static_cast<uint8_t*>(::operator new[](soff + nb + 1, std::align_val_t{16}));
+            uint8_t* dbuf = static_cast<uint8_t*>(::operator new[](doff + nb + 1, std::align_val_t{16}));
             // exact-size views: the +1 keeps zero-byte buffers valid; nothing may touch it
             if (nb) std::memcpy(sbuf + soff, in.data(), nb);
             std::memset(dbuf, 0x5A, doff + nb + 1);
             st = plan_permute((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff), c, opt, &plan, &why);
-            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); delete[] sbuf; delete[] dbuf; continue; }
-            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); delete[] sbuf; delete[] dbuf; continue; }
+            auto release = [&] {
+                ::operator delete[](sbuf, std::align_val_t{16});
+                ::operator delete[](dbuf, std::align_val_t{16});
+            };
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); release(); continue; }
+            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); release(); continue; }
             if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
             for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
             write_file(outf, dbuf + doff, nb);
             std::printf("ok %s\n", describe(plan).c_str());
-            delete[] sbuf;
-            delete[] dbuf;
+            release();
         } else if (op == "stencil") {
             // stencil rows cols radius shape nweights w... infile outfile  (float grids)
             int64_t rows, cols; int radius, shape, nw; std::string inf, outf;
@@ -450,8 +456,12 @@ int main(int argc, char** argv) {
             std::memset(dbuf, 0x5A, doff + nb + 1);
             if (nb && off + span > ni) { std::printf("err -3 box outside the input\n"); return 3; }
             st = plan_permute((uint64_t)(dbuf + doff), (uint64_t)(sbuf + soff) + off, c, opt, &plan, &why);
-            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); delete[] sbuf; delete[] dbuf; continue; }
-            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); delete[] sbuf; delete[] dbuf; continue; }
+            auto release = [&] {
+                ::operator delete[](sbuf, std::align_val_t{16});
+                ::operator delete[](dbuf, std::align_val_t{16});
+            };
+            if (st != RR_OK) { std::printf("err %d %s\n", (int)st, why.c_str()); release(); continue; }
+            if (!emulate(plan)) { std::printf("err -1 no kernel for plan\n"); release(); continue; }
             if (dbuf[doff + nb] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
             for (int i = 0; i < doff; ++i) if (dbuf[i] != 0x5A) { std::printf("err -2 wrote before the start\n"); return 3; }
             write_file(outf, dbuf + doff, nb);

@@ -40,7 +40,7 @@ def run(jobs):
     """Run jobs through the emulator.  Each job is a dict:
        permute:     op, dims, perm, esize, input (uint8), src_off, dst_off, in_rb, out_rb, order,
                     max_g, ragged, xcd (None: the planner's choice), umt, diag,
-                    fill (None: the planner's choice)
+                    fill (None: the planner's choice), weave
        reorder:     op, dims, base, range, order, esize, input (uint8), src_off, dst_off, umt, max_g
        gather:      op, src_count, esize, input (uint8), idx (int64) or start/stride/count, src_off, dst_off
        interlace:   op, n, count, esize, planes (list of uint8), off, in_rb, out_rb, weave
@@ -62,7 +62,8 @@ def run(jobs):
                                        str(int(j.get("ragged", False))),
                                        str(-1 if j.get("xcd") is None else int(j["xcd"])),
                                        str(int(j.get("umt", 0))), str(int(j.get("diag", False))),
-                                       str(-1 if j.get("fill") is None else int(j["fill"])), inf, outf]))
+                                       str(-1 if j.get("fill") is None else int(j["fill"])),
+                                       str(int(j.get("weave", True))), inf, outf]))
             elif j["op"] == "stencil":
                 np.ascontiguousarray(j["grid"], dtype=np.float32).tofile(inf)
                 w = [repr(float(v)) for v in np.asarray(j["weights"], dtype=np.float32).reshape(-1)]

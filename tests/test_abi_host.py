@@ -139,9 +139,12 @@ def test_plan_uses_widest_vectors_on_aligned_buffers():
 
 def test_interlace_plan_classes():
     """2-8 sets of 1-8-byte elements on 16-byte boundaries, a whole number of 16-byte
-    vectors each, are joined and split in registers (both sides streamed unless the
-    cache override sends the joined side through the caches); any other case keeps
-    the LDS tile, as does the override that switches the register path off."""
+    vectors each, are joined and split in registers -- except an interlace whose tile
+    writes whole 16-byte vectors of merged short rows, an eight-set de-interlace and
+    an interlace of eight sets of 4-8-byte elements, which keep the tile.  The joined side is streamed, but for the stores of an
+    interlace of an odd number of sets, unless the cache override says otherwise.  Any
+    other case keeps the LDS tile, as does the override that switches the register
+    path off."""
     base = 1 << 40   # describe only reads pointer values
 
     def cls(n, count, e, off=0, de=False, key="class"):
@@ -149,23 +152,38 @@ def test_interlace_plan_classes():
         planes = [base + n * pb + (c + 1) * (pb + 4096) + off for c in range(n)]
         return rr.interlace_describe(base + off, planes, count, e, de)[key]
 
+    merged = 0
     for n in range(2, 9):
         for e in (1, 2, 4, 8):
             count = 1000 * 16 // e
-            assert cls(n, count, e) == cls(n, count, e, de=True) == "weave"
-            assert cls(n, count, e, key="cached") == "0"
-            # two 64-group chunks per wave up to three sets and for a four-set
-            # de-interlace, else one (LDS per workgroup)
-            assert cls(n, count, e, key="chunks") == ("2" if n <= 3 else "1")
-            assert cls(n, count, e, de=True, key="chunks") == ("2" if n <= 4 else "1")
+            rr.set_tile_override(weave=False)
+            try:
+                tile_merges = bool(int(cls(n, count, e, key="flags")) & 8)
+            finally:
+                rr.set_tile_override()
+            merged += tile_merges
+            assert cls(n, count, e) == ("tile" if tile_merges or (n == 8 and e >= 4) else "weave"), (n, e)
+            assert cls(n, count, e, de=True) == ("weave" if n <= 7 else "tile"), (n, e)
+            if not tile_merges and not (n == 8 and e >= 4):
+                assert cls(n, count, e, key="cached") == str(n % 2)
+                # two 64-group chunks per wave up to three sets, one from four on
+                assert cls(n, count, e, key="chunks") == ("2" if n <= 3 else "1")
+            if n <= 7:
+                assert cls(n, count, e, de=True, key="cached") == "0"
+                assert cls(n, count, e, de=True, key="chunks") == ("2" if n <= 4 else "1")
             assert cls(n, count, e, off=4) == "tile"             # misaligned
             assert cls(n, count + 1, e) == "tile"                # partial vector
+    assert 0 < merged < 28   # complex64 pairs and RGBA bytes keep the tile's merged stores
+    assert cls(8, 4096, 1) == "weave" and cls(8, 4096, 4) == "tile"
+    assert cls(2, 1 << 20, 4) == cls(4, 1 << 20, 1) == "tile"
     assert cls(9, 4096, 4) == cls(2, 4096, 3) == cls(2, 4096, 16) == "tile"
     assert cls(1, 4096, 4) == "copy"
     assert cls(3, 0, 4) == "empty"
     rr.set_tile_override(cache=3)
     try:
-        assert cls(3, 4096, 4, key="cached") == cls(3, 4096, 4, de=True, key="cached") == "1"
+        assert cls(4, 4096, 4, key="cached") == cls(3, 4096, 4, de=True, key="cached") == "1"
+        rr.set_tile_override(cache=0)
+        assert cls(3, 4096, 4, key="cached") == "0"
         rr.set_tile_override(cache=2)   # writes cached: the interlace's joined side only
         assert cls(3, 4096, 4, key="cached") == "1" and cls(3, 4096, 4, de=True, key="cached") == "0"
         rr.set_tile_override(weave=False)

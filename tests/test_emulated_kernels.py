@@ -403,9 +403,9 @@ def test_emu_flat_read_and_merged_store_paths():
     assert any(f & 4 for f in flags[1::2]), "no de-interlace plan took the flat read"
     assert any(f & 8 for f in flags[0::2]), "no interlace plan took the merged store"
     # permutes whose input tile is one contiguous range of short rows
-    jobs = [_perm_job((4096, 3), (1, 0), 4, 9500), _perm_job((64, 48, 6), (2, 0, 1), 2, 9501),
-            _perm_job((2048, 5, 2), (1, 2, 0), 8, 9502)]
-    _check(jobs)
+    jobs = [_perm_job((4096, 3), (1, 0), 4, 9500, weave=False), _perm_job((64, 48, 6), (2, 0, 1), 2, 9501, weave=False),
+            _perm_job((2048, 5, 2), (1, 2, 0), 8, 9502, weave=False)]
+    assert all(int(s.split("flags=")[1].split()[0]) & 4 for s, _ in _check(jobs)[:2])
 
 
 # Micro-tile edge the planner keeps for interlace-shaped problems (n short output
@@ -425,7 +425,7 @@ def test_emu_short_output_rows_line_fill():
     count = 4104
     jobs, keys = [], []
     for (e, n), g in SHORT_ROW_G.items():
-        jobs.append(_perm_job((n, count), (1, 0), e, 9600 + 17 * n + e))
+        jobs.append(_perm_job((n, count), (1, 0), e, 9600 + 17 * n + e, weave=False))
         planes = [rr_synth.random_bytes(9700 + 17 * n + e + 1000 * c, count * e) for c in range(n)]
         jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, weave=False))
         keys += [(e, n, g)] * 2
@@ -440,23 +440,61 @@ def test_emu_short_output_rows_line_fill():
 @pytest.mark.parametrize("e", [1, 2, 4, 8])
 def test_emu_register_interlace(e):
     """Interlace and de-interlace of 2-8 sets on 16-byte boundaries with a whole number
-    of 16-byte vectors per set take the register path (several workgroups plus a
-    partial one) and match the oracle; a misaligned set, a partial vector or the
-    override keep the LDS tile, also bit-exact."""
+    of 16-byte vectors per set take the register path where the planner picks it
+    (several workgroups plus a partial one) and match the oracle; a misaligned set,
+    a partial vector or the override keep the LDS tile, also bit-exact.  Every case
+    is planned as the library plans it for aligned pointers."""
+    import paper_1011_3583_amd as rr
+    base = 1 << 40
+
+    def planned(n, count, de, off):
+        pb = count * e
+        planes = [base + off + n * pb + (c + 1) * (pb + 4096) for c in range(n)]
+        return rr.interlace_describe(base + off, planes, count, e, de)["class"]
+
     jobs, want = [], []
     for n in range(2, 9):
-        for off, count, weave, kind in [(0, 773 * 16 // e, True, "weave"), (16, 64 * 16 // e + 16 // e, True, "weave"),
-                                        (0, 773 * 16 // e, False, "tile"), (4, 300 * 16 // e, True, "tile"),
-                                        (0, 300 * 16 // e + 1, True, "tile")]:
+        for off, count, weave in [(0, 773 * 16 // e, True), (16, 64 * 16 // e + 16 // e, True),
+                                  (0, 773 * 16 // e, False), (4, 300 * 16 // e, True), (0, 300 * 16 // e + 1, True)]:
             seed = 11000 + 100 * n + 10 * e + off + count % 7 + int(weave)
             planes = [rr_synth.random_bytes(seed + c, count * e) for c in range(n)]
             jobs.append(dict(op="interlace", n=n, count=count, esize=e, planes=planes, off=off, weave=weave))
             jobs.append(dict(op="deinterlace", n=n, count=count, esize=e, off=off, weave=weave,
                              input=rr_synth.random_bytes(seed + 50, n * count * e)))
-            want += [kind, kind]
+            want += [planned(n, count, de, off) if weave else "tile" for de in (False, True)]
+    assert want.count("weave") >= 20, want.count("weave")
     res = _check(jobs)
     for j, k, (status, _) in zip(jobs, want, res):
         assert f"class={k}" in status, (j["op"], j["n"], j["count"], j["off"], status)
+
+
+# Permutes that swap the two fastest axes where one has 2-8 entries, with or
+# without a batch axis in front: (dims, perm, element bytes, class).  Whole
+# 16-byte vectors per set take the register interlace; a partial vector, nine
+# sets or batched sets under 4 KiB keep the tile.
+WEAVE_PERMUTES = [((3, 4096), (1, 0), 4, "weave"), ((4096, 3), (1, 0), 4, "weave"),
+                  ((2, 24576), (1, 0), 8, "weave"), ((24576, 2), (1, 0), 8, "weave"),
+                  ((8, 6208), (1, 0), 1, "weave"), ((6208, 5), (1, 0), 2, "weave"),
+                  ((5, 3, 12352), (0, 2, 1), 2, "weave"), ((4, 3072, 7), (0, 2, 1), 4, "weave"),
+                  ((3, 4, 2056), (0, 2, 1), 8, "weave"), ((2, 8208, 6), (0, 2, 1), 1, "weave"),
+                  ((3, 4097), (1, 0), 4, "tile"), ((9, 4096), (1, 0), 4, "tile"),
+                  ((1000, 3, 64), (0, 2, 1), 4, "tile")]
+
+
+def test_emu_register_interlace_permutes():
+    """Small-axis transposes (interlace / de-interlace shaped, batched or not) run the
+    register interlace where it applies and match the oracle; at a 4-byte offset
+    they take the tile, also bit-exact."""
+    jobs, want = [], []
+    for i, (dims, perm, e, kind) in enumerate(WEAVE_PERMUTES):
+        jobs.append(_perm_job(dims, perm, e, 12600 + i))
+        jobs.append(_perm_job(dims, perm, e, 12700 + i, src_off=4, dst_off=4))
+        want += [kind, "tile"]
+    res = _check(jobs)
+    for j, k, (status, _) in zip(jobs, want, res):
+        assert f"class={k}" in status, (j["dims"], j.get("src_off"), status)
+    batches = [int(st.split("batches=")[1].split()[0]) for (st, _), k in zip(res, want) if k == "weave"]
+    assert max(batches) == 5 and min(batches) == 1, batches
 
 
 def test_emu_flat_read_byte_tail():
