@@ -1036,10 +1036,15 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
     for (uint32_t base = 0; base < total; base += NT * B) {
         uint32_t w[B][NWI];
         uint32_t lo[B];
+        uint64_t src[B];
         bool ok[B];
         // Every lane loads (a lane past the tile's valid extent re-reads the tile's
         // first vector, which exists whenever the tile does): loads behind per-lane
-        // branches are issued one at a time, each waited for before the next.
+        // branches are issued one at a time, each waited for before the next.  All
+        // addresses are formed before the first load: address arithmetic between
+        // the loads made the compiler wait for each load before the next (a
+        // register it rewrote could still be the target of the previous round's
+        // load), leaving one load in flight per lane.
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const uint32_t f = base + u * NT + tid;
@@ -1047,9 +1052,13 @@ RR_HD void read_phase(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_
             uint32_t x = (f - ib * a.rch) * WIN;
             ok[u] = f < total && ib < t.TBv && x < rowvalid;
             if (!ok[u]) { ib = 0; x = 0; }
-            gload<WIN, S>(reinterpret_cast<const uint8_t*>(t.bin + row_in(a, ib) + x), w[u]);
+            src[u] = t.bin + row_in(a, ib) + x;
             lo[u] = lds_pos<RG>(a, ib, x);
         }
+        sched_fence();
+#pragma unroll
+        for (int u = 0; u < B; ++u) gload<WIN, S>(reinterpret_cast<const uint8_t*>(src[u]), w[u]);
+        sched_fence();
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (ok[u]) sstore<WIN>(lds + lo[u], w[u]);
@@ -1066,12 +1075,15 @@ RR_HD void read_flat(const TileArgs& a, const TileCtx& t, uint8_t* lds, uint32_t
     for (uint32_t base = 0; base < nvec; base += NT * B) {
         uint32_t w[B][4];
         bool ok[B];
+        // every lane loads (past the end: the range's first vector), so the B
+        // loads issue back to back instead of each behind its own branch
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             const uint32_t v = base + u * NT + tid;
             ok[u] = v < nvec;
-            if (ok[u]) gload<16, S>(reinterpret_cast<const uint8_t*>(t.bin) + (uint64_t)v * 16, w[u]);
+            gload<16, S>(reinterpret_cast<const uint8_t*>(t.bin) + (uint64_t)(ok[u] ? v : 0u) * 16, w[u]);
         }
+        sched_fence();
 #pragma unroll
         for (int u = 0; u < B; ++u)
             if (ok[u]) sstore<16>(lds + (base + u * NT + tid) * 16, w[u]);
@@ -1114,43 +1126,39 @@ RR_HD void read_rows(uint32_t nrows, uint32_t rowbytes, SrcRow src_row, LdsAt ld
     const uint32_t per = nfull + ((rowbytes & 15u) / U);
     if (per == 0 || nrows == 0) return;
     RowWalk w(tid, per);
+    using Elem = uint32_t[NWords<U>::value];
     while (w.row < nrows) {
         uint32_t v[B][4];
         uint32_t lo[B];
+        uint64_t src[B];
         uint8_t kind[B];   // 0: none, 1: 16-byte vector, 2: one U-byte element
+        // addresses first, then the loads back to back (an element lands in the
+        // first words of its vector's registers, so no copy waits for it)
 #pragma unroll
         for (int u = 0; u < B; ++u) {
             kind[u] = 0;
             lo[u] = 0;
+            src[u] = 0;
             if (w.row < nrows) {
                 const uint64_t rowp = src_row(w.row);
-                if (w.col < nfull) {
-                    const uint32_t x = w.col << 4;
-                    gload16u<S>(reinterpret_cast<const uint8_t*>(rowp + x), v[u]);
-                    lo[u] = lds_at(w.row, x);
-                    kind[u] = 1;
-                } else {
-                    const uint32_t x = (nfull << 4) + (w.col - nfull) * U;
-                    uint32_t e[NWords<U>::value];
-                    gload<U, S>(reinterpret_cast<const uint8_t*>(rowp + x), e);
-#pragma unroll
-                    for (int q = 0; q < NWords<U>::value; ++q) v[u][q] = e[q];
-                    lo[u] = lds_at(w.row, x);
-                    kind[u] = 2;
-                }
+                const uint32_t x = w.col < nfull ? w.col << 4 : (nfull << 4) + (w.col - nfull) * U;
+                src[u] = rowp + x;
+                lo[u] = lds_at(w.row, x);
+                kind[u] = w.col < nfull ? 1 : 2;
                 w.step();
             }
         }
+        sched_fence();
 #pragma unroll
         for (int u = 0; u < B; ++u) {
-            if (kind[u] == 1) {
-                sstore<16>(lds + lo[u], v[u]);
-            } else if (kind[u] == 2) {
-                uint32_t e[NWords<U>::value];
+            if (kind[u] == 1) gload16u<S>(reinterpret_cast<const uint8_t*>(src[u]), v[u]);
+            else if (kind[u] == 2) gload<U, S>(reinterpret_cast<const uint8_t*>(src[u]), *reinterpret_cast<Elem*>(&v[u][0]));
+        }
+        sched_fence();
 #pragma unroll
-                for (int q = 0; q < NWords<U>::value; ++q) e[q] = v[u][q];
-                sstore<U>(lds + lo[u], e);
-            }
+        for (int u = 0; u < B; ++u) {
+            if (kind[u] == 1) sstore<16>(lds + lo[u], v[u]);
+            else if (kind[u] == 2) sstore<U>(lds + lo[u], *reinterpret_cast<const Elem*>(&v[u][0]));
         }
     }
 }
