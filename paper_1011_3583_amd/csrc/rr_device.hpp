@@ -861,11 +861,20 @@ RR_HD void select_stage(const SelectArgs& a, uint32_t block, uint8_t* lds, uint3
     const uint64_t end = a.src_end;
     uint32_t w[M][4];
     bool full[M];
+    // Every lane loads when the run holds a 16-byte vector at all (a vector past
+    // the end re-reads the run's last whole one, discarded): loads behind
+    // per-lane branches left one load in flight at a time.
+    if (end >= reinterpret_cast<uint64_t>(a.src) + 16u) {
 #pragma unroll
-    for (int u = 0; u < M; ++u) {
-        const uint8_t* p = base + 16u * (u * NT + tid);
-        full[u] = reinterpret_cast<uint64_t>(p) + 16u <= end;
-        if (full[u]) gload16u<true>(p, w[u]);
+        for (int u = 0; u < M; ++u) {
+            const uint8_t* p = base + 16u * (u * NT + tid);
+            full[u] = reinterpret_cast<uint64_t>(p) + 16u <= end;
+            gload16u<true>(full[u] ? p : reinterpret_cast<const uint8_t*>(end - 16u), w[u]);
+        }
+        sched_fence();
+    } else {
+#pragma unroll
+        for (int u = 0; u < M; ++u) full[u] = false;
     }
 #pragma unroll
     for (int u = 0; u < M; ++u) {
