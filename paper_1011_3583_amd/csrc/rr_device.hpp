@@ -1467,55 +1467,86 @@ RR_HD void write_tile(const TileArgs& a, const TileCtx& t, const uint8_t* lds, u
             return;
         }
     }
+    // Work items are taken WB per round: every item's LDS rows and store
+    // addresses first, then all the round's stores back to back.  Computing an
+    // address between stores made the compiler wait for every outstanding store
+    // (the plane-table branch of the address can load, and the wait it needs
+    // stayed in the shared path), so a thread's stores went out one at a time.
     if (G > 1 || a.k == 1) {
-        for (uint32_t gi = tid; gi < a.nwork; gi += NT) {
-            const uint32_t ma = mdiv(gi, a.mnmb);
-            const uint32_t mb = gi - ma * a.nmb;
-            const uint32_t ia0 = ma * G, ib0 = mb * G;
-            if (ia0 < t.TAv && ib0 < t.TBv) {
+        constexpr int WB = G == 1 ? 4 : G == 2 ? 2 : 1;
+        constexpr bool CAN_MERGE = W >= 4 && W * G >= 16;
+        constexpr int NV = CAN_MERGE ? W * G / 16 : 1;   // 16-byte vectors of a merged micro-tile
+        constexpr int PER = W >= 4 ? W / 4 : 1;
+        const bool table = (a.flags & TF_OUT_TABLE) != 0;
+        const bool merge = CAN_MERGE && !table && (a.flags & TF_OUT_MERGE);
+        for (uint32_t g0 = tid; g0 < a.nwork; g0 += NT * WB) {
+            uint32_t o[WB][G][NW];
+            uint64_t dst[WB][G];
+            bool ok[WB];
+#pragma unroll
+            for (int w = 0; w < WB; ++w) {
+                const uint32_t gi = g0 + (uint32_t)w * NT;
+                const uint32_t ma = mdiv(gi, a.mnmb);
+                const uint32_t mb = gi - ma * a.nmb;
+                const uint32_t ia0 = ma * G, ib0 = mb * G;
+                ok[w] = gi < a.nwork && ia0 < t.TAv && ib0 < t.TBv;
+                if (!ok[w]) continue;
                 uint32_t r[G][NW];
 #pragma unroll
                 for (int j = 0; j < G; ++j) sload<W>(lds + lds_pos<rot_group<U, G>()>(a, ib0 + j, ia0 * U), r[j]);
-                uint32_t o[G][NW];
-                xpose<U, G>(r, o);
-                if (a.flags & TF_OUT_TABLE) {
+                xpose<U, G>(r, o[w]);
+                if (table) {
 #pragma unroll
-                    for (int i = 0; i < G; ++i)
-                        gstore<W, S>(reinterpret_cast<uint8_t*>(a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U), o[i]);
-                } else if (W >= 4 && W * G >= 16 && (a.flags & TF_OUT_MERGE)) {
+                    for (int i = 0; i < G; ++i) dst[w][i] = a.table[ia0 + i] + t.bout + (uint64_t)ib0 * U;
+                } else {
+                    const uint64_t q = t.bout + row_out(a, ia0) + (merge ? 0 : (uint64_t)ib0 * U);
+#pragma unroll
+                    for (int i = 0; i < G; ++i) dst[w][i] = merge ? q + (uint64_t)i * 16u : q + (uint64_t)i * a.soutA[0];
+                }
+            }
+            sched_fence();
+#pragma unroll
+            for (int w = 0; w < WB; ++w) {
+                if (!ok[w]) continue;
+                if (merge) {
                     // the G output rows are back to back: store them as 16-byte vectors
-                    constexpr int NV = (W * G >= 16) ? W * G / 16 : 1;
-                    constexpr int PER = W >= 4 ? W / 4 : 1;
-                    uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0));
                     uint32_t flat[NV * 4];
 #pragma unroll
                     for (int i = 0; i < G; ++i)
 #pragma unroll
                         for (int c = 0; c < PER; ++c)
-                            if (i * PER + c < NV * 4) flat[i * PER + c] = o[i][c];
+                            if (i * PER + c < NV * 4) flat[i * PER + c] = o[w][i][c];
 #pragma unroll
-                    for (int v = 0; v < NV; ++v) {
-                        const uint32_t(&fv)[4] = *reinterpret_cast<const uint32_t(*)[4]>(&flat[v * 4]);
-                        gstore<16, S>(q + v * 16, fv);
-                    }
+                    for (int v = 0; v < NV; ++v)
+                        gstore<16, S>(reinterpret_cast<uint8_t*>(dst[w][v]), *reinterpret_cast<const uint32_t(*)[4]>(&flat[v * 4]));
                 } else {
-                    uint8_t* q = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia0) + (uint64_t)ib0 * U);
 #pragma unroll
-                    for (int i = 0; i < G; ++i) gstore<W, S>(q + (uint64_t)i * a.soutA[0], o[i]);
+                    for (int i = 0; i < G; ++i) gstore<W, S>(reinterpret_cast<uint8_t*>(dst[w][i]), o[w][i]);
                 }
             }
         }
     } else {
-        for (uint32_t gi = tid; gi < a.nwork; gi += NT) {
-            const uint32_t ia = mdiv(gi, a.mnmb);
-            const uint32_t m = gi - ia * a.nmb;
-            const uint32_t ib = mdiv(m, a.mk);
-            const uint32_t s = m - ib * a.k;
-            if (ia < t.TAv && ib < t.TBv) {
-                uint32_t v[NWords<U>::value];
-                sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, ib, (ia * a.k + s) * U), v);
-                gstore<U, S>(reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia) + (uint64_t)m * U), v);
+        constexpr int WB = U == 16 ? 1 : 4;
+        for (uint32_t g0 = tid; g0 < a.nwork; g0 += NT * WB) {
+            uint32_t v[WB][NWords<U>::value];
+            uint64_t dst[WB];
+            bool ok[WB];
+#pragma unroll
+            for (int w = 0; w < WB; ++w) {
+                const uint32_t gi = g0 + (uint32_t)w * NT;
+                const uint32_t ia = mdiv(gi, a.mnmb);
+                const uint32_t m = gi - ia * a.nmb;
+                const uint32_t ib = mdiv(m, a.mk);
+                const uint32_t s = m - ib * a.k;
+                ok[w] = gi < a.nwork && ia < t.TAv && ib < t.TBv;
+                if (!ok[w]) continue;
+                sload<U>(lds + lds_pos<rot_group<U, 1>()>(a, ib, (ia * a.k + s) * U), v[w]);
+                dst[w] = t.bout + row_out(a, ia) + (uint64_t)m * U;
             }
+            sched_fence();
+#pragma unroll
+            for (int w = 0; w < WB; ++w)
+                if (ok[w]) gstore<U, S>(reinterpret_cast<uint8_t*>(dst[w]), v[w]);
         }
     }
 }
