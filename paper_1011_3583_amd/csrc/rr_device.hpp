@@ -1250,44 +1250,66 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
         const uint32_t ib = mdiv(q, a.mk);
         return lds_pos<RG>(a, ib, (ia * k + (q - ib * k)) * U);
     };
-    for (RowWalk w(tid, per); w.row < t.TAv; w.step()) {
-        const uint32_t ia = w.row;
-        uint8_t* rowp = reinterpret_cast<uint8_t*>(t.bout + row_out(a, ia));
-        if (w.col < nfull) {
-            const uint32_t q0 = w.col * EPV;
-            // element j of the vector: rows q0 + j (single-unit elements, one
-            // rotation group: one address, then a pitch per row) or unit q0 + j
-            const uint32_t base0 = k == 1 ? lds_pos<RG>(a, q0, ia * U) : 0u;
-            auto at = [&](uint32_t j) { return k == 1 ? base0 + j * a.pitch : unit_at(ia, q0 + j); };
-            uint32_t o[4];
-            if constexpr (U >= 4) {
+    // Items go B per round: each item's row address and LDS gather first, then
+    // the round's stores back to back (an address formed between stores made
+    // the compiler wait for every outstanding store).
+    constexpr int B = READ_BATCH;
+    using Elem = uint32_t[NWords<U>::value];
+    RowWalk w(tid, per);
+    while (w.row < t.TAv) {
+        uint32_t o[B][4];
+        uint64_t dst[B];
+        uint8_t kind[B];   // 0: none, 1: 16-byte vector, 2: one U-byte unit
 #pragma unroll
-                for (int j = 0; j < EPV; ++j) {
-                    uint32_t e[NWords<U>::value];
-                    sload<U>(lds + at(j), e);
+        for (int u = 0; u < B; ++u) {
+            kind[u] = 0;
+            dst[u] = 0;
+            if (w.row >= t.TAv) continue;
+            const uint32_t ia = w.row;
+            const uint64_t rowp = t.bout + row_out(a, ia);
+            if (w.col < nfull) {
+                const uint32_t q0 = w.col * EPV;
+                // element j of the vector: rows q0 + j (single-unit elements, one
+                // rotation group: one address, then a pitch per row) or unit q0 + j
+                const uint32_t base0 = k == 1 ? lds_pos<RG>(a, q0, ia * U) : 0u;
+                auto at = [&](uint32_t j) { return k == 1 ? base0 + j * a.pitch : unit_at(ia, q0 + j); };
+                if constexpr (U >= 4) {
 #pragma unroll
-                    for (int q = 0; q < U / 4; ++q) o[j * (U / 4) + q] = e[q];
-                }
-            } else {
-                constexpr int PER_WORD = 4 / U;
+                    for (int j = 0; j < EPV; ++j) {
+                        uint32_t e[NWords<U>::value];
+                        sload<U>(lds + at(j), e);
 #pragma unroll
-                for (int q = 0; q < 4; ++q) {
-                    uint32_t acc = 0;
-#pragma unroll
-                    for (int b = 0; b < PER_WORD; ++b) {
-                        uint32_t e[1];
-                        sload<U>(lds + at(q * PER_WORD + b), e);
-                        acc |= e[0] << (8 * U * b);
+                        for (int q = 0; q < U / 4; ++q) o[u][j * (U / 4) + q] = e[q];
                     }
-                    o[q] = acc;
+                } else {
+                    constexpr int PER_WORD = 4 / U;
+#pragma unroll
+                    for (int q = 0; q < 4; ++q) {
+                        uint32_t acc = 0;
+#pragma unroll
+                        for (int b = 0; b < PER_WORD; ++b) {
+                            uint32_t e[1];
+                            sload<U>(lds + at(q * PER_WORD + b), e);
+                            acc |= e[0] << (8 * U * b);
+                        }
+                        o[u][q] = acc;
+                    }
                 }
+                dst[u] = rowp + (w.col << 4);
+                kind[u] = 1;
+            } else {
+                const uint32_t q = nfull * EPV + (w.col - nfull);
+                sload<U>(lds + unit_at(ia, q), *reinterpret_cast<Elem*>(&o[u][0]));
+                dst[u] = rowp + (uint64_t)q * U;
+                kind[u] = 2;
             }
-            gstore16u<S>(rowp + (w.col << 4), o);
-        } else {
-            const uint32_t q = nfull * EPV + (w.col - nfull);
-            uint32_t e[NWords<U>::value];
-            sload<U>(lds + unit_at(ia, q), e);
-            gstore<U, S>(rowp + (uint64_t)q * U, e);
+            w.step();
+        }
+        sched_fence();
+#pragma unroll
+        for (int u = 0; u < B; ++u) {
+            if (kind[u] == 1) gstore16u<S>(reinterpret_cast<uint8_t*>(dst[u]), o[u]);
+            else if (kind[u] == 2) gstore<U, S>(reinterpret_cast<uint8_t*>(dst[u]), *reinterpret_cast<const Elem*>(&o[u][0]));
         }
     }
 }
