@@ -1253,7 +1253,7 @@ RR_HD void write_ragged(const TileArgs& a, const TileCtx& t, const uint8_t* lds,
     // Items go B per round: each item's row address and LDS gather first, then
     // the round's stores back to back (an address formed between stores made
     // the compiler wait for every outstanding store).
-    constexpr int B = READ_BATCH;
+    constexpr int B = U == 2 ? 2 : READ_BATCH;
     using Elem = uint32_t[NWords<U>::value];
     RowWalk w(tid, per);
     while (w.row < t.TAv) {
