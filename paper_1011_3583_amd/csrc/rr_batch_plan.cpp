@@ -52,9 +52,7 @@ rr_status plan_job(const rr_job& j, const TileOptions& opt, Plan* p, std::string
     Canon c;
     rr_status st = validate_job(j, &c, why);
     if (st != RR_OK) return st;
-    TileOptions o = opt;
-    o.weave = 0;   // the batched kernels run copies, runs and tiles
-    return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, o, p, why);
+    return plan_permute((uint64_t)j.dst, (uint64_t)j.src, c, batch_job_options(opt, c.total_bytes), p, why);
 }
 
 // Host threads that plan (or validate) a batch of njobs: one below 256 jobs

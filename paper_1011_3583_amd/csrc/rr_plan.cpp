@@ -48,6 +48,18 @@ bool override_active(const TileOptions& o) {
            o.fill != -1 || o.weave != 1;
 }
 
+TileOptions batch_job_options(const TileOptions& opt, int64_t bytes_per_side) {
+    TileOptions o = opt;
+    o.weave = 0;
+    if (!override_active(opt) && bytes_per_side <= BATCH_SMALL_JOB_BYTES) {
+        o.in_row_bytes = 512;
+        o.out_row_bytes = 256;
+        o.order_out = 1;
+        o.cache = 3;
+    }
+    return o;
+}
+
 TileOptions current_tile_options() {
     std::lock_guard<std::mutex> lk(g_override_mu);
     TileOptions o = g_override;

@@ -258,6 +258,16 @@ TileOptions current_tile_options();
 void set_tile_override(const TileOptions& o);
 bool override_active(const TileOptions& o);
 
+// Options for a job planned into a batch group (batched calls and handles, the
+// serving loop).  The register interlace is off: the batch kernels run copies,
+// runs and tiles.  Unless opt is an override (or a tuner candidate), a job of at
+// most BATCH_SMALL_JOB_BYTES per side gets 512-byte input and 256-byte output
+// row targets, output-order tile traversal and cached tile accesses.  That is
+// the shape the batch tuner picks for many small odd-shaped jobs, whose
+// neighbours in a group share lines and run from L2.
+constexpr int64_t BATCH_SMALL_JOB_BYTES = 128ll << 20;
+TileOptions batch_job_options(const TileOptions& opt, int64_t bytes_per_side);
+
 // Tuning cache: device architecture and HIP runtime version (the context, one per
 // process) + canonical problem + alignment class -> tile options.  Keys read
 //   <arch>@hip<version>|r<rank>:e<bytes>:a<src align>/<dst align>:d<dims>:p<perm>[:s<strides>]

@@ -740,9 +740,8 @@ rr_status rr_serve_submit(rr_server* s, const rr_job* job, uint64_t* ticket) {
     j->out_bytes = nb;
     if (nb > 0) {
         const uint64_t dst = own ? PLACEHOLDER_DST : (uint64_t)job->dst;
-        TileOptions opt = current_tile_options();
-        opt.weave = 0;   // jobs run in batch groups (copies, runs and tiles)
-        st = plan_permute(dst, (uint64_t)job->src, c, opt, &j->plan, &why);
+        st = plan_permute(dst, (uint64_t)job->src, c, batch_job_options(current_tile_options(), c.total_bytes),
+                          &j->plan, &why);
         if (st != RR_OK) return fail(st, why);
         if (!(s->cfg.flags & RR_SERVE_DIRECT) && s->cfg.chunk_bytes > 0 && j->plan.grid > 1 &&
             j->plan.bytes > s->cfg.chunk_bytes) {

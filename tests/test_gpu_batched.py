@@ -229,3 +229,33 @@ def test_large_one_shot_batch_in_chunks(rr):
     assert st == rr.STATUS_CODE["RR_ERR_INVALID_ARG"], st
     assert f"job {len(specs) - 1}" in rr.last_error()
     assert bool((J.dst == 0x77).all())
+
+
+def test_small_jobs_take_the_batch_shape(rr):
+    """With no tile override, jobs of at most 128 MiB per side planned into a batch
+    take 512-byte input and 256-byte output row targets, output-order traversal and
+    cached tile accesses: the batch's workgroups add up to the jobs' single-permute
+    grids under that override (and not to their built-in grids), and every output
+    equals the oracle."""
+    rr.tune_clear()
+    specs = rr_synth.sample_jobs(779, njobs=96, total_range=(1e3, 3e5))
+    J = Jobs(rr, specs, 41)
+    _say("small-job batch shape", len(specs))
+    b = rr.Batch(J.arr, 0)
+    total = sum(g["workgroups"] for g in b.groups())
+
+    def grids(**kw):
+        rr.set_tile_override(weave=False, **kw)
+        try:
+            return sum(int(rr.plan_describe(s["dims"], s["perm"], s["esize"], j.dst, j.src)["grid"])
+                       for s, j in zip(specs, J.arr))
+        finally:
+            rr.set_tile_override(0, 0, None)
+
+    small = grids(in_row_bytes=512, out_row_bytes=256, order_out=True, cache=3)
+    builtin = grids()
+    assert total == small, (total, small, builtin)
+    assert small != builtin
+    b.launch(torch.cuda.current_stream())
+    torch.cuda.synchronize()
+    _check_all_vs_oracle(J)
