@@ -442,7 +442,10 @@ rr_status rr_interlace_describe(const void* flat, const void* const* planes, int
  * 16-byte boundary and every set a whole number of 16-byte vectors, are joined or
  * split in registers, one 16-byte vector of each set per thread; the cache bits
  * then say whether the joined side goes through the caches, streamed by
- * default). */
+ * default).  RR_TILE_DIAG / RR_TILE_NO_DIAG switch the diagonal tile order on or
+ * off everywhere; with neither the planner uses it for 2-D transposes of 1-8-byte
+ * elements whose rows are a power of two of at least 4 KiB on both sides
+ * (RR_ERR_INVALID_ARG for both flags). */
 #define RR_TILE_ORDER_OUT 1
 #define RR_TILE_ORDER_IN 2
 #define RR_TILE_FORCE_RAGGED 4  /* use the odd-shape (ragged) tile path everywhere (testing) */
@@ -451,6 +454,7 @@ rr_status rr_interlace_describe(const void* flat, const void* const* planes, int
 #define RR_TILE_UMT_ALWAYS 32   /* unaligned micro-tiles even where aligned ones fit (testing) */
 #define RR_TILE_NO_XCD 64       /* never hand XCDs contiguous tile ranges */
 #define RR_TILE_DIAG 128        /* diagonal tile order: consecutive tiles step along both tile-grid axes */
+#define RR_TILE_NO_DIAG (1 << 30) /* never the diagonal order (neither diag flag: the built-in choice) */
 #define RR_TILE_FILL (1 << 27)  /* odd extents: refit tile extents for the fewest tiles within the tile size */
 #define RR_TILE_NO_FILL (1 << 28) /* keep the row-target tile extents on odd extents */
 #define RR_TILE_NO_WEAVE (1 << 29) /* interlace through the LDS tile only */

@@ -334,7 +334,7 @@ def reorder_describe(dims, base, range_, order, elem_size: int, dst: int = 0, sr
 
 def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=None,
                       force_ragged: bool = False, max_g: int = 0, tile_kib: int = 0, xcd=None,
-                      umt: int = 0, cache=None, diag: bool = False, fill=None, weave: bool = True):
+                      umt: int = 0, cache=None, diag=None, fill=None, weave: bool = True):
     """order_out: True = output order, False = input order, None = built-in choice.
     force_ragged: plan the odd-shape tile path even where aligned micro-tiles fit.
     max_g: cap on the register micro-tile edge (0 = none, else 1, 2, 4, 8, 16).
@@ -344,7 +344,8 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     umt: unaligned micro-tiles, 1 on odd shapes (instead of G = 1 rows), 2 everywhere.
     cache: global accesses of tiles, 0 non-temporal, 1 loads cached, 2 stores cached,
     3 both; None = the planner's choice by 128-byte line alignment.
-    diag: diagonal tile order.  fill: True / False switch the odd-extent refit (fewer,
+    diag: diagonal tile order, True / False on / off, None = built-in (on for 2-D
+    transposes at power-of-two row pitches of 4 KiB or more, 1-8-byte elements).  fill: True / False switch the odd-extent refit (fewer,
     fuller tiles where a tile does not divide an outer axis) on / off, None = built-in.
     weave: False sends every interlace and de-interlace through the LDS tile instead of
     the register path for aligned sets of 1-8-byte elements."""
@@ -355,7 +356,7 @@ def set_tile_override(in_row_bytes: int = 0, out_row_bytes: int = 0, order_out=N
     flags |= 0 if xcd is None else (8 if xcd else 64)
     flags |= {0: 0, 1: 16, 2: 32}[int(umt)]
     flags |= 0 if cache is None else (int(cache) + 1) << 24
-    flags |= 128 if diag else 0
+    flags |= 0 if diag is None else (128 if diag else (1 << 30))
     flags |= 0 if fill is None else ((1 << 27) if fill else (1 << 28))
     flags |= 0 if weave else (1 << 29)
     check(lib().rr_set_tile_override(int(in_row_bytes), int(out_row_bytes), flags))

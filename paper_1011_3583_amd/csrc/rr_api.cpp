@@ -342,14 +342,16 @@ rr_status rr_set_tile_override(int in_row_bytes, int out_row_bytes, int flags) {
         return fail(RR_ERR_INVALID_ARG, "RR_TILE_XCD and RR_TILE_NO_XCD together");
     if ((flags & RR_TILE_FILL) && (flags & RR_TILE_NO_FILL))
         return fail(RR_ERR_INVALID_ARG, "RR_TILE_FILL and RR_TILE_NO_FILL together");
-    const int cache = ((flags >> 24) & 0x7) - 1;   // bits 24..26; 27, 28: fill flags; 29: weave
+    if ((flags & RR_TILE_DIAG) && (flags & RR_TILE_NO_DIAG))
+        return fail(RR_ERR_INVALID_ARG, "RR_TILE_DIAG and RR_TILE_NO_DIAG together");
+    const int cache = ((flags >> 24) & 0x7) - 1;   // bits 24..26; 27, 28: fill flags; 29: weave; 30: no diag
     if (cache > 3) return fail(RR_ERR_INVALID_ARG, "cache policy must be 0..3");
     TileOptions o;
     o.max_g = max_g;
     o.tile_kib = tile_kib;
     o.xcd = (flags & RR_TILE_XCD) ? 1 : (flags & RR_TILE_NO_XCD) ? 0 : -1;
     o.cache = cache;
-    o.diag = (flags & RR_TILE_DIAG) ? 1 : 0;
+    o.diag = (flags & RR_TILE_DIAG) ? 1 : (flags & RR_TILE_NO_DIAG) ? 0 : -1;
     o.fill = (flags & RR_TILE_FILL) ? 1 : (flags & RR_TILE_NO_FILL) ? 0 : -1;
     o.weave = (flags & RR_TILE_NO_WEAVE) ? 0 : 1;
     o.umt = (flags & RR_TILE_UMT_ALWAYS) ? 2 : (flags & RR_TILE_UMT) ? 1 : 0;
@@ -375,9 +377,12 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
     // unaligned micro-tiles, cache policy, diagonal order, odd-extent refit (the
     // first candidate is the built-in plan); candidates that plan to the same launch
     // as an earlier one are skipped
+    // (diag: the first candidate takes the built-in choice; the others the plain
+    // order unless they say otherwise, so the search covers both orders where the
+    // built-in choice is diagonal)
     struct Cand { int in_rb, out_rb, order, max_g, kib, xcd = -1, umt = 0, cache = -1, diag = 0, fill = -1; };
     static const Cand cands[] = {
-        {0, 0, -1, 0, 0},      {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
+        {0, 0, -1, 0, 0, -1, 0, -1, -1}, {0, 0, 1, 0, 0},        {0, 0, 0, 0, 0},        {0, 0, -1, 0, 64},
         {0, 0, 1, 0, 32},      {128, 256, -1, 0, 64},  {256, 128, -1, 0, 64},  {256, 512, -1, 0, 64},
         {512, 256, -1, 0, 64}, {512, 512, -1, 0, 64},  {1024, 256, -1, 0, 64}, {256, 1024, -1, 0, 64},
         {1024, 1024, -1, 0, 64}, {2048, 512, -1, 0, 64}, {512, 2048, -1, 0, 64}, {256, 512, 1, 0, 64},
@@ -395,7 +400,7 @@ rr_status rr_tune_permute(void* dst, const void* src, int ndim, const int64_t* d
         {0, 0, -1, 0, 0, -1, 0, -1, 1}, {0, 0, 0, 0, 0, -1, 0, -1, 1}, {0, 0, -1, 0, 64, -1, 0, -1, 1},
         {1024, 256, 1, 0, 0, -1, 0, -1, 1}, {256, 1024, 1, 0, 0, -1, 0, -1, 1}, {512, 512, 0, 0, 0, -1, 0, -1, 1},
         {0, 0, -1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 1, 0, 0, -1, 0, -1, 0, 0}, {0, 0, 0, 0, 0, -1, 0, -1, 0, 0},
-        {512, 512, -1, 0, 64, -1, 0, -1, 0, 0}};
+        {512, 512, -1, 0, 64, -1, 0, -1, 0, 0}, {0, 0, -1, 0, 0, -1, 0, -1, 0}};
     hipStream_t hs = (hipStream_t)stream;
     hipEvent_t e0, e1;
     if (hipEventCreate(&e0) != hipSuccess) return fail(RR_ERR_HIP, "hipEventCreate");

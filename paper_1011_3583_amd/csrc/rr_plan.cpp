@@ -44,7 +44,7 @@ TileOptions g_override;
 
 bool override_active(const TileOptions& o) {
     return o.in_row_bytes != 0 || o.out_row_bytes != 0 || o.order_out != -1 || o.force_ragged ||
-           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != 0 ||
+           o.max_g != 0 || o.tile_kib != 0 || o.xcd != -1 || o.umt != 0 || o.cache != -1 || o.diag != -1 ||
            o.fill != -1 || o.weave != 1;
 }
 
@@ -168,7 +168,8 @@ bool valid_tile_kib(int k) { return k == 0 || (k >= 4 && k <= 64); }
 // One entry per line:
 //   key in_row_bytes out_row_bytes order_out [max_g [tile_kib [xcd [umt [cache [diag [fill]]]]]]]
 // (an entry without the xcd field never uses XCD ranges, one without cache plans
-// its accesses by line alignment, one without fill takes the built-in refit)
+// its accesses by line alignment, one without diag keeps the plain tile order,
+// one without fill takes the built-in refit; diag -1 is the built-in choice)
 int tune_parse(const std::string& text, int* skipped) {
     std::istringstream lines(text);
     std::string line;
@@ -180,6 +181,7 @@ int tune_parse(const std::string& text, int* skipped) {
         std::string key;
         if (!(in >> key)) continue;   // blank line
         TileOptions o;
+        o.diag = 0;   // lines written before the built-in diagonal rule were timed without it
         if (!(in >> o.in_row_bytes >> o.out_row_bytes >> o.order_out)) return -1;
         if (!(in >> o.max_g)) { o.max_g = 0; o.xcd = 0; }
         else if (!(in >> o.tile_kib)) { o.tile_kib = 0; o.xcd = 0; }
@@ -192,7 +194,7 @@ int tune_parse(const std::string& text, int* skipped) {
         if (in >> extra) return -1;
         if (o.in_row_bytes < 0 || o.in_row_bytes > 4096 || o.out_row_bytes < 0 || o.out_row_bytes > 4096 ||
             o.order_out < -1 || o.order_out > 1 || !valid_max_g(o.max_g) || !valid_tile_kib(o.tile_kib) ||
-            o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3 || o.diag < 0 ||
+            o.xcd < -1 || o.xcd > 1 || o.umt < 0 || o.umt > 2 || o.cache < -1 || o.cache > 3 || o.diag < -1 ||
             o.diag > 1 || o.fill < -1 || o.fill > 1)
             return -1;
         if (key.find('|') == std::string::npos) return -1;   // no context
@@ -743,6 +745,20 @@ static rr_status finish_tile(TileArgs& a, int U, int G, int k, uint64_t row_alig
     return RR_OK;
 }
 
+// Built-in diagonal tile order: 2-D transposes of 1-8-byte elements whose rows
+// are a power of two of at least 4 KiB on both sides.  Concurrent tiles then
+// start on rows 2^k bytes apart, which the HBM3E address hashing still piles
+// onto few channels (the partition camping of Sec. II); the skew spreads them.
+// Measured from cold caches on 4096^2-16384^2 and 16384 x 4096 transposes
+// (16 MiB and more per side): +1-41 %, one case -1 %.  At other pitches
+// (16000^2, 8320 x 8192, 12288^2) and for 16-byte elements it lost up to 23 %,
+// so those keep the plain order, as do smaller problems (not measured).
+static bool diag_by_default(const Canon& c) {
+    if (c.rank != 2 || c.perm[0] != 1 || c.strided || c.elem_bytes > 8 || c.total_bytes < (16ll << 20)) return false;
+    auto pow2 = [](int64_t x) { return x >= 4096 && (x & (x - 1)) == 0; };
+    return pow2(c.dims[0] * c.elem_bytes) && pow2(c.dims[1] * c.elem_bytes);
+}
+
 static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const TileOptions& opt,
                            Plan* p, std::string* why) {
     p->kind = K_TILE;
@@ -1034,7 +1050,7 @@ static rr_status plan_tile(uint64_t dst, uint64_t src, const Canon& c, const Til
     rr_status st = finish_tile(a, U, G, k, ra, flat_ok && !umt, src, b1 > 0 ? (uint64_t)d[b1] : 0, opt, why);
     if (st != RR_OK) return st;
     cache_policy(a, opt);
-    if (opt.diag && a.ngrid >= 2) a.flags |= TF_DIAG;
+    if (a.ngrid >= 2 && (opt.diag == 1 || (opt.diag == -1 && diag_by_default(c)))) a.flags |= TF_DIAG;
     p->grid = a.ntiles;
     p->bytes = (uint64_t)c.total_bytes;
     return RR_OK;

@@ -236,7 +236,8 @@ struct TileOptions {
     int tile_kib = 0;       // tile size the planner shrinks to (KiB of LDS; 0 = 16)
     int xcd = -1;           // 1: contiguous tile range per XCD (per entry in batches), 0: never,
                             // -1: where the cache policy reads or writes through the caches
-    int diag = 0;           // 1: diagonal tile order (the paper's answer to partition camping)
+    int diag = -1;          // diagonal tile order (the paper's answer to partition camping): 1 on,
+                            // 0 off, -1 built-in (on for 2-D transposes at power-of-two pitches)
     int cache = -1;         // global accesses of tiles: 0 non-temporal, 1 loads cached,
                             // 2 stores cached, 3 both; -1: by line alignment (cache_policy)
     int umt = 0;            // unaligned micro-tiles: 1 where aligned ones do not fit (instead

@@ -61,7 +61,7 @@ def run(jobs):
                                        rb, str(j.get("order", -1)), str(j.get("max_g", 0)),
                                        str(int(j.get("ragged", False))),
                                        str(-1 if j.get("xcd") is None else int(j["xcd"])),
-                                       str(int(j.get("umt", 0))), str(int(j.get("diag", False))),
+                                       str(int(j.get("umt", 0))), str(-1 if j.get("diag") is None else int(j["diag"])),
                                        str(-1 if j.get("fill") is None else int(j["fill"])),
                                        str(int(j.get("weave", True))), inf, outf]))
             elif j["op"] == "stencil":

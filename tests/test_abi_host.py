@@ -534,3 +534,29 @@ def test_tuning_file_of_another_device_or_runtime_is_skipped(tmp_path):
     with pytest.raises(rr.RRError):
         rr.tune_load(str(path))
     assert rr.plan_describe(dims, perm, e, dst=1 << 20, src=1 << 30) == base
+
+
+def test_diagonal_order_by_default():
+    """2-D transposes of 1-8-byte elements whose rows are a power of two of at least
+    4 KiB on both sides (16 MiB or more per side) take the diagonal tile order by
+    default; other pitches, 16-byte elements, small problems and higher ranks keep
+    the plain order; the override switches it either way."""
+    def diag(dims, e, perm=(1, 0)):
+        return bool(int(rr.plan_describe(dims, perm, e, dst=1 << 30, src=1 << 33)["flags"]) & 4096)
+
+    for e in (1, 2, 4, 8):
+        assert diag((8192, 8192), e) and diag((16384, 4096), e) and diag((4096, 16384), e), e
+    assert diag((4096, 4096), 1)
+    assert not diag((8192, 8192), 16)
+    assert not diag((8320, 8192), 4) and not diag((16000, 16000), 4) and not diag((12288, 12288), 1)
+    assert not diag((1024, 1024), 4)                       # 4 MiB: below the measured sizes
+    assert not diag((512, 512, 256), 4, (2, 1, 0))         # rank 3
+    rr.set_tile_override(diag=False)
+    try:
+        assert not diag((8192, 8192), 4)
+        rr.set_tile_override(diag=True)
+        assert diag((8320, 8192), 4)
+        with pytest.raises(rr.RRError):
+            rr.check(rr.lib().rr_set_tile_override(0, 0, 128 | (1 << 30)))
+    finally:
+        rr.set_tile_override()
