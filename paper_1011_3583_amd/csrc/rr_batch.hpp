@@ -42,10 +42,15 @@ constexpr uint64_t batch_buckets(uint64_t total_blocks) {
 }
 
 // Which of its job's workgroups an entry runs: blocks [first, first + count)
-// of a launch of `job_blocks` workgroups.  A whole job is {0, grid, grid}.
+// of a launch of `job_blocks` workgroups, taken by the group's workgroups
+// [start, start + count).  A whole job is {0, grid, start, grid}.  One 16-byte
+// record, so a workgroup reads everything it maps by in a single load once it
+// knows its entry.
 struct EntryRange {
     uint32_t first;
     uint32_t job_blocks;
+    uint32_t start;
+    uint32_t count;
 };
 
 // One entry of a batch: a planned job, or a contiguous range of its workgroups.

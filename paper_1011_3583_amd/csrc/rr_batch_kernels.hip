@@ -12,18 +12,30 @@
 
 namespace rr {
 
+// Register budget of the batch tile kernels: eight waves per SIMD.  At the
+// compiler's own choice the job lookups of a batch workgroup take these kernels
+// a few scalar registers past the eight-wave limit (seven waves); held to eight
+// they keep the excess in vector-register lanes, and the 4096-job batch ran
+// 2-4 % faster.  The two largest micro-tiles and the 2-byte G = 1 kernel would
+// spill vector registers to memory at that budget and keep the compiler's choice.
+template <int U, int G>
+constexpr int batch_tile_waves() { return (U == 1 && G == 16) || (U == 2 && (G == 8 || G == 1)) ? 1 : 8; }
+
 // One launch per kernel family covers every job of a batch group; the
 // workgroup index walks the concatenation of the jobs' own launch grids.
+
 template <int U, int G>
-__global__ __launch_bounds__(NT) void k_batch_tile(const TileArgs* __restrict__ args,
-                                                   const uint32_t* __restrict__ prefix,
-                                                   const EntryRange* __restrict__ ranges, uint32_t njobs,
-                                                   uint32_t total) {
+__global__ __launch_bounds__(NT) __attribute__((amdgpu_waves_per_eu(batch_tile_waves<U, G>(), 8)))
+void k_batch_tile(const TileArgs* __restrict__ args, const uint32_t* __restrict__ prefix,
+                  const EntryRange* __restrict__ ranges, uint32_t njobs, uint32_t total) {
     extern __shared__ __attribute__((aligned(16))) uint8_t smem[];
     for (uint32_t b = blockIdx.x; b < total; b += gridDim.x) {
         const uint32_t j = find_job(prefix, njobs, b);
+        // the entry's record and the job's flags are loaded together: both
+        // depend on j only
+        const EntryRange r = ranges[j];
         const TileArgs& a = args[j];
-        const TileCtx t = tile_decode(a, batch_block_to_tile(a, prefix, ranges, j, b));
+        const TileCtx t = tile_decode(a, batch_block_to_tile(a.flags, r, b));
         read_dispatch<U, G>(a, t, smem, threadIdx.x);
         __syncthreads();
         write_phase<U, G>(a, t, smem, threadIdx.x);

@@ -246,9 +246,11 @@ rr_status build_batch(const std::vector<BatchEntry>& entries, BatchPlan* out, st
             const BatchEntry& e = entries[members[m]];
             const Plan& p = *e.plan;
             prefix[m] = (uint32_t)acc;
-            acc += e.nblocks;
             ranges[m].first = e.first_block;
             ranges[m].job_blocks = p.grid;
+            ranges[m].start = (uint32_t)acc;
+            ranges[m].count = e.nblocks;
+            acc += e.nblocks;
             g.bytes += e.bytes;
             if (g.kind == K_COPY) std::memcpy(argp + m * sizeof(CopyArgs), &p.copy, sizeof(CopyArgs));
             else if (g.kind == K_RUN) std::memcpy(argp + m * sizeof(RunArgs), &p.run, sizeof(RunArgs));

@@ -1597,43 +1597,44 @@ RR_HD uint32_t find_job(const uint32_t* prefix, uint32_t njobs, uint32_t b) {
     return lo;
 }
 
-// Block (tile, or run-copy block) of workgroup b of entry j in a batch group,
+// Block (tile, or run-copy block) of workgroup b of entry r in a batch group,
 // each XCD taking a contiguous run of the entry's blocks.  Workgroups reach the
 // XCDs round-robin (workgroup b on XCD b % 8); this gives each XCD a contiguous
 // run of the entry's blocks instead, as xcd_range does for a single launch.
-// The entry's workgroups [prefix[j], prefix[j+1]) map one to one onto its
-// blocks [first, first + n): workgroup b is virtual index v = b - prefix[j] +
-// prefix[j] % 8 (so v % 8 is its XCD), and XCD x's runs are laid out in x order.
-RR_HD uint32_t batch_xcd_block(const uint32_t* prefix, const EntryRange* ranges, uint32_t j, uint32_t b) {
-    const uint32_t lb = b - prefix[j];
-    const uint32_t n = prefix[j + 1] - prefix[j], q0 = prefix[j] % NXCD;
+// The entry's workgroups [start, start + n) map one to one onto its blocks
+// [first, first + n): workgroup b is virtual index v = b - start + start % 8
+// (so v % 8 is its XCD), and XCD x's runs are laid out in x order.
+RR_HD uint32_t batch_xcd_block(const EntryRange& r, uint32_t b) {
+    const uint32_t lb = b - r.start;
+    const uint32_t n = r.count, q0 = r.start % NXCD;
     const uint32_t v = lb + q0, x = v % NXCD, k = v / NXCD;
     // tiles of the XCDs before x: the virtual indices in [q0, q0 + n) whose XCD is
     // below x, i.e. #{u < q0 + n : u % 8 < x} - #{u < q0 : u % 8 < x} (q0 < 8)
     const uint32_t m = q0 + n;
     const uint32_t start = (m / NXCD) * x + umin(m % NXCD, x) - umin(q0, x);
-    return ranges[j].first + start + k - (x < q0 ? 1u : 0u);
+    return r.first + start + k - (x < q0 ? 1u : 0u);
 }
-// Tile of workgroup b of entry j: XCD ranges with TF_XCD, else in order.
-RR_HD uint32_t batch_block_to_tile(const TileArgs& a, const uint32_t* prefix, const EntryRange* ranges,
-                                   uint32_t j, uint32_t b) {
-    if (!(a.flags & TF_XCD)) return ranges[j].first + (b - prefix[j]);
-    return batch_xcd_block(prefix, ranges, j, b);
+// Tile of workgroup b of entry r: XCD ranges with TF_XCD, else in order.
+RR_HD uint32_t batch_block_to_tile(uint32_t flags, const EntryRange& r, uint32_t b) {
+    if (!(flags & TF_XCD)) return r.first + (b - r.start);
+    return batch_xcd_block(r, b);
 }
 
 template <int W>
 RR_HD void batch_copy_block(const CopyArgs* args, const uint32_t* prefix, const EntryRange* ranges,
                             uint32_t njobs, uint32_t b, uint32_t tid) {
     const uint32_t j = find_job(prefix, njobs, b);
-    copy_thread<W>(args[j], b - prefix[j] + ranges[j].first, ranges[j].job_blocks, tid);
+    const EntryRange r = ranges[j];
+    copy_thread<W>(args[j], b - r.start + r.first, r.job_blocks, tid);
 }
 
 template <int W>
 RR_HD void batch_run_block(const RunArgs* args, const uint32_t* prefix, const EntryRange* ranges,
                            uint32_t njobs, uint32_t b, uint32_t tid) {
     const uint32_t j = find_job(prefix, njobs, b);
+    const EntryRange r = ranges[j];
     const RunArgs& a = args[j];
-    run_thread<W>(a, a.cached ? batch_xcd_block(prefix, ranges, j, b) : b - prefix[j] + ranges[j].first, tid);
+    run_thread<W>(a, a.cached ? batch_xcd_block(r, b) : b - r.start + r.first, tid);
 }
 
 }  // namespace rr

@@ -99,11 +99,19 @@ static void run_batch_tile_ug(const BatchGroup& g, const uint8_t* table) {
     const uint32_t* prefix = reinterpret_cast<const uint32_t*>(table + g.prefix_off);
     const EntryRange* ranges = reinterpret_cast<const EntryRange*>(table + g.range_off);
     std::vector<std::vector<uint8_t>> seen(g.njobs);   // each entry's tiles taken once
-    for (uint32_t j = 0; j < g.njobs; ++j) seen[j].assign(prefix[j + 1] - prefix[j], 0);
+    for (uint32_t j = 0; j < g.njobs; ++j) {
+        seen[j].assign(prefix[j + 1] - prefix[j], 0);
+        // the record repeats the entry's workgroup range from the prefix sums
+        if (ranges[j].start != prefix[j] || ranges[j].count != prefix[j + 1] - prefix[j]) {
+            std::fprintf(stderr, "entry %u: record (%u, %u) != prefix range (%u, %u)\n", j, ranges[j].start,
+                         ranges[j].count, prefix[j], prefix[j + 1] - prefix[j]);
+            std::abort();
+        }
+    }
     for (uint32_t b = 0; b < g.total_blocks; ++b) {
         const uint32_t j = find_job(prefix, g.njobs, b);
         const TileArgs& a = args[j];
-        const uint32_t tile = batch_block_to_tile(a, prefix, ranges, j, b);
+        const uint32_t tile = batch_block_to_tile(a.flags, ranges[j], b);
         const uint32_t rel = tile - ranges[j].first;
         if (tile < ranges[j].first || rel >= seen[j].size() || seen[j][rel]++) {
             std::fprintf(stderr, "batch block %u (entry %u) -> bad tile %u\n", b, j, tile);
@@ -583,8 +591,11 @@ int main(int argc, char** argv) {
                     if (db[sizes[(size_t)i]] != 0x5A) { std::printf("err -2 wrote past the end\n"); return 3; }
                     write_file(outs[(size_t)i], db, sizes[(size_t)i]);
                 }
-                std::printf(ok ? "ok groups=%zu jobs=%u bytes=%llu\n" : "err -1 no kernel\n", bp.groups.size(),
-                            bp.njobs, (unsigned long long)bp.bytes);
+                std::string variants;
+                for (const BatchGroup& g : bp.groups)
+                    variants += (variants.empty() ? "" : ",") + std::to_string(g.kind) + ":" + std::to_string(g.variant);
+                std::printf(ok ? "ok groups=%zu jobs=%u bytes=%llu variants=%s\n" : "err -1 no kernel\n",
+                            bp.groups.size(), bp.njobs, (unsigned long long)bp.bytes, variants.c_str());
             }
             for (uint8_t* q : bufs) delete[] q;
         } else {
