@@ -548,6 +548,25 @@ def test_emu_batched_many_jobs_threaded_planning():
             (j["dims"], j["perm"], j["esize"])
 
 
+def test_emu_batched_planning_passes_reuse_the_host_workers():
+    """Several batches of 600 jobs in one process, each planned in slices on the
+    library's host worker threads: an invalid batch in between reports its lowest
+    invalid job (of two, in different slices), and the batches after it still
+    plan and run bit-exact."""
+    first, second = _batched_jobs(61, 600, 4000), _batched_jobs(62, 600, 4000)
+    bad = _batched_jobs(63, 600, 4000)
+    for k in (520, 450):   # (0, 0) is not a permutation: job 450 is the lowest invalid one
+        bad[k] = _perm_job((2, 3), (0, 0), 4, 9000 + k)
+    res = emu_runner.run([dict(op="batched", jobs=first), dict(op="batched", jobs=bad),
+                          dict(op="batched", jobs=second)])
+    assert res[1][0].startswith("err") and " job 450 " in res[1][0], res[1][0]
+    for (status, outs), jobs in ((res[0], first), (res[2], second)):
+        assert status.startswith("ok"), status
+        for j, out in zip(jobs, outs):
+            assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
+                (j["dims"], j["perm"], j["esize"])
+
+
 @pytest.mark.parametrize("seed,opts", [(1, (0, 0, 0)), (2, (512, 256, 0)), (3, (256, 1024, 1))])
 def test_emu_batched_uneven_jobs(seed, opts):
     """A batch of uneven jobs of every kernel family: each job equals the oracle alone."""
