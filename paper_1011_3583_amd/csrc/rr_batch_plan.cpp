@@ -70,8 +70,8 @@ static int planning_threads(int njobs) {
 
 // Worker threads kept for the life of the process to run the slices of a
 // validation or planning pass.  Starting and joining a thread per slice cost
-// 30-100 us per thread on every call (7 threads: 0.2-0.7 ms, more than
-// validating 4096 jobs on one core), and a one-shot batch waits for that
+// 30-100 us per thread on every call (7 threads: 0.2-0.7 ms, about what
+// validating 4096 jobs takes on one core), and a one-shot batch waits for that
 // before its first chunk runs.  One pass at a time uses the workers; a caller
 // that finds them busy, or runs in a child forked after they started, starts
 // threads of its own as before.  The pool is never destroyed: its workers are
