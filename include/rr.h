@@ -194,7 +194,10 @@ rr_status rr_deinterlace(void* const* dsts, const void* src, int n, int64_t coun
  * staged and launched in up to four chunks of consecutive jobs (the first a
  * sixteenth of them), so the device runs the first chunks while the host plans the
  * rest; each chunk takes a ring slot, and its table goes up on a fourth stream of
- * the library.
+ * the library.  Batches of 256 jobs or more are validated and planned in slices
+ * on up to seven host worker threads that the library starts on first use and
+ * keeps, asleep between calls, until process exit (a call that finds them busy
+ * starts threads of its own for that call).
  * Errors: the first invalid job's error (nothing is launched), RR_ERR_NO_MEMORY,
  * RR_ERR_HIP.
  */
@@ -227,7 +230,8 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
  *    race on the table and must be ordered by the caller (events or one
  *    stream).  Not for graph capture (the copy would be recorded as a node that
  *    reads the calling thread's staging buffer).
- * Host planning uses per-thread buffers kept across calls.
+ * Host planning uses per-thread buffers kept across calls and, for 256 jobs or
+ * more, the host worker threads described under rr_permute_batched.
  * Errors: the first invalid job's error (nothing is launched), RR_ERR_UNSUPPORTED,
  * RR_ERR_HIP.
  */
