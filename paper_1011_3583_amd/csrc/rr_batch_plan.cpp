@@ -5,6 +5,7 @@
 #include <algorithm>
 #include <condition_variable>
 #include <cstring>
+#include <exception>
 #include <functional>
 #include <map>
 #include <mutex>
@@ -110,11 +111,20 @@ class SlicePool {
             ++gen_;
         }
         cv_.notify_all();
-        body(0);
-        for (int t = use; t < nt; ++t) body(t);
+        // the workers use `body` until they report back: wait for them even if
+        // the caller's own slices throw
+        std::exception_ptr err;
+        try {
+            body(0);
+            for (int t = use; t < nt; ++t) body(t);
+        } catch (...) {
+            err = std::current_exception();
+        }
         std::unique_lock<std::mutex> lk(mu_);
         done_.wait(lk, [&] { return pending_ == 0; });
         body_ = nullptr;
+        lk.unlock();
+        if (err) std::rethrow_exception(err);
         return true;
     }
 
