@@ -220,7 +220,7 @@ rr_status rr_permute_batched(const rr_job* jobs, int njobs, rr_stream_t stream);
  * differences:
  *  - the job table lives in a fixed 4 MiB device array of the library (one copy
  *    per GPU, held until the process ends) instead of a staging ring; a batch
- *    whose table exceeds it (about 6000 tiled jobs) fails with
+ *    whose table exceeds it (about 5700 tiled jobs) fails with
  *    RR_ERR_UNSUPPORTED before anything is enqueued;
  *  - the table is copied from pageable host memory with a stream-ordered copy
  *    on `stream` (the call may block until the work already queued on `stream`
