@@ -23,6 +23,8 @@
 #include <cstdlib>
 #include <cstring>
 #include <algorithm>
+#include <atomic>
+#include <thread>
 #include <fstream>
 #include <new>
 #include <sstream>
@@ -581,8 +583,31 @@ int main(int argc, char** argv) {
             } else {
                 st = plan_batch(jobs.data(), k, opt, &bp, &why, &bad);
             }
+            // chunk < 0: -chunk host threads plan the same batch at once, 6 times
+            // each, while the library's planning workers are shared among them;
+            // every plan must equal the one above byte for byte
+            int differ = 0;
+            if (st == RR_OK && chunk < 0) {
+                std::atomic<int> diffs{0};
+                std::vector<std::thread> th;
+                for (int t = 0; t < -chunk; ++t)
+                    th.emplace_back([&] {
+                        for (int r = 0; r < 6; ++r) {
+                            BatchPlan q;
+                            std::string w;
+                            int b2 = -1;
+                            if (plan_batch(jobs.data(), k, opt, &q, &w, &b2) != RR_OK || q.table != bp.table ||
+                                q.groups.size() != bp.groups.size())
+                                ++diffs;
+                        }
+                    });
+                for (std::thread& x : th) x.join();
+                differ = diffs.load();
+            }
             if (st != RR_OK) {
                 std::printf("err %d job %d %s\n", (int)st, bad, why.c_str());
+            } else if (differ) {
+                std::printf("err -3 %d concurrent plans differ\n", differ);
             } else {
                 bool ok = true;
                 for (const BatchGroup& g : bp.groups) ok = ok && emulate_group(g, bp.table.data());

@@ -567,6 +567,19 @@ def test_emu_batched_planning_passes_reuse_the_host_workers():
                 (j["dims"], j["perm"], j["esize"])
 
 
+def test_emu_batched_planning_from_several_threads_at_once():
+    """Four host threads plan the same 600-job batch six times each at once, sharing
+    the library's planning workers (a pass that finds them busy starts threads of
+    its own): every plan equals the single-threaded one byte for byte, and the batch
+    runs bit-exact."""
+    jobs = _batched_jobs(64, 600, 4000)
+    status, outs = emu_runner.run([dict(op="batched", jobs=jobs, chunk=-4)])[0]
+    assert status.startswith("ok"), status
+    for j, out in zip(jobs, outs):
+        assert np.array_equal(out, oracle.permute(j["input"], j["dims"], j["perm"], j["esize"])), \
+            (j["dims"], j["perm"], j["esize"])
+
+
 @pytest.mark.parametrize("seed,opts", [(1, (0, 0, 0)), (2, (512, 256, 0)), (3, (256, 1024, 1))])
 def test_emu_batched_uneven_jobs(seed, opts):
     """A batch of uneven jobs of every kernel family: each job equals the oracle alone."""
