@@ -133,6 +133,38 @@ def test_batched_calls_on_two_streams_share_side_streams(rr):
         _check_all_vs_oracle(J)
 
 
+def test_batched_calls_from_several_host_threads(rr):
+    """Four host threads each issue three batched calls of 600 jobs at once, each on
+    a stream of its own: the calls plan in slices on the library's planning workers
+    (or on threads of their own when those are busy) and share the staging ring and
+    side streams; every job equals the oracle."""
+    import threading
+    specs = _uneven(5, 600, 3000)
+    Js = [Jobs(rr, specs, 50 + k) for k in range(4)]
+    torch.cuda.synchronize()
+    streams = [torch.cuda.Stream() for _ in Js]
+    errs = []
+
+    def run(k):
+        try:
+            for _ in range(3):
+                rr.check(rr.permute_batched_raw(Js[k].arr, len(specs), streams[k].cuda_stream))
+        except Exception as e:   # reported below, on the test's thread
+            errs.append(e)
+
+    th = [threading.Thread(target=run, args=(k,)) for k in range(len(Js))]
+    _say("four host threads, three batched calls of 600 jobs each")
+    for t in th:
+        t.start()
+    for t in th:
+        t.join()
+    for st in streams:
+        st.synchronize()
+    assert not errs, errs
+    for J in Js:
+        _check_all_vs_oracle(J)
+
+
 @pytest.mark.parametrize("flags", [0, 4, 2, 1, 1 | 4, 1 | 2])
 def test_batch_handle_modes(rr, flags):
     specs = _uneven(3, 120, 20000)
